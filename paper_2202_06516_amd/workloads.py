@@ -1,0 +1,141 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+This module holds inputs only -- lattice sizes, solid and drop placements,
+wettability values and seeded synthetic fields -- and none of the method's
+arithmetic (no equation of state, collision, streaming or measurement).  Both
+the GPU library and the CPU oracle receive what it produces.
+
+Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
+  sessile_2d   D2Q9 FP64 128x128 periodic, cylinder r=24 at (64,40), drop r0=20
+               tangent on top at (64,84), 5000 steps, angle every 100 steps
+  sessile_3d   D3Q19 FP32 256^3 walled box, sphere r=60 at (128,128,92), drop
+               r0=40 tangent on top at (128,128,192), 20000 steps
+  striped_3d   D3Q19 FP32 512^3 walled box, sphere r=120 with latitude stripes
+               (width 16) of two wettabilities, sessile or pendent drop r0=80,
+               gravity 1e-6 .. 1e-5 lu
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# wall chemical potentials of the paper's wettability sweep (Sec. IV C)
+MU_W_SWEEP = (-0.01, 0.04, 0.1)
+
+
+def sessile_2d(mu_w=0.04, n=128, scale=1.0):
+    """Cylinder + tangent drop on a periodic square lattice (scaled with n/128)."""
+    s = n / 128.0 * scale
+    return dict(dim=2, n=(n, n), wall=(0, 0), solids=[dict(center=(64 * s, 40 * s), radius=24 * s, mu_w=mu_w)],
+                drops=[((64 * s, 84 * s), 20 * s)], steps=5000, every=100)
+
+
+def sessile_3d(mu_w=0.04, n=256):
+    """Sphere + tangent drop in a walled cube (the 256^3 layout, scaled with n/256)."""
+    s = n / 256.0
+    cz = 92 * s
+    R = 60 * s
+    r0 = 40 * s
+    return dict(dim=3, n=(n, n, n), wall=(1, 1, 1),
+                solids=[dict(center=(128 * s, 128 * s, cz), radius=R, mu_w=mu_w)],
+                drops=[((128 * s, 128 * s, cz + R + r0), r0)], steps=20000, every=500, n_sectors=32)
+
+
+def striped_3d(n=512, pendent=False, g=1e-6, mu1=-0.0183, mu2=0.0700, width=16.0):
+    """Sphere with latitude stripes; sessile (drop above) or pendent (drop below)."""
+    s = n / 512.0
+    R, r0 = 120 * s, 80 * s
+    if pendent:
+        cz = 336 * s
+        drop = ((256 * s, 256 * s, cz - R - r0), r0)
+        gv = (0.0, 0.0, -g)
+    else:
+        cz = 176 * s
+        drop = ((256 * s, 256 * s, cz + R + r0), r0)
+        gv = (0.0, 0.0, -g)
+    return dict(dim=3, n=(n, n, n), wall=(1, 1, 1),
+                solids=[dict(center=(256 * s, 256 * s, cz), radius=R, stripes=(mu1, mu2, width * s))],
+                drops=[drop], g=gv, g_start=10000, steps=50000, every=500, n_sectors=64)
+
+
+def wedge_density(shape, center, R, theta0_deg, rho_m, rho_lo, rho_hi, slope=0.05, half_chord=30.0,
+                  top=40.0, side=90.0, floor=10.0):
+    """Synthetic 2-D liquid region meeting a circle at a prescribed angle.
+
+    The liquid is bounded by two straight lines through the points of the
+    circle (center, R) at +-half_chord from the vertical axis, each at angle
+    theta0 to the circle's tangent measured through the liquid, plus a flat top,
+    a floor floor lu above the centre (so the lines' second crossings of the
+    circle stay dry) and two far side walls.  The density is rho_m + slope * s, with s the
+    minimum of the signed distances to these lines (positive inside), clipped
+    to [rho_lo, rho_hi].  Along any lattice link near a contact point the
+    density is affine, so isodensity crossings lie exactly on the line.
+    Returns an array of shape (1, ny, nx).
+    """
+    _, ny, nx = shape
+    cx, cy = center
+    phi = np.arcsin(half_chord / R)
+    th = np.deg2rad(theta0_deg)
+    lines = []  # (point, inward unit normal)
+    for side_sign in (1.0, -1.0):
+        px, py = cx + side_sign * R * np.sin(phi), cy + R * np.cos(phi)
+        # tangent toward the axis and outward normal at the contact point
+        tx, ty = -side_sign * np.cos(phi), np.sin(phi)
+        nx_, ny_ = side_sign * np.sin(phi), np.cos(phi)
+        # interface direction: rotate t toward n by theta0
+        vx, vy = np.cos(th) * tx + np.sin(th) * nx_, np.cos(th) * ty + np.sin(th) * ny_
+        # inward normal of the line: the side containing the tangent direction t
+        mx, my = -vy, vx
+        if mx * tx + my * ty < 0:
+            mx, my = -mx, -my
+        lines.append((px, py, mx, my))
+    ytop = cy + R + top
+    lines.append((cx, ytop, 0.0, -1.0))
+    lines.append((cx, cy + floor, 0.0, 1.0))
+    lines.append((cx - side, cy, 1.0, 0.0))
+    lines.append((cx + side, cy, -1.0, 0.0))
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    s = np.full((ny, nx), np.inf)
+    for px, py, mx, my in lines:
+        s = np.minimum(s, (xx - px) * mx + (yy - py) * my)
+    rho = np.clip(rho_m + slope * s, rho_lo, rho_hi)
+    return rho[None, :, :]
+
+
+def random_state_perturbation(shape, q, seed, amplitude=1e-3):
+    """Seeded multiplicative noise factors (1 + a*U(-1,1)) for populations [q, *shape]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return 1.0 + amplitude * rng.uniform(-1.0, 1.0, size=(q,) + tuple(shape))
+
+
+def batch_cases(n_cases=512, seed=0, nmin=64, nmax=512, rs=(16.0, 128.0), r0=(12.0, 96.0),
+                mu=(-0.01, 0.1), W=10.0, max_tries=100):
+    """Case table of independent 2-D drops on cylinders (seeded PCG64).
+
+    Sides uniform in [nmin, nmax]; cylinder radius, drop radius and wall
+    chemical potential uniform in the given ranges.  A draw is feasible if
+    2 R_s + 2 r0 + 2 W + 8 <= ny and 2 max(R_s, r0) + 8 <= nx; infeasible
+    draws are redrawn up to max_tries times, then both radii are scaled down.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cases = []
+    accepted = 0
+    for _ in range(n_cases):
+        nx = int(rng.integers(nmin, nmax + 1))
+        ny = int(rng.integers(nmin, nmax + 1))
+        ok = False
+        for _t in range(max_tries):
+            Rs = float(rng.uniform(*rs))
+            rd = float(rng.uniform(*r0))
+            muw = float(rng.uniform(*mu))
+            if 2 * Rs + 2 * rd + 2 * W + 8 <= ny and 2 * max(Rs, rd) + 8 <= nx:
+                ok = True
+                break
+        if ok:
+            accepted += 1
+        else:
+            f = min((ny - 2 * W - 8) / (2 * Rs + 2 * rd), (nx - 8) / (2 * max(Rs, rd)))
+            Rs, rd = Rs * f, rd * f
+        cy = W + 4 + Rs
+        cases.append(dict(n=(nx, ny), solid=dict(center=(nx / 2.0, cy), radius=Rs, mu_w=muw),
+                          drop=((nx / 2.0, cy + Rs + rd), rd)))
+    return cases, accepted / n_cases
