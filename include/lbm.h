@@ -1,0 +1,240 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) multiphase lattice Boltzmann library.
+ *
+ * The library advances the multiphase lattice Boltzmann equation of
+ * Liu, Yao, Li & Wen, "Contact angle measurement on curved wetting surface in
+ * multiphase lattice Boltzmann method" (arXiv:2202.06516) on one GPU, and
+ * measures the contact angle of a drop on a curved wetting solid inside the
+ * time step.  Every entry point takes plain pointers and sizes; no C++ or
+ * framework types cross this boundary.
+ *
+ * Method (paper sections and equations):
+ *   - MRT lattice Boltzmann equation, Eq. 1, rates S of Sec. II A; the BGK
+ *     collision of Eq. 3 is available as the case of equal rates;
+ *   - second-order equilibrium, Eq. 2; streaming, Eq. 4;
+ *   - chemical potential of the Peng-Robinson fluid, Eq. 10-12, gradients by
+ *     fourth-order central differences (Sec. II B);
+ *   - non-ideal force F = -rho grad(mu) + cs^2 grad(rho), Eq. 7, applied by
+ *     the exact-difference method, Eq. 13; optional body force rho g (Sec. IV);
+ *   - wetting: a prescribed chemical potential on two solid layers, whose
+ *     densities follow Eq. 14 (Sec. III A);
+ *   - streaming at the curved wall: halfway bounce-back, or linear
+ *     interpolated bounce-back with an exact mass correction (Sec. III A);
+ *   - contact angle: isodensity crossings on liquid-gas links (Eq. 15), the
+ *     crossings nearest 1 and 2 lattice units from the substrate, their secant
+ *     meets the substrate at the contact point, angle to the substrate tangent
+ *     through the liquid (Sec. III B, Fig. 1).
+ *
+ * Conventions shared by all entry points:
+ *   - every call returns lbm_status; 0 is success; a call never aborts;
+ *   - on failure, lbm_last_error() describes the error; the string is owned
+ *     by the context and stays valid until the next call on that context;
+ *   - the context owns every buffer it allocates; caller buffers stay the
+ *     caller's and are only read or written during the call (or, for device
+ *     pointers, by work the call enqueues on the context's stream);
+ *   - arrays are x-fastest: index = (z * ny + y) * nx + x; populations are
+ *     structure-of-arrays [Q][nz][ny][nx];
+ *   - direction order D2Q9:  0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1)
+ *                            5 (1,1) 6 (-1,1) 7 (-1,-1) 8 (1,-1);
+ *     D3Q19: 0 (0,0,0) 1 (1,0,0) 2 (-1,0,0) 3 (0,1,0) 4 (0,-1,0) 5 (0,0,1)
+ *            6 (0,0,-1) 7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0)
+ *            11 (1,0,1) 12 (-1,0,-1) 13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1)
+ *            16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1);
+ *   - the state of a context is the pre-collision populations S_t after
+ *     streaming; the step counter t counts completed steps;
+ *   - work is enqueued on the context's stream (the one in lbm_config, else
+ *     one the context creates); calls that return host data synchronise it;
+ *   - a context is not thread-safe: one thread at a time per context.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,             /* invalid argument or configuration */
+    LBM_E_NOMEM = -2,           /* host or device allocation failed */
+    LBM_E_DEVICE = -3,          /* a HIP call failed */
+    LBM_E_STATE = -4,           /* call out of order (e.g. step before init) */
+    LBM_E_NONFINITE = -5,       /* a density became non-finite, <= 0, or >= 1/b */
+    LBM_E_NO_CONTACT_LINE = -6, /* no sector holds both selected crossings */
+    LBM_E_UNSUPPORTED = -7      /* valid request the library does not implement */
+} lbm_status;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum { LBM_F32 = 0, LBM_F64 = 1, LBM_F32_MIXED = 2 };
+enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
+enum { LBM_MRT = 0, LBM_BGK = 1 };
+enum { LBM_BC_HALFWAY = 0, LBM_BC_BOUZIDI_MC = 1 };
+
+#define LBM_MAX_SECTORS 64
+#define LBM_MAX_SOLIDS 16
+
+/* Configuration of one lattice.  lbm_config_default() fills every field. */
+typedef struct {
+    int lattice;          /* LBM_D2Q9 or LBM_D3Q19 */
+    int precision;        /* LBM_F32 / LBM_F64: storage and arithmetic of the step;
+                             LBM_F32_MIXED: FP32 storage, FP64 arithmetic */
+    int n[3];             /* lattice size; n[2] must be 1 for D2Q9 */
+    int axis_bc[3];       /* per axis LBM_PERIODIC, or LBM_WALL = two solid layers at both ends */
+    int collision;        /* LBM_MRT (Eq. 1) or LBM_BGK (Eq. 3) */
+    int bc_mode;          /* LBM_BC_HALFWAY or LBM_BC_BOUZIDI_MC at solid walls */
+    double tau;           /* relaxation time; s_v = 1/tau (Sec. II A) */
+    double s_e, s_eps, s_q;  /* MRT rates of Sec. II A (defaults 1.64, 1.54, 1.9) */
+    double s_pi, s_m;     /* D3Q19 rates of the 4th-order (pi) and 3rd-order (m) moments */
+    double Tr;            /* reduced temperature T/Tc (Sec. II B) */
+    double pr_a, pr_b, pr_R, pr_omega;  /* Peng-Robinson a, b, R, acentric factor (Eq. 10) */
+    double k;             /* mesh-space scaling of Eq. 12 */
+    double kappa;         /* gradient coefficient kappa-hat of Eq. 12 */
+    double g[3];          /* body acceleration in lattice units; force rho g on fluid nodes */
+    int64_t g_start_step; /* first step t at which g acts */
+    double rho_l, rho_g;  /* coexistence densities; <= 0 selects the Maxwell construction */
+    double wall_mu;       /* chemical potential of outer walls; NaN selects k^2 mu_sat */
+    void* stream;         /* hipStream_t to enqueue on, or NULL for a context-owned stream */
+} lbm_config;
+
+/* Fill *cfg with the library defaults for the given lattice. */
+void lbm_config_default(lbm_config* cfg, int lattice);
+
+enum { LBM_SOLID_SPHERE = 0 };                       /* circle in 2-D, sphere in 3-D */
+enum { LBM_WET_UNIFORM = 0, LBM_WET_STRIPES = 1 };
+
+/* A convex solid primitive.  A node is solid iff |x - center| <= radius.
+ * Wettability (Sec. III A): mu_w on its solid nodes, or with LBM_WET_STRIPES
+ * alternating mu_w / mu_w2 in latitude stripes of arc length stripe_width,
+ * stripe = floor(radius * polar_angle / stripe_width), polar angle from pole. */
+typedef struct {
+    int kind;            /* LBM_SOLID_SPHERE */
+    int wet_mode;        /* LBM_WET_UNIFORM or LBM_WET_STRIPES */
+    double center[3];
+    double radius;
+    double mu_w, mu_w2;
+    double stripe_width;
+    double pole[3];      /* stripe pole direction; zero vector selects +y (2-D) or +z (3-D) */
+} lbm_solid;
+
+/* A drop for the initial density field of Eq. 16. */
+typedef struct {
+    double center[3];
+    double radius;
+} lbm_drop;
+
+/* Which solid and how many azimuthal sectors the measurement uses. */
+typedef struct {
+    int solid_index;     /* index into the array given to lbm_set_solid */
+    int n_sectors;       /* 3-D: 1..64 azimuthal sectors about the drop axis; ignored in 2-D (2 sides) */
+    double rho_m;        /* isodensity level; <= 0 selects (rho_l + rho_g) / 2 */
+} lbm_measure_opts;
+
+/* One contact-angle measurement.  Angles in degrees; NaN where invalid. */
+typedef struct {
+    int64_t step;        /* t of the density field measured */
+    int32_t status;      /* LBM_OK or LBM_E_NO_CONTACT_LINE */
+    int32_t n_sectors;
+    int32_t n_valid;
+    int32_t pad_;
+    double mean_deg;     /* mean over valid sectors */
+    double adv_deg;      /* sector the tangential part of g points to (NaN if g has none) */
+    double rec_deg;      /* the opposite sector */
+    double axis[3];      /* unit vector from the substrate centre to the liquid centroid */
+    double sector_deg[LBM_MAX_SECTORS];
+    double contact[LBM_MAX_SECTORS][3];  /* contact point per sector, lattice coordinates */
+} lbm_angle;
+
+typedef struct {
+    double Tc, T, alpha;          /* critical temperature, temperature, alpha(T) */
+    double rho_g, rho_l;          /* coexistence densities in use */
+    double mu_sat, p_sat;         /* psi'(rho) and p0 at coexistence (C = 0 in Eq. 9) */
+    double wall_mu;               /* outer-wall chemical potential in use */
+    double rho_m;                 /* default isodensity level */
+    int32_t Q;
+    int32_t precision;
+    int64_t N;                    /* nodes */
+    int64_t step;                 /* completed steps */
+    int64_t n_fluid, n_layer1, n_layer2, n_boundary;
+} lbm_info;
+
+enum {
+    LBM_FIELD_RHO = 0,   /* [N] density of S_t (fluid), Eq. 14 fill on the two solid layers */
+    LBM_FIELD_F = 1,     /* [Q][N] populations S_t */
+    LBM_FIELD_VEL = 2,   /* [3][N] v = u + F / (2 rho), Sec. II B */
+    LBM_FIELD_MU = 3,    /* [N] chemical potential of Eq. 12; wall value on the solid layers */
+    LBM_FIELD_CLASS = 4, /* [N] uint8: 0 fluid, 1 first solid layer, 2 second, 3 deeper solid */
+    LBM_FIELD_MASS = 5   /* one double: sum of S_t over fluid nodes */
+};
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Create a context: validates cfg, computes the coexistence densities,
+ * allocates the lattice on the current HIP device.  Errors: LBM_E_ARG,
+ * LBM_E_NOMEM, LBM_E_DEVICE.  *out is NULL on failure. */
+lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out);
+
+/* Free a context and everything it owns.  NULL is accepted. */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Set the solids (Sec. III A): classify nodes into fluid / first layer /
+ * second layer / deeper solid, compute the wall fraction q of every cut link
+ * and the wall chemical potential of every solid-layer node.  mu_w_map, if
+ * not NULL, is a host array of N doubles that overrides the primitives'
+ * wettability node by node.  Invalidates the state: call lbm_init_drops or
+ * lbm_write next.  Errors: LBM_E_ARG (n > LBM_MAX_SOLIDS, bad primitive). */
+lbm_status lbm_set_solid(lbm_ctx* ctx, const lbm_solid* prims, int n, const double* mu_w_map);
+
+/* Initial density by Eq. 16 (tanh profile of width W around each drop;
+ * where drops overlap the larger density wins); state = f_eq(rho, 0) on fluid
+ * nodes; t = 0. */
+lbm_status lbm_init_drops(lbm_ctx* ctx, const lbm_drop* drops, int n, double W);
+
+/* Advance nsteps steps.  If measure_every > 0, the contact angle of
+ * lbm_set_measure's options is measured inside the step, on the density of
+ * every step t with t % measure_every == 0.  If series is not NULL, up to cap
+ * measurements are copied to it and *n_written is set (this synchronises);
+ * otherwise the call only enqueues work.  Errors: LBM_E_STATE before any
+ * initial state, LBM_E_NONFINITE if a density went bad (checked when the
+ * call synchronises). */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps, int measure_every,
+                    lbm_angle* series, int cap, int* n_written);
+
+/* Measurement options used by lbm_step's in-step measurement. */
+lbm_status lbm_set_measure(lbm_ctx* ctx, const lbm_measure_opts* opts);
+
+/* Measure the contact angle of the current state (synchronises).
+ * Returns LBM_E_NO_CONTACT_LINE (out->mean_deg = NaN) if no sector is valid. */
+lbm_status lbm_measure_angle(lbm_ctx* ctx, const lbm_measure_opts* opts, lbm_angle* out);
+
+/* Copy a field of the current state to dst (host memory unless
+ * dst_on_device).  bytes must equal the field size: N * elem for RHO and MU,
+ * Q * N * elem for F, 3 * N * elem for VEL (elem = 4 for LBM_F32 and
+ * LBM_F32_MIXED, 8 for LBM_F64), N for CLASS, 8 for MASS (always double).  Synchronises. */
+lbm_status lbm_read(lbm_ctx* ctx, int field, void* dst, size_t bytes, int dst_on_device);
+
+/* Replace the state.  LBM_FIELD_F: populations S_t (checkpoint restore);
+ * LBM_FIELD_RHO: density, state = f_eq(rho, 0) on fluid nodes.  Sizes as for
+ * lbm_read.  Does not change t. */
+lbm_status lbm_write(lbm_ctx* ctx, int field, const void* src, size_t bytes, int src_on_device);
+
+/* Wait for enqueued work; LBM_E_NONFINITE if a density went bad. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+lbm_status lbm_get_info(lbm_ctx* ctx, lbm_info* info);
+
+/* Step the lattice nsteps times (no measurement) with a HIP event pair
+ * around every kernel launch, and report the mean duration in milliseconds of
+ * each kernel kind: names[i] (static strings) and ms[i] for i < *n_kinds
+ * (cap entries at most).  Synchronises. */
+lbm_status lbm_profile_step(lbm_ctx* ctx, int64_t nsteps, const char** names, double* ms,
+                            int cap, int* n_kinds);
+
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,866 @@
+// api.hip -- the C ABI of lbm.h: contexts, launches, hipGraph step loops.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kGraphSteps = 32;  // steps per captured graph (even: buffer parity is preserved)
+constexpr int kMassBlocks = 1024;
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg{};
+    std::string err;
+    PRState pr{};
+    double wall_mu = 0, rho_m = 0;
+    double mu_ref = 0;  // stored mu is mu - mu_ref (k^2 mu_sat)
+    int dim = 2, Q = 9;
+    bool f64 = false;
+    size_t elem = 4;
+    Dims d{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;  // state S_t is in f[cur]
+    void *rho = nullptr, *mu = nullptr;
+    uint8_t* cls = nullptr;
+    uint32_t* nbmask = nullptr;
+    long long *l1_node = nullptr, *l2_node = nullptr, *b_node = nullptr;
+    uint32_t *l1_mask = nullptr, *l2_mask = nullptr, *b_mask = nullptr;
+    void *l1_inv = nullptr, *l2_inv = nullptr, *b_q = nullptr;
+    int n_l1 = 0, n_l2 = 0, n_b = 0;
+    long long n_fluid = 0;
+    DevCtl* ctl = nullptr;
+    AngleRec* last = nullptr;
+    AngleRec* series = nullptr;
+    int series_capacity = 0;
+    double* mass_part = nullptr;
+    double* mass_out = nullptr;
+    bool have_geometry = false, have_state = false;
+    std::vector<Solid> solids;
+    lbm_measure_opts mopts{0, 32, 0.0};
+    long long t = 0;  // host mirror of the step counter
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(ctx, LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+lbm_status dalloc(lbm_ctx* c, T** p, size_t bytes) {
+    dfree(*p);
+    *p = nullptr;
+    if (bytes == 0) return LBM_OK;
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, LBM_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* c) {
+    for (auto& g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+MeasureParams measure_params(const lbm_ctx* c, const lbm_measure_opts& o) {
+    MeasureParams mp{};
+    const Solid& s = c->solids[o.solid_index];
+    for (int k = 0; k < 3; ++k) {
+        mp.c[k] = k < c->dim ? s.c[k] : 0.0;
+        mp.g[k] = k < c->dim ? c->cfg.g[k] : 0.0;
+    }
+    mp.R = s.r;
+    mp.rho_m = o.rho_m > 0 ? o.rho_m : c->rho_m;
+    mp.n_sectors = c->dim == 2 ? 2 : o.n_sectors;
+    mp.dim = c->dim;
+    return mp;
+}
+
+lbm_status check_measure_opts(lbm_ctx* c, const lbm_measure_opts& o) {
+    if (o.solid_index < 0 || o.solid_index >= (int)c->solids.size())
+        return fail(c, LBM_E_ARG, "measure: solid_index out of range (set solids first)");
+    if (c->dim == 3 && (o.n_sectors < 1 || o.n_sectors > LBM_MAX_SECTORS))
+        return fail(c, LBM_E_ARG, "measure: n_sectors must lie in 1..64");
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// typed launcher
+// ---------------------------------------------------------------------------
+template <class L, typename R, typename C = R>
+struct Run {
+    static Thermo thermo(const lbm_ctx* c) {
+        const double k2 = c->cfg.k * c->cfg.k;
+        const PRState& p = c->pr;
+        Thermo th;
+        th.k2RT = k2 * p.R * p.T;
+        th.k2A = k2 * p.a * p.alpha / (2.0 * std::sqrt(2.0) * p.b);
+        th.k2aal = k2 * p.a * p.alpha;
+        th.b = p.b;
+        th.s2m1 = std::sqrt(2.0) - 1.0;
+        th.s2p1 = std::sqrt(2.0) + 1.0;
+        th.mu_ref = c->mu_ref;
+        th.kappa = c->cfg.kappa;
+        return th;
+    }
+    static Collision<C> collision(const lbm_ctx* c) {
+        Collision<C> cp{};
+        const lbm_config& g = c->cfg;
+        cp.bgk = g.collision == LBM_BGK;
+        cp.omega = (C)(1.0 / g.tau);
+        const double sv = 1.0 / g.tau;
+        for (int k = 0; k < 19; ++k) cp.rate[k] = C(0);
+        for (int k = 0; k < L::Q; ++k) {
+            double s = 0;
+            switch (L::kind(k)) {
+                case 1: s = g.s_e; break;
+                case 2: s = g.s_eps; break;
+                case 3: s = g.s_q; break;
+                case 4: s = sv; break;
+                case 5: s = g.s_pi; break;
+                case 6: s = g.s_m; break;
+                default: s = 0; break;
+            }
+            cp.rate[k] = (C)(s / row_norm2<L>(k));
+        }
+        for (int k = 0; k < 3; ++k) cp.g[k] = (C)(k < c->dim ? g.g[k] : 0.0);
+        cp.g_start = g.g_start_step;
+        return cp;
+    }
+    static dim3 grid(const lbm_ctx* c) { return dim3((c->d.nx + 63) / 64, (c->d.ny + 3) / 4, c->d.nz); }
+
+    // the launches of one step, reading f[src] and writing f[1-src]
+    static void step_launches(lbm_ctx* c, int src, const MeasureParams& mp, hipEvent_t* ev, int* kinds) {
+        const dim3 blk(64, 4, 1), grd = grid(c);
+        const R* fin = (const R*)c->f[src];
+        R* fout = (R*)c->f[1 - src];
+        R* rho = (R*)c->rho;
+        R* mu = (R*)c->mu;
+        const R inv_b = (R)(1.0 / c->pr.b);
+        int k = 0;
+        auto mark = [&](int kind) {
+            if (ev) {
+                (void)hipEventRecord(ev[2 * k + 1], c->stream);
+                kinds[k] = kind;
+                ++k;
+            }
+        };
+        auto start = [&]() {
+            if (ev) (void)hipEventRecord(ev[2 * k], c->stream);
+        };
+        start();
+        k_density<L, R, C><<<grd, blk, 0, c->stream>>>(fin, rho, c->cls, c->d, c->ctl, mp.rho_m, inv_b);
+        mark(0);
+        if (c->n_l1) {
+            start();
+            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
+                                                                        c->n_l1, rho, c->d);
+            mark(1);
+        }
+        if (c->n_l2) {
+            start();
+            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
+                                                                        c->n_l2, rho, c->d);
+            mark(2);
+        }
+        start();
+        k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        mark(3);
+        start();
+        k_collide<L, R, C><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->nbmask, c->d, collision(c), c->ctl);
+        mark(4);
+        if (c->cfg.bc_mode == LBM_BC_BOUZIDI_MC && c->n_b) {
+            start();
+            k_bc<L, R, C><<<(c->n_b + 255) / 256, 256, 0, c->stream>>>(c->b_node, c->b_mask, (const R*)c->b_q, c->n_b,
+                                                                     fout, c->d);
+            mark(5);
+        }
+        start();
+        k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1);
+        mark(6);
+        if (kinds) kinds[k] = -1;
+    }
+
+    // density, solid fill and mu of the current state (no measurement)
+    static void derive(lbm_ctx* c, bool with_mu) {
+        const dim3 blk(64, 4, 1), grd = grid(c);
+        R* rho = (R*)c->rho;
+        MeasureParams mp{};
+        mp.rho_m = c->rho_m;
+        mp.n_sectors = 2;
+        mp.dim = c->dim;
+        k_density<L, R, C><<<grd, blk, 0, c->stream>>>((const R*)c->f[c->cur], rho, c->cls, c->d, c->ctl, mp.rho_m,
+                                                      (R)(1.0 / c->pr.b));
+        if (c->n_l1)
+            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
+                                                                        c->n_l1, rho, c->d);
+        if (c->n_l2)
+            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
+                                                                        c->n_l2, rho, c->d);
+        if (with_mu) k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+    }
+
+    static void velocity(lbm_ctx* c, void* out) {
+        derive(c, true);
+        k_velocity<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((const R*)c->f[c->cur], (const R*)c->rho,
+                                                                     (const R*)c->mu, c->cls, c->d, collision(c), c->t,
+                                                                     (R*)out);
+    }
+
+    static void measure_now(lbm_ctx* c, const MeasureParams& mp) {
+        const dim3 blk(64, 4, 1), grd = grid(c);
+        R* rho = (R*)c->rho;
+        k_density<L, R, C><<<grd, blk, 0, c->stream>>>((const R*)c->f[c->cur], rho, c->cls, c->d, c->ctl, mp.rho_m,
+                                                      (R)(1.0 / c->pr.b));
+        if (c->n_l1)
+            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
+                                                                        c->n_l1, rho, c->d);
+        if (c->n_l2)
+            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
+                                                                        c->n_l2, rho, c->d);
+        k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, nullptr, c->last, 0);
+    }
+
+    static void init_feq(lbm_ctx* c) {
+        k_init_feq<L, R><<<2048, 256, 0, c->stream>>>((const R*)c->rho, (R*)c->f[c->cur], c->cls, c->d.N);
+    }
+
+    static void mass(lbm_ctx* c) {
+        k_mass_partial<L, R><<<kMassBlocks, 256, 0, c->stream>>>((const R*)c->f[c->cur], c->cls, c->d.N, c->mass_part);
+        k_mass_final<<<1, 64, 0, c->stream>>>(c->mass_part, kMassBlocks, c->mass_out);
+    }
+
+};
+
+// dispatch on (lattice, storage precision, arithmetic precision)
+template <template <class, typename, typename> class Op, typename... Args>
+void dispatch(lbm_ctx* c, Args&&... args) {
+    const int p = c->cfg.precision;
+    if (c->dim == 2) {
+        if (p == LBM_F64) Op<D2Q9, double, double>::go(c, args...);
+        else if (p == LBM_F32_MIXED) Op<D2Q9, float, double>::go(c, args...);
+        else Op<D2Q9, float, float>::go(c, args...);
+    } else {
+        if (p == LBM_F64) Op<D3Q19, double, double>::go(c, args...);
+        else if (p == LBM_F32_MIXED) Op<D3Q19, float, double>::go(c, args...);
+        else Op<D3Q19, float, float>::go(c, args...);
+    }
+}
+
+template <class L, typename R, typename C>
+struct OpStep {
+    static void go(lbm_ctx* c, int src, const MeasureParams* mp, hipEvent_t* ev, int* kinds) {
+        Run<L, R, C>::step_launches(c, src, *mp, ev, kinds);
+    }
+};
+template <class L, typename R, typename C>
+struct OpDerive {
+    static void go(lbm_ctx* c, bool with_mu) { Run<L, R, C>::derive(c, with_mu); }
+};
+template <class L, typename R, typename C>
+struct OpVel {
+    static void go(lbm_ctx* c, void* out) { Run<L, R, C>::velocity(c, out); }
+};
+template <class L, typename R, typename C>
+struct OpMeasure {
+    static void go(lbm_ctx* c, const MeasureParams* mp) { Run<L, R, C>::measure_now(c, *mp); }
+};
+template <class L, typename R, typename C>
+struct OpInit {
+    static void go(lbm_ctx* c) { Run<L, R, C>::init_feq(c); }
+};
+template <class L, typename R, typename C>
+struct OpMass {
+    static void go(lbm_ctx* c) { Run<L, R, C>::mass(c); }
+};
+
+// copy a host double array into a device array of the context precision
+lbm_status upload_real(lbm_ctx* c, void** dst, const std::vector<double>& v) {
+    lbm_status s = dalloc(c, (char**)dst, v.size() * c->elem);
+    if (s != LBM_OK || v.empty()) return s;
+    if (c->f64) {
+        HIPCHK(c, hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> t(v.begin(), v.end());
+        HIPCHK(c, hipMemcpy(*dst, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+    }
+    return LBM_OK;
+}
+
+template <typename T>
+lbm_status upload(lbm_ctx* c, T** dst, const std::vector<T>& v) {
+    lbm_status s = dalloc(c, dst, v.size() * sizeof(T));
+    if (s != LBM_OK || v.empty()) return s;
+    HIPCHK(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status ctl_reset(lbm_ctx* c, int every, int force, int cap) {
+    k_ctl_reset<<<1, 64, 0, c->stream>>>(c->ctl, every, force, cap);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status check_status(lbm_ctx* c) {
+    DevCtl h;
+    HIPCHK(c, hipMemcpyAsync(&h, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h.status & 1) return fail(c, LBM_E_NONFINITE, "a density became non-finite, non-positive or >= 1/b");
+    return LBM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void lbm_config_default(lbm_config* cfg, int lattice) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->lattice = lattice;
+    cfg->precision = lattice == LBM_D2Q9 ? LBM_F64 : LBM_F32;
+    cfg->n[0] = cfg->n[1] = 128;
+    cfg->n[2] = lattice == LBM_D2Q9 ? 1 : 128;
+    cfg->axis_bc[0] = cfg->axis_bc[1] = cfg->axis_bc[2] = LBM_PERIODIC;
+    cfg->collision = lattice == LBM_D2Q9 ? LBM_MRT : LBM_BGK;
+    cfg->bc_mode = LBM_BC_HALFWAY;
+    cfg->tau = 1.0;
+    cfg->s_e = 1.64;
+    cfg->s_eps = 1.54;
+    cfg->s_q = 1.9;
+    cfg->s_pi = 1.54;
+    cfg->s_m = 1.9;
+    cfg->Tr = 0.6;
+    cfg->pr_a = 2.0 / 49.0;
+    cfg->pr_b = 2.0 / 21.0;
+    cfg->pr_R = 1.0;
+    cfg->pr_omega = 0.344;
+    cfg->k = 0.28;
+    cfg->kappa = 0.01;
+    cfg->g_start_step = 0;
+    cfg->rho_l = cfg->rho_g = 0.0;
+    cfg->wall_mu = NAN;
+    cfg->stream = nullptr;
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
+    if (!out) return LBM_E_ARG;
+    *out = nullptr;
+    if (!cfg) return LBM_E_ARG;
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_E_NOMEM;
+    c->cfg = *cfg;
+    auto bad = [&](const std::string& m) {
+        delete c;
+        return LBM_E_ARG;
+        (void)m;
+    };
+    if (cfg->lattice != LBM_D2Q9 && cfg->lattice != LBM_D3Q19) return bad("lattice");
+    if (cfg->precision != LBM_F32 && cfg->precision != LBM_F64 && cfg->precision != LBM_F32_MIXED)
+        return bad("precision");
+    c->dim = cfg->lattice == LBM_D2Q9 ? 2 : 3;
+    c->Q = c->dim == 2 ? 9 : 19;
+    c->f64 = cfg->precision == LBM_F64;
+    c->elem = c->f64 ? 8 : 4;
+    if (c->dim == 2 && cfg->n[2] != 1) return bad("n[2] must be 1 for D2Q9");
+    for (int k = 0; k < c->dim; ++k) {
+        if (cfg->n[k] < 5 || cfg->n[k] > (1 << 20)) return bad("n out of range");
+        if (cfg->axis_bc[k] != LBM_PERIODIC && cfg->axis_bc[k] != LBM_WALL) return bad("axis_bc");
+        if (cfg->axis_bc[k] == LBM_WALL && cfg->n[k] < 8) return bad("wall axis needs n >= 8");
+    }
+    const long long N = (long long)cfg->n[0] * cfg->n[1] * (c->dim == 3 ? cfg->n[2] : 1);
+    if ((unsigned long long)N * (unsigned long long)c->Q >= (1ull << 32)) return bad("N * Q must stay below 2^32");
+    if (!(cfg->tau > 0.5)) return bad("tau must exceed 1/2");
+    if (cfg->collision != LBM_MRT && cfg->collision != LBM_BGK) return bad("collision");
+    if (cfg->bc_mode != LBM_BC_HALFWAY && cfg->bc_mode != LBM_BC_BOUZIDI_MC) return bad("bc_mode");
+    if (!(cfg->k > 0) || !(cfg->kappa >= 0) || !(cfg->pr_a > 0) || !(cfg->pr_b > 0) || !(cfg->pr_R > 0))
+        return bad("thermodynamic parameters");
+    c->d.nx = cfg->n[0];
+    c->d.ny = cfg->n[1];
+    c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
+    c->d.N = N;
+    c->pr.a = cfg->pr_a;
+    c->pr.b = cfg->pr_b;
+    c->pr.R = cfg->pr_R;
+    c->pr.omega = cfg->pr_omega;
+    c->pr.Tr = cfg->Tr;
+    std::string err;
+    if (!pr_solve(c->pr, err)) return bad(err);
+    if (cfg->rho_l > 0) c->pr.rho_l = cfg->rho_l;
+    if (cfg->rho_g > 0) c->pr.rho_g = cfg->rho_g;
+    c->rho_m = 0.5 * (c->pr.rho_l + c->pr.rho_g);
+    c->wall_mu = std::isnan(cfg->wall_mu) ? cfg->k * cfg->k * c->pr.mu_sat : cfg->wall_mu;
+    c->mu_ref = cfg->k * cfg->k * c->pr.mu_sat;
+
+    lbm_status s = LBM_OK;
+    if (cfg->stream) {
+        c->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return LBM_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    const size_t fbytes = (size_t)c->Q * N * c->elem;
+    if ((s = dalloc(c, (char**)&c->f[0], fbytes)) || (s = dalloc(c, (char**)&c->f[1], fbytes)) ||
+        (s = dalloc(c, (char**)&c->rho, N * c->elem)) || (s = dalloc(c, (char**)&c->mu, N * c->elem)) ||
+        (s = dalloc(c, &c->cls, (size_t)N)) || (s = dalloc(c, &c->nbmask, (size_t)N * 4)) ||
+        (s = dalloc(c, &c->ctl, sizeof(DevCtl))) || (s = dalloc(c, &c->last, sizeof(AngleRec))) ||
+        (s = dalloc(c, &c->mass_part, kMassBlocks * sizeof(double))) || (s = dalloc(c, &c->mass_out, sizeof(double)))) {
+        lbm_destroy(c);
+        return s;
+    }
+    DevCtl h{};
+    for (auto& k : h.keys) k[0] = k[1] = ~0ull;
+    if (hipMemcpy(c->ctl, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_E_DEVICE;
+    }
+    // a lattice with no solid
+    if (lbm_set_solid(c, nullptr, 0, nullptr) != LBM_OK) {
+        lbm_destroy(c);
+        return LBM_E_DEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    void* ps[] = {c->f[0], c->f[1], c->rho, c->mu, c->cls, c->nbmask, c->l1_node, c->l2_node, c->b_node,
+                  c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
+                  c->mass_part, c->mass_out};
+    for (void* p : ps) dfree(p);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double* mu_w_map) {
+    if (!c) return LBM_E_ARG;
+    if (n < 0 || n > LBM_MAX_SOLIDS || (n > 0 && !prims)) return fail(c, LBM_E_ARG, "set_solid: bad primitive count");
+    std::vector<Solid> ss;
+    for (int i = 0; i < n; ++i) {
+        const lbm_solid& p = prims[i];
+        if (p.kind != LBM_SOLID_SPHERE || !(p.radius > 0)) return fail(c, LBM_E_ARG, "set_solid: bad primitive");
+        if (p.wet_mode != LBM_WET_UNIFORM && p.wet_mode != LBM_WET_STRIPES)
+            return fail(c, LBM_E_ARG, "set_solid: bad wet_mode");
+        if (p.wet_mode == LBM_WET_STRIPES && !(p.stripe_width > 0))
+            return fail(c, LBM_E_ARG, "set_solid: stripe_width must be positive");
+        Solid s{};
+        for (int k = 0; k < 3; ++k) s.c[k] = k < c->dim ? p.center[k] : 0.0;
+        s.r = p.radius;
+        s.wet_mode = p.wet_mode;
+        s.mu1 = p.mu_w;
+        s.mu2 = p.mu_w2;
+        s.width = p.stripe_width;
+        double pl[3] = {p.pole[0], p.pole[1], c->dim == 3 ? p.pole[2] : 0.0};
+        double pn = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        if (pn == 0) {
+            pl[0] = 0; pl[1] = c->dim == 2 ? 1 : 0; pl[2] = c->dim == 2 ? 0 : 1;
+            pn = 1;
+        }
+        for (int k = 0; k < 3; ++k) s.pole[k] = pl[k] / pn;
+        ss.push_back(s);
+    }
+    Geometry g;
+    std::string err;
+    const int wall[3] = {c->cfg.axis_bc[0] == LBM_WALL, c->cfg.axis_bc[1] == LBM_WALL,
+                         c->dim == 3 && c->cfg.axis_bc[2] == LBM_WALL};
+    if (!build_geometry(g, c->dim, c->cfg.n, wall, ss, mu_w_map, c->wall_mu, err)) return fail(c, LBM_E_ARG, err);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->solids = ss;
+    lbm_status s;
+    HIPCHK(c, hipMemcpy(c->cls, g.cls.data(), g.N, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->nbmask, g.nbmask.data(), g.N * 4, hipMemcpyHostToDevice));
+    if ((s = upload(c, &c->l1_node, g.l1_node)) || (s = upload(c, &c->l2_node, g.l2_node)) ||
+        (s = upload(c, &c->b_node, g.b_node)) || (s = upload(c, &c->l1_mask, g.l1_mask)) ||
+        (s = upload(c, &c->l2_mask, g.l2_mask)) || (s = upload(c, &c->b_mask, g.b_mask)) ||
+        (s = upload_real(c, &c->l1_inv, g.l1_inv)) || (s = upload_real(c, &c->l2_inv, g.l2_inv)) ||
+        (s = upload_real(c, &c->b_q, g.b_q)))
+        return s;
+    c->n_l1 = (int)g.l1_node.size();
+    c->n_l2 = (int)g.l2_node.size();
+    c->n_b = (int)g.b_node.size();
+    c->n_fluid = g.n_fluid;
+    // static wall chemical potential on the two solid layers; zero elsewhere
+    {
+        std::vector<double> muh((size_t)g.N, 0.0);
+        for (size_t i = 0; i < g.l1_node.size(); ++i) muh[g.l1_node[i]] = g.l1_mu[i] - c->mu_ref;
+        for (size_t i = 0; i < g.l2_node.size(); ++i) muh[g.l2_node[i]] = g.l2_mu[i] - c->mu_ref;
+        if (c->f64) {
+            HIPCHK(c, hipMemcpy(c->mu, muh.data(), g.N * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> t(muh.begin(), muh.end());
+            HIPCHK(c, hipMemcpy(c->mu, t.data(), g.N * 4, hipMemcpyHostToDevice));
+        }
+        std::vector<char> zero((size_t)g.N * c->elem, 0);
+        HIPCHK(c, hipMemcpy(c->rho, zero.data(), zero.size(), hipMemcpyHostToDevice));
+    }
+    c->have_geometry = true;
+    c->have_state = false;
+    if (!c->solids.empty() && c->mopts.solid_index >= (int)c->solids.size()) c->mopts.solid_index = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_drops(lbm_ctx* c, const lbm_drop* drops, int n, double W) {
+    if (!c) return LBM_E_ARG;
+    if (n < 1 || !drops || !(W > 0)) return fail(c, LBM_E_ARG, "init_drops: need n >= 1 drops and W > 0");
+    const Dims& d = c->d;
+    std::vector<uint8_t> cls(d.N);
+    HIPCHK(c, hipMemcpy(cls.data(), c->cls, d.N, hipMemcpyDeviceToHost));
+    std::vector<double> rho(d.N, 0.0);
+    const double rg = c->pr.rho_g, rl = c->pr.rho_l;
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < d.N; ++i) {
+        if ((cls[i] & 3) != 0) continue;
+        const int x = (int)(i % d.nx), y = (int)((i / d.nx) % d.ny), z = (int)(i / ((long long)d.nx * d.ny));
+        double best = -1e300;
+        for (int k = 0; k < n; ++k) {
+            const double dx = x - drops[k].center[0], dy = y - drops[k].center[1];
+            const double dz = c->dim == 3 ? z - drops[k].center[2] : 0.0;
+            const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+            // Eq. 16
+            const double v = 0.5 * (rg + rl) + 0.5 * (rg - rl) * std::tanh(2.0 * (r - drops[k].radius) / W);
+            if (v > best) best = v;
+        }
+        rho[i] = best;
+    }
+    lbm_status s;
+    if (c->f64) {
+        s = lbm_write(c, LBM_FIELD_RHO, rho.data(), rho.size() * 8, 0);
+    } else {
+        std::vector<float> fr(rho.begin(), rho.end());
+        s = lbm_write(c, LBM_FIELD_RHO, fr.data(), fr.size() * 4, 0);
+    }
+    if (s != LBM_OK) return s;
+    c->t = 0;
+    k_ctl_set<<<1, 64, 0, c->stream>>>(c->ctl, 0, 0, 0, 0, 1);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int src_on_device) {
+    if (!c) return LBM_E_ARG;
+    if (!src) return fail(c, LBM_E_ARG, "write: null source");
+    if (!c->have_geometry) return fail(c, LBM_E_STATE, "write: no geometry");
+    const size_t N = (size_t)c->d.N;
+    const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (field == LBM_FIELD_RHO) {
+        if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "write RHO: bytes must be N * elem");
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(c->rho, src, bytes, kind));
+        // zero both population buffers, then f = f_eq(rho, 0)
+        const size_t fb = (size_t)c->Q * N * c->elem;
+        if (c->f64) {
+            k_fill_value<double><<<2048, 256, 0, c->stream>>>((double*)c->f[0], fb / 8, 0.0);
+            k_fill_value<double><<<2048, 256, 0, c->stream>>>((double*)c->f[1], fb / 8, 0.0);
+        } else {
+            k_fill_value<float><<<2048, 256, 0, c->stream>>>((float*)c->f[0], fb / 4, 0.0f);
+            k_fill_value<float><<<2048, 256, 0, c->stream>>>((float*)c->f[1], fb / 4, 0.0f);
+        }
+        dispatch<OpInit>(c);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->have_state = true;
+        return LBM_OK;
+    }
+    if (field == LBM_FIELD_F) {
+        const size_t fb = (size_t)c->Q * N * c->elem;
+        if (bytes != fb) return fail(c, LBM_E_ARG, "write F: bytes must be Q * N * elem");
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(c->f[c->cur], src, bytes, kind));
+        c->have_state = true;
+        return LBM_OK;
+    }
+    return fail(c, LBM_E_ARG, "write: field must be RHO or F");
+}
+
+lbm_status lbm_set_measure(lbm_ctx* c, const lbm_measure_opts* o) {
+    if (!c || !o) return LBM_E_ARG;
+    lbm_status s = check_measure_opts(c, *o);
+    if (s) return s;
+    c->mopts = *o;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+static lbm_status ensure_series(lbm_ctx* c, int cap) {
+    if (cap <= c->series_capacity) return LBM_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    lbm_status s = dalloc(c, &c->series, (size_t)cap * sizeof(AngleRec));
+    if (s) {
+        c->series_capacity = 0;
+        return s;
+    }
+    c->series_capacity = cap;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* series, int cap, int* n_written) {
+    if (!c) return LBM_E_ARG;
+    if (n_written) *n_written = 0;
+    if (!c->have_state) return fail(c, LBM_E_STATE, "step: no initial state (call lbm_init_drops or lbm_write)");
+    if (nsteps < 0 || measure_every < 0 || cap < 0) return fail(c, LBM_E_ARG, "step: negative argument");
+    if (measure_every > 0 && c->solids.empty()) return fail(c, LBM_E_ARG, "step: measurement needs a solid");
+    if (series && cap > 0) {
+        lbm_status s = ensure_series(c, cap);
+        if (s) return s;
+    } else if (c->series_capacity == 0) {
+        lbm_status s = ensure_series(c, 1);
+        if (s) return s;
+    }
+    MeasureParams mp{};
+    if (!c->solids.empty()) {
+        lbm_status s = check_measure_opts(c, c->mopts);
+        if (s) return s;
+        mp = measure_params(c, c->mopts);
+    } else {
+        mp.rho_m = c->rho_m;
+        mp.n_sectors = 2;
+        mp.dim = c->dim;
+    }
+    lbm_status s = ctl_reset(c, measure_every, 0, series ? cap : 0);
+    if (s) return s;
+    int64_t done = 0;
+    // odd leading step to reach buffer parity 0, then whole graphs, then the rest
+    while (done < nsteps && (c->cur != 0 || nsteps - done < kGraphSteps)) {
+        dispatch<OpStep>(c, c->cur, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+        c->cur ^= 1;
+        ++done;
+        ++c->t;
+    }
+    if (nsteps - done >= kGraphSteps) {
+        if (!c->graph[0]) {
+            hipGraph_t g;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < kGraphSteps; ++k) dispatch<OpStep>(c, k & 1, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+            HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+            hipError_t e = hipGraphInstantiate(&c->graph[0], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->graph[0] = nullptr;
+                return fail(c, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+        }
+        while (nsteps - done >= kGraphSteps) {
+            HIPCHK(c, hipGraphLaunch(c->graph[0], c->stream));
+            done += kGraphSteps;
+            c->t += kGraphSteps;
+        }
+    }
+    while (done < nsteps) {
+        dispatch<OpStep>(c, c->cur, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+        c->cur ^= 1;
+        ++done;
+        ++c->t;
+    }
+    HIPCHK(c, hipGetLastError());
+    if (series && cap > 0) {
+        DevCtl h;
+        HIPCHK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int nw = h.series_count < cap ? h.series_count : cap;
+        if (nw > 0) HIPCHK(c, hipMemcpy(series, c->series, (size_t)nw * sizeof(AngleRec), hipMemcpyDeviceToHost));
+        if (n_written) *n_written = nw;
+        if (h.status & 1) return fail(c, LBM_E_NONFINITE, "a density became non-finite, non-positive or >= 1/b");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_measure_angle(lbm_ctx* c, const lbm_measure_opts* o, lbm_angle* out) {
+    if (!c || !o || !out) return LBM_E_ARG;
+    if (!c->have_state) return fail(c, LBM_E_STATE, "measure: no state");
+    lbm_status s = check_measure_opts(c, *o);
+    if (s) return s;
+    const MeasureParams mp = measure_params(c, *o);
+    if ((s = ctl_reset(c, 0, 1, 0))) return s;
+    dispatch<OpMeasure>(c, &mp);
+    if ((s = ctl_reset(c, 0, 0, 0))) return s;
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out, c->last, sizeof(AngleRec), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out->step = c->t;
+    if (out->status != 0) return fail(c, LBM_E_NO_CONTACT_LINE, "no sector holds both selected crossings");
+    return LBM_OK;
+}
+
+lbm_status lbm_read(lbm_ctx* c, int field, void* dst, size_t bytes, int dst_on_device) {
+    if (!c || !dst) return c ? fail(c, LBM_E_ARG, "read: null destination") : LBM_E_ARG;
+    if (!c->have_state && field != LBM_FIELD_CLASS) return fail(c, LBM_E_STATE, "read: no state");
+    const size_t N = (size_t)c->d.N;
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    lbm_status s;
+    switch (field) {
+        case LBM_FIELD_RHO:
+        case LBM_FIELD_MU:
+            if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "read: bytes must be N * elem");
+            if ((s = ctl_reset(c, 0, 0, 0))) return s;
+            dispatch<OpDerive>(c, field == LBM_FIELD_MU);
+            HIPCHK(c, hipGetLastError());
+            HIPCHK(c, hipMemcpyAsync(dst, field == LBM_FIELD_RHO ? c->rho : c->mu, bytes, kind, c->stream));
+            if (field == LBM_FIELD_MU) {
+                // undo the stored shift on fluid and solid-layer nodes (deeper solid reads mu_ref)
+                if (dst_on_device) {
+                    if (c->f64) k_add_value<double><<<1024, 256, 0, c->stream>>>((double*)dst, N, c->mu_ref);
+                    else k_add_value<float><<<1024, 256, 0, c->stream>>>((float*)dst, N, (float)c->mu_ref);
+                    HIPCHK(c, hipGetLastError());
+                } else {
+                    HIPCHK(c, hipStreamSynchronize(c->stream));
+                    if (c->f64) for (size_t i = 0; i < N; ++i) ((double*)dst)[i] += c->mu_ref;
+                    else for (size_t i = 0; i < N; ++i) ((float*)dst)[i] = (float)((double)((float*)dst)[i] + c->mu_ref);
+                }
+            }
+            break;
+        case LBM_FIELD_F:
+            if (bytes != (size_t)c->Q * N * c->elem) return fail(c, LBM_E_ARG, "read F: bytes must be Q * N * elem");
+            HIPCHK(c, hipMemcpyAsync(dst, c->f[c->cur], bytes, kind, c->stream));
+            break;
+        case LBM_FIELD_VEL: {
+            if (bytes != 3 * N * c->elem) return fail(c, LBM_E_ARG, "read VEL: bytes must be 3 * N * elem");
+            if ((s = ctl_reset(c, 0, 0, 0))) return s;
+            void* tmp = nullptr;
+            if (dst_on_device) tmp = dst;
+            else if ((s = dalloc(c, (char**)&tmp, bytes))) return s;
+            dispatch<OpVel>(c, tmp);
+            HIPCHK(c, hipGetLastError());
+            if (!dst_on_device) {
+                HIPCHK(c, hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                dfree(tmp);
+            }
+            break;
+        }
+        case LBM_FIELD_CLASS: {
+            if (bytes != N) return fail(c, LBM_E_ARG, "read CLASS: bytes must be N");
+            std::vector<uint8_t> h(N);
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            HIPCHK(c, hipMemcpy(h.data(), c->cls, N, hipMemcpyDeviceToHost));
+            for (auto& v : h) v &= 3;
+            HIPCHK(c, hipMemcpy(dst, h.data(), N, dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+            break;
+        }
+        case LBM_FIELD_MASS:
+            if (bytes != 8) return fail(c, LBM_E_ARG, "read MASS: bytes must be 8");
+            dispatch<OpMass>(c);
+            HIPCHK(c, hipGetLastError());
+            HIPCHK(c, hipMemcpyAsync(dst, c->mass_out, 8, kind, c->stream));
+            break;
+        default:
+            return fail(c, LBM_E_ARG, "read: unknown field");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+    if (!c) return LBM_E_ARG;
+    return check_status(c);
+}
+
+lbm_status lbm_get_info(lbm_ctx* c, lbm_info* info) {
+    if (!c || !info) return LBM_E_ARG;
+    std::memset(info, 0, sizeof *info);
+    info->Tc = c->pr.Tc;
+    info->T = c->pr.T;
+    info->alpha = c->pr.alpha;
+    info->rho_g = c->pr.rho_g;
+    info->rho_l = c->pr.rho_l;
+    info->mu_sat = c->pr.mu_sat;
+    info->p_sat = c->pr.p_sat;
+    info->wall_mu = c->wall_mu;
+    info->rho_m = c->rho_m;
+    info->Q = c->Q;
+    info->precision = c->cfg.precision;
+    info->N = c->d.N;
+    info->step = c->t;
+    info->n_fluid = c->n_fluid;
+    info->n_layer1 = c->n_l1;
+    info->n_layer2 = c->n_l2;
+    info->n_boundary = c->n_b;
+    return LBM_OK;
+}
+
+lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, double* ms, int cap, int* n_kinds) {
+    static const char* kNames[7] = {"k_density", "k_fill_layer1", "k_fill_layer2", "k_mu",
+                                    "k_collide", "k_bc",          "k_finalize"};
+    if (!c || !names || !ms || !n_kinds) return LBM_E_ARG;
+    if (!c->have_state) return fail(c, LBM_E_STATE, "profile: no state");
+    if (nsteps < 1) return fail(c, LBM_E_ARG, "profile: nsteps >= 1");
+    MeasureParams mp{};
+    if (!c->solids.empty()) mp = measure_params(c, c->mopts);
+    else { mp.rho_m = c->rho_m; mp.n_sectors = 2; mp.dim = c->dim; }
+    lbm_status s = ctl_reset(c, 0, 0, 0);
+    if (s) return s;
+    hipEvent_t ev[16];
+    for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+    double tot[7] = {0, 0, 0, 0, 0, 0, 0};
+    int cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t t = 0; t < nsteps; ++t) {
+        int kinds[9];
+        dispatch<OpStep>(c, c->cur, &mp, ev, kinds);
+        c->cur ^= 1;
+        ++c->t;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int k = 0; k < 8 && kinds[k] >= 0; ++k) {
+            float e = 0;
+            HIPCHK(c, hipEventElapsedTime(&e, ev[2 * k], ev[2 * k + 1]));
+            tot[kinds[k]] += e;
+            cnt[kinds[k]] += 1;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    int n = 0;
+    for (int k = 0; k < 7 && n < cap; ++k) {
+        if (!cnt[k]) continue;
+        names[n] = kNames[k];
+        ms[n] = tot[k] / cnt[k];
+        ++n;
+    }
+    *n_kinds = n;
+    return check_status(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,719 @@
+// kernels.hpp -- HIP kernels of one multiphase lattice Boltzmann step on gfx950.
+//
+// One step t -> t+1 (paper Sec. II and Sec. III A), as separate launches:
+//   k_density   rho = sum_i S_i over fluid nodes; on measure steps also the
+//               integer centroid sums of the liquid (rho >= rho_m)
+//   k_fill      Eq. 14 over the compact list of first-layer solid nodes, then
+//               (second launch) over the second layer
+//   k_mu        mu = k^2 psi'(rho) - kappa lap4(rho) on fluid nodes (Eq. 11-12);
+//               on measure steps the same pass finds the isodensity crossings
+//               of Eq. 15 near the substrate and keeps, per sector and band,
+//               the crossing nearest 1 or 2 lu from the wall (64-bit atomicMin)
+//   k_collide   F = -rho grad4(mu) + cs^2 grad4(rho) + rho g (Eq. 7), MRT or BGK
+//               relaxation (Eq. 1-3) with exact-difference forcing (Eq. 13), then
+//               push streaming (Eq. 4) with halfway bounce-back at solid links
+//   k_bc        (linear interpolated bounce-back only) replaces the halfway
+//               values at cut links and adds the mass correction to S_0
+//   k_finalize  one block: on measure steps turns the selected crossings into
+//               contact angles (secant, contact point, tangent; Fig. 1), then
+//               clears the reduction slots and advances t
+// The wall chemical potential of the two solid layers is static and is written
+// into mu once, when the solids are set.
+//
+// Data layout in HBM: populations structure-of-arrays [Q][N], x fastest, two
+// buffers (state S_t in one, S_{t+1} written to the other); rho[N], mu[N] in
+// the step precision; cls[N] uint8 (bits 0-1 class, bit 2 boundary fluid
+// node); nbmask[N] uint32 (bit i: neighbour x+e_i is solid), read only for
+// boundary nodes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum : uint8_t { CLS_FLUID = 0, CLS_L1 = 1, CLS_L2 = 2, CLS_DEEP = 3, CLS_MASK = 3, CLS_BOUNDARY = 4 };
+
+struct Dims {
+    int nx, ny, nz;
+    long long N;
+};
+
+// Peng-Robinson coefficients of psi'(rho) (Eq. 11, C = 0), pre-scaled by k^2.
+// psi' is evaluated in double precision; the kernels store mu - mu_ref with
+// mu_ref = k^2 mu_sat, which leaves every gradient unchanged and keeps FP32
+// storage of mu accurate near coexistence.
+struct Thermo {
+    double k2RT;      // k^2 R T
+    double k2A;       // k^2 a alpha / (2 sqrt2 b)
+    double k2aal;     // k^2 a alpha
+    double b;
+    double s2m1, s2p1;  // sqrt2 - 1, sqrt2 + 1
+    double mu_ref;
+    double kappa;
+};
+
+template <typename R>
+struct Collision {
+    int bgk;
+    R omega;         // 1/tau for the BGK path
+    R rate[19];      // MRT: s_k / |row_k|^2 per moment
+    R g[3];
+    long long g_start;
+};
+
+// Reduction slots of the in-step measurement and the step counter.
+struct DevCtl {
+    long long t;                 // completed steps
+    int every;                   // measurement cadence of the running lbm_step call
+    int force_measure;           // 1: measure whatever t is (standalone measurement)
+    int status;                  // bit 0: non-finite / non-physical density seen
+    int series_count, series_cap;
+    int pad_;
+    unsigned long long cnt, sx, sy, sz;      // liquid centroid sums
+    unsigned long long keys[64][2];          // per sector, per band (1 lu, 2 lu)
+};
+
+struct MeasureParams {
+    double c[3];     // substrate centre
+    double R;        // substrate radius
+    double rho_m;    // isodensity level
+    double g[3];     // body acceleration (advancing side)
+    int n_sectors;
+    int dim;
+};
+
+// Result record; the layout is that of lbm_angle in lbm.h.
+struct AngleRec {
+    long long step;
+    int status, n_sectors, n_valid, pad_;
+    double mean_deg, adv_deg, rec_deg;
+    double axis[3];
+    double sector_deg[64];
+    double contact[64][3];
+};
+
+__device__ __forceinline__ bool measuring(const DevCtl* ctl) {
+    return ctl->force_measure || (ctl->every > 0 && (ctl->t % ctl->every) == 0);
+}
+
+__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ double psi_prime(double rho, const Thermo& th) {
+    const double br = th.b * rho;
+    const double om = 1.0 - br;
+    const double t1 = th.k2RT * log(rho / om);
+    const double t2 = th.k2A * log((th.s2m1 + br) / (th.s2p1 - br));
+    const double t3 = th.k2RT / om;
+    const double t4 = th.k2aal * rho / (1.0 + 2.0 * br - br * br);
+    return t1 - t2 + t3 - t4;
+}
+
+// fourth-order central differences (Sec. II B) written on differences of
+// neighbouring values, which are exact in floating point where the field is smooth
+template <typename R>
+__device__ __forceinline__ R d1c(R m2, R m1, R p1, R p2) {
+    return ((m2 - p2) + R(8) * (p1 - m1)) * R(1.0 / 12.0);
+}
+template <typename R>
+__device__ __forceinline__ R d2c(R m2, R m1, R c, R p1, R p2) {
+    return (R(16) * ((m1 - c) + (p1 - c)) - ((m2 - c) + (p2 - c))) * R(1.0 / 12.0);
+}
+
+// ---------------------------------------------------------------------------
+// density (+ liquid centroid on measure steps)
+// ---------------------------------------------------------------------------
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __restrict__ rho,
+                                                 const uint8_t* __restrict__ cls, Dims d,
+                                                 DevCtl* __restrict__ ctl, double rho_m, R inv_b) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool in = x < d.nx && y < d.ny;
+    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    bool liquid = false;
+    if (in && (cls[idx] & CLS_MASK) == CLS_FLUID) {
+        C s = C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) s += (C)f[(size_t)i * d.N + idx];
+        rho[idx] = (R)s;
+        if (!(s > C(0) && s < (C)inv_b)) atomicOr(&ctl->status, 1);  // also catches NaN
+        liquid = (double)s >= rho_m;
+    }
+    if (!measuring(ctl)) return;
+    // block reduction of (count, x, y, z) over liquid nodes
+    __shared__ unsigned long long red[4][4];
+    unsigned long long v[4] = {liquid ? 1ull : 0ull, liquid ? (unsigned long long)x : 0ull,
+                               liquid ? (unsigned long long)y : 0ull, liquid ? (unsigned long long)z : 0ull};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += __shfl_down(v[k], off, 64);
+    const int lane = threadIdx.x, wave = threadIdx.y;
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (wave == 0 && lane < 4) {
+        unsigned long long s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        if (s) atomicAdd((&ctl->cnt) + lane, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 14 over a compact list: rho(s) = sum_i w_i rho(s+e_i) s_w / sum_i w_i s_w
+// ---------------------------------------------------------------------------
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_fill(const long long* __restrict__ node, const uint32_t* __restrict__ mask,
+                                              const R* __restrict__ inv_den, int count, R* __restrict__ rho, Dims d) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const long long idx = node[k];
+    const uint32_t m = mask[k];
+    const int x = (int)(idx % d.nx), y = (int)((idx / d.nx) % d.ny), z = (int)(idx / ((long long)d.nx * d.ny));
+    C num = C(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        if (m & (1u << i)) {
+            const int X = wrapc(x + L::E[i][0], d.nx), Y = wrapc(y + L::E[i][1], d.ny);
+            const int Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) : 0;
+            num += C(L::w(i)) * (C)rho[((long long)Z * d.ny + Y) * d.nx + X];
+        }
+    }
+    rho[idx] = (R)(num * (C)inv_den[k]);
+}
+
+// ---------------------------------------------------------------------------
+// measurement helpers (double precision, shared by k_mu and k_finalize)
+// ---------------------------------------------------------------------------
+struct Frame {
+    double a[3], b1[3], b2[3];
+    bool ok;
+};
+
+__device__ inline Frame make_frame(const DevCtl* ctl, const MeasureParams& mp) {
+    Frame F;
+    const unsigned long long n = ctl->cnt;
+    F.ok = n > 0;
+    double G[3] = {0, 0, 0};
+    if (n) {
+        G[0] = (double)ctl->sx / (double)n;
+        G[1] = (double)ctl->sy / (double)n;
+        G[2] = mp.dim == 3 ? (double)ctl->sz / (double)n : 0.0;
+    }
+    double a[3] = {G[0] - mp.c[0], G[1] - mp.c[1], mp.dim == 3 ? G[2] - mp.c[2] : 0.0};
+    double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    if (an > 0) {
+        a[0] /= an; a[1] /= an; a[2] /= an;
+    } else {
+        a[0] = 0; a[1] = mp.dim == 2 ? 1.0 : 0.0; a[2] = mp.dim == 2 ? 0.0 : 1.0;
+    }
+    // reference axis: the lattice axis least aligned with a, compared on a 1/1024 grid
+    int kb = 0;
+    long long best = 1ll << 40;
+    for (int k = 0; k < mp.dim; ++k) {
+        long long qv = llround(fabs(a[k]) * 1024.0);
+        if (qv < best) { best = qv; kb = k; }
+    }
+    double b[3] = {0, 0, 0};
+    b[kb] = 1.0;
+    const double ab = a[kb];
+    for (int k = 0; k < 3; ++k) b[k] -= ab * a[k];
+    const double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    for (int k = 0; k < 3; ++k) { F.a[k] = a[k]; F.b1[k] = b[k] / bn; }
+    F.b2[0] = a[1] * F.b1[2] - a[2] * F.b1[1];
+    F.b2[1] = a[2] * F.b1[0] - a[0] * F.b1[2];
+    F.b2[2] = a[0] * F.b1[1] - a[1] * F.b1[0];
+    return F;
+}
+
+__device__ inline int sector_of(const double r[3], const Frame& F, int dim, int ns) {
+    const double r1 = r[0] * F.b1[0] + r[1] * F.b1[1] + r[2] * F.b1[2];
+    if (dim == 2) return r1 >= 0.0 ? 0 : 1;
+    const double r2 = r[0] * F.b2[0] + r[1] * F.b2[1] + r[2] * F.b2[2];
+    const double psi = atan2(r2, r1);
+    int s = (int)floor((psi + M_PI) / (2.0 * M_PI) * ns);
+    if (s >= ns) s -= ns;
+    if (s < 0) s = 0;
+    return s;
+}
+
+// crossing point of Eq. 15 on the link from gas node (x,y,z) along e
+__device__ inline void crossing_point(double rho_g_node, double rho_l_node, double rho_m, int x, int y, int z,
+                                      int ex, int ey, int ez, double p[3]) {
+    const double t = (rho_m - rho_g_node) / (rho_l_node - rho_g_node);
+    p[0] = x + t * ex;
+    p[1] = y + t * ey;
+    p[2] = z + t * ez;
+}
+
+// ---------------------------------------------------------------------------
+// chemical potential (+ fused crossing search on measure steps)
+// ---------------------------------------------------------------------------
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __restrict__ mu,
+                                            const uint8_t* __restrict__ cls, Dims d, Thermo th,
+                                            DevCtl* __restrict__ ctl, MeasureParams mp) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool in = x < d.nx && y < d.ny;
+    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    const bool fluid = in && (cls[idx] & CLS_MASK) == CLS_FLUID;
+    R r0 = R(0);
+    if (fluid) {
+        r0 = rho[idx];
+        const long long sx = 1, sy = d.nx, sz = (long long)d.nx * d.ny;
+        const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
+        const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
+        const long long row = ((long long)z * d.ny + y) * d.nx;
+        const long long pl = (long long)z * sz;
+        const C c0 = (C)r0;
+        C lap = d2c<C>(rho[row + xm2], rho[row + xm1], c0, rho[row + xp1], rho[row + xp2]);
+        lap += d2c<C>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], c0, rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
+        if (L::D == 3) {
+            const int zm1 = wrapc(z - 1, d.nz), zm2 = wrapc(z - 2, d.nz), zp1 = wrapc(z + 1, d.nz), zp2 = wrapc(z + 2, d.nz);
+            const long long col = (long long)y * sy + x;
+            lap += d2c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], c0, rho[zp1 * sz + col], rho[zp2 * sz + col]);
+        }
+        (void)sx;
+        mu[idx] = (R)((psi_prime((double)r0, th) - th.mu_ref) - th.kappa * (double)lap);
+    }
+    if (!measuring(ctl)) return;
+    // gas-side nodes near the substrate test their links for a crossing
+    bool cand = false;
+    double rx = x - mp.c[0], ry = y - mp.c[1], rz = (L::D == 3) ? z - mp.c[2] : 0.0;
+    if (fluid && (double)r0 < mp.rho_m) {
+        const double dn = sqrt(rx * rx + ry * ry + rz * rz) - mp.R;
+        cand = dn < 4.0;  // crossings lie within sqrt(2) of the node; bands end at 2.5
+    }
+    if (__ballot(cand) == 0) return;  // whole wave away from the contact region
+    if (!cand) return;
+    const Frame F = make_frame(ctl, mp);
+    if (!F.ok) return;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int X = wrapc(x + L::E[i][0], d.nx), Y = wrapc(y + L::E[i][1], d.ny);
+        const int Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) : 0;
+        const long long j = ((long long)Z * d.ny + Y) * d.nx + X;
+        if ((cls[j] & CLS_MASK) != CLS_FLUID) continue;
+        const double rl = (double)rho[j];
+        if (!(rl >= mp.rho_m)) continue;
+        double p[3];
+        crossing_point((double)r0, rl, mp.rho_m, x, y, z, L::E[i][0], L::E[i][1], L::E[i][2], p);
+        const double r[3] = {p[0] - mp.c[0], p[1] - mp.c[1], p[2] - mp.c[2]};
+        const double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) - mp.R;
+        if (!(dist >= 0.5 && dist < 2.5)) continue;
+        const int band = dist < 1.5 ? 1 : 2;
+        const int s = sector_of(r, F, mp.dim, mp.n_sectors);
+        const float kv = (float)fabs(dist - (double)band);
+        const unsigned long long key =
+            ((unsigned long long)__float_as_uint(kv) << 32) | (unsigned long long)(idx * L::Q + i);
+        atomicMin(&ctl->keys[s][band - 1], key);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collision + push streaming
+// ---------------------------------------------------------------------------
+template <class L, typename R>
+__device__ __forceinline__ void equilibrium(R rho, R ux, R uy, R uz, R feq[L::Q]) {
+    const R uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const R eu = R(L::E[i][0]) * ux + R(L::E[i][1]) * uy + R(L::E[i][2]) * uz;
+        feq[i] = rho * R(L::w(i)) * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+    }
+}
+
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* __restrict__ fout,
+                                                 const R* __restrict__ rho, const R* __restrict__ mu,
+                                                 const uint8_t* __restrict__ cls, const uint32_t* __restrict__ nbmask,
+                                                 Dims d, Collision<C> cp, const DevCtl* __restrict__ ctl) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= d.nx || y >= d.ny) return;
+    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    const uint8_t c = cls[idx];
+    if ((c & CLS_MASK) != CLS_FLUID) return;
+
+    const long long sy = d.nx, sz = (long long)d.nx * d.ny;
+    const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
+    const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
+    const int zm1 = L::D == 3 ? wrapc(z - 1, d.nz) : 0, zm2 = L::D == 3 ? wrapc(z - 2, d.nz) : 0;
+    const int zp1 = L::D == 3 ? wrapc(z + 1, d.nz) : 0, zp2 = L::D == 3 ? wrapc(z + 2, d.nz) : 0;
+    const long long row = (long long)z * sz + (long long)y * sy;
+    const long long pl = (long long)z * sz;
+    const long long col = (long long)y * sy + x;
+
+    // Eq. 7 with fourth-order central differences
+    const C r0 = (C)rho[idx];
+    C gmx = d1c<C>(mu[row + xm2], mu[row + xm1], mu[row + xp1], mu[row + xp2]);
+    C grx = d1c<C>(rho[row + xm2], rho[row + xm1], rho[row + xp1], rho[row + xp2]);
+    C gmy = d1c<C>(mu[pl + ym2 * sy + x], mu[pl + ym1 * sy + x], mu[pl + yp1 * sy + x], mu[pl + yp2 * sy + x]);
+    C gry = d1c<C>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
+    C gmz = C(0), grz = C(0);
+    if (L::D == 3) {
+        gmz = d1c<C>(mu[zm2 * sz + col], mu[zm1 * sz + col], mu[zp1 * sz + col], mu[zp2 * sz + col]);
+        grz = d1c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], rho[zp1 * sz + col], rho[zp2 * sz + col]);
+    }
+    const bool grav = ctl->t >= cp.g_start;
+    const C third = C(1.0 / 3.0);
+    C Fx = -r0 * gmx + grx * third, Fy = -r0 * gmy + gry * third, Fz = -r0 * gmz + grz * third;
+    if (grav) {
+        Fx += r0 * cp.g[0];
+        Fy += r0 * cp.g[1];
+        Fz += r0 * cp.g[2];
+    }
+
+    C f[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) f[i] = (C)fin[(size_t)i * d.N + idx];
+    C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        rs += f[i];
+        if (L::E[i][0]) jx += C(L::E[i][0]) * f[i];
+        if (L::E[i][1]) jy += C(L::E[i][1]) * f[i];
+        if (L::E[i][2]) jz += C(L::E[i][2]) * f[i];
+    }
+    const C ir = C(1) / rs;
+    const C ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    C feq[L::Q], feq2[L::Q];
+    equilibrium<L, C>(rs, ux, uy, uz, feq);
+    equilibrium<L, C>(rs, ux + Fx * ir, uy + Fy * ir, uz + Fz * ir, feq2);
+
+    C out[L::Q];
+    if (cp.bgk) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) out[i] = f[i] - cp.omega * (f[i] - feq[i]) + (feq2[i] - feq[i]);
+    } else {
+        C dev[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            dev[i] = f[i] - feq[i];
+            out[i] = f[i] + (feq2[i] - feq[i]);
+        }
+        // non-conserved moments of the deviation, relaxed and mapped back by M^T D^-1
+#pragma unroll
+        for (int k = 0; k < L::Q; ++k) {
+            if (L::kind(k) == 0) continue;
+            C mk = C(0);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const double mki = L::m(k, i);
+                if (mki != 0.0) mk += C(mki) * dev[i];
+            }
+            const C ck = mk * cp.rate[k];
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const double mki = L::m(k, i);
+                if (mki != 0.0) out[i] -= C(mki) * ck;
+            }
+        }
+    }
+
+    // push streaming; a link into a solid node bounces back to the node itself
+    const uint32_t bm = (c & CLS_BOUNDARY) ? nbmask[idx] : 0u;
+    const int xs[3] = {xm1, x, xp1};
+    const int ys[3] = {ym1, y, yp1};
+    const int zs[3] = {zm1, z, zp1};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        if (bm & (1u << i)) {
+            fout[(size_t)L::OPP[i] * d.N + idx] = (R)out[i];
+        } else {
+            const int X = xs[L::E[i][0] + 1], Y = ys[L::E[i][1] + 1], Z = zs[L::E[i][2] + 1];
+            fout[(size_t)i * d.N + ((long long)Z * d.ny + Y) * d.nx + X] = (R)out[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// linear interpolated bounce-back with mass correction (after k_collide)
+// ---------------------------------------------------------------------------
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_bc(const long long* __restrict__ node, const uint32_t* __restrict__ nbm,
+                                            const R* __restrict__ qv, int count, R* __restrict__ f, Dims d) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const long long idx = node[k];
+    const uint32_t m = nbm[k];
+    const int x = (int)(idx % d.nx), y = (int)((idx / d.nx) % d.ny), z = (int)(idx / ((long long)d.nx * d.ny));
+    C val[L::Q], outj[L::Q];
+#pragma unroll
+    for (int j = 1; j < L::Q; ++j) {
+        val[j] = C(0);
+        outj[j] = C(0);
+        if (!(m & (1u << j))) continue;
+        const int ib = L::OPP[j];
+        const C q = (C)qv[(size_t)k * L::Q + j];
+        const C oj = (C)f[(size_t)ib * d.N + idx];  // halfway value = post-collision f_j(x)
+        C v = oj;
+        if (q < C(0.5)) {
+            if (!(m & (1u << ib))) v = C(2) * q * oj + (C(1) - C(2) * q) * (C)f[(size_t)j * d.N + idx];
+        } else {
+            C fib;
+            if (m & (1u << ib)) {
+                fib = (C)f[(size_t)j * d.N + idx];
+            } else {
+                const int X = wrapc(x + L::E[ib][0], d.nx), Y = wrapc(y + L::E[ib][1], d.ny);
+                const int Z = L::D == 3 ? wrapc(z + L::E[ib][2], d.nz) : 0;
+                fib = (C)f[(size_t)ib * d.N + ((long long)Z * d.ny + Y) * d.nx + X];
+            }
+            v = oj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * fib;
+        }
+        val[j] = v;
+        outj[j] = oj;
+    }
+    C dm = C(0);
+#pragma unroll
+    for (int j = 1; j < L::Q; ++j) {
+        if (!(m & (1u << j))) continue;
+        f[(size_t)L::OPP[j] * d.N + idx] = (R)val[j];
+        dm += outj[j] - val[j];
+    }
+    f[idx] = (R)((C)f[idx] + dm);
+}
+
+// ---------------------------------------------------------------------------
+// finalize: contact angles from the selected crossings; clear; advance t
+// ---------------------------------------------------------------------------
+template <class L, typename R>
+__global__ void __launch_bounds__(64) k_finalize(const R* __restrict__ rho, DevCtl* __restrict__ ctl, Dims d,
+                                                 MeasureParams mp, AngleRec* __restrict__ series,
+                                                 AngleRec* __restrict__ last, int tick) {
+    const int s = threadIdx.x;
+    const bool meas = measuring(ctl);
+    __shared__ double th[64];
+    __shared__ double cpt[64][3];
+    if (meas) {
+        const Frame F = make_frame(ctl, mp);
+        double theta = NAN, cp3[3] = {NAN, NAN, NAN};
+        if (F.ok && s < mp.n_sectors) {
+            const unsigned long long k1 = ctl->keys[s][0], k2 = ctl->keys[s][1];
+            if (k1 != ~0ull && k2 != ~0ull) {
+                double P[2][3];
+                const unsigned long long ks[2] = {k1, k2};
+                for (int b = 0; b < 2; ++b) {
+                    const unsigned long long id = ks[b] & 0xffffffffull;
+                    const long long node = (long long)(id / L::Q);
+                    const int i = (int)(id % L::Q);
+                    int ex = 0, ey = 0, ez = 0;
+#pragma unroll
+                    for (int q = 0; q < L::Q; ++q)
+                        if (q == i) { ex = L::E[q][0]; ey = L::E[q][1]; ez = L::E[q][2]; }
+                    const int x = (int)(node % d.nx), y = (int)((node / d.nx) % d.ny);
+                    const int z = (int)(node / ((long long)d.nx * d.ny));
+                    const int X = wrapc(x + ex, d.nx), Y = wrapc(y + ey, d.ny);
+                    const int Z = L::D == 3 ? wrapc(z + ez, d.nz) : 0;
+                    const long long j = ((long long)Z * d.ny + Y) * d.nx + X;
+                    crossing_point((double)rho[node], (double)rho[j], mp.rho_m, x, y, z, ex, ey, ez, P[b]);
+                }
+                // meridional coordinates (w: distance from the drop axis, s: along it)
+                double r1[3], r2[3];
+                for (int k = 0; k < 3; ++k) { r1[k] = P[0][k] - mp.c[k]; r2[k] = P[1][k] - mp.c[k]; }
+                const double s1 = r1[0] * F.a[0] + r1[1] * F.a[1] + r1[2] * F.a[2];
+                const double s2 = r2[0] * F.a[0] + r2[1] * F.a[1] + r2[2] * F.a[2];
+                double q1[3], q2[3];
+                for (int k = 0; k < 3; ++k) { q1[k] = r1[k] - s1 * F.a[k]; q2[k] = r2[k] - s2 * F.a[k]; }
+                const double w1 = sqrt(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]);
+                const double w2 = sqrt(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2]);
+                const double dw = w2 - w1, ds = s2 - s1;
+                const double A = dw * dw + ds * ds;
+                if (A > 0.0) {
+                    // secant P1 + lam (P2 - P1) meets the substrate circle |.| = R
+                    const double B = w1 * dw + s1 * ds;
+                    const double C = w1 * w1 + s1 * s1 - mp.R * mp.R;
+                    const double disc = B * B - A * C;
+                    double lam;
+                    if (disc >= 0.0) {
+                        const double sq = sqrt(disc);
+                        const double lp = (-B + sq) / A, lm = (-B - sq) / A;
+                        lam = lp <= 0.0 ? lp : lm;  // nearest hit behind P1, else the first one ahead
+                    } else {
+                        lam = -B / A;  // no intersection: closest approach
+                    }
+                    const double w0 = w1 + lam * dw, s0 = s1 + lam * ds;
+                    const double r0 = sqrt(w0 * w0 + s0 * s0);
+                    const double nw = w0 / r0, ns = s0 / r0;      // outward normal
+                    const double tw = -ns, ts = nw;               // tangent toward the drop axis
+                    const double vl = sqrt(A);
+                    const double vw = dw / vl, vs = ds / vl;
+                    const double ang = atan2(vw * nw + vs * ns, vw * tw + vs * ts) * (180.0 / M_PI);
+                    for (int k = 0; k < 3; ++k) cp3[k] = mp.c[k] + s0 * F.a[k] + (w1 > 0.0 ? w0 * q1[k] / w1 : 0.0);
+                    if (ang >= 0.0) theta = ang;
+                }
+            }
+        }
+        th[s] = theta;
+        cpt[s][0] = cp3[0]; cpt[s][1] = cp3[1]; cpt[s][2] = cp3[2];
+        __syncthreads();
+        if (s == 0) {
+            AngleRec rec;
+            rec.step = ctl->t;
+            rec.n_sectors = mp.n_sectors;
+            rec.pad_ = 0;
+            double sum = 0.0;
+            int nv = 0;
+            for (int k = 0; k < 64; ++k) {
+                rec.sector_deg[k] = NAN;
+                rec.contact[k][0] = rec.contact[k][1] = rec.contact[k][2] = NAN;
+            }
+            for (int k = 0; k < mp.n_sectors; ++k) {
+                rec.sector_deg[k] = th[k];
+                rec.contact[k][0] = cpt[k][0]; rec.contact[k][1] = cpt[k][1]; rec.contact[k][2] = cpt[k][2];
+                if (!isnan(th[k])) { sum += th[k]; ++nv; }
+            }
+            for (int k = 0; k < 3; ++k) rec.axis[k] = F.a[k];
+            rec.n_valid = nv;
+            rec.status = nv ? 0 : -6;
+            rec.mean_deg = nv ? sum / nv : NAN;
+            rec.adv_deg = rec.rec_deg = NAN;
+            const double ga = mp.g[0] * F.a[0] + mp.g[1] * F.a[1] + mp.g[2] * F.a[2];
+            const double gt[3] = {mp.g[0] - ga * F.a[0], mp.g[1] - ga * F.a[1], mp.g[2] - ga * F.a[2]};
+            if (nv && gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2] > 0.0) {
+                const int sa = sector_of(gt, F, mp.dim, mp.n_sectors);
+                const int sr = mp.dim == 2 ? 1 - sa : (sa + mp.n_sectors / 2) % mp.n_sectors;
+                rec.adv_deg = th[sa];
+                rec.rec_deg = th[sr];
+            }
+            *last = rec;
+            if (series && ctl->series_count < ctl->series_cap) series[ctl->series_count] = rec;
+        }
+        __syncthreads();
+        // clear the reduction slots for the next measurement
+        ctl->keys[s][0] = ~0ull;
+        ctl->keys[s][1] = ~0ull;
+        if (s == 0) {
+            ctl->cnt = ctl->sx = ctl->sy = ctl->sz = 0ull;
+            if (series && ctl->series_count < ctl->series_cap) ctl->series_count += 1;
+        }
+    }
+    if (s == 0 && tick) ctl->t += 1;
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_fill_value(R* __restrict__ p, size_t n, R v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_ctl_reset(DevCtl* ctl, int every, int force, int series_cap) {
+    const int s = threadIdx.x;
+    ctl->keys[s][0] = ~0ull;
+    ctl->keys[s][1] = ~0ull;
+    if (s == 0) {
+        ctl->cnt = ctl->sx = ctl->sy = ctl->sz = 0ull;
+        ctl->every = every;
+        ctl->force_measure = force;
+        ctl->series_count = 0;
+        ctl->series_cap = series_cap;
+    }
+}
+
+__global__ void k_ctl_set(DevCtl* ctl, long long t, int every, int force, int series_cap, int clear_status) {
+    if (threadIdx.x == 0) {
+        ctl->t = t;
+        ctl->every = every;
+        ctl->force_measure = force;
+        ctl->series_count = 0;
+        ctl->series_cap = series_cap;
+        if (clear_status) ctl->status = 0;
+    }
+}
+
+// state = f_eq(rho, 0) on fluid nodes, zero elsewhere
+template <class L, typename R>
+__global__ void k_init_feq(const R* __restrict__ rho, R* __restrict__ f, const uint8_t* __restrict__ cls, long long N) {
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+        const bool fl = (cls[n] & CLS_MASK) == CLS_FLUID;
+        const R r = fl ? rho[n] : R(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) f[(size_t)i * N + n] = r * R(L::w(i));
+    }
+}
+
+// v = u + F / (2 rho) (Sec. II B), with F of Eq. 7 from the current rho and mu
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, const R* __restrict__ rho,
+                                                  const R* __restrict__ mu, const uint8_t* __restrict__ cls, Dims d,
+                                                  Collision<C> cp, long long t, R* __restrict__ vel) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= d.nx || y >= d.ny) return;
+    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    if ((cls[idx] & CLS_MASK) != CLS_FLUID) {
+        vel[idx] = vel[d.N + idx] = vel[2 * d.N + idx] = R(0);
+        return;
+    }
+    const C r0 = (C)rho[idx];
+    C Fa[3] = {C(0), C(0), C(0)};
+    for (int a = 0; a < L::D; ++a) {
+        int o[3] = {0, 0, 0};
+        long long id[5];
+        for (int k = -2; k <= 2; ++k) {
+            o[a] = k;
+            const int X = wrapc(x + o[0], d.nx), Y = wrapc(y + o[1], d.ny), Z = L::D == 3 ? wrapc(z + o[2], d.nz) : 0;
+            id[k + 2] = ((long long)Z * d.ny + Y) * d.nx + X;
+        }
+        const C gm = d1c<C>(mu[id[0]], mu[id[1]], mu[id[3]], mu[id[4]]);
+        const C gr = d1c<C>(rho[id[0]], rho[id[1]], rho[id[3]], rho[id[4]]);
+        Fa[a] = -r0 * gm + gr * C(1.0 / 3.0);
+        if (t >= cp.g_start) Fa[a] += r0 * cp.g[a];
+    }
+    C rs = C(0), j[3] = {C(0), C(0), C(0)};
+    for (int i = 0; i < L::Q; ++i) {
+        const C fi = (C)fin[(size_t)i * d.N + idx];
+        rs += fi;
+        j[0] += C(L::E[i][0]) * fi;
+        j[1] += C(L::E[i][1]) * fi;
+        j[2] += C(L::E[i][2]) * fi;
+    }
+    for (int a = 0; a < 3; ++a) vel[(size_t)a * d.N + idx] = (R)(j[a] / rs + Fa[a] / (C(2) * rs));
+}
+
+// deterministic mass: per-block FP64 partial sums in a fixed order
+template <class L, typename R>
+__global__ void __launch_bounds__(256) k_mass_partial(const R* __restrict__ f, const uint8_t* __restrict__ cls,
+                                                      long long N, double* __restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    const long long per = (N + gridDim.x - 1) / gridDim.x;
+    const long long beg = (long long)blockIdx.x * per, end = beg + per < N ? beg + per : N;
+    for (long long n = beg + threadIdx.x; n < end; n += 256) {
+        if ((cls[n] & CLS_MASK) != CLS_FLUID) continue;
+        for (int i = 0; i < L::Q; ++i) s += (double)f[(size_t)i * N + n];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_mass_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s;
+    }
+}
+
+}  // namespace lbm
+
+namespace lbm {
+template <typename R>
+__global__ void k_add_value(R* __restrict__ p, size_t n, R v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] += v;
+}
+}  // namespace lbm

@@ -1,0 +1,291 @@
+"""ctypes binding of the C ABI declared in include/lbm.h (liblbm.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+liblbm.so.  The functions keep the C names; ``Lattice`` is a thin convenience
+wrapper used by the tests and the benchmark.  If the shared library has not
+been built, loading fails loudly -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+
+LBM_OK, LBM_E_ARG, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_NO_CONTACT_LINE, \
+    LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+LBM_D2Q9, LBM_D3Q19 = 0, 1
+LBM_F32, LBM_F64, LBM_F32_MIXED = 0, 1, 2
+LBM_PERIODIC, LBM_WALL = 0, 1
+LBM_MRT, LBM_BGK = 0, 1
+LBM_BC_HALFWAY, LBM_BC_BOUZIDI_MC = 0, 1
+LBM_SOLID_SPHERE = 0
+LBM_WET_UNIFORM, LBM_WET_STRIPES = 0, 1
+FIELD_RHO, FIELD_F, FIELD_VEL, FIELD_MU, FIELD_CLASS, FIELD_MASS = range(6)
+MAX_SECTORS = 64
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+class lbm_config(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("precision", C.c_int), ("n", C.c_int * 3), ("axis_bc", C.c_int * 3),
+        ("collision", C.c_int), ("bc_mode", C.c_int),
+        ("tau", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
+        ("s_pi", C.c_double), ("s_m", C.c_double), ("Tr", C.c_double),
+        ("pr_a", C.c_double), ("pr_b", C.c_double), ("pr_R", C.c_double), ("pr_omega", C.c_double),
+        ("k", C.c_double), ("kappa", C.c_double), ("g", C.c_double * 3), ("g_start_step", C.c_int64),
+        ("rho_l", C.c_double), ("rho_g", C.c_double), ("wall_mu", C.c_double), ("stream", C.c_void_p),
+    ]
+
+
+class lbm_solid(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int), ("wet_mode", C.c_int), ("center", C.c_double * 3), ("radius", C.c_double),
+        ("mu_w", C.c_double), ("mu_w2", C.c_double), ("stripe_width", C.c_double), ("pole", C.c_double * 3),
+    ]
+
+
+class lbm_drop(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("radius", C.c_double)]
+
+
+class lbm_measure_opts(C.Structure):
+    _fields_ = [("solid_index", C.c_int), ("n_sectors", C.c_int), ("rho_m", C.c_double)]
+
+
+class lbm_angle(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("status", C.c_int32), ("n_sectors", C.c_int32), ("n_valid", C.c_int32),
+        ("pad_", C.c_int32), ("mean_deg", C.c_double), ("adv_deg", C.c_double), ("rec_deg", C.c_double),
+        ("axis", C.c_double * 3), ("sector_deg", C.c_double * MAX_SECTORS),
+        ("contact", (C.c_double * 3) * MAX_SECTORS),
+    ]
+
+    def sectors(self):
+        return np.array(self.sector_deg[: self.n_sectors])
+
+
+class lbm_info(C.Structure):
+    _fields_ = [
+        ("Tc", C.c_double), ("T", C.c_double), ("alpha", C.c_double), ("rho_g", C.c_double),
+        ("rho_l", C.c_double), ("mu_sat", C.c_double), ("p_sat", C.c_double), ("wall_mu", C.c_double),
+        ("rho_m", C.c_double), ("Q", C.c_int32), ("precision", C.c_int32), ("N", C.c_int64),
+        ("step", C.c_int64), ("n_fluid", C.c_int64), ("n_layer1", C.c_int64), ("n_layer2", C.c_int64),
+        ("n_boundary", C.c_int64),
+    ]
+
+
+_lib = None
+
+# exported symbols of include/lbm.h (the binding and the tests check them)
+EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops",
+           "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
+           "lbm_get_info", "lbm_profile_step", "lbm_last_error")
+
+
+def lib():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} not built: run `python -m paper_2202_06516_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, vp, i, i64, d = C.POINTER, C.c_void_p, C.c_int, C.c_int64, C.c_double
+    L.lbm_config_default.restype = None
+    L.lbm_config_default.argtypes = [P(lbm_config), i]
+    L.lbm_create.argtypes = [P(lbm_config), P(vp)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_set_solid.argtypes = [vp, P(lbm_solid), i, P(d)]
+    L.lbm_init_drops.argtypes = [vp, P(lbm_drop), i, d]
+    L.lbm_step.argtypes = [vp, i64, i, P(lbm_angle), i, P(i)]
+    L.lbm_set_measure.argtypes = [vp, P(lbm_measure_opts)]
+    L.lbm_measure_angle.argtypes = [vp, P(lbm_measure_opts), P(lbm_angle)]
+    L.lbm_read.argtypes = [vp, i, vp, C.c_size_t, i]
+    L.lbm_write.argtypes = [vp, i, vp, C.c_size_t, i]
+    L.lbm_sync.argtypes = [vp]
+    L.lbm_get_info.argtypes = [vp, P(lbm_info)]
+    L.lbm_profile_step.argtypes = [vp, i64, P(C.c_char_p), P(d), i, P(i)]
+    L.lbm_last_error.restype = C.c_char_p
+    L.lbm_last_error.argtypes = [vp]
+    for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
+                 "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
+                 "lbm_get_info", "lbm_profile_step"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def config_default(lattice: int) -> lbm_config:
+    cfg = lbm_config()
+    lib().lbm_config_default(C.byref(cfg), lattice)
+    return cfg
+
+
+class Lattice:
+    """One lbm context: create, set solids, initialise, step, measure, read."""
+
+    def __init__(self, lattice=LBM_D2Q9, n=(128, 128, 1), precision=None, axis_bc=(0, 0, 0), stream=None,
+                 **params):
+        cfg = config_default(lattice)
+        if precision is not None:
+            cfg.precision = precision
+        nn = list(n) + [1] * (3 - len(n))
+        for k in range(3):
+            cfg.n[k] = nn[k]
+            cfg.axis_bc[k] = axis_bc[k] if k < len(axis_bc) else 0
+        for key, val in params.items():
+            if key == "g":
+                for k in range(3):
+                    cfg.g[k] = val[k] if k < len(val) else 0.0
+            else:
+                if not hasattr(cfg, key):
+                    raise KeyError(key)
+                setattr(cfg, key, val)
+        if stream is not None:
+            cfg.stream = stream
+        self.cfg = cfg
+        self.dim = 2 if lattice == LBM_D2Q9 else 3
+        self.Q = 9 if self.dim == 2 else 19
+        self.shape = (1 if self.dim == 2 else nn[2], nn[1], nn[0])
+        self.N = int(np.prod(self.shape))
+        self.dtype = np.float64 if cfg.precision == LBM_F64 else np.float32
+        h = C.c_void_p()
+        st = lib().lbm_create(C.byref(cfg), C.byref(h))
+        if st != 0:
+            raise LbmError(st, "lbm_create failed (invalid configuration?)")
+        self._h = h
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise LbmError(st, lib().lbm_last_error(self._h).decode())
+        return st
+
+    # -- set-up ------------------------------------------------------------
+    def set_solids(self, solids, mu_w_map=None):
+        arr = (lbm_solid * max(len(solids), 1))()
+        for i, s in enumerate(solids):
+            arr[i].kind = LBM_SOLID_SPHERE
+            c = list(s["center"]) + [0.0] * (3 - len(s["center"]))
+            for k in range(3):
+                arr[i].center[k] = c[k]
+            arr[i].radius = s["radius"]
+            if "stripes" in s:
+                arr[i].wet_mode = LBM_WET_STRIPES
+                arr[i].mu_w, arr[i].mu_w2, arr[i].stripe_width = s["stripes"]
+            else:
+                arr[i].wet_mode = LBM_WET_UNIFORM
+                arr[i].mu_w = s.get("mu_w", 0.0)
+            pole = s.get("pole", (0.0, 0.0, 0.0))
+            for k in range(3):
+                arr[i].pole[k] = pole[k] if k < len(pole) else 0.0
+        mp = None
+        if mu_w_map is not None:
+            self._muw = np.ascontiguousarray(mu_w_map, dtype=np.float64).reshape(-1)
+            mp = self._muw.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(lib().lbm_set_solid(self._h, arr, len(solids), mp))
+
+    def init_drops(self, drops, W=10.0):
+        arr = (lbm_drop * len(drops))()
+        for i, (c, r) in enumerate(drops):
+            cc = list(c) + [0.0] * (3 - len(c))
+            for k in range(3):
+                arr[i].center[k] = cc[k]
+            arr[i].radius = r
+        self._check(lib().lbm_init_drops(self._h, arr, len(drops), float(W)))
+
+    def set_measure(self, solid_index=0, n_sectors=32, rho_m=0.0):
+        o = lbm_measure_opts(solid_index, n_sectors, rho_m)
+        self._check(lib().lbm_set_measure(self._h, C.byref(o)))
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n, measure_every=0, cap=0):
+        if cap:
+            arr = (lbm_angle * cap)()
+            nw = C.c_int()
+            self._check(lib().lbm_step(self._h, int(n), int(measure_every), arr, cap, C.byref(nw)))
+            return [arr[i] for i in range(nw.value)]
+        self._check(lib().lbm_step(self._h, int(n), int(measure_every), None, 0, None))
+        return []
+
+    def sync(self):
+        self._check(lib().lbm_sync(self._h))
+
+    def measure(self, solid_index=0, n_sectors=32, rho_m=0.0, allow_missing=True):
+        o = lbm_measure_opts(solid_index, n_sectors, rho_m)
+        a = lbm_angle()
+        st = lib().lbm_measure_angle(self._h, C.byref(o), C.byref(a))
+        if st not in (0, LBM_E_NO_CONTACT_LINE) or (st != 0 and not allow_missing):
+            self._check(st)
+        return a
+
+    # -- fields ------------------------------------------------------------
+    def read(self, field):
+        if field == FIELD_CLASS:
+            out = np.empty(self.shape, dtype=np.uint8)
+        elif field == FIELD_MASS:
+            out = np.empty(1, dtype=np.float64)
+        elif field == FIELD_F:
+            out = np.empty((self.Q,) + self.shape, dtype=self.dtype)
+        elif field == FIELD_VEL:
+            out = np.empty((3,) + self.shape, dtype=self.dtype)
+        else:
+            out = np.empty(self.shape, dtype=self.dtype)
+        self._check(lib().lbm_read(self._h, field, out.ctypes.data, out.nbytes, 0))
+        return out[0] if field == FIELD_MASS else out
+
+    def read_device(self, field, ptr, nbytes):
+        self._check(lib().lbm_read(self._h, field, C.c_void_p(ptr), nbytes, 1))
+
+    def write(self, field, arr):
+        a = np.ascontiguousarray(arr, dtype=self.dtype)
+        self._check(lib().lbm_write(self._h, field, a.ctypes.data, a.nbytes, 0))
+
+    @property
+    def rho(self):
+        return self.read(FIELD_RHO)
+
+    @property
+    def f(self):
+        return self.read(FIELD_F)
+
+    def mass(self):
+        return float(self.read(FIELD_MASS))
+
+    def info(self):
+        inf = lbm_info()
+        self._check(lib().lbm_get_info(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in lbm_info._fields_}
+
+    def profile(self, nsteps):
+        names = (C.c_char_p * 8)()
+        ms = (C.c_double * 8)()
+        n = C.c_int()
+        self._check(lib().lbm_profile_step(self._h, int(nsteps), names, ms, 8, C.byref(n)))
+        return {names[i].decode(): ms[i] for i in range(n.value)}
+
+
+def angle_dict(a):
+    return dict(step=a.step, status=a.status, mean=a.mean_deg, adv=a.adv_deg, rec=a.rec_deg,
+                sectors=list(a.sector_deg[: a.n_sectors]), n_valid=a.n_valid)
+
+
+__all__ = [n for n in dir() if not n.startswith("_")] + ["math"]

@@ -1,0 +1,50 @@
+"""Build the same seeded workload on the GPU library and on the CPU oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2202_06516_amd import lbm as G
+
+# common physical parameters (both sides receive exactly these)
+BASE = dict(tau=1.0, s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.54, s_m=1.9, Tr=0.6, k=0.28, kappa=0.01)
+
+
+def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start=0, **extra):
+    lat = G.LBM_D2Q9 if wl["dim"] == 2 else G.LBM_D3Q19
+    n = tuple(wl["n"]) + ((1,) if wl["dim"] == 2 else ())
+    params = dict(BASE)
+    params.update(extra)
+    gp = G.Lattice(lat, n=n, precision=precision, axis_bc=tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"])),
+                   collision=G.LBM_MRT if collision == "mrt" else G.LBM_BGK,
+                   bc_mode=G.LBM_BC_HALFWAY if bc == "halfway" else G.LBM_BC_BOUZIDI_MC,
+                   g=g, g_start_step=g_start, **params)
+    gp.set_solids(wl["solids"])
+    if wl.get("drops"):
+        gp.init_drops(wl["drops"], W=10.0)
+    return gp
+
+
+def oracle_lattice(wl, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start=0, **extra):
+    import oracle as O
+    params = dict(BASE)
+    params.update(extra)
+    wall = tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"]))
+    o = O.Oracle(wl["dim"], wl["n"], wall, bgk=int(collision == "bgk"), bc_mode=int(bc != "halfway"),
+                 g=g, g_start=g_start, **params)
+    for s in wl["solids"]:
+        if "stripes" in s:
+            o.add_sphere(s["center"], s["radius"], stripes=s["stripes"], pole=s.get("pole"))
+        else:
+            o.add_sphere(s["center"], s["radius"], mu_w=s.get("mu_w", 0.0), pole=s.get("pole"))
+    if wl.get("drops"):
+        o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=10.0)
+    return o
+
+
+def rel_err(a, b, mask=None):
+    """max |a-b| / max |b| over the mask."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if mask is not None:
+        a, b = a[mask], b[mask]
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
