@@ -2,7 +2,7 @@
 
 Workload (default): D3Q19 FP32, 256^3 walled box, sphere r=60 at (128,128,92),
 drop r0=40 tangent on top, wall chemical potential 0.04 (the middle of the
-paper's sweep), Tr=0.6, BGK tau=1, contact angle every 500 steps over 32
+paper's sweep), Tr=0.8, BGK tau=1, contact angle every 500 steps over 32
 azimuthal sectors.  Inputs are synthetic and resident in HBM before timing.
 
 Prints one JSON line: MLUPS (fluid-node updates per second), the roofline of
@@ -35,11 +35,38 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps at full size (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only time a plain device copy of GIB gibibytes (bandwidth / counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(gib):
+    """A plain copy kernel of known size: achieved GB/s and the bytes it must move."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * 4 * n
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "mean_ms": round(ms, 4),
+                      "achieved_GBs": round(moved / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy > 0:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -54,7 +81,7 @@ def main():
     stream = torch.cuda.Stream()
     lat = G.Lattice(G.LBM_D3Q19, n=wl["n"], precision=prec, axis_bc=(1, 1, 1), stream=stream.cuda_stream,
                     collision=G.LBM_BGK if args.collision == "bgk" else G.LBM_MRT, bc_mode=G.LBM_BC_HALFWAY,
-                    tau=1.0, Tr=0.6, k=0.28, kappa=0.01)
+                    tau=1.0, Tr=wl["Tr"], k=0.28, kappa=0.01)
     lat.set_solids(wl["solids"])
     lat.init_drops(wl["drops"], W=10.0)
     lat.set_measure(0, wl["n_sectors"])
@@ -93,7 +120,7 @@ def main():
         "dtype": {"f32": "f32", "f32mixed": "f32 storage / f64 math", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"sessile drop on a sphere, D3Q19 {args.n}^3 walled box, sphere r={60 * args.n // 256}, "
-                               f"drop r0={40 * args.n // 256}, mu_w=0.04, Tr=0.6, {args.collision.upper()} tau=1, "
+                               f"drop r0={40 * args.n // 256}, mu_w=0.04, Tr={wl['Tr']}, {args.collision.upper()} tau=1, "
                                f"angle every {wl['every']} steps over {wl['n_sectors']} sectors",
                    "lattice": [args.n] * 3, "fluid_nodes": n_fluid, "precision": args.precision,
                    "collision": args.collision},

@@ -9,7 +9,9 @@ Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
   sessile_2d   D2Q9 FP64 128x128 periodic, cylinder r=24 at (64,40), drop r0=20
                tangent on top at (64,84), 5000 steps, angle every 100 steps
   sessile_3d   D3Q19 FP32 256^3 walled box, sphere r=60 at (128,128,92), drop
-               r0=40 tangent on top at (128,128,192), 20000 steps
+               r0=40 tangent on top at (128,128,192), 20000 steps, Tr=0.8 (the
+               paper's second temperature; the three-dimensional lattice is not
+               stable at Tr=0.6 with this forcing)
   striped_3d   D3Q19 FP32 512^3 walled box, sphere r=120 with latitude stripes
                (width 16) of two wettabilities, sessile or pendent drop r0=80,
                gravity 1e-6 .. 1e-5 lu
@@ -25,7 +27,8 @@ MU_W_SWEEP = (-0.01, 0.04, 0.1)
 def sessile_2d(mu_w=0.04, n=128, scale=1.0):
     """Cylinder + tangent drop on a periodic square lattice (scaled with n/128)."""
     s = n / 128.0 * scale
-    return dict(dim=2, n=(n, n), wall=(0, 0), solids=[dict(center=(64 * s, 40 * s), radius=24 * s, mu_w=mu_w)],
+    return dict(dim=2, n=(n, n), wall=(0, 0), Tr=0.6,
+                solids=[dict(center=(64 * s, 40 * s), radius=24 * s, mu_w=mu_w)],
                 drops=[((64 * s, 84 * s), 20 * s)], steps=5000, every=100)
 
 
@@ -35,7 +38,7 @@ def sessile_3d(mu_w=0.04, n=256):
     cz = 92 * s
     R = 60 * s
     r0 = 40 * s
-    return dict(dim=3, n=(n, n, n), wall=(1, 1, 1),
+    return dict(dim=3, n=(n, n, n), wall=(1, 1, 1), Tr=0.8,
                 solids=[dict(center=(128 * s, 128 * s, cz), radius=R, mu_w=mu_w)],
                 drops=[((128 * s, 128 * s, cz + R + r0), r0)], steps=20000, every=500, n_sectors=32)
 
@@ -52,7 +55,7 @@ def striped_3d(n=512, pendent=False, g=1e-6, mu1=-0.0183, mu2=0.0700, width=16.0
         cz = 176 * s
         drop = ((256 * s, 256 * s, cz + R + r0), r0)
         gv = (0.0, 0.0, -g)
-    return dict(dim=3, n=(n, n, n), wall=(1, 1, 1),
+    return dict(dim=3, n=(n, n, n), wall=(1, 1, 1), Tr=0.8,
                 solids=[dict(center=(256 * s, 256 * s, cz), radius=R, stripes=(mu1, mu2, width * s))],
                 drops=[drop], g=gv, g_start=10000, steps=50000, every=500, n_sectors=64)
 

@@ -13,6 +13,8 @@ def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0),
     lat = G.LBM_D2Q9 if wl["dim"] == 2 else G.LBM_D3Q19
     n = tuple(wl["n"]) + ((1,) if wl["dim"] == 2 else ())
     params = dict(BASE)
+    if "Tr" in wl:
+        params["Tr"] = wl["Tr"]
     params.update(extra)
     gp = G.Lattice(lat, n=n, precision=precision, axis_bc=tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"])),
                    collision=G.LBM_MRT if collision == "mrt" else G.LBM_BGK,
@@ -27,6 +29,8 @@ def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0),
 def oracle_lattice(wl, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start=0, **extra):
     import oracle as O
     params = dict(BASE)
+    if "Tr" in wl:
+        params["Tr"] = wl["Tr"]
     params.update(extra)
     wall = tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"]))
     o = O.Oracle(wl["dim"], wl["n"], wall, bgk=int(collision == "bgk"), bc_mode=int(bc != "halfway"),
