@@ -3,11 +3,12 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "host.hpp"
 #include "kernels.hpp"
 
@@ -33,10 +34,12 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* f[2] = {nullptr, nullptr};
-    int cur = 0;  // state S_t is in f[cur]
+    int cur = 0;        // populations of the current state are in f[cur]
+    bool fstar = false;  // f[cur] holds post-collision populations (pull form), else S_t
     void *rho = nullptr, *mu = nullptr;
     uint8_t* cls = nullptr;
     uint32_t* nbmask = nullptr;
+    int* bidx = nullptr;
     long long *l1_node = nullptr, *l2_node = nullptr, *b_node = nullptr;
     uint32_t *l1_mask = nullptr, *l2_mask = nullptr, *b_mask = nullptr;
     void *l1_inv = nullptr, *l2_inv = nullptr, *b_q = nullptr;
@@ -158,99 +161,111 @@ struct Run {
         cp.g_start = g.g_start_step;
         return cp;
     }
-    static dim3 grid(const lbm_ctx* c) { return dim3((c->d.nx + 63) / 64, (c->d.ny + 3) / 4, c->d.nz); }
+    static dim3 grid(const lbm_ctx* c) { return dim3(c->d.nblocks, 1, 1); }
 
-    // the launches of one step, reading f[src] and writing f[1-src]
-    static void step_launches(lbm_ctx* c, int src, const MeasureParams& mp, hipEvent_t* ev, int* kinds) {
+    static WallBC wall(const lbm_ctx* c) {
+        WallBC bc;
+        bc.nbmask = c->nbmask;
+        bc.bidx = c->bidx;
+        bc.q = c->b_q;
+        bc.bouzidi = c->cfg.bc_mode == LBM_BC_BOUZIDI_MC;
+        return bc;
+    }
+    static void density(lbm_ctx* c, const R* f, bool pull, double rho_m) {
+        const dim3 blk(64, 4, 1), grd = grid(c);
+        const R inv_b = (R)(1.0 / c->pr.b);
+        if (pull)
+            k_density<L, R, C, true><<<grd, blk, 0, c->stream>>>(f, (R*)c->rho, c->cls, c->d, wall(c), c->ctl, rho_m, inv_b);
+        else
+            k_density<L, R, C, false><<<grd, blk, 0, c->stream>>>(f, (R*)c->rho, c->cls, c->d, wall(c), c->ctl, rho_m, inv_b);
+    }
+    static void fills(lbm_ctx* c, hipEvent_t* ev, int* kinds, int& k) {
+        R* rho = (R*)c->rho;
+        if (c->n_l1) {
+            if (ev) (void)hipEventRecord(ev[2 * k], c->stream);
+            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
+                                                                           c->n_l1, rho, c->d);
+            if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = 1; }
+        }
+        if (c->n_l2) {
+            if (ev) (void)hipEventRecord(ev[2 * k], c->stream);
+            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
+                                                                           c->n_l2, rho, c->d);
+            if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = 2; }
+        }
+    }
+
+    // the launches of one step, reading f[src] and writing f[1-src]; pull
+    // selects the form of f[src] (post-collision populations, else S_t)
+    static void step_launches(lbm_ctx* c, int src, bool pull, const MeasureParams& mp, hipEvent_t* ev, int* kinds) {
         const dim3 blk(64, 4, 1), grd = grid(c);
         const R* fin = (const R*)c->f[src];
         R* fout = (R*)c->f[1 - src];
         R* rho = (R*)c->rho;
         R* mu = (R*)c->mu;
-        const R inv_b = (R)(1.0 / c->pr.b);
         int k = 0;
-        auto mark = [&](int kind) {
-            if (ev) {
-                (void)hipEventRecord(ev[2 * k + 1], c->stream);
-                kinds[k] = kind;
-                ++k;
-            }
-        };
-        auto start = [&]() {
-            if (ev) (void)hipEventRecord(ev[2 * k], c->stream);
-        };
+        auto start = [&]() { if (ev) (void)hipEventRecord(ev[2 * k], c->stream); };
+        auto mark = [&](int kind) { if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = kind; } };
         start();
-        k_density<L, R, C><<<grd, blk, 0, c->stream>>>(fin, rho, c->cls, c->d, c->ctl, mp.rho_m, inv_b);
+        density(c, fin, pull, mp.rho_m);
         mark(0);
-        if (c->n_l1) {
-            start();
-            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
-                                                                        c->n_l1, rho, c->d);
-            mark(1);
-        }
-        if (c->n_l2) {
-            start();
-            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
-                                                                        c->n_l2, rho, c->d);
-            mark(2);
-        }
+        fills(c, ev, kinds, k);
         start();
         k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c), c->ctl, mp);
         mark(3);
         start();
-        k_collide<L, R, C><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->nbmask, c->d, collision(c), c->ctl);
-        mark(4);
-        if (c->cfg.bc_mode == LBM_BC_BOUZIDI_MC && c->n_b) {
-            start();
-            k_bc<L, R, C><<<(c->n_b + 255) / 256, 256, 0, c->stream>>>(c->b_node, c->b_mask, (const R*)c->b_q, c->n_b,
-                                                                     fout, c->d);
-            mark(5);
+        const WallBC bc = wall(c);
+        const Collision<C> cp = collision(c);
+        const bool mrt = c->cfg.collision == LBM_MRT;
+        if (pull) {
+            if (mrt) k_collide<L, R, C, true, true><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+            else k_collide<L, R, C, true, false><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+        } else {
+            if (mrt) k_collide<L, R, C, false, true><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+            else k_collide<L, R, C, false, false><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
         }
+        mark(4);
         start();
         k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1);
         mark(6);
         if (kinds) kinds[k] = -1;
     }
 
+    // S_t of the current state into f[1 - cur] (free between steps)
+    static R* materialize(lbm_ctx* c) {
+        R* out = (R*)c->f[1 - c->cur];
+        if (c->fstar)
+            k_materialize<L, R, C, true><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((const R*)c->f[c->cur], out, c->cls, c->d, wall(c));
+        else
+            k_materialize<L, R, C, false><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((const R*)c->f[c->cur], out, c->cls, c->d, wall(c));
+        return out;
+    }
+
     // density, solid fill and mu of the current state (no measurement)
     static void derive(lbm_ctx* c, bool with_mu) {
-        const dim3 blk(64, 4, 1), grd = grid(c);
-        R* rho = (R*)c->rho;
         MeasureParams mp{};
         mp.rho_m = c->rho_m;
         mp.n_sectors = 2;
         mp.dim = c->dim;
-        k_density<L, R, C><<<grd, blk, 0, c->stream>>>((const R*)c->f[c->cur], rho, c->cls, c->d, c->ctl, mp.rho_m,
-                                                      (R)(1.0 / c->pr.b));
-        if (c->n_l1)
-            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
-                                                                        c->n_l1, rho, c->d);
-        if (c->n_l2)
-            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
-                                                                        c->n_l2, rho, c->d);
-        if (with_mu) k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
+        int k = 0;
+        fills(c, nullptr, nullptr, k);
+        if (with_mu) k_mu<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
     }
 
     static void velocity(lbm_ctx* c, void* out) {
         derive(c, true);
-        k_velocity<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((const R*)c->f[c->cur], (const R*)c->rho,
-                                                                     (const R*)c->mu, c->cls, c->d, collision(c), c->t,
-                                                                     (R*)out);
+        const R* S = materialize(c);
+        k_velocity<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>(S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d,
+                                                                        collision(c), c->t, (R*)out);
     }
 
     static void measure_now(lbm_ctx* c, const MeasureParams& mp) {
-        const dim3 blk(64, 4, 1), grd = grid(c);
-        R* rho = (R*)c->rho;
-        k_density<L, R, C><<<grd, blk, 0, c->stream>>>((const R*)c->f[c->cur], rho, c->cls, c->d, c->ctl, mp.rho_m,
-                                                      (R)(1.0 / c->pr.b));
-        if (c->n_l1)
-            k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
-                                                                        c->n_l1, rho, c->d);
-        if (c->n_l2)
-            k_fill<L, R, C><<<(c->n_l2 + 255) / 256, 256, 0, c->stream>>>(c->l2_node, c->l2_mask, (const R*)c->l2_inv,
-                                                                        c->n_l2, rho, c->d);
-        k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
-        k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, nullptr, c->last, 0);
+        density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
+        int k = 0;
+        fills(c, nullptr, nullptr, k);
+        k_mu<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->rho, c->ctl, c->d, mp, nullptr, c->last, 0);
     }
 
     static void init_feq(lbm_ctx* c) {
@@ -258,7 +273,8 @@ struct Run {
     }
 
     static void mass(lbm_ctx* c) {
-        k_mass_partial<L, R><<<kMassBlocks, 256, 0, c->stream>>>((const R*)c->f[c->cur], c->cls, c->d.N, c->mass_part);
+        const R* S = materialize(c);
+        k_mass_partial<L, R><<<kMassBlocks, 256, 0, c->stream>>>(S, c->cls, c->d.N, c->mass_part);
         k_mass_final<<<1, 64, 0, c->stream>>>(c->mass_part, kMassBlocks, c->mass_out);
     }
 
@@ -281,8 +297,8 @@ void dispatch(lbm_ctx* c, Args&&... args) {
 
 template <class L, typename R, typename C>
 struct OpStep {
-    static void go(lbm_ctx* c, int src, const MeasureParams* mp, hipEvent_t* ev, int* kinds) {
-        Run<L, R, C>::step_launches(c, src, *mp, ev, kinds);
+    static void go(lbm_ctx* c, int src, bool pull, const MeasureParams* mp, hipEvent_t* ev, int* kinds) {
+        Run<L, R, C>::step_launches(c, src, pull, *mp, ev, kinds);
     }
 };
 template <class L, typename R, typename C>
@@ -300,6 +316,10 @@ struct OpMeasure {
 template <class L, typename R, typename C>
 struct OpInit {
     static void go(lbm_ctx* c) { Run<L, R, C>::init_feq(c); }
+};
+template <class L, typename R, typename C>
+struct OpMaterialize {
+    static void go(lbm_ctx* c, void** out) { *out = Run<L, R, C>::materialize(c); }
 };
 template <class L, typename R, typename C>
 struct OpMass {
@@ -415,6 +435,13 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->d.ny = cfg->n[1];
     c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
     c->d.N = N;
+    c->d.tx = (c->d.nx + 63) / 64;
+    c->d.ty = (c->d.ny + 3) / 4;
+    c->d.nblocks = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)c->d.nz;
+    {
+        const char* e = std::getenv("LBM_XCD_REMAP");
+        c->d.xcd_remap = e ? std::atoi(e) != 0 : 1;
+    }
     c->pr.a = cfg->pr_a;
     c->pr.b = cfg->pr_b;
     c->pr.R = cfg->pr_R;
@@ -442,6 +469,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if ((s = dalloc(c, (char**)&c->f[0], fbytes)) || (s = dalloc(c, (char**)&c->f[1], fbytes)) ||
         (s = dalloc(c, (char**)&c->rho, N * c->elem)) || (s = dalloc(c, (char**)&c->mu, N * c->elem)) ||
         (s = dalloc(c, &c->cls, (size_t)N)) || (s = dalloc(c, &c->nbmask, (size_t)N * 4)) ||
+        (s = dalloc(c, &c->bidx, (size_t)N * 4)) ||
         (s = dalloc(c, &c->ctl, sizeof(DevCtl))) || (s = dalloc(c, &c->last, sizeof(AngleRec))) ||
         (s = dalloc(c, &c->mass_part, kMassBlocks * sizeof(double))) || (s = dalloc(c, &c->mass_out, sizeof(double)))) {
         lbm_destroy(c);
@@ -466,7 +494,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    void* ps[] = {c->f[0], c->f[1], c->rho, c->mu, c->cls, c->nbmask, c->l1_node, c->l2_node, c->b_node,
+    void* ps[] = {c->f[0], c->f[1], c->rho, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
                   c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
                   c->mass_part, c->mass_out};
     for (void* p : ps) dfree(p);
@@ -513,6 +541,11 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
     lbm_status s;
     HIPCHK(c, hipMemcpy(c->cls, g.cls.data(), g.N, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->nbmask, g.nbmask.data(), g.N * 4, hipMemcpyHostToDevice));
+    {
+        std::vector<int> bi((size_t)g.N, -1);
+        for (size_t k = 0; k < g.b_node.size(); ++k) bi[g.b_node[k]] = (int)k;
+        HIPCHK(c, hipMemcpy(c->bidx, bi.data(), g.N * 4, hipMemcpyHostToDevice));
+    }
     if ((s = upload(c, &c->l1_node, g.l1_node)) || (s = upload(c, &c->l2_node, g.l2_node)) ||
         (s = upload(c, &c->b_node, g.b_node)) || (s = upload(c, &c->l1_mask, g.l1_mask)) ||
         (s = upload(c, &c->l2_mask, g.l2_mask)) || (s = upload(c, &c->b_mask, g.b_mask)) ||
@@ -603,6 +636,7 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
         dispatch<OpInit>(c);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->fstar = false;
         c->have_state = true;
         return LBM_OK;
     }
@@ -611,6 +645,7 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
         if (bytes != fb) return fail(c, LBM_E_ARG, "write F: bytes must be Q * N * elem");
         HIPCHK(c, hipStreamSynchronize(c->stream));
         HIPCHK(c, hipMemcpy(c->f[c->cur], src, bytes, kind));
+        c->fstar = false;
         c->have_state = true;
         return LBM_OK;
     }
@@ -665,18 +700,22 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
     lbm_status s = ctl_reset(c, measure_every, 0, series ? cap : 0);
     if (s) return s;
     int64_t done = 0;
-    // odd leading step to reach buffer parity 0, then whole graphs, then the rest
-    while (done < nsteps && (c->cur != 0 || nsteps - done < kGraphSteps)) {
-        dispatch<OpStep>(c, c->cur, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+    auto eager = [&]() {
+        dispatch<OpStep>(c, c->cur, c->fstar, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
         c->cur ^= 1;
+        c->fstar = true;
         ++done;
         ++c->t;
-    }
+    };
+    // eager steps until the populations are in pull form in buffer 0, then
+    // whole captured graphs (an even number of steps keeps the parity), then the rest
+    while (done < nsteps && (!c->fstar || c->cur != 0 || nsteps - done < kGraphSteps)) eager();
     if (nsteps - done >= kGraphSteps) {
         if (!c->graph[0]) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < kGraphSteps; ++k) dispatch<OpStep>(c, k & 1, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+            for (int k = 0; k < kGraphSteps; ++k)
+                dispatch<OpStep>(c, k & 1, true, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
             HIPCHK(c, hipStreamEndCapture(c->stream, &g));
             hipError_t e = hipGraphInstantiate(&c->graph[0], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -691,12 +730,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
             c->t += kGraphSteps;
         }
     }
-    while (done < nsteps) {
-        dispatch<OpStep>(c, c->cur, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
-        c->cur ^= 1;
-        ++done;
-        ++c->t;
-    }
+    while (done < nsteps) eager();
     HIPCHK(c, hipGetLastError());
     if (series && cap > 0) {
         DevCtl h;
@@ -756,7 +790,12 @@ lbm_status lbm_read(lbm_ctx* c, int field, void* dst, size_t bytes, int dst_on_d
             break;
         case LBM_FIELD_F:
             if (bytes != (size_t)c->Q * N * c->elem) return fail(c, LBM_E_ARG, "read F: bytes must be Q * N * elem");
-            HIPCHK(c, hipMemcpyAsync(dst, c->f[c->cur], bytes, kind, c->stream));
+            {
+                void* S = nullptr;
+                dispatch<OpMaterialize>(c, &S);
+                HIPCHK(c, hipGetLastError());
+                HIPCHK(c, hipMemcpyAsync(dst, S, bytes, kind, c->stream));
+            }
             break;
         case LBM_FIELD_VEL: {
             if (bytes != 3 * N * c->elem) return fail(c, LBM_E_ARG, "read VEL: bytes must be 3 * N * elem");
@@ -840,8 +879,9 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
     int cnt[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t t = 0; t < nsteps; ++t) {
         int kinds[9];
-        dispatch<OpStep>(c, c->cur, &mp, ev, kinds);
+        dispatch<OpStep>(c, c->cur, c->fstar, &mp, ev, kinds);
         c->cur ^= 1;
+        c->fstar = true;
         ++c->t;
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int k = 0; k < 8 && kinds[k] >= 0; ++k) {

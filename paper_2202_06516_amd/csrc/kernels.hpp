@@ -39,7 +39,26 @@ enum : uint8_t { CLS_FLUID = 0, CLS_L1 = 1, CLS_L2 = 2, CLS_DEEP = 3, CLS_MASK =
 struct Dims {
     int nx, ny, nz;
     long long N;
+    int tx, ty;          // 64 x 4 node tiles per row / per plane
+    unsigned nblocks;    // tx * ty * nz workgroups
+    int xcd_remap;       // 1: contiguous tile ranges per XCD
 };
+
+// Node of this thread.  Workgroups are dispatched to the 8 XCDs round-robin
+// by workgroup id; with xcd_remap each XCD receives one contiguous range of
+// tiles (a slab of z planes), so the stencil neighbours of a tile sit in the
+// same L2.  The map is a bijection of [0, nblocks).
+__device__ __forceinline__ void tile_node(const Dims& d, int& x, int& y, int& z) {
+    unsigned t = blockIdx.x;
+    if (d.xcd_remap) {
+        const unsigned q = d.nblocks >> 3, r = d.nblocks & 7u, xcd = t & 7u, loc = t >> 3;
+        t = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
+    }
+    const unsigned txi = t % (unsigned)d.tx, rest = t / (unsigned)d.tx;
+    x = (int)txi * 64 + (int)threadIdx.x;
+    y = (int)(rest % (unsigned)d.ty) * 4 + (int)threadIdx.y;
+    z = (int)(rest / (unsigned)d.ty);
+}
 
 // Peng-Robinson coefficients of psi'(rho) (Eq. 11, C = 0), pre-scaled by k^2.
 // psi' is evaluated in double precision; the kernels store mu - mu_ref with
@@ -101,13 +120,14 @@ __device__ __forceinline__ bool measuring(const DevCtl* ctl) {
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-__device__ __forceinline__ double psi_prime(double rho, const Thermo& th) {
-    const double br = th.b * rho;
-    const double om = 1.0 - br;
-    const double t1 = th.k2RT * log(rho / om);
-    const double t2 = th.k2A * log((th.s2m1 + br) / (th.s2p1 - br));
-    const double t3 = th.k2RT / om;
-    const double t4 = th.k2aal * rho / (1.0 + 2.0 * br - br * br);
+template <typename T>
+__device__ __forceinline__ T psi_prime(T rho, const Thermo& th) {
+    const T br = (T)th.b * rho;
+    const T om = T(1) - br;
+    const T t1 = (T)th.k2RT * log(rho / om);
+    const T t2 = (T)th.k2A * log(((T)th.s2m1 + br) / ((T)th.s2p1 - br));
+    const T t3 = (T)th.k2RT / om;
+    const T t4 = (T)th.k2aal * rho / (T(1) + T(2) * br - br * br);
     return t1 - t2 + t3 - t4;
 }
 
@@ -123,24 +143,95 @@ __device__ __forceinline__ R d2c(R m2, R m1, R c, R p1, R p2) {
 }
 
 // ---------------------------------------------------------------------------
+// gather of the pre-collision populations S_t(x) of a fluid node
+// ---------------------------------------------------------------------------
+// The context keeps the populations in one of two forms.  Form S (after an
+// initial condition or a checkpoint): buffer = S_t, read in place.  Form F*:
+// buffer = post-collision populations of the previous step, and Eq. 4 is a
+// pull, S_i(x) = f*_i(x - e_i).  A link whose source x - e_i is solid carries
+// the missing population of the curved wall: halfway bounce-back
+// S_i = f*_j(x) with j = opp(i), or the linear interpolation in the wall
+// fraction q of the link from x along e_j, and the difference to f*_j(x) is
+// added to S_0 so that the fluid mass is unchanged (Sec. III A).
+struct WallBC {
+    const uint32_t* nbmask;  // bit j: x + e_j solid (boundary fluid nodes)
+    const int* bidx;         // boundary-list index of a boundary fluid node
+    const void* q;           // [n_boundary][Q] wall fractions (storage precision)
+    int bouzidi;
+};
+
+template <class L, typename R, typename C, bool PULL>
+__device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, long long idx, int x, int y, int z,
+                                       uint8_t c, const WallBC& bc, R S[L::Q]) {
+    if (!PULL) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + idx];
+        return;
+    }
+    const int xs[3] = {wrapc(x - 1, d.nx), x, wrapc(x + 1, d.nx)};
+    const int ys[3] = {wrapc(y - 1, d.ny), y, wrapc(y + 1, d.ny)};
+    const int zs[3] = {L::D == 3 ? wrapc(z - 1, d.nz) : 0, z, L::D == 3 ? wrapc(z + 1, d.nz) : 0};
+    // source x - e_i
+#define LBM_SRC(i) (((long long)zs[1 - L::E[i][2]] * d.ny + ys[1 - L::E[i][1]]) * d.nx + xs[1 - L::E[i][0]])
+    if (!(c & CLS_BOUNDARY)) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + (i ? LBM_SRC(i) : idx)];
+        return;
+    }
+    const uint32_t bm = bc.nbmask[idx];
+    const int k = bc.bouzidi ? bc.bidx[idx] : 0;
+    C dm = C(0);
+    S[0] = f[idx];
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int j = L::OPP[i];
+        if (!(bm & (1u << j))) {
+            S[i] = f[(size_t)i * d.N + LBM_SRC(i)];
+            continue;
+        }
+        const R outj = f[(size_t)j * d.N + idx];  // what left x toward the wall
+        if (!bc.bouzidi) {
+            S[i] = outj;
+            continue;
+        }
+        const C q = (C)((const R*)bc.q)[(size_t)k * L::Q + j];
+        C v = (C)outj;
+        if (q < C(0.5)) {
+            if (!(bm & (1u << i))) {  // x + e_i is the fluid node behind x
+                const long long b = ((long long)zs[1 + L::E[i][2]] * d.ny + ys[1 + L::E[i][1]]) * d.nx + xs[1 + L::E[i][0]];
+                v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)f[(size_t)j * d.N + b];
+            }
+        } else {
+            v = (C)outj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * (C)f[(size_t)i * d.N + idx];
+        }
+        S[i] = (R)v;
+        dm += (C)outj - v;
+    }
+#undef LBM_SRC
+    if (bc.bouzidi) S[0] = (R)((C)S[0] + dm);
+}
+
+// ---------------------------------------------------------------------------
 // density (+ liquid centroid on measure steps)
 // ---------------------------------------------------------------------------
-template <class L, typename R, typename C = R>
+template <class L, typename R, typename C, bool PULL>
 __global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __restrict__ rho,
-                                                 const uint8_t* __restrict__ cls, Dims d,
+                                                 const uint8_t* __restrict__ cls, Dims d, WallBC bc,
                                                  DevCtl* __restrict__ ctl, double rho_m, R inv_b) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+    int x, y, z;
+    tile_node(d, x, y, z);
     const bool in = x < d.nx && y < d.ny;
     const long long idx = ((long long)z * d.ny + y) * d.nx + x;
     bool liquid = false;
-    if (in && (cls[idx] & CLS_MASK) == CLS_FLUID) {
-        C s = C(0);
+    const uint8_t c = in ? cls[idx] : (uint8_t)CLS_DEEP;
+    if ((c & CLS_MASK) == CLS_FLUID) {
+        R S[L::Q];
+        gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
+        double s = 0.0;  // summed in double, as the collision's own moments are
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) s += (C)f[(size_t)i * d.N + idx];
+        for (int i = 0; i < L::Q; ++i) s += (double)S[i];
         rho[idx] = (R)s;
-        if (!(s > C(0) && s < (C)inv_b)) atomicOr(&ctl->status, 1);  // also catches NaN
+        if (!(s > 0.0 && s < (double)inv_b)) atomicOr(&ctl->status, 1);  // also catches NaN
         liquid = (double)s >= rho_m;
     }
     if (!measuring(ctl)) return;
@@ -157,9 +248,26 @@ __global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __r
         for (int k = 0; k < 4; ++k) red[wave][k] = v[k];
     __syncthreads();
     if (wave == 0 && lane < 4) {
-        unsigned long long s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-        if (s) atomicAdd((&ctl->cnt) + lane, s);
+        unsigned long long sum = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        if (sum) atomicAdd((&ctl->cnt) + lane, sum);
     }
+}
+
+// state S_t of every node (zero on solid nodes) into out
+template <class L, typename R, typename C, bool PULL>
+__global__ void __launch_bounds__(256) k_materialize(const R* __restrict__ f, R* __restrict__ out,
+                                                     const uint8_t* __restrict__ cls, Dims d, WallBC bc) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    if (x >= d.nx || y >= d.ny) return;
+    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    const uint8_t c = cls[idx];
+    R S[L::Q];
+    if ((c & CLS_MASK) == CLS_FLUID) gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
+    else
+        for (int i = 0; i < L::Q; ++i) S[i] = R(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) out[(size_t)i * d.N + idx] = S[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -256,9 +364,8 @@ template <class L, typename R, typename C = R>
 __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __restrict__ mu,
                                             const uint8_t* __restrict__ cls, Dims d, Thermo th,
                                             DevCtl* __restrict__ ctl, MeasureParams mp) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+    int x, y, z;
+    tile_node(d, x, y, z);
     const bool in = x < d.nx && y < d.ny;
     const long long idx = ((long long)z * d.ny + y) * d.nx + x;
     const bool fluid = in && (cls[idx] & CLS_MASK) == CLS_FLUID;
@@ -279,7 +386,7 @@ __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __rest
             lap += d2c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], c0, rho[zp1 * sz + col], rho[zp2 * sz + col]);
         }
         (void)sx;
-        mu[idx] = (R)((psi_prime((double)r0, th) - th.mu_ref) - th.kappa * (double)lap);
+        mu[idx] = (R)((psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap);
     }
     if (!measuring(ctl)) return;
     // gas-side nodes near the substrate test their links for a crossing
@@ -318,87 +425,95 @@ __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __rest
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
-template <class L, typename R>
-__device__ __forceinline__ void equilibrium(R rho, R ux, R uy, R uz, R feq[L::Q]) {
-    const R uu = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const R eu = R(L::E[i][0]) * ux + R(L::E[i][1]) * uy + R(L::E[i][2]) * uz;
-        feq[i] = rho * R(L::w(i)) * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-    }
-}
-
-template <class L, typename R, typename C = R>
+template <class L, typename R, typename C, bool PULL, bool MRT>
 __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* __restrict__ fout,
                                                  const R* __restrict__ rho, const R* __restrict__ mu,
-                                                 const uint8_t* __restrict__ cls, const uint32_t* __restrict__ nbmask,
-                                                 Dims d, Collision<C> cp, const DevCtl* __restrict__ ctl) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+                                                 const uint8_t* __restrict__ cls, Dims d, WallBC bc,
+                                                 Collision<C> cp, const DevCtl* __restrict__ ctl) {
+    int x, y, z;
+    tile_node(d, x, y, z);
     if (x >= d.nx || y >= d.ny) return;
     const long long idx = ((long long)z * d.ny + y) * d.nx + x;
     const uint8_t c = cls[idx];
     if ((c & CLS_MASK) != CLS_FLUID) return;
 
+    R S[L::Q];
+    gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
+
     const long long sy = d.nx, sz = (long long)d.nx * d.ny;
     const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
     const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
-    const int zm1 = L::D == 3 ? wrapc(z - 1, d.nz) : 0, zm2 = L::D == 3 ? wrapc(z - 2, d.nz) : 0;
-    const int zp1 = L::D == 3 ? wrapc(z + 1, d.nz) : 0, zp2 = L::D == 3 ? wrapc(z + 2, d.nz) : 0;
     const long long row = (long long)z * sz + (long long)y * sy;
     const long long pl = (long long)z * sz;
     const long long col = (long long)y * sy + x;
 
-    // Eq. 7 with fourth-order central differences
-    const C r0 = (C)rho[idx];
-    C gmx = d1c<C>(mu[row + xm2], mu[row + xm1], mu[row + xp1], mu[row + xp2]);
-    C grx = d1c<C>(rho[row + xm2], rho[row + xm1], rho[row + xp1], rho[row + xp2]);
-    C gmy = d1c<C>(mu[pl + ym2 * sy + x], mu[pl + ym1 * sy + x], mu[pl + yp1 * sy + x], mu[pl + yp2 * sy + x]);
-    C gry = d1c<C>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
-    C gmz = C(0), grz = C(0);
+    // Eq. 7 with fourth-order central differences.  The two terms of F cancel
+    // almost exactly inside an interface at rest, so F, and the moments it
+    // shifts, are formed in double precision whatever the storage type.
+    typedef double D;
+    const D r0 = (D)rho[idx];
+    const D gmx = d1c<D>(mu[row + xm2], mu[row + xm1], mu[row + xp1], mu[row + xp2]);
+    const D grx = d1c<D>(rho[row + xm2], rho[row + xm1], rho[row + xp1], rho[row + xp2]);
+    const D gmy = d1c<D>(mu[pl + ym2 * sy + x], mu[pl + ym1 * sy + x], mu[pl + yp1 * sy + x], mu[pl + yp2 * sy + x]);
+    const D gry = d1c<D>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
+    D gmz = D(0), grz = D(0);
     if (L::D == 3) {
-        gmz = d1c<C>(mu[zm2 * sz + col], mu[zm1 * sz + col], mu[zp1 * sz + col], mu[zp2 * sz + col]);
-        grz = d1c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], rho[zp1 * sz + col], rho[zp2 * sz + col]);
+        const int zm1 = wrapc(z - 1, d.nz), zm2 = wrapc(z - 2, d.nz), zp1 = wrapc(z + 1, d.nz), zp2 = wrapc(z + 2, d.nz);
+        gmz = d1c<D>(mu[zm2 * sz + col], mu[zm1 * sz + col], mu[zp1 * sz + col], mu[zp2 * sz + col]);
+        grz = d1c<D>(rho[zm2 * sz + col], rho[zm1 * sz + col], rho[zp1 * sz + col], rho[zp2 * sz + col]);
     }
-    const bool grav = ctl->t >= cp.g_start;
-    const C third = C(1.0 / 3.0);
-    C Fx = -r0 * gmx + grx * third, Fy = -r0 * gmy + gry * third, Fz = -r0 * gmz + grz * third;
-    if (grav) {
-        Fx += r0 * cp.g[0];
-        Fy += r0 * cp.g[1];
-        Fz += r0 * cp.g[2];
+    const D third = D(1.0 / 3.0);
+    D Fx = -r0 * gmx + grx * third, Fy = -r0 * gmy + gry * third, Fz = -r0 * gmz + grz * third;
+    if (ctl->t >= cp.g_start) {
+        Fx += r0 * (D)cp.g[0];
+        Fy += r0 * (D)cp.g[1];
+        Fz += r0 * (D)cp.g[2];
     }
 
-    C f[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) f[i] = (C)fin[(size_t)i * d.N + idx];
-    C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+    // moments of S: density and velocity (Eq. 2 arguments), in double
+    D rd = D(0), jx = D(0), jy = D(0), jz = D(0);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        rs += f[i];
-        if (L::E[i][0]) jx += C(L::E[i][0]) * f[i];
-        if (L::E[i][1]) jy += C(L::E[i][1]) * f[i];
-        if (L::E[i][2]) jz += C(L::E[i][2]) * f[i];
+        const D fi = (D)S[i];
+        rd += fi;
+        if (L::E[i][0]) jx += D(L::E[i][0]) * fi;
+        if (L::E[i][1]) jy += D(L::E[i][1]) * fi;
+        if (L::E[i][2]) jz += D(L::E[i][2]) * fi;
     }
-    const C ir = C(1) / rs;
-    const C ux = jx * ir, uy = jy * ir, uz = jz * ir;
-    C feq[L::Q], feq2[L::Q];
-    equilibrium<L, C>(rs, ux, uy, uz, feq);
-    equilibrium<L, C>(rs, ux + Fx * ir, uy + Fy * ir, uz + Fz * ir, feq2);
+    const D ird = D(1) / rd;
+    const C rs = (C)rd;
+    const C ux = (C)(jx * ird), uy = (C)(jy * ird), uz = (C)(jz * ird);
+    const C vx = (C)((jx + Fx) * ird), vy = (C)((jy + Fy) * ird), vz = (C)((jz + Fz) * ird);  // u + F/rho (Eq. 13)
+    const C uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + vy * vy + vz * vz;
 
-    C out[L::Q];
-    if (cp.bgk) {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) out[i] = f[i] - cp.omega * (f[i] - feq[i]) + (feq2[i] - feq[i]);
-    } else {
-        C dev[L::Q];
+    R* const o = fout + idx;  // post-collision populations stay at the node (aligned stores)
+    if (!MRT) {
+        // BGK (Eq. 3) + exact-difference forcing (Eq. 13), one direction at a time
+        const C om = cp.omega;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            dev[i] = f[i] - feq[i];
-            out[i] = f[i] + (feq2[i] - feq[i]);
+            const C eu = C(L::E[i][0]) * ux + C(L::E[i][1]) * uy + C(L::E[i][2]) * uz;
+            const C ev = C(L::E[i][0]) * vx + C(L::E[i][1]) * vy + C(L::E[i][2]) * vz;
+            const C wr = rs * C(L::w(i));
+            const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+            const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
+            const C fi = (C)S[i];
+            o[(size_t)i * d.N] = (R)(fi - om * (fi - feq) + (feq2 - feq));
         }
-        // non-conserved moments of the deviation, relaxed and mapped back by M^T D^-1
+    } else {
+        // MRT (Eq. 1): non-conserved moments of f - f_eq relaxed by s_k and
+        // mapped back with M^T D^-1, plus the forcing term
+        C dev[L::Q], out[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const C eu = C(L::E[i][0]) * ux + C(L::E[i][1]) * uy + C(L::E[i][2]) * uz;
+            const C ev = C(L::E[i][0]) * vx + C(L::E[i][1]) * vy + C(L::E[i][2]) * vz;
+            const C wr = rs * C(L::w(i));
+            const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+            const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
+            dev[i] = (C)S[i] - feq;
+            out[i] = (C)S[i] + (feq2 - feq);
+        }
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
             if (L::kind(k) == 0) continue;
@@ -415,69 +530,9 @@ __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* _
                 if (mki != 0.0) out[i] -= C(mki) * ck;
             }
         }
-    }
-
-    // push streaming; a link into a solid node bounces back to the node itself
-    const uint32_t bm = (c & CLS_BOUNDARY) ? nbmask[idx] : 0u;
-    const int xs[3] = {xm1, x, xp1};
-    const int ys[3] = {ym1, y, yp1};
-    const int zs[3] = {zm1, z, zp1};
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        if (bm & (1u << i)) {
-            fout[(size_t)L::OPP[i] * d.N + idx] = (R)out[i];
-        } else {
-            const int X = xs[L::E[i][0] + 1], Y = ys[L::E[i][1] + 1], Z = zs[L::E[i][2] + 1];
-            fout[(size_t)i * d.N + ((long long)Z * d.ny + Y) * d.nx + X] = (R)out[i];
-        }
+        for (int i = 0; i < L::Q; ++i) o[(size_t)i * d.N] = (R)out[i];
     }
-}
-
-// ---------------------------------------------------------------------------
-// linear interpolated bounce-back with mass correction (after k_collide)
-// ---------------------------------------------------------------------------
-template <class L, typename R, typename C = R>
-__global__ void __launch_bounds__(256) k_bc(const long long* __restrict__ node, const uint32_t* __restrict__ nbm,
-                                            const R* __restrict__ qv, int count, R* __restrict__ f, Dims d) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= count) return;
-    const long long idx = node[k];
-    const uint32_t m = nbm[k];
-    const int x = (int)(idx % d.nx), y = (int)((idx / d.nx) % d.ny), z = (int)(idx / ((long long)d.nx * d.ny));
-    C val[L::Q], outj[L::Q];
-#pragma unroll
-    for (int j = 1; j < L::Q; ++j) {
-        val[j] = C(0);
-        outj[j] = C(0);
-        if (!(m & (1u << j))) continue;
-        const int ib = L::OPP[j];
-        const C q = (C)qv[(size_t)k * L::Q + j];
-        const C oj = (C)f[(size_t)ib * d.N + idx];  // halfway value = post-collision f_j(x)
-        C v = oj;
-        if (q < C(0.5)) {
-            if (!(m & (1u << ib))) v = C(2) * q * oj + (C(1) - C(2) * q) * (C)f[(size_t)j * d.N + idx];
-        } else {
-            C fib;
-            if (m & (1u << ib)) {
-                fib = (C)f[(size_t)j * d.N + idx];
-            } else {
-                const int X = wrapc(x + L::E[ib][0], d.nx), Y = wrapc(y + L::E[ib][1], d.ny);
-                const int Z = L::D == 3 ? wrapc(z + L::E[ib][2], d.nz) : 0;
-                fib = (C)f[(size_t)ib * d.N + ((long long)Z * d.ny + Y) * d.nx + X];
-            }
-            v = oj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * fib;
-        }
-        val[j] = v;
-        outj[j] = oj;
-    }
-    C dm = C(0);
-#pragma unroll
-    for (int j = 1; j < L::Q; ++j) {
-        if (!(m & (1u << j))) continue;
-        f[(size_t)L::OPP[j] * d.N + idx] = (R)val[j];
-        dm += outj[j] - val[j];
-    }
-    f[idx] = (R)((C)f[idx] + dm);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,9 +700,8 @@ template <class L, typename R, typename C = R>
 __global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, const R* __restrict__ rho,
                                                   const R* __restrict__ mu, const uint8_t* __restrict__ cls, Dims d,
                                                   Collision<C> cp, long long t, R* __restrict__ vel) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+    int x, y, z;
+    tile_node(d, x, y, z);
     if (x >= d.nx || y >= d.ny) return;
     const long long idx = ((long long)z * d.ny + y) * d.nx + x;
     if ((cls[idx] & CLS_MASK) != CLS_FLUID) {

@@ -88,11 +88,12 @@ def test_d3q19_f64_bouzidi_periodic():
     fields_close(gp, o, 1e-12)
 
 
-@pytest.mark.parametrize("precision,steps,tol", [(G.LBM_F32_MIXED, 100, 2e-7), (G.LBM_F32, 20, 1e-6)])
+@pytest.mark.parametrize("precision,steps,tol", [(G.LBM_F32_MIXED, 100, 2e-7), (G.LBM_F32, 30, 1e-6)])
 def test_d3q19_f32_small(precision, steps, tol):
     """FP32 storage.  With FP64 arithmetic the density error stays at the
-    storage rounding (~1e-7) however long the run; FP32 arithmetic drifts by
-    ~3e-8 per step, so it is held to the 1e-6 bound over 20 steps only."""
+    storage rounding (~1e-7) however long the run; with FP32 arithmetic (FP64
+    force and moments) it drifts by ~1.2e-8 per step, so that mode is held to
+    the 1e-6 bound over 30 steps only."""
     wl = small_3d()
     gp = gpu_lattice(wl, precision, "bgk", "halfway", **SMALL)
     o = oracle_lattice(wl, "bgk", "halfway", **SMALL)
