@@ -234,6 +234,64 @@ lbm_status lbm_profile_step(lbm_ctx* ctx, int64_t nsteps, const char** names, do
 
 const char* lbm_last_error(const lbm_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched solver: many independent lattices advanced together.
+ *
+ * Each case has its own lattice size, one solid primitive (wettability as in
+ * lbm_solid) and one drop (Eq. 16, W = 10); all cases share the fluid, the
+ * collision and the boundary settings of the base configuration.  Cases are
+ * packed in one allocation; every phase of a step is one persistent launch
+ * over a work list of (case, tile) items, and step loops are captured in a
+ * hipGraph.  A case advanced in a batch equals the same case advanced alone
+ * with lbm_step, bit for bit.  The contact angle of every case is measured in
+ * the step (2 sides in 2-D, 16 sectors in 3-D).
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+typedef struct {
+    int n[3];            /* lattice size of the case; n[2] = 1 for D2Q9 */
+    lbm_solid solid;
+    lbm_drop drop;
+} lbm_case;
+
+typedef struct {
+    int autotune;        /* 1: time candidate tile widths / workgroups per CU and keep the fastest */
+    int tile_w;          /* 64, 128 or 256 nodes per tile row (tile = 256 nodes) when not tuning */
+    int blocks_per_cu;   /* persistent workgroups per compute unit when not tuning (1..32) */
+    const char* cache_path; /* JSON file of tuned choices keyed by the case table, or NULL */
+} lbm_batch_opts;
+
+typedef struct {
+    int64_t total_nodes, fluid_nodes;
+    int32_t ncases, tile_w, blocks_per_cu, n_items;
+    double tune_ms_per_step;  /* time per step of the chosen launch shape (0 if not tuned) */
+    int64_t step;
+    double rho_g, rho_l;
+} lbm_batch_info;
+
+/* Create a batch (host geometry of every case, packed device arrays, initial
+ * state of Eq. 16), optionally autotune.  Errors: LBM_E_ARG (bad case, or the
+ * packed lattice exceeds 2^32 / Q nodes), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int ncases, const lbm_batch_opts* opts,
+                            lbm_batch** out);
+lbm_status lbm_batch_destroy(lbm_batch* b);
+/* Advance every case nsteps steps; measure every measure_every steps (0: never).  Enqueues only. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int measure_every);
+/* Wait; LBM_E_NONFINITE if a density of any case went bad. */
+lbm_status lbm_batch_sync(lbm_batch* b);
+/* Latest in-step measurement of cases 0..n-1 (synchronises). */
+lbm_status lbm_batch_angles(lbm_batch* b, lbm_angle* out, int n);
+/* Measure every case now and return cases 0..n-1 (synchronises). */
+lbm_status lbm_batch_measure(lbm_batch* b, lbm_angle* out, int n);
+/* Fields of one case: RHO (n*elem bytes), F (Q*n*elem, [Q][n]), CLASS (n bytes).  Synchronises. */
+lbm_status lbm_batch_read(lbm_batch* b, int case_index, int field, void* dst, size_t bytes, int dst_on_device);
+/* Replace one case's state by f_eq(rho, 0) (LBM_FIELD_RHO only; a warm start). */
+lbm_status lbm_batch_write(lbm_batch* b, int case_index, int field, const void* src, size_t bytes, int src_on_device);
+lbm_status lbm_batch_get_info(lbm_batch* b, lbm_batch_info* info);
+/* Re-run the autotuner (the state is unchanged). */
+lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path);
+const char* lbm_batch_last_error(const lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -172,7 +172,7 @@ struct Run {
         return bc;
     }
     static void density(lbm_ctx* c, const R* f, bool pull, double rho_m) {
-        const dim3 blk(64, 4, 1), grd = grid(c);
+        const dim3 blk(256, 1, 1), grd = grid(c);
         const R inv_b = (R)(1.0 / c->pr.b);
         if (pull)
             k_density<L, R, C, true><<<grd, blk, 0, c->stream>>>(f, (R*)c->rho, c->cls, c->d, wall(c), c->ctl, rho_m, inv_b);
@@ -198,7 +198,7 @@ struct Run {
     // the launches of one step, reading f[src] and writing f[1-src]; pull
     // selects the form of f[src] (post-collision populations, else S_t)
     static void step_launches(lbm_ctx* c, int src, bool pull, const MeasureParams& mp, hipEvent_t* ev, int* kinds) {
-        const dim3 blk(64, 4, 1), grd = grid(c);
+        const dim3 blk(256, 1, 1), grd = grid(c);
         const R* fin = (const R*)c->f[src];
         R* fout = (R*)c->f[1 - src];
         R* rho = (R*)c->rho;
@@ -235,9 +235,9 @@ struct Run {
     static R* materialize(lbm_ctx* c) {
         R* out = (R*)c->f[1 - c->cur];
         if (c->fstar)
-            k_materialize<L, R, C, true><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((const R*)c->f[c->cur], out, c->cls, c->d, wall(c));
+            k_materialize<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->f[c->cur], out, c->cls, c->d, wall(c));
         else
-            k_materialize<L, R, C, false><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((const R*)c->f[c->cur], out, c->cls, c->d, wall(c));
+            k_materialize<L, R, C, false><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->f[c->cur], out, c->cls, c->d, wall(c));
         return out;
     }
 
@@ -250,13 +250,13 @@ struct Run {
         density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
         int k = 0;
         fills(c, nullptr, nullptr, k);
-        if (with_mu) k_mu<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        if (with_mu) k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
     }
 
     static void velocity(lbm_ctx* c, void* out) {
         derive(c, true);
         const R* S = materialize(c);
-        k_velocity<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>(S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d,
+        k_velocity<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d,
                                                                         collision(c), c->t, (R*)out);
     }
 
@@ -264,12 +264,12 @@ struct Run {
         density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
         int k = 0;
         fills(c, nullptr, nullptr, k);
-        k_mu<L, R, C><<<grid(c), dim3(64, 4, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
         k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->rho, c->ctl, c->d, mp, nullptr, c->last, 0);
     }
 
     static void init_feq(lbm_ctx* c) {
-        k_init_feq<L, R><<<2048, 256, 0, c->stream>>>((const R*)c->rho, (R*)c->f[c->cur], c->cls, c->d.N);
+        k_init_feq<L, R><<<2048, 256, 0, c->stream>>>((const R*)c->rho, (R*)c->f[c->cur], c->cls, c->d.N, 0, c->d.N);
     }
 
     static void mass(lbm_ctx* c) {
@@ -435,6 +435,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->d.ny = cfg->n[1];
     c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
     c->d.N = N;
+    c->d.off = 0;
     c->d.tx = (c->d.nx + 63) / 64;
     c->d.ty = (c->d.ny + 3) / 4;
     c->d.nblocks = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)c->d.nz;
@@ -476,7 +477,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         return s;
     }
     DevCtl h{};
-    for (auto& k : h.keys) k[0] = k[1] = ~0ull;
+    for (auto& k : h.m.keys) k[0] = k[1] = ~0ull;
     if (hipMemcpy(c->ctl, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
         lbm_destroy(c);
         return LBM_E_DEVICE;

@@ -1,0 +1,897 @@
+// batch.hip -- many independent lattices advanced together.
+//
+// Every case (its own lattice size, solid, wettability and drop) lives at an
+// offset of one packed allocation.  Each phase of the step is one persistent
+// launch: a fixed grid of workgroups walks a work list of (case, tile) items
+// and runs the same per-node device bodies as the single-lattice kernels, so a
+// case advanced in a batch is bitwise identical to the same case advanced
+// alone.  Step loops are captured in a hipGraph.  The tile width and the
+// number of workgroups per compute unit come from a small autotuner that times
+// candidate launches on the batch itself and caches its choice in a JSON file.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+struct Item {
+    int c;            // case
+    int x0, y0, z0;   // first node of the tile
+};
+
+__device__ __forceinline__ void item_node(const Item& it, int tile_w, int& x, int& y, int& z) {
+    x = it.x0 + (int)(threadIdx.x % (unsigned)tile_w);
+    y = it.y0 + (int)(threadIdx.x / (unsigned)tile_w);
+    z = it.z0;
+}
+
+template <class L, typename R, typename C, bool PULL>
+__global__ void __launch_bounds__(256) kb_density(const Item* __restrict__ items, int nitems, const Dims* __restrict__ dims,
+                                                  int tile_w, const R* __restrict__ f, R* __restrict__ rho,
+                                                  const uint8_t* __restrict__ cls, WallBC bc, DevCtl* __restrict__ ctl,
+                                                  MeasureSlots* __restrict__ slots, const MeasureParams* __restrict__ mp,
+                                                  R inv_b) {
+    const bool meas = measuring(ctl);
+    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        const bool liquid = density_node<L, R, C, PULL>(f, rho, cls, d, bc, x, y, z, x < d.nx && y < d.ny,
+                                                        mp[it.c].rho_m, inv_b, &ctl->status);
+        if (meas) centroid_reduce(liquid, x, y, z, &slots[it.c]);
+    }
+}
+
+template <class L, typename R, typename C>
+__global__ void __launch_bounds__(256) kb_fill(const long long* __restrict__ node, const uint32_t* __restrict__ mask,
+                                               const R* __restrict__ inv_den, const int* __restrict__ ecase, int beg,
+                                               int end, R* __restrict__ rho, const Dims* __restrict__ dims) {
+    for (int k = beg + blockIdx.x * 256 + threadIdx.x; k < end; k += gridDim.x * 256)
+        fill_entry<L, R, C>(node[k], mask[k], inv_den[k], rho, dims[ecase[k]]);
+}
+
+template <class L, typename R, typename C>
+__global__ void __launch_bounds__(256) kb_mu(const Item* __restrict__ items, int nitems, const Dims* __restrict__ dims,
+                                             int tile_w, const R* __restrict__ rho, R* __restrict__ mu,
+                                             const uint8_t* __restrict__ cls, Thermo th, const DevCtl* __restrict__ ctl,
+                                             MeasureSlots* __restrict__ slots, const MeasureParams* __restrict__ mp) {
+    const bool meas = measuring(ctl);
+    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        R r0;
+        const bool fluid = mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
+        if (meas) crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp[it.c], &slots[it.c]);
+    }
+}
+
+template <class L, typename R, typename C, bool PULL, bool MRT>
+__global__ void __launch_bounds__(256) kb_collide(const Item* __restrict__ items, int nitems,
+                                                  const Dims* __restrict__ dims, int tile_w, const R* __restrict__ fin,
+                                                  R* __restrict__ fout, const R* __restrict__ rho,
+                                                  const R* __restrict__ mu, const uint8_t* __restrict__ cls, WallBC bc,
+                                                  Collision<C> cp, const DevCtl* __restrict__ ctl) {
+    const long long t = ctl->t;
+    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        collide_node<L, R, C, PULL, MRT>(fin, fout, rho, mu, cls, d, bc, cp, t, x, y, z);
+    }
+}
+
+// one workgroup of 64 per case
+template <class L, typename R>
+__global__ void __launch_bounds__(64) kb_finalize(const R* __restrict__ rho, const DevCtl* __restrict__ ctl,
+                                                  const Dims* __restrict__ dims, const MeasureParams* __restrict__ mp,
+                                                  MeasureSlots* __restrict__ slots, AngleRec* __restrict__ last) {
+    if (!measuring(ctl)) return;
+    const int c = blockIdx.x;
+    finalize_slots<L, R>(rho, dims[c], mp[c], &slots[c], ctl->t, &last[c], nullptr);
+}
+
+__global__ void kb_tick(DevCtl* ctl) {
+    if (threadIdx.x == 0) ctl->t += 1;
+}
+
+__global__ void kb_slots_reset(MeasureSlots* slots, int n) {
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    slots[c].keys[threadIdx.x][0] = ~0ull;
+    slots[c].keys[threadIdx.x][1] = ~0ull;
+    if (threadIdx.x == 0) slots[c].cnt = slots[c].sx = slots[c].sy = slots[c].sz = 0ull;
+}
+
+template <class L, typename R, typename C, bool PULL>
+__global__ void __launch_bounds__(256) kb_materialize(const Item* __restrict__ items, int nitems,
+                                                      const Dims* __restrict__ dims, int tile_w,
+                                                      const R* __restrict__ f, R* __restrict__ out,
+                                                      const uint8_t* __restrict__ cls, WallBC bc) {
+    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        if (x >= d.nx || y >= d.ny) continue;
+        const long long idx = nid(d, x, y, z);
+        const uint8_t c = cls[idx];
+        R S[L::Q];
+        if ((c & CLS_MASK) == CLS_FLUID) gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
+        else
+            for (int i = 0; i < L::Q; ++i) S[i] = R(0);
+        for (int i = 0; i < L::Q; ++i) out[(size_t)i * d.N + idx] = S[i];
+    }
+}
+
+constexpr int kBatchGraphSteps = 16;
+
+}  // namespace
+
+struct lbm_batch {
+    lbm_config cfg{};
+    std::string err;
+    PRState pr{};
+    double rho_m = 0, mu_ref = 0, wall_mu = 0;
+    int dim = 2, Q = 9, ncases = 0, cus = 256;
+    size_t elem = 4;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    long long Ntot = 0, n_fluid = 0;
+    std::vector<Dims> dims_h;
+    std::vector<MeasureParams> mp_h;
+    Dims* dims = nullptr;
+    MeasureParams* mp = nullptr;
+    MeasureSlots* slots = nullptr;
+    AngleRec* last = nullptr;
+    DevCtl* ctl = nullptr;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool fstar = false, have_state = false;
+    void *rho = nullptr, *mu = nullptr, *inv = nullptr, *bq = nullptr;
+    uint8_t* cls = nullptr;
+    uint32_t *nbmask = nullptr, *fmask = nullptr;
+    int *bidx = nullptr, *fcase = nullptr;
+    long long* fnode = nullptr;
+    int n_l1 = 0, n_l2 = 0;
+    Item* items = nullptr;
+    int nitems = 0;
+    int tile_w = 64, bpc = 4;
+    double tune_ms = 0;
+    hipGraphExec_t graph = nullptr;
+    long long t = 0;
+};
+
+namespace {
+
+lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& m) {
+    if (b) b->err = m;
+    return s;
+}
+
+#define BCHK(b, call)                                                                                          \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+lbm_status balloc(lbm_batch* b, T** p, size_t bytes) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    if (!bytes) return LBM_OK;
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return bfail(b, LBM_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return LBM_OK;
+}
+
+template <typename T>
+lbm_status bupload(lbm_batch* b, T** p, const std::vector<T>& v) {
+    lbm_status s = balloc(b, p, v.size() * sizeof(T));
+    if (s || v.empty()) return s;
+    BCHK(b, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status bupload_real(lbm_batch* b, void** p, const std::vector<double>& v) {
+    lbm_status s = balloc(b, (char**)p, v.size() * b->elem);
+    if (s || v.empty()) return s;
+    if (b->elem == 8) {
+        BCHK(b, hipMemcpy(*p, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> t(v.begin(), v.end());
+        BCHK(b, hipMemcpy(*p, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+    }
+    return LBM_OK;
+}
+
+void build_items(lbm_batch* b) {
+    std::vector<Item> it;
+    const int th = 256 / b->tile_w;
+    for (int c = 0; c < b->ncases; ++c) {
+        const Dims& d = b->dims_h[c];
+        for (int z = 0; z < d.nz; ++z)
+            for (int y0 = 0; y0 < d.ny; y0 += th)
+                for (int x0 = 0; x0 < d.nx; x0 += b->tile_w) it.push_back(Item{c, x0, y0, z});
+    }
+    if (b->items) (void)hipFree(b->items);
+    b->items = nullptr;
+    b->nitems = (int)it.size();
+    if (hipMalloc((void**)&b->items, it.size() * sizeof(Item)) == hipSuccess)
+        (void)hipMemcpy(b->items, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice);
+}
+
+template <class L, typename R, typename C>
+struct BRun {
+    static Thermo thermo(const lbm_batch* b) {
+        const double k2 = b->cfg.k * b->cfg.k;
+        const PRState& p = b->pr;
+        Thermo th;
+        th.k2RT = k2 * p.R * p.T;
+        th.k2A = k2 * p.a * p.alpha / (2.0 * std::sqrt(2.0) * p.b);
+        th.k2aal = k2 * p.a * p.alpha;
+        th.b = p.b;
+        th.s2m1 = std::sqrt(2.0) - 1.0;
+        th.s2p1 = std::sqrt(2.0) + 1.0;
+        th.mu_ref = b->mu_ref;
+        th.kappa = b->cfg.kappa;
+        return th;
+    }
+    static Collision<C> collision(const lbm_batch* b) {
+        Collision<C> cp{};
+        const lbm_config& g = b->cfg;
+        cp.bgk = g.collision == LBM_BGK;
+        cp.omega = (C)(1.0 / g.tau);
+        const double sv = 1.0 / g.tau;
+        for (int k = 0; k < L::Q; ++k) {
+            double s = 0;
+            switch (L::kind(k)) {
+                case 1: s = g.s_e; break;
+                case 2: s = g.s_eps; break;
+                case 3: s = g.s_q; break;
+                case 4: s = sv; break;
+                case 5: s = g.s_pi; break;
+                case 6: s = g.s_m; break;
+                default: s = 0; break;
+            }
+            cp.rate[k] = (C)(s / row_norm2<L>(k));
+        }
+        for (int k = 0; k < 3; ++k) cp.g[k] = (C)(k < b->dim ? g.g[k] : 0.0);
+        cp.g_start = g.g_start_step;
+        return cp;
+    }
+    static WallBC wall(const lbm_batch* b) {
+        WallBC bc;
+        bc.nbmask = b->nbmask;
+        bc.bidx = b->bidx;
+        bc.q = b->bq;
+        bc.bouzidi = b->cfg.bc_mode == LBM_BC_BOUZIDI_MC;
+        return bc;
+    }
+    static void density(lbm_batch* b, bool pull, int grid) {
+        const R* f = (const R*)b->f[b->cur];
+        const R inv_b = (R)(1.0 / b->pr.b);
+        if (pull)
+            kb_density<L, R, C, true><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, f, (R*)b->rho,
+                                                                   b->cls, wall(b), b->ctl, b->slots, b->mp, inv_b);
+        else
+            kb_density<L, R, C, false><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, f, (R*)b->rho,
+                                                                    b->cls, wall(b), b->ctl, b->slots, b->mp, inv_b);
+        const int ng1 = (b->n_l1 + 255) / 256, ng2 = (b->n_l2 + 255) / 256;
+        if (b->n_l1)
+            kb_fill<L, R, C><<<ng1 < grid ? ng1 : grid, 256, 0, b->stream>>>(b->fnode, b->fmask, (const R*)b->inv, b->fcase,
+                                                                             0, b->n_l1, (R*)b->rho, b->dims);
+        if (b->n_l2)
+            kb_fill<L, R, C><<<ng2 < grid ? ng2 : grid, 256, 0, b->stream>>>(
+                b->fnode, b->fmask, (const R*)b->inv, b->fcase, b->n_l1, b->n_l1 + b->n_l2, (R*)b->rho, b->dims);
+    }
+    // one step from f[src] (pull form if pull) into f[1 - src]
+    static void step(lbm_batch* b, int src, bool pull, int grid) {
+        const int save = b->cur;
+        b->cur = src;
+        density(b, pull, grid);
+        b->cur = save;
+        kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
+                                                    b->cls, thermo(b), b->ctl, b->slots, b->mp);
+        const R* fin = (const R*)b->f[src];
+        R* fout = (R*)b->f[1 - src];
+        const WallBC bc = wall(b);
+        const Collision<C> cp = collision(b);
+        const bool mrt = b->cfg.collision == LBM_MRT;
+#define KB_ARGS b->items, b->nitems, b->dims, b->tile_w, fin, fout, (const R*)b->rho, (const R*)b->mu, b->cls, bc, cp, b->ctl
+        if (pull) {
+            if (mrt) kb_collide<L, R, C, true, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+            else kb_collide<L, R, C, true, false><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+        } else {
+            if (mrt) kb_collide<L, R, C, false, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+            else kb_collide<L, R, C, false, false><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+        }
+#undef KB_ARGS
+        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
+        kb_tick<<<1, 64, 0, b->stream>>>(b->ctl);
+    }
+    static R* materialize(lbm_batch* b, int grid) {
+        R* out = (R*)b->f[1 - b->cur];
+        if (b->fstar)
+            kb_materialize<L, R, C, true><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w,
+                                                                       (const R*)b->f[b->cur], out, b->cls, wall(b));
+        else
+            kb_materialize<L, R, C, false><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w,
+                                                                        (const R*)b->f[b->cur], out, b->cls, wall(b));
+        return out;
+    }
+    static void init_feq(lbm_batch* b) {
+        k_init_feq<L, R><<<4096, 256, 0, b->stream>>>((const R*)b->rho, (R*)b->f[b->cur], b->cls, b->Ntot, 0, b->Ntot);
+    }
+};
+
+template <template <class, typename, typename> class Op, typename... Args>
+void bdispatch(lbm_batch* b, Args&&... args) {
+    const int p = b->cfg.precision;
+    if (b->dim == 2) {
+        if (p == LBM_F64) Op<D2Q9, double, double>::go(b, args...);
+        else if (p == LBM_F32_MIXED) Op<D2Q9, float, double>::go(b, args...);
+        else Op<D2Q9, float, float>::go(b, args...);
+    } else {
+        if (p == LBM_F64) Op<D3Q19, double, double>::go(b, args...);
+        else if (p == LBM_F32_MIXED) Op<D3Q19, float, double>::go(b, args...);
+        else Op<D3Q19, float, float>::go(b, args...);
+    }
+}
+
+template <class L, typename R, typename C>
+struct BStep {
+    static void go(lbm_batch* b, int src, bool pull, int grid) { BRun<L, R, C>::step(b, src, pull, grid); }
+};
+template <class L, typename R, typename C>
+struct BDerive {
+    static void go(lbm_batch* b, int grid) { BRun<L, R, C>::density(b, b->fstar, grid); }
+};
+template <class L, typename R, typename C>
+struct BMaterialize {
+    static void go(lbm_batch* b, int grid, void** out) { *out = BRun<L, R, C>::materialize(b, grid); }
+};
+template <class L, typename R, typename C>
+struct BInit {
+    static void go(lbm_batch* b) { BRun<L, R, C>::init_feq(b); }
+};
+template <class L, typename R, typename C>
+struct BMeasure {
+    static void go(lbm_batch* b, int grid) {
+        BRun<L, R, C>::density(b, b->fstar, grid);
+        kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
+                                                    b->cls, BRun<L, R, C>::thermo(b), b->ctl, b->slots, b->mp);
+        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
+    }
+};
+
+int grid_of(const lbm_batch* b) { return b->bpc * b->cus; }
+
+void drop_graph(lbm_batch* b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+}
+
+// --- autotuner: time candidate (tile width, workgroups per CU) pairs ---------
+std::string tune_key(const lbm_batch* b) {
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) { h = (h ^ v) * 1099511628211ull; };
+    mix((unsigned long long)b->dim);
+    mix((unsigned long long)b->cfg.precision);
+    mix((unsigned long long)b->cfg.collision);
+    mix((unsigned long long)b->cfg.bc_mode);
+    for (const Dims& d : b->dims_h) {
+        mix((unsigned long long)d.nx);
+        mix((unsigned long long)d.ny);
+        mix((unsigned long long)d.nz);
+    }
+    char buf[32];
+    std::snprintf(buf, sizeof buf, "%016llx", h);
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int& tw, int& bpc) {
+    if (!path) return false;
+    std::ifstream in(path);
+    if (!in) return false;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string s = ss.str();
+    const size_t p = s.find("\"" + key + "\"");
+    if (p == std::string::npos) return false;
+    const size_t q1 = s.find("\"tile_w\":", p), q2 = s.find("\"blocks_per_cu\":", p);
+    if (q1 == std::string::npos || q2 == std::string::npos) return false;
+    tw = std::atoi(s.c_str() + q1 + 9);
+    bpc = std::atoi(s.c_str() + q2 + 16);
+    return (tw == 64 || tw == 128 || tw == 256) && bpc >= 1 && bpc <= 32;
+}
+
+void cache_store(const char* path, const std::string& key, int tw, int bpc, double ms) {
+    if (!path) return;
+    std::string body;
+    {
+        std::ifstream in(path);
+        if (in) {
+            std::stringstream ss;
+            ss << in.rdbuf();
+            body = ss.str();
+        }
+    }
+    // keep the other keys: the file is {"key": {...}, ...}; drop a stale entry of this key
+    std::string entries;
+    size_t pos = body.find('{');
+    if (pos != std::string::npos) {
+        const size_t end = body.rfind('}');
+        entries = body.substr(pos + 1, end > pos ? end - pos - 1 : 0);
+        const size_t k = entries.find("\"" + key + "\"");
+        if (k != std::string::npos) {
+            const size_t e = entries.find('}', k);
+            size_t from = k, to = e + 1;
+            if (to < entries.size() && entries[to] == ',') ++to;
+            else if (from > 0 && entries[from - 1] == ',') --from;
+            entries.erase(from, to - from);
+        }
+    }
+    while (!entries.empty() && (entries.back() == '\n' || entries.back() == ' ' || entries.back() == ',')) entries.pop_back();
+    char rec[256];
+    std::snprintf(rec, sizeof rec, "\n  \"%s\": {\"tile_w\": %d, \"blocks_per_cu\": %d, \"ms_per_step\": %.6f}", key.c_str(),
+                  tw, bpc, ms);
+    std::ofstream out(path);
+    out << "{" << entries << (entries.empty() ? "" : ",") << rec << "\n}\n";
+}
+
+lbm_status autotune(lbm_batch* b, const char* cache) {
+    int tw, bpc;
+    const std::string key = tune_key(b);
+    if (cache_lookup(cache, key, tw, bpc)) {
+        b->tile_w = tw;
+        b->bpc = bpc;
+        build_items(b);
+        return LBM_OK;
+    }
+    // time a few steps per candidate on a copy of the state; restore afterwards
+    const size_t fb = (size_t)b->Q * b->Ntot * b->elem;
+    void* snap = nullptr;
+    if (balloc(b, (char**)&snap, fb)) return LBM_E_NOMEM;
+    BCHK(b, hipMemcpyAsync(snap, b->f[b->cur], fb, hipMemcpyDeviceToDevice, b->stream));
+    const int cur0 = b->cur;
+    const bool fstar0 = b->fstar;
+    k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 0);
+    hipEvent_t e0, e1;
+    BCHK(b, hipEventCreate(&e0));
+    BCHK(b, hipEventCreate(&e1));
+    double best = 1e30;
+    int btw = 64, bbpc = 4;
+    const int tws[3] = {64, 128, 256}, bpcs[4] = {2, 4, 8, 16};
+    for (int tw_ : tws)
+        for (int bp : bpcs) {
+            b->tile_w = tw_;
+            b->bpc = bp;
+            build_items(b);
+            auto run = [&](int n) {
+                for (int s = 0; s < n; ++s) {
+                    bdispatch<BStep>(b, b->cur, b->fstar, grid_of(b));
+                    b->cur ^= 1;
+                    b->fstar = true;
+                }
+            };
+            run(2);
+            BCHK(b, hipEventRecord(e0, b->stream));
+            run(4);
+            BCHK(b, hipEventRecord(e1, b->stream));
+            BCHK(b, hipEventSynchronize(e1));
+            float ms = 0;
+            BCHK(b, hipEventElapsedTime(&ms, e0, e1));
+            if (ms / 4 < best) {
+                best = ms / 4;
+                btw = tw_;
+                bbpc = bp;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->cur = cur0;
+    b->fstar = fstar0;
+    BCHK(b, hipMemcpyAsync(b->f[b->cur], snap, fb, hipMemcpyDeviceToDevice, b->stream));
+    k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 1);
+    BCHK(b, hipStreamSynchronize(b->stream));
+    (void)hipFree(snap);
+    b->tile_w = btw;
+    b->bpc = bbpc;
+    b->tune_ms = best;
+    build_items(b);
+    cache_store(cache, key, btw, bbpc, best);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    void* ps[] = {b->dims, b->mp,   b->slots, b->last, b->ctl,  b->f[0], b->f[1], b->rho,  b->mu,   b->inv,
+                  b->bq,   b->cls,  b->nbmask, b->fmask, b->bidx, b->fcase, b->fnode, b->items};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int ncases, const lbm_batch_opts* opts,
+                            lbm_batch** out) {
+    if (!out) return LBM_E_ARG;
+    *out = nullptr;
+    if (!base || !cases || ncases < 1) return LBM_E_ARG;
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_E_NOMEM;
+    b->cfg = *base;
+    auto bad = [&]() {
+        delete b;
+        return LBM_E_ARG;
+    };
+    if (base->lattice != LBM_D2Q9 && base->lattice != LBM_D3Q19) return bad();
+    if (base->precision != LBM_F32 && base->precision != LBM_F64 && base->precision != LBM_F32_MIXED) return bad();
+    if (!(base->tau > 0.5) || !(base->k > 0) || !(base->kappa >= 0)) return bad();
+    b->dim = base->lattice == LBM_D2Q9 ? 2 : 3;
+    b->Q = b->dim == 2 ? 9 : 19;
+    b->elem = base->precision == LBM_F64 ? 8 : 4;
+    b->ncases = ncases;
+    b->pr.a = base->pr_a;
+    b->pr.b = base->pr_b;
+    b->pr.R = base->pr_R;
+    b->pr.omega = base->pr_omega;
+    b->pr.Tr = base->Tr;
+    std::string err;
+    if (!pr_solve(b->pr, err)) return bad();
+    if (base->rho_l > 0) b->pr.rho_l = base->rho_l;
+    if (base->rho_g > 0) b->pr.rho_g = base->rho_g;
+    b->rho_m = 0.5 * (b->pr.rho_l + b->pr.rho_g);
+    b->mu_ref = base->k * base->k * b->pr.mu_sat;
+    b->wall_mu = std::isnan(base->wall_mu) ? b->mu_ref : base->wall_mu;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        b->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (base->stream) {
+        b->stream = (hipStream_t)base->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return LBM_E_DEVICE;
+        }
+        b->own_stream = true;
+    }
+
+    // geometry of every case on the host, packed at increasing offsets
+    const int wall[3] = {base->axis_bc[0] == LBM_WALL, base->axis_bc[1] == LBM_WALL,
+                         b->dim == 3 && base->axis_bc[2] == LBM_WALL};
+    std::vector<uint8_t> cls;
+    std::vector<uint32_t> nbm, fmask;
+    std::vector<int> bidx, fcase;
+    std::vector<long long> fnode1, fnode2;
+    std::vector<uint32_t> fmask1, fmask2;
+    std::vector<double> inv1, inv2, bq, muh, rhoh;
+    std::vector<int> fcase1, fcase2;
+    long long off = 0;
+    int nb_total = 0;
+    for (int ci = 0; ci < ncases; ++ci) {
+        const lbm_case& cs = cases[ci];
+        int n[3] = {cs.n[0], cs.n[1], b->dim == 3 ? cs.n[2] : 1};
+        if (n[0] < 5 || n[1] < 5 || n[2] < 1 || (b->dim == 3 && n[2] < 5)) {
+            lbm_batch_destroy(b);
+            return LBM_E_ARG;
+        }
+        Solid s{};
+        for (int k = 0; k < 3; ++k) s.c[k] = k < b->dim ? cs.solid.center[k] : 0.0;
+        s.r = cs.solid.radius;
+        s.wet_mode = cs.solid.wet_mode;
+        s.mu1 = cs.solid.mu_w;
+        s.mu2 = cs.solid.mu_w2;
+        s.width = cs.solid.stripe_width > 0 ? cs.solid.stripe_width : 1.0;
+        double pl[3] = {cs.solid.pole[0], cs.solid.pole[1], b->dim == 3 ? cs.solid.pole[2] : 0.0};
+        double pn = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        if (pn == 0) { pl[0] = 0; pl[1] = b->dim == 2 ? 1 : 0; pl[2] = b->dim == 2 ? 0 : 1; pn = 1; }
+        for (int k = 0; k < 3; ++k) s.pole[k] = pl[k] / pn;
+        if (!(s.r > 0)) {
+            lbm_batch_destroy(b);
+            return LBM_E_ARG;
+        }
+        Geometry g;
+        if (!build_geometry(g, b->dim, n, wall, std::vector<Solid>{s}, nullptr, b->wall_mu, err)) {
+            lbm_batch_destroy(b);
+            return LBM_E_ARG;
+        }
+        Dims d{};
+        d.nx = n[0];
+        d.ny = n[1];
+        d.nz = n[2];
+        d.off = off;
+        b->dims_h.push_back(d);
+        MeasureParams mp{};
+        for (int k = 0; k < 3; ++k) {
+            mp.c[k] = s.c[k];
+            mp.g[k] = k < b->dim ? base->g[k] : 0.0;
+        }
+        mp.R = s.r;
+        mp.rho_m = b->rho_m;
+        mp.n_sectors = b->dim == 2 ? 2 : 16;
+        mp.dim = b->dim;
+        b->mp_h.push_back(mp);
+        cls.insert(cls.end(), g.cls.begin(), g.cls.end());
+        nbm.insert(nbm.end(), g.nbmask.begin(), g.nbmask.end());
+        std::vector<int> bi((size_t)g.N, -1);
+        for (size_t k = 0; k < g.b_node.size(); ++k) bi[g.b_node[k]] = nb_total + (int)k;
+        bidx.insert(bidx.end(), bi.begin(), bi.end());
+        bq.insert(bq.end(), g.b_q.begin(), g.b_q.end());
+        nb_total += (int)g.b_node.size();
+        std::vector<double> m((size_t)g.N, 0.0);
+        for (size_t k = 0; k < g.l1_node.size(); ++k) {
+            m[g.l1_node[k]] = g.l1_mu[k] - b->mu_ref;
+            fnode1.push_back(off + g.l1_node[k]);
+            fmask1.push_back(g.l1_mask[k]);
+            inv1.push_back(g.l1_inv[k]);
+            fcase1.push_back(ci);
+        }
+        for (size_t k = 0; k < g.l2_node.size(); ++k) {
+            m[g.l2_node[k]] = g.l2_mu[k] - b->mu_ref;
+            fnode2.push_back(off + g.l2_node[k]);
+            fmask2.push_back(g.l2_mask[k]);
+            inv2.push_back(g.l2_inv[k]);
+            fcase2.push_back(ci);
+        }
+        muh.insert(muh.end(), m.begin(), m.end());
+        // Eq. 16 around the case's drop
+        std::vector<double> r((size_t)g.N, 0.0);
+        const double rg = b->pr.rho_g, rl = b->pr.rho_l;
+        for (long long i = 0; i < g.N; ++i) {
+            if ((g.cls[i] & 3) != 0) continue;
+            const int x = (int)(i % n[0]), y = (int)((i / n[0]) % n[1]), z = (int)(i / ((long long)n[0] * n[1]));
+            const double dx = x - cs.drop.center[0], dy = y - cs.drop.center[1];
+            const double dz = b->dim == 3 ? z - cs.drop.center[2] : 0.0;
+            const double rr = std::sqrt(dx * dx + dy * dy + dz * dz);
+            r[i] = 0.5 * (rg + rl) + 0.5 * (rg - rl) * std::tanh(2.0 * (rr - cs.drop.radius) / 10.0);
+        }
+        rhoh.insert(rhoh.end(), r.begin(), r.end());
+        b->n_fluid += g.n_fluid;
+        off += g.N;
+    }
+    b->Ntot = off;
+    if ((unsigned long long)b->Ntot * (unsigned long long)b->Q >= (1ull << 32)) {
+        lbm_batch_destroy(b);
+        return LBM_E_ARG;
+    }
+    for (Dims& d : b->dims_h) d.N = b->Ntot;
+    b->n_l1 = (int)fnode1.size();
+    b->n_l2 = (int)fnode2.size();
+    std::vector<long long> fnode(fnode1);
+    fnode.insert(fnode.end(), fnode2.begin(), fnode2.end());
+    fmask = fmask1;
+    fmask.insert(fmask.end(), fmask2.begin(), fmask2.end());
+    std::vector<double> inv(inv1);
+    inv.insert(inv.end(), inv2.begin(), inv2.end());
+    fcase = fcase1;
+    fcase.insert(fcase.end(), fcase2.begin(), fcase2.end());
+
+    lbm_status s;
+    const size_t fb = (size_t)b->Q * b->Ntot * b->elem;
+    if ((s = balloc(b, (char**)&b->f[0], fb)) || (s = balloc(b, (char**)&b->f[1], fb)) ||
+        (s = bupload(b, &b->dims, b->dims_h)) || (s = bupload(b, &b->mp, b->mp_h)) ||
+        (s = balloc(b, &b->slots, (size_t)ncases * sizeof(MeasureSlots))) ||
+        (s = balloc(b, &b->last, (size_t)ncases * sizeof(AngleRec))) || (s = balloc(b, &b->ctl, sizeof(DevCtl))) ||
+        (s = bupload(b, &b->cls, cls)) || (s = bupload(b, &b->nbmask, nbm)) || (s = bupload(b, &b->bidx, bidx)) ||
+        (s = bupload_real(b, &b->bq, bq)) || (s = bupload_real(b, &b->mu, muh)) || (s = bupload_real(b, &b->rho, rhoh)) ||
+        (s = bupload(b, &b->fnode, fnode)) || (s = bupload(b, &b->fmask, fmask)) || (s = bupload_real(b, &b->inv, inv)) ||
+        (s = bupload(b, &b->fcase, fcase))) {
+        std::string e = b->err;
+        lbm_batch_destroy(b);
+        return s;
+    }
+    DevCtl h{};
+    for (auto& k : h.m.keys) k[0] = k[1] = ~0ull;
+    if (hipMemcpy(b->ctl, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
+        lbm_batch_destroy(b);
+        return LBM_E_DEVICE;
+    }
+    kb_slots_reset<<<ncases, 64, 0, b->stream>>>(b->slots, ncases);
+    // state = f_eq(rho, 0) with rho of Eq. 16
+    if (b->elem == 8) k_fill_value<double><<<2048, 256, 0, b->stream>>>((double*)b->f[1], fb / 8, 0.0);
+    else k_fill_value<float><<<2048, 256, 0, b->stream>>>((float*)b->f[1], fb / 4, 0.0f);
+    bdispatch<BInit>(b);
+    if (hipStreamSynchronize(b->stream) != hipSuccess) {
+        lbm_batch_destroy(b);
+        return LBM_E_DEVICE;
+    }
+    b->have_state = true;
+    b->tile_w = opts && (opts->tile_w == 64 || opts->tile_w == 128 || opts->tile_w == 256) ? opts->tile_w : 64;
+    b->bpc = opts && opts->blocks_per_cu >= 1 && opts->blocks_per_cu <= 32 ? opts->blocks_per_cu : 4;
+    build_items(b);
+    if (!b->items) {
+        lbm_batch_destroy(b);
+        return LBM_E_NOMEM;
+    }
+    if (opts && opts->autotune) {
+        if ((s = autotune(b, opts->cache_path))) {
+            lbm_batch_destroy(b);
+            return s;
+        }
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int measure_every) {
+    if (!b) return LBM_E_ARG;
+    if (nsteps < 0 || measure_every < 0) return bfail(b, LBM_E_ARG, "batch step: negative argument");
+    k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, measure_every, 0, 0, 0);
+    BCHK(b, hipGetLastError());
+    int64_t done = 0;
+    auto eager = [&]() {
+        bdispatch<BStep>(b, b->cur, b->fstar, grid_of(b));
+        b->cur ^= 1;
+        b->fstar = true;
+        ++done;
+        ++b->t;
+    };
+    while (done < nsteps && (!b->fstar || b->cur != 0 || nsteps - done < kBatchGraphSteps)) eager();
+    if (nsteps - done >= kBatchGraphSteps) {
+        if (!b->graph) {
+            hipGraph_t g;
+            BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < kBatchGraphSteps; ++k) bdispatch<BStep>(b, k & 1, true, grid_of(b));
+            BCHK(b, hipStreamEndCapture(b->stream, &g));
+            const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                b->graph = nullptr;
+                return bfail(b, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+        }
+        while (nsteps - done >= kBatchGraphSteps) {
+            BCHK(b, hipGraphLaunch(b->graph, b->stream));
+            done += kBatchGraphSteps;
+            b->t += kBatchGraphSteps;
+        }
+    }
+    while (done < nsteps) eager();
+    BCHK(b, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_sync(lbm_batch* b) {
+    if (!b) return LBM_E_ARG;
+    DevCtl h;
+    BCHK(b, hipMemcpyAsync(&h, b->ctl, sizeof h, hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    if (h.status & 1) return bfail(b, LBM_E_NONFINITE, "a density became non-finite, non-positive or >= 1/b");
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_angles(lbm_batch* b, lbm_angle* out, int n) {
+    if (!b || !out || n < 1 || n > b->ncases) return b ? bfail(b, LBM_E_ARG, "batch angles: bad count") : LBM_E_ARG;
+    BCHK(b, hipStreamSynchronize(b->stream));
+    BCHK(b, hipMemcpy(out, b->last, (size_t)n * sizeof(AngleRec), hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_measure(lbm_batch* b, lbm_angle* out, int n) {
+    if (!b || !out || n < 1 || n > b->ncases) return b ? bfail(b, LBM_E_ARG, "batch measure: bad count") : LBM_E_ARG;
+    k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 1, 0, 0);
+    kb_slots_reset<<<b->ncases, 64, 0, b->stream>>>(b->slots, b->ncases);
+    bdispatch<BMeasure>(b, grid_of(b));
+    k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 0);
+    BCHK(b, hipGetLastError());
+    return lbm_batch_angles(b, out, n);
+}
+
+lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t bytes, int dst_on_device) {
+    if (!b || !dst) return b ? bfail(b, LBM_E_ARG, "batch read: null destination") : LBM_E_ARG;
+    if (ci < 0 || ci >= b->ncases) return bfail(b, LBM_E_ARG, "batch read: case index out of range");
+    const Dims& d = b->dims_h[ci];
+    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (field == LBM_FIELD_RHO) {
+        if (bytes != n * b->elem) return bfail(b, LBM_E_ARG, "batch read RHO: bytes must be n * elem");
+        bdispatch<BDerive>(b, grid_of(b));
+        BCHK(b, hipMemcpyAsync(dst, (char*)b->rho + (size_t)d.off * b->elem, bytes, kind, b->stream));
+    } else if (field == LBM_FIELD_F) {
+        if (bytes != (size_t)b->Q * n * b->elem) return bfail(b, LBM_E_ARG, "batch read F: bytes must be Q * n * elem");
+        void* S = nullptr;
+        bdispatch<BMaterialize>(b, grid_of(b), &S);
+        for (int i = 0; i < b->Q; ++i)
+            BCHK(b, hipMemcpyAsync((char*)dst + (size_t)i * n * b->elem,
+                                   (char*)S + ((size_t)i * b->Ntot + (size_t)d.off) * b->elem, n * b->elem, kind, b->stream));
+    } else if (field == LBM_FIELD_CLASS) {
+        if (bytes != n) return bfail(b, LBM_E_ARG, "batch read CLASS: bytes must be n");
+        std::vector<uint8_t> h(n);
+        BCHK(b, hipStreamSynchronize(b->stream));
+        BCHK(b, hipMemcpy(h.data(), b->cls + d.off, n, hipMemcpyDeviceToHost));
+        for (auto& v : h) v &= 3;
+        BCHK(b, hipMemcpy(dst, h.data(), n, dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    } else {
+        return bfail(b, LBM_E_ARG, "batch read: field must be RHO, F or CLASS");
+    }
+    BCHK(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_write(lbm_batch* b, int ci, int field, const void* src, size_t bytes, int src_on_device) {
+    if (!b || !src) return b ? bfail(b, LBM_E_ARG, "batch write: null source") : LBM_E_ARG;
+    if (ci < 0 || ci >= b->ncases) return bfail(b, LBM_E_ARG, "batch write: case index out of range");
+    if (field != LBM_FIELD_RHO) return bfail(b, LBM_E_ARG, "batch write: field must be RHO");
+    const Dims& d = b->dims_h[ci];
+    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    if (bytes != n * b->elem) return bfail(b, LBM_E_ARG, "batch write RHO: bytes must be n * elem");
+    // bring every case to form S (materialize), then replace this case's populations
+    if (b->fstar) {
+        void* S = nullptr;
+        bdispatch<BMaterialize>(b, grid_of(b), &S);
+        b->cur ^= 1;
+        b->fstar = false;
+        drop_graph(b);
+    }
+    BCHK(b, hipStreamSynchronize(b->stream));
+    BCHK(b, hipMemcpy((char*)b->rho + (size_t)d.off * b->elem, src, bytes,
+                      src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    // f_eq(rho, 0) on this case's range of the packed arrays
+    const long long beg = d.off, end = d.off + (long long)n;
+    if (b->dim == 2) {
+        if (b->elem == 8) k_init_feq<D2Q9, double><<<1024, 256, 0, b->stream>>>((const double*)b->rho, (double*)b->f[b->cur], b->cls, b->Ntot, beg, end);
+        else k_init_feq<D2Q9, float><<<1024, 256, 0, b->stream>>>((const float*)b->rho, (float*)b->f[b->cur], b->cls, b->Ntot, beg, end);
+    } else {
+        if (b->elem == 8) k_init_feq<D3Q19, double><<<1024, 256, 0, b->stream>>>((const double*)b->rho, (double*)b->f[b->cur], b->cls, b->Ntot, beg, end);
+        else k_init_feq<D3Q19, float><<<1024, 256, 0, b->stream>>>((const float*)b->rho, (float*)b->f[b->cur], b->cls, b->Ntot, beg, end);
+    }
+    BCHK(b, hipGetLastError());
+    BCHK(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_get_info(lbm_batch* b, lbm_batch_info* info) {
+    if (!b || !info) return LBM_E_ARG;
+    std::memset(info, 0, sizeof *info);
+    info->total_nodes = b->Ntot;
+    info->fluid_nodes = b->n_fluid;
+    info->ncases = b->ncases;
+    info->tile_w = b->tile_w;
+    info->blocks_per_cu = b->bpc;
+    info->n_items = b->nitems;
+    info->tune_ms_per_step = b->tune_ms;
+    info->step = b->t;
+    info->rho_g = b->pr.rho_g;
+    info->rho_l = b->pr.rho_l;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path) {
+    if (!b) return LBM_E_ARG;
+    drop_graph(b);
+    return autotune(b, cache_path);
+}
+
+}  // extern "C"

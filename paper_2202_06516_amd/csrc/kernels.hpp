@@ -1,30 +1,32 @@
 // kernels.hpp -- HIP kernels of one multiphase lattice Boltzmann step on gfx950.
 //
 // One step t -> t+1 (paper Sec. II and Sec. III A), as separate launches:
-//   k_density   rho = sum_i S_i over fluid nodes; on measure steps also the
+//   density     rho = sum_i S_i over fluid nodes; on measure steps also the
 //               integer centroid sums of the liquid (rho >= rho_m)
-//   k_fill      Eq. 14 over the compact list of first-layer solid nodes, then
+//   fill        Eq. 14 over the compact list of first-layer solid nodes, then
 //               (second launch) over the second layer
-//   k_mu        mu = k^2 psi'(rho) - kappa lap4(rho) on fluid nodes (Eq. 11-12);
+//   mu          mu = k^2 psi'(rho) - kappa lap4(rho) on fluid nodes (Eq. 11-12);
 //               on measure steps the same pass finds the isodensity crossings
 //               of Eq. 15 near the substrate and keeps, per sector and band,
 //               the crossing nearest 1 or 2 lu from the wall (64-bit atomicMin)
-//   k_collide   F = -rho grad4(mu) + cs^2 grad4(rho) + rho g (Eq. 7), MRT or BGK
-//               relaxation (Eq. 1-3) with exact-difference forcing (Eq. 13), then
-//               push streaming (Eq. 4) with halfway bounce-back at solid links
-//   k_bc        (linear interpolated bounce-back only) replaces the halfway
-//               values at cut links and adds the mass correction to S_0
-//   k_finalize  one block: on measure steps turns the selected crossings into
-//               contact angles (secant, contact point, tangent; Fig. 1), then
-//               clears the reduction slots and advances t
+//   collide     F = -rho grad4(mu) + cs^2 grad4(rho) + rho g (Eq. 7), MRT or BGK
+//               relaxation (Eq. 1-3) with exact-difference forcing (Eq. 13);
+//               streaming (Eq. 4) is the gather at the start of the next step
+//   finalize    one block per lattice: on measure steps turns the selected
+//               crossings into contact angles (secant, contact point, tangent;
+//               Fig. 1), then clears the reduction slots and advances t
 // The wall chemical potential of the two solid layers is static and is written
 // into mu once, when the solids are set.
 //
+// Every per-node computation is a device function ("body") shared by two kinds
+// of launch: one lattice tiled by 64 x 4 node workgroups, or many packed
+// lattices walked by a persistent work list (the batched solver).  A lattice
+// lives at offset off of the packed arrays; N is the population stride.
+//
 // Data layout in HBM: populations structure-of-arrays [Q][N], x fastest, two
-// buffers (state S_t in one, S_{t+1} written to the other); rho[N], mu[N] in
-// the step precision; cls[N] uint8 (bits 0-1 class, bit 2 boundary fluid
-// node); nbmask[N] uint32 (bit i: neighbour x+e_i is solid), read only for
-// boundary nodes.
+// buffers; rho[N], mu[N] in the storage precision; cls[N] uint8 (bits 0-1
+// class, bit 2 boundary fluid node); nbmask[N] uint32 (bit j: x+e_j solid) and
+// bidx[N] (boundary-list index), read only for boundary nodes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,11 +40,16 @@ enum : uint8_t { CLS_FLUID = 0, CLS_L1 = 1, CLS_L2 = 2, CLS_DEEP = 3, CLS_MASK =
 
 struct Dims {
     int nx, ny, nz;
-    long long N;
+    long long N;         // population stride (all packed nodes)
+    long long off;       // first node of this lattice in the packed arrays
     int tx, ty;          // 64 x 4 node tiles per row / per plane
     unsigned nblocks;    // tx * ty * nz workgroups
     int xcd_remap;       // 1: contiguous tile ranges per XCD
 };
+
+__device__ __forceinline__ long long nid(const Dims& d, int x, int y, int z) {
+    return d.off + ((long long)z * d.ny + y) * d.nx + x;
+}
 
 // Node of this thread.  Workgroups are dispatched to the 8 XCDs round-robin
 // by workgroup id; with xcd_remap each XCD receives one contiguous range of
@@ -55,8 +62,8 @@ __device__ __forceinline__ void tile_node(const Dims& d, int& x, int& y, int& z)
         t = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
     }
     const unsigned txi = t % (unsigned)d.tx, rest = t / (unsigned)d.tx;
-    x = (int)txi * 64 + (int)threadIdx.x;
-    y = (int)(rest % (unsigned)d.ty) * 4 + (int)threadIdx.y;
+    x = (int)txi * 64 + (int)(threadIdx.x & 63);
+    y = (int)(rest % (unsigned)d.ty) * 4 + (int)(threadIdx.x >> 6);
     z = (int)(rest / (unsigned)d.ty);
 }
 
@@ -83,16 +90,21 @@ struct Collision {
     long long g_start;
 };
 
-// Reduction slots of the in-step measurement and the step counter.
+// Reduction slots of one lattice's in-step measurement.
+struct MeasureSlots {
+    unsigned long long cnt, sx, sy, sz;      // liquid centroid sums
+    unsigned long long keys[64][2];          // per sector, per band (1 lu, 2 lu)
+};
+
+// Step counter, measurement cadence and status word (one per context).
 struct DevCtl {
     long long t;                 // completed steps
-    int every;                   // measurement cadence of the running lbm_step call
+    int every;                   // measurement cadence of the running step call
     int force_measure;           // 1: measure whatever t is (standalone measurement)
     int status;                  // bit 0: non-finite / non-physical density seen
     int series_count, series_cap;
     int pad_;
-    unsigned long long cnt, sx, sy, sz;      // liquid centroid sums
-    unsigned long long keys[64][2];          // per sector, per band (1 lu, 2 lu)
+    MeasureSlots m;              // slots of a single-lattice context
 };
 
 struct MeasureParams {
@@ -172,7 +184,7 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
     const int ys[3] = {wrapc(y - 1, d.ny), y, wrapc(y + 1, d.ny)};
     const int zs[3] = {L::D == 3 ? wrapc(z - 1, d.nz) : 0, z, L::D == 3 ? wrapc(z + 1, d.nz) : 0};
     // source x - e_i
-#define LBM_SRC(i) (((long long)zs[1 - L::E[i][2]] * d.ny + ys[1 - L::E[i][1]]) * d.nx + xs[1 - L::E[i][0]])
+#define LBM_SRC(i) nid(d, xs[1 - L::E[i][0]], ys[1 - L::E[i][1]], zs[1 - L::E[i][2]])
     if (!(c & CLS_BOUNDARY)) {
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + (i ? LBM_SRC(i) : idx)];
@@ -198,7 +210,7 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
         C v = (C)outj;
         if (q < C(0.5)) {
             if (!(bm & (1u << i))) {  // x + e_i is the fluid node behind x
-                const long long b = ((long long)zs[1 + L::E[i][2]] * d.ny + ys[1 + L::E[i][1]]) * d.nx + xs[1 + L::E[i][0]];
+                const long long b = nid(d, xs[1 + L::E[i][0]], ys[1 + L::E[i][1]], zs[1 + L::E[i][2]]);
                 v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)f[(size_t)j * d.N + b];
             }
         } else {
@@ -214,28 +226,27 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
 // ---------------------------------------------------------------------------
 // density (+ liquid centroid on measure steps)
 // ---------------------------------------------------------------------------
+// rho of a fluid node from its gathered populations; true if liquid
 template <class L, typename R, typename C, bool PULL>
-__global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __restrict__ rho,
-                                                 const uint8_t* __restrict__ cls, Dims d, WallBC bc,
-                                                 DevCtl* __restrict__ ctl, double rho_m, R inv_b) {
-    int x, y, z;
-    tile_node(d, x, y, z);
-    const bool in = x < d.nx && y < d.ny;
-    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
-    bool liquid = false;
-    const uint8_t c = in ? cls[idx] : (uint8_t)CLS_DEEP;
-    if ((c & CLS_MASK) == CLS_FLUID) {
-        R S[L::Q];
-        gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
-        double s = 0.0;  // summed in double, as the collision's own moments are
+__device__ __forceinline__ bool density_node(const R* __restrict__ f, R* __restrict__ rho,
+                                             const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc, int x,
+                                             int y, int z, bool in, double rho_m, R inv_b, int* status) {
+    if (!in) return false;
+    const long long idx = nid(d, x, y, z);
+    const uint8_t c = cls[idx];
+    if ((c & CLS_MASK) != CLS_FLUID) return false;
+    R S[L::Q];
+    gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
+    double s = 0.0;  // summed in double, as the collision's own moments are
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) s += (double)S[i];
-        rho[idx] = (R)s;
-        if (!(s > 0.0 && s < (double)inv_b)) atomicOr(&ctl->status, 1);  // also catches NaN
-        liquid = (double)s >= rho_m;
-    }
-    if (!measuring(ctl)) return;
-    // block reduction of (count, x, y, z) over liquid nodes
+    for (int i = 0; i < L::Q; ++i) s += (double)S[i];
+    rho[idx] = (R)s;
+    if (!(s > 0.0 && s < (double)inv_b)) atomicOr(status, 1);  // also catches NaN
+    return s >= rho_m;
+}
+
+// block reduction (256 threads, 4 waves) of the liquid centroid sums
+__device__ __forceinline__ void centroid_reduce(bool liquid, int x, int y, int z, MeasureSlots* ms) {
     __shared__ unsigned long long red[4][4];
     unsigned long long v[4] = {liquid ? 1ull : 0ull, liquid ? (unsigned long long)x : 0ull,
                                liquid ? (unsigned long long)y : 0ull, liquid ? (unsigned long long)z : 0ull};
@@ -243,14 +254,26 @@ __global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __r
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] += __shfl_down(v[k], off, 64);
-    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0)
         for (int k = 0; k < 4; ++k) red[wave][k] = v[k];
     __syncthreads();
     if (wave == 0 && lane < 4) {
-        unsigned long long sum = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-        if (sum) atomicAdd((&ctl->cnt) + lane, sum);
+        const unsigned long long sum = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        if (sum) atomicAdd((&ms->cnt) + lane, sum);
     }
+    __syncthreads();
+}
+
+template <class L, typename R, typename C, bool PULL>
+__global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __restrict__ rho,
+                                                 const uint8_t* __restrict__ cls, Dims d, WallBC bc,
+                                                 DevCtl* __restrict__ ctl, double rho_m, R inv_b) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    const bool liquid = density_node<L, R, C, PULL>(f, rho, cls, d, bc, x, y, z, x < d.nx && y < d.ny, rho_m, inv_b,
+                                                    &ctl->status);
+    if (measuring(ctl)) centroid_reduce(liquid, x, y, z, &ctl->m);
 }
 
 // state S_t of every node (zero on solid nodes) into out
@@ -260,7 +283,7 @@ __global__ void __launch_bounds__(256) k_materialize(const R* __restrict__ f, R*
     int x, y, z;
     tile_node(d, x, y, z);
     if (x >= d.nx || y >= d.ny) return;
-    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    const long long idx = nid(d, x, y, z);
     const uint8_t c = cls[idx];
     R S[L::Q];
     if ((c & CLS_MASK) == CLS_FLUID) gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
@@ -273,24 +296,28 @@ __global__ void __launch_bounds__(256) k_materialize(const R* __restrict__ f, R*
 // ---------------------------------------------------------------------------
 // Eq. 14 over a compact list: rho(s) = sum_i w_i rho(s+e_i) s_w / sum_i w_i s_w
 // ---------------------------------------------------------------------------
-template <class L, typename R, typename C = R>
-__global__ void __launch_bounds__(256) k_fill(const long long* __restrict__ node, const uint32_t* __restrict__ mask,
-                                              const R* __restrict__ inv_den, int count, R* __restrict__ rho, Dims d) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= count) return;
-    const long long idx = node[k];
-    const uint32_t m = mask[k];
-    const int x = (int)(idx % d.nx), y = (int)((idx / d.nx) % d.ny), z = (int)(idx / ((long long)d.nx * d.ny));
+template <class L, typename R, typename C>
+__device__ __forceinline__ void fill_entry(long long idx, uint32_t m, R inv_den, R* __restrict__ rho, const Dims& d) {
+    const long long loc = idx - d.off;
+    const int x = (int)(loc % d.nx), y = (int)((loc / d.nx) % d.ny), z = (int)(loc / ((long long)d.nx * d.ny));
     C num = C(0);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         if (m & (1u << i)) {
             const int X = wrapc(x + L::E[i][0], d.nx), Y = wrapc(y + L::E[i][1], d.ny);
             const int Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) : 0;
-            num += C(L::w(i)) * (C)rho[((long long)Z * d.ny + Y) * d.nx + X];
+            num += C(L::w(i)) * (C)rho[nid(d, X, Y, Z)];
         }
     }
-    rho[idx] = (R)(num * (C)inv_den[k]);
+    rho[idx] = (R)(num * (C)inv_den);
+}
+
+template <class L, typename R, typename C = R>
+__global__ void __launch_bounds__(256) k_fill(const long long* __restrict__ node, const uint32_t* __restrict__ mask,
+                                              const R* __restrict__ inv_den, int count, R* __restrict__ rho, Dims d) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    fill_entry<L, R, C>(node[k], mask[k], inv_den[k], rho, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,15 +328,15 @@ struct Frame {
     bool ok;
 };
 
-__device__ inline Frame make_frame(const DevCtl* ctl, const MeasureParams& mp) {
+__device__ inline Frame make_frame(const MeasureSlots* ms, const MeasureParams& mp) {
     Frame F;
-    const unsigned long long n = ctl->cnt;
+    const unsigned long long n = ms->cnt;
     F.ok = n > 0;
     double G[3] = {0, 0, 0};
     if (n) {
-        G[0] = (double)ctl->sx / (double)n;
-        G[1] = (double)ctl->sy / (double)n;
-        G[2] = mp.dim == 3 ? (double)ctl->sz / (double)n : 0.0;
+        G[0] = (double)ms->sx / (double)n;
+        G[1] = (double)ms->sy / (double)n;
+        G[2] = mp.dim == 3 ? (double)ms->sz / (double)n : 0.0;
     }
     double a[3] = {G[0] - mp.c[0], G[1] - mp.c[1], mp.dim == 3 ? G[2] - mp.c[2] : 0.0};
     double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
@@ -360,51 +387,54 @@ __device__ inline void crossing_point(double rho_g_node, double rho_l_node, doub
 // ---------------------------------------------------------------------------
 // chemical potential (+ fused crossing search on measure steps)
 // ---------------------------------------------------------------------------
-template <class L, typename R, typename C = R>
-__global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __restrict__ mu,
-                                            const uint8_t* __restrict__ cls, Dims d, Thermo th,
-                                            DevCtl* __restrict__ ctl, MeasureParams mp) {
-    int x, y, z;
-    tile_node(d, x, y, z);
-    const bool in = x < d.nx && y < d.ny;
-    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
-    const bool fluid = in && (cls[idx] & CLS_MASK) == CLS_FLUID;
-    R r0 = R(0);
-    if (fluid) {
-        r0 = rho[idx];
-        const long long sx = 1, sy = d.nx, sz = (long long)d.nx * d.ny;
-        const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
-        const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
-        const long long row = ((long long)z * d.ny + y) * d.nx;
-        const long long pl = (long long)z * sz;
-        const C c0 = (C)r0;
-        C lap = d2c<C>(rho[row + xm2], rho[row + xm1], c0, rho[row + xp1], rho[row + xp2]);
-        lap += d2c<C>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], c0, rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
-        if (L::D == 3) {
-            const int zm1 = wrapc(z - 1, d.nz), zm2 = wrapc(z - 2, d.nz), zp1 = wrapc(z + 1, d.nz), zp2 = wrapc(z + 2, d.nz);
-            const long long col = (long long)y * sy + x;
-            lap += d2c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], c0, rho[zp1 * sz + col], rho[zp2 * sz + col]);
-        }
-        (void)sx;
-        mu[idx] = (R)((psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap);
+template <class L, typename R, typename C>
+__device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict__ mu, const uint8_t* __restrict__ cls,
+                                        const Dims& d, const Thermo& th, int x, int y, int z, bool in, R& r0) {
+    r0 = R(0);
+    if (!in) return false;
+    const long long idx = nid(d, x, y, z);
+    if ((cls[idx] & CLS_MASK) != CLS_FLUID) return false;
+    r0 = rho[idx];
+    const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
+    const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
+    const long long sy = d.nx, sz = (long long)d.nx * d.ny;
+    const long long row = d.off + ((long long)z * d.ny + y) * d.nx;
+    const long long pl = d.off + (long long)z * sz;
+    const C c0 = (C)r0;
+    C lap = d2c<C>(rho[row + xm2], rho[row + xm1], c0, rho[row + xp1], rho[row + xp2]);
+    lap += d2c<C>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], c0, rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
+    if (L::D == 3) {
+        const int zm1 = wrapc(z - 1, d.nz), zm2 = wrapc(z - 2, d.nz), zp1 = wrapc(z + 1, d.nz), zp2 = wrapc(z + 2, d.nz);
+        const long long col = d.off + (long long)y * sy + x;
+        lap += d2c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], c0, rho[zp1 * sz + col], rho[zp2 * sz + col]);
     }
-    if (!measuring(ctl)) return;
-    // gas-side nodes near the substrate test their links for a crossing
+    mu[idx] = (R)((psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap);
+    return true;
+}
+
+// gas-side fluid nodes near the substrate test their links for an isodensity
+// crossing (Eq. 15) and offer it to the per-(sector, band) minimum.  Called by
+// every lane of the wave (the ballot skips waves away from the contact region).
+template <class L, typename R>
+__device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const uint8_t* __restrict__ cls,
+                                               const Dims& d, int x, int y, int z, bool fluid, R r0,
+                                               const MeasureParams& mp, MeasureSlots* ms) {
     bool cand = false;
-    double rx = x - mp.c[0], ry = y - mp.c[1], rz = (L::D == 3) ? z - mp.c[2] : 0.0;
+    const double rx = x - mp.c[0], ry = y - mp.c[1], rz = (L::D == 3) ? z - mp.c[2] : 0.0;
     if (fluid && (double)r0 < mp.rho_m) {
         const double dn = sqrt(rx * rx + ry * ry + rz * rz) - mp.R;
         cand = dn < 4.0;  // crossings lie within sqrt(2) of the node; bands end at 2.5
     }
-    if (__ballot(cand) == 0) return;  // whole wave away from the contact region
+    if (__ballot(cand) == 0) return;
     if (!cand) return;
-    const Frame F = make_frame(ctl, mp);
+    const Frame F = make_frame(ms, mp);
     if (!F.ok) return;
+    const long long idx = nid(d, x, y, z), loc = idx - d.off;
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int X = wrapc(x + L::E[i][0], d.nx), Y = wrapc(y + L::E[i][1], d.ny);
         const int Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) : 0;
-        const long long j = ((long long)Z * d.ny + Y) * d.nx + X;
+        const long long j = nid(d, X, Y, Z);
         if ((cls[j] & CLS_MASK) != CLS_FLUID) continue;
         const double rl = (double)rho[j];
         if (!(rl >= mp.rho_m)) continue;
@@ -416,24 +446,34 @@ __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __rest
         const int band = dist < 1.5 ? 1 : 2;
         const int s = sector_of(r, F, mp.dim, mp.n_sectors);
         const float kv = (float)fabs(dist - (double)band);
+        // link id within the lattice: ties go to the lower node, then the lower direction
         const unsigned long long key =
-            ((unsigned long long)__float_as_uint(kv) << 32) | (unsigned long long)(idx * L::Q + i);
-        atomicMin(&ctl->keys[s][band - 1], key);
+            ((unsigned long long)__float_as_uint(kv) << 32) | (unsigned long long)(loc * L::Q + i);
+        atomicMin(&ms->keys[s][band - 1], key);
     }
+}
+
+template <class L, typename R, typename C>
+__global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __restrict__ mu,
+                                            const uint8_t* __restrict__ cls, Dims d, Thermo th,
+                                            DevCtl* __restrict__ ctl, MeasureParams mp) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    R r0;
+    const bool fluid = mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
+    if (measuring(ctl)) crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp, &ctl->m);
 }
 
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
 template <class L, typename R, typename C, bool PULL, bool MRT>
-__global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* __restrict__ fout,
-                                                 const R* __restrict__ rho, const R* __restrict__ mu,
-                                                 const uint8_t* __restrict__ cls, Dims d, WallBC bc,
-                                                 Collision<C> cp, const DevCtl* __restrict__ ctl) {
-    int x, y, z;
-    tile_node(d, x, y, z);
+__device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __restrict__ fout,
+                                             const R* __restrict__ rho, const R* __restrict__ mu,
+                                             const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
+                                             const Collision<C>& cp, long long t, int x, int y, int z) {
     if (x >= d.nx || y >= d.ny) return;
-    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    const long long idx = nid(d, x, y, z);
     const uint8_t c = cls[idx];
     if ((c & CLS_MASK) != CLS_FLUID) return;
 
@@ -443,9 +483,9 @@ __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* _
     const long long sy = d.nx, sz = (long long)d.nx * d.ny;
     const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
     const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
-    const long long row = (long long)z * sz + (long long)y * sy;
-    const long long pl = (long long)z * sz;
-    const long long col = (long long)y * sy + x;
+    const long long row = d.off + (long long)z * sz + (long long)y * sy;
+    const long long pl = d.off + (long long)z * sz;
+    const long long col = d.off + (long long)y * sy + x;
 
     // Eq. 7 with fourth-order central differences.  The two terms of F cancel
     // almost exactly inside an interface at rest, so F, and the moments it
@@ -464,7 +504,7 @@ __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* _
     }
     const D third = D(1.0 / 3.0);
     D Fx = -r0 * gmx + grx * third, Fy = -r0 * gmy + gry * third, Fz = -r0 * gmz + grz * third;
-    if (ctl->t >= cp.g_start) {
+    if (t >= cp.g_start) {
         Fx += r0 * (D)cp.g[0];
         Fy += r0 * (D)cp.g[1];
         Fz += r0 * (D)cp.g[2];
@@ -535,121 +575,138 @@ __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* _
     }
 }
 
+template <class L, typename R, typename C, bool PULL, bool MRT>
+__global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* __restrict__ fout,
+                                                 const R* __restrict__ rho, const R* __restrict__ mu,
+                                                 const uint8_t* __restrict__ cls, Dims d, WallBC bc,
+                                                 Collision<C> cp, const DevCtl* __restrict__ ctl) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    collide_node<L, R, C, PULL, MRT>(fin, fout, rho, mu, cls, d, bc, cp, ctl->t, x, y, z);
+}
+
 // ---------------------------------------------------------------------------
 // finalize: contact angles from the selected crossings; clear; advance t
 // ---------------------------------------------------------------------------
+// One lattice's contact angles from its selected crossings (64 threads, one
+// per sector).  Writes the record to *last (and *rec2 if not null) and clears
+// the slots for the next measurement.
+template <class L, typename R>
+__device__ void finalize_slots(const R* __restrict__ rho, const Dims& d, const MeasureParams& mp,
+                               MeasureSlots* __restrict__ ms, long long t, AngleRec* __restrict__ last,
+                               AngleRec* __restrict__ rec2) {
+    const int s = threadIdx.x;
+    __shared__ double th[64];
+    __shared__ double cpt[64][3];
+    const Frame F = make_frame(ms, mp);
+    double theta = NAN, cp3[3] = {NAN, NAN, NAN};
+    if (F.ok && s < mp.n_sectors) {
+        const unsigned long long k1 = ms->keys[s][0], k2 = ms->keys[s][1];
+        if (k1 != ~0ull && k2 != ~0ull) {
+            double P[2][3];
+            const unsigned long long ks[2] = {k1, k2};
+            for (int b = 0; b < 2; ++b) {
+                const unsigned long long id = ks[b] & 0xffffffffull;
+                const long long loc = (long long)(id / L::Q);
+                const int i = (int)(id % L::Q);
+                int ex = 0, ey = 0, ez = 0;
+#pragma unroll
+                for (int q = 0; q < L::Q; ++q)
+                    if (q == i) { ex = L::E[q][0]; ey = L::E[q][1]; ez = L::E[q][2]; }
+                const int x = (int)(loc % d.nx), y = (int)((loc / d.nx) % d.ny);
+                const int z = (int)(loc / ((long long)d.nx * d.ny));
+                const int X = wrapc(x + ex, d.nx), Y = wrapc(y + ey, d.ny);
+                const int Z = L::D == 3 ? wrapc(z + ez, d.nz) : 0;
+                crossing_point((double)rho[d.off + loc], (double)rho[nid(d, X, Y, Z)], mp.rho_m, x, y, z, ex, ey, ez,
+                               P[b]);
+            }
+            // meridional coordinates (w: distance from the drop axis, s: along it)
+            double r1[3], r2[3];
+            for (int k = 0; k < 3; ++k) { r1[k] = P[0][k] - mp.c[k]; r2[k] = P[1][k] - mp.c[k]; }
+            const double s1 = r1[0] * F.a[0] + r1[1] * F.a[1] + r1[2] * F.a[2];
+            const double s2 = r2[0] * F.a[0] + r2[1] * F.a[1] + r2[2] * F.a[2];
+            double q1[3], q2[3];
+            for (int k = 0; k < 3; ++k) { q1[k] = r1[k] - s1 * F.a[k]; q2[k] = r2[k] - s2 * F.a[k]; }
+            const double w1 = sqrt(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]);
+            const double w2 = sqrt(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2]);
+            const double dw = w2 - w1, ds = s2 - s1;
+            const double A = dw * dw + ds * ds;
+            if (A > 0.0) {
+                // secant P1 + lam (P2 - P1) meets the substrate circle |.| = R
+                const double B = w1 * dw + s1 * ds;
+                const double C = w1 * w1 + s1 * s1 - mp.R * mp.R;
+                const double disc = B * B - A * C;
+                double lam;
+                if (disc >= 0.0) {
+                    const double sq = sqrt(disc);
+                    const double lp = (-B + sq) / A, lm = (-B - sq) / A;
+                    lam = lp <= 0.0 ? lp : lm;  // nearest hit behind P1, else the first one ahead
+                } else {
+                    lam = -B / A;  // no intersection: closest approach
+                }
+                const double w0 = w1 + lam * dw, s0 = s1 + lam * ds;
+                const double r0 = sqrt(w0 * w0 + s0 * s0);
+                const double nw = w0 / r0, ns = s0 / r0;      // outward normal
+                const double tw = -ns, ts = nw;               // tangent toward the drop axis
+                const double vl = sqrt(A);
+                const double vw = dw / vl, vs = ds / vl;
+                const double ang = atan2(vw * nw + vs * ns, vw * tw + vs * ts) * (180.0 / M_PI);
+                for (int k = 0; k < 3; ++k) cp3[k] = mp.c[k] + s0 * F.a[k] + (w1 > 0.0 ? w0 * q1[k] / w1 : 0.0);
+                if (ang >= 0.0) theta = ang;
+            }
+        }
+    }
+    th[s] = theta;
+    cpt[s][0] = cp3[0]; cpt[s][1] = cp3[1]; cpt[s][2] = cp3[2];
+    __syncthreads();
+    if (s == 0) {
+        AngleRec* rec = last;
+        rec->step = t;
+        rec->n_sectors = mp.n_sectors;
+        rec->pad_ = 0;
+        double sum = 0.0;
+        int nv = 0;
+        for (int k = 0; k < 64; ++k) {
+            const bool use = k < mp.n_sectors;
+            rec->sector_deg[k] = use ? th[k] : NAN;
+            rec->contact[k][0] = use ? cpt[k][0] : NAN;
+            rec->contact[k][1] = use ? cpt[k][1] : NAN;
+            rec->contact[k][2] = use ? cpt[k][2] : NAN;
+            if (use && !isnan(th[k])) { sum += th[k]; ++nv; }
+        }
+        for (int k = 0; k < 3; ++k) rec->axis[k] = F.a[k];
+        rec->n_valid = nv;
+        rec->status = nv ? 0 : -6;
+        rec->mean_deg = nv ? sum / nv : NAN;
+        rec->adv_deg = rec->rec_deg = NAN;
+        const double ga = mp.g[0] * F.a[0] + mp.g[1] * F.a[1] + mp.g[2] * F.a[2];
+        const double gt[3] = {mp.g[0] - ga * F.a[0], mp.g[1] - ga * F.a[1], mp.g[2] - ga * F.a[2]};
+        if (nv && gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2] > 0.0) {
+            const int sa = sector_of(gt, F, mp.dim, mp.n_sectors);
+            const int sr = mp.dim == 2 ? 1 - sa : (sa + mp.n_sectors / 2) % mp.n_sectors;
+            rec->adv_deg = th[sa];
+            rec->rec_deg = th[sr];
+        }
+        if (rec2) *rec2 = *rec;
+    }
+    __syncthreads();
+    // clear the reduction slots for the next measurement
+    ms->keys[s][0] = ~0ull;
+    ms->keys[s][1] = ~0ull;
+    if (s == 0) ms->cnt = ms->sx = ms->sy = ms->sz = 0ull;
+}
+
 template <class L, typename R>
 __global__ void __launch_bounds__(64) k_finalize(const R* __restrict__ rho, DevCtl* __restrict__ ctl, Dims d,
                                                  MeasureParams mp, AngleRec* __restrict__ series,
                                                  AngleRec* __restrict__ last, int tick) {
-    const int s = threadIdx.x;
-    const bool meas = measuring(ctl);
-    __shared__ double th[64];
-    __shared__ double cpt[64][3];
-    if (meas) {
-        const Frame F = make_frame(ctl, mp);
-        double theta = NAN, cp3[3] = {NAN, NAN, NAN};
-        if (F.ok && s < mp.n_sectors) {
-            const unsigned long long k1 = ctl->keys[s][0], k2 = ctl->keys[s][1];
-            if (k1 != ~0ull && k2 != ~0ull) {
-                double P[2][3];
-                const unsigned long long ks[2] = {k1, k2};
-                for (int b = 0; b < 2; ++b) {
-                    const unsigned long long id = ks[b] & 0xffffffffull;
-                    const long long node = (long long)(id / L::Q);
-                    const int i = (int)(id % L::Q);
-                    int ex = 0, ey = 0, ez = 0;
-#pragma unroll
-                    for (int q = 0; q < L::Q; ++q)
-                        if (q == i) { ex = L::E[q][0]; ey = L::E[q][1]; ez = L::E[q][2]; }
-                    const int x = (int)(node % d.nx), y = (int)((node / d.nx) % d.ny);
-                    const int z = (int)(node / ((long long)d.nx * d.ny));
-                    const int X = wrapc(x + ex, d.nx), Y = wrapc(y + ey, d.ny);
-                    const int Z = L::D == 3 ? wrapc(z + ez, d.nz) : 0;
-                    const long long j = ((long long)Z * d.ny + Y) * d.nx + X;
-                    crossing_point((double)rho[node], (double)rho[j], mp.rho_m, x, y, z, ex, ey, ez, P[b]);
-                }
-                // meridional coordinates (w: distance from the drop axis, s: along it)
-                double r1[3], r2[3];
-                for (int k = 0; k < 3; ++k) { r1[k] = P[0][k] - mp.c[k]; r2[k] = P[1][k] - mp.c[k]; }
-                const double s1 = r1[0] * F.a[0] + r1[1] * F.a[1] + r1[2] * F.a[2];
-                const double s2 = r2[0] * F.a[0] + r2[1] * F.a[1] + r2[2] * F.a[2];
-                double q1[3], q2[3];
-                for (int k = 0; k < 3; ++k) { q1[k] = r1[k] - s1 * F.a[k]; q2[k] = r2[k] - s2 * F.a[k]; }
-                const double w1 = sqrt(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]);
-                const double w2 = sqrt(q2[0] * q2[0] + q2[1] * q2[1] + q2[2] * q2[2]);
-                const double dw = w2 - w1, ds = s2 - s1;
-                const double A = dw * dw + ds * ds;
-                if (A > 0.0) {
-                    // secant P1 + lam (P2 - P1) meets the substrate circle |.| = R
-                    const double B = w1 * dw + s1 * ds;
-                    const double C = w1 * w1 + s1 * s1 - mp.R * mp.R;
-                    const double disc = B * B - A * C;
-                    double lam;
-                    if (disc >= 0.0) {
-                        const double sq = sqrt(disc);
-                        const double lp = (-B + sq) / A, lm = (-B - sq) / A;
-                        lam = lp <= 0.0 ? lp : lm;  // nearest hit behind P1, else the first one ahead
-                    } else {
-                        lam = -B / A;  // no intersection: closest approach
-                    }
-                    const double w0 = w1 + lam * dw, s0 = s1 + lam * ds;
-                    const double r0 = sqrt(w0 * w0 + s0 * s0);
-                    const double nw = w0 / r0, ns = s0 / r0;      // outward normal
-                    const double tw = -ns, ts = nw;               // tangent toward the drop axis
-                    const double vl = sqrt(A);
-                    const double vw = dw / vl, vs = ds / vl;
-                    const double ang = atan2(vw * nw + vs * ns, vw * tw + vs * ts) * (180.0 / M_PI);
-                    for (int k = 0; k < 3; ++k) cp3[k] = mp.c[k] + s0 * F.a[k] + (w1 > 0.0 ? w0 * q1[k] / w1 : 0.0);
-                    if (ang >= 0.0) theta = ang;
-                }
-            }
-        }
-        th[s] = theta;
-        cpt[s][0] = cp3[0]; cpt[s][1] = cp3[1]; cpt[s][2] = cp3[2];
+    if (measuring(ctl)) {
+        const bool keep = series && ctl->series_count < ctl->series_cap;
+        finalize_slots<L, R>(rho, d, mp, &ctl->m, ctl->t, last, keep ? series + ctl->series_count : nullptr);
         __syncthreads();
-        if (s == 0) {
-            AngleRec rec;
-            rec.step = ctl->t;
-            rec.n_sectors = mp.n_sectors;
-            rec.pad_ = 0;
-            double sum = 0.0;
-            int nv = 0;
-            for (int k = 0; k < 64; ++k) {
-                rec.sector_deg[k] = NAN;
-                rec.contact[k][0] = rec.contact[k][1] = rec.contact[k][2] = NAN;
-            }
-            for (int k = 0; k < mp.n_sectors; ++k) {
-                rec.sector_deg[k] = th[k];
-                rec.contact[k][0] = cpt[k][0]; rec.contact[k][1] = cpt[k][1]; rec.contact[k][2] = cpt[k][2];
-                if (!isnan(th[k])) { sum += th[k]; ++nv; }
-            }
-            for (int k = 0; k < 3; ++k) rec.axis[k] = F.a[k];
-            rec.n_valid = nv;
-            rec.status = nv ? 0 : -6;
-            rec.mean_deg = nv ? sum / nv : NAN;
-            rec.adv_deg = rec.rec_deg = NAN;
-            const double ga = mp.g[0] * F.a[0] + mp.g[1] * F.a[1] + mp.g[2] * F.a[2];
-            const double gt[3] = {mp.g[0] - ga * F.a[0], mp.g[1] - ga * F.a[1], mp.g[2] - ga * F.a[2]};
-            if (nv && gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2] > 0.0) {
-                const int sa = sector_of(gt, F, mp.dim, mp.n_sectors);
-                const int sr = mp.dim == 2 ? 1 - sa : (sa + mp.n_sectors / 2) % mp.n_sectors;
-                rec.adv_deg = th[sa];
-                rec.rec_deg = th[sr];
-            }
-            *last = rec;
-            if (series && ctl->series_count < ctl->series_cap) series[ctl->series_count] = rec;
-        }
-        __syncthreads();
-        // clear the reduction slots for the next measurement
-        ctl->keys[s][0] = ~0ull;
-        ctl->keys[s][1] = ~0ull;
-        if (s == 0) {
-            ctl->cnt = ctl->sx = ctl->sy = ctl->sz = 0ull;
-            if (series && ctl->series_count < ctl->series_cap) ctl->series_count += 1;
-        }
+        if (threadIdx.x == 0 && keep) ctl->series_count += 1;
     }
-    if (s == 0 && tick) ctl->t += 1;
+    if (threadIdx.x == 0 && tick) ctl->t += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -660,12 +717,12 @@ __global__ void k_fill_value(R* __restrict__ p, size_t n, R v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ void k_ctl_reset(DevCtl* ctl, int every, int force, int series_cap) {
+static __global__ void k_ctl_reset(DevCtl* ctl, int every, int force, int series_cap) {
     const int s = threadIdx.x;
-    ctl->keys[s][0] = ~0ull;
-    ctl->keys[s][1] = ~0ull;
+    ctl->m.keys[s][0] = ~0ull;
+    ctl->m.keys[s][1] = ~0ull;
     if (s == 0) {
-        ctl->cnt = ctl->sx = ctl->sy = ctl->sz = 0ull;
+        ctl->m.cnt = ctl->m.sx = ctl->m.sy = ctl->m.sz = 0ull;
         ctl->every = every;
         ctl->force_measure = force;
         ctl->series_count = 0;
@@ -673,7 +730,7 @@ __global__ void k_ctl_reset(DevCtl* ctl, int every, int force, int series_cap) {
     }
 }
 
-__global__ void k_ctl_set(DevCtl* ctl, long long t, int every, int force, int series_cap, int clear_status) {
+static __global__ void k_ctl_set(DevCtl* ctl, long long t, int every, int force, int series_cap, int clear_status) {
     if (threadIdx.x == 0) {
         ctl->t = t;
         ctl->every = every;
@@ -684,10 +741,12 @@ __global__ void k_ctl_set(DevCtl* ctl, long long t, int every, int force, int se
     }
 }
 
-// state = f_eq(rho, 0) on fluid nodes, zero elsewhere
+// state = f_eq(rho, 0) on fluid nodes of [beg, end), zero on its other nodes
 template <class L, typename R>
-__global__ void k_init_feq(const R* __restrict__ rho, R* __restrict__ f, const uint8_t* __restrict__ cls, long long N) {
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+__global__ void k_init_feq(const R* __restrict__ rho, R* __restrict__ f, const uint8_t* __restrict__ cls, long long N,
+                           long long beg, long long end) {
+    for (long long n = beg + (long long)blockIdx.x * blockDim.x + threadIdx.x; n < end;
+         n += (long long)gridDim.x * blockDim.x) {
         const bool fl = (cls[n] & CLS_MASK) == CLS_FLUID;
         const R r = fl ? rho[n] : R(0);
 #pragma unroll
@@ -695,7 +754,8 @@ __global__ void k_init_feq(const R* __restrict__ rho, R* __restrict__ f, const u
     }
 }
 
-// v = u + F / (2 rho) (Sec. II B), with F of Eq. 7 from the current rho and mu
+// v = u + F / (2 rho) (Sec. II B), with F of Eq. 7 from the current rho and mu;
+// fin holds S_t
 template <class L, typename R, typename C = R>
 __global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, const R* __restrict__ rho,
                                                   const R* __restrict__ mu, const uint8_t* __restrict__ cls, Dims d,
@@ -703,35 +763,36 @@ __global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, con
     int x, y, z;
     tile_node(d, x, y, z);
     if (x >= d.nx || y >= d.ny) return;
-    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    const long long idx = nid(d, x, y, z);
     if ((cls[idx] & CLS_MASK) != CLS_FLUID) {
         vel[idx] = vel[d.N + idx] = vel[2 * d.N + idx] = R(0);
         return;
     }
-    const C r0 = (C)rho[idx];
-    C Fa[3] = {C(0), C(0), C(0)};
+    typedef double D;
+    const D r0 = (D)rho[idx];
+    D Fa[3] = {D(0), D(0), D(0)};
     for (int a = 0; a < L::D; ++a) {
         int o[3] = {0, 0, 0};
         long long id[5];
         for (int k = -2; k <= 2; ++k) {
             o[a] = k;
             const int X = wrapc(x + o[0], d.nx), Y = wrapc(y + o[1], d.ny), Z = L::D == 3 ? wrapc(z + o[2], d.nz) : 0;
-            id[k + 2] = ((long long)Z * d.ny + Y) * d.nx + X;
+            id[k + 2] = nid(d, X, Y, Z);
         }
-        const C gm = d1c<C>(mu[id[0]], mu[id[1]], mu[id[3]], mu[id[4]]);
-        const C gr = d1c<C>(rho[id[0]], rho[id[1]], rho[id[3]], rho[id[4]]);
-        Fa[a] = -r0 * gm + gr * C(1.0 / 3.0);
-        if (t >= cp.g_start) Fa[a] += r0 * cp.g[a];
+        const D gm = d1c<D>(mu[id[0]], mu[id[1]], mu[id[3]], mu[id[4]]);
+        const D gr = d1c<D>(rho[id[0]], rho[id[1]], rho[id[3]], rho[id[4]]);
+        Fa[a] = -r0 * gm + gr * D(1.0 / 3.0);
+        if (t >= cp.g_start) Fa[a] += r0 * (D)cp.g[a];
     }
-    C rs = C(0), j[3] = {C(0), C(0), C(0)};
+    D rs = D(0), j[3] = {D(0), D(0), D(0)};
     for (int i = 0; i < L::Q; ++i) {
-        const C fi = (C)fin[(size_t)i * d.N + idx];
+        const D fi = (D)fin[(size_t)i * d.N + idx];
         rs += fi;
-        j[0] += C(L::E[i][0]) * fi;
-        j[1] += C(L::E[i][1]) * fi;
-        j[2] += C(L::E[i][2]) * fi;
+        j[0] += D(L::E[i][0]) * fi;
+        j[1] += D(L::E[i][1]) * fi;
+        j[2] += D(L::E[i][2]) * fi;
     }
-    for (int a = 0; a < 3; ++a) vel[(size_t)a * d.N + idx] = (R)(j[a] / rs + Fa[a] / (C(2) * rs));
+    for (int a = 0; a < 3; ++a) vel[(size_t)a * d.N + idx] = (R)(j[a] / rs + Fa[a] / (D(2) * rs));
 }
 
 // deterministic mass: per-block FP64 partial sums in a fixed order
@@ -755,7 +816,7 @@ __global__ void __launch_bounds__(256) k_mass_partial(const R* __restrict__ f, c
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_mass_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+static __global__ void k_mass_final(const double* __restrict__ part, int n, double* __restrict__ out) {
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int i = 0; i < n; ++i) s += part[i];

@@ -84,12 +84,28 @@ class lbm_info(C.Structure):
     ]
 
 
+class lbm_case(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("solid", lbm_solid), ("drop", lbm_drop)]
+
+
+class lbm_batch_opts(C.Structure):
+    _fields_ = [("autotune", C.c_int), ("tile_w", C.c_int), ("blocks_per_cu", C.c_int), ("cache_path", C.c_char_p)]
+
+
+class lbm_batch_info(C.Structure):
+    _fields_ = [("total_nodes", C.c_int64), ("fluid_nodes", C.c_int64), ("ncases", C.c_int32), ("tile_w", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("n_items", C.c_int32), ("tune_ms_per_step", C.c_double),
+                ("step", C.c_int64), ("rho_g", C.c_double), ("rho_l", C.c_double)]
+
+
 _lib = None
 
 # exported symbols of include/lbm.h (the binding and the tests check them)
 EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops",
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
-           "lbm_get_info", "lbm_profile_step", "lbm_last_error")
+           "lbm_get_info", "lbm_profile_step", "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy",
+           "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read",
+           "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_last_error")
 
 
 def lib():
@@ -117,9 +133,23 @@ def lib():
     L.lbm_profile_step.argtypes = [vp, i64, P(C.c_char_p), P(d), i, P(i)]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_last_error.argtypes = [vp]
+    L.lbm_batch_create.argtypes = [P(lbm_config), P(lbm_case), i, P(lbm_batch_opts), P(vp)]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_step.argtypes = [vp, i64, i]
+    L.lbm_batch_sync.argtypes = [vp]
+    L.lbm_batch_angles.argtypes = [vp, P(lbm_angle), i]
+    L.lbm_batch_measure.argtypes = [vp, P(lbm_angle), i]
+    L.lbm_batch_read.argtypes = [vp, i, i, vp, C.c_size_t, i]
+    L.lbm_batch_write.argtypes = [vp, i, i, vp, C.c_size_t, i]
+    L.lbm_batch_get_info.argtypes = [vp, P(lbm_batch_info)]
+    L.lbm_batch_tune.argtypes = [vp, C.c_char_p]
+    L.lbm_batch_last_error.restype = C.c_char_p
+    L.lbm_batch_last_error.argtypes = [vp]
     for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
                  "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
-                 "lbm_get_info", "lbm_profile_step"):
+                 "lbm_get_info", "lbm_profile_step", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_step",
+                 "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read", "lbm_batch_write",
+                 "lbm_batch_get_info", "lbm_batch_tune"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -281,6 +311,120 @@ class Lattice:
         n = C.c_int()
         self._check(lib().lbm_profile_step(self._h, int(nsteps), names, ms, 8, C.byref(n)))
         return {names[i].decode(): ms[i] for i in range(n.value)}
+
+
+def _fill_solid(dst, s):
+    dst.kind = LBM_SOLID_SPHERE
+    c = list(s["center"]) + [0.0] * (3 - len(s["center"]))
+    for k in range(3):
+        dst.center[k] = c[k]
+    dst.radius = s["radius"]
+    if "stripes" in s:
+        dst.wet_mode = LBM_WET_STRIPES
+        dst.mu_w, dst.mu_w2, dst.stripe_width = s["stripes"]
+    else:
+        dst.wet_mode = LBM_WET_UNIFORM
+        dst.mu_w = s.get("mu_w", 0.0)
+
+
+class Batch:
+    """Many independent lattices (one solid and one drop each) advanced together."""
+
+    def __init__(self, cases, lattice=LBM_D2Q9, precision=LBM_F32, axis_bc=(0, 0, 0), autotune=False, tile_w=64,
+                 blocks_per_cu=4, cache_path=None, stream=None, **params):
+        cfg = config_default(lattice)
+        cfg.precision = precision
+        for k in range(3):
+            cfg.axis_bc[k] = axis_bc[k] if k < len(axis_bc) else 0
+        for key, val in params.items():
+            if key == "g":
+                for k in range(3):
+                    cfg.g[k] = val[k] if k < len(val) else 0.0
+            else:
+                if not hasattr(cfg, key):
+                    raise KeyError(key)
+                setattr(cfg, key, val)
+        if stream is not None:
+            cfg.stream = stream
+        self.cfg = cfg
+        self.dim = 2 if lattice == LBM_D2Q9 else 3
+        self.Q = 9 if self.dim == 2 else 19
+        self.dtype = np.float64 if precision == LBM_F64 else np.float32
+        arr = (lbm_case * len(cases))()
+        self.shapes = []
+        for i, cs in enumerate(cases):
+            n = list(cs["n"]) + [1] * (3 - len(cs["n"]))
+            for k in range(3):
+                arr[i].n[k] = n[k]
+            _fill_solid(arr[i].solid, cs["solid"])
+            c, r = cs["drop"]
+            cc = list(c) + [0.0] * (3 - len(c))
+            for k in range(3):
+                arr[i].drop.center[k] = cc[k]
+            arr[i].drop.radius = r
+            self.shapes.append((n[2], n[1], n[0]))
+        self._cache = cache_path.encode() if cache_path else None
+        opts = lbm_batch_opts(int(autotune), tile_w, blocks_per_cu, self._cache)
+        h = C.c_void_p()
+        st = lib().lbm_batch_create(C.byref(cfg), arr, len(cases), C.byref(opts), C.byref(h))
+        if st != 0:
+            raise LbmError(st, "lbm_batch_create failed")
+        self._h = h
+        self.ncases = len(cases)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise LbmError(st, lib().lbm_batch_last_error(self._h).decode())
+
+    def step(self, n, measure_every=0):
+        self._check(lib().lbm_batch_step(self._h, int(n), int(measure_every)))
+
+    def sync(self):
+        self._check(lib().lbm_batch_sync(self._h))
+
+    def angles(self):
+        arr = (lbm_angle * self.ncases)()
+        self._check(lib().lbm_batch_angles(self._h, arr, self.ncases))
+        return list(arr)
+
+    def measure(self):
+        arr = (lbm_angle * self.ncases)()
+        self._check(lib().lbm_batch_measure(self._h, arr, self.ncases))
+        return list(arr)
+
+    def read(self, case, field):
+        shp = self.shapes[case]
+        if field == FIELD_CLASS:
+            out = np.empty(shp, dtype=np.uint8)
+        elif field == FIELD_F:
+            out = np.empty((self.Q,) + shp, dtype=self.dtype)
+        else:
+            out = np.empty(shp, dtype=self.dtype)
+        self._check(lib().lbm_batch_read(self._h, case, field, out.ctypes.data, out.nbytes, 0))
+        return out
+
+    def write_rho(self, case, rho):
+        a = np.ascontiguousarray(rho, dtype=self.dtype)
+        self._check(lib().lbm_batch_write(self._h, case, FIELD_RHO, a.ctypes.data, a.nbytes, 0))
+
+    def write_rho_device(self, case, ptr, nbytes):
+        self._check(lib().lbm_batch_write(self._h, case, FIELD_RHO, C.c_void_p(ptr), nbytes, 1))
+
+    def info(self):
+        inf = lbm_batch_info()
+        self._check(lib().lbm_batch_get_info(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in lbm_batch_info._fields_}
+
+    def tune(self, cache_path=None):
+        self._check(lib().lbm_batch_tune(self._h, cache_path.encode() if cache_path else None))
 
 
 def angle_dict(a):

@@ -1,0 +1,85 @@
+"""Batched solver: every case equals the same case run alone, bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2202_06516_amd import lbm as G
+from paper_2202_06516_amd import workloads as W
+
+from .pairs import BASE, gpu_lattice, oracle_lattice, rel_err
+
+pytestmark = pytest.mark.gpu
+
+PHYS = dict(BASE, Tr=0.8)
+
+
+def small_cases(n=5, seed=7):
+    cases, _ = W.batch_cases(n, seed=seed, nmin=64, nmax=112, rs=(8.0, 14.0), r0=(7.0, 11.0), mu=(-0.01, 0.1))
+    return cases
+
+
+def single(case, precision, **kw):
+    wl = dict(dim=2, n=case["n"], wall=(0, 0), solids=[case["solid"]], drops=[case["drop"]])
+    return gpu_lattice(wl, precision, **kw)
+
+
+@pytest.mark.parametrize("precision", [G.LBM_F64, G.LBM_F32])
+def test_batch_equals_single(precision):
+    cases = small_cases()
+    b = G.Batch(cases, precision=precision, tile_w=128, blocks_per_cu=2, **PHYS)
+    b.step(45, measure_every=15)
+    b.sync()
+    ang = b.angles()
+    for i, cs in enumerate(cases):
+        s = single(cs, precision, Tr=0.8)
+        sa = s.step(45, measure_every=15, cap=4)
+        fb, fs = b.read(i, G.FIELD_F), s.f
+        assert np.array_equal(fb, fs), f"case {i}: max diff {np.abs(fb - fs).max()}"
+        assert np.array_equal(b.read(i, G.FIELD_RHO), s.rho)
+        last = sa[-1]
+        assert ang[i].step == last.step == 30
+        for k in range(2):
+            x, y = ang[i].sector_deg[k], last.sector_deg[k]
+            assert (math.isnan(x) and math.isnan(y)) or x == y
+
+
+def test_batch_case_against_oracle():
+    cases = small_cases(3, seed=11)
+    b = G.Batch(cases, precision=G.LBM_F64, **PHYS)
+    b.step(20)
+    for i, cs in enumerate(cases):
+        wl = dict(dim=2, n=cs["n"], wall=(0, 0), solids=[cs["solid"]], drops=[cs["drop"]])
+        o = oracle_lattice(wl, Tr=0.8)
+        o.step(20)
+        o.update_derived()
+        assert rel_err(b.read(i, G.FIELD_RHO), o.rho, o.cls == 0) < 1e-12
+
+
+def test_launch_shape_does_not_change_results(tmp_path):
+    cases = small_cases(4, seed=3)
+    a = G.Batch(cases, precision=G.LBM_F32, tile_w=64, blocks_per_cu=4, **PHYS)
+    c = G.Batch(cases, precision=G.LBM_F32, autotune=True, cache_path=str(tmp_path / "tune.json"), **PHYS)
+    inf = c.info()
+    assert inf["tile_w"] in (64, 128, 256) and 1 <= inf["blocks_per_cu"] <= 32
+    a.step(40)
+    c.step(40)
+    for i in range(len(cases)):
+        assert np.array_equal(a.read(i, G.FIELD_F), c.read(i, G.FIELD_F))
+    # the cached choice is reused
+    d = G.Batch(cases, precision=G.LBM_F32, autotune=True, cache_path=str(tmp_path / "tune.json"), **PHYS)
+    assert (d.info()["tile_w"], d.info()["blocks_per_cu"]) == (inf["tile_w"], inf["blocks_per_cu"])
+
+
+def test_batch_warm_write():
+    cases = small_cases(3, seed=5)
+    b = G.Batch(cases, precision=G.LBM_F64, **PHYS)
+    b.step(10)
+    rho = b.read(1, G.FIELD_RHO)
+    b.write_rho(1, rho)
+    s = single(cases[1], G.LBM_F64, Tr=0.8)
+    s.step(10)
+    s.write(G.FIELD_RHO, s.rho)
+    b.step(7)
+    s.step(7)
+    assert np.array_equal(b.read(1, G.FIELD_F), s.f)
