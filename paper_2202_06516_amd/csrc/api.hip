@@ -442,6 +442,8 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     {
         const char* e = std::getenv("LBM_XCD_REMAP");
         c->d.xcd_remap = e ? std::atoi(e) != 0 : 1;
+        const char* zf = std::getenv("LBM_ZFIRST");
+        c->d.zfirst = c->dim == 3 && zf && std::atoi(zf) != 0;
     }
     c->pr.a = cfg->pr_a;
     c->pr.b = cfg->pr_b;

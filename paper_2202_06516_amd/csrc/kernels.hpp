@@ -45,6 +45,7 @@ struct Dims {
     int tx, ty;          // 64 x 4 node tiles per row / per plane
     unsigned nblocks;    // tx * ty * nz workgroups
     int xcd_remap;       // 1: contiguous tile ranges per XCD
+    int zfirst;          // 1: tiles walk z fastest (three-dimensional lattices)
 };
 
 __device__ __forceinline__ long long nid(const Dims& d, int x, int y, int z) {
@@ -60,6 +61,14 @@ __device__ __forceinline__ void tile_node(const Dims& d, int& x, int& y, int& z)
     if (d.xcd_remap) {
         const unsigned q = d.nblocks >> 3, r = d.nblocks & 7u, xcd = t & 7u, loc = t >> 3;
         t = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
+    }
+    if (d.zfirst) {
+        // z fastest: the planes above and below a tile are in flight together
+        z = (int)(t % (unsigned)d.nz);
+        t /= (unsigned)d.nz;
+        x = (int)(t % (unsigned)d.tx) * 64 + (int)(threadIdx.x & 63);
+        y = (int)(t / (unsigned)d.tx) * 4 + (int)(threadIdx.x >> 6);
+        return;
     }
     const unsigned txi = t % (unsigned)d.tx, rest = t / (unsigned)d.tx;
     x = (int)txi * 64 + (int)(threadIdx.x & 63);
