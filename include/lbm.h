@@ -292,6 +292,93 @@ lbm_status lbm_batch_get_info(lbm_batch* b, lbm_batch_info* info);
 lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path);
 const char* lbm_batch_last_error(const lbm_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start
+ *
+ * A convolutional U-Net maps three planes of a 2-D lattice (channel 0: 1 on
+ * solid nodes; channel 1: a value on solid nodes, the scaled wall chemical
+ * potential; channel 2: a constant, the scaled drop volume) to
+ * phi = (rho - rho_g) / (rho_l - rho_g) of the equilibrated drop.  Its output,
+ * made mass-exact by lbm_unet_warm_rho, replaces the initial density of
+ * Eq. 16 through lbm_write / lbm_batch_write (RHO).  This is an extension:
+ * the paper initialises every run with Eq. 16 (Sec. IV).
+ *
+ * Architecture: levels l = 0..L-1 with C_l = base_channels * 2^l channels;
+ * per level two 3x3 convolutions (zero padding 1) each followed by ReLU; 2x2
+ * max pooling between encoder levels; per decoder level a 2x2 stride-2
+ * transposed convolution from C_{l+1} to C_l channels, concatenation
+ * [upsampled | encoder output of level l], two 3x3 convolutions with ReLU; a
+ * 1x1 head to one channel, no activation.  Products run on BF16 MFMA tiles
+ * with FP32 accumulation; activations and their gradients are BF16;
+ * weights, gradients and Adam moments are FP32.
+ *
+ * Tensors crossing this interface are FP32 device arrays, NHWC:
+ * inputs x [n][H][W][in_channels], outputs and targets [n][H][W]
+ * (the lattice's x is W, its y is H).
+ *
+ * Parameters form one FP32 vector in this order:
+ *   for l = 0..L-1:  conv W [C_l][3][3][C_in(l)], b [C_l];  conv W [C_l][3][3][C_l], b [C_l]
+ *                    (C_in(0) = in_channels, C_in(l) = C_{l-1});
+ *   for l = L-2..0:  up W [2][2][C_l][C_{l+1}] (row (2a + b) C_l + co: output pixel
+ *                    (2h + a, 2w + b) from input pixel (h, w)), b [C_l];
+ *                    conv W [C_l][3][3][2 C_l] (input channels: upsampled first), b [C_l];
+ *                    conv W [C_l][3][3][C_l], b [C_l];
+ *   head w [C_0], b [1].
+ * A 3x3 weight W[co][dy + 1][dx + 1][ci] multiplies input pixel (h + dy, w + dx).
+ * The loss is the mean squared error over the n H W outputs.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_unet lbm_unet;
+
+typedef struct {
+    int H, W;            /* lattice rows and columns; divisible by 2^(levels-1) */
+    int batch;           /* largest n of a call */
+    int in_channels;     /* 1..8 (3 for the warm start) */
+    int base_channels;   /* C_0: a multiple of 8 that divides 256 (8..128) */
+    int levels;          /* L: 1..6 */
+    double lr, beta1, beta2, eps;  /* Adam */
+    void* stream;        /* hipStream_t or NULL (the network creates one) */
+} lbm_unet_config;
+
+enum { LBM_UNET_WEIGHTS = 0, LBM_UNET_GRADS = 1 };
+
+/* H = W = 256, batch 8, 3 inputs, C_0 = 32, L = 4, Adam 1e-3 / 0.9 / 0.999 / 1e-8. */
+void lbm_unet_config_default(lbm_unet_config* cfg);
+/* Allocate the network (weights zero; set them with lbm_unet_set_params).
+ * Errors: LBM_E_ARG (a field out of range), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_unet_create(const lbm_unet_config* cfg, lbm_unet** out);
+lbm_status lbm_unet_destroy(lbm_unet* u);
+int64_t lbm_unet_param_count(const lbm_unet* u);
+/* Replace the weights (n = lbm_unet_param_count) and reset the Adam state. */
+lbm_status lbm_unet_set_params(lbm_unet* u, const float* p, int64_t n, int src_on_device);
+/* Copy out the weights (LBM_UNET_WEIGHTS) or the gradients of the last backward pass (LBM_UNET_GRADS). */
+lbm_status lbm_unet_get_params(lbm_unet* u, float* p, int64_t n, int which, int dst_on_device);
+/* y = network(x) for n samples (1 <= n <= batch); x, y on the device.  Synchronises. */
+lbm_status lbm_unet_forward(lbm_unet* u, const float* x, float* y, int n);
+/* Forward, loss against target (device), and gradients of every parameter; loss (host, nullable). */
+lbm_status lbm_unet_backward(lbm_unet* u, const float* x, const float* target, int n, double* loss);
+/* lbm_unet_backward, then one Adam step with bias correction. */
+lbm_status lbm_unet_train_step(lbm_unet* u, const float* x, const float* target, int n, double* loss);
+lbm_status lbm_unet_set_lr(lbm_unet* u, double lr);
+
+/* Input planes from a lattice's CLASS field (device, [n] uint8): x[i] =
+ * {solid, solid ? solid_value : 0, plane} (x device FP32 [n][3]).  Enqueues on stream. */
+lbm_status lbm_unet_encode(const uint8_t* cls, int64_t n, double solid_value, double plane, float* x, void* stream);
+/* Training target from a density field (device, elem of precision): phi =
+ * (rho - rho_g) / (rho_l - rho_g) on fluid nodes, 0 on solid nodes.  Enqueues on stream. */
+lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, int64_t n, double rho_g, double rho_l,
+                           float* phi, void* stream);
+/* Density for a warm start from a predicted phi (device [n]): fluid nodes get
+ * rho_g + (rho_l - rho_g) s clamp(phi + delta, 0, 1), with delta (bisection)
+ * and s (close to 1) chosen so that the fluid mass equals that of rho_ref
+ * (the cold initial state), solid nodes 0; rho_out has the element type of
+ * precision.  info (host, nullable, 5 doubles) = {reference mass, written
+ * mass, delta, s, fluid nodes}.  Runs on the network's stream; synchronises.
+ * LBM_E_ARG if the reference mass is not strictly between n_fluid rho_g and
+ * n_fluid rho_l. */
+lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int64_t n,
+                             int precision, double rho_g, double rho_l, void* rho_out, double* info);
+const char* lbm_unet_last_error(const lbm_unet* u);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,12 @@ Backward passes are the chain rule of those definitions.  The flat
 parameter order is the one the C interface documents for
 lbm_unet_get_params.
 
+ReLU masks and pooling choices are discrete decisions taken on forward
+values.  With storage="bf16" the forward pass rounds, as the GPU network
+stores them, the input, the convolution weights and every activation to
+bfloat16 (round to nearest even; all arithmetic stays float64), so that both
+sides take those decisions on the same values; gradients are never rounded.
+
 Pins (tests/test_oracle_unet.py): the convolution against
 scipy.signal.correlate2d, tap convention with a delta kernel, the
 transposed convolution as the adjoint of its data gradient and against
@@ -104,6 +110,14 @@ def upconv2_bwd(x, w, gy):
     return gx, gw, gy.sum(axis=(0, 1, 2))
 
 
+def bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def mse(y, t):
     d = y - t
     return float(np.mean(d * d)), 2.0 * d / d.size
@@ -164,15 +178,24 @@ def init_params(rng, levels=4, base=32, in_channels=3):
 # ---------------------------------------------------------------------------
 # the network
 # ---------------------------------------------------------------------------
-def forward(theta, x, levels=4, base=32):
-    """x [n,H,W,Cin] -> y [n,H,W] and the activations the backward pass needs."""
+def forward(theta, x, levels=4, base=32, storage="fp64"):
+    """x [n,H,W,Cin] -> y [n,H,W] and the activations the backward pass needs.
+
+    storage="bf16": the input, the 3x3 and transposed-convolution weights and
+    every stored activation are rounded to bfloat16 (see the module notes).
+    """
+    q = bf16 if storage == "bf16" else (lambda a: a)
     p = unpack(theta, levels, base, x.shape[3])
-    cache = {"x": x}
+    for name in list(p):
+        if name.endswith(".w") and name != "head.w":
+            p[name] = q(p[name])
+    x = q(x)
+    cache = {"x": x, "p": p}
     h = x
     skips = []
     for l in range(levels):
-        a = relu(conv3x3(h, p[f"enc{l}a.w"], p[f"enc{l}a.b"]))
-        b = relu(conv3x3(a, p[f"enc{l}b.w"], p[f"enc{l}b.b"]))
+        a = q(relu(conv3x3(h, p[f"enc{l}a.w"], p[f"enc{l}a.b"])))
+        b = q(relu(conv3x3(a, p[f"enc{l}b.w"], p[f"enc{l}b.b"])))
         cache[f"enc{l}.in"], cache[f"enc{l}.a"], cache[f"enc{l}.b"] = h, a, b
         skips.append(b)
         if l < levels - 1:
@@ -180,10 +203,10 @@ def forward(theta, x, levels=4, base=32):
             cache[f"pool{l}.arg"] = arg
     h = skips[-1]
     for l in range(levels - 2, -1, -1):
-        u = upconv2(h, p[f"up{l}.w"], p[f"up{l}.b"])
+        u = q(upconv2(h, p[f"up{l}.w"], p[f"up{l}.b"]))
         cat = np.concatenate([u, skips[l]], axis=3)
-        a = relu(conv3x3(cat, p[f"dec{l}a.w"], p[f"dec{l}a.b"]))
-        b = relu(conv3x3(a, p[f"dec{l}b.w"], p[f"dec{l}b.b"]))
+        a = q(relu(conv3x3(cat, p[f"dec{l}a.w"], p[f"dec{l}a.b"])))
+        b = q(relu(conv3x3(a, p[f"dec{l}b.w"], p[f"dec{l}b.b"])))
         cache[f"up{l}.in"], cache[f"dec{l}.cat"], cache[f"dec{l}.a"], cache[f"dec{l}.b"] = h, cat, a, b
         h = b
     cache["head.in"] = h
@@ -194,7 +217,7 @@ def forward(theta, x, levels=4, base=32):
 def backward(theta, cache, gy, levels=4, base=32):
     """Gradient of every parameter (flat, C-interface order) and of the input, given dL/dy."""
     x = cache["x"]
-    p = unpack(theta, levels, base, x.shape[3])
+    p = cache["p"]   # the weights the forward pass used
     g = {}
     h = cache["head.in"]
     g["head.w"] = np.einsum("nhw,nhwc->c", gy, h)
@@ -225,8 +248,8 @@ def backward(theta, cache, gy, levels=4, base=32):
     return pack(g, levels, base, x.shape[3]), gx
 
 
-def loss_and_grad(theta, x, t, levels=4, base=32):
-    y, cache = forward(theta, x, levels, base)
+def loss_and_grad(theta, x, t, levels=4, base=32, storage="fp64"):
+    y, cache = forward(theta, x, levels, base, storage)
     L, gy = mse(y, t)
     grad, _ = backward(theta, cache, gy, levels, base)
     return L, grad, y

@@ -1,0 +1,1279 @@
+// unet.hip -- the learned warm start: a convolutional U-Net trained and run on
+// gfx950 with hand-written BF16 MFMA kernels (FP32 accumulation), and the
+// kernels that turn lattice fields into its inputs and targets and its output
+// back into a mass-exact density field.
+//
+// The network maps (solid mask, wall chemical potential on the solid, drop
+// volume plane) on a 2-D lattice to phi = (rho - rho_g) / (rho_l - rho_g) of
+// the equilibrated drop.  Levels l = 0..L-1 carry C0 * 2^l channels: two 3x3
+// same-padded convolutions with ReLU per level, 2x2 max pooling down, a 2x2
+// stride-2 transposed convolution up, skip connections by channel
+// concatenation (upsampled first, skip second), and a 1x1 head.  Activations
+// and their gradients are NHWC BF16; master weights, gradients and the Adam
+// moments are FP32, with BF16 copies for the products.
+//
+// Every product is one implicit-GEMM kernel on MFMA 16x16x32 BF16 tiles:
+// BM x BN output tiles per 256-thread workgroup (four waves, 2 x 2), K in
+// chunks of 32 staged through LDS with the next chunk's global loads in flight
+// during the current chunk's MFMAs.  Loader functors gather 16-byte vectors
+// of an operand either along K or along M/N, so that every pass is a GEMM
+// whose operands are read in their stored layout: the 3x3 convolution (im2col
+// on the fly), its data gradient (mirrored taps, ReLU mask fused into the
+// load), its weight gradient (split-K, bias gradient as an extra column of
+// ones, deterministic reduction), and the transposed convolution with its two
+// gradients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef long long i64;
+
+constexpr int BK = 32;    // K chunk per LDS stage (one MFMA 16x16x32 step)
+constexpr int CPAD = 8;   // the network input is padded to 8 channels (one 16-byte vector)
+
+__device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+    return v;
+}
+__device__ __forceinline__ bf16x8 masked8(bf16x8 v, bf16x8 m) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (!((float)m[j] > 0.f)) v[j] = (bf16)0.f;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Operand loaders.  elem(mn, k) is element (row mn, reduction index k) of A
+// (mn = m) or of B (mn = n); vec(mn, k) returns the 8 elements that follow
+// along the loader's vector axis: k..k+7 when KMAJ, mn..mn+7 otherwise.  The
+// GEMM calls vec only for vectors that lie wholly inside the matrix.
+// ---------------------------------------------------------------------------
+
+// pixel index m of a B x H x W grid -> (b, h, w)
+struct Grid {
+    int B, H, W;
+    __device__ __forceinline__ void split(i64 m, int& b, int& h, int& w) const {
+        const i64 q = m / W;
+        w = (int)(m - q * W);
+        b = (int)(q / H);
+        h = (int)(q - (i64)b * H);
+    }
+};
+
+// im2col of a 3x3 same-padded convolution over one NHWC tensor or the channel
+// concatenation [X1 | X2]: element (m = pixel, k = tap * (C1 + C2) + c) with
+// tap = 3 (dy + 1) + (dx + 1).  flip mirrors the tap (dy, dx) -> (-dy, -dx);
+// mask, if set, zeroes values whose ReLU output (same shape as X1) is not
+// positive.
+struct Im2col {
+    static constexpr bool KMAJ = true;
+    const bf16* X1;
+    const bf16* X2;
+    const bf16* mask;
+    Grid g;
+    int C1, C2, flip;
+    __device__ __forceinline__ bool locate(i64 m, i64 k, i64& p, int& c) const {
+        const int C = C1 + C2;
+        int tap = (int)(k / C);
+        c = (int)(k - (i64)tap * C);
+        if (flip) tap = 8 - tap;
+        int b, h, w;
+        g.split(m, b, h, w);
+        h += tap / 3 - 1;
+        w += tap % 3 - 1;
+        if (h < 0 || h >= g.H || w < 0 || w >= g.W) return false;
+        p = ((i64)b * g.H + h) * g.W + w;
+        return true;
+    }
+    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const {
+        i64 p;
+        int c;
+        if (!locate(m, k, p, c)) return (bf16)0.f;
+        if (c < C1) {
+            if (mask && !((float)mask[p * C1 + c] > 0.f)) return (bf16)0.f;
+            return X1[p * C1 + c];
+        }
+        return X2[p * C2 + (c - C1)];
+    }
+    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const {
+        i64 p;
+        int c;
+        if (!locate(m, k, p, c)) return zero8();
+        if (c < C1) {
+            const bf16x8 v = ld8(X1 + p * C1 + c);
+            return mask ? masked8(v, ld8(mask + p * C1 + c)) : v;
+        }
+        return ld8(X2 + p * C2 + (c - C1));
+    }
+};
+
+// B of the convolution: element (n = co, k) = Wb[n * K + k] (weights [Co][9][Cp]);
+// and of the transposed convolution: element (n = (2a + b) Co + co, k = ci)
+struct RowsK {
+    static constexpr bool KMAJ = true;
+    const bf16* P;
+    i64 K;
+    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return P[n * K + k]; }
+    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(P + n * K + k); }
+};
+
+// B of the convolution's data gradient: element (n = ci, k = tap * Co + co) =
+// Wb[co][tap][ci] (the taps are mirrored by the Im2col of dY)
+struct ConvWT {
+    static constexpr bool KMAJ = false;
+    const bf16* Wb;
+    int Co, Cp;
+    __device__ __forceinline__ i64 at(i64 n, i64 k) const {
+        const i64 tap = k / Co, co = k - tap * Co;
+        return (co * 9 + tap) * Cp + n;
+    }
+    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return Wb[at(n, k)]; }
+    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(Wb + at(n, k)); }
+};
+
+// A of the convolution's weight gradient: element (m = co, k = pixel) =
+// dY[pixel][co], zeroed where the ReLU output Y is not positive
+struct DYmasked {
+    static constexpr bool KMAJ = false;
+    const bf16* dY;
+    const bf16* Y;
+    int Co;
+    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const {
+        const i64 i = k * Co + m;
+        return (float)Y[i] > 0.f ? dY[i] : (bf16)0.f;
+    }
+    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const {
+        const i64 i = k * Co + m;
+        return masked8(ld8(dY + i), ld8(Y + i));
+    }
+};
+
+// B of the convolution's weight gradient: element (n, k = pixel) = im2col
+// (pixel, n) for n < 9 (C1 + C2), and 1 for n = 9 (C1 + C2) (the bias column)
+struct Im2colOnes {
+    static constexpr bool KMAJ = false;
+    Im2col a;
+    i64 nbias;
+    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return n == nbias ? (bf16)1.f : a.elem(k, n); }
+    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const {
+        // a vector along n lies within one tap (C1, C2 multiples of 8); read it pixel by pixel
+        i64 p;
+        int c;
+        if (!a.locate(k, n, p, c)) return zero8();
+        if (c < a.C1) return ld8(a.X1 + p * a.C1 + c);
+        return ld8(a.X2 + p * a.C2 + (c - a.C1));
+    }
+};
+
+// A of the transposed convolution: element (m = pixel, k = ci) = X[pixel][ci]
+struct RowsKA {
+    static constexpr bool KMAJ = true;
+    const bf16* X;
+    int C;
+    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const { return X[m * C + k]; }
+    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const { return ld8(X + m * C + k); }
+};
+
+// output pixel of the transposed convolution for input pixel m and offset ab = 2a + b
+struct UpMap {
+    Grid g;  // the input grid; the output grid is B x 2H x 2W
+    __device__ __forceinline__ i64 out(i64 m, int ab) const {
+        int b, h, w;
+        g.split(m, b, h, w);
+        return ((i64)b * 2 * g.H + 2 * h + (ab >> 1)) * (2 * g.W) + 2 * w + (ab & 1);
+    }
+};
+
+// A of the transposed convolution's data gradient: element (m = input pixel,
+// k = ab * Co + co) = dY[out(m, ab)][co]
+struct UpGatherK {
+    static constexpr bool KMAJ = true;
+    const bf16* dY;
+    UpMap u;
+    int Co;
+    __device__ __forceinline__ i64 at(i64 m, i64 k) const {
+        const int ab = (int)(k / Co);
+        return u.out(m, ab) * Co + (k - (i64)ab * Co);
+    }
+    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const { return dY[at(m, k)]; }
+    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const { return ld8(dY + at(m, k)); }
+};
+
+// B of the transposed convolution's data gradient: element (n = ci, k = row) = Wt[row][ci]
+struct RowsN {
+    static constexpr bool KMAJ = false;
+    const bf16* P;
+    int C;
+    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return P[k * C + n]; }
+    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(P + k * C + n); }
+};
+
+// A of the transposed convolution's weight gradient: element (m = ab * Co + co,
+// k = input pixel) = dY[out(k, ab)][co]
+struct UpGatherM {
+    static constexpr bool KMAJ = false;
+    const bf16* dY;
+    UpMap u;
+    int Co;
+    __device__ __forceinline__ i64 at(i64 m, i64 k) const {
+        const int ab = (int)(m / Co);
+        return u.out(k, ab) * Co + (m - (i64)ab * Co);
+    }
+    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const { return dY[at(m, k)]; }
+    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const { return ld8(dY + at(m, k)); }
+};
+
+// B of the transposed convolution's weight gradient: element (n = ci, k = pixel)
+// = X[pixel][ci] for n < C, 1 for n = C (the bias column)
+struct ColsOnes {
+    static constexpr bool KMAJ = false;
+    const bf16* X;
+    int C;
+    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return n == C ? (bf16)1.f : X[k * C + n]; }
+    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(X + k * C + n); }
+};
+
+// ---------------------------------------------------------------------------
+// Epilogues (called once per output element, with bounds checks inside)
+// ---------------------------------------------------------------------------
+struct EpiBiasRelu {  // Y[m][n] = relu(acc + bias[n]) in BF16
+    bf16* Y;
+    const float* bias;
+    i64 M;
+    int N;
+    __device__ __forceinline__ void operator()(i64 m, i64 n, float v) const {
+        if (m >= M || n >= N) return;
+        v += bias[n];
+        Y[m * N + n] = (bf16)(v > 0.f ? v : 0.f);
+    }
+};
+
+struct EpiSplit {  // columns [0, N1) -> Y1[m][n], [N1, N1 + N2) -> Y2[m][n - N1] (BF16)
+    bf16* Y1;
+    bf16* Y2;
+    i64 M;
+    int N1, N2;
+    __device__ __forceinline__ void operator()(i64 m, i64 n, float v) const {
+        if (m >= M || n >= N1 + N2) return;
+        if (n < N1) Y1[m * N1 + n] = (bf16)v;
+        else Y2[m * N2 + (n - N1)] = (bf16)v;
+    }
+};
+
+struct EpiPartial {  // split-K partial sums, FP32 [z][M][N]
+    float* P;
+    i64 M, N;
+    __device__ __forceinline__ void operator()(i64 m, i64 n, float v) const {
+        if (m >= M || n >= N) return;
+        P[(i64)blockIdx.z * M * N + m * N + n] = v;
+    }
+};
+
+struct EpiUp {  // column n = ab * Co + co of input pixel m -> Y[out(m, ab)][co] = acc + bias[co]
+    bf16* Y;
+    const float* bias;
+    UpMap u;
+    i64 M;
+    int Co;
+    __device__ __forceinline__ void operator()(i64 m, i64 n, float v) const {
+        if (m >= M || n >= 4LL * Co) return;
+        const int ab = (int)(n / Co), co = (int)(n - (i64)ab * Co);
+        Y[u.out(m, ab) * Co + co] = (bf16)(v + bias[co]);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// The GEMM: C[M][N] = sum_k A(m, k) B(k, n) over k in [z kchunk, (z+1) kchunk)
+// ---------------------------------------------------------------------------
+template <class L>
+__device__ __forceinline__ bf16x8 load_vec(const L& l, i64 mn, i64 k, i64 mnlim, i64 klim) {
+    if constexpr (L::KMAJ) {
+        if (mn < mnlim && k + 8 <= klim) return l.vec(mn, k);
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (mn < mnlim && k + j < klim) ? l.elem(mn, k + j) : (bf16)0.f;
+        return v;
+    } else {
+        if (k < klim && mn + 8 <= mnlim) return l.vec(mn, k);
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (k < klim && mn + j < mnlim) ? l.elem(mn + j, k) : (bf16)0.f;
+        return v;
+    }
+}
+
+// tile coordinates of vector v of a BMN x BK stage
+template <bool KMAJ, int BMN>
+__device__ __forceinline__ void vec_coord(int v, int& mn, int& kk) {
+    if (KMAJ) {
+        mn = v / (BK / 8);
+        kk = (v % (BK / 8)) * 8;
+    } else {
+        kk = v / (BMN / 8);
+        mn = (v % (BMN / 8)) * 8;
+    }
+}
+
+template <int BM, int BN, class LA, class LB, class EPI>
+__global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N, i64 K, i64 kchunk) {
+    // LDS: K-major operands as [rows][BK + 8], M/N-major as [BK][rows + 8]
+    constexpr int AC = (LA::KMAJ ? BK : BM) + 8, BC = (LB::KMAJ ? BK : BN) + 8;
+    constexpr int AR = LA::KMAJ ? BM : BK, BR = LB::KMAJ ? BN : BK;
+    __shared__ __attribute__((aligned(16))) bf16 As[AR * AC];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BR * BC];
+    constexpr int NVA = BM * BK / 8, NVB = BN * BK / 8;
+    constexpr int RA = (NVA + 255) / 256, RB = (NVB + 255) / 256;
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    static_assert(TM >= 1 && TN >= 1, "tile too small");
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const i64 m0 = (i64)blockIdx.x * BM, n0 = (i64)blockIdx.y * BN;
+    const i64 kb = (i64)blockIdx.z * kchunk;
+    const i64 ke = kb + kchunk < K ? kb + kchunk : K;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+    floatx4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    bf16x8 ra[RA], rb[RB];
+    auto fetch = [&](i64 k0) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int v = tid + 256 * r;
+            if (NVA % 256 == 0 || v < NVA) {
+                int mn, kk;
+                vec_coord<LA::KMAJ, BM>(v, mn, kk);
+                ra[r] = load_vec(A, m0 + mn, k0 + kk, M, ke);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int v = tid + 256 * r;
+            if (NVB % 256 == 0 || v < NVB) {
+                int mn, kk;
+                vec_coord<LB::KMAJ, BN>(v, mn, kk);
+                rb[r] = load_vec(B, n0 + mn, k0 + kk, N, ke);
+            }
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            const int v = tid + 256 * r;
+            if (NVA % 256 == 0 || v < NVA) {
+                int mn, kk;
+                vec_coord<LA::KMAJ, BM>(v, mn, kk);
+                *reinterpret_cast<bf16x8*>(&As[LA::KMAJ ? mn * AC + kk : kk * AC + mn]) = ra[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int v = tid + 256 * r;
+            if (NVB % 256 == 0 || v < NVB) {
+                int mn, kk;
+                vec_coord<LB::KMAJ, BN>(v, mn, kk);
+                *reinterpret_cast<bf16x8*>(&Bs[LB::KMAJ ? mn * BC + kk : kk * BC + mn]) = rb[r];
+            }
+        }
+    };
+
+    if (kb < ke) fetch(kb);
+    for (i64 k0 = kb; k0 < ke; k0 += BK) {
+        stash();
+        __syncthreads();
+        if (k0 + BK < ke) fetch(k0 + BK);
+        // MFMA 16x16x32 operands: lane holds row (lane % 16), k = 8 (lane / 16) .. + 7
+        const int kg = (lane >> 4) * 8, rl = lane & 15;
+        bf16x8 a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int row = wm + i * 16 + rl;
+            if constexpr (LA::KMAJ) {
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[row * AC + kg]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[i][j] = As[(kg + j) * AC + row];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TN; ++i) {
+            const int row = wn + i * 16 + rl;
+            if constexpr (LB::KMAJ) {
+                b[i] = *reinterpret_cast<const bf16x8*>(&Bs[row * BC + kg]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[i][j] = Bs[(kg + j) * BC + row];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D layout: lane holds column (lane % 16), rows 4 (lane / 16) .. + 3
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                epi(m0 + wm + i * 16 + (lane >> 4) * 4 + q, n0 + wn + j * 16 + (lane & 15), acc[i][j][q]);
+}
+
+// K split into z chunks (multiples of BK); returns the number of chunks launched
+inline i64 kchunk_of(i64 K, int z) {
+    const i64 c = ((K + z - 1) / z + BK - 1) / BK * BK;
+    return c < BK ? BK : c;
+}
+inline int nchunks(i64 K, int z) {
+    const i64 c = kchunk_of(K, z);
+    const i64 n = (K + c - 1) / c;
+    return (int)(n < 1 ? 1 : n);
+}
+
+template <int BM, int BN, class LA, class LB, class EPI>
+void launch_gemm(hipStream_t s, const LA& A, const LB& B, const EPI& e, i64 M, i64 N, i64 K, int z) {
+    dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)nchunks(K, z));
+    k_gemm<BM, BN, LA, LB, EPI><<<grid, 256, 0, s>>>(A, B, e, M, N, K, kchunk_of(K, z));
+}
+
+// A GEMM without split-K: 128-row tiles when they give at least 1024
+// workgroups, 64-row tiles otherwise; 32 columns when N <= 32, else 64
+template <class LA, class LB, class EPI>
+void gemm(hipStream_t s, const LA& A, const LB& B, const EPI& e, i64 M, i64 N, i64 K) {
+    const bool narrow = N <= 32;
+    const i64 big = ((M + 127) / 128) * ((N + (narrow ? 31 : 63)) / (narrow ? 32 : 64));
+    if (narrow) {
+        if (big >= 1024) launch_gemm<128, 32>(s, A, B, e, M, N, K, 1);
+        else launch_gemm<64, 32>(s, A, B, e, M, N, K, 1);
+    } else {
+        if (big >= 1024) launch_gemm<128, 64>(s, A, B, e, M, N, K, 1);
+        else launch_gemm<64, 64>(s, A, B, e, M, N, K, 1);
+    }
+}
+
+// K splits for a weight gradient: about 2048 workgroups, at least 1024 pixels
+// per chunk, and no more partials than the buffer holds
+int splits_for(i64 M, i64 N, i64 K, i64 cap_elems) {
+    const i64 tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    i64 z = (2048 + tiles - 1) / tiles;
+    z = std::min<i64>(z, std::max<i64>(1, K / 1024));
+    while (z > 1 && (i64)nchunks(K, (int)z) * M * N > cap_elems) --z;
+    return (int)std::max<i64>(1, z);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions, elementwise layers, loss and optimiser
+// ---------------------------------------------------------------------------
+inline int blocks_for(i64 n) {
+    const i64 b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+#define GRID_STRIDE(i, n) \
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
+
+// split-K partials of a convolution's weight gradient, [z][Co][9 Cp + 1], summed
+// in a fixed order into gw [Co][9][Ci] (channels >= Ci are padding) and gb [Co]
+__global__ void k_reduce_conv(const float* __restrict__ P, int z, int Co, int Cp, int Ci, float* __restrict__ gw,
+                              float* __restrict__ gb) {
+    const i64 N1 = 9LL * Cp + 1, MN = (i64)Co * N1;
+    GRID_STRIDE(idx, MN) {
+        float s = 0.f;
+        for (int k = 0; k < z; ++k) s += P[(i64)k * MN + idx];
+        const i64 co = idx / N1, n = idx - co * N1;
+        if (n == 9LL * Cp) {
+            gb[co] = s;
+        } else {
+            const i64 t = n / Cp, c = n - t * Cp;
+            if (c < Ci) gw[(co * 9 + t) * Ci + c] = s;
+        }
+    }
+}
+
+// partials of a transposed convolution's weight gradient, [z][4 Co][Ci + 1] ->
+// gw [4 Co][Ci] and gb [Co] (the bias sums the four offsets)
+__global__ void k_reduce_up(const float* __restrict__ P, int z, int Co, int Ci, float* __restrict__ gw,
+                            float* __restrict__ gb) {
+    const i64 N1 = Ci + 1, MN = 4LL * Co * N1, NW = 4LL * Co * Ci;
+    GRID_STRIDE(idx, NW + Co) {
+        float s = 0.f;
+        if (idx < NW) {
+            const i64 r = idx / Ci, c = idx - r * Ci;
+            for (int k = 0; k < z; ++k) s += P[(i64)k * MN + r * N1 + c];
+            gw[idx] = s;
+        } else {
+            const i64 co = idx - NW;
+            for (int ab = 0; ab < 4; ++ab)
+                for (int k = 0; k < z; ++k) s += P[(i64)k * MN + (ab * Co + co) * N1 + Ci];
+            gb[co] = s;
+        }
+    }
+}
+
+// 2x2 max pooling (NHWC), with the position (0..3) of the first maximum kept
+__global__ void k_pool_fwd(const bf16* __restrict__ X, bf16* __restrict__ Y, uint8_t* __restrict__ arg, Grid g, int C) {
+    const int Ho = g.H / 2, Wo = g.W / 2;
+    const i64 n = (i64)g.B * Ho * Wo * C;
+    GRID_STRIDE(i, n) {
+        const int c = (int)(i % C);
+        const i64 q = i / C;
+        const int w = (int)(q % Wo), h = (int)((q / Wo) % Ho), b = (int)(q / ((i64)Wo * Ho));
+        float best = -INFINITY;
+        int bi = 0;
+        for (int a = 0; a < 4; ++a) {
+            const i64 p = ((i64)b * g.H + 2 * h + (a >> 1)) * g.W + 2 * w + (a & 1);
+            const float v = (float)X[p * C + c];
+            if (v > best) {
+                best = v;
+                bi = a;
+            }
+        }
+        Y[i] = (bf16)best;
+        arg[i] = (uint8_t)bi;
+    }
+}
+
+// dX += dY at the position of each window's maximum (dX already holds the
+// gradient that reaches the pooled tensor's input through the skip connection)
+__global__ void k_pool_bwd(const bf16* __restrict__ dY, const uint8_t* __restrict__ arg, bf16* __restrict__ dX, Grid g,
+                           int C) {
+    const int Ho = g.H / 2, Wo = g.W / 2;
+    const i64 n = (i64)g.B * Ho * Wo * C;
+    GRID_STRIDE(i, n) {
+        const int c = (int)(i % C);
+        const i64 q = i / C;
+        const int w = (int)(q % Wo), h = (int)((q / Wo) % Ho), b = (int)(q / ((i64)Wo * Ho));
+        const int a = arg[i];
+        const i64 p = ((i64)b * g.H + 2 * h + (a >> 1)) * g.W + 2 * w + (a & 1);
+        dX[p * C + c] = (bf16)((float)dX[p * C + c] + (float)dY[i]);
+    }
+}
+
+// 1x1 head to one FP32 channel (C a multiple of 8)
+__global__ void k_head_fwd(const bf16* __restrict__ X, const float* __restrict__ w, const float* __restrict__ b,
+                           float* __restrict__ y, i64 P, int C) {
+    GRID_STRIDE(p, P) {
+        float s = b[0];
+        for (int c = 0; c < C; c += 8) {
+            const bf16x8 v = ld8(X + p * C + c);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += (float)v[j] * w[c + j];
+        }
+        y[p] = s;
+    }
+}
+
+__global__ void k_head_bwd_x(const float* __restrict__ dy, const float* __restrict__ w, bf16* __restrict__ dX, i64 P,
+                             int C) {
+    GRID_STRIDE(i, P * C) { dX[i] = (bf16)(dy[i / C] * w[i % C]); }
+}
+
+// head weight and bias gradients: per-block partials [blk][C + 1] (C divides 256)
+__global__ void __launch_bounds__(256) k_head_bwd_w(const float* __restrict__ dy, const bf16* __restrict__ X, i64 P,
+                                                    int C, float* __restrict__ part) {
+    __shared__ float red[256];
+    __shared__ float redb[256];
+    const int c = threadIdx.x % C, grp = threadIdx.x / C, ngrp = 256 / C;
+    const i64 per = (P + gridDim.x - 1) / gridDim.x;
+    const i64 beg = (i64)blockIdx.x * per, end = std::min<i64>(P, beg + per);
+    float s = 0.f, sb = 0.f;
+    for (i64 p = beg + grp; p < end; p += ngrp) {
+        s += dy[p] * (float)X[p * C + c];
+        if (c == 0) sb += dy[p];
+    }
+    red[threadIdx.x] = s;
+    redb[threadIdx.x] = sb;
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        float t = 0.f;
+        for (int k = 0; k < ngrp; ++k) t += red[k * C + threadIdx.x];
+        part[(i64)blockIdx.x * (C + 1) + threadIdx.x] = t;
+    }
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < ngrp; ++k) t += redb[k * C];
+        part[(i64)blockIdx.x * (C + 1) + C] = t;
+    }
+}
+
+__global__ void k_head_reduce(const float* __restrict__ part, int nblk, int C, float* __restrict__ gw,
+                              float* __restrict__ gb) {
+    const int c = threadIdx.x;
+    if (c > C) return;
+    float s = 0.f;
+    for (int k = 0; k < nblk; ++k) s += part[(i64)k * (C + 1) + c];
+    if (c < C) gw[c] = s;
+    else gb[0] = s;
+}
+
+// mean squared error: dL/dy and per-block FP64 partial sums
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t, i64 n,
+                                             float* __restrict__ dy, double* __restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    GRID_STRIDE(i, n) {
+        const float e = y[i] - t[i];
+        s += (double)e * e;
+        dy[i] = 2.f * e / (float)n;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+// Adam with bias correction (c1 = 1 - beta1^t, c2 = 1 - beta2^t)
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       i64 n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    GRID_STRIDE(i, n) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// FP32 [rows][Ci] -> BF16 [rows][Cp], zero in the padding channels
+__global__ void k_cast_pad(const float* __restrict__ x, bf16* __restrict__ y, i64 rows, int Ci, int Cp) {
+    GRID_STRIDE(i, rows * Cp) {
+        const i64 r = i / Cp;
+        const int c = (int)(i - r * Cp);
+        y[i] = (bf16)(c < Ci ? x[r * Ci + c] : 0.f);
+    }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, i64 n, float v) {
+    GRID_STRIDE(i, n) { p[i] = v; }
+}
+
+// ---------------------------------------------------------------------------
+// Lattice <-> network fields
+// ---------------------------------------------------------------------------
+constexpr uint8_t SOLID_BITS = 3;  // low two class bits: 0 fluid, 1..3 solid layers
+
+__global__ void k_encode(const uint8_t* __restrict__ cls, i64 n, float solid_value, float plane, float* __restrict__ x) {
+    GRID_STRIDE(i, n) {
+        const bool s = (cls[i] & SOLID_BITS) != 0;
+        x[3 * i + 0] = s ? 1.f : 0.f;
+        x[3 * i + 1] = s ? solid_value : 0.f;
+        x[3 * i + 2] = plane;
+    }
+}
+
+template <typename R>
+__global__ void k_target(const R* __restrict__ rho, const uint8_t* __restrict__ cls, i64 n, double rho_g, double rho_l,
+                         float* __restrict__ phi) {
+    GRID_STRIDE(i, n) {
+        phi[i] = (cls[i] & SOLID_BITS) ? 0.f : (float)(((double)rho[i] - rho_g) / (rho_l - rho_g));
+    }
+}
+
+// One workgroup: the mass-exact density from a predicted phi.  Fluid nodes get
+// rho = rho_g + (rho_l - rho_g) s clamp(phi + delta, 0, 1) with delta found by
+// bisection so that the fluid mass equals that of rho_ref, and s (close to 1)
+// removing what the bisection leaves; solid nodes get 0.
+// out = {mass of rho_ref, mass written, delta, s, fluid nodes}.
+template <typename R>
+__global__ void __launch_bounds__(1024) k_warm_rho(const float* __restrict__ phi, const R* __restrict__ rho_ref,
+                                                   const uint8_t* __restrict__ cls, i64 n, double rho_g, double rho_l,
+                                                   R* __restrict__ rho, double* __restrict__ out) {
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    auto block_sum = [&](double v) {
+        red[t] = v;
+        __syncthreads();
+        for (int o = 512; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        const double s = red[0];
+        __syncthreads();
+        return s;
+    };
+    auto clamped = [&](i64 i, double d) { return fmin(1.0, fmax(0.0, (double)phi[i] + d)); };
+    double m = 0.0, nf = 0.0;
+    for (i64 i = t; i < n; i += 1024)
+        if (!(cls[i] & SOLID_BITS)) {
+            m += (double)rho_ref[i];
+            nf += 1.0;
+        }
+    const double mass = block_sum(m), nfl = block_sum(nf);
+    const double target = (mass - nfl * rho_g) / (rho_l - rho_g);  // wanted sum of clamp(phi + delta, 0, 1)
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        double s = 0.0;
+        for (i64 i = t; i < n; i += 1024)
+            if (!(cls[i] & SOLID_BITS)) s += clamped(i, mid);
+        if (block_sum(s) < target) lo = mid;
+        else hi = mid;
+    }
+    const double delta = 0.5 * (lo + hi);
+    double s = 0.0;
+    for (i64 i = t; i < n; i += 1024)
+        if (!(cls[i] & SOLID_BITS)) s += clamped(i, delta);
+    const double got = block_sum(s);
+    const double scale = got > 0.0 ? target / got : 1.0;
+    double mw = 0.0;
+    for (i64 i = t; i < n; i += 1024) {
+        R r = R(0);
+        if (!(cls[i] & SOLID_BITS)) {
+            r = (R)(rho_g + (rho_l - rho_g) * scale * clamped(i, delta));
+            mw += (double)r;
+        }
+        rho[i] = r;
+    }
+    const double written = block_sum(mw);
+    if (t == 0) {
+        out[0] = mass;
+        out[1] = written;
+        out[2] = delta;
+        out[3] = scale;
+        out[4] = nfl;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Network state
+// ---------------------------------------------------------------------------
+struct Param {
+    i64 n = 0, off = 0;
+};
+
+struct Conv {  // 3x3 conv + ReLU over [Ci1 | Ci2] input channels
+    int Ci1, Ci2, Co;
+    int Cp;  // input channels of the BF16 weight copy (Ci1 + Ci2, or the padded network input)
+    Param w, b;
+    bf16* wb = nullptr;  // BF16 [Co][9][Cp]
+};
+
+struct Up {  // 2x2 stride-2 transposed convolution, weights [4 Co][Ci]
+    int Ci, Co;
+    Param w, b;
+    bf16* wb = nullptr;
+};
+
+struct Act {  // an activation and its gradient, BF16 NHWC
+    bf16* x = nullptr;
+    bf16* d = nullptr;
+};
+
+}  // namespace
+
+struct lbm_unet {
+    lbm_unet_config cfg{};
+    std::string err;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int H = 0, W = 0, B = 0, L = 0, C0 = 0, Cin = 0, Cinp = 0;
+    int nb = 0;  // samples in the current call
+    std::vector<Conv> enc, dec;
+    std::vector<Up> up;
+    Param hw, hb;
+    i64 nparam = 0;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    std::vector<Act> c1, c2, pool, upo, d1, d2;
+    std::vector<uint8_t*> arg;
+    bf16* x0 = nullptr;  // BF16 input, channels padded
+    float *y = nullptr, *dy = nullptr;
+    float* part = nullptr;
+    i64 part_n = 0;
+    float* hpart = nullptr;
+    double *lpart = nullptr, *loss = nullptr, *winfo = nullptr;
+    i64 step = 0;
+};
+
+namespace {
+
+constexpr int HEAD_BLOCKS = 512;
+constexpr int MSE_BLOCKS = 1024;
+
+lbm_status ufail(lbm_unet* u, lbm_status s, const std::string& msg) {
+    if (u) u->err = msg;
+    return s;
+}
+
+#define UCHK(u, call)                                                                                           \
+    do {                                                                                                        \
+        hipError_t e_ = (call);                                                                                 \
+        if (e_ != hipSuccess) return ufail(u, LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+Grid grid_of(const lbm_unet* u, int l) { return Grid{u->nb, u->H >> l, u->W >> l}; }
+i64 pixels(const lbm_unet* u, int l) { return (i64)u->nb * (u->H >> l) * (u->W >> l); }
+
+void refresh_bf16(lbm_unet* u) {
+    for (auto* layers : {&u->enc, &u->dec})
+        for (auto& c : *layers) {
+            const i64 rows = (i64)c.Co * 9;
+            k_cast_pad<<<blocks_for(rows * c.Cp), 256, 0, u->stream>>>(u->w + c.w.off, c.wb, rows, c.Ci1 + c.Ci2, c.Cp);
+        }
+    for (auto& p : u->up)
+        k_cast_pad<<<blocks_for(4LL * p.Co * p.Ci), 256, 0, u->stream>>>(u->w + p.w.off, p.wb, 4LL * p.Co, p.Ci, p.Ci);
+}
+
+// y = relu(conv3x3([x1 | x2]) + b); x1 holds C1 channels (Cp - Ci2 of them)
+void conv_fwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, bf16* y, int l) {
+    const i64 P = pixels(u, l);
+    Im2col A{x1, x2, nullptr, grid_of(u, l), c.Cp - c.Ci2, c.Ci2, 0};
+    RowsK B{c.wb, 9LL * c.Cp};
+    EpiBiasRelu e{y, u->w + c.b.off, P, c.Co};
+    gemm(u->stream, A, B, e, P, c.Co, 9LL * c.Cp);
+}
+
+// backward of y = relu(conv3x3([x1 | x2]) + b): weight and bias gradients into
+// g; data gradients written to dx1 / dx2 when dx1 is set
+void conv_bwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const bf16* y, const bf16* dy, bf16* dx1,
+              bf16* dx2, int l) {
+    const i64 P = pixels(u, l);
+    const Grid g = grid_of(u, l);
+    if (dx1) {
+        Im2col A{dy, nullptr, y, g, c.Co, 0, 1};
+        ConvWT B{c.wb, c.Co, c.Cp};
+        EpiSplit e{dx1, dx2, P, c.Ci1, c.Ci2};
+        gemm(u->stream, A, B, e, P, (i64)c.Ci1 + c.Ci2, 9LL * c.Co);
+    }
+    const i64 N1 = 9LL * c.Cp + 1;
+    DYmasked A2{dy, y, c.Co};
+    Im2colOnes B2{Im2col{x1, x2, nullptr, g, c.Cp - c.Ci2, c.Ci2, 0}, 9LL * c.Cp};
+    const int z = splits_for(c.Co, N1, P, u->part_n);
+    EpiPartial e2{u->part, c.Co, N1};
+    launch_gemm<64, 64>(u->stream, A2, B2, e2, c.Co, N1, P, z);
+    k_reduce_conv<<<blocks_for((i64)c.Co * N1), 256, 0, u->stream>>>(u->part, nchunks(P, z), c.Co, c.Cp, c.Ci1 + c.Ci2,
+                                                                     u->g + c.w.off, u->g + c.b.off);
+}
+
+void up_fwd(lbm_unet* u, const Up& p, const bf16* x, bf16* y, int lin) {
+    const i64 P = pixels(u, lin);
+    RowsKA A{x, p.Ci};
+    RowsK B{p.wb, p.Ci};
+    EpiUp e{y, u->w + p.b.off, UpMap{grid_of(u, lin)}, P, p.Co};
+    gemm(u->stream, A, B, e, P, 4LL * p.Co, p.Ci);
+}
+
+void up_bwd(lbm_unet* u, const Up& p, const bf16* x, const bf16* dy, bf16* dx, int lin) {
+    const i64 P = pixels(u, lin);
+    const UpMap um{grid_of(u, lin)};
+    UpGatherK A{dy, um, p.Co};
+    RowsN B{p.wb, p.Ci};
+    EpiSplit e{dx, nullptr, P, p.Ci, 0};
+    gemm(u->stream, A, B, e, P, p.Ci, 4LL * p.Co);
+    const i64 N1 = p.Ci + 1;
+    UpGatherM A2{dy, um, p.Co};
+    ColsOnes B2{x, p.Ci};
+    const int z = splits_for(4LL * p.Co, N1, P, u->part_n);
+    EpiPartial e2{u->part, 4LL * p.Co, N1};
+    launch_gemm<64, 64>(u->stream, A2, B2, e2, 4LL * p.Co, N1, P, z);
+    k_reduce_up<<<blocks_for(4LL * p.Co * p.Ci + p.Co), 256, 0, u->stream>>>(u->part, nchunks(P, z), p.Co, p.Ci,
+                                                                              u->g + p.w.off, u->g + p.b.off);
+}
+
+void forward(lbm_unet* u) {
+    const int L = u->L;
+    const bf16* in = u->x0;
+    for (int l = 0; l < L; ++l) {
+        conv_fwd(u, u->enc[2 * l], in, nullptr, u->c1[l].x, l);
+        conv_fwd(u, u->enc[2 * l + 1], u->c1[l].x, nullptr, u->c2[l].x, l);
+        if (l < L - 1) {
+            const int C = u->enc[2 * l].Co;
+            const i64 n = pixels(u, l + 1) * C;
+            k_pool_fwd<<<blocks_for(n), 256, 0, u->stream>>>(u->c2[l].x, u->pool[l].x, u->arg[l], grid_of(u, l), C);
+            in = u->pool[l].x;
+        }
+    }
+    const bf16* x = u->c2[L - 1].x;
+    for (int j = 0; j < L - 1; ++j) {
+        const int l = L - 2 - j;  // output level
+        up_fwd(u, u->up[j], x, u->upo[j].x, l + 1);
+        conv_fwd(u, u->dec[2 * j], u->upo[j].x, u->c2[l].x, u->d1[j].x, l);
+        conv_fwd(u, u->dec[2 * j + 1], u->d1[j].x, nullptr, u->d2[j].x, l);
+        x = u->d2[j].x;
+    }
+    const i64 P0 = pixels(u, 0);
+    k_head_fwd<<<blocks_for(P0), 256, 0, u->stream>>>(x, u->w + u->hw.off, u->w + u->hb.off, u->y, P0, u->C0);
+}
+
+void backward(lbm_unet* u) {
+    const int L = u->L;
+    const i64 P0 = pixels(u, 0);
+    const Act& last = L > 1 ? u->d2[L - 2] : u->c2[0];
+    k_head_bwd_x<<<blocks_for(P0 * u->C0), 256, 0, u->stream>>>(u->dy, u->w + u->hw.off, last.d, P0, u->C0);
+    k_head_bwd_w<<<HEAD_BLOCKS, 256, 0, u->stream>>>(u->dy, last.x, P0, u->C0, u->hpart);
+    k_head_reduce<<<1, 512, 0, u->stream>>>(u->hpart, HEAD_BLOCKS, u->C0, u->g + u->hw.off, u->g + u->hb.off);
+    for (int j = L - 2; j >= 0; --j) {
+        const int l = L - 2 - j;
+        const Conv& a = u->dec[2 * j];
+        const Conv& b = u->dec[2 * j + 1];
+        conv_bwd(u, b, u->d1[j].x, nullptr, u->d2[j].x, u->d2[j].d, u->d1[j].d, nullptr, l);
+        // the first decoder convolution reads [up | skip]: its data gradient
+        // splits into d(up) and the skip part of d(c2) (written here, added to below)
+        conv_bwd(u, a, u->upo[j].x, u->c2[l].x, u->d1[j].x, u->d1[j].d, u->upo[j].d, u->c2[l].d, l);
+        const Act& xin = j == 0 ? u->c2[L - 1] : u->d2[j - 1];
+        up_bwd(u, u->up[j], xin.x, u->upo[j].d, xin.d, l + 1);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const Conv& a = u->enc[2 * l];
+        const Conv& b = u->enc[2 * l + 1];
+        if (l < L - 1) {
+            const i64 n = pixels(u, l + 1) * a.Co;
+            k_pool_bwd<<<blocks_for(n), 256, 0, u->stream>>>(u->pool[l].d, u->arg[l], u->c2[l].d, grid_of(u, l), a.Co);
+        }
+        conv_bwd(u, b, u->c1[l].x, nullptr, u->c2[l].x, u->c2[l].d, u->c1[l].d, nullptr, l);
+        const bf16* xin = l == 0 ? u->x0 : u->pool[l - 1].x;
+        conv_bwd(u, a, xin, nullptr, u->c1[l].x, u->c1[l].d, l == 0 ? nullptr : u->pool[l - 1].d, nullptr, l);
+    }
+}
+
+lbm_status load_input(lbm_unet* u, const float* x, int n) {
+    if (n < 1 || n > u->B) return ufail(u, LBM_E_ARG, "sample count must be in 1..batch");
+    u->nb = n;
+    const i64 P = pixels(u, 0);
+    k_cast_pad<<<blocks_for(P * u->Cinp), 256, 0, u->stream>>>(x, u->x0, P, u->Cin, u->Cinp);
+    return LBM_OK;
+}
+
+lbm_status fwd_bwd(lbm_unet* u, const float* x, const float* t, int n, double* loss) {
+    lbm_status s = load_input(u, x, n);
+    if (s) return s;
+    forward(u);
+    const i64 np = pixels(u, 0);
+    k_mse<<<MSE_BLOCKS, 256, 0, u->stream>>>(u->y, t, np, u->dy, u->lpart);
+    k_sum_parts<<<1, 64, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
+    backward(u);
+    UCHK(u, hipGetLastError());
+    if (loss) UCHK(u, hipMemcpyAsync(loss, u->loss, 8, hipMemcpyDeviceToHost, u->stream));
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_unet_last_error(const lbm_unet* u) { return u ? u->err.c_str() : "null network"; }
+
+void lbm_unet_config_default(lbm_unet_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->H = 256;
+    c->W = 256;
+    c->batch = 8;
+    c->in_channels = 3;
+    c->base_channels = 32;
+    c->levels = 4;
+    c->lr = 1e-3;
+    c->beta1 = 0.9;
+    c->beta2 = 0.999;
+    c->eps = 1e-8;
+    c->stream = nullptr;
+}
+
+lbm_status lbm_unet_destroy(lbm_unet* u) {
+    if (!u) return LBM_OK;
+    if (u->stream) (void)hipStreamSynchronize(u->stream);
+    auto fr = [](void* p) {
+        if (p) (void)hipFree(p);
+    };
+    for (auto* layers : {&u->enc, &u->dec})
+        for (auto& c : *layers) fr(c.wb);
+    for (auto& p : u->up) fr(p.wb);
+    for (auto* acts : {&u->c1, &u->c2, &u->pool, &u->upo, &u->d1, &u->d2})
+        for (auto& a : *acts) {
+            fr(a.x);
+            fr(a.d);
+        }
+    for (auto p : u->arg) fr(p);
+    for (void* p : {(void*)u->w, (void*)u->g, (void*)u->m, (void*)u->v, (void*)u->x0, (void*)u->y, (void*)u->dy,
+                    (void*)u->part, (void*)u->hpart, (void*)u->lpart, (void*)u->loss, (void*)u->winfo})
+        fr(p);
+    if (u->own_stream && u->stream) (void)hipStreamDestroy(u->stream);
+    delete u;
+    return LBM_OK;
+}
+
+lbm_status lbm_unet_create(const lbm_unet_config* cfg, lbm_unet** out) {
+    if (!out || !cfg) return LBM_E_ARG;
+    *out = nullptr;
+    const int L = cfg->levels, C0 = cfg->base_channels;
+    if (L < 1 || L > 6 || C0 < 8 || C0 > 128 || C0 % 8 || 256 % C0 || cfg->batch < 1 || cfg->in_channels < 1 ||
+        cfg->in_channels > CPAD || cfg->H < 1 || cfg->W < 1 || cfg->H % (1 << (L - 1)) || cfg->W % (1 << (L - 1)) ||
+        !(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) ||
+        !(cfg->eps > 0))
+        return LBM_E_ARG;
+    if ((i64)cfg->batch * cfg->H * cfg->W * C0 > (1LL << 36)) return LBM_E_ARG;
+    lbm_unet* u = new (std::nothrow) lbm_unet();
+    if (!u) return LBM_E_NOMEM;
+    u->cfg = *cfg;
+    u->H = cfg->H;
+    u->W = cfg->W;
+    u->B = cfg->batch;
+    u->L = L;
+    u->C0 = C0;
+    u->Cin = cfg->in_channels;
+    u->Cinp = CPAD;
+    if (cfg->stream) {
+        u->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&u->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete u;
+            return LBM_E_DEVICE;
+        }
+        u->own_stream = true;
+    }
+    // parameters in the order lbm.h documents for lbm_unet_get_params
+    i64 off = 0;
+    auto param = [&](i64 n) {
+        Param p;
+        p.n = n;
+        p.off = off;
+        off += n;
+        return p;
+    };
+    int ci = u->Cin, cip = u->Cinp;
+    for (int l = 0; l < L; ++l) {
+        const int co = C0 << l;
+        for (int k = 0; k < 2; ++k) {
+            Conv c;
+            c.Ci1 = k == 0 ? ci : co;
+            c.Ci2 = 0;
+            c.Co = co;
+            c.Cp = k == 0 ? cip : co;
+            c.w = param((i64)co * 9 * c.Ci1);
+            c.b = param(co);
+            u->enc.push_back(c);
+        }
+        ci = cip = co;
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        const int co = C0 << l;
+        Up p;
+        p.Ci = 2 * co;
+        p.Co = co;
+        p.w = param(4LL * co * p.Ci);
+        p.b = param(co);
+        u->up.push_back(p);
+        for (int k = 0; k < 2; ++k) {
+            Conv c;
+            c.Ci1 = co;
+            c.Ci2 = k == 0 ? co : 0;
+            c.Co = co;
+            c.Cp = c.Ci1 + c.Ci2;
+            c.w = param((i64)co * 9 * c.Cp);
+            c.b = param(co);
+            u->dec.push_back(c);
+        }
+    }
+    u->hw = param(C0);
+    u->hb = param(1);
+    u->nparam = off;
+
+    bool ok = true;
+    auto dalloc = [&](void** p, i64 bytes) {
+        ok = ok && hipMalloc(p, (size_t)std::max<i64>(bytes, 16)) == hipSuccess;
+    };
+    const i64 P0 = (i64)u->B * u->H * u->W;
+    dalloc((void**)&u->w, off * 4);
+    dalloc((void**)&u->g, off * 4);
+    dalloc((void**)&u->m, off * 4);
+    dalloc((void**)&u->v, off * 4);
+    dalloc((void**)&u->x0, P0 * u->Cinp * 2);
+    dalloc((void**)&u->y, P0 * 4);
+    dalloc((void**)&u->dy, P0 * 4);
+    dalloc((void**)&u->hpart, (i64)HEAD_BLOCKS * (C0 + 1) * 4);
+    dalloc((void**)&u->lpart, MSE_BLOCKS * 8);
+    dalloc((void**)&u->loss, 8);
+    dalloc((void**)&u->winfo, 8 * 8);
+    for (auto* layers : {&u->enc, &u->dec})
+        for (auto& c : *layers) dalloc((void**)&c.wb, (i64)c.Co * 9 * c.Cp * 2);
+    for (auto& p : u->up) dalloc((void**)&p.wb, 4LL * p.Co * p.Ci * 2);
+    auto act = [&](i64 n) {
+        Act a;
+        dalloc((void**)&a.x, n * 2);
+        dalloc((void**)&a.d, n * 2);
+        return a;
+    };
+    for (int l = 0; l < L; ++l) {
+        const i64 P = (i64)u->B * (u->H >> l) * (u->W >> l);
+        const int co = C0 << l;
+        u->c1.push_back(act(P * co));
+        u->c2.push_back(act(P * co));
+        if (l < L - 1) {
+            const i64 Pn = (i64)u->B * (u->H >> (l + 1)) * (u->W >> (l + 1));
+            u->pool.push_back(act(Pn * co));
+            uint8_t* a = nullptr;
+            dalloc((void**)&a, Pn * co);
+            u->arg.push_back(a);
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        const i64 P = (i64)u->B * (u->H >> l) * (u->W >> l);
+        const int co = C0 << l;
+        u->upo.push_back(act(P * co));
+        u->d1.push_back(act(P * co));
+        u->d2.push_back(act(P * co));
+    }
+    i64 maxw = 0;
+    for (auto* layers : {&u->enc, &u->dec})
+        for (auto& c : *layers) maxw = std::max<i64>(maxw, (i64)c.Co * (9LL * c.Cp + 1));
+    for (auto& p : u->up) maxw = std::max<i64>(maxw, 4LL * p.Co * (p.Ci + 1));
+    u->part_n = std::max<i64>(maxw * 8, (i64)16 << 20);
+    dalloc((void**)&u->part, u->part_n * 4);
+    if (!ok) {
+        (void)hipGetLastError();
+        lbm_unet_destroy(u);
+        return LBM_E_NOMEM;
+    }
+    for (float* p : {u->w, u->g, u->m, u->v}) k_fill_f32<<<blocks_for(off), 256, 0, u->stream>>>(p, off, 0.f);
+    refresh_bf16(u);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(u->stream) != hipSuccess) {
+        lbm_unet_destroy(u);
+        return LBM_E_DEVICE;
+    }
+    *out = u;
+    return LBM_OK;
+}
+
+int64_t lbm_unet_param_count(const lbm_unet* u) { return u ? u->nparam : 0; }
+
+lbm_status lbm_unet_set_params(lbm_unet* u, const float* p, int64_t n, int on_device) {
+    if (!u || !p) return u ? ufail(u, LBM_E_ARG, "set_params: null pointer") : LBM_E_ARG;
+    if (n != u->nparam) return ufail(u, LBM_E_ARG, "set_params: count differs from lbm_unet_param_count");
+    UCHK(u, hipMemcpyAsync(u->w, p, (size_t)n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           u->stream));
+    k_fill_f32<<<blocks_for(n), 256, 0, u->stream>>>(u->m, n, 0.f);
+    k_fill_f32<<<blocks_for(n), 256, 0, u->stream>>>(u->v, n, 0.f);
+    u->step = 0;
+    refresh_bf16(u);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_unet_get_params(lbm_unet* u, float* p, int64_t n, int which, int on_device) {
+    if (!u || !p) return u ? ufail(u, LBM_E_ARG, "get_params: null pointer") : LBM_E_ARG;
+    if (n != u->nparam) return ufail(u, LBM_E_ARG, "get_params: count differs from lbm_unet_param_count");
+    const float* src = which == LBM_UNET_WEIGHTS ? u->w : which == LBM_UNET_GRADS ? u->g : nullptr;
+    if (!src) return ufail(u, LBM_E_ARG, "get_params: which must be LBM_UNET_WEIGHTS or LBM_UNET_GRADS");
+    UCHK(u, hipMemcpyAsync(p, src, (size_t)n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           u->stream));
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_unet_forward(lbm_unet* u, const float* x, float* y, int n) {
+    if (!u || !x || !y) return u ? ufail(u, LBM_E_ARG, "forward: null pointer") : LBM_E_ARG;
+    lbm_status s = load_input(u, x, n);
+    if (s) return s;
+    forward(u);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipMemcpyAsync(y, u->y, (size_t)pixels(u, 0) * 4, hipMemcpyDeviceToDevice, u->stream));
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_unet_backward(lbm_unet* u, const float* x, const float* target, int n, double* loss) {
+    if (!u || !x || !target) return u ? ufail(u, LBM_E_ARG, "backward: null pointer") : LBM_E_ARG;
+    return fwd_bwd(u, x, target, n, loss);
+}
+
+lbm_status lbm_unet_train_step(lbm_unet* u, const float* x, const float* target, int n, double* loss) {
+    if (!u || !x || !target) return u ? ufail(u, LBM_E_ARG, "train_step: null pointer") : LBM_E_ARG;
+    lbm_status s = fwd_bwd(u, x, target, n, loss);
+    if (s) return s;
+    u->step += 1;
+    const double b1 = u->cfg.beta1, b2 = u->cfg.beta2;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)u->step));
+    const float c2 = (float)(1.0 - std::pow(b2, (double)u->step));
+    k_adam<<<blocks_for(u->nparam), 256, 0, u->stream>>>(u->w, u->g, u->m, u->v, u->nparam, (float)u->cfg.lr,
+                                                         (float)b1, (float)b2, (float)u->cfg.eps, c1, c2);
+    refresh_bf16(u);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_unet_set_lr(lbm_unet* u, double lr) {
+    if (!u) return LBM_E_ARG;
+    if (!(lr > 0)) return ufail(u, LBM_E_ARG, "set_lr: the rate must be positive");
+    u->cfg.lr = lr;
+    return LBM_OK;
+}
+
+lbm_status lbm_unet_encode(const uint8_t* cls, int64_t n, double solid_value, double plane, float* x, void* stream) {
+    if (!cls || !x || n < 1) return LBM_E_ARG;
+    k_encode<<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(cls, n, (float)solid_value, (float)plane, x);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, int64_t n, double rho_g, double rho_l,
+                           float* phi, void* stream) {
+    if (!rho || !cls || !phi || n < 1 || !(rho_l > rho_g)) return LBM_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == LBM_F64)
+        k_target<double><<<blocks_for(n), 256, 0, s>>>((const double*)rho, cls, n, rho_g, rho_l, phi);
+    else if (precision == LBM_F32 || precision == LBM_F32_MIXED)
+        k_target<float><<<blocks_for(n), 256, 0, s>>>((const float*)rho, cls, n, rho_g, rho_l, phi);
+    else
+        return LBM_E_ARG;
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int64_t n,
+                             int precision, double rho_g, double rho_l, void* rho_out, double* info) {
+    if (!u) return LBM_E_ARG;
+    if (!phi || !rho_ref || !cls || !rho_out || n < 1 || !(rho_l > rho_g))
+        return ufail(u, LBM_E_ARG, "warm_rho: null pointer, empty field or rho_l <= rho_g");
+    if (precision == LBM_F64)
+        k_warm_rho<double><<<1, 1024, 0, u->stream>>>(phi, (const double*)rho_ref, cls, n, rho_g, rho_l,
+                                                      (double*)rho_out, u->winfo);
+    else if (precision == LBM_F32 || precision == LBM_F32_MIXED)
+        k_warm_rho<float><<<1, 1024, 0, u->stream>>>(phi, (const float*)rho_ref, cls, n, rho_g, rho_l, (float*)rho_out,
+                                                     u->winfo);
+    else
+        return ufail(u, LBM_E_ARG, "warm_rho: unknown precision");
+    double h[5];
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipMemcpyAsync(h, u->winfo, sizeof h, hipMemcpyDeviceToHost, u->stream));
+    UCHK(u, hipStreamSynchronize(u->stream));
+    if (info) std::memcpy(info, h, sizeof h);
+    const double target = (h[0] - h[4] * rho_g) / (rho_l - rho_g);
+    if (!(target > 0.0 && target < h[4]))
+        return ufail(u, LBM_E_ARG, "warm_rho: the reference mass is outside (n_fluid rho_g, n_fluid rho_l)");
+    return LBM_OK;
+}
+
+}  // extern "C"

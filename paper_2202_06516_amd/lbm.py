@@ -92,6 +92,15 @@ class lbm_batch_opts(C.Structure):
     _fields_ = [("autotune", C.c_int), ("tile_w", C.c_int), ("blocks_per_cu", C.c_int), ("cache_path", C.c_char_p)]
 
 
+class lbm_unet_config(C.Structure):
+    _fields_ = [("H", C.c_int), ("W", C.c_int), ("batch", C.c_int), ("in_channels", C.c_int),
+                ("base_channels", C.c_int), ("levels", C.c_int), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("stream", C.c_void_p)]
+
+
+LBM_UNET_WEIGHTS, LBM_UNET_GRADS = 0, 1
+
+
 class lbm_batch_info(C.Structure):
     _fields_ = [("total_nodes", C.c_int64), ("fluid_nodes", C.c_int64), ("ncases", C.c_int32), ("tile_w", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("n_items", C.c_int32), ("tune_ms_per_step", C.c_double),
@@ -105,7 +114,11 @@ EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
            "lbm_get_info", "lbm_profile_step", "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy",
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read",
-           "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_last_error")
+           "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_last_error",
+           "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
+           "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_backward",
+           "lbm_unet_train_step", "lbm_unet_set_lr", "lbm_unet_encode", "lbm_unet_target", "lbm_unet_warm_rho",
+           "lbm_unet_last_error")
 
 
 def lib():
@@ -145,6 +158,27 @@ def lib():
     L.lbm_batch_tune.argtypes = [vp, C.c_char_p]
     L.lbm_batch_last_error.restype = C.c_char_p
     L.lbm_batch_last_error.argtypes = [vp]
+    L.lbm_unet_config_default.restype = None
+    L.lbm_unet_config_default.argtypes = [P(lbm_unet_config)]
+    L.lbm_unet_create.argtypes = [P(lbm_unet_config), P(vp)]
+    L.lbm_unet_destroy.argtypes = [vp]
+    L.lbm_unet_param_count.restype = i64
+    L.lbm_unet_param_count.argtypes = [vp]
+    L.lbm_unet_set_params.argtypes = [vp, vp, i64, i]
+    L.lbm_unet_get_params.argtypes = [vp, vp, i64, i, i]
+    L.lbm_unet_forward.argtypes = [vp, vp, vp, i]
+    L.lbm_unet_backward.argtypes = [vp, vp, vp, i, P(d)]
+    L.lbm_unet_train_step.argtypes = [vp, vp, vp, i, P(d)]
+    L.lbm_unet_set_lr.argtypes = [vp, d]
+    L.lbm_unet_encode.argtypes = [vp, i64, d, d, vp, vp]
+    L.lbm_unet_target.argtypes = [vp, i, vp, i64, d, d, vp, vp]
+    L.lbm_unet_warm_rho.argtypes = [vp, vp, vp, vp, i64, i, d, d, vp, P(d)]
+    L.lbm_unet_last_error.restype = C.c_char_p
+    L.lbm_unet_last_error.argtypes = [vp]
+    for name in ("lbm_unet_create", "lbm_unet_destroy", "lbm_unet_set_params", "lbm_unet_get_params",
+                 "lbm_unet_forward", "lbm_unet_backward", "lbm_unet_train_step", "lbm_unet_set_lr",
+                 "lbm_unet_encode", "lbm_unet_target", "lbm_unet_warm_rho"):
+        getattr(L, name).restype = C.c_int
     for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
                  "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
                  "lbm_get_info", "lbm_profile_step", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_step",
@@ -415,6 +449,10 @@ class Batch:
         a = np.ascontiguousarray(rho, dtype=self.dtype)
         self._check(lib().lbm_batch_write(self._h, case, FIELD_RHO, a.ctypes.data, a.nbytes, 0))
 
+    def read_device(self, case, field, ptr, nbytes):
+        """Copy one case's field into device memory at ptr."""
+        self._check(lib().lbm_batch_read(self._h, case, field, C.c_void_p(ptr), nbytes, 1))
+
     def write_rho_device(self, case, ptr, nbytes):
         self._check(lib().lbm_batch_write(self._h, case, FIELD_RHO, C.c_void_p(ptr), nbytes, 1))
 
@@ -425,6 +463,96 @@ class Batch:
 
     def tune(self, cache_path=None):
         self._check(lib().lbm_batch_tune(self._h, cache_path.encode() if cache_path else None))
+
+
+class Unet:
+    """The warm-start U-Net (lbm_unet_*): device pointers in, device pointers out.
+
+    Arrays are passed as integer device addresses (for instance
+    ``tensor.data_ptr()`` of a contiguous torch tensor on the GPU) or, for
+    parameters, as host numpy arrays.
+    """
+
+    def __init__(self, H=256, W=256, batch=8, in_channels=3, base_channels=32, levels=4, lr=1e-3,
+                 beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        cfg = lbm_unet_config()
+        lib().lbm_unet_config_default(C.byref(cfg))
+        cfg.H, cfg.W, cfg.batch, cfg.in_channels = H, W, batch, in_channels
+        cfg.base_channels, cfg.levels = base_channels, levels
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, beta1, beta2, eps
+        if stream is not None:
+            cfg.stream = stream
+        self.cfg = cfg
+        h = C.c_void_p()
+        st = lib().lbm_unet_create(C.byref(cfg), C.byref(h))
+        if st != 0:
+            raise LbmError(st, "lbm_unet_create failed")
+        self._h = h
+        self.n_params = int(lib().lbm_unet_param_count(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise LbmError(st, lib().lbm_unet_last_error(self._h).decode())
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {a.size}")
+        self._check(lib().lbm_unet_set_params(self._h, a.ctypes.data, a.size, 0))
+
+    def params(self, which=LBM_UNET_WEIGHTS):
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(lib().lbm_unet_get_params(self._h, out.ctypes.data, out.size, which, 0))
+        return out
+
+    def grads(self):
+        return self.params(LBM_UNET_GRADS)
+
+    def forward(self, x_ptr, y_ptr, n):
+        self._check(lib().lbm_unet_forward(self._h, C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(n)))
+
+    def backward(self, x_ptr, t_ptr, n):
+        loss = C.c_double()
+        self._check(lib().lbm_unet_backward(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(n), C.byref(loss)))
+        return loss.value
+
+    def train_step(self, x_ptr, t_ptr, n):
+        loss = C.c_double()
+        self._check(lib().lbm_unet_train_step(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(n),
+                                              C.byref(loss)))
+        return loss.value
+
+    def set_lr(self, lr):
+        self._check(lib().lbm_unet_set_lr(self._h, float(lr)))
+
+    def warm_rho(self, phi_ptr, rho_ref_ptr, cls_ptr, n, precision, rho_g, rho_l, rho_out_ptr):
+        info = (C.c_double * 5)()
+        self._check(lib().lbm_unet_warm_rho(self._h, C.c_void_p(phi_ptr), C.c_void_p(rho_ref_ptr),
+                                            C.c_void_p(cls_ptr), int(n), int(precision), float(rho_g),
+                                            float(rho_l), C.c_void_p(rho_out_ptr), info))
+        return dict(mass_ref=info[0], mass_written=info[1], delta=info[2], scale=info[3], n_fluid=info[4])
+
+
+def unet_encode(cls_ptr, n, solid_value, plane, x_ptr, stream=None):
+    st = lib().lbm_unet_encode(C.c_void_p(cls_ptr), int(n), float(solid_value), float(plane), C.c_void_p(x_ptr),
+                               C.c_void_p(stream) if stream else None)
+    if st != 0:
+        raise LbmError(st, "lbm_unet_encode failed")
+
+
+def unet_target(rho_ptr, precision, cls_ptr, n, rho_g, rho_l, phi_ptr, stream=None):
+    st = lib().lbm_unet_target(C.c_void_p(rho_ptr), int(precision), C.c_void_p(cls_ptr), int(n), float(rho_g),
+                               float(rho_l), C.c_void_p(phi_ptr), C.c_void_p(stream) if stream else None)
+    if st != 0:
+        raise LbmError(st, "lbm_unet_target failed")
 
 
 def angle_dict(a):

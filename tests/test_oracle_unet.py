@@ -189,3 +189,27 @@ def test_encode_and_target_definitions():
     rho = np.array([1.0, 9.0, 9.0, 9.0, 0.5, 3.0])
     t = U.target(rho, cls, 0.5, 3.0)
     assert np.allclose(t, [0.2, 0, 0, 0, 0.0, 1.0])
+
+
+def test_bf16_rounding_equals_torch_cpu_cast():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(8)
+    a = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-6, 6, 10000),
+                        # exact midpoints between neighbouring bfloat16 values, both parities
+                        ((rng.integers(0x0080, 0x7F00, 2000).astype(np.uint32) << 16) + 0x8000)
+                        .view(np.float32),
+                        np.array([0.0, -0.0, 1.0, -3.5, 65504.0, 1e-30])]).astype(np.float32)
+    ref = torch.tensor(a).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    assert np.array_equal(U.bf16(a), ref)
+
+
+def test_bf16_storage_forward_stays_close_to_fp64():
+    rng = np.random.default_rng(9)
+    th = U.init_params(rng, 3, 8, 3)
+    x = rng.standard_normal((2, 16, 16, 3))
+    y64, _ = U.forward(th, x, 3, 8)
+    y16, c = U.forward(th, x, 3, 8, storage="bf16")
+    assert np.linalg.norm(y16 - y64) <= 2e-2 * np.linalg.norm(y64)
+    for k, v in c.items():
+        if isinstance(v, np.ndarray) and k.endswith((".a", ".b", ".cat")):
+            assert np.array_equal(v, U.bf16(v)), k
