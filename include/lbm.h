@@ -295,10 +295,11 @@ const char* lbm_batch_last_error(const lbm_batch* b);
 /* ------------------------------------------------------------------------
  * Learned warm start
  *
- * A convolutional U-Net maps three planes of a 2-D lattice (channel 0: 1 on
- * solid nodes; channel 1: a value on solid nodes, the scaled wall chemical
- * potential; channel 2: a constant, the scaled drop volume) to
- * phi = (rho - rho_g) / (rho_l - rho_g) of the equilibrated drop.  Its output,
+ * A convolutional U-Net maps planes of a 2-D lattice (channel 0: 1 on solid
+ * nodes; channel 1: a value on solid nodes, the scaled wall chemical
+ * potential; channel 2: a constant, the scaled drop volume; channel 3: phi of
+ * the cold initial state of Eq. 16) to phi = (rho - rho_g) / (rho_l - rho_g)
+ * of the equilibrated drop.  Its output,
  * made mass-exact by lbm_unet_warm_rho, replaces the initial density of
  * Eq. 16 through lbm_write / lbm_batch_write (RHO).  This is an extension:
  * the paper initialises every run with Eq. 16 (Sec. IV).
@@ -354,6 +355,8 @@ lbm_status lbm_unet_set_params(lbm_unet* u, const float* p, int64_t n, int src_o
 lbm_status lbm_unet_get_params(lbm_unet* u, float* p, int64_t n, int which, int dst_on_device);
 /* y = network(x) for n samples (1 <= n <= batch); x, y on the device.  Synchronises. */
 lbm_status lbm_unet_forward(lbm_unet* u, const float* x, float* y, int n);
+/* Forward and the loss against target (device) only; loss (host). */
+lbm_status lbm_unet_loss(lbm_unet* u, const float* x, const float* target, int n, double* loss);
 /* Forward, loss against target (device), and gradients of every parameter; loss (host, nullable). */
 lbm_status lbm_unet_backward(lbm_unet* u, const float* x, const float* target, int n, double* loss);
 /* lbm_unet_backward, then one Adam step with bias correction. */
@@ -361,22 +364,28 @@ lbm_status lbm_unet_train_step(lbm_unet* u, const float* x, const float* target,
 lbm_status lbm_unet_set_lr(lbm_unet* u, double lr);
 
 /* Input planes from a lattice's CLASS field (device, [n] uint8): x[i] =
- * {solid, solid ? solid_value : 0, plane} (x device FP32 [n][3]).  Enqueues on stream. */
-lbm_status lbm_unet_encode(const uint8_t* cls, int64_t n, double solid_value, double plane, float* x, void* stream);
+ * {solid, solid ? solid_value : 0, plane} (x device FP32 [n][3]), and with
+ * phi0 (device [n], nullable; the phi of the cold initial state) a fourth
+ * channel phi0[i] (x [n][4]).  Enqueues on stream. */
+lbm_status lbm_unet_encode(const uint8_t* cls, const float* phi0, int64_t n, double solid_value, double plane,
+                           float* x, void* stream);
 /* Training target from a density field (device, elem of precision): phi =
  * (rho - rho_g) / (rho_l - rho_g) on fluid nodes, 0 on solid nodes.  Enqueues on stream. */
 lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, int64_t n, double rho_g, double rho_l,
                            float* phi, void* stream);
 /* Density for a warm start from a predicted phi (device [n]): fluid nodes get
- * rho_g + (rho_l - rho_g) s clamp(phi + delta, 0, 1), with delta (bisection)
- * and s (close to 1) chosen so that the fluid mass equals that of rho_ref
- * (the cold initial state), solid nodes 0; rho_out has the element type of
- * precision.  info (host, nullable, 5 doubles) = {reference mass, written
+ * rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1),
+ * with delta (bisection) and s (close to 1) chosen so that the fluid mass
+ * equals that of rho_ref (the cold initial state), solid nodes 0; rho_out has
+ * the element type of precision.  cut in [0, 0.25) sends predictions within
+ * cut of pure gas or liquid to exactly rho_g or rho_l (the gas density is
+ * about a hundredth of the liquid's, so small errors in phi would otherwise
+ * move it far).  info (host, nullable, 5 doubles) = {reference mass, written
  * mass, delta, s, fluid nodes}.  Runs on the network's stream; synchronises.
- * LBM_E_ARG if the reference mass is not strictly between n_fluid rho_g and
- * n_fluid rho_l. */
+ * LBM_E_ARG if cut is out of range or the reference mass is not strictly
+ * between n_fluid rho_g and n_fluid rho_l. */
 lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int64_t n,
-                             int precision, double rho_g, double rho_l, void* rho_out, double* info);
+                             int precision, double rho_g, double rho_l, double cut, void* rho_out, double* info);
 const char* lbm_unet_last_error(const lbm_unet* u);
 
 #ifdef __cplusplus

@@ -266,11 +266,13 @@ def adam_step(theta, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 # ---------------------------------------------------------------------------
 # lattice <-> network fields
 # ---------------------------------------------------------------------------
-def encode(cls, solid_value, plane):
-    """Input planes from a class field (low two bits nonzero = solid)."""
+def encode(cls, solid_value, plane, phi0=None):
+    """Input planes from a class field (low two bits nonzero = solid), and phi0 as a fourth if given."""
     s = (np.asarray(cls) & 3) != 0
-    return np.stack([s.astype(np.float64), np.where(s, solid_value, 0.0),
-                     np.full(s.shape, float(plane))], axis=-1)
+    planes = [s.astype(np.float64), np.where(s, solid_value, 0.0), np.full(s.shape, float(plane))]
+    if phi0 is not None:
+        planes.append(np.asarray(phi0, dtype=np.float64))
+    return np.stack(planes, axis=-1)
 
 
 def target(rho, cls, rho_g, rho_l):
@@ -278,24 +280,24 @@ def target(rho, cls, rho_g, rho_l):
     return np.where(s, 0.0, (np.asarray(rho, dtype=np.float64) - rho_g) / (rho_l - rho_g))
 
 
-def warm_rho(phi, rho_ref, cls, rho_g, rho_l):
-    """Mass-exact density from phi: rho_g + (rho_l - rho_g) s clamp(phi + delta, 0, 1) on fluid nodes.
+def warm_rho(phi, rho_ref, cls, rho_g, rho_l, cut=0.0):
+    """Mass-exact density from phi on fluid nodes:
+    rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1).
 
-    delta solves sum_fluid clamp(phi + delta, 0, 1) = (M - n_f rho_g) / (rho_l - rho_g),
-    M the fluid mass of rho_ref (found by scipy's brentq), and s = 1 up to
-    the root finder's residual.
+    delta solves sum_fluid clamp(...) = (M - n_f rho_g) / (rho_l - rho_g), M
+    the fluid mass of rho_ref (found by scipy's brentq), and s = 1 up to the
+    root finder's residual.
     """
     from scipy.optimize import brentq
     fl = (np.asarray(cls) & 3) == 0
     ph = np.asarray(phi, dtype=np.float64)[fl]
     M = float(np.asarray(rho_ref, dtype=np.float64)[fl].sum())
     want = (M - fl.sum() * rho_g) / (rho_l - rho_g)
-    f = lambda d: np.clip(ph + d, 0.0, 1.0).sum() - want
-    delta = brentq(f, -1.0, 1.0, xtol=1e-15, rtol=1e-15, maxiter=500)
-    got = np.clip(ph + delta, 0.0, 1.0).sum()
-    s = want / got
+    g = lambda d: np.clip((ph + d - cut) / (1.0 - 2.0 * cut), 0.0, 1.0)
+    delta = brentq(lambda d: g(d).sum() - want, -1.0, 1.0, xtol=1e-15, rtol=1e-15, maxiter=500)
+    s = want / g(delta).sum()
     out = np.zeros(np.shape(cls))
-    out[fl] = rho_g + (rho_l - rho_g) * s * np.clip(ph + delta, 0.0, 1.0)
+    out[fl] = rho_g + (rho_l - rho_g) * s * g(delta)
     return out, M, delta
 
 

@@ -24,10 +24,25 @@ HIP_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
+    """Compile every source to an object in parallel, then link liblbm.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    odir = os.path.join(HERE, "_lib", "obj")
+    os.makedirs(odir, exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    compile_flags = [f for f in HIP_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(odir, os.path.basename(src) + ".o")
+        cmd = ["hipcc", *compile_flags, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+        objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIP_FLAGS, "-o", tmp, *srcs]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fopenmp", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

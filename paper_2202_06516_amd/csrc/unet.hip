@@ -685,12 +685,16 @@ __global__ void k_fill_f32(float* __restrict__ p, i64 n, float v) {
 // ---------------------------------------------------------------------------
 constexpr uint8_t SOLID_BITS = 3;  // low two class bits: 0 fluid, 1..3 solid layers
 
-__global__ void k_encode(const uint8_t* __restrict__ cls, i64 n, float solid_value, float plane, float* __restrict__ x) {
+// x[i] = {solid, solid ? solid_value : 0, plane[, phi0[i]]} (3 or 4 channels)
+__global__ void k_encode(const uint8_t* __restrict__ cls, const float* __restrict__ phi0, i64 n, float solid_value,
+                         float plane, float* __restrict__ x) {
+    const int C = phi0 ? 4 : 3;
     GRID_STRIDE(i, n) {
         const bool s = (cls[i] & SOLID_BITS) != 0;
-        x[3 * i + 0] = s ? 1.f : 0.f;
-        x[3 * i + 1] = s ? solid_value : 0.f;
-        x[3 * i + 2] = plane;
+        x[C * i + 0] = s ? 1.f : 0.f;
+        x[C * i + 1] = s ? solid_value : 0.f;
+        x[C * i + 2] = plane;
+        if (phi0) x[C * i + 3] = phi0[i];
     }
 }
 
@@ -703,14 +707,14 @@ __global__ void k_target(const R* __restrict__ rho, const uint8_t* __restrict__ 
 }
 
 // One workgroup: the mass-exact density from a predicted phi.  Fluid nodes get
-// rho = rho_g + (rho_l - rho_g) s clamp(phi + delta, 0, 1) with delta found by
-// bisection so that the fluid mass equals that of rho_ref, and s (close to 1)
-// removing what the bisection leaves; solid nodes get 0.
-// out = {mass of rho_ref, mass written, delta, s, fluid nodes}.
+// rho = rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1)
+// with delta found by bisection so that the fluid mass equals that of
+// rho_ref, and s (close to 1) removing what the bisection leaves; solid nodes
+// get 0.  out = {mass of rho_ref, mass written, delta, s, fluid nodes}.
 template <typename R>
 __global__ void __launch_bounds__(1024) k_warm_rho(const float* __restrict__ phi, const R* __restrict__ rho_ref,
                                                    const uint8_t* __restrict__ cls, i64 n, double rho_g, double rho_l,
-                                                   R* __restrict__ rho, double* __restrict__ out) {
+                                                   double cut, R* __restrict__ rho, double* __restrict__ out) {
     __shared__ double red[1024];
     const int t = threadIdx.x;
     auto block_sum = [&](double v) {
@@ -724,7 +728,8 @@ __global__ void __launch_bounds__(1024) k_warm_rho(const float* __restrict__ phi
         __syncthreads();
         return s;
     };
-    auto clamped = [&](i64 i, double d) { return fmin(1.0, fmax(0.0, (double)phi[i] + d)); };
+    const double span = 1.0 - 2.0 * cut;
+    auto clamped = [&](i64 i, double d) { return fmin(1.0, fmax(0.0, ((double)phi[i] + d - cut) / span)); };
     double m = 0.0, nf = 0.0;
     for (i64 i = t; i < n; i += 1024)
         if (!(cls[i] & SOLID_BITS)) {
@@ -1205,6 +1210,20 @@ lbm_status lbm_unet_forward(lbm_unet* u, const float* x, float* y, int n) {
     return LBM_OK;
 }
 
+lbm_status lbm_unet_loss(lbm_unet* u, const float* x, const float* target, int n, double* loss) {
+    if (!u || !x || !target || !loss) return u ? ufail(u, LBM_E_ARG, "loss: null pointer") : LBM_E_ARG;
+    lbm_status s = load_input(u, x, n);
+    if (s) return s;
+    forward(u);
+    const i64 np = pixels(u, 0);
+    k_mse<<<MSE_BLOCKS, 256, 0, u->stream>>>(u->y, target, np, u->dy, u->lpart);
+    k_sum_parts<<<1, 64, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipMemcpyAsync(loss, u->loss, 8, hipMemcpyDeviceToHost, u->stream));
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_unet_backward(lbm_unet* u, const float* x, const float* target, int n, double* loss) {
     if (!u || !x || !target) return u ? ufail(u, LBM_E_ARG, "backward: null pointer") : LBM_E_ARG;
     return fwd_bwd(u, x, target, n, loss);
@@ -1233,9 +1252,10 @@ lbm_status lbm_unet_set_lr(lbm_unet* u, double lr) {
     return LBM_OK;
 }
 
-lbm_status lbm_unet_encode(const uint8_t* cls, int64_t n, double solid_value, double plane, float* x, void* stream) {
+lbm_status lbm_unet_encode(const uint8_t* cls, const float* phi0, int64_t n, double solid_value, double plane,
+                           float* x, void* stream) {
     if (!cls || !x || n < 1) return LBM_E_ARG;
-    k_encode<<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(cls, n, (float)solid_value, (float)plane, x);
+    k_encode<<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(cls, phi0, n, (float)solid_value, (float)plane, x);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
@@ -1253,16 +1273,17 @@ lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, i
 }
 
 lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int64_t n,
-                             int precision, double rho_g, double rho_l, void* rho_out, double* info) {
+                             int precision, double rho_g, double rho_l, double cut, void* rho_out, double* info) {
     if (!u) return LBM_E_ARG;
     if (!phi || !rho_ref || !cls || !rho_out || n < 1 || !(rho_l > rho_g))
         return ufail(u, LBM_E_ARG, "warm_rho: null pointer, empty field or rho_l <= rho_g");
+    if (!(cut >= 0.0 && cut < 0.25)) return ufail(u, LBM_E_ARG, "warm_rho: cut must be in [0, 0.25)");
     if (precision == LBM_F64)
-        k_warm_rho<double><<<1, 1024, 0, u->stream>>>(phi, (const double*)rho_ref, cls, n, rho_g, rho_l,
+        k_warm_rho<double><<<1, 1024, 0, u->stream>>>(phi, (const double*)rho_ref, cls, n, rho_g, rho_l, cut,
                                                       (double*)rho_out, u->winfo);
     else if (precision == LBM_F32 || precision == LBM_F32_MIXED)
-        k_warm_rho<float><<<1, 1024, 0, u->stream>>>(phi, (const float*)rho_ref, cls, n, rho_g, rho_l, (float*)rho_out,
-                                                     u->winfo);
+        k_warm_rho<float><<<1, 1024, 0, u->stream>>>(phi, (const float*)rho_ref, cls, n, rho_g, rho_l, cut,
+                                                     (float*)rho_out, u->winfo);
     else
         return ufail(u, LBM_E_ARG, "warm_rho: unknown precision");
     double h[5];

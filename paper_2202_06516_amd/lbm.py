@@ -116,7 +116,7 @@ EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read",
            "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_last_error",
            "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
-           "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_backward",
+           "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward",
            "lbm_unet_train_step", "lbm_unet_set_lr", "lbm_unet_encode", "lbm_unet_target", "lbm_unet_warm_rho",
            "lbm_unet_last_error")
 
@@ -168,15 +168,16 @@ def lib():
     L.lbm_unet_get_params.argtypes = [vp, vp, i64, i, i]
     L.lbm_unet_forward.argtypes = [vp, vp, vp, i]
     L.lbm_unet_backward.argtypes = [vp, vp, vp, i, P(d)]
+    L.lbm_unet_loss.argtypes = [vp, vp, vp, i, P(d)]
     L.lbm_unet_train_step.argtypes = [vp, vp, vp, i, P(d)]
     L.lbm_unet_set_lr.argtypes = [vp, d]
-    L.lbm_unet_encode.argtypes = [vp, i64, d, d, vp, vp]
+    L.lbm_unet_encode.argtypes = [vp, vp, i64, d, d, vp, vp]
     L.lbm_unet_target.argtypes = [vp, i, vp, i64, d, d, vp, vp]
-    L.lbm_unet_warm_rho.argtypes = [vp, vp, vp, vp, i64, i, d, d, vp, P(d)]
+    L.lbm_unet_warm_rho.argtypes = [vp, vp, vp, vp, i64, i, d, d, d, vp, P(d)]
     L.lbm_unet_last_error.restype = C.c_char_p
     L.lbm_unet_last_error.argtypes = [vp]
     for name in ("lbm_unet_create", "lbm_unet_destroy", "lbm_unet_set_params", "lbm_unet_get_params",
-                 "lbm_unet_forward", "lbm_unet_backward", "lbm_unet_train_step", "lbm_unet_set_lr",
+                 "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward", "lbm_unet_train_step", "lbm_unet_set_lr",
                  "lbm_unet_encode", "lbm_unet_target", "lbm_unet_warm_rho"):
         getattr(L, name).restype = C.c_int
     for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
@@ -236,7 +237,10 @@ class Lattice:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: module globals may be gone
+            pass
 
     def _check(self, st):
         if st != 0:
@@ -412,7 +416,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: module globals may be gone
+            pass
 
     def _check(self, st):
         if st != 0:
@@ -496,7 +503,10 @@ class Unet:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: module globals may be gone
+            pass
 
     def _check(self, st):
         if st != 0:
@@ -519,6 +529,11 @@ class Unet:
     def forward(self, x_ptr, y_ptr, n):
         self._check(lib().lbm_unet_forward(self._h, C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(n)))
 
+    def loss(self, x_ptr, t_ptr, n):
+        loss = C.c_double()
+        self._check(lib().lbm_unet_loss(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(n), C.byref(loss)))
+        return loss.value
+
     def backward(self, x_ptr, t_ptr, n):
         loss = C.c_double()
         self._check(lib().lbm_unet_backward(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(n), C.byref(loss)))
@@ -533,16 +548,17 @@ class Unet:
     def set_lr(self, lr):
         self._check(lib().lbm_unet_set_lr(self._h, float(lr)))
 
-    def warm_rho(self, phi_ptr, rho_ref_ptr, cls_ptr, n, precision, rho_g, rho_l, rho_out_ptr):
+    def warm_rho(self, phi_ptr, rho_ref_ptr, cls_ptr, n, precision, rho_g, rho_l, rho_out_ptr, cut=0.0):
         info = (C.c_double * 5)()
         self._check(lib().lbm_unet_warm_rho(self._h, C.c_void_p(phi_ptr), C.c_void_p(rho_ref_ptr),
                                             C.c_void_p(cls_ptr), int(n), int(precision), float(rho_g),
-                                            float(rho_l), C.c_void_p(rho_out_ptr), info))
+                                            float(rho_l), float(cut), C.c_void_p(rho_out_ptr), info))
         return dict(mass_ref=info[0], mass_written=info[1], delta=info[2], scale=info[3], n_fluid=info[4])
 
 
-def unet_encode(cls_ptr, n, solid_value, plane, x_ptr, stream=None):
-    st = lib().lbm_unet_encode(C.c_void_p(cls_ptr), int(n), float(solid_value), float(plane), C.c_void_p(x_ptr),
+def unet_encode(cls_ptr, n, solid_value, plane, x_ptr, stream=None, phi0_ptr=None):
+    st = lib().lbm_unet_encode(C.c_void_p(cls_ptr), C.c_void_p(phi0_ptr) if phi0_ptr else None, int(n),
+                               float(solid_value), float(plane), C.c_void_p(x_ptr),
                                C.c_void_p(stream) if stream else None)
     if st != 0:
         raise LbmError(st, "lbm_unet_encode failed")

@@ -15,6 +15,10 @@ Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
   striped_3d   D3Q19 FP32 512^3 walled box, sphere r=120 with latitude stripes
                (width 16) of two wettabilities, sessile or pendent drop r0=80,
                gravity 1e-6 .. 1e-5 lu
+  batch_cases  many D2Q9 drops on cylinders of random sizes (batched solver)
+  warmstart_cases  256^2 D2Q9 drops on cylinders, cylinder radius 16..64, drop
+               radius 18..48 (smaller drops dissolve into the gas at Tr=0.8
+               before they settle), mu_w -0.01..0.1 (learned warm start)
 """
 from __future__ import annotations
 
@@ -142,3 +146,27 @@ def batch_cases(n_cases=512, seed=0, nmin=64, nmax=512, rs=(16.0, 128.0), r0=(12
         cases.append(dict(n=(nx, ny), solid=dict(center=(nx / 2.0, cy), radius=Rs, mu_w=muw),
                           drop=((nx / 2.0, cy + Rs + rd), rd)))
     return cases, accepted / n_cases
+
+
+# seed offsets of the disjoint warm-start sets (training, validation, test)
+WARM_SEEDS = dict(train=1000, val=2000, test=3000)
+
+
+def warmstart_cases(n_cases, seed, side=256, rs=(16.0, 64.0), r0=(18.0, 48.0), mu=(-0.01, 0.1), W=10.0):
+    """Drops on cylinders for the learned warm start (seeded PCG64).
+
+    A side x side periodic D2Q9 lattice; cylinder radius, drop radius and
+    wall chemical potential uniform in the given ranges; the cylinder is
+    centred horizontally with its lowest point W + 4 above the bottom row and
+    the drop (Eq. 16 profile) tangent on top.  Returns the case table.
+    """
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    cases = []
+    for _ in range(n_cases):
+        Rs = float(rng.uniform(*rs))
+        rd = float(rng.uniform(*r0))
+        muw = float(rng.uniform(*mu))
+        cy = W + 4 + Rs
+        cases.append(dict(n=(side, side), solid=dict(center=(side / 2.0, cy), radius=Rs, mu_w=muw),
+                          drop=((side / 2.0, cy + Rs + rd), rd)))
+    return cases

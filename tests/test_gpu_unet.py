@@ -168,6 +168,12 @@ def test_field_kernels_match_their_definitions():
     G.unet_encode(cd.data_ptr(), n, 0.4, 0.125, x.data_ptr())
     torch.cuda.synchronize()
     assert np.array_equal(x.cpu().numpy(), U.encode(cls, 0.4, 0.125).astype(np.float32))
+    phi0 = rng.random(n).astype(np.float32)
+    x4 = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    p0 = dev(phi0)
+    G.unet_encode(cd.data_ptr(), n, -0.1, 0.5, x4.data_ptr(), phi0_ptr=p0.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(x4.cpu().numpy(), U.encode(cls, -0.1, 0.5, phi0).astype(np.float32))
     rho_g, rho_l = 0.0716, 6.43
     for prec, dt in ((G.LBM_F64, torch.float64), (G.LBM_F32, torch.float32)):
         rho = np.where(rng.random(n) < 0.3, rho_l, rho_g) * (1 + 0.01 * rng.standard_normal(n))
@@ -182,12 +188,16 @@ def test_field_kernels_match_their_definitions():
         pd = dev(pred)
         out = torch.empty(n, dtype=dt, device="cuda")
         net = make_net(1, 8, 8, 8, 1)
-        info = net.warm_rho(pd.data_ptr(), rd.data_ptr(), cd.data_ptr(), n, prec, rho_g, rho_l, out.data_ptr())
-        got = out.cpu().numpy().astype(np.float64)
-        want, M, delta = U.warm_rho(pred, rd.cpu().numpy(), cls, rho_g, rho_l)
-        tol = 1e-12 if prec == G.LBM_F64 else 2e-7
-        assert abs(info["mass_ref"] - M) <= 1e-12 * M
-        assert abs(got[(cls & 3) == 0].sum() - M) <= tol * M * (1 if prec == G.LBM_F64 else 10)
-        assert abs(info["delta"] - delta) <= 1e-9
-        assert np.max(np.abs(got - want)) <= tol * rho_l * 4
-        assert np.all(got[(cls & 3) != 0] == 0)
+        for cut in (0.0, 0.1):
+            info = net.warm_rho(pd.data_ptr(), rd.data_ptr(), cd.data_ptr(), n, prec, rho_g, rho_l, out.data_ptr(),
+                                cut=cut)
+            got = out.cpu().numpy().astype(np.float64)
+            want, M, delta = U.warm_rho(pred, rd.cpu().numpy(), cls, rho_g, rho_l, cut=cut)
+            tol = 1e-12 if prec == G.LBM_F64 else 2e-7
+            assert abs(info["mass_ref"] - M) <= 1e-12 * M
+            assert abs(got[(cls & 3) == 0].sum() - M) <= tol * M * (1 if prec == G.LBM_F64 else 10)
+            assert abs(info["delta"] - delta) <= 1e-9
+            assert np.max(np.abs(got - want)) <= tol * rho_l * 4
+            assert np.all(got[(cls & 3) != 0] == 0)
+        with pytest.raises(G.LbmError):
+            net.warm_rho(pd.data_ptr(), rd.data_ptr(), cd.data_ptr(), n, prec, rho_g, rho_l, out.data_ptr(), cut=0.3)

@@ -178,6 +178,14 @@ def test_warm_rho_exact_mass_bounds_and_monotone():
     assert rho[fl].min() >= rho_g - 1e-12 and rho[fl].max() <= rho_l * (1 + 1e-9)
     order = np.argsort(phi[fl])
     assert np.all(np.diff(rho[fl][order]) >= -1e-12)
+    # with a cut, predictions near 0 and 1 become exactly gas and liquid
+    rho, M, delta = U.warm_rho(phi, ref, cls, rho_g, rho_l, cut=0.1)
+    assert np.isclose(rho[fl].sum(), M, rtol=1e-13)
+    lo = phi[fl] + delta <= 0.1
+    hi = phi[fl] + delta >= 0.9
+    assert lo.any() and hi.any()
+    assert np.allclose(rho[fl][lo], rho_g, rtol=1e-12) and np.allclose(rho[fl][hi], rho[fl].max(), rtol=1e-12)
+    assert np.all(np.diff(rho[fl][order]) >= -1e-12)
 
 
 def test_encode_and_target_definitions():
@@ -186,6 +194,8 @@ def test_encode_and_target_definitions():
     assert np.array_equal(x[:, 0], [0, 1, 1, 1, 0, 0])
     assert np.array_equal(x[:, 1], [0, 0.5, 0.5, 0.5, 0, 0])
     assert np.all(x[:, 2] == 0.25)
+    x4 = U.encode(cls, 0.5, 0.25, phi0=np.arange(6) / 10)
+    assert x4.shape == (6, 4) and np.array_equal(x4[:, :3], x) and np.array_equal(x4[:, 3], np.arange(6) / 10)
     rho = np.array([1.0, 9.0, 9.0, 9.0, 0.5, 3.0])
     t = U.target(rho, cls, 0.5, 3.0)
     assert np.allclose(t, [0.2, 0, 0, 0, 0.0, 1.0])
