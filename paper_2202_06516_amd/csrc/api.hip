@@ -162,6 +162,8 @@ struct Run {
         return cp;
     }
     static dim3 grid(const lbm_ctx* c) { return dim3(c->d.nblocks, 1, 1); }
+    // the crossing search walks the tiles in a grid-stride loop
+    static dim3 cross_grid(const lbm_ctx* c) { return dim3(c->d.nblocks < 2048u ? c->d.nblocks : 2048u, 1, 1); }
 
     static WallBC wall(const lbm_ctx* c) {
         WallBC bc;
@@ -211,8 +213,11 @@ struct Run {
         mark(0);
         fills(c, ev, kinds, k);
         start();
-        k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
         mark(3);
+        start();
+        k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, c->ctl, mp);
+        mark(5);
         start();
         const WallBC bc = wall(c);
         const Collision<C> cp = collision(c);
@@ -250,7 +255,7 @@ struct Run {
         density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
         int k = 0;
         fills(c, nullptr, nullptr, k);
-        if (with_mu) k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        if (with_mu) k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c));
     }
 
     static void velocity(lbm_ctx* c, void* out) {
@@ -264,7 +269,8 @@ struct Run {
         density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
         int k = 0;
         fills(c, nullptr, nullptr, k);
-        k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c), c->ctl, mp);
+        k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c));
+        k_cross<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, c->ctl, mp);
         k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->rho, c->ctl, c->d, mp, nullptr, c->last, 0);
     }
 
@@ -436,14 +442,19 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
     c->d.N = N;
     c->d.off = 0;
-    c->d.tx = (c->d.nx + 63) / 64;
-    c->d.ty = (c->d.ny + 3) / 4;
+    {
+        // tile width: the widest of 256, 128, 64 nodes that the row fills (wide rows
+        // straddle fewer cache lines in the x-shifted gathers); LBM_TILE_W overrides
+        const char* e = std::getenv("LBM_TILE_W");
+        const int tw = e ? std::atoi(e) : (c->d.nx >= 256 ? 256 : c->d.nx >= 128 ? 128 : 64);
+        c->d.tws = tw == 256 ? 8 : tw == 128 ? 7 : 6;
+    }
+    c->d.tx = (c->d.nx + (1 << c->d.tws) - 1) >> c->d.tws;
+    c->d.ty = (c->d.ny + (256 >> c->d.tws) - 1) / (256 >> c->d.tws);
     c->d.nblocks = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)c->d.nz;
     {
         const char* e = std::getenv("LBM_XCD_REMAP");
         c->d.xcd_remap = e ? std::atoi(e) != 0 : 1;
-        const char* zf = std::getenv("LBM_ZFIRST");
-        c->d.zfirst = c->dim == 3 && zf && std::atoi(zf) != 0;
     }
     c->pr.a = cfg->pr_a;
     c->pr.b = cfg->pr_b;
@@ -867,7 +878,7 @@ lbm_status lbm_get_info(lbm_ctx* c, lbm_info* info) {
 
 lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, double* ms, int cap, int* n_kinds) {
     static const char* kNames[7] = {"k_density", "k_fill_layer1", "k_fill_layer2", "k_mu",
-                                    "k_collide", "k_bc",          "k_finalize"};
+                                    "k_collide", "k_cross",       "k_finalize"};
     if (!c || !names || !ms || !n_kinds) return LBM_E_ARG;
     if (!c->have_state) return fail(c, LBM_E_STATE, "profile: no state");
     if (nsteps < 1) return fail(c, LBM_E_ARG, "profile: nsteps >= 1");

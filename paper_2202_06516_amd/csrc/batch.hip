@@ -68,17 +68,37 @@ __global__ void __launch_bounds__(256) kb_fill(const long long* __restrict__ nod
 template <class L, typename R, typename C>
 __global__ void __launch_bounds__(256) kb_mu(const Item* __restrict__ items, int nitems, const Dims* __restrict__ dims,
                                              int tile_w, const R* __restrict__ rho, R* __restrict__ mu,
-                                             const uint8_t* __restrict__ cls, Thermo th, const DevCtl* __restrict__ ctl,
-                                             MeasureSlots* __restrict__ slots, const MeasureParams* __restrict__ mp) {
-    const bool meas = measuring(ctl);
+                                             const uint8_t* __restrict__ cls, Thermo th) {
     for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
         const Item it = items[k];
         const Dims d = dims[it.c];
         int x, y, z;
         item_node(it, tile_w, x, y, z);
         R r0;
-        const bool fluid = mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
-        if (meas) crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp[it.c], &slots[it.c]);
+        (void)mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
+    }
+}
+
+// the crossing search of a measure step, its own launch (returns at once otherwise)
+template <class L, typename R>
+__global__ void __launch_bounds__(256) kb_cross(const Item* __restrict__ items, int nitems, const Dims* __restrict__ dims,
+                                                int tile_w, const R* __restrict__ rho, const uint8_t* __restrict__ cls,
+                                                const DevCtl* __restrict__ ctl, MeasureSlots* __restrict__ slots,
+                                                const MeasureParams* __restrict__ mp) {
+    if (!measuring(ctl)) return;
+    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        bool fluid = false;
+        R r0 = R(0);
+        if (x < d.nx && y < d.ny) {
+            const long long idx = nid(d, x, y, z);
+            fluid = (cls[idx] & CLS_MASK) == CLS_FLUID;
+            if (fluid) r0 = rho[idx];
+        }
+        crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp[it.c], &slots[it.c]);
     }
 }
 
@@ -312,7 +332,9 @@ struct BRun {
         density(b, pull, grid);
         b->cur = save;
         kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
-                                                    b->cls, thermo(b), b->ctl, b->slots, b->mp);
+                                                    b->cls, thermo(b));
+        kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
+                                                    b->ctl, b->slots, b->mp);
         const R* fin = (const R*)b->f[src];
         R* fout = (R*)b->f[1 - src];
         const WallBC bc = wall(b);
@@ -380,7 +402,9 @@ struct BMeasure {
     static void go(lbm_batch* b, int grid) {
         BRun<L, R, C>::density(b, b->fstar, grid);
         kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
-                                                    b->cls, BRun<L, R, C>::thermo(b), b->ctl, b->slots, b->mp);
+                                                    b->cls, BRun<L, R, C>::thermo(b));
+        kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
+                                                    b->ctl, b->slots, b->mp);
         kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
     }
 };

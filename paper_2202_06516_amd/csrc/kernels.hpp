@@ -42,14 +42,22 @@ struct Dims {
     int nx, ny, nz;
     long long N;         // population stride (all packed nodes)
     long long off;       // first node of this lattice in the packed arrays
-    int tx, ty;          // 64 x 4 node tiles per row / per plane
+    int tx, ty;          // tiles per row / per plane
     unsigned nblocks;    // tx * ty * nz workgroups
     int xcd_remap;       // 1: contiguous tile ranges per XCD
-    int zfirst;          // 1: tiles walk z fastest (three-dimensional lattices)
+    int tws;             // log2 of the tile width: tiles of 2^tws x 256 / 2^tws nodes (one per 256-thread workgroup)
 };
 
 __device__ __forceinline__ long long nid(const Dims& d, int x, int y, int z) {
     return d.off + ((long long)z * d.ny + y) * d.nx + x;
+}
+
+// Node of this thread in tile t (x fastest, then y, then z).
+__device__ __forceinline__ void tile_coords(const Dims& d, unsigned t, int& x, int& y, int& z) {
+    const unsigned txi = t % (unsigned)d.tx, rest = t / (unsigned)d.tx;
+    x = (int)(txi << d.tws) + (int)(threadIdx.x & ((1u << d.tws) - 1u));
+    y = (int)(rest % (unsigned)d.ty) * (256 >> d.tws) + (int)(threadIdx.x >> d.tws);
+    z = (int)(rest / (unsigned)d.ty);
 }
 
 // Node of this thread.  Workgroups are dispatched to the 8 XCDs round-robin
@@ -62,18 +70,7 @@ __device__ __forceinline__ void tile_node(const Dims& d, int& x, int& y, int& z)
         const unsigned q = d.nblocks >> 3, r = d.nblocks & 7u, xcd = t & 7u, loc = t >> 3;
         t = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
     }
-    if (d.zfirst) {
-        // z fastest: the planes above and below a tile are in flight together
-        z = (int)(t % (unsigned)d.nz);
-        t /= (unsigned)d.nz;
-        x = (int)(t % (unsigned)d.tx) * 64 + (int)(threadIdx.x & 63);
-        y = (int)(t / (unsigned)d.tx) * 4 + (int)(threadIdx.x >> 6);
-        return;
-    }
-    const unsigned txi = t % (unsigned)d.tx, rest = t / (unsigned)d.tx;
-    x = (int)txi * 64 + (int)(threadIdx.x & 63);
-    y = (int)(rest % (unsigned)d.ty) * 4 + (int)(threadIdx.x >> 6);
-    z = (int)(rest / (unsigned)d.ty);
+    tile_coords(d, t, x, y, z);
 }
 
 // Peng-Robinson coefficients of psi'(rho) (Eq. 11, C = 0), pre-scaled by k^2.
@@ -141,6 +138,21 @@ __device__ __forceinline__ bool measuring(const DevCtl* ctl) {
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Periodic neighbour offsets of coordinate v (0 <= v < n >= 2) along an axis
+// of the given stride: index differences to v - 2, v - 1, v + 1, v + 2.
+// Within one lattice they fit 32 bits; node indices stay 64-bit.
+struct Nbr {
+    int m2, m1, p1, p2;
+};
+__device__ __forceinline__ Nbr nbr_offsets(int v, int n, int stride) {
+    Nbr o;
+    o.m1 = (v >= 1 ? -1 : n - 1) * stride;
+    o.m2 = (v >= 2 ? -2 : n - 2) * stride;
+    o.p1 = (v + 1 < n ? 1 : 1 - n) * stride;
+    o.p2 = (v + 2 < n ? 2 : 2 - n) * stride;
+    return o;
+}
+
 template <typename T>
 __device__ __forceinline__ T psi_prime(T rho, const Thermo& th) {
     const T br = (T)th.b * rho;
@@ -149,6 +161,19 @@ __device__ __forceinline__ T psi_prime(T rho, const Thermo& th) {
     const T t2 = (T)th.k2A * log(((T)th.s2m1 + br) / ((T)th.s2p1 - br));
     const T t3 = (T)th.k2RT / om;
     const T t4 = (T)th.k2aal * rho / (T(1) + T(2) * br - br * br);
+    return t1 - t2 + t3 - t4;
+}
+
+// FP32 arithmetic: hardware reciprocal and logarithm (about one ulp each)
+template <>
+__device__ __forceinline__ float psi_prime<float>(float rho, const Thermo& th) {
+    const float br = (float)th.b * rho;
+    const float om = 1.f - br;
+    const float iom = __fdividef(1.f, om);
+    const float t1 = (float)th.k2RT * __logf(rho * iom);
+    const float t2 = (float)th.k2A * __logf(__fdividef((float)th.s2m1 + br, (float)th.s2p1 - br));
+    const float t3 = (float)th.k2RT * iom;
+    const float t4 = __fdividef((float)th.k2aal * rho, 1.f + 2.f * br - br * br);
     return t1 - t2 + t3 - t4;
 }
 
@@ -189,11 +214,13 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
         for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + idx];
         return;
     }
-    const int xs[3] = {wrapc(x - 1, d.nx), x, wrapc(x + 1, d.nx)};
-    const int ys[3] = {wrapc(y - 1, d.ny), y, wrapc(y + 1, d.ny)};
-    const int zs[3] = {L::D == 3 ? wrapc(z - 1, d.nz) : 0, z, L::D == 3 ? wrapc(z + 1, d.nz) : 0};
+    // index offsets of x - 1, x, x + 1 along each axis (periodic wrap)
+    const int ox[3] = {x >= 1 ? -1 : d.nx - 1, 0, x + 1 < d.nx ? 1 : 1 - d.nx};
+    const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.nx, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.nx};
+    const int sz = d.nx * d.ny;
+    const int oz[3] = {L::D == 3 ? (z >= 1 ? -1 : d.nz - 1) * sz : 0, 0, L::D == 3 ? (z + 1 < d.nz ? 1 : 1 - d.nz) * sz : 0};
     // source x - e_i
-#define LBM_SRC(i) nid(d, xs[1 - L::E[i][0]], ys[1 - L::E[i][1]], zs[1 - L::E[i][2]])
+#define LBM_SRC(i) (idx + (ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]))
     if (!(c & CLS_BOUNDARY)) {
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + (i ? LBM_SRC(i) : idx)];
@@ -219,7 +246,7 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
         C v = (C)outj;
         if (q < C(0.5)) {
             if (!(bm & (1u << i))) {  // x + e_i is the fluid node behind x
-                const long long b = nid(d, xs[1 + L::E[i][0]], ys[1 + L::E[i][1]], zs[1 + L::E[i][2]]);
+                const long long b = idx + (ox[1 + L::E[i][0]] + oy[1 + L::E[i][1]] + oz[1 + L::E[i][2]]);
                 v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)f[(size_t)j * d.N + b];
             }
         } else {
@@ -404,18 +431,14 @@ __device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict
     const long long idx = nid(d, x, y, z);
     if ((cls[idx] & CLS_MASK) != CLS_FLUID) return false;
     r0 = rho[idx];
-    const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
-    const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
-    const long long sy = d.nx, sz = (long long)d.nx * d.ny;
-    const long long row = d.off + ((long long)z * d.ny + y) * d.nx;
-    const long long pl = d.off + (long long)z * sz;
+    const R* p = rho + idx;
+    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
     const C c0 = (C)r0;
-    C lap = d2c<C>(rho[row + xm2], rho[row + xm1], c0, rho[row + xp1], rho[row + xp2]);
-    lap += d2c<C>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], c0, rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
+    C lap = d2c<C>(p[ox.m2], p[ox.m1], c0, p[ox.p1], p[ox.p2]);
+    lap += d2c<C>(p[oy.m2], p[oy.m1], c0, p[oy.p1], p[oy.p2]);
     if (L::D == 3) {
-        const int zm1 = wrapc(z - 1, d.nz), zm2 = wrapc(z - 2, d.nz), zp1 = wrapc(z + 1, d.nz), zp2 = wrapc(z + 2, d.nz);
-        const long long col = d.off + (long long)y * sy + x;
-        lap += d2c<C>(rho[zm2 * sz + col], rho[zm1 * sz + col], c0, rho[zp1 * sz + col], rho[zp2 * sz + col]);
+        const Nbr oz = nbr_offsets(z, d.nz, d.nx * d.ny);
+        lap += d2c<C>(p[oz.m2], p[oz.m1], c0, p[oz.p1], p[oz.p2]);
     }
     mu[idx] = (R)((psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap);
     return true;
@@ -464,18 +487,42 @@ __device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const 
 
 template <class L, typename R, typename C>
 __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __restrict__ mu,
-                                            const uint8_t* __restrict__ cls, Dims d, Thermo th,
-                                            DevCtl* __restrict__ ctl, MeasureParams mp) {
+                                            const uint8_t* __restrict__ cls, Dims d, Thermo th) {
     int x, y, z;
     tile_node(d, x, y, z);
     R r0;
-    const bool fluid = mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
-    if (measuring(ctl)) crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp, &ctl->m);
+    (void)mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
+}
+
+// The crossing search of a measure step (Sec. III B), its own launch so that
+// the mu kernel carries none of its code: a grid-stride loop over the tiles
+// that returns at once on steps that do not measure.
+template <class L, typename R>
+__global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const uint8_t* __restrict__ cls, Dims d,
+                                               DevCtl* __restrict__ ctl, MeasureParams mp) {
+    if (!measuring(ctl)) return;
+    const unsigned ntiles = (unsigned)d.tx * (unsigned)d.ty * (unsigned)d.nz;
+    for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int x, y, z;
+        tile_coords(d, t, x, y, z);
+        bool fluid = false;
+        R r0 = R(0);
+        if (x < d.nx && y < d.ny) {
+            const long long idx = nid(d, x, y, z);
+            fluid = (cls[idx] & CLS_MASK) == CLS_FLUID;
+            if (fluid) r0 = rho[idx];
+        }
+        crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp, &ctl->m);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
+template <class L, typename R, typename C, bool MRT>
+__device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
+                                              R* __restrict__ o, long long N);
+
 template <class L, typename R, typename C, bool PULL, bool MRT>
 __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __restrict__ fout,
                                              const R* __restrict__ rho, const R* __restrict__ mu,
@@ -489,27 +536,23 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     R S[L::Q];
     gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
 
-    const long long sy = d.nx, sz = (long long)d.nx * d.ny;
-    const int xm1 = wrapc(x - 1, d.nx), xm2 = wrapc(x - 2, d.nx), xp1 = wrapc(x + 1, d.nx), xp2 = wrapc(x + 2, d.nx);
-    const int ym1 = wrapc(y - 1, d.ny), ym2 = wrapc(y - 2, d.ny), yp1 = wrapc(y + 1, d.ny), yp2 = wrapc(y + 2, d.ny);
-    const long long row = d.off + (long long)z * sz + (long long)y * sy;
-    const long long pl = d.off + (long long)z * sz;
-    const long long col = d.off + (long long)y * sy + x;
-
     // Eq. 7 with fourth-order central differences.  The two terms of F cancel
     // almost exactly inside an interface at rest, so F, and the moments it
     // shifts, are formed in double precision whatever the storage type.
     typedef double D;
-    const D r0 = (D)rho[idx];
-    const D gmx = d1c<D>(mu[row + xm2], mu[row + xm1], mu[row + xp1], mu[row + xp2]);
-    const D grx = d1c<D>(rho[row + xm2], rho[row + xm1], rho[row + xp1], rho[row + xp2]);
-    const D gmy = d1c<D>(mu[pl + ym2 * sy + x], mu[pl + ym1 * sy + x], mu[pl + yp1 * sy + x], mu[pl + yp2 * sy + x]);
-    const D gry = d1c<D>(rho[pl + ym2 * sy + x], rho[pl + ym1 * sy + x], rho[pl + yp1 * sy + x], rho[pl + yp2 * sy + x]);
+    const R* pr = rho + idx;
+    const R* pm = mu + idx;
+    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
+    const D r0 = (D)pr[0];
+    const D gmx = d1c<D>(pm[ox.m2], pm[ox.m1], pm[ox.p1], pm[ox.p2]);
+    const D grx = d1c<D>(pr[ox.m2], pr[ox.m1], pr[ox.p1], pr[ox.p2]);
+    const D gmy = d1c<D>(pm[oy.m2], pm[oy.m1], pm[oy.p1], pm[oy.p2]);
+    const D gry = d1c<D>(pr[oy.m2], pr[oy.m1], pr[oy.p1], pr[oy.p2]);
     D gmz = D(0), grz = D(0);
     if (L::D == 3) {
-        const int zm1 = wrapc(z - 1, d.nz), zm2 = wrapc(z - 2, d.nz), zp1 = wrapc(z + 1, d.nz), zp2 = wrapc(z + 2, d.nz);
-        gmz = d1c<D>(mu[zm2 * sz + col], mu[zm1 * sz + col], mu[zp1 * sz + col], mu[zp2 * sz + col]);
-        grz = d1c<D>(rho[zm2 * sz + col], rho[zm1 * sz + col], rho[zp1 * sz + col], rho[zp2 * sz + col]);
+        const Nbr oz = nbr_offsets(z, d.nz, d.nx * d.ny);
+        gmz = d1c<D>(pm[oz.m2], pm[oz.m1], pm[oz.p1], pm[oz.p2]);
+        grz = d1c<D>(pr[oz.m2], pr[oz.m1], pr[oz.p1], pr[oz.p2]);
     }
     const D third = D(1.0 / 3.0);
     D Fx = -r0 * gmx + grx * third, Fy = -r0 * gmy + gry * third, Fz = -r0 * gmz + grz * third;
@@ -518,7 +561,16 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
         Fy += r0 * (D)cp.g[1];
         Fz += r0 * (D)cp.g[2];
     }
+    collide_apply<L, R, C, MRT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
+}
 
+// Collision of one fluid node from its gathered populations S and the force
+// F (Eq. 7, plus the body force): MRT or BGK relaxation with exact-difference
+// forcing; post-collision populations stored at the node, o[i * N].
+template <class L, typename R, typename C, bool MRT>
+__device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
+                                              R* __restrict__ o, long long N) {
+    typedef double D;
     // moments of S: density and velocity (Eq. 2 arguments), in double
     D rd = D(0), jx = D(0), jy = D(0), jz = D(0);
 #pragma unroll
@@ -535,7 +587,7 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     const C vx = (C)((jx + Fx) * ird), vy = (C)((jy + Fy) * ird), vz = (C)((jz + Fz) * ird);  // u + F/rho (Eq. 13)
     const C uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + vy * vy + vz * vz;
 
-    R* const o = fout + idx;  // post-collision populations stay at the node (aligned stores)
+    const long long sN = N;   // post-collision populations stay at the node (aligned stores)
     if (!MRT) {
         // BGK (Eq. 3) + exact-difference forcing (Eq. 13), one direction at a time
         const C om = cp.omega;
@@ -547,7 +599,7 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
             const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
             const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
             const C fi = (C)S[i];
-            o[(size_t)i * d.N] = (R)(fi - om * (fi - feq) + (feq2 - feq));
+            o[(size_t)i * sN] = (R)(fi - om * (fi - feq) + (feq2 - feq));
         }
     } else {
         // MRT (Eq. 1): non-conserved moments of f - f_eq relaxed by s_k and
@@ -580,7 +632,7 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
             }
         }
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) o[(size_t)i * d.N] = (R)out[i];
+        for (int i = 0; i < L::Q; ++i) o[(size_t)i * sN] = (R)out[i];
     }
 }
 

@@ -85,10 +85,12 @@ def generate(cases, steps, check_every=1000, stream=None, log=print):
     """Advance cases to equilibrium; returns inputs x, targets t (device) and per-case angles."""
     torch = _torch()
     H, W = cases[0]["n"][1], cases[0]["n"][0]
+    t0 = time.perf_counter()
     b = make_batch(cases, stream)
     inf = b.info()
     rho_g, rho_l = inf["rho_g"], inf["rho_l"]
     n = len(cases)
+    log(f"generate: {n} cases set up in {time.perf_counter() - t0:.1f} s")
     x = torch.empty((n, H, W, IN_CHANNELS), dtype=torch.float32, device="cuda")
     encode_cases(b, cases, x, stream=stream)
     hist = []
@@ -97,7 +99,7 @@ def generate(cases, steps, check_every=1000, stream=None, log=print):
         b.step(check_every, measure_every=check_every)
         a = b.angles()
         hist.append([x.mean_deg if x.status == 0 else np.nan for x in a])
-        if (k + 1) % 10 == 0:
+        if (k + 1) % 5 == 0:
             log(f"generate: {n} cases, step {(k + 1) * check_every}, {time.perf_counter() - t0:.1f} s")
     try:
         b.sync()
