@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# HBM bytes per k_collide launch from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000) counters,
+# scaled by a plain-copy calibration; valid only for the kernel as it stands when they were taken
+# (profiles/k_collide_d3q19_f32_256cube.md).  Keyed by (lattice side, precision, collision).
+COUNTED_TRAFFIC = {(256, "f32", "bgk"): 3.381e9}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -35,8 +40,10 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps at full size (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="sessile3d", choices=["sessile3d", "batch"],
-                    help="sessile3d: the 256^3 D3Q19 benchmark; batch: 512 seeded D2Q9 cases in one batch")
+    ap.add_argument("--workload", default="sessile3d", choices=["sessile3d", "batch", "unet"],
+                    help="sessile3d: the 256^3 D3Q19 benchmark; batch: 512 seeded D2Q9 cases in one batch; "
+                         "unet: training steps of the warm-start U-Net at 256^2")
+    ap.add_argument("--batch", type=int, default=8, help="unet: samples per training step")
     ap.add_argument("--cases", type=int, default=512)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of GIB gibibytes (bandwidth / counter calibration)")
@@ -75,6 +82,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "unet":
+        unet_bench(args)
         return
     import torch
 
@@ -131,7 +141,8 @@ def main():
                    "lattice": [args.n] * 3, "fluid_nodes": n_fluid, "precision": args.precision,
                    "collision": args.collision},
         "roofline": {"bound": "hbm", "kernel": "k_collide", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": COUNTED_TRAFFIC.get((args.n, args.precision, args.collision)),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
         "step_efficiency": {"algorithmic_bytes_per_update": 2 * Q * 4,
                             "achieved_GBs": round(step_alg_bytes / (ms_step * 1e-3) / 1e9, 1),
@@ -181,6 +192,64 @@ def batch_bench(args):
                    "tuned_ms_per_step": inf["tune_ms_per_step"], "setup_s": round(t_setup, 2)},
         "cases_with_contact_angle": valid,
     }), flush=True)
+
+
+def unet_bench(args):
+    """Training throughput of the warm-start U-Net (BF16 MFMA, FP32 accumulation) on synthetic inputs."""
+    import numpy as np
+    import torch
+
+    from paper_2202_06516_amd import lbm as G
+    from paper_2202_06516_amd import warmstart as WS
+
+    B, H, W = args.batch, 256, 256
+    stream = torch.cuda.Stream()
+    net = G.Unet(H=H, W=W, batch=B, in_channels=WS.IN_CHANNELS, base_channels=32, levels=4,
+                 stream=stream.cuda_stream)
+    WS.init_params(net, seed=0)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.rand((B, H, W, WS.IN_CHANNELS), device="cuda", generator=gen)
+    t = torch.rand((B, H, W), device="cuda", generator=gen)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 200))
+    warm = max(1, min(args.warmup, 50))
+    for _ in range(warm):
+        net.train_step(x.data_ptr(), t.data_ptr(), B)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        net.train_step(x.data_ptr(), t.data_ptr(), B)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    flops = 3 * WS.forward_flops(H, W) * B          # forward + data gradients + weight gradients
+    tflops = flops / (ms * 1e-3) / 1e12
+    out = {
+        "metric": "U-Net training samples/s (256^2, 4 levels, 32..256 channels)", "value": round(B * steps / dt, 1),
+        "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": round(dt * 1e3 / steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
+        "data": "synthetic",
+        "config": {"workload": f"warm-start U-Net training step, batch {B}, 256x256, 4 inputs",
+                   "params": net.n_params, "fwd_gflop_per_sample": round(WS.forward_flops(H, W) / 1e9, 3)},
+        "roofline": {"bound": "mfma", "kernel": "all k_gemm launches of a training step (HIP events on its stream)",
+                     "achieved": round(tflops, 1), "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu:
+        import oracle.unet_ref as U
+        rng = np.random.default_rng(0)
+        th = np.asarray(U.init_params(rng, 4, 32, WS.IN_CHANNELS))
+        xs = rng.random((1, H, W, WS.IN_CHANNELS))
+        ts = rng.random((1, H, W))
+        c0 = time.perf_counter()
+        U.loss_and_grad(th, xs, ts, 4, 32)
+        cdt = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": round(1.0 / cdt, 4), "unit": "samples/s", "cores": os.cpu_count(),
+                               "kind": "oracle", "sample": "one 256x256 sample, FP64 numpy forward + backward"}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(wl, steps, collision):

@@ -362,6 +362,15 @@ lbm_status lbm_unet_backward(lbm_unet* u, const float* x, const float* target, i
 /* lbm_unet_backward, then one Adam step with bias correction. */
 lbm_status lbm_unet_train_step(lbm_unet* u, const float* x, const float* target, int n, double* loss);
 lbm_status lbm_unet_set_lr(lbm_unet* u, double lr);
+/* Checkpoint: write the weights, the Adam moments and the Adam step to path
+ * ("LBMUNET1", int32 {in_channels, base_channels, levels, 0}, int64 {parameter
+ * count, step}, FP32 weights, first moments, second moments; host byte
+ * order).  Synchronises.  LBM_E_ARG if the file cannot be written. */
+lbm_status lbm_unet_save(lbm_unet* u, const char* path);
+/* Restore a checkpoint written by lbm_unet_save for the same architecture
+ * (in_channels, base_channels, levels; H, W and batch may differ).
+ * LBM_E_ARG if the file is missing, truncated or of another architecture. */
+lbm_status lbm_unet_load(lbm_unet* u, const char* path);
 
 /* Input planes from a lattice's CLASS field (device, [n] uint8): x[i] =
  * {solid, solid ? solid_value : 0, plane} (x device FP32 [n][3]), and with
@@ -379,8 +388,8 @@ lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, i
  * equals that of rho_ref (the cold initial state), solid nodes 0; rho_out has
  * the element type of precision.  cut in [0, 0.25) sends predictions within
  * cut of pure gas or liquid to exactly rho_g or rho_l (the gas density is
- * about a hundredth of the liquid's, so small errors in phi would otherwise
- * move it far).  info (host, nullable, 5 doubles) = {reference mass, written
+ * 1/37 of the liquid's at Tr = 0.8 and 1/850 at Tr = 0.6, so small errors in
+ * phi would otherwise move it by multiples of itself).  info (host, nullable, 5 doubles) = {reference mass, written
  * mass, delta, s, fluid nodes}.  Runs on the network's stream; synchronises.
  * LBM_E_ARG if cut is out of range or the reference mass is not strictly
  * between n_fluid rho_g and n_fluid rho_l. */

@@ -636,8 +636,9 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
     const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (field == LBM_FIELD_RHO) {
         if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "write RHO: bytes must be N * elem");
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        HIPCHK(c, hipMemcpy(c->rho, src, bytes, kind));
+        // stream-ordered: a device-to-device copy may otherwise still be in
+        // flight when the kernels below (or the caller's next writes to src) run
+        HIPCHK(c, hipMemcpyAsync(c->rho, src, bytes, kind, c->stream));
         // zero both population buffers, then f = f_eq(rho, 0)
         const size_t fb = (size_t)c->Q * N * c->elem;
         if (c->f64) {
@@ -657,8 +658,8 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
     if (field == LBM_FIELD_F) {
         const size_t fb = (size_t)c->Q * N * c->elem;
         if (bytes != fb) return fail(c, LBM_E_ARG, "write F: bytes must be Q * N * elem");
+        HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src, bytes, kind, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        HIPCHK(c, hipMemcpy(c->f[c->cur], src, bytes, kind));
         c->fstar = false;
         c->have_state = true;
         return LBM_OK;
@@ -832,7 +833,8 @@ lbm_status lbm_read(lbm_ctx* c, int field, void* dst, size_t bytes, int dst_on_d
             HIPCHK(c, hipStreamSynchronize(c->stream));
             HIPCHK(c, hipMemcpy(h.data(), c->cls, N, hipMemcpyDeviceToHost));
             for (auto& v : h) v &= 3;
-            HIPCHK(c, hipMemcpy(dst, h.data(), N, dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+            if (dst_on_device) HIPCHK(c, hipMemcpyAsync(dst, h.data(), N, hipMemcpyHostToDevice, c->stream));
+            else std::memcpy(dst, h.data(), N);
             break;
         }
         case LBM_FIELD_MASS:

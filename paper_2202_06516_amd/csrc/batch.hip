@@ -856,7 +856,8 @@ lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t byt
         BCHK(b, hipStreamSynchronize(b->stream));
         BCHK(b, hipMemcpy(h.data(), b->cls + d.off, n, hipMemcpyDeviceToHost));
         for (auto& v : h) v &= 3;
-        BCHK(b, hipMemcpy(dst, h.data(), n, dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+        if (dst_on_device) BCHK(b, hipMemcpyAsync(dst, h.data(), n, hipMemcpyHostToDevice, b->stream));
+        else std::memcpy(dst, h.data(), n);
     } else {
         return bfail(b, LBM_E_ARG, "batch read: field must be RHO, F or CLASS");
     }
@@ -880,8 +881,10 @@ lbm_status lbm_batch_write(lbm_batch* b, int ci, int field, const void* src, siz
         drop_graph(b);
     }
     BCHK(b, hipStreamSynchronize(b->stream));
-    BCHK(b, hipMemcpy((char*)b->rho + (size_t)d.off * b->elem, src, bytes,
-                      src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    // stream-ordered: a device-to-device copy may otherwise still be in flight
+    // when k_init_feq runs (or when the caller reuses src)
+    BCHK(b, hipMemcpyAsync((char*)b->rho + (size_t)d.off * b->elem, src, bytes,
+                           src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream));
     // f_eq(rho, 0) on this case's range of the packed arrays
     const long long beg = d.off, end = d.off + (long long)n;
     if (b->dim == 2) {

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -59,21 +60,39 @@ __device__ __forceinline__ bf16x8 masked8(bf16x8 v, bf16x8 m) {
 
 // ---------------------------------------------------------------------------
 // Operand loaders.  elem(mn, k) is element (row mn, reduction index k) of A
-// (mn = m) or of B (mn = n); vec(mn, k) returns the 8 elements that follow
-// along the loader's vector axis: k..k+7 when KMAJ, mn..mn+7 otherwise.  The
-// GEMM calls vec only for vectors that lie wholly inside the matrix.
+// (mn = m) or of B (mn = n); vec(row(mn), mn, k) returns the 8 elements that
+// follow along the loader's vector axis: k..k+7 when KMAJ, mn..mn+7
+// otherwise.  A thread's mn is fixed for the whole K loop, so row(mn) holds
+// what depends on it alone (pixel coordinates, tap and channel), computed once
+// per tile.  The GEMM calls vec only for vectors wholly inside the matrix.
 // ---------------------------------------------------------------------------
+
+// Division by a kernel-invariant divisor d >= 1 of 0 <= n < 2^31: multiply by
+// a precomputed 32-bit reciprocal and shift (the round-up method of Granlund
+// and Montgomery); all GEMM indices stay below 2^31.
+struct FastDiv {
+    uint32_t d, m, s;
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return (__umulhi(n, m) + n) >> s; }
+};
+inline FastDiv fastdiv(uint32_t d) {
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    return FastDiv{d, (uint32_t)((1ull << 32) * ((1ull << s) - d) / d + 1), s};
+}
 
 // pixel index m of a B x H x W grid -> (b, h, w)
 struct Grid {
     int B, H, W;
-    __device__ __forceinline__ void split(i64 m, int& b, int& h, int& w) const {
-        const i64 q = m / W;
-        w = (int)(m - q * W);
-        b = (int)(q / H);
-        h = (int)(q - (i64)b * H);
+    FastDiv fH, fW;
+    __device__ __forceinline__ void split(uint32_t m, int& b, int& h, int& w) const {
+        const uint32_t q = fW.div(m);
+        w = (int)(m - q * (uint32_t)W);
+        const uint32_t bb = fH.div(q);
+        h = (int)(q - bb * (uint32_t)H);
+        b = (int)bb;
     }
 };
+inline Grid make_grid(int B, int H, int W) { return Grid{B, H, W, fastdiv((uint32_t)H), fastdiv((uint32_t)W)}; }
 
 // im2col of a 3x3 same-padded convolution over one NHWC tensor or the channel
 // concatenation [X1 | X2]: element (m = pixel, k = tap * (C1 + C2) + c) with
@@ -87,15 +106,17 @@ struct Im2col {
     const bf16* mask;
     Grid g;
     int C1, C2, flip;
+    FastDiv fC;  // C1 + C2
     __device__ __forceinline__ bool locate(i64 m, i64 k, i64& p, int& c) const {
-        const int C = C1 + C2;
-        int tap = (int)(k / C);
-        c = (int)(k - (i64)tap * C);
+        const uint32_t kk = (uint32_t)k;
+        int tap = (int)fC.div(kk);
+        c = (int)(kk - (uint32_t)tap * fC.d);
         if (flip) tap = 8 - tap;
         int b, h, w;
-        g.split(m, b, h, w);
-        h += tap / 3 - 1;
-        w += tap % 3 - 1;
+        g.split((uint32_t)m, b, h, w);
+        const int t3 = tap / 3;
+        h += t3 - 1;
+        w += tap - 3 * t3 - 1;
         if (h < 0 || h >= g.H || w < 0 || w >= g.W) return false;
         p = ((i64)b * g.H + h) * g.W + w;
         return true;
@@ -110,10 +131,23 @@ struct Im2col {
         }
         return X2[p * C2 + (c - C1)];
     }
-    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const {
-        i64 p;
-        int c;
-        if (!locate(m, k, p, c)) return zero8();
+    struct Row {
+        int b, h, w;
+    };
+    __device__ __forceinline__ Row row(i64 m) const {
+        Row r;
+        g.split((uint32_t)m, r.b, r.h, r.w);
+        return r;
+    }
+    __device__ __forceinline__ bf16x8 vec(const Row& r, i64, i64 k) const {
+        const uint32_t kk = (uint32_t)k;
+        int tap = (int)fC.div(kk);
+        const int c = (int)(kk - (uint32_t)tap * fC.d);
+        if (flip) tap = 8 - tap;
+        const int t3 = tap / 3;
+        const int h = r.h + t3 - 1, w = r.w + tap - 3 * t3 - 1;
+        if (h < 0 || h >= g.H || w < 0 || w >= g.W) return zero8();
+        const i64 p = ((i64)r.b * g.H + h) * g.W + w;
         if (c < C1) {
             const bf16x8 v = ld8(X1 + p * C1 + c);
             return mask ? masked8(v, ld8(mask + p * C1 + c)) : v;
@@ -121,6 +155,9 @@ struct Im2col {
         return ld8(X2 + p * C2 + (c - C1));
     }
 };
+inline Im2col make_im2col(const bf16* X1, const bf16* X2, const bf16* mask, Grid g, int C1, int C2, int flip) {
+    return Im2col{X1, X2, mask, g, C1, C2, flip, fastdiv((uint32_t)(C1 + C2))};
+}
 
 // B of the convolution: element (n = co, k) = Wb[n * K + k] (weights [Co][9][Cp]);
 // and of the transposed convolution: element (n = (2a + b) Co + co, k = ci)
@@ -129,7 +166,9 @@ struct RowsK {
     const bf16* P;
     i64 K;
     __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return P[n * K + k]; }
-    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(P + n * K + k); }
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 n, i64 k) const { return ld8(P + n * K + k); }
 };
 
 // B of the convolution's data gradient: element (n = ci, k = tap * Co + co) =
@@ -138,12 +177,15 @@ struct ConvWT {
     static constexpr bool KMAJ = false;
     const bf16* Wb;
     int Co, Cp;
+    FastDiv fCo;
     __device__ __forceinline__ i64 at(i64 n, i64 k) const {
-        const i64 tap = k / Co, co = k - tap * Co;
-        return (co * 9 + tap) * Cp + n;
+        const uint32_t kk = (uint32_t)k, tap = fCo.div(kk), co = kk - tap * (uint32_t)Co;
+        return ((i64)co * 9 + tap) * Cp + n;
     }
     __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return Wb[at(n, k)]; }
-    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(Wb + at(n, k)); }
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 n, i64 k) const { return ld8(Wb + at(n, k)); }
 };
 
 // A of the convolution's weight gradient: element (m = co, k = pixel) =
@@ -157,7 +199,9 @@ struct DYmasked {
         const i64 i = k * Co + m;
         return (float)Y[i] > 0.f ? dY[i] : (bf16)0.f;
     }
-    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const {
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 m, i64 k) const {
         const i64 i = k * Co + m;
         return masked8(ld8(dY + i), ld8(Y + i));
     }
@@ -170,13 +214,24 @@ struct Im2colOnes {
     Im2col a;
     i64 nbias;
     __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return n == nbias ? (bf16)1.f : a.elem(k, n); }
-    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const {
-        // a vector along n lies within one tap (C1, C2 multiples of 8); read it pixel by pixel
-        i64 p;
-        int c;
-        if (!a.locate(k, n, p, c)) return zero8();
-        if (c < a.C1) return ld8(a.X1 + p * a.C1 + c);
-        return ld8(a.X2 + p * a.C2 + (c - a.C1));
+    struct Row {
+        int c, dy, dx;
+    };
+    __device__ __forceinline__ Row row(i64 n) const {  // tap and channel of column n (n < nbias)
+        const uint32_t nn = (uint32_t)(n < nbias ? n : 0), tap = a.fC.div(nn);
+        const int t3 = (int)tap / 3;
+        return Row{(int)(nn - tap * a.fC.d), t3 - 1, (int)tap - 3 * t3 - 1};
+    }
+    __device__ __forceinline__ bf16x8 vec(const Row& r, i64, i64 k) const {
+        // a vector along n lies within one tap (C1, C2 multiples of 8)
+        int b, h, w;
+        a.g.split((uint32_t)k, b, h, w);
+        h += r.dy;
+        w += r.dx;
+        if (h < 0 || h >= a.g.H || w < 0 || w >= a.g.W) return zero8();
+        const i64 p = ((i64)b * a.g.H + h) * a.g.W + w;
+        if (r.c < a.C1) return ld8(a.X1 + p * a.C1 + r.c);
+        return ld8(a.X2 + p * a.C2 + (r.c - a.C1));
     }
 };
 
@@ -186,7 +241,9 @@ struct RowsKA {
     const bf16* X;
     int C;
     __device__ __forceinline__ bf16 elem(i64 m, i64 k) const { return X[m * C + k]; }
-    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const { return ld8(X + m * C + k); }
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 m, i64 k) const { return ld8(X + m * C + k); }
 };
 
 // output pixel of the transposed convolution for input pixel m and offset ab = 2a + b
@@ -194,7 +251,7 @@ struct UpMap {
     Grid g;  // the input grid; the output grid is B x 2H x 2W
     __device__ __forceinline__ i64 out(i64 m, int ab) const {
         int b, h, w;
-        g.split(m, b, h, w);
+        g.split((uint32_t)m, b, h, w);
         return ((i64)b * 2 * g.H + 2 * h + (ab >> 1)) * (2 * g.W) + 2 * w + (ab & 1);
     }
 };
@@ -206,12 +263,21 @@ struct UpGatherK {
     const bf16* dY;
     UpMap u;
     int Co;
+    FastDiv fCo;
     __device__ __forceinline__ i64 at(i64 m, i64 k) const {
-        const int ab = (int)(k / Co);
-        return u.out(m, ab) * Co + (k - (i64)ab * Co);
+        const uint32_t kk = (uint32_t)k, ab = fCo.div(kk);
+        return u.out(m, (int)ab) * Co + (kk - ab * (uint32_t)Co);
     }
     __device__ __forceinline__ bf16 elem(i64 m, i64 k) const { return dY[at(m, k)]; }
-    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const { return ld8(dY + at(m, k)); }
+    struct Row {
+        i64 base;  // output pixel (2h, 2w) of input pixel m
+    };
+    __device__ __forceinline__ Row row(i64 m) const { return Row{u.out(m, 0)}; }
+    __device__ __forceinline__ bf16x8 vec(const Row& r, i64, i64 k) const {
+        const uint32_t kk = (uint32_t)k, ab = fCo.div(kk);
+        const i64 q = r.base + (i64)(ab >> 1) * (2 * u.g.W) + (ab & 1);
+        return ld8(dY + q * Co + (kk - ab * (uint32_t)Co));
+    }
 };
 
 // B of the transposed convolution's data gradient: element (n = ci, k = row) = Wt[row][ci]
@@ -220,7 +286,9 @@ struct RowsN {
     const bf16* P;
     int C;
     __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return P[k * C + n]; }
-    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(P + k * C + n); }
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 n, i64 k) const { return ld8(P + k * C + n); }
 };
 
 // A of the transposed convolution's weight gradient: element (m = ab * Co + co,
@@ -230,12 +298,15 @@ struct UpGatherM {
     const bf16* dY;
     UpMap u;
     int Co;
+    FastDiv fCo;
     __device__ __forceinline__ i64 at(i64 m, i64 k) const {
-        const int ab = (int)(m / Co);
-        return u.out(k, ab) * Co + (m - (i64)ab * Co);
+        const uint32_t mm = (uint32_t)m, ab = fCo.div(mm);
+        return u.out(k, (int)ab) * Co + (mm - ab * (uint32_t)Co);
     }
     __device__ __forceinline__ bf16 elem(i64 m, i64 k) const { return dY[at(m, k)]; }
-    __device__ __forceinline__ bf16x8 vec(i64 m, i64 k) const { return ld8(dY + at(m, k)); }
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 m, i64 k) const { return ld8(dY + at(m, k)); }
 };
 
 // B of the transposed convolution's weight gradient: element (n = ci, k = pixel)
@@ -245,7 +316,9 @@ struct ColsOnes {
     const bf16* X;
     int C;
     __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return n == C ? (bf16)1.f : X[k * C + n]; }
-    __device__ __forceinline__ bf16x8 vec(i64 n, i64 k) const { return ld8(X + k * C + n); }
+    struct Row {};
+    __device__ __forceinline__ Row row(i64) const { return Row{}; }
+    __device__ __forceinline__ bf16x8 vec(const Row&, i64 n, i64 k) const { return ld8(X + k * C + n); }
 };
 
 // ---------------------------------------------------------------------------
@@ -290,10 +363,11 @@ struct EpiUp {  // column n = ab * Co + co of input pixel m -> Y[out(m, ab)][co]
     UpMap u;
     i64 M;
     int Co;
+    FastDiv fCo;
     __device__ __forceinline__ void operator()(i64 m, i64 n, float v) const {
         if (m >= M || n >= 4LL * Co) return;
-        const int ab = (int)(n / Co), co = (int)(n - (i64)ab * Co);
-        Y[u.out(m, ab) * Co + co] = (bf16)(v + bias[co]);
+        const uint32_t nn = (uint32_t)n, ab = fCo.div(nn), co = nn - ab * (uint32_t)Co;
+        Y[u.out(m, (int)ab) * Co + co] = (bf16)(v + bias[co]);
     }
 };
 
@@ -301,15 +375,16 @@ struct EpiUp {  // column n = ab * Co + co of input pixel m -> Y[out(m, ab)][co]
 // The GEMM: C[M][N] = sum_k A(m, k) B(k, n) over k in [z kchunk, (z+1) kchunk)
 // ---------------------------------------------------------------------------
 template <class L>
-__device__ __forceinline__ bf16x8 load_vec(const L& l, i64 mn, i64 k, i64 mnlim, i64 klim) {
+__device__ __forceinline__ bf16x8 load_vec(const L& l, const typename L::Row& row, i64 mn, i64 k, i64 mnlim,
+                                          i64 klim) {
     if constexpr (L::KMAJ) {
-        if (mn < mnlim && k + 8 <= klim) return l.vec(mn, k);
+        if (mn < mnlim && k + 8 <= klim) return l.vec(row, mn, k);
         bf16x8 v;
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = (mn < mnlim && k + j < klim) ? l.elem(mn, k + j) : (bf16)0.f;
         return v;
     } else {
-        if (k < klim && mn + 8 <= mnlim) return l.vec(mn, k);
+        if (k < klim && mn + 8 <= mnlim) return l.vec(row, mn, k);
         bf16x8 v;
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = (k < klim && mn + j < mnlim) ? l.elem(mn + j, k) : (bf16)0.f;
@@ -334,8 +409,8 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
     // LDS: K-major operands as [rows][BK + 8], M/N-major as [BK][rows + 8]
     constexpr int AC = (LA::KMAJ ? BK : BM) + 8, BC = (LB::KMAJ ? BK : BN) + 8;
     constexpr int AR = LA::KMAJ ? BM : BK, BR = LB::KMAJ ? BN : BK;
-    __shared__ __attribute__((aligned(16))) bf16 As[AR * AC];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[BR * BC];
+    __shared__ __attribute__((aligned(16))) bf16 As[2][AR * AC];  // two stages: one barrier per K chunk
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BR * BC];
     constexpr int NVA = BM * BK / 8, NVB = BN * BK / 8;
     constexpr int RA = (NVA + 255) / 256, RB = (NVB + 255) / 256;
     constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
@@ -354,6 +429,21 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
         for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     bf16x8 ra[RA], rb[RB];
+    // per-slot row state, fixed for the whole K loop
+    typename LA::Row rowa[RA];
+    typename LB::Row rowb[RB];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+        int mn, kk;
+        vec_coord<LA::KMAJ, BM>(tid + 256 * r, mn, kk);
+        rowa[r] = A.row(m0 + mn);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        int mn, kk;
+        vec_coord<LB::KMAJ, BN>(tid + 256 * r, mn, kk);
+        rowb[r] = B.row(n0 + mn);
+    }
     auto fetch = [&](i64 k0) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
@@ -361,7 +451,7 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
             if (NVA % 256 == 0 || v < NVA) {
                 int mn, kk;
                 vec_coord<LA::KMAJ, BM>(v, mn, kk);
-                ra[r] = load_vec(A, m0 + mn, k0 + kk, M, ke);
+                ra[r] = load_vec(A, rowa[r], m0 + mn, k0 + kk, M, ke);
             }
         }
 #pragma unroll
@@ -370,18 +460,18 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
             if (NVB % 256 == 0 || v < NVB) {
                 int mn, kk;
                 vec_coord<LB::KMAJ, BN>(v, mn, kk);
-                rb[r] = load_vec(B, n0 + mn, k0 + kk, N, ke);
+                rb[r] = load_vec(B, rowb[r], n0 + mn, k0 + kk, N, ke);
             }
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int st) {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
             const int v = tid + 256 * r;
             if (NVA % 256 == 0 || v < NVA) {
                 int mn, kk;
                 vec_coord<LA::KMAJ, BM>(v, mn, kk);
-                *reinterpret_cast<bf16x8*>(&As[LA::KMAJ ? mn * AC + kk : kk * AC + mn]) = ra[r];
+                *reinterpret_cast<bf16x8*>(&As[st][LA::KMAJ ? mn * AC + kk : kk * AC + mn]) = ra[r];
             }
         }
 #pragma unroll
@@ -390,16 +480,25 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
             if (NVB % 256 == 0 || v < NVB) {
                 int mn, kk;
                 vec_coord<LB::KMAJ, BN>(v, mn, kk);
-                *reinterpret_cast<bf16x8*>(&Bs[LB::KMAJ ? mn * BC + kk : kk * BC + mn]) = rb[r];
+                *reinterpret_cast<bf16x8*>(&Bs[st][LB::KMAJ ? mn * BC + kk : kk * BC + mn]) = rb[r];
             }
         }
     };
 
-    if (kb < ke) fetch(kb);
+    // stage st is read by the MFMAs while the next chunk's global loads are in
+    // flight and then land in stage st ^ 1; the barrier that ends a chunk
+    // both publishes st ^ 1 and retires every read of st
+    if (kb < ke) {
+        fetch(kb);
+        stash(0);
+    }
+    __syncthreads();
+    int st = 0;
     for (i64 k0 = kb; k0 < ke; k0 += BK) {
-        stash();
-        __syncthreads();
-        if (k0 + BK < ke) fetch(k0 + BK);
+        const bool more = k0 + BK < ke;
+        if (more) fetch(k0 + BK);
+        const bf16* As_ = As[st];
+        const bf16* Bs_ = Bs[st];
         // MFMA 16x16x32 operands: lane holds row (lane % 16), k = 8 (lane / 16) .. + 7
         const int kg = (lane >> 4) * 8, rl = lane & 15;
         bf16x8 a[TM], b[TN];
@@ -407,20 +506,20 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
         for (int i = 0; i < TM; ++i) {
             const int row = wm + i * 16 + rl;
             if constexpr (LA::KMAJ) {
-                a[i] = *reinterpret_cast<const bf16x8*>(&As[row * AC + kg]);
+                a[i] = *reinterpret_cast<const bf16x8*>(&As_[row * AC + kg]);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) a[i][j] = As[(kg + j) * AC + row];
+                for (int j = 0; j < 8; ++j) a[i][j] = As_[(kg + j) * AC + row];
             }
         }
 #pragma unroll
         for (int i = 0; i < TN; ++i) {
             const int row = wn + i * 16 + rl;
             if constexpr (LB::KMAJ) {
-                b[i] = *reinterpret_cast<const bf16x8*>(&Bs[row * BC + kg]);
+                b[i] = *reinterpret_cast<const bf16x8*>(&Bs_[row * BC + kg]);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) b[i][j] = Bs[(kg + j) * BC + row];
+                for (int j = 0; j < 8; ++j) b[i][j] = Bs_[(kg + j) * BC + row];
             }
         }
 #pragma unroll
@@ -428,7 +527,9 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
 #pragma unroll
             for (int j = 0; j < TN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) stash(st ^ 1);
         __syncthreads();
+        st ^= 1;
     }
     // D layout: lane holds column (lane % 16), rows 4 (lane / 16) .. + 3
 #pragma unroll
@@ -472,12 +573,12 @@ void gemm(hipStream_t s, const LA& A, const LB& B, const EPI& e, i64 M, i64 N, i
     }
 }
 
-// K splits for a weight gradient: about 2048 workgroups, at least 1024 pixels
+// K splits for a weight gradient: about 1024 workgroups, at least 2048 pixels
 // per chunk, and no more partials than the buffer holds
 int splits_for(i64 M, i64 N, i64 K, i64 cap_elems) {
     const i64 tiles = ((M + 63) / 64) * ((N + 63) / 64);
-    i64 z = (2048 + tiles - 1) / tiles;
-    z = std::min<i64>(z, std::max<i64>(1, K / 1024));
+    i64 z = (1024 + tiles - 1) / tiles;
+    z = std::min<i64>(z, std::max<i64>(1, K / 2048));
     while (z > 1 && (i64)nchunks(K, (int)z) * M * N > cap_elems) --z;
     return (int)std::max<i64>(1, z);
 }
@@ -490,55 +591,80 @@ inline int blocks_for(i64 n) {
     return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
+inline int reduce_blocks(i64 outputs) {  // 64 outputs per workgroup
+    const i64 b = (outputs + 63) / 64;
+    return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
 #define GRID_STRIDE(i, n) \
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
 
+// Sum over k of P[k][i] for the 64 outputs i = base + lane of a workgroup:
+// its four waves add interleaved quarters of k, combined in a fixed order
+// (deterministic); valid in wave 0.
+__device__ __forceinline__ float zsum64(const float* __restrict__ P, int z, i64 MN, i64 idx, float (*red)[64]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float s = 0.f;
+    if (idx < MN)
+        for (int k = wave; k < z; k += 4) s += P[(i64)k * MN + idx];
+    red[wave][lane] = s;
+    __syncthreads();
+    const float t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    __syncthreads();
+    return t;
+}
+
 // split-K partials of a convolution's weight gradient, [z][Co][9 Cp + 1], summed
-// in a fixed order into gw [Co][9][Ci] (channels >= Ci are padding) and gb [Co]
-__global__ void k_reduce_conv(const float* __restrict__ P, int z, int Co, int Cp, int Ci, float* __restrict__ gw,
-                              float* __restrict__ gb) {
+// into gw [Co][9][Ci] (channels >= Ci are padding) and gb [Co]
+__global__ void __launch_bounds__(256) k_reduce_conv(const float* __restrict__ P, int z, int Co, int Cp, int Ci,
+                                                     float* __restrict__ gw, float* __restrict__ gb) {
+    __shared__ float red[4][64];
     const i64 N1 = 9LL * Cp + 1, MN = (i64)Co * N1;
-    GRID_STRIDE(idx, MN) {
-        float s = 0.f;
-        for (int k = 0; k < z; ++k) s += P[(i64)k * MN + idx];
-        const i64 co = idx / N1, n = idx - co * N1;
-        if (n == 9LL * Cp) {
-            gb[co] = s;
-        } else {
-            const i64 t = n / Cp, c = n - t * Cp;
-            if (c < Ci) gw[(co * 9 + t) * Ci + c] = s;
+    for (i64 base = (i64)blockIdx.x * 64; base < MN; base += (i64)gridDim.x * 64) {
+        const i64 idx = base + (threadIdx.x & 63);
+        const float s = zsum64(P, z, MN, idx, red);
+        if (threadIdx.x < 64 && idx < MN) {
+            const i64 co = idx / N1, n = idx - co * N1;
+            if (n == 9LL * Cp) {
+                gb[co] = s;
+            } else {
+                const i64 t = n / Cp, c = n - t * Cp;
+                if (c < Ci) gw[(co * 9 + t) * Ci + c] = s;
+            }
         }
     }
 }
 
-// partials of a transposed convolution's weight gradient, [z][4 Co][Ci + 1] ->
-// gw [4 Co][Ci] and gb [Co] (the bias sums the four offsets)
-__global__ void k_reduce_up(const float* __restrict__ P, int z, int Co, int Ci, float* __restrict__ gw,
-                            float* __restrict__ gb) {
-    const i64 N1 = Ci + 1, MN = 4LL * Co * N1, NW = 4LL * Co * Ci;
-    GRID_STRIDE(idx, NW + Co) {
-        float s = 0.f;
-        if (idx < NW) {
-            const i64 r = idx / Ci, c = idx - r * Ci;
-            for (int k = 0; k < z; ++k) s += P[(i64)k * MN + r * N1 + c];
-            gw[idx] = s;
-        } else {
-            const i64 co = idx - NW;
-            for (int ab = 0; ab < 4; ++ab)
-                for (int k = 0; k < z; ++k) s += P[(i64)k * MN + (ab * Co + co) * N1 + Ci];
-            gb[co] = s;
+// partials of a transposed convolution's weight gradient, [z][4 Co][Ci + 1]:
+// the weight columns into gw [4 Co][Ci]; the ones column into T [4 Co]
+__global__ void __launch_bounds__(256) k_reduce_up(const float* __restrict__ P, int z, int Co, int Ci,
+                                                   float* __restrict__ gw, float* __restrict__ T) {
+    __shared__ float red[4][64];
+    const i64 N1 = Ci + 1, MN = 4LL * Co * N1;
+    for (i64 base = (i64)blockIdx.x * 64; base < MN; base += (i64)gridDim.x * 64) {
+        const i64 idx = base + (threadIdx.x & 63);
+        const float s = zsum64(P, z, MN, idx, red);
+        if (threadIdx.x < 64 && idx < MN) {
+            const i64 r = idx / N1, c = idx - r * N1;
+            if (c < Ci) gw[r * Ci + c] = s;
+            else T[r] = s;
         }
     }
+}
+
+// transposed-convolution bias gradient: the four offsets of each channel, in order
+__global__ void k_up_bias(const float* __restrict__ T, int Co, float* __restrict__ gb) {
+    const int co = blockIdx.x * blockDim.x + threadIdx.x;
+    if (co < Co) gb[co] = ((T[co] + T[Co + co]) + T[2 * Co + co]) + T[3 * Co + co];
 }
 
 // 2x2 max pooling (NHWC), with the position (0..3) of the first maximum kept
 __global__ void k_pool_fwd(const bf16* __restrict__ X, bf16* __restrict__ Y, uint8_t* __restrict__ arg, Grid g, int C) {
-    const int Ho = g.H / 2, Wo = g.W / 2;
+    const uint32_t Ho = g.H / 2, Wo = g.W / 2, uC = C;
     const i64 n = (i64)g.B * Ho * Wo * C;
     GRID_STRIDE(i, n) {
-        const int c = (int)(i % C);
-        const i64 q = i / C;
-        const int w = (int)(q % Wo), h = (int)((q / Wo) % Ho), b = (int)(q / ((i64)Wo * Ho));
+        const uint32_t ii = (uint32_t)i, q = ii / uC, c = ii - q * uC, q2 = q / Wo;
+        const int w = (int)(q - q2 * Wo), h = (int)(q2 % Ho), b = (int)(q2 / Ho);
         float best = -INFINITY;
         int bi = 0;
         for (int a = 0; a < 4; ++a) {
@@ -558,12 +684,11 @@ __global__ void k_pool_fwd(const bf16* __restrict__ X, bf16* __restrict__ Y, uin
 // gradient that reaches the pooled tensor's input through the skip connection)
 __global__ void k_pool_bwd(const bf16* __restrict__ dY, const uint8_t* __restrict__ arg, bf16* __restrict__ dX, Grid g,
                            int C) {
-    const int Ho = g.H / 2, Wo = g.W / 2;
+    const uint32_t Ho = g.H / 2, Wo = g.W / 2, uC = C;
     const i64 n = (i64)g.B * Ho * Wo * C;
     GRID_STRIDE(i, n) {
-        const int c = (int)(i % C);
-        const i64 q = i / C;
-        const int w = (int)(q % Wo), h = (int)((q / Wo) % Ho), b = (int)(q / ((i64)Wo * Ho));
+        const uint32_t ii = (uint32_t)i, q = ii / uC, c = ii - q * uC, q2 = q / Wo;
+        const int w = (int)(q - q2 * Wo), h = (int)(q2 % Ho), b = (int)(q2 / Ho);
         const int a = arg[i];
         const i64 p = ((i64)b * g.H + 2 * h + (a >> 1)) * g.W + 2 * w + (a & 1);
         dX[p * C + c] = (bf16)((float)dX[p * C + c] + (float)dY[i]);
@@ -586,7 +711,10 @@ __global__ void k_head_fwd(const bf16* __restrict__ X, const float* __restrict__
 
 __global__ void k_head_bwd_x(const float* __restrict__ dy, const float* __restrict__ w, bf16* __restrict__ dX, i64 P,
                              int C) {
-    GRID_STRIDE(i, P * C) { dX[i] = (bf16)(dy[i / C] * w[i % C]); }
+    GRID_STRIDE(i, P * C) {
+        const uint32_t ii = (uint32_t)i, p = ii / (uint32_t)C;
+        dX[i] = (bf16)(dy[p] * w[ii - p * (uint32_t)C]);
+    }
 }
 
 // head weight and bias gradients: per-block partials [blk][C + 1] (C divides 256)
@@ -617,14 +745,23 @@ __global__ void __launch_bounds__(256) k_head_bwd_w(const float* __restrict__ dy
     }
 }
 
-__global__ void k_head_reduce(const float* __restrict__ part, int nblk, int C, float* __restrict__ gw,
-                              float* __restrict__ gb) {
-    const int c = threadIdx.x;
-    if (c > C) return;
+// sums of the head partials: one workgroup per channel (and one for the bias), fixed-order tree
+__global__ void __launch_bounds__(256) k_head_reduce(const float* __restrict__ part, int nblk, int C,
+                                                     float* __restrict__ gw, float* __restrict__ gb) {
+    __shared__ float red[256];
+    const int c = blockIdx.x;  // 0..C
     float s = 0.f;
-    for (int k = 0; k < nblk; ++k) s += part[(i64)k * (C + 1) + c];
-    if (c < C) gw[c] = s;
-    else gb[0] = s;
+    for (int k = threadIdx.x; k < nblk; k += 256) s += part[(i64)k * (C + 1) + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < C) gw[c] = red[0];
+        else gb[0] = red[0];
+    }
 }
 
 // mean squared error: dL/dy and per-block FP64 partial sums
@@ -646,12 +783,18 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        *out = s * scale;
+__global__ void __launch_bounds__(256) k_sum_parts(const double* __restrict__ part, int n, double scale,
+                                                   double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // Adam with bias correction (c1 = 1 - beta1^t, c2 = 1 - beta2^t)
@@ -818,6 +961,7 @@ struct lbm_unet {
     float* part = nullptr;
     i64 part_n = 0;
     float* hpart = nullptr;
+    float* upb = nullptr;  // transposed-convolution bias partials [4 Co]
     double *lpart = nullptr, *loss = nullptr, *winfo = nullptr;
     i64 step = 0;
 };
@@ -838,7 +982,7 @@ lbm_status ufail(lbm_unet* u, lbm_status s, const std::string& msg) {
         if (e_ != hipSuccess) return ufail(u, LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-Grid grid_of(const lbm_unet* u, int l) { return Grid{u->nb, u->H >> l, u->W >> l}; }
+Grid grid_of(const lbm_unet* u, int l) { return make_grid(u->nb, u->H >> l, u->W >> l); }
 i64 pixels(const lbm_unet* u, int l) { return (i64)u->nb * (u->H >> l) * (u->W >> l); }
 
 void refresh_bf16(lbm_unet* u) {
@@ -854,7 +998,7 @@ void refresh_bf16(lbm_unet* u) {
 // y = relu(conv3x3([x1 | x2]) + b); x1 holds C1 channels (Cp - Ci2 of them)
 void conv_fwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, bf16* y, int l) {
     const i64 P = pixels(u, l);
-    Im2col A{x1, x2, nullptr, grid_of(u, l), c.Cp - c.Ci2, c.Ci2, 0};
+    const Im2col A = make_im2col(x1, x2, nullptr, grid_of(u, l), c.Cp - c.Ci2, c.Ci2, 0);
     RowsK B{c.wb, 9LL * c.Cp};
     EpiBiasRelu e{y, u->w + c.b.off, P, c.Co};
     gemm(u->stream, A, B, e, P, c.Co, 9LL * c.Cp);
@@ -867,44 +1011,45 @@ void conv_bwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const 
     const i64 P = pixels(u, l);
     const Grid g = grid_of(u, l);
     if (dx1) {
-        Im2col A{dy, nullptr, y, g, c.Co, 0, 1};
-        ConvWT B{c.wb, c.Co, c.Cp};
+        const Im2col A = make_im2col(dy, nullptr, y, g, c.Co, 0, 1);
+        ConvWT B{c.wb, c.Co, c.Cp, fastdiv((uint32_t)c.Co)};
         EpiSplit e{dx1, dx2, P, c.Ci1, c.Ci2};
         gemm(u->stream, A, B, e, P, (i64)c.Ci1 + c.Ci2, 9LL * c.Co);
     }
     const i64 N1 = 9LL * c.Cp + 1;
     DYmasked A2{dy, y, c.Co};
-    Im2colOnes B2{Im2col{x1, x2, nullptr, g, c.Cp - c.Ci2, c.Ci2, 0}, 9LL * c.Cp};
+    Im2colOnes B2{make_im2col(x1, x2, nullptr, g, c.Cp - c.Ci2, c.Ci2, 0), 9LL * c.Cp};
     const int z = splits_for(c.Co, N1, P, u->part_n);
     EpiPartial e2{u->part, c.Co, N1};
     launch_gemm<64, 64>(u->stream, A2, B2, e2, c.Co, N1, P, z);
-    k_reduce_conv<<<blocks_for((i64)c.Co * N1), 256, 0, u->stream>>>(u->part, nchunks(P, z), c.Co, c.Cp, c.Ci1 + c.Ci2,
-                                                                     u->g + c.w.off, u->g + c.b.off);
+    k_reduce_conv<<<reduce_blocks((i64)c.Co * N1), 256, 0, u->stream>>>(u->part, nchunks(P, z), c.Co, c.Cp,
+                                                                        c.Ci1 + c.Ci2, u->g + c.w.off, u->g + c.b.off);
 }
 
 void up_fwd(lbm_unet* u, const Up& p, const bf16* x, bf16* y, int lin) {
     const i64 P = pixels(u, lin);
     RowsKA A{x, p.Ci};
     RowsK B{p.wb, p.Ci};
-    EpiUp e{y, u->w + p.b.off, UpMap{grid_of(u, lin)}, P, p.Co};
+    EpiUp e{y, u->w + p.b.off, UpMap{grid_of(u, lin)}, P, p.Co, fastdiv((uint32_t)p.Co)};
     gemm(u->stream, A, B, e, P, 4LL * p.Co, p.Ci);
 }
 
 void up_bwd(lbm_unet* u, const Up& p, const bf16* x, const bf16* dy, bf16* dx, int lin) {
     const i64 P = pixels(u, lin);
     const UpMap um{grid_of(u, lin)};
-    UpGatherK A{dy, um, p.Co};
+    UpGatherK A{dy, um, p.Co, fastdiv((uint32_t)p.Co)};
     RowsN B{p.wb, p.Ci};
     EpiSplit e{dx, nullptr, P, p.Ci, 0};
     gemm(u->stream, A, B, e, P, p.Ci, 4LL * p.Co);
     const i64 N1 = p.Ci + 1;
-    UpGatherM A2{dy, um, p.Co};
+    UpGatherM A2{dy, um, p.Co, fastdiv((uint32_t)p.Co)};
     ColsOnes B2{x, p.Ci};
     const int z = splits_for(4LL * p.Co, N1, P, u->part_n);
     EpiPartial e2{u->part, 4LL * p.Co, N1};
     launch_gemm<64, 64>(u->stream, A2, B2, e2, 4LL * p.Co, N1, P, z);
-    k_reduce_up<<<blocks_for(4LL * p.Co * p.Ci + p.Co), 256, 0, u->stream>>>(u->part, nchunks(P, z), p.Co, p.Ci,
-                                                                              u->g + p.w.off, u->g + p.b.off);
+    k_reduce_up<<<reduce_blocks(4LL * p.Co * N1), 256, 0, u->stream>>>(u->part, nchunks(P, z), p.Co, p.Ci,
+                                                                       u->g + p.w.off, u->upb);
+    k_up_bias<<<(p.Co + 255) / 256, 256, 0, u->stream>>>(u->upb, p.Co, u->g + p.b.off);
 }
 
 void forward(lbm_unet* u) {
@@ -938,7 +1083,7 @@ void backward(lbm_unet* u) {
     const Act& last = L > 1 ? u->d2[L - 2] : u->c2[0];
     k_head_bwd_x<<<blocks_for(P0 * u->C0), 256, 0, u->stream>>>(u->dy, u->w + u->hw.off, last.d, P0, u->C0);
     k_head_bwd_w<<<HEAD_BLOCKS, 256, 0, u->stream>>>(u->dy, last.x, P0, u->C0, u->hpart);
-    k_head_reduce<<<1, 512, 0, u->stream>>>(u->hpart, HEAD_BLOCKS, u->C0, u->g + u->hw.off, u->g + u->hb.off);
+    k_head_reduce<<<u->C0 + 1, 256, 0, u->stream>>>(u->hpart, HEAD_BLOCKS, u->C0, u->g + u->hw.off, u->g + u->hb.off);
     for (int j = L - 2; j >= 0; --j) {
         const int l = L - 2 - j;
         const Conv& a = u->dec[2 * j];
@@ -977,7 +1122,7 @@ lbm_status fwd_bwd(lbm_unet* u, const float* x, const float* t, int n, double* l
     forward(u);
     const i64 np = pixels(u, 0);
     k_mse<<<MSE_BLOCKS, 256, 0, u->stream>>>(u->y, t, np, u->dy, u->lpart);
-    k_sum_parts<<<1, 64, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
+    k_sum_parts<<<1, 256, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
     backward(u);
     UCHK(u, hipGetLastError());
     if (loss) UCHK(u, hipMemcpyAsync(loss, u->loss, 8, hipMemcpyDeviceToHost, u->stream));
@@ -1023,7 +1168,7 @@ lbm_status lbm_unet_destroy(lbm_unet* u) {
         }
     for (auto p : u->arg) fr(p);
     for (void* p : {(void*)u->w, (void*)u->g, (void*)u->m, (void*)u->v, (void*)u->x0, (void*)u->y, (void*)u->dy,
-                    (void*)u->part, (void*)u->hpart, (void*)u->lpart, (void*)u->loss, (void*)u->winfo})
+                    (void*)u->part, (void*)u->hpart, (void*)u->upb, (void*)u->lpart, (void*)u->loss, (void*)u->winfo})
         fr(p);
     if (u->own_stream && u->stream) (void)hipStreamDestroy(u->stream);
     delete u;
@@ -1039,7 +1184,8 @@ lbm_status lbm_unet_create(const lbm_unet_config* cfg, lbm_unet** out) {
         !(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) ||
         !(cfg->eps > 0))
         return LBM_E_ARG;
-    if ((i64)cfg->batch * cfg->H * cfg->W * C0 > (1LL << 36)) return LBM_E_ARG;
+    // GEMM row indices (pixels) and element offsets within one activation stay below 2^31
+    if ((i64)cfg->batch * cfg->H * cfg->W * (C0 << 1) >= (1LL << 31)) return LBM_E_ARG;
     lbm_unet* u = new (std::nothrow) lbm_unet();
     if (!u) return LBM_E_NOMEM;
     u->cfg = *cfg;
@@ -1119,6 +1265,7 @@ lbm_status lbm_unet_create(const lbm_unet_config* cfg, lbm_unet** out) {
     dalloc((void**)&u->y, P0 * 4);
     dalloc((void**)&u->dy, P0 * 4);
     dalloc((void**)&u->hpart, (i64)HEAD_BLOCKS * (C0 + 1) * 4);
+    dalloc((void**)&u->upb, 4LL * (C0 << (L - 1)) * 4);
     dalloc((void**)&u->lpart, MSE_BLOCKS * 8);
     dalloc((void**)&u->loss, 8);
     dalloc((void**)&u->winfo, 8 * 8);
@@ -1217,7 +1364,7 @@ lbm_status lbm_unet_loss(lbm_unet* u, const float* x, const float* target, int n
     forward(u);
     const i64 np = pixels(u, 0);
     k_mse<<<MSE_BLOCKS, 256, 0, u->stream>>>(u->y, target, np, u->dy, u->lpart);
-    k_sum_parts<<<1, 64, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
+    k_sum_parts<<<1, 256, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
     UCHK(u, hipGetLastError());
     UCHK(u, hipMemcpyAsync(loss, u->loss, 8, hipMemcpyDeviceToHost, u->stream));
     UCHK(u, hipStreamSynchronize(u->stream));
@@ -1239,6 +1386,55 @@ lbm_status lbm_unet_train_step(lbm_unet* u, const float* x, const float* target,
     const float c2 = (float)(1.0 - std::pow(b2, (double)u->step));
     k_adam<<<blocks_for(u->nparam), 256, 0, u->stream>>>(u->w, u->g, u->m, u->v, u->nparam, (float)u->cfg.lr,
                                                          (float)b1, (float)b2, (float)u->cfg.eps, c1, c2);
+    refresh_bf16(u);
+    UCHK(u, hipGetLastError());
+    UCHK(u, hipStreamSynchronize(u->stream));
+    return LBM_OK;
+}
+
+// checkpoint file: "LBMUNET1", int32 {in_channels, base_channels, levels, 0},
+// int64 {parameter count, Adam step}, then FP32 weights, first and second
+// Adam moments (little-endian, as the host writes them)
+static const char kUnetMagic[8] = {'L', 'B', 'M', 'U', 'N', 'E', 'T', '1'};
+
+lbm_status lbm_unet_save(lbm_unet* u, const char* path) {
+    if (!u || !path) return u ? ufail(u, LBM_E_ARG, "save: null path") : LBM_E_ARG;
+    std::vector<float> buf((size_t)u->nparam * 3);
+    UCHK(u, hipMemcpyAsync(buf.data(), u->w, (size_t)u->nparam * 4, hipMemcpyDeviceToHost, u->stream));
+    UCHK(u, hipMemcpyAsync(buf.data() + u->nparam, u->m, (size_t)u->nparam * 4, hipMemcpyDeviceToHost, u->stream));
+    UCHK(u, hipMemcpyAsync(buf.data() + 2 * u->nparam, u->v, (size_t)u->nparam * 4, hipMemcpyDeviceToHost, u->stream));
+    UCHK(u, hipStreamSynchronize(u->stream));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return ufail(u, LBM_E_ARG, std::string("save: cannot open ") + path);
+    const int32_t hdr[4] = {u->Cin, u->C0, u->L, 0};
+    const int64_t cnt[2] = {u->nparam, u->step};
+    bool ok = std::fwrite(kUnetMagic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4 && std::fwrite(cnt, 8, 2, f) == 2 &&
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? LBM_OK : ufail(u, LBM_E_ARG, std::string("save: write failed: ") + path);
+}
+
+lbm_status lbm_unet_load(lbm_unet* u, const char* path) {
+    if (!u || !path) return u ? ufail(u, LBM_E_ARG, "load: null path") : LBM_E_ARG;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return ufail(u, LBM_E_ARG, std::string("load: cannot open ") + path);
+    char magic[8];
+    int32_t hdr[4];
+    int64_t cnt[2];
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kUnetMagic, 8) == 0 && std::fread(hdr, 4, 4, f) == 4 &&
+              std::fread(cnt, 8, 2, f) == 2;
+    if (!ok || hdr[0] != u->Cin || hdr[1] != u->C0 || hdr[2] != u->L || cnt[0] != u->nparam || cnt[1] < 0) {
+        std::fclose(f);
+        return ufail(u, LBM_E_ARG, std::string("load: not a checkpoint of this architecture: ") + path);
+    }
+    std::vector<float> buf((size_t)u->nparam * 3);
+    ok = std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return ufail(u, LBM_E_ARG, std::string("load: truncated file: ") + path);
+    UCHK(u, hipMemcpyAsync(u->w, buf.data(), (size_t)u->nparam * 4, hipMemcpyHostToDevice, u->stream));
+    UCHK(u, hipMemcpyAsync(u->m, buf.data() + u->nparam, (size_t)u->nparam * 4, hipMemcpyHostToDevice, u->stream));
+    UCHK(u, hipMemcpyAsync(u->v, buf.data() + 2 * u->nparam, (size_t)u->nparam * 4, hipMemcpyHostToDevice, u->stream));
+    u->step = cnt[1];
     refresh_bf16(u);
     UCHK(u, hipGetLastError());
     UCHK(u, hipStreamSynchronize(u->stream));

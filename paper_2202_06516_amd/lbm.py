@@ -117,8 +117,8 @@ EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "
            "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_last_error",
            "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
            "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward",
-           "lbm_unet_train_step", "lbm_unet_set_lr", "lbm_unet_encode", "lbm_unet_target", "lbm_unet_warm_rho",
-           "lbm_unet_last_error")
+           "lbm_unet_train_step", "lbm_unet_set_lr", "lbm_unet_save", "lbm_unet_load", "lbm_unet_encode",
+           "lbm_unet_target", "lbm_unet_warm_rho", "lbm_unet_last_error")
 
 
 def lib():
@@ -128,6 +128,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise OSError(f"{LIB_PATH} not built: run `python -m paper_2202_06516_amd.build`")
+    # PyTorch for ROCm ships its own HIP runtime under the same soname.  Loaded
+    # first, it also serves this library and the process holds one runtime;
+    # loaded after this library, it would bring a second runtime that then
+    # finds no GPU.  So import it first when it is installed.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, vp, i, i64, d = C.POINTER, C.c_void_p, C.c_int, C.c_int64, C.c_double
     L.lbm_config_default.restype = None
@@ -171,6 +179,8 @@ def lib():
     L.lbm_unet_loss.argtypes = [vp, vp, vp, i, P(d)]
     L.lbm_unet_train_step.argtypes = [vp, vp, vp, i, P(d)]
     L.lbm_unet_set_lr.argtypes = [vp, d]
+    L.lbm_unet_save.argtypes = [vp, C.c_char_p]
+    L.lbm_unet_load.argtypes = [vp, C.c_char_p]
     L.lbm_unet_encode.argtypes = [vp, vp, i64, d, d, vp, vp]
     L.lbm_unet_target.argtypes = [vp, i, vp, i64, d, d, vp, vp]
     L.lbm_unet_warm_rho.argtypes = [vp, vp, vp, vp, i64, i, d, d, d, vp, P(d)]
@@ -178,6 +188,7 @@ def lib():
     L.lbm_unet_last_error.argtypes = [vp]
     for name in ("lbm_unet_create", "lbm_unet_destroy", "lbm_unet_set_params", "lbm_unet_get_params",
                  "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward", "lbm_unet_train_step", "lbm_unet_set_lr",
+                 "lbm_unet_save", "lbm_unet_load",
                  "lbm_unet_encode", "lbm_unet_target", "lbm_unet_warm_rho"):
         getattr(L, name).restype = C.c_int
     for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
@@ -326,6 +337,10 @@ class Lattice:
     def write(self, field, arr):
         a = np.ascontiguousarray(arr, dtype=self.dtype)
         self._check(lib().lbm_write(self._h, field, a.ctypes.data, a.nbytes, 0))
+
+    def write_device(self, field, ptr, nbytes):
+        """Replace RHO (then f = f_eq(rho, 0)) or F from device memory at ptr."""
+        self._check(lib().lbm_write(self._h, field, C.c_void_p(ptr), nbytes, 1))
 
     @property
     def rho(self):
@@ -547,6 +562,12 @@ class Unet:
 
     def set_lr(self, lr):
         self._check(lib().lbm_unet_set_lr(self._h, float(lr)))
+
+    def save(self, path):
+        self._check(lib().lbm_unet_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        self._check(lib().lbm_unet_load(self._h, str(path).encode()))
 
     def warm_rho(self, phi_ptr, rho_ref_ptr, cls_ptr, n, precision, rho_g, rho_l, rho_out_ptr, cut=0.0):
         info = (C.c_double * 5)()

@@ -156,6 +156,20 @@ def init_params(net, seed):
     return theta
 
 
+def forward_flops(H, W, levels=4, base=32, in_channels=IN_CHANNELS):
+    """2 x multiply-adds of one forward pass of one sample (3x3 and transposed convolutions, head)."""
+    C = [base << l for l in range(levels)]
+    f, cin = 0, in_channels
+    for l in range(levels):
+        P = (H >> l) * (W >> l)
+        f += 2 * P * 9 * C[l] * (cin + C[l])
+        cin = C[l]
+    for l in range(levels - 2, -1, -1):
+        P = (H >> l) * (W >> l)
+        f += 2 * P * C[l + 1] * C[l] + 2 * P * 9 * C[l] * (2 * C[l] + C[l])
+    return f + 2 * H * W * C[0]
+
+
 def mean_loss(net, x, t):
     B = net.cfg.batch
     tot, n = 0.0, x.shape[0]
@@ -257,8 +271,11 @@ def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, stream=None, log
     for i in range(n):
         sc = settle_step(cold[:, i], ref[i], tol, every)
         sw = settle_step(warm[:, i], ref[i], tol, every)
+        late = warm[len(warm) // 2:, i]
         res.append(dict(case=i, theta_ref=float(ref[i]), cold=sc, warm=sw, settled=bool(settled[i]),
-                        theta_warm0=float(warm[0, i]), theta_cold0=float(cold[0, i])))
+                        theta_warm0=float(warm[0, i]), theta_cold0=float(cold[0, i]),
+                        theta_warm_end=float(warm[-1, i]),
+                        warm_late_maxdev=float(np.nanmax(np.abs(late - ref[i]))) if np.isfinite(late).any() else None))
     use = [r for r in res if r["settled"] and r["cold"] is not None]
     ok = [r for r in use if r["warm"] is not None]
     ratios = np.array([r["cold"] / r["warm"] for r in ok]) if ok else np.array([np.nan])
@@ -272,7 +289,7 @@ def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, stream=None, log
 
 
 def run(train_cases, val_cases, test_cases, gen_steps, horizon, epochs, levels=4, base=32, batch=8, lr=1e-3,
-        seed=0, log=print):
+        seed=0, log=print, ckpt=None, cut=0.05):
     """The whole pipeline on one GPU; returns a JSON-able report."""
     torch = _torch()
     st = torch.cuda.Stream()
@@ -294,8 +311,10 @@ def run(train_cases, val_cases, test_cases, gen_steps, horizon, epochs, levels=4
         hist = train(net, x, t, epochs, lr=lr, seed=seed + 1, xv=xv, tv=tv, log=log)
         rep["training"] = dict(epochs=epochs, seconds=round(time.perf_counter() - t0, 2), params=net.n_params,
                                first=hist[0], last=hist[-1])
+        if ckpt:
+            net.save(ckpt)
         del x, t
-        summary, res, _ = evaluate(net, test_cases, horizon, stream=st.cuda_stream, log=log)
+        summary, res, _ = evaluate(net, test_cases, horizon, cut=cut, stream=st.cuda_stream, log=log)
         rep["warm_start"] = summary
         rep["cases"] = res
         net.close()
@@ -315,16 +334,30 @@ def main(argv=None):
     ap.add_argument("--base", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--ckpt", default=None, help="write the trained network here (or read it with --eval-only)")
+    ap.add_argument("--eval-only", action="store_true", help="load --ckpt and only run the cold/warm evaluation")
+    ap.add_argument("--cut", type=float, default=0.05)
     a = ap.parse_args(argv)
     kw = dict(side=a.side)
     if a.side != 256:   # radii scale with the lattice
         s = a.side / 256.0
         kw.update(rs=(max(12.0, 16.0 * s), 64.0 * s), r0=(max(18.0, 18.0 * s), max(20.0, 48.0 * s)))
-    tr = WL.warmstart_cases(a.train, WL.WARM_SEEDS["train"], **kw)
-    va = WL.warmstart_cases(a.val, WL.WARM_SEEDS["val"], **kw) if a.val else []
     te = WL.warmstart_cases(a.test, WL.WARM_SEEDS["test"], **kw)
-    rep = run(tr, va, te, a.gen_steps, a.horizon, a.epochs, levels=a.levels, base=a.base, lr=a.lr,
-              log=lambda s: print(s, flush=True))
+    log = lambda s: print(s, flush=True)
+    if a.eval_only:
+        torch = _torch()
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            net = G.Unet(H=a.side, W=a.side, batch=8, in_channels=IN_CHANNELS, base_channels=a.base,
+                         levels=a.levels, stream=st.cuda_stream)
+            net.load(a.ckpt)
+            summary, res, _ = evaluate(net, te, a.horizon, cut=a.cut, stream=st.cuda_stream, log=log)
+        rep = dict(warm_start=summary, cases=res)
+    else:
+        tr = WL.warmstart_cases(a.train, WL.WARM_SEEDS["train"], **kw)
+        va = WL.warmstart_cases(a.val, WL.WARM_SEEDS["val"], **kw) if a.val else []
+        rep = run(tr, va, te, a.gen_steps, a.horizon, a.epochs, levels=a.levels, base=a.base, lr=a.lr, log=log,
+                  ckpt=a.ckpt, cut=a.cut)
     line = json.dumps({k: v for k, v in rep.items() if k != "cases"})
     print(line, flush=True)
     if a.out:

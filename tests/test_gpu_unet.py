@@ -201,3 +201,28 @@ def test_field_kernels_match_their_definitions():
             assert np.all(got[(cls & 3) != 0] == 0)
         with pytest.raises(G.LbmError):
             net.warm_rho(pd.data_ptr(), rd.data_ptr(), cd.data_ptr(), n, prec, rho_g, rho_l, out.data_ptr(), cut=0.3)
+
+
+def test_checkpoint_resumes_training_exactly(tmp_path):
+    from paper_2202_06516_amd import lbm as G
+    th, x, t = case(2, 16, 32, 32, 2, 14)
+    xd, td = dev(x), dev(t)
+    a = make_net(2, 16, 32, 32, 2)
+    a.set_params(th)
+    for _ in range(3):
+        a.train_step(xd.data_ptr(), td.data_ptr(), 2)
+    ck = tmp_path / "net.ckpt"
+    a.save(ck)
+    b = make_net(2, 16, 64, 48, 4)          # another lattice size and batch: same architecture
+    b.load(ck)
+    assert np.array_equal(a.params(), b.params())
+    la = a.train_step(xd.data_ptr(), td.data_ptr(), 2)
+    c = make_net(2, 16, 32, 32, 2)
+    c.load(ck)
+    lc = c.train_step(xd.data_ptr(), td.data_ptr(), 2)
+    assert la == lc and np.array_equal(a.params(), c.params())   # Adam moments and step restored
+    other = make_net(2, 8, 32, 32, 2)
+    with pytest.raises(G.LbmError):
+        other.load(ck)
+    with pytest.raises(G.LbmError):
+        a.load(tmp_path / "missing.ckpt")
