@@ -382,19 +382,25 @@ lbm_status lbm_unet_encode(const uint8_t* cls, const float* phi0, int64_t n, dou
  * (rho - rho_g) / (rho_l - rho_g) on fluid nodes, 0 on solid nodes.  Enqueues on stream. */
 lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, int64_t n, double rho_g, double rho_l,
                            float* phi, void* stream);
-/* Density for a warm start from a predicted phi (device [n]): fluid nodes get
- * rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1),
- * with delta (bisection) and s (close to 1) chosen so that the fluid mass
- * equals that of rho_ref (the cold initial state), solid nodes 0; rho_out has
- * the element type of precision.  cut in [0, 0.25) sends predictions within
- * cut of pure gas or liquid to exactly rho_g or rho_l (the gas density is
- * 1/37 of the liquid's at Tr = 0.8 and 1/850 at Tr = 0.6, so small errors in
- * phi would otherwise move it by multiples of itself).  info (host, nullable, 5 doubles) = {reference mass, written
- * mass, delta, s, fluid nodes}.  Runs on the network's stream; synchronises.
- * LBM_E_ARG if cut is out of range or the reference mass is not strictly
+/* Density for a warm start from a predicted phi (device [ny][nx]) of a 2-D
+ * lattice: with smooth = r > 0, phi is first replaced, on fluid nodes, by its
+ * mean over the fluid nodes of the (2r + 1)^2 window around each (periodic
+ * images; r = 2 removes the one-node artefacts a prediction can carry, which
+ * the fourth-order force would otherwise amplify; needs nx ny <= H W).  Fluid
+ * nodes then get rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) /
+ * (1 - 2 cut), 0, 1), with delta (bisection) and s (close to 1) chosen so that
+ * the fluid mass equals that of rho_ref (the cold initial state), solid nodes
+ * 0; rho_out has the element type of precision.  cut in [0, 0.25) sends
+ * predictions within cut of pure gas or liquid to exactly rho_g or rho_l (the
+ * gas density is 1/37 of the liquid's at Tr = 0.8 and 1/850 at Tr = 0.6, so
+ * small errors in phi would otherwise move it by multiples of itself).  info
+ * (host, nullable, 5 doubles) = {reference mass, written mass, delta, s, fluid
+ * nodes}.  Runs on the network's stream; synchronises.  LBM_E_ARG if cut or
+ * smooth (0..8) is out of range, or the reference mass is not strictly
  * between n_fluid rho_g and n_fluid rho_l. */
-lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int64_t n,
-                             int precision, double rho_g, double rho_l, double cut, void* rho_out, double* info);
+lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int nx, int ny,
+                             int precision, double rho_g, double rho_l, double cut, int smooth, void* rho_out,
+                             double* info);
 const char* lbm_unet_last_error(const lbm_unet* u);
 
 #ifdef __cplusplus

@@ -280,15 +280,37 @@ def target(rho, cls, rho_g, rho_l):
     return np.where(s, 0.0, (np.asarray(rho, dtype=np.float64) - rho_g) / (rho_l - rho_g))
 
 
-def warm_rho(phi, rho_ref, cls, rho_g, rho_l, cut=0.0):
+def smooth_fluid(phi, cls, r):
+    """Mean of phi over the fluid nodes of each fluid node's (2r+1)^2 window,
+    periodic images; 0 on solid nodes.  phi, cls: [ny][nx]."""
+    phi = np.asarray(phi, dtype=np.float64)
+    fl = (np.asarray(cls) & 3) == 0
+    ny, nx = phi.shape
+    out = np.zeros_like(phi)
+    for y in range(ny):
+        for x in range(nx):
+            if not fl[y, x]:
+                continue
+            ys = [(y + d) % ny for d in range(-r, r + 1)]
+            xs = [(x + d) % nx for d in range(-r, r + 1)]
+            win = np.ix_(ys, xs)
+            out[y, x] = phi[win][fl[win]].mean()
+    return out
+
+
+def warm_rho(phi, rho_ref, cls, rho_g, rho_l, cut=0.0, smooth=0):
     """Mass-exact density from phi on fluid nodes:
-    rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1).
+    rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1),
+    phi first replaced by smooth_fluid(phi, cls, smooth) when smooth > 0
+    (phi, rho_ref, cls then [ny][nx]).
 
     delta solves sum_fluid clamp(...) = (M - n_f rho_g) / (rho_l - rho_g), M
     the fluid mass of rho_ref (found by scipy's brentq), and s = 1 up to the
     root finder's residual.
     """
     from scipy.optimize import brentq
+    if smooth > 0:
+        phi = smooth_fluid(phi, cls, smooth)
     fl = (np.asarray(cls) & 3) == 0
     ph = np.asarray(phi, dtype=np.float64)[fl]
     M = float(np.asarray(rho_ref, dtype=np.float64)[fl].sum())

@@ -849,6 +849,36 @@ __global__ void k_target(const R* __restrict__ rho, const uint8_t* __restrict__ 
     }
 }
 
+// Mean of phi over the fluid nodes of the (2 r + 1)^2 window around each fluid
+// node (periodic images; solid nodes neither contribute nor receive: 0), in
+// a fixed order.  Removes the sub-interface-width artefacts a prediction can
+// carry, whose one-node jumps the fourth-order force would turn into a blow-up.
+__global__ void k_smooth_fluid(const float* __restrict__ phi, const uint8_t* __restrict__ cls, int nx, int ny, int r,
+                               float* __restrict__ out) {
+    GRID_STRIDE(i, (i64)nx * ny) {
+        if (cls[i] & SOLID_BITS) {
+            out[i] = 0.f;
+            continue;
+        }
+        const int x = (int)(i % nx), y = (int)(i / nx);
+        float num = 0.f, den = 0.f;
+        for (int dy = -r; dy <= r; ++dy) {
+            int yy = (y + dy) % ny;
+            if (yy < 0) yy += ny;
+            for (int dx = -r; dx <= r; ++dx) {
+                int xx = (x + dx) % nx;
+                if (xx < 0) xx += nx;
+                const i64 j = (i64)yy * nx + xx;
+                if (!(cls[j] & SOLID_BITS)) {
+                    num += phi[j];
+                    den += 1.f;
+                }
+            }
+        }
+        out[i] = num / den;
+    }
+}
+
 // One workgroup: the mass-exact density from a predicted phi.  Fluid nodes get
 // rho = rho_g + (rho_l - rho_g) s clamp((phi + delta - cut) / (1 - 2 cut), 0, 1)
 // with delta found by bisection so that the fluid mass equals that of
@@ -961,7 +991,8 @@ struct lbm_unet {
     float* part = nullptr;
     i64 part_n = 0;
     float* hpart = nullptr;
-    float* upb = nullptr;  // transposed-convolution bias partials [4 Co]
+    float* upb = nullptr;   // transposed-convolution bias partials [4 Co]
+    float* sphi = nullptr;  // smoothed phi of lbm_unet_warm_rho [H W]
     double *lpart = nullptr, *loss = nullptr, *winfo = nullptr;
     i64 step = 0;
 };
@@ -1168,7 +1199,7 @@ lbm_status lbm_unet_destroy(lbm_unet* u) {
         }
     for (auto p : u->arg) fr(p);
     for (void* p : {(void*)u->w, (void*)u->g, (void*)u->m, (void*)u->v, (void*)u->x0, (void*)u->y, (void*)u->dy,
-                    (void*)u->part, (void*)u->hpart, (void*)u->upb, (void*)u->lpart, (void*)u->loss, (void*)u->winfo})
+                    (void*)u->part, (void*)u->hpart, (void*)u->upb, (void*)u->lpart, (void*)u->loss, (void*)u->winfo, (void*)u->sphi})
         fr(p);
     if (u->own_stream && u->stream) (void)hipStreamDestroy(u->stream);
     delete u;
@@ -1269,6 +1300,7 @@ lbm_status lbm_unet_create(const lbm_unet_config* cfg, lbm_unet** out) {
     dalloc((void**)&u->lpart, MSE_BLOCKS * 8);
     dalloc((void**)&u->loss, 8);
     dalloc((void**)&u->winfo, 8 * 8);
+    dalloc((void**)&u->sphi, (i64)u->H * u->W * 4);
     for (auto* layers : {&u->enc, &u->dec})
         for (auto& c : *layers) dalloc((void**)&c.wb, (i64)c.Co * 9 * c.Cp * 2);
     for (auto& p : u->up) dalloc((void**)&p.wb, 4LL * p.Co * p.Ci * 2);
@@ -1468,12 +1500,20 @@ lbm_status lbm_unet_target(const void* rho, int precision, const uint8_t* cls, i
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
-lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int64_t n,
-                             int precision, double rho_g, double rho_l, double cut, void* rho_out, double* info) {
+lbm_status lbm_unet_warm_rho(lbm_unet* u, const float* phi, const void* rho_ref, const uint8_t* cls, int nx, int ny,
+                             int precision, double rho_g, double rho_l, double cut, int smooth, void* rho_out,
+                             double* info) {
     if (!u) return LBM_E_ARG;
-    if (!phi || !rho_ref || !cls || !rho_out || n < 1 || !(rho_l > rho_g))
+    const i64 n = (i64)nx * ny;
+    if (!phi || !rho_ref || !cls || !rho_out || nx < 1 || ny < 1 || !(rho_l > rho_g))
         return ufail(u, LBM_E_ARG, "warm_rho: null pointer, empty field or rho_l <= rho_g");
     if (!(cut >= 0.0 && cut < 0.25)) return ufail(u, LBM_E_ARG, "warm_rho: cut must be in [0, 0.25)");
+    if (smooth < 0 || smooth > 8) return ufail(u, LBM_E_ARG, "warm_rho: smooth must be in 0..8");
+    if (smooth > 0) {
+        if (n > (i64)u->H * u->W) return ufail(u, LBM_E_ARG, "warm_rho: smoothing needs nx * ny <= H * W");
+        k_smooth_fluid<<<blocks_for(n), 256, 0, u->stream>>>(phi, cls, nx, ny, smooth, u->sphi);
+        phi = u->sphi;
+    }
     if (precision == LBM_F64)
         k_warm_rho<double><<<1, 1024, 0, u->stream>>>(phi, (const double*)rho_ref, cls, n, rho_g, rho_l, cut,
                                                       (double*)rho_out, u->winfo);

@@ -183,7 +183,7 @@ def lib():
     L.lbm_unet_load.argtypes = [vp, C.c_char_p]
     L.lbm_unet_encode.argtypes = [vp, vp, i64, d, d, vp, vp]
     L.lbm_unet_target.argtypes = [vp, i, vp, i64, d, d, vp, vp]
-    L.lbm_unet_warm_rho.argtypes = [vp, vp, vp, vp, i64, i, d, d, d, vp, P(d)]
+    L.lbm_unet_warm_rho.argtypes = [vp, vp, vp, vp, i, i, i, d, d, d, i, vp, P(d)]
     L.lbm_unet_last_error.restype = C.c_char_p
     L.lbm_unet_last_error.argtypes = [vp]
     for name in ("lbm_unet_create", "lbm_unet_destroy", "lbm_unet_set_params", "lbm_unet_get_params",
@@ -569,11 +569,12 @@ class Unet:
     def load(self, path):
         self._check(lib().lbm_unet_load(self._h, str(path).encode()))
 
-    def warm_rho(self, phi_ptr, rho_ref_ptr, cls_ptr, n, precision, rho_g, rho_l, rho_out_ptr, cut=0.0):
+    def warm_rho(self, phi_ptr, rho_ref_ptr, cls_ptr, nx, ny, precision, rho_g, rho_l, rho_out_ptr, cut=0.0,
+                 smooth=0):
         info = (C.c_double * 5)()
         self._check(lib().lbm_unet_warm_rho(self._h, C.c_void_p(phi_ptr), C.c_void_p(rho_ref_ptr),
-                                            C.c_void_p(cls_ptr), int(n), int(precision), float(rho_g),
-                                            float(rho_l), float(cut), C.c_void_p(rho_out_ptr), info))
+                                            C.c_void_p(cls_ptr), int(nx), int(ny), int(precision), float(rho_g),
+                                            float(rho_l), float(cut), int(smooth), C.c_void_p(rho_out_ptr), info))
         return dict(mass_ref=info[0], mass_written=info[1], delta=info[2], scale=info[3], n_fluid=info[4])
 
 

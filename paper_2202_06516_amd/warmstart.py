@@ -13,9 +13,10 @@ library's kernels:
 2. ``train``: Adam on the BF16 MFMA network (lbm_unet_train_step), seeded
    minibatch order, cosine learning-rate decay.
 3. ``evaluate``: every test case runs twice in one batch, cold (Eq. 16) and
-   warm (the network's phi made mass-exact by lbm_unet_warm_rho, predictions
-   within ``cut`` of pure gas or liquid sent to it, and written with
-   lbm_batch_write), both measured every ``every`` steps.  The steps to
+   warm (the network's phi smoothed over a 5 x 5 fluid window, made
+   mass-exact by lbm_unet_warm_rho, predictions within ``cut`` of pure gas or
+   liquid sent to it, and written with lbm_batch_write), both measured every
+   ``every`` steps.  The steps to
    equilibrium of a run are the first measured step after which its angle
    stays within ``tol`` degrees of the cold run's final angle up to the
    horizon; a warm run that never settles there, or loses its contact line,
@@ -221,7 +222,7 @@ def settle_step(series, ref, tol, every):
     return (k + 1) * every
 
 
-def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, stream=None, log=print):
+def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, smooth=2, stream=None, log=print):
     """Cold vs warm steps to equilibrium of the test cases (both in one batch)."""
     torch = _torch()
     n = len(cases)
@@ -242,8 +243,8 @@ def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, stream=None, log
     for i in range(n):
         b.read_device(n + i, G.FIELD_RHO, rho_ref.data_ptr(), rho_ref.numel() * 4)
         b.read_device(n + i, G.FIELD_CLASS, cls.data_ptr(), cls.numel())
-        info = net.warm_rho(phi[i].data_ptr(), rho_ref.data_ptr(), cls.data_ptr(), H * W, G.LBM_F32, rho_g, rho_l,
-                            rho_new.data_ptr(), cut=cut)
+        info = net.warm_rho(phi[i].data_ptr(), rho_ref.data_ptr(), cls.data_ptr(), W, H, G.LBM_F32, rho_g, rho_l,
+                            rho_new.data_ptr(), cut=cut, smooth=smooth)
         mass_err = max(mass_err, abs(info["mass_written"] - info["mass_ref"]) / info["mass_ref"])
         b.write_rho_device(n + i, rho_new.data_ptr(), rho_new.numel() * 4)
     series = np.full((horizon // every, 2 * n), np.nan)
@@ -283,13 +284,13 @@ def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, stream=None, log
                    median_cold=float(np.median([r["cold"] for r in use])) if use else None,
                    median_warm=float(np.median([r["warm"] for r in ok])) if ok else None,
                    median_ratio=float(np.median(ratios)), mean_ratio=float(np.mean(ratios)),
-                   max_rel_mass_error=mass_err, tol_deg=tol, every=every, horizon=horizon, cut=cut,
+                   max_rel_mass_error=mass_err, tol_deg=tol, every=every, horizon=horizon, cut=cut, smooth=smooth,
                    any_nonfinite=nonfinite)
     return summary, res, series
 
 
 def run(train_cases, val_cases, test_cases, gen_steps, horizon, epochs, levels=4, base=32, batch=8, lr=1e-3,
-        seed=0, log=print, ckpt=None, cut=0.05):
+        seed=0, log=print, ckpt=None, cut=0.05, smooth=2):
     """The whole pipeline on one GPU; returns a JSON-able report."""
     torch = _torch()
     st = torch.cuda.Stream()
@@ -314,7 +315,7 @@ def run(train_cases, val_cases, test_cases, gen_steps, horizon, epochs, levels=4
         if ckpt:
             net.save(ckpt)
         del x, t
-        summary, res, _ = evaluate(net, test_cases, horizon, cut=cut, stream=st.cuda_stream, log=log)
+        summary, res, _ = evaluate(net, test_cases, horizon, cut=cut, smooth=smooth, stream=st.cuda_stream, log=log)
         rep["warm_start"] = summary
         rep["cases"] = res
         net.close()
@@ -337,6 +338,7 @@ def main(argv=None):
     ap.add_argument("--ckpt", default=None, help="write the trained network here (or read it with --eval-only)")
     ap.add_argument("--eval-only", action="store_true", help="load --ckpt and only run the cold/warm evaluation")
     ap.add_argument("--cut", type=float, default=0.05)
+    ap.add_argument("--smooth", type=int, default=2, help="radius of the fluid-window mean applied to predictions")
     a = ap.parse_args(argv)
     kw = dict(side=a.side)
     if a.side != 256:   # radii scale with the lattice
@@ -351,13 +353,13 @@ def main(argv=None):
             net = G.Unet(H=a.side, W=a.side, batch=8, in_channels=IN_CHANNELS, base_channels=a.base,
                          levels=a.levels, stream=st.cuda_stream)
             net.load(a.ckpt)
-            summary, res, _ = evaluate(net, te, a.horizon, cut=a.cut, stream=st.cuda_stream, log=log)
+            summary, res, _ = evaluate(net, te, a.horizon, cut=a.cut, smooth=a.smooth, stream=st.cuda_stream, log=log)
         rep = dict(warm_start=summary, cases=res)
     else:
         tr = WL.warmstart_cases(a.train, WL.WARM_SEEDS["train"], **kw)
         va = WL.warmstart_cases(a.val, WL.WARM_SEEDS["val"], **kw) if a.val else []
         rep = run(tr, va, te, a.gen_steps, a.horizon, a.epochs, levels=a.levels, base=a.base, lr=a.lr, log=log,
-                  ckpt=a.ckpt, cut=a.cut)
+                  ckpt=a.ckpt, cut=a.cut, smooth=a.smooth)
     line = json.dumps({k: v for k, v in rep.items() if k != "cases"})
     print(line, flush=True)
     if a.out:

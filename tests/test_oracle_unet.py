@@ -223,3 +223,22 @@ def test_bf16_storage_forward_stays_close_to_fp64():
     for k, v in c.items():
         if isinstance(v, np.ndarray) and k.endswith((".a", ".b", ".cat")):
             assert np.array_equal(v, U.bf16(v)), k
+
+
+def test_smoothing_definition():
+    rng = np.random.default_rng(12)
+    ny, nx = 9, 11
+    cls = np.zeros((ny, nx), dtype=np.uint8)
+    cls[3:6, 4:8] = 1                                  # a solid block
+    const = np.full((ny, nx), 0.37)
+    s = U.smooth_fluid(const, cls, 2)
+    assert np.allclose(s[cls == 0], 0.37, rtol=0, atol=1e-15) and np.all(s[cls != 0] == 0)
+    phi = rng.random((ny, nx))
+    s = U.smooth_fluid(phi, cls, 1)
+    # brute force at a node next to the block and at a node that wraps around the corner
+    for (y, x) in ((2, 5), (0, 0)):
+        vals = [phi[(y + dy) % ny, (x + dx) % nx] for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                if cls[(y + dy) % ny, (x + dx) % nx] == 0]
+        assert np.isclose(s[y, x], np.mean(vals), rtol=1e-14)
+    # the window mean never leaves the range of the fluid values
+    assert s[cls == 0].min() >= phi[cls == 0].min() and s[cls == 0].max() <= phi[cls == 0].max()
