@@ -33,10 +33,21 @@ struct Item {
     int x0, y0, z0;   // first node of the tile
 };
 
+// tile_w is 64, 128 or 256: shifts, not divisions
 __device__ __forceinline__ void item_node(const Item& it, int tile_w, int& x, int& y, int& z) {
-    x = it.x0 + (int)(threadIdx.x % (unsigned)tile_w);
-    y = it.y0 + (int)(threadIdx.x / (unsigned)tile_w);
+    x = it.x0 + (int)(threadIdx.x & (unsigned)(tile_w - 1));
+    y = it.y0 + (int)(threadIdx.x >> (__ffs(tile_w) - 1));
     z = it.z0;
+}
+
+// First work-list slot of this workgroup.  Workgroups are dealt to the 8 XCDs
+// round-robin by id; the slots are permuted so that each XCD owns a
+// contiguous run of gridDim.x / 8 consecutive items in every sweep (the
+// neighbouring tiles of a case, and the stencil rows they share, meet in one
+// L2).  A bijection of [0, gridDim.x); item k of sweep j is slot + j gridDim.x.
+__device__ __forceinline__ int xcd_slot() {
+    const unsigned g = gridDim.x, b = blockIdx.x, q = g >> 3, r = g & 7u, xcd = b & 7u, loc = b >> 3;
+    return (int)((xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc);
 }
 
 template <class L, typename R, typename C, bool PULL>
@@ -46,7 +57,7 @@ __global__ void __launch_bounds__(256) kb_density(const Item* __restrict__ items
                                                   MeasureSlots* __restrict__ slots, const MeasureParams* __restrict__ mp,
                                                   R inv_b) {
     const bool meas = measuring(ctl);
-    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
         const Item it = items[k];
         const Dims d = dims[it.c];
         int x, y, z;
@@ -69,7 +80,7 @@ template <class L, typename R, typename C>
 __global__ void __launch_bounds__(256) kb_mu(const Item* __restrict__ items, int nitems, const Dims* __restrict__ dims,
                                              int tile_w, const R* __restrict__ rho, R* __restrict__ mu,
                                              const uint8_t* __restrict__ cls, Thermo th) {
-    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
         const Item it = items[k];
         const Dims d = dims[it.c];
         int x, y, z;
@@ -86,7 +97,7 @@ __global__ void __launch_bounds__(256) kb_cross(const Item* __restrict__ items, 
                                                 const DevCtl* __restrict__ ctl, MeasureSlots* __restrict__ slots,
                                                 const MeasureParams* __restrict__ mp) {
     if (!measuring(ctl)) return;
-    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
         const Item it = items[k];
         const Dims d = dims[it.c];
         int x, y, z;
@@ -109,7 +120,7 @@ __global__ void __launch_bounds__(256) kb_collide(const Item* __restrict__ items
                                                   const R* __restrict__ mu, const uint8_t* __restrict__ cls, WallBC bc,
                                                   Collision<C> cp, const DevCtl* __restrict__ ctl) {
     const long long t = ctl->t;
-    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
         const Item it = items[k];
         const Dims d = dims[it.c];
         int x, y, z;
@@ -145,7 +156,7 @@ __global__ void __launch_bounds__(256) kb_materialize(const Item* __restrict__ i
                                                       const Dims* __restrict__ dims, int tile_w,
                                                       const R* __restrict__ f, R* __restrict__ out,
                                                       const uint8_t* __restrict__ cls, WallBC bc) {
-    for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
         const Item it = items[k];
         const Dims d = dims[it.c];
         int x, y, z;
