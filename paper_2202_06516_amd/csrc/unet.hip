@@ -45,6 +45,27 @@ constexpr int BK = 32;    // K chunk per LDS stage (one MFMA 16x16x32 step)
 constexpr int CPAD = 8;   // the network input is padded to 8 channels (one 16-byte vector)
 
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+// MFMA operand of row r from an LDS stage stored k-major by row ([k][rows],
+// row contiguous), with the transposing 64-bit LDS read.  Within each group of
+// 16 lanes, lane t addresses 4 consecutive rows at one k, and lane i of the
+// group receives, in slot j, element i % 4 of the vector that lane
+// 4 j + i / 4 addressed.  Lane t = 4 j + q of group g therefore addresses
+// rows 4 q .. 4 q + 3 at k = 8 g + j (and 8 g + 4 + j for the second read),
+// which leaves lane i holding row i at k = 8 g .. 8 g + 7: the layout the
+// MFMA takes.  p = &stage[0][row0]; stride = elements per k row.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+__device__ __forceinline__ bf16x8 ld_tr8(const bf16* p, int stride, int lane) {
+    const int t = lane & 15, g = lane >> 4;
+    const bf16* q = p + (8 * g + (t >> 2)) * stride + 4 * (t & 3);
+    const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)q);
+    const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(q + 4 * stride));
+    bf16x8 r;
+    __builtin_memcpy(&r, &lo, 8);
+    __builtin_memcpy(reinterpret_cast<char*>(&r) + 8, &hi, 8);
+    return r;
+}
 __device__ __forceinline__ bf16x8 zero8() {
     bf16x8 v;
 #pragma unroll
@@ -508,8 +529,7 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
             if constexpr (LA::KMAJ) {
                 a[i] = *reinterpret_cast<const bf16x8*>(&As_[row * AC + kg]);
             } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) a[i][j] = As_[(kg + j) * AC + row];
+                a[i] = ld_tr8(&As_[wm + i * 16], AC, lane);
             }
         }
 #pragma unroll
@@ -518,8 +538,7 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
             if constexpr (LB::KMAJ) {
                 b[i] = *reinterpret_cast<const bf16x8*>(&Bs_[row * BC + kg]);
             } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) b[i][j] = Bs_[(kg + j) * BC + row];
+                b[i] = ld_tr8(&Bs_[wn + i * 16], BC, lane);
             }
         }
 #pragma unroll
@@ -539,6 +558,197 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 epi(m0 + wm + i * 16 + (lane >> 4) * 4 + q, n0 + wn + j * 16 + (lane & 15), acc[i][j][q]);
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of a 3x3 convolution with all nine taps in one workgroup
+// ---------------------------------------------------------------------------
+// P[z][co][tap Cp + c] = sum over the pixels p of chunk z of dYm[p][co] X[p + s(tap)][c],
+// P[z][co][9 Cp] = sum dYm[p][co] (the bias), dYm = dY where the ReLU output
+// Y > 0, X = [X1 | X2] (C1 + C2 = Cp channels), s(tap) the tap's pixel shift
+// (zero outside the image).  The reduction runs over segments of 32 pixels
+// of one image row: a stage holds dYm of the segment ([32][BM] per pixel)
+// and X of the three rows around it ([3][34][BN]), so each X element read
+// from memory feeds the nine taps from LDS.  A workgroup is G groups of four
+// waves; group q takes every G-th segment of the chunk with stages of its
+// own, and the groups' sums are added in LDS in group order at the end
+// (deterministic).  Within a group the waves are 2 x 2, each 16 TM x 16 TN of
+// (co, c) for every tap; both operands enter the MFMA through the transposing
+// LDS read.
+constexpr int SEG = 32;  // pixels per segment = one MFMA K step
+
+template <int TM, int TN, int G>
+__global__ void __launch_bounds__(256 * G) k_wgrad3x3(const bf16* __restrict__ dY, const bf16* __restrict__ Y,
+                                                      const bf16* __restrict__ X1, const bf16* __restrict__ X2,
+                                                      int C1, int C2, int Co, Grid g, int segs_row, int nsegs,
+                                                      int spc, float* __restrict__ P) {
+    constexpr int BM = 32 * TM, BN = 32 * TN, DC = BM + 8, XC = BN + 8, XW = SEG + 2;
+    constexpr int NVD = SEG * BM / 8, NVX = 3 * XW * BN / 8;
+    constexpr int RD = (NVD + 255) / 256, RX = (NVX + 255) / 256;
+    constexpr int DS = SEG * DC, XS = 3 * XW * XC;  // elements per stage
+    __shared__ __attribute__((aligned(16))) bf16 lds[G * 2 * (DS + XS)];
+    static_assert(BM * BN * 4 <= G * 2 * (DS + XS) * 2, "reduction buffer");
+
+    const int q = threadIdx.x >> 8, tid = threadIdx.x & 255, lane = tid & 63, wave = tid >> 6;
+    bf16* Ds = lds + q * 2 * (DS + XS);  // this group's two stages: Ds[st], then Xs[st]
+    bf16* Xs = Ds + 2 * DS;
+    const int co0 = blockIdx.x * BM, c0 = blockIdx.y * BN, Cp = C1 + C2;
+    const int s0 = blockIdx.z * spc, s1 = min(nsegs, s0 + spc);
+    const int iters = (s1 - s0 + G - 1) / G;  // the same for every group (barriers)
+    const int wm = (wave >> 1) * 16 * TM, wn = (wave & 1) * 16 * TN;
+    const bool bias = blockIdx.y == 0;
+
+    floatx4 acc[9][TM][TN];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[t][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+
+    bf16x8 rd[RD], rx[RX];
+    auto fetch = [&](int s) {  // s < s1
+        const int row = s / segs_row, w0 = (s - row * segs_row) * SEG;
+        const int b = row / g.H, h = row - b * g.H;
+#pragma unroll
+        for (int r = 0; r < RD; ++r) {
+            const int v = tid + 256 * r;
+            if (NVD % 256 == 0 || v < NVD) {
+                const int px = v / (BM / 8), cv = (v % (BM / 8)) * 8;
+                const int w = w0 + px, co = co0 + cv;
+                rd[r] = zero8();
+                if (w < g.W && co < Co) {
+                    const i64 i = (((i64)b * g.H + h) * g.W + w) * Co + co;
+                    rd[r] = masked8(ld8(dY + i), ld8(Y + i));
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const int v = tid + 256 * r;
+            if (NVX % 256 == 0 || v < NVX) {
+                const int dr = v / (XW * BN / 8), rem = v - dr * (XW * BN / 8);
+                const int j = rem / (BN / 8), cv = (rem % (BN / 8)) * 8;
+                const int hh = h + dr - 1, w = w0 + j - 1, c = c0 + cv;
+                rx[r] = zero8();
+                if (hh >= 0 && hh < g.H && w >= 0 && w < g.W && c < Cp) {
+                    const i64 p = ((i64)b * g.H + hh) * g.W + w;
+                    rx[r] = c < C1 ? ld8(X1 + p * C1 + c) : ld8(X2 + p * C2 + (c - C1));
+                }
+            }
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < RD; ++r) {
+            const int v = tid + 256 * r;
+            if (NVD % 256 == 0 || v < NVD) {
+                const int px = v / (BM / 8), cv = (v % (BM / 8)) * 8;
+                *reinterpret_cast<bf16x8*>(&Ds[st * DS + px * DC + cv]) = rd[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const int v = tid + 256 * r;
+            if (NVX % 256 == 0 || v < NVX) {
+                const int dr = v / (XW * BN / 8), rem = v - dr * (XW * BN / 8);
+                const int j = rem / (BN / 8), cv = (rem % (BN / 8)) * 8;
+                *reinterpret_cast<bf16x8*>(&Xs[st * XS + (dr * XW + j) * XC + cv]) = rx[r];
+            }
+        }
+    };
+
+    // group q handles segments s0 + q + G it, it < iters, where they exist
+    if (iters > 0 && s0 + q < s1) {
+        fetch(s0 + q);
+        stash(0);
+    }
+    __syncthreads();
+    int st = 0;
+    for (int it = 0; it < iters; ++it) {
+        const int s = s0 + q + G * it;
+        const bool have = s < s1, more = s + G < s1;
+        if (more) fetch(s + G);
+        if (have) {
+            const bf16* D_ = Ds + st * DS;
+            const bf16* X_ = Xs + st * XS;
+            bf16x8 a[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = ld_tr8(D_ + wm + 16 * i, DC, lane);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t % 3;  // offsets into the stage's three rows and 34 columns
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const bf16x8 bv = ld_tr8(X_ + (dy * XW + dx) * XC + wn + 16 * j, XC, lane);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+                        acc[t][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv, acc[t][i][j], 0, 0, 0);
+                }
+            }
+            if (bias && tid < BM) {
+#pragma unroll 8
+                for (int px = 0; px < SEG; ++px) bsum += (float)D_[px * DC + tid];
+            }
+        }
+        if (more) stash(st ^ 1);
+        __syncthreads();
+        st ^= 1;
+    }
+
+    // sum the groups in LDS (group order), one tap at a time; group 0 writes
+    const i64 N1 = 9LL * Cp + 1;
+    float* Pz = P + (i64)blockIdx.z * Co * N1;
+    float* red = reinterpret_cast<float*>(lds);  // [BM][BN]
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        for (int k = 1; k < G; ++k) {
+            if (q == k) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            red[(wm + 16 * i + (lane >> 4) * 4 + e) * BN + wn + 16 * j + (lane & 15)] = acc[t][i][j][e];
+            }
+            __syncthreads();
+            if (q == 0) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[t][i][j][e] += red[(wm + 16 * i + (lane >> 4) * 4 + e) * BN + wn + 16 * j + (lane & 15)];
+            }
+            __syncthreads();
+        }
+        if (q == 0) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int c = c0 + wn + 16 * j + (lane & 15);
+                    if (c >= Cp) continue;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int co = co0 + wm + 16 * i + (lane >> 4) * 4 + e;
+                        if (co < Co) Pz[(i64)co * N1 + (i64)t * Cp + c] = acc[t][i][j][e];
+                    }
+                }
+        }
+    }
+    if (bias) {
+        for (int k = 1; k < G; ++k) {
+            if (q == k && tid < BM) red[tid] = bsum;
+            __syncthreads();
+            if (q == 0 && tid < BM) bsum += red[tid];
+            __syncthreads();
+        }
+        if (q == 0 && tid < BM && co0 + tid < Co) Pz[(i64)(co0 + tid) * N1 + 9LL * Cp] = bsum;
+    }
 }
 
 // K split into z chunks (multiples of BK); returns the number of chunks launched
@@ -1035,6 +1245,25 @@ void conv_fwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, bf16* 
     gemm(u->stream, A, B, e, P, c.Co, 9LL * c.Cp);
 }
 
+// split-K partials of a convolution's weight and bias gradients into u->part
+// ([z][Co][9 Cp + 1]); returns z.  32 x 32 channel tiles, four groups of four
+// waves per workgroup, about 256 workgroups (one per compute unit) and at
+// least two segments per group, so that the partials stay near 9 MB.
+int wgrad3x3(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const bf16* y, const bf16* dy, const Grid& g) {
+    constexpr int G = 4;
+    const int segs_row = (g.W + SEG - 1) / SEG, nsegs = g.B * g.H * segs_row;
+    const int tiles = ((c.Co + 31) / 32) * ((c.Cp + 31) / 32);
+    const i64 N1 = 9LL * c.Cp + 1;
+    int z = std::max(1, std::min((256 + tiles - 1) / tiles, nsegs / (2 * G)));
+    z = (int)std::min<i64>(z, std::max<i64>(1, u->part_n / ((i64)c.Co * N1)));
+    const int spc = (nsegs + z - 1) / z;
+    z = (nsegs + spc - 1) / spc;  // every chunk holds at least one segment
+    const dim3 grid((unsigned)((c.Co + 31) / 32), (unsigned)((c.Cp + 31) / 32), (unsigned)z);
+    k_wgrad3x3<1, 1, G><<<grid, 256 * G, 0, u->stream>>>(dy, y, x1, x2, c.Cp - c.Ci2, c.Ci2, c.Co, g, segs_row, nsegs,
+                                                         spc, u->part);
+    return z;
+}
+
 // backward of y = relu(conv3x3([x1 | x2]) + b): weight and bias gradients into
 // g; data gradients written to dx1 / dx2 when dx1 is set
 void conv_bwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const bf16* y, const bf16* dy, bf16* dx1,
@@ -1048,13 +1277,9 @@ void conv_bwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const 
         gemm(u->stream, A, B, e, P, (i64)c.Ci1 + c.Ci2, 9LL * c.Co);
     }
     const i64 N1 = 9LL * c.Cp + 1;
-    DYmasked A2{dy, y, c.Co};
-    Im2colOnes B2{make_im2col(x1, x2, nullptr, g, c.Cp - c.Ci2, c.Ci2, 0), 9LL * c.Cp};
-    const int z = splits_for(c.Co, N1, P, u->part_n);
-    EpiPartial e2{u->part, c.Co, N1};
-    launch_gemm<64, 64>(u->stream, A2, B2, e2, c.Co, N1, P, z);
-    k_reduce_conv<<<reduce_blocks((i64)c.Co * N1), 256, 0, u->stream>>>(u->part, nchunks(P, z), c.Co, c.Cp,
-                                                                        c.Ci1 + c.Ci2, u->g + c.w.off, u->g + c.b.off);
+    const int nz = wgrad3x3(u, c, x1, x2, y, dy, g);
+    k_reduce_conv<<<reduce_blocks((i64)c.Co * N1), 256, 0, u->stream>>>(u->part, nz, c.Co, c.Cp, c.Ci1 + c.Ci2,
+                                                                        u->g + c.w.off, u->g + c.b.off);
 }
 
 void up_fwd(lbm_unet* u, const Up& p, const bf16* x, bf16* y, int lin) {
