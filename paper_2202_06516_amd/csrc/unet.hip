@@ -12,16 +12,19 @@
 // and their gradients are NHWC BF16; master weights, gradients and the Adam
 // moments are FP32, with BF16 copies for the products.
 //
-// Every product is one implicit-GEMM kernel on MFMA 16x16x32 BF16 tiles:
-// BM x BN output tiles per 256-thread workgroup (four waves, 2 x 2), K in
-// chunks of 32 staged through LDS with the next chunk's global loads in flight
-// during the current chunk's MFMAs.  Loader functors gather 16-byte vectors
-// of an operand either along K or along M/N, so that every pass is a GEMM
-// whose operands are read in their stored layout: the 3x3 convolution (im2col
-// on the fly), its data gradient (mirrored taps, ReLU mask fused into the
-// load), its weight gradient (split-K, bias gradient as an extra column of
-// ones, deterministic reduction), and the transposed convolution with its two
-// gradients.
+// Every product runs on MFMA 16x16x32 BF16 tiles with operands staged through
+// LDS (four waves of 2 x 2 per group, the next stage's global loads in flight
+// during the current stage's MFMAs), in three kernels:
+//  - the 3x3 convolution and its data gradient (mirrored taps, transposed
+//    weights, ReLU mask fused into the load) are tap-blocked: a stage holds
+//    one input row of a pixel segment and the three taps of that row, and
+//    feeds the three taps from LDS;
+//  - the 3x3 weight gradient holds dY of a 32-pixel segment and the three
+//    input rows around it, and accumulates all nine taps (split over pixel
+//    chunks, partials summed in a fixed order: deterministic);
+//  - the transposed convolution and its gradients use a generic implicit GEMM
+//    whose loader functors gather 16-byte vectors along K or along M/N.
+// Operands stored along M/N enter the MFMA through the transposing LDS read.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -115,73 +118,7 @@ struct Grid {
 };
 inline Grid make_grid(int B, int H, int W) { return Grid{B, H, W, fastdiv((uint32_t)H), fastdiv((uint32_t)W)}; }
 
-// im2col of a 3x3 same-padded convolution over one NHWC tensor or the channel
-// concatenation [X1 | X2]: element (m = pixel, k = tap * (C1 + C2) + c) with
-// tap = 3 (dy + 1) + (dx + 1).  flip mirrors the tap (dy, dx) -> (-dy, -dx);
-// mask, if set, zeroes values whose ReLU output (same shape as X1) is not
-// positive.
-struct Im2col {
-    static constexpr bool KMAJ = true;
-    const bf16* X1;
-    const bf16* X2;
-    const bf16* mask;
-    Grid g;
-    int C1, C2, flip;
-    FastDiv fC;  // C1 + C2
-    __device__ __forceinline__ bool locate(i64 m, i64 k, i64& p, int& c) const {
-        const uint32_t kk = (uint32_t)k;
-        int tap = (int)fC.div(kk);
-        c = (int)(kk - (uint32_t)tap * fC.d);
-        if (flip) tap = 8 - tap;
-        int b, h, w;
-        g.split((uint32_t)m, b, h, w);
-        const int t3 = tap / 3;
-        h += t3 - 1;
-        w += tap - 3 * t3 - 1;
-        if (h < 0 || h >= g.H || w < 0 || w >= g.W) return false;
-        p = ((i64)b * g.H + h) * g.W + w;
-        return true;
-    }
-    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const {
-        i64 p;
-        int c;
-        if (!locate(m, k, p, c)) return (bf16)0.f;
-        if (c < C1) {
-            if (mask && !((float)mask[p * C1 + c] > 0.f)) return (bf16)0.f;
-            return X1[p * C1 + c];
-        }
-        return X2[p * C2 + (c - C1)];
-    }
-    struct Row {
-        int b, h, w;
-    };
-    __device__ __forceinline__ Row row(i64 m) const {
-        Row r;
-        g.split((uint32_t)m, r.b, r.h, r.w);
-        return r;
-    }
-    __device__ __forceinline__ bf16x8 vec(const Row& r, i64, i64 k) const {
-        const uint32_t kk = (uint32_t)k;
-        int tap = (int)fC.div(kk);
-        const int c = (int)(kk - (uint32_t)tap * fC.d);
-        if (flip) tap = 8 - tap;
-        const int t3 = tap / 3;
-        const int h = r.h + t3 - 1, w = r.w + tap - 3 * t3 - 1;
-        if (h < 0 || h >= g.H || w < 0 || w >= g.W) return zero8();
-        const i64 p = ((i64)r.b * g.H + h) * g.W + w;
-        if (c < C1) {
-            const bf16x8 v = ld8(X1 + p * C1 + c);
-            return mask ? masked8(v, ld8(mask + p * C1 + c)) : v;
-        }
-        return ld8(X2 + p * C2 + (c - C1));
-    }
-};
-inline Im2col make_im2col(const bf16* X1, const bf16* X2, const bf16* mask, Grid g, int C1, int C2, int flip) {
-    return Im2col{X1, X2, mask, g, C1, C2, flip, fastdiv((uint32_t)(C1 + C2))};
-}
-
-// B of the convolution: element (n = co, k) = Wb[n * K + k] (weights [Co][9][Cp]);
-// and of the transposed convolution: element (n = (2a + b) Co + co, k = ci)
+// B of the transposed convolution: element (n = (2a + b) Co + co, k = ci) = Wb[n * K + k]
 struct RowsK {
     static constexpr bool KMAJ = true;
     const bf16* P;
@@ -190,70 +127,6 @@ struct RowsK {
     struct Row {};
     __device__ __forceinline__ Row row(i64) const { return Row{}; }
     __device__ __forceinline__ bf16x8 vec(const Row&, i64 n, i64 k) const { return ld8(P + n * K + k); }
-};
-
-// B of the convolution's data gradient: element (n = ci, k = tap * Co + co) =
-// Wb[co][tap][ci] (the taps are mirrored by the Im2col of dY)
-struct ConvWT {
-    static constexpr bool KMAJ = false;
-    const bf16* Wb;
-    int Co, Cp;
-    FastDiv fCo;
-    __device__ __forceinline__ i64 at(i64 n, i64 k) const {
-        const uint32_t kk = (uint32_t)k, tap = fCo.div(kk), co = kk - tap * (uint32_t)Co;
-        return ((i64)co * 9 + tap) * Cp + n;
-    }
-    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return Wb[at(n, k)]; }
-    struct Row {};
-    __device__ __forceinline__ Row row(i64) const { return Row{}; }
-    __device__ __forceinline__ bf16x8 vec(const Row&, i64 n, i64 k) const { return ld8(Wb + at(n, k)); }
-};
-
-// A of the convolution's weight gradient: element (m = co, k = pixel) =
-// dY[pixel][co], zeroed where the ReLU output Y is not positive
-struct DYmasked {
-    static constexpr bool KMAJ = false;
-    const bf16* dY;
-    const bf16* Y;
-    int Co;
-    __device__ __forceinline__ bf16 elem(i64 m, i64 k) const {
-        const i64 i = k * Co + m;
-        return (float)Y[i] > 0.f ? dY[i] : (bf16)0.f;
-    }
-    struct Row {};
-    __device__ __forceinline__ Row row(i64) const { return Row{}; }
-    __device__ __forceinline__ bf16x8 vec(const Row&, i64 m, i64 k) const {
-        const i64 i = k * Co + m;
-        return masked8(ld8(dY + i), ld8(Y + i));
-    }
-};
-
-// B of the convolution's weight gradient: element (n, k = pixel) = im2col
-// (pixel, n) for n < 9 (C1 + C2), and 1 for n = 9 (C1 + C2) (the bias column)
-struct Im2colOnes {
-    static constexpr bool KMAJ = false;
-    Im2col a;
-    i64 nbias;
-    __device__ __forceinline__ bf16 elem(i64 n, i64 k) const { return n == nbias ? (bf16)1.f : a.elem(k, n); }
-    struct Row {
-        int c, dy, dx;
-    };
-    __device__ __forceinline__ Row row(i64 n) const {  // tap and channel of column n (n < nbias)
-        const uint32_t nn = (uint32_t)(n < nbias ? n : 0), tap = a.fC.div(nn);
-        const int t3 = (int)tap / 3;
-        return Row{(int)(nn - tap * a.fC.d), t3 - 1, (int)tap - 3 * t3 - 1};
-    }
-    __device__ __forceinline__ bf16x8 vec(const Row& r, i64, i64 k) const {
-        // a vector along n lies within one tap (C1, C2 multiples of 8)
-        int b, h, w;
-        a.g.split((uint32_t)k, b, h, w);
-        h += r.dy;
-        w += r.dx;
-        if (h < 0 || h >= a.g.H || w < 0 || w >= a.g.W) return zero8();
-        const i64 p = ((i64)b * a.g.H + h) * a.g.W + w;
-        if (r.c < a.C1) return ld8(a.X1 + p * a.C1 + r.c);
-        return ld8(a.X2 + p * a.C2 + (r.c - a.C1));
-    }
 };
 
 // A of the transposed convolution: element (m = pixel, k = ci) = X[pixel][ci]
@@ -751,6 +624,212 @@ __global__ void __launch_bounds__(256 * G) k_wgrad3x3(const bf16* __restrict__ d
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution and its data gradient, tap-blocked through LDS
+// ---------------------------------------------------------------------------
+// out[p][n] = epi(sum over taps u and input channels c of In[p + s(u)][c] B(n, u, c))
+// with In = [X1 | X2] (C1 + C2 = Cin channels; zero outside the image and,
+// when mask is set, where mask <= 0), s(u) = (u / 3 - 1, u % 3 - 1), and
+//   forward (WT = false): B(n, u, c) = W[n][u][c]       (n = output channel)
+//   data gradient (WT):   B(n, u, c) = W[c][8 - u][n]   (n = input channel of the forward)
+// for BF16 weights W [Co][9][Cp].  The pixels are cut into segments of BM
+// pixels of one image row; a workgroup owns BN channels and a strided set
+// of segments, and runs through the stages of all of them in one pipeline
+// (the next stage's loads in flight during the current stage's MFMAs, across
+// segment boundaries too).  A stage is (32 input channels, one tap row dy)
+// of a segment: the input row h + dy - 1 over BM + 2 pixels and the weights
+// of the three taps of that row, so each staged input row feeds the three
+// taps from LDS.  Workgroup ids are dealt to the 8 XCDs round-robin; the
+// segment slots are permuted so that each XCD works on one contiguous band
+// of segments (neighbouring rows share its L2).
+__device__ __forceinline__ int xcd_slot(unsigned b, unsigned G) {
+    const unsigned q = G >> 3, r = G & 7u, xcd = b & 7u, loc = b >> 3;
+    return (int)((xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc);
+}
+
+template <int TM, int TN, bool WT, class EPI>
+__global__ void __launch_bounds__(256) k_conv3x3(const bf16* __restrict__ X1, const bf16* __restrict__ X2,
+                                                 const bf16* __restrict__ mask, int C1, int C2,
+                                                 const bf16* __restrict__ Wb, int Cp, int Nout, Grid g, int segs_row,
+                                                 int nsegs, EPI epi) {
+    constexpr int BM = 32 * TM, BN = 32 * TN, XW = BM + 2, XC = BK + 8;
+    constexpr int WC = WT ? BN + 8 : BK + 8, WR = WT ? BK : BN;  // per tap: [WR][WC]
+    constexpr int XS = XW * XC, WS = 3 * WR * WC;
+    constexpr int NVX = XW * BK / 8, NVW = 3 * BN * BK / 8;
+    constexpr int RX = (NVX + 255) / 256, RW = (NVW + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 Xs[2][XS];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[2][WS];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int slot = xcd_slot(blockIdx.x, gridDim.x), stride = (int)gridDim.x;
+    const int n0 = blockIdx.y * BN, Cin = C1 + C2;
+    const int wm = (wave >> 1) * 16 * TM, wn = (wave & 1) * 16 * TN;
+    const int nst = 3 * ((Cin + BK - 1) / BK);  // stages per segment: (channel chunk, dy)
+    const int total = slot < nsegs ? ((nsegs - 1 - slot) / stride + 1) * nst : 0;
+
+    floatx4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // stage k of this workgroup: segment slot + (k / nst) stride, (chunk, dy) from k % nst
+    auto locate = [&](int k, int& b, int& h, int& w0, int& cc, int& dy) {
+        const int ks = k / nst, kk = k - ks * nst;
+        const int seg = slot + ks * stride, row = seg / segs_row;
+        w0 = (seg - row * segs_row) * BM;
+        b = row / g.H;
+        h = row - b * g.H;
+        cc = (kk / 3) * BK;
+        dy = kk - (kk / 3) * 3;
+    };
+    bf16x8 rx[RX], rw[RW];
+    auto fetch = [&](int k) {
+        int b, h, w0, cc, dy;
+        locate(k, b, h, w0, cc, dy);
+        const int hh = h + dy - 1;
+        const bool hin = hh >= 0 && hh < g.H;
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const int v = tid + 256 * r;
+            if (NVX % 256 == 0 || v < NVX) {
+                const int j = v / (BK / 8), cv = (v % (BK / 8)) * 8;
+                const int w = w0 + j - 1, c = cc + cv;
+                rx[r] = zero8();
+                if (hin && w >= 0 && w < g.W && c < Cin) {
+                    const i64 p = ((i64)b * g.H + hh) * g.W + w;
+                    if (c < C1) {
+                        const bf16x8 x = ld8(X1 + p * C1 + c);
+                        rx[r] = mask ? masked8(x, ld8(mask + p * C1 + c)) : x;
+                    } else {
+                        rx[r] = ld8(X2 + p * C2 + (c - C1));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int v = tid + 256 * r;
+            if (NVW % 256 == 0 || v < NVW) {
+                rw[r] = zero8();
+                if constexpr (!WT) {  // [dx][n][c]: 8 consecutive c of output channel n
+                    const int dx = v / (BN * BK / 8), rem = v - dx * (BN * BK / 8);
+                    const int n = rem / (BK / 8), cv = (rem % (BK / 8)) * 8;
+                    const int co = n0 + n, c = cc + cv;
+                    if (co < Nout && c < Cin) rw[r] = ld8(Wb + ((i64)co * 9 + 3 * dy + dx) * Cp + c);
+                } else {  // [dx][c][n]: 8 consecutive n (forward input channels) of channel c
+                    const int dx = v / (BN * BK / 8), rem = v - dx * (BN * BK / 8);
+                    const int c = rem / (BN / 8), nv = (rem % (BN / 8)) * 8;
+                    const int co = cc + c, ci = n0 + nv;
+                    if (co < Cin && ci < Nout) rw[r] = ld8(Wb + ((i64)co * 9 + 8 - (3 * dy + dx)) * Cp + ci);
+                }
+            }
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < RX; ++r) {
+            const int v = tid + 256 * r;
+            if (NVX % 256 == 0 || v < NVX) {
+                const int j = v / (BK / 8), cv = (v % (BK / 8)) * 8;
+                *reinterpret_cast<bf16x8*>(&Xs[st][j * XC + cv]) = rx[r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int v = tid + 256 * r;
+            if (NVW % 256 == 0 || v < NVW) {
+                const int dx = v / (BN * BK / 8), rem = v - dx * (BN * BK / 8);
+                int a, e;
+                if constexpr (!WT) {
+                    a = rem / (BK / 8);
+                    e = (rem % (BK / 8)) * 8;
+                } else {
+                    a = rem / (BN / 8);
+                    e = (rem % (BN / 8)) * 8;
+                }
+                *reinterpret_cast<bf16x8*>(&Ws[st][(dx * WR + a) * WC + e]) = rw[r];
+            }
+        }
+    };
+
+    if (total > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    int st = 0;
+    const int kg = (lane >> 4) * 8, rl = lane & 15;
+    for (int k = 0; k < total; ++k) {
+        const bool more = k + 1 < total;
+        if (more) fetch(k + 1);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            bf16x8 a[TM], bv[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&Xs[st][(wm + 16 * i + rl + dx) * XC + kg]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (!WT) bv[j] = *reinterpret_cast<const bf16x8*>(&Ws[st][(dx * WR + wn + 16 * j + rl) * WC + kg]);
+                else bv[j] = ld_tr8(&Ws[st][dx * WR * WC + wn + 16 * j], WC, lane);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (k % nst == nst - 1) {  // the segment is complete: write it, start the next from zero
+            int b, h, w0, cc, dy;
+            locate(k, b, h, w0, cc, dy);
+            const i64 prow = ((i64)b * g.H + h) * g.W;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int w = w0 + wm + 16 * i + (lane >> 4) * 4 + q;
+                    if (w < g.W) {
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) epi(prow + w, n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (more) stash(st ^ 1);
+        __syncthreads();
+        st ^= 1;
+    }
+}
+
+// One tap-blocked convolution pass: segments of 128 pixels (64 on rows of
+// 64, 32 on rows of at most 32), 64 channels per workgroup (32 when there are
+// at most 32), one segment per workgroup
+template <bool WT, class EPI>
+void conv3x3(hipStream_t s, const bf16* X1, const bf16* X2, const bf16* mask, int C1, int C2, const bf16* Wb, int Cp,
+             int Nout, const Grid& g, const EPI& e) {
+    const int bm = g.W > 64 ? 128 : g.W > 32 ? 64 : 32;
+    const int segs_row = (g.W + bm - 1) / bm, nsegs = g.B * g.H * segs_row;
+    const bool narrow = Nout <= 32;
+    const dim3 grid((unsigned)nsegs, narrow ? 1u : (unsigned)((Nout + 63) / 64));
+#define LBM_CONV(tm, tn) \
+    k_conv3x3<tm, tn, WT, EPI><<<grid, 256, 0, s>>>(X1, X2, mask, C1, C2, Wb, Cp, Nout, g, segs_row, nsegs, e)
+    if (bm == 128) {
+        if (narrow) LBM_CONV(4, 1);
+        else LBM_CONV(4, 2);
+    } else if (bm == 64) {
+        if (narrow) LBM_CONV(2, 1);
+        else LBM_CONV(2, 2);
+    } else {
+        if (narrow) LBM_CONV(1, 1);
+        else LBM_CONV(1, 2);
+    }
+#undef LBM_CONV
+}
+
 // K split into z chunks (multiples of BK); returns the number of chunks launched
 inline i64 kchunk_of(i64 K, int z) {
     const i64 c = ((K + z - 1) / z + BK - 1) / BK * BK;
@@ -801,39 +880,44 @@ inline int blocks_for(i64 n) {
     return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
-inline int reduce_blocks(i64 outputs) {  // 64 outputs per workgroup
-    const i64 b = (outputs + 63) / 64;
-    return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
-}
 
 #define GRID_STRIDE(i, n) \
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (i64)gridDim.x * blockDim.x)
 
-// Sum over k of P[k][i] for the 64 outputs i = base + lane of a workgroup:
-// its four waves add interleaved quarters of k, combined in a fixed order
-// (deterministic); valid in wave 0.
-__device__ __forceinline__ float zsum64(const float* __restrict__ P, int z, i64 MN, i64 idx, float (*red)[64]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Sum over k of P[k][i] for the OUT outputs i = base + (thread % OUT) of a
+// workgroup: its 256 / OUT slices of threads add interleaved parts of k,
+// combined in slice order (deterministic); valid in the first OUT threads.
+// OUT = 16 when there are many partials (more workgroups, more loads in
+// flight), 64 otherwise.
+template <int OUT>
+__device__ __forceinline__ float zsum(const float* __restrict__ P, int z, i64 MN, i64 idx, float* red) {
+    constexpr int NS = 256 / OUT;
+    const int o = threadIdx.x % OUT, sl = threadIdx.x / OUT;
     float s = 0.f;
-    if (idx < MN)
-        for (int k = wave; k < z; k += 4) s += P[(i64)k * MN + idx];
-    red[wave][lane] = s;
+    if (idx < MN) {
+#pragma unroll 4
+        for (int k = sl; k < z; k += NS) s += P[(i64)k * MN + idx];
+    }
+    red[sl * OUT + o] = s;
     __syncthreads();
-    const float t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    float t = 0.f;
+    if (sl == 0)
+        for (int k = 0; k < NS; ++k) t += red[k * OUT + o];
     __syncthreads();
     return t;
 }
 
 // split-K partials of a convolution's weight gradient, [z][Co][9 Cp + 1], summed
 // into gw [Co][9][Ci] (channels >= Ci are padding) and gb [Co]
+template <int OUT>
 __global__ void __launch_bounds__(256) k_reduce_conv(const float* __restrict__ P, int z, int Co, int Cp, int Ci,
                                                      float* __restrict__ gw, float* __restrict__ gb) {
-    __shared__ float red[4][64];
+    __shared__ float red[256];
     const i64 N1 = 9LL * Cp + 1, MN = (i64)Co * N1;
-    for (i64 base = (i64)blockIdx.x * 64; base < MN; base += (i64)gridDim.x * 64) {
-        const i64 idx = base + (threadIdx.x & 63);
-        const float s = zsum64(P, z, MN, idx, red);
-        if (threadIdx.x < 64 && idx < MN) {
+    for (i64 base = (i64)blockIdx.x * OUT; base < MN; base += (i64)gridDim.x * OUT) {
+        const i64 idx = base + (threadIdx.x % OUT);
+        const float s = zsum<OUT>(P, z, MN, idx, red);
+        if (threadIdx.x < OUT && idx < MN) {
             const i64 co = idx / N1, n = idx - co * N1;
             if (n == 9LL * Cp) {
                 gb[co] = s;
@@ -847,19 +931,25 @@ __global__ void __launch_bounds__(256) k_reduce_conv(const float* __restrict__ P
 
 // partials of a transposed convolution's weight gradient, [z][4 Co][Ci + 1]:
 // the weight columns into gw [4 Co][Ci]; the ones column into T [4 Co]
+template <int OUT>
 __global__ void __launch_bounds__(256) k_reduce_up(const float* __restrict__ P, int z, int Co, int Ci,
                                                    float* __restrict__ gw, float* __restrict__ T) {
-    __shared__ float red[4][64];
+    __shared__ float red[256];
     const i64 N1 = Ci + 1, MN = 4LL * Co * N1;
-    for (i64 base = (i64)blockIdx.x * 64; base < MN; base += (i64)gridDim.x * 64) {
-        const i64 idx = base + (threadIdx.x & 63);
-        const float s = zsum64(P, z, MN, idx, red);
-        if (threadIdx.x < 64 && idx < MN) {
+    for (i64 base = (i64)blockIdx.x * OUT; base < MN; base += (i64)gridDim.x * OUT) {
+        const i64 idx = base + (threadIdx.x % OUT);
+        const float s = zsum<OUT>(P, z, MN, idx, red);
+        if (threadIdx.x < OUT && idx < MN) {
             const i64 r = idx / N1, c = idx - r * N1;
             if (c < Ci) gw[r * Ci + c] = s;
             else T[r] = s;
         }
     }
+}
+
+inline int reduce_blocks(i64 outputs, int per) {  // per outputs per workgroup
+    const i64 b = (outputs + per - 1) / per;
+    return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
 }
 
 // transposed-convolution bias gradient: the four offsets of each channel, in order
@@ -1239,10 +1329,8 @@ void refresh_bf16(lbm_unet* u) {
 // y = relu(conv3x3([x1 | x2]) + b); x1 holds C1 channels (Cp - Ci2 of them)
 void conv_fwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, bf16* y, int l) {
     const i64 P = pixels(u, l);
-    const Im2col A = make_im2col(x1, x2, nullptr, grid_of(u, l), c.Cp - c.Ci2, c.Ci2, 0);
-    RowsK B{c.wb, 9LL * c.Cp};
     EpiBiasRelu e{y, u->w + c.b.off, P, c.Co};
-    gemm(u->stream, A, B, e, P, c.Co, 9LL * c.Cp);
+    conv3x3<false>(u->stream, x1, x2, nullptr, c.Cp - c.Ci2, c.Ci2, c.wb, c.Cp, c.Co, grid_of(u, l), e);
 }
 
 // split-K partials of a convolution's weight and bias gradients into u->part
@@ -1271,15 +1359,19 @@ void conv_bwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const 
     const i64 P = pixels(u, l);
     const Grid g = grid_of(u, l);
     if (dx1) {
-        const Im2col A = make_im2col(dy, nullptr, y, g, c.Co, 0, 1);
-        ConvWT B{c.wb, c.Co, c.Cp, fastdiv((uint32_t)c.Co)};
         EpiSplit e{dx1, dx2, P, c.Ci1, c.Ci2};
-        gemm(u->stream, A, B, e, P, (i64)c.Ci1 + c.Ci2, 9LL * c.Co);
+        conv3x3<true>(u->stream, dy, nullptr, y, c.Co, 0, c.wb, c.Cp, c.Ci1 + c.Ci2, g, e);
     }
     const i64 N1 = 9LL * c.Cp + 1;
     const int nz = wgrad3x3(u, c, x1, x2, y, dy, g);
-    k_reduce_conv<<<reduce_blocks((i64)c.Co * N1), 256, 0, u->stream>>>(u->part, nz, c.Co, c.Cp, c.Ci1 + c.Ci2,
-                                                                        u->g + c.w.off, u->g + c.b.off);
+    if (nz >= 32)
+        k_reduce_conv<16><<<reduce_blocks((i64)c.Co * N1, 16), 256, 0, u->stream>>>(u->part, nz, c.Co, c.Cp,
+                                                                                     c.Ci1 + c.Ci2, u->g + c.w.off,
+                                                                                     u->g + c.b.off);
+    else
+        k_reduce_conv<64><<<reduce_blocks((i64)c.Co * N1, 64), 256, 0, u->stream>>>(u->part, nz, c.Co, c.Cp,
+                                                                                     c.Ci1 + c.Ci2, u->g + c.w.off,
+                                                                                     u->g + c.b.off);
 }
 
 void up_fwd(lbm_unet* u, const Up& p, const bf16* x, bf16* y, int lin) {
@@ -1303,8 +1395,13 @@ void up_bwd(lbm_unet* u, const Up& p, const bf16* x, const bf16* dy, bf16* dx, i
     const int z = splits_for(4LL * p.Co, N1, P, u->part_n);
     EpiPartial e2{u->part, 4LL * p.Co, N1};
     launch_gemm<64, 64>(u->stream, A2, B2, e2, 4LL * p.Co, N1, P, z);
-    k_reduce_up<<<reduce_blocks(4LL * p.Co * N1), 256, 0, u->stream>>>(u->part, nchunks(P, z), p.Co, p.Ci,
-                                                                       u->g + p.w.off, u->upb);
+    const int nz = nchunks(P, z);
+    if (nz >= 32)
+        k_reduce_up<16><<<reduce_blocks(4LL * p.Co * N1, 16), 256, 0, u->stream>>>(u->part, nz, p.Co, p.Ci,
+                                                                                   u->g + p.w.off, u->upb);
+    else
+        k_reduce_up<64><<<reduce_blocks(4LL * p.Co * N1, 64), 256, 0, u->stream>>>(u->part, nz, p.Co, p.Ci,
+                                                                                   u->g + p.w.off, u->upb);
     k_up_bias<<<(p.Co + 255) / 256, 256, 0, u->stream>>>(u->upb, p.Co, u->g + p.b.off);
 }
 
