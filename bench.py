@@ -234,7 +234,7 @@ def unet_bench(args):
         "data": "synthetic",
         "config": {"workload": f"warm-start U-Net training step, batch {B}, 256x256, 4 inputs",
                    "params": net.n_params, "fwd_gflop_per_sample": round(WS.forward_flops(H, W) / 1e9, 3)},
-        "roofline": {"bound": "mfma", "kernel": "all k_gemm launches of a training step (HIP events on its stream)",
+        "roofline": {"bound": "mfma", "kernel": "whole training step, every kernel (HIP events on its stream)",
                      "achieved": round(tflops, 1), "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 4),
                      "traffic": None},
     }

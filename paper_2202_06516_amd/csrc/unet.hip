@@ -442,33 +442,35 @@ __global__ void __launch_bounds__(256) k_gemm(LA A, LB B, EPI epi, i64 M, i64 N,
 // (zero outside the image).  The reduction runs over segments of 32 pixels
 // of one image row: a stage holds dYm of the segment ([32][BM] per pixel)
 // and X of the three rows around it ([3][34][BN]), so each X element read
-// from memory feeds the nine taps from LDS.  A workgroup is G groups of four
+// from memory feeds the nine taps from LDS.  A workgroup is G groups of W
 // waves; group q takes every G-th segment of the chunk with stages of its
 // own, and the groups' sums are added in LDS in group order at the end
-// (deterministic).  Within a group the waves are 2 x 2, each 16 TM x 16 TN of
+// (deterministic).  Within a group the W waves share the BM = 16 TM output
+// channels and split the BN = 16 TN W input channels, each 16 TM x 16 TN of
 // (co, c) for every tap; both operands enter the MFMA through the transposing
 // LDS read.
 constexpr int SEG = 32;  // pixels per segment = one MFMA K step
 
-template <int TM, int TN, int G>
-__global__ void __launch_bounds__(256 * G) k_wgrad3x3(const bf16* __restrict__ dY, const bf16* __restrict__ Y,
+template <int TM, int TN, int W, int G>
+__global__ void __launch_bounds__(64 * W * G) k_wgrad3x3(const bf16* __restrict__ dY, const bf16* __restrict__ Y,
                                                       const bf16* __restrict__ X1, const bf16* __restrict__ X2,
                                                       int C1, int C2, int Co, Grid g, int segs_row, int nsegs,
                                                       int spc, float* __restrict__ P) {
-    constexpr int BM = 32 * TM, BN = 32 * TN, DC = BM + 8, XC = BN + 8, XW = SEG + 2;
+    constexpr int NT = 64 * W;  // threads per group
+    constexpr int BM = 16 * TM, BN = 16 * TN * W, DC = BM + 8, XC = BN + 8, XW = SEG + 2;
     constexpr int NVD = SEG * BM / 8, NVX = 3 * XW * BN / 8;
-    constexpr int RD = (NVD + 255) / 256, RX = (NVX + 255) / 256;
+    constexpr int RD = (NVD + NT - 1) / NT, RX = (NVX + NT - 1) / NT;
     constexpr int DS = SEG * DC, XS = 3 * XW * XC;  // elements per stage
     __shared__ __attribute__((aligned(16))) bf16 lds[G * 2 * (DS + XS)];
     static_assert(BM * BN * 4 <= G * 2 * (DS + XS) * 2, "reduction buffer");
 
-    const int q = threadIdx.x >> 8, tid = threadIdx.x & 255, lane = tid & 63, wave = tid >> 6;
+    const int q = threadIdx.x / NT, tid = threadIdx.x % NT, lane = tid & 63, wave = tid >> 6;
     bf16* Ds = lds + q * 2 * (DS + XS);  // this group's two stages: Ds[st], then Xs[st]
     bf16* Xs = Ds + 2 * DS;
     const int co0 = blockIdx.x * BM, c0 = blockIdx.y * BN, Cp = C1 + C2;
     const int s0 = blockIdx.z * spc, s1 = min(nsegs, s0 + spc);
     const int iters = (s1 - s0 + G - 1) / G;  // the same for every group (barriers)
-    const int wm = (wave >> 1) * 16 * TM, wn = (wave & 1) * 16 * TN;
+    const int wm = 0, wn = wave * 16 * TN;
     const bool bias = blockIdx.y == 0;
 
     floatx4 acc[9][TM][TN];
@@ -486,8 +488,8 @@ __global__ void __launch_bounds__(256 * G) k_wgrad3x3(const bf16* __restrict__ d
         const int b = row / g.H, h = row - b * g.H;
 #pragma unroll
         for (int r = 0; r < RD; ++r) {
-            const int v = tid + 256 * r;
-            if (NVD % 256 == 0 || v < NVD) {
+            const int v = tid + NT * r;
+            if (NVD % NT == 0 || v < NVD) {
                 const int px = v / (BM / 8), cv = (v % (BM / 8)) * 8;
                 const int w = w0 + px, co = co0 + cv;
                 rd[r] = zero8();
@@ -499,8 +501,8 @@ __global__ void __launch_bounds__(256 * G) k_wgrad3x3(const bf16* __restrict__ d
         }
 #pragma unroll
         for (int r = 0; r < RX; ++r) {
-            const int v = tid + 256 * r;
-            if (NVX % 256 == 0 || v < NVX) {
+            const int v = tid + NT * r;
+            if (NVX % NT == 0 || v < NVX) {
                 const int dr = v / (XW * BN / 8), rem = v - dr * (XW * BN / 8);
                 const int j = rem / (BN / 8), cv = (rem % (BN / 8)) * 8;
                 const int hh = h + dr - 1, w = w0 + j - 1, c = c0 + cv;
@@ -515,16 +517,16 @@ __global__ void __launch_bounds__(256 * G) k_wgrad3x3(const bf16* __restrict__ d
     auto stash = [&](int st) {
 #pragma unroll
         for (int r = 0; r < RD; ++r) {
-            const int v = tid + 256 * r;
-            if (NVD % 256 == 0 || v < NVD) {
+            const int v = tid + NT * r;
+            if (NVD % NT == 0 || v < NVD) {
                 const int px = v / (BM / 8), cv = (v % (BM / 8)) * 8;
                 *reinterpret_cast<bf16x8*>(&Ds[st * DS + px * DC + cv]) = rd[r];
             }
         }
 #pragma unroll
         for (int r = 0; r < RX; ++r) {
-            const int v = tid + 256 * r;
-            if (NVX % 256 == 0 || v < NVX) {
+            const int v = tid + NT * r;
+            if (NVX % NT == 0 || v < NVX) {
                 const int dr = v / (XW * BN / 8), rem = v - dr * (XW * BN / 8);
                 const int j = rem / (BN / 8), cv = (rem % (BN / 8)) * 8;
                 *reinterpret_cast<bf16x8*>(&Xs[st * XS + (dr * XW + j) * XC + cv]) = rx[r];
@@ -1334,21 +1336,28 @@ void conv_fwd(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, bf16* 
 }
 
 // split-K partials of a convolution's weight and bias gradients into u->part
-// ([z][Co][9 Cp + 1]); returns z.  32 x 32 channel tiles, four groups of four
-// waves per workgroup, about 256 workgroups (one per compute unit) and at
-// least two segments per group, so that the partials stay near 9 MB.
+// ([z][Co][9 Cp + 1]); returns z.  Tiles of 32 output by 64 input channels
+// (four waves per group, three groups) or, for at most 32 input channels, 32
+// by 32 (two waves per group, six groups): 12 waves per workgroup; about 256
+// workgroups (one per compute unit) and at least two segments per group, so
+// that the partials stay small.
 int wgrad3x3(lbm_unet* u, const Conv& c, const bf16* x1, const bf16* x2, const bf16* y, const bf16* dy, const Grid& g) {
-    constexpr int G = 4;
+    const bool wide = c.Cp > 32;
+    const int BN = wide ? 64 : 32, G = wide ? 3 : 6;
     const int segs_row = (g.W + SEG - 1) / SEG, nsegs = g.B * g.H * segs_row;
-    const int tiles = ((c.Co + 31) / 32) * ((c.Cp + 31) / 32);
+    const int tiles = ((c.Co + 31) / 32) * ((c.Cp + BN - 1) / BN);
     const i64 N1 = 9LL * c.Cp + 1;
     int z = std::max(1, std::min((256 + tiles - 1) / tiles, nsegs / (2 * G)));
     z = (int)std::min<i64>(z, std::max<i64>(1, u->part_n / ((i64)c.Co * N1)));
     const int spc = (nsegs + z - 1) / z;
     z = (nsegs + spc - 1) / spc;  // every chunk holds at least one segment
-    const dim3 grid((unsigned)((c.Co + 31) / 32), (unsigned)((c.Cp + 31) / 32), (unsigned)z);
-    k_wgrad3x3<1, 1, G><<<grid, 256 * G, 0, u->stream>>>(dy, y, x1, x2, c.Cp - c.Ci2, c.Ci2, c.Co, g, segs_row, nsegs,
-                                                         spc, u->part);
+    const dim3 grid((unsigned)((c.Co + 31) / 32), (unsigned)((c.Cp + BN - 1) / BN), (unsigned)z);
+    if (wide)
+        k_wgrad3x3<2, 1, 4, 3><<<grid, 768, 0, u->stream>>>(dy, y, x1, x2, c.Cp - c.Ci2, c.Ci2, c.Co, g, segs_row,
+                                                            nsegs, spc, u->part);
+    else
+        k_wgrad3x3<2, 1, 2, 6><<<grid, 768, 0, u->stream>>>(dy, y, x1, x2, c.Cp - c.Ci2, c.Ci2, c.Co, g, segs_row,
+                                                            nsegs, spc, u->part);
     return z;
 }
 
