@@ -84,6 +84,7 @@ def check_against_oracle(levels, base, H, W, n, seed, batch=None, fwd_tol=1e-2, 
     (2, 8, 12, 20, 3),      # pooling, transposed convolution, skip; 720 pixels: ragged tiles
     (3, 16, 32, 24, 2),
     (2, 32, 10, 6, 1),      # tiny: every tile ragged, level 1 is 5 x 3
+    (2, 16, 6, 80, 2),      # rows of 80 and 40 pixels: ragged 128-, 64- and 32-pixel segments
 ])
 def test_small_networks_match_the_oracle(levels, base, H, W, n):
     check_against_oracle(levels, base, H, W, n, seed=100 + levels * 10 + n)
