@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per k_collide launch from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000) counters,
 # scaled by a plain-copy calibration; valid only for the kernel as it stands when they were taken
 # (profiles/k_collide_d3q19_f32_256cube.md).  Keyed by (lattice side, precision, collision).
-COUNTED_TRAFFIC = {(256, "f32", "bgk"): 3.381e9}
+COUNTED_TRAFFIC = {(256, "f32", "bgk"): 3.284e9}
 
 
 def parse():
@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--precision", default="f32", choices=["f32", "f32mixed", "f64"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
     ap.add_argument("--profile-steps", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps at full size (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps at full size (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="sessile3d", choices=["sessile3d", "batch", "unet"],
                     help="sessile3d: the 256^3 D3Q19 benchmark; batch: 512 seeded D2Q9 cases in one batch; "

@@ -519,11 +519,11 @@ __global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const 
 // ---------------------------------------------------------------------------
 // collision + push streaming
 // ---------------------------------------------------------------------------
-template <class L, typename R, typename C, bool MRT>
+template <class L, typename R, typename C, bool MRT, bool NT>
 __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
                                               R* __restrict__ o, long long N);
 
-template <class L, typename R, typename C, bool PULL, bool MRT>
+template <class L, typename R, typename C, bool PULL, bool MRT, bool NT = false>
 __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __restrict__ fout,
                                              const R* __restrict__ rho, const R* __restrict__ mu,
                                              const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
@@ -561,13 +561,25 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
         Fy += r0 * (D)cp.g[1];
         Fz += r0 * (D)cp.g[2];
     }
-    collide_apply<L, R, C, MRT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
+    collide_apply<L, R, C, MRT, NT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
 }
 
 // Collision of one fluid node from its gathered populations S and the force
 // F (Eq. 7, plus the body force): MRT or BGK relaxation with exact-difference
 // forcing; post-collision populations stored at the node, o[i * N].
-template <class L, typename R, typename C, bool MRT>
+// A store of one post-collision population: non-temporal (NT) where the
+// lattice is swept in whole aligned rows, so that the stream does not evict
+// the density and chemical-potential planes the stencils re-read (the
+// populations are next read one step later, after the whole lattice has
+// passed through the caches); plain for the batched solver, whose ragged rows
+// would turn into partial-line writes.
+template <bool NT, typename R>
+__device__ __forceinline__ void put(R* p, R v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <class L, typename R, typename C, bool MRT, bool NT>
 __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
                                               R* __restrict__ o, long long N) {
     typedef double D;
@@ -599,7 +611,7 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
             const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
             const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
             const C fi = (C)S[i];
-            o[(size_t)i * sN] = (R)(fi - om * (fi - feq) + (feq2 - feq));
+            put<NT>(&o[(size_t)i * sN], (R)(fi - om * (fi - feq) + (feq2 - feq)));
         }
     } else {
         // MRT (Eq. 1): non-conserved moments of f - f_eq relaxed by s_k and
@@ -632,7 +644,7 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
             }
         }
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) o[(size_t)i * sN] = (R)out[i];
+        for (int i = 0; i < L::Q; ++i) put<NT>(&o[(size_t)i * sN], (R)out[i]);
     }
 }
 
@@ -643,7 +655,7 @@ __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* _
                                                  Collision<C> cp, const DevCtl* __restrict__ ctl) {
     int x, y, z;
     tile_node(d, x, y, z);
-    collide_node<L, R, C, PULL, MRT>(fin, fout, rho, mu, cls, d, bc, cp, ctl->t, x, y, z);
+    collide_node<L, R, C, PULL, MRT, true>(fin, fout, rho, mu, cls, d, bc, cp, ctl->t, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
