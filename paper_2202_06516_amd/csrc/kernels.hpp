@@ -428,19 +428,25 @@ __device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict
                                         const Dims& d, const Thermo& th, int x, int y, int z, bool in, R& r0) {
     r0 = R(0);
     if (!in) return false;
+    // the class and the density stencil are loaded together (every offset is
+    // in bounds: periodic images), and the class decides only the store
     const long long idx = nid(d, x, y, z);
-    if ((cls[idx] & CLS_MASK) != CLS_FLUID) return false;
-    r0 = rho[idx];
+    const uint8_t c = cls[idx];
     const R* p = rho + idx;
+    const R rc = p[0];
     const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
-    const C c0 = (C)r0;
+    const C c0 = (C)rc;
     C lap = d2c<C>(p[ox.m2], p[ox.m1], c0, p[ox.p1], p[ox.p2]);
     lap += d2c<C>(p[oy.m2], p[oy.m1], c0, p[oy.p1], p[oy.p2]);
     if (L::D == 3) {
         const Nbr oz = nbr_offsets(z, d.nz, d.nx * d.ny);
         lap += d2c<C>(p[oz.m2], p[oz.m1], c0, p[oz.p1], p[oz.p2]);
     }
-    mu[idx] = (R)((psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap);
+    const C m = (psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap;
+    asm volatile("" : : "v"(m));  // keeps the loads above the class test
+    if ((c & CLS_MASK) != CLS_FLUID) return false;
+    r0 = rc;
+    mu[idx] = (R)m;
     return true;
 }
 
@@ -531,12 +537,10 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     if (x >= d.nx || y >= d.ny) return;
     const long long idx = nid(d, x, y, z);
     const uint8_t c = cls[idx];
-    if ((c & CLS_MASK) != CLS_FLUID) return;
 
-    R S[L::Q];
-    gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
-
-    // Eq. 7 with fourth-order central differences.  The two terms of F cancel
+    // Eq. 7 with fourth-order central differences, formed before the class
+    // test so that the stencil loads go out with the class load (every offset
+    // is in bounds: periodic images).  The two terms of F cancel
     // almost exactly inside an interface at rest, so F, and the moments it
     // shifts, are formed in double precision whatever the storage type.
     typedef double D;
@@ -561,6 +565,11 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
         Fy += r0 * (D)cp.g[1];
         Fz += r0 * (D)cp.g[2];
     }
+    asm volatile("" : : "v"(Fx), "v"(Fy), "v"(Fz));  // keeps the loads above the class test
+    if ((c & CLS_MASK) != CLS_FLUID) return;
+
+    R S[L::Q];
+    gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
     collide_apply<L, R, C, MRT, NT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
 }
 
