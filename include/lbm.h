@@ -290,6 +290,13 @@ lbm_status lbm_batch_write(lbm_batch* b, int case_index, int field, const void* 
 lbm_status lbm_batch_get_info(lbm_batch* b, lbm_batch_info* info);
 /* Re-run the autotuner (the state is unchanged). */
 lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path);
+/* Advance every case nsteps steps (no measurement) with a HIP event pair
+ * around each launch of kb_density, kb_mu and kb_collide, and report their
+ * mean duration in milliseconds: names[i] (static strings) and ms[i] for
+ * i < *n_kinds (cap entries at most).  Synchronises.  Errors: LBM_E_ARG,
+ * LBM_E_STATE before any initial state, LBM_E_DEVICE, LBM_E_NONFINITE. */
+lbm_status lbm_batch_profile_step(lbm_batch* b, int64_t nsteps, const char** names, double* ms, int cap,
+                                  int* n_kinds);
 const char* lbm_batch_last_error(const lbm_batch* b);
 
 /* ------------------------------------------------------------------------

@@ -319,15 +319,19 @@ struct BRun {
         bc.bouzidi = b->cfg.bc_mode == LBM_BC_BOUZIDI_MC;
         return bc;
     }
-    static void density(lbm_batch* b, bool pull, int grid) {
+    // ev, if set, holds event pairs recorded around kb_density (0, 1), kb_mu
+    // (2, 3) and kb_collide (4, 5) on the batch's stream
+    static void density(lbm_batch* b, bool pull, int grid, hipEvent_t* ev = nullptr) {
         const R* f = (const R*)b->f[b->cur];
         const R inv_b = (R)(1.0 / b->pr.b);
+        if (ev) (void)hipEventRecord(ev[0], b->stream);
         if (pull)
             kb_density<L, R, C, true><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, f, (R*)b->rho,
                                                                    b->cls, wall(b), b->ctl, b->slots, b->mp, inv_b);
         else
             kb_density<L, R, C, false><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, f, (R*)b->rho,
                                                                     b->cls, wall(b), b->ctl, b->slots, b->mp, inv_b);
+        if (ev) (void)hipEventRecord(ev[1], b->stream);
         const int ng1 = (b->n_l1 + 255) / 256, ng2 = (b->n_l2 + 255) / 256;
         if (b->n_l1)
             kb_fill<L, R, C><<<ng1 < grid ? ng1 : grid, 256, 0, b->stream>>>(b->fnode, b->fmask, (const R*)b->inv, b->fcase,
@@ -337,13 +341,15 @@ struct BRun {
                 b->fnode, b->fmask, (const R*)b->inv, b->fcase, b->n_l1, b->n_l1 + b->n_l2, (R*)b->rho, b->dims);
     }
     // one step from f[src] (pull form if pull) into f[1 - src]
-    static void step(lbm_batch* b, int src, bool pull, int grid) {
+    static void step(lbm_batch* b, int src, bool pull, int grid, hipEvent_t* ev = nullptr) {
         const int save = b->cur;
         b->cur = src;
-        density(b, pull, grid);
+        density(b, pull, grid, ev);
         b->cur = save;
+        if (ev) (void)hipEventRecord(ev[2], b->stream);
         kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
                                                     b->cls, thermo(b));
+        if (ev) (void)hipEventRecord(ev[3], b->stream);
         kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
                                                     b->ctl, b->slots, b->mp);
         const R* fin = (const R*)b->f[src];
@@ -352,6 +358,7 @@ struct BRun {
         const Collision<C> cp = collision(b);
         const bool mrt = b->cfg.collision == LBM_MRT;
 #define KB_ARGS b->items, b->nitems, b->dims, b->tile_w, fin, fout, (const R*)b->rho, (const R*)b->mu, b->cls, bc, cp, b->ctl
+        if (ev) (void)hipEventRecord(ev[4], b->stream);
         if (pull) {
             if (mrt) kb_collide<L, R, C, true, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
             else kb_collide<L, R, C, true, false><<<grid, 256, 0, b->stream>>>(KB_ARGS);
@@ -360,6 +367,7 @@ struct BRun {
             else kb_collide<L, R, C, false, false><<<grid, 256, 0, b->stream>>>(KB_ARGS);
         }
 #undef KB_ARGS
+        if (ev) (void)hipEventRecord(ev[5], b->stream);
         kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
         kb_tick<<<1, 64, 0, b->stream>>>(b->ctl);
     }
@@ -395,6 +403,12 @@ void bdispatch(lbm_batch* b, Args&&... args) {
 template <class L, typename R, typename C>
 struct BStep {
     static void go(lbm_batch* b, int src, bool pull, int grid) { BRun<L, R, C>::step(b, src, pull, grid); }
+};
+template <class L, typename R, typename C>
+struct BStepTimed {
+    static void go(lbm_batch* b, int src, bool pull, int grid, hipEvent_t* ev) {
+        BRun<L, R, C>::step(b, src, pull, grid, ev);
+    }
 };
 template <class L, typename R, typename C>
 struct BDerive {
@@ -816,6 +830,49 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int measure_every) {
     while (done < nsteps) eager();
     BCHK(b, hipGetLastError());
     return LBM_OK;
+}
+
+lbm_status lbm_batch_profile_step(lbm_batch* b, int64_t nsteps, const char** names, double* ms, int cap,
+                                  int* n_kinds) {
+    static const char* kNames[3] = {"kb_density", "kb_mu", "kb_collide"};
+    if (!b || !names || !ms || !n_kinds || cap < 0) return LBM_E_ARG;
+    if (!b->have_state) return bfail(b, LBM_E_STATE, "batch profile: no state");
+    if (nsteps < 1) return bfail(b, LBM_E_ARG, "batch profile: nsteps >= 1");
+    k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 0);
+    BCHK(b, hipGetLastError());
+    hipEvent_t ev[6];
+    int made = 0;
+    for (auto& e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) break;
+        ++made;
+    }
+    if (made < 6) {
+        for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+        return bfail(b, LBM_E_DEVICE, "batch profile: hipEventCreate failed");
+    }
+    double tot[3] = {0, 0, 0};
+    hipError_t err = hipSuccess;
+    for (int64_t t = 0; t < nsteps && err == hipSuccess; ++t) {
+        bdispatch<BStepTimed>(b, b->cur, b->fstar, grid_of(b), ev);
+        b->cur ^= 1;
+        b->fstar = true;
+        ++b->t;
+        err = hipStreamSynchronize(b->stream);
+        for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+            float e = 0;
+            err = hipEventElapsedTime(&e, ev[2 * k], ev[2 * k + 1]);
+            tot[k] += e;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch profile: ") + hipGetErrorString(err));
+    int n = 0;
+    for (int k = 0; k < 3 && n < cap; ++k, ++n) {
+        names[n] = kNames[k];
+        ms[n] = tot[k] / (double)nsteps;
+    }
+    *n_kinds = n;
+    return lbm_batch_sync(b);
 }
 
 lbm_status lbm_batch_sync(lbm_batch* b) {

@@ -114,7 +114,7 @@ EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
            "lbm_get_info", "lbm_profile_step", "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy",
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read",
-           "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_last_error",
+           "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step", "lbm_batch_last_error",
            "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
            "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward",
            "lbm_unet_train_step", "lbm_unet_set_lr", "lbm_unet_save", "lbm_unet_load", "lbm_unet_encode",
@@ -164,6 +164,7 @@ def lib():
     L.lbm_batch_write.argtypes = [vp, i, i, vp, C.c_size_t, i]
     L.lbm_batch_get_info.argtypes = [vp, P(lbm_batch_info)]
     L.lbm_batch_tune.argtypes = [vp, C.c_char_p]
+    L.lbm_batch_profile_step.argtypes = [vp, i64, P(C.c_char_p), P(d), i, P(i)]
     L.lbm_batch_last_error.restype = C.c_char_p
     L.lbm_batch_last_error.argtypes = [vp]
     L.lbm_unet_config_default.restype = None
@@ -195,7 +196,7 @@ def lib():
                  "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
                  "lbm_get_info", "lbm_profile_step", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_step",
                  "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read", "lbm_batch_write",
-                 "lbm_batch_get_info", "lbm_batch_tune"):
+                 "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -485,6 +486,14 @@ class Batch:
 
     def tune(self, cache_path=None):
         self._check(lib().lbm_batch_tune(self._h, cache_path.encode() if cache_path else None))
+
+    def profile(self, nsteps):
+        """Mean ms per launch of kb_density, kb_mu and kb_collide over nsteps eager steps."""
+        names = (C.c_char_p * 8)()
+        ms = (C.c_double * 8)()
+        n = C.c_int()
+        self._check(lib().lbm_batch_profile_step(self._h, int(nsteps), names, ms, 8, C.byref(n)))
+        return {names[i].decode(): ms[i] for i in range(n.value)}
 
 
 class Unet:
