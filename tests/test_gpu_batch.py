@@ -130,3 +130,19 @@ def test_device_writes_equal_host_writes(precision):
     s_host.step(25)
     s_dev.step(25)
     assert np.array_equal(s_host.f, s_dev.f)
+
+
+def test_profiled_steps_are_ordinary_steps():
+    # lbm_batch_profile_step times the three main kernels over eager steps; the
+    # state it leaves equals that of the same number of ordinary steps
+    cases = small_cases(3, seed=13)
+    a = G.Batch(cases, precision=G.LBM_F32, **PHYS)
+    c = G.Batch(cases, precision=G.LBM_F32, **PHYS)
+    prof = a.profile(7)
+    assert set(prof) == {"kb_density", "kb_mu", "kb_collide"}
+    assert all(v > 0.0 for v in prof.values())
+    c.step(7)
+    c.sync()
+    assert a.info()["step"] == c.info()["step"] == 7
+    for i in range(len(cases)):
+        assert np.array_equal(a.read(i, G.FIELD_F), c.read(i, G.FIELD_F))
