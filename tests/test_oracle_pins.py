@@ -360,3 +360,52 @@ def test_no_liquid_no_contact_line():
     o.set_rho(np.full(o.shape, o.info()["rho_g"]))
     a = o.measure()
     assert a.status == -6 and math.isnan(a.mean_deg)
+
+
+# ------------------------------------------------------------ Laplace's law
+
+
+def _bulk_roots(mu_hat, T, alpha, k):
+    """Gas and liquid densities whose bulk chemical potential k^2 psi'(rho) is mu_hat."""
+    from scipy.optimize import brentq
+    g = lambda r: k * k * O.pr_mu(r, T, alpha) - mu_hat  # noqa: E731
+    grid = np.linspace(1e-3, 1.0 / O.PR_B - 1e-3, 4000)
+    vals = np.array([g(r) for r in grid])
+    idx = np.nonzero(np.sign(vals[:-1]) != np.sign(vals[1:]))[0]
+    assert len(idx) == 3, "chemical potential outside the two-phase window"
+    return (brentq(g, grid[idx[0]], grid[idx[0] + 1], xtol=1e-15),
+            brentq(g, grid[idx[-1]], grid[idx[-1] + 1], xtol=1e-15))
+
+
+def test_laplace_law_free_drops():
+    """Laplace's law for a free drop (2-D: Delta p = gamma / R).
+
+    Drops of three radii relax in periodic boxes.  At equilibrium the
+    chemical potential is uniform (the force of Eq. 7 vanishes where mu is
+    constant; on the lattice up to about a tenth of its rise mu - mu_sat, so
+    the mean of the liquid and gas values is used); the pressure jump follows from the Peng-Robinson bulk pressures
+    of the liquid and the gas that have that chemical potential (Gibbs-Duhem),
+    and R is the equimolar radius.  Laplace's law holds if R Delta p, the
+    surface tension, is the same for every drop.
+    """
+    Tr, k, kappa = 0.8, 0.28, 0.01
+    mx = O.maxwell(Tr)
+    T, al = mx["T"], mx["alpha"]
+    gam = []
+    for R, n in ((12, 64), (16, 72), (24, 96)):
+        o = O.Oracle(2, (n, n), (0, 0), Tr=Tr, k=k, kappa=kappa)
+        o.init_drops([(n / 2, n / 2)], [R], W=10.0)
+        o.step(4000)
+        o.update_derived()
+        rho, mu = o.rho.reshape(n, n), o.mu.reshape(n, n)
+        mu_in, mu_out = mu[n // 2, n // 2], mu[0, 0]
+        dmu = 0.5 * (mu_in + mu_out) - k * k * mx["mu_sat"]
+        # raised by the curvature, and uniform up to the discretisation's residual
+        assert dmu > 0 and abs(mu_in - mu_out) < 0.15 * dmu
+        rg, rl = _bulk_roots(0.5 * (mu_in + mu_out), T, al, k)
+        assert abs(rho[0, 0] / rg - 1) < 0.02 and abs(rho[n // 2, n // 2] / rl - 1) < 0.02
+        dp = k * k * (O.pr_p0(rl, T, al) - O.pr_p0(rg, T, al))
+        Re = math.sqrt(((rho - rg) / (rl - rg)).sum() / math.pi)
+        assert abs(Re / R - 1) < 0.1
+        gam.append(dp * Re)
+    assert max(gam) / min(gam) - 1 < 0.04, gam
