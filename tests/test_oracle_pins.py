@@ -409,3 +409,57 @@ def test_laplace_law_free_drops():
         assert abs(Re / R - 1) < 0.1
         gam.append(dp * Re)
     assert max(gam) / min(gam) - 1 < 0.04, gam
+
+
+# ------------------------------------------------------ brute force on 8 x 8
+
+
+def test_one_step_matches_brute_force_on_8x8():
+    """One whole step of a periodic 8 x 8 D2Q9 lattice without solids, computed
+    by brute force with array shifts: rho, the chemical potential of Eq. 12
+    (fourth-order Laplacian), the force of Eq. 7 (fourth-order gradients), the
+    MRT collision of Eq. 1 in the moment basis built from its polynomials, the
+    exact-difference forcing of Eq. 13, and the streaming of Eq. 4."""
+    Tr, k, kappa, tau, s_e, s_eps, s_q = 0.8, 0.28, 0.01, 1.0, 1.64, 1.54, 1.9
+    o = O.Oracle(2, (8, 8), Tr=Tr, k=k, kappa=kappa, tau=tau, s_e=s_e, s_eps=s_eps, s_q=s_q)
+    rng = np.random.Generator(np.random.PCG64(8))
+    o.set_rho(rng.uniform(0.3, 6.5, o.shape))
+    o.step(1)                                     # a state with non-equilibrium parts
+    f = o.f.copy()[:, 0]                          # [Q][y][x]
+    inf = o.info()
+    e, w = O.lattice(2)
+    ex, ey = e[:, 0].astype(float), e[:, 1].astype(float)
+
+    def sh(a, dx, dy):                            # a(x + dx, y + dy), periodic
+        return np.roll(np.roll(a, -dy, axis=0), -dx, axis=1)
+
+    def d1(a, ax):
+        s = (lambda j: sh(a, j, 0)) if ax == 0 else (lambda j: sh(a, 0, j))
+        return (s(-2) - 8 * s(-1) + 8 * s(1) - s(2)) / 12.0
+
+    def lap(a):
+        return sum((-sh(a, 2 * dx, 2 * dy) + 16 * sh(a, dx, dy) - 30 * a + 16 * sh(a, -dx, -dy)
+                    - sh(a, -2 * dx, -2 * dy)) / 12.0 for dx, dy in ((1, 0), (0, 1)))
+
+    rho = f.sum(0)
+    psi1 = np.vectorize(lambda r: O.pr_mu(r, inf["T"], inf["alpha"]))(rho)
+    mu = k * k * psi1 - kappa * lap(rho)
+    Fx = -rho * d1(mu, 0) + d1(rho, 0) / 3.0
+    Fy = -rho * d1(mu, 1) + d1(rho, 1) / 3.0
+    ux = np.tensordot(ex, f, 1) / rho
+    uy = np.tensordot(ey, f, 1) / rho
+
+    def feq(vx, vy):
+        eu = ex[:, None, None] * vx + ey[:, None, None] * vy
+        return w[:, None, None] * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * (vx ** 2 + vy ** 2))
+
+    c2 = ex ** 2 + ey ** 2
+    M = np.array([np.ones(9), -4 + 3 * c2, 4 - 10.5 * c2 + 4.5 * c2 ** 2, ex, (-5 + 3 * c2) * ex,
+                  ey, (-5 + 3 * c2) * ey, ex ** 2 - ey ** 2, ex * ey])
+    S = np.diag([0, s_e, s_eps, 0, s_q, 0, s_q, 1 / tau, 1 / tau])
+    f0, f1 = feq(ux, uy), feq(ux + Fx / rho, uy + Fy / rho)
+    m, meq = np.tensordot(M, f, 1), np.tensordot(M, f0, 1)
+    post = np.tensordot(np.linalg.inv(M), m - np.tensordot(S, m - meq, 1), 1) + f1 - f0
+    new = np.array([sh(post[i], -int(ex[i]), -int(ey[i])) for i in range(9)])   # f_i(x) = f*_i(x - e_i)
+    o.step(1)
+    assert np.max(np.abs(o.f[:, 0] - new)) < 1e-13 * np.max(np.abs(new))
