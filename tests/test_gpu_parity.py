@@ -185,3 +185,21 @@ def test_bad_arguments():
     with pytest.raises(G.LbmError) as e:
         gp.step(1)
     assert e.value.status == G.LBM_E_STATE
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tiny_periodic_lattices_match_the_oracle(dim):
+    # 8 x 8 (x 8) without solids: every tile ragged, every neighbour offset wraps
+    n = (8, 8, 8) if dim == 3 else (8, 8)
+    wl = dict(dim=dim, n=n, wall=(0,) * dim, solids=[], drops=[], Tr=0.8)
+    gp = gpu_lattice(wl, G.LBM_F64)
+    o = oracle_lattice(wl)
+    rng = np.random.Generator(np.random.PCG64(88 + dim))
+    idx = np.indices(o.shape).astype(float)
+    rho0 = 2.5 + 1.5 * np.sin(2 * np.pi * idx[-1] / 8) * np.cos(2 * np.pi * idx[-2] / 8) \
+        + rng.uniform(-0.05, 0.05, o.shape)
+    gp.write(G.FIELD_RHO, rho0)
+    o.set_rho(rho0)
+    gp.step(12)
+    o.step(12)
+    fields_close(gp, o, 1e-12)

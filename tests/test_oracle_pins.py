@@ -354,6 +354,48 @@ def test_wedge_drop_measured_exactly(theta0):
         assert abs(a.contact[s][1] - (60 + 60 * math.cos(math.asin(0.5)))) < 1e-9
 
 
+@pytest.mark.parametrize("mu_w", [-0.01, 0.1])
+def test_relaxed_drop_agrees_with_spherical_cap(mu_w):
+    # Sec. IV A: without gravity the drop relaxes to a circular cap, and the
+    # spherical-cap method gives its angle from the base length L (between the
+    # two contact points) and the height H above that chord: R0 = (4 H^2 +
+    # L^2) / 8 H, tan(beta) = L / 2 (R0 - H), theta = beta - alpha on a convex
+    # substrate, alpha the half-angle of the chord seen from the substrate
+    # centre.  The in-step measurement uses only the interface within 2.5 lu of
+    # the substrate; the cap method uses the whole drop.
+    wl = W.sessile_2d(mu_w=mu_w)                      # 128^2, cylinder 24, drop 20, Tr = 0.6
+    o = O.Oracle(2, wl["n"], (0, 0), Tr=wl["Tr"], k=0.28, kappa=0.01)
+    sol = wl["solids"][0]
+    o.add_sphere(sol["center"], sol["radius"], mu_w=mu_w)
+    o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=10.0)
+    o.step(8000)
+    a = o.measure()
+    assert a.status == 0 and a.n_valid == 2
+    o.update_derived()
+    nx, ny = wl["n"]
+    rho, cls = o.rho.reshape(ny, nx), o.cls.reshape(ny, nx)
+    inf = o.info()
+    rm = 0.5 * (inf["rho_l"] + inf["rho_g"])
+    pts = []
+    for dx, dy in ((1, 0), (0, 1)):                   # rho_m crossings on fluid-fluid links
+        r0, r1 = rho[: ny - dy, : nx - dx], rho[dy:, dx:]
+        ok = (cls[: ny - dy, : nx - dx] == 0) & (cls[dy:, dx:] == 0) & ((r0 - rm) * (r1 - rm) < 0)
+        yy, xx = np.nonzero(ok)
+        t = (rm - r0[ok]) / (r1[ok] - r0[ok])
+        pts.append(np.c_[xx + t * dx, yy + t * dy])
+    pts = np.vstack(pts)
+    cs, Rs = np.array(sol["center"][:2]), sol["radius"]
+    c1, c2 = np.array(a.contact[0][:2]), np.array(a.contact[1][:2])
+    L = np.linalg.norm(c2 - c1)
+    mid = 0.5 * (c1 + c2)
+    up = (mid - cs) / np.linalg.norm(mid - cs)
+    H = float(np.max((pts - mid) @ up))
+    R0 = (4 * H * H + L * L) / (8 * H)
+    beta = math.degrees(math.atan2(L, 2 * (R0 - H)))
+    alpha = math.degrees(math.asin(0.5 * L / Rs))
+    assert abs(a.mean_deg - (beta - alpha)) < 1.5, (a.mean_deg, beta - alpha)
+
+
 def test_no_liquid_no_contact_line():
     o = O.Oracle(2, (40, 40))
     o.add_sphere((20, 10), 6, mu_w=0.0)
