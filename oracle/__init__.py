@@ -58,6 +58,14 @@ class Angle(C.Structure):
         return np.array(self.sector_deg[: self.n_sectors])
 
 
+class Young(C.Structure):
+    _fields_ = [
+        ("step", C.c_longlong), ("status", C.c_int), ("n_sectors", C.c_int),
+        ("count", (C.c_int * 2) * 64), ("phi_d", C.c_double * 64), ("theta_eq_deg", C.c_double * 64),
+        ("force", C.c_double * 64),
+    ]
+
+
 _lib = None
 
 
@@ -87,6 +95,7 @@ def lib():
         L.ora_step.argtypes = [v, C.c_longlong]
         L.ora_step_measured.argtypes = [v, C.c_longlong, i, i, i, d, p(Angle), i, p(i)]
         L.ora_measure.argtypes = [v, i, i, d, p(Angle)]
+        L.ora_young_force.argtypes = [v, i, i, d, d, d, d, d, d, d, p(Angle), p(Young)]
         L.ora_field.restype = v; L.ora_field.argtypes = [v, i]
         L.ora_update_derived.argtypes = [v]
         L.ora_velocity.argtypes = [v, p(d)]
@@ -256,6 +265,14 @@ class Oracle:
         a = Angle()
         lib().ora_measure(self._h, solid, n_sectors, float(rho_m), C.byref(a))
         return a
+
+    def young_force(self, gamma, theta1_deg, theta2_deg, roughness=1.0, band=(0.1, 0.9), solid=0, n_sectors=2,
+                    rho_m=0.0):
+        """Eq. 17 / Eq. 18 per sector on a measurement made now: (Angle, Young)."""
+        a, y = Angle(), Young()
+        lib().ora_young_force(self._h, solid, n_sectors, float(rho_m), float(band[0]), float(band[1]), float(gamma),
+                              float(theta1_deg), float(theta2_deg), float(roughness), C.byref(a), C.byref(y))
+        return a, y
 
     def _view(self, which, count, dtype=np.float64):
         ptr = lib().ora_field(self._h, which)

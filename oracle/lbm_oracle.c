@@ -846,6 +846,37 @@ static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1]
 
 typedef struct { double key_val; unsigned long long key; double p[3]; } cand_t;
 
+/* measurement frame about the drop axis a: b1 = the lattice axis least aligned
+ * with a (|a_k| compared on a 1/1024 grid, ties to the lower axis),
+ * orthogonalised; b2 = a x b1 */
+static void frame_of(int dim, const double a[3], double b1[3], double b2[3]) {
+    int kb = 0;
+    long best = 1L << 40;
+    for (int d = 0; d < dim; ++d) {
+        long qv = lround(fabs(a[d]) * 1024.0);
+        if (qv < best) { best = qv; kb = d; }
+    }
+    for (int d = 0; d < 3; ++d) b1[d] = 0.0;
+    b1[kb] = 1.0;
+    double ab = dot3(a, b1);
+    for (int d = 0; d < 3; ++d) b1[d] -= ab * a[d];
+    double bn = sqrt(dot3(b1, b1));
+    for (int d = 0; d < 3; ++d) b1[d] /= bn;
+    b2[0] = a[1] * b1[2] - a[2] * b1[1];
+    b2[1] = a[2] * b1[0] - a[0] * b1[2];
+    b2[2] = a[0] * b1[1] - a[1] * b1[0];
+}
+
+/* sector of a position r relative to the substrate centre (2-D: the side of the axis) */
+static int sector_of(int dim, const double r[3], const double b1[3], const double b2[3], int n_sectors) {
+    if (dim == 2) return dot3(r, b1) >= 0.0 ? 0 : 1;
+    double psi = atan2(dot3(r, b2), dot3(r, b1));
+    int sec = (int)floor((psi + M_PI) / (2.0 * M_PI) * n_sectors);
+    if (sec >= n_sectors) sec -= n_sectors;
+    if (sec < 0) sec = 0;
+    return sec;
+}
+
 int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* out) {
     memset(out, 0, sizeof *out);
     out->step = c->step;
@@ -877,23 +908,8 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
     if (an == 0) { a[0] = 0; a[1] = c->dim == 2 ? 1 : 0; a[2] = c->dim == 2 ? 0 : 1; }
     else for (int d = 0; d < 3; ++d) a[d] /= an;
     for (int d = 0; d < 3; ++d) out->axis[d] = a[d];
-    /* frame: lattice axis least aligned with a (|a_k| compared on a 1/1024 grid,
-     * ties to the lower axis), orthogonalised; b2 = a x b1 */
-    int kb = 0;
-    long best = 1L << 40;
-    for (int d = 0; d < c->dim; ++d) {
-        long qv = lround(fabs(a[d]) * 1024.0);
-        if (qv < best) { best = qv; kb = d; }
-    }
-    double b1[3] = {0, 0, 0}, b2[3];
-    b1[kb] = 1.0;
-    double ab = dot3(a, b1);
-    for (int d = 0; d < 3; ++d) b1[d] -= ab * a[d];
-    double bn = sqrt(dot3(b1, b1));
-    for (int d = 0; d < 3; ++d) b1[d] /= bn;
-    b2[0] = a[1] * b1[2] - a[2] * b1[1];
-    b2[1] = a[2] * b1[0] - a[0] * b1[2];
-    b2[2] = a[0] * b1[1] - a[1] * b1[0];
+    double b1[3], b2[3];
+    frame_of(c->dim, a, b1, b2);
 
     /* all liquid-gas links between fluid nodes; crossing by Eq. 15 */
     cand_t best1[64], best2[64];
@@ -910,15 +926,7 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
             double dist = sqrt(dot3(r, r)) - pr->r;
             if (!(dist >= 0.5 && dist < 2.5)) continue;
             int band = dist < 1.5 ? 1 : 2;
-            int sec;
-            if (c->dim == 2) {
-                sec = dot3(r, b1) >= 0.0 ? 0 : 1;
-            } else {
-                double psi = atan2(dot3(r, b2), dot3(r, b1));
-                sec = (int)floor((psi + M_PI) / (2.0 * M_PI) * n_sectors);
-                if (sec >= n_sectors) sec -= n_sectors;
-                if (sec < 0) sec = 0;
-            }
+            int sec = sector_of(c->dim, r, b1, b2, n_sectors);
             float kv = (float)fabs(dist - band);
             uint32_t bits;
             memcpy(&bits, &kv, 4);
@@ -997,5 +1005,71 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
         out->rec_deg = out->sector_deg[sr];
     }
     out->status = 0;
+    return 0;
+}
+
+/* Unbalanced Young force at the contact lines (Sec. IV E, Eq. 17) with the
+ * equilibrium angle of the modified Cassie-Baxter relation (Eq. 18).
+ *
+ * Reading: the isodensity lines of the diffuse interface end on the substrate
+ * over a footprint; in each sector the footprint is the set of fluid nodes
+ * next to the substrate (a lattice neighbour inside the primitive) whose
+ * density lies between rho_g + band_lo (rho_l - rho_g) and rho_g + band_hi
+ * (rho_l - rho_g).  phi_d is the share of those nodes over the mu_w surface
+ * (stripe index even, or a uniform primitive), 1 - phi_d over the mu_w2
+ * surface.  The angle and the sectors are those of the measurement made on
+ * the same density. */
+static int surface_kind(const ora_prim* pr, const double r[3]) {
+    if (pr->wet_mode == 0) return 0;
+    double rn = sqrt(dot3(r, r));
+    double cosp = rn > 0 ? dot3(r, pr->pole) / rn : 1.0;
+    if (cosp > 1) cosp = 1;
+    if (cosp < -1) cosp = -1;
+    long long stripe = (long long)floor(pr->r * acos(cosp) / pr->width);
+    return (int)(stripe % 2);
+}
+
+int ora_young_force(ora_ctx* c, int solid, int n_sectors, double rho_m, double band_lo, double band_hi,
+                    double gamma, double theta1_deg, double theta2_deg, double roughness,
+                    ora_angle* angle, ora_young* out) {
+    memset(out, 0, sizeof *out);
+    for (int s = 0; s < 64; ++s) out->phi_d[s] = out->theta_eq_deg[s] = out->force[s] = NAN;
+    int st = ora_measure(c, solid, n_sectors, rho_m, angle);
+    out->step = angle->step;
+    out->n_sectors = angle->n_sectors;
+    out->status = st;
+    if (st != 0) return st;
+    const ora_prim* pr = &c->prim[solid];
+    double b1[3], b2[3];
+    frame_of(c->dim, angle->axis, b1, b2);
+    const double lo = c->rho_g + band_lo * (c->rho_l - c->rho_g), hi = c->rho_g + band_hi * (c->rho_l - c->rho_g);
+    for (long long n = 0; n < c->N; ++n) {
+        if (c->cls[n] != C_FLUID || !(c->rho[n] >= lo && c->rho[n] <= hi)) continue;
+        int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
+        int touches = 0;
+        for (int i = 1; i < c->Q && !touches; ++i) {
+            int X = x + c->e[i][0], Y = y + c->e[i][1], Z = z + c->e[i][2];
+            X = (X + c->nx) % c->nx;
+            Y = (Y + c->ny) % c->ny;
+            Z = (Z + c->nz) % c->nz;
+            touches = inside_prim(pr, X, Y, Z);
+        }
+        if (!touches) continue;
+        double r[3] = {x - pr->c[0], y - pr->c[1], c->dim == 3 ? z - pr->c[2] : 0.0};
+        out->count[sector_of(c->dim, r, b1, b2, angle->n_sectors)][surface_kind(pr, r)]++;
+    }
+    const double c1 = cos(theta1_deg * M_PI / 180.0), c2 = cos(theta2_deg * M_PI / 180.0);
+    for (int s = 0; s < angle->n_sectors; ++s) {
+        int tot = out->count[s][0] + out->count[s][1];
+        if (tot == 0) continue;
+        double phi = (double)out->count[s][0] / tot;
+        double ce = roughness * phi * c1 + (1.0 - phi) * c2;
+        if (ce > 1) ce = 1;
+        if (ce < -1) ce = -1;
+        out->phi_d[s] = phi;
+        out->theta_eq_deg[s] = acos(ce) * 180.0 / M_PI;
+        if (!isnan(angle->sector_deg[s]))
+            out->force[s] = gamma * (cos(angle->sector_deg[s] * M_PI / 180.0) - ce);
+    }
     return 0;
 }

@@ -76,6 +76,24 @@ int  ora_step_measured(ora_ctx* c, long long nsteps, int every, int solid, int n
                        double rho_m, ora_angle* series, int cap, int* n_written);
 int  ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* out);
 
+/* Unbalanced Young force per sector (Sec. IV E, Eq. 17) with the equilibrium
+ * angle of Eq. 18, on a measurement made here on the same density (written to
+ * *angle).  The footprint of a sector: fluid nodes with a lattice neighbour
+ * inside the primitive and a density in [rho_g + band_lo (rho_l - rho_g),
+ * rho_g + band_hi (rho_l - rho_g)]; count[s][0] on the mu_w surface (even
+ * stripe or uniform), count[s][1] on mu_w2; phi_d = count[s][0] / total. */
+typedef struct {
+    long long step;
+    int status, n_sectors;
+    int count[64][2];
+    double phi_d[64];           /* NaN without footprint */
+    double theta_eq_deg[64];    /* Eq. 18 */
+    double force[64];           /* Eq. 17; NaN where the sector has no angle */
+} ora_young;
+int  ora_young_force(ora_ctx* c, int solid, int n_sectors, double rho_m, double band_lo, double band_hi,
+                     double gamma, double theta1_deg, double theta2_deg, double roughness,
+                     ora_angle* angle, ora_young* out);
+
 /* fields: 0 f (state, [Q][N]), 1 rho, 2 mu, 3 force ([3][N]), 4 class (uchar), 5 fpost */
 void* ora_field(ora_ctx* c, int which);
 int   ora_update_derived(ora_ctx* c);   /* rho, fill, mu, force of the current state */

@@ -505,3 +505,64 @@ def test_one_step_matches_brute_force_on_8x8():
     new = np.array([sh(post[i], -int(ex[i]), -int(ey[i])) for i in range(9)])   # f_i(x) = f*_i(x - e_i)
     o.step(1)
     assert np.max(np.abs(o.f[:, 0] - new)) < 1e-13 * np.max(np.abs(new))
+
+
+# --------------------------------------------- unbalanced Young force (Eq. 17, 18)
+
+
+def _wedge_on(theta0, stripes=None, slope=1.0):
+    # the wedge drop of the exact-measurement pin on a uniform or striped circle
+    o = O.Oracle(2, (200, 180))
+    o.add_sphere((100, 60), 60, mu_w=0.0, stripes=stripes)
+    inf = o.info()
+    rm = 0.5 * (inf["rho_l"] + inf["rho_g"])
+    o.set_rho(W.wedge_density(o.shape, (100, 60), 60, theta0, rm, inf["rho_g"], inf["rho_l"], slope=slope))
+    return o
+
+
+@pytest.mark.parametrize("theta0", [60, 120])
+def test_young_force_on_a_uniform_surface(theta0):
+    # one surface: phi_d = 1, theta_eq = theta_s1 (Eq. 18 with phi_d = 1, r = 1)
+    # and F = gamma (cos theta - cos theta_s1) (Eq. 17), theta the measured angle
+    o = _wedge_on(theta0)
+    a, y = o.young_force(gamma=0.07, theta1_deg=100.0, theta2_deg=40.0)
+    assert a.status == 0 and y.status == 0 and a.n_valid == 2
+    for s in range(2):
+        assert y.count[s][0] > 0 and y.count[s][1] == 0
+        assert y.phi_d[s] == 1.0
+        assert abs(y.theta_eq_deg[s] - 100.0) < 1e-12
+        ref = 0.07 * (math.cos(math.radians(theta0)) - math.cos(math.radians(100.0)))
+        assert abs(y.force[s] - ref) < 1e-12
+    assert y.count[0][0] == y.count[1][0]        # mirror-symmetric footprints
+
+
+def test_young_force_on_the_second_stripe():
+    # the contact points sit at polar angle 30 deg on the circle of radius 60
+    # (arc length 31.4 from the pole); with stripes 20 wide they lie on stripe
+    # 1 (mu_w2), 11 lu from either border, and so does the whole footprint:
+    # phi_d = 0, theta_eq = theta_s2
+    o = _wedge_on(90, stripes=(0.0, 0.05, 20.0))
+    a, y = o.young_force(gamma=0.05, theta1_deg=70.0, theta2_deg=130.0)
+    assert a.status == 0
+    for s in range(2):
+        assert y.count[s][0] == 0 and y.count[s][1] > 0
+        assert y.phi_d[s] == 0.0 and abs(y.theta_eq_deg[s] - 130.0) < 1e-12
+        ref = 0.05 * (math.cos(math.radians(a.sector_deg[s])) - math.cos(math.radians(130.0)))
+        assert abs(y.force[s] - ref) < 1e-12
+
+
+def test_young_force_at_a_stripe_border():
+    # a border that crosses the footprint splits it (Eq. 18): phi_d strictly
+    # between 0 and 1, and growing as the border moves away from the pole
+    # (more of the footprint on the first stripe); both sides alike by symmetry
+    arc = 60 * math.pi / 6                           # arc length of the contact points
+    phis = []
+    for width in (arc - 1.0, arc, arc + 1.0):
+        o = _wedge_on(90, stripes=(0.0, 0.05, width))
+        a, y = o.young_force(gamma=0.05, theta1_deg=70.0, theta2_deg=130.0)
+        assert y.count[0][0] == y.count[1][0] and y.count[0][1] == y.count[1][1]
+        assert 0.0 < y.phi_d[0] < 1.0
+        c = y.phi_d[0] * math.cos(math.radians(70.0)) + (1 - y.phi_d[0]) * math.cos(math.radians(130.0))
+        assert abs(math.cos(math.radians(y.theta_eq_deg[0])) - c) < 1e-12
+        phis.append(y.phi_d[0])
+    assert phis[0] < phis[1] < phis[2]
