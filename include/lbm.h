@@ -225,7 +225,41 @@ lbm_status lbm_sync(lbm_ctx* ctx);
 
 lbm_status lbm_get_info(lbm_ctx* ctx, lbm_info* info);
 
-/* Step the lattice nsteps times (no measurement) with a HIP event pair
+/* Unbalanced Young force at the contact lines (Sec. IV E, Eq. 17) with the
+ * equilibrium angle of the modified Cassie-Baxter relation (Eq. 18).  The
+ * footprint of a sector is the set of fluid nodes with a lattice neighbour
+ * inside the measured substrate whose density lies between rho_g + band_lo
+ * (rho_l - rho_g) and rho_g + band_hi (rho_l - rho_g): where the diffuse
+ * interface's isodensity lines end on the substrate.  phi_d is the share of
+ * the footprint over the substrate's mu_w surface (a uniform substrate, or its
+ * even latitude stripes), 1 - phi_d over its mu_w2 stripes. */
+typedef struct {
+    double gamma;        /* liquid-gas surface tension, lattice units */
+    double theta1_deg;   /* equilibrium angle of the mu_w surface */
+    double theta2_deg;   /* equilibrium angle of the mu_w2 stripes (unused on a uniform substrate) */
+    double roughness;    /* r of Eq. 18 (1: smooth); > 0 */
+    double band_lo, band_hi;  /* footprint band in (0, 1); 0 and 0 select 0.1 and 0.9 */
+} lbm_young_opts;
+
+typedef struct {
+    int64_t step;        /* t of the density used */
+    int32_t status;      /* LBM_OK or LBM_E_NO_CONTACT_LINE */
+    int32_t n_sectors;
+    int32_t count[LBM_MAX_SECTORS][2];     /* footprint nodes on the mu_w / mu_w2 surface */
+    double phi_d[LBM_MAX_SECTORS];         /* count[s][0] / (count[s][0] + count[s][1]); NaN without footprint */
+    double theta_eq_deg[LBM_MAX_SECTORS];  /* Eq. 18; NaN without footprint */
+    double force[LBM_MAX_SECTORS];         /* Eq. 17: gamma (cos theta_s - cos theta_eq); NaN where either is */
+} lbm_young;
+
+/* Measure now (as lbm_measure_angle with the options of lbm_set_measure; the
+ * angle is written to *angle) and compute, on the same density, the footprint
+ * counts, phi_d, theta_eq and the unbalanced Young force per sector into *out.
+ * Synchronises.  Errors: LBM_E_ARG (null pointer, gamma not finite,
+ * roughness <= 0, band outside 0 < band_lo < band_hi < 1), LBM_E_STATE,
+ * LBM_E_NO_CONTACT_LINE (out->status set, every value NaN), LBM_E_DEVICE. */
+lbm_status lbm_young_force(lbm_ctx* ctx, const lbm_young_opts* opts, lbm_angle* angle, lbm_young* out);
+
+/* Step the lattice nsteps times (no measurement) with a HIP event pair/* Step the lattice nsteps times (no measurement) with a HIP event pair
  * around every kernel launch, and report the mean duration in milliseconds of
  * each kernel kind: names[i] (static strings) and ms[i] for i < *n_kinds
  * (cap entries at most).  Synchronises. */

@@ -51,6 +51,7 @@ struct lbm_ctx {
     int series_capacity = 0;
     double* mass_part = nullptr;
     double* mass_out = nullptr;
+    unsigned* young_counts = nullptr;  // [LBM_MAX_SECTORS][2] footprint counts of lbm_young_force
     bool have_geometry = false, have_state = false;
     std::vector<Solid> solids;
     lbm_measure_opts mopts{0, 32, 0.0};
@@ -274,6 +275,11 @@ struct Run {
         k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->rho, c->ctl, c->d, mp, nullptr, c->last, 0);
     }
 
+    static void young_count(lbm_ctx* c, const YoungParams& yp) {
+        k_young_count<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, yp,
+                                                                            c->young_counts);
+    }
+
     static void init_feq(lbm_ctx* c) {
         k_init_feq<L, R><<<2048, 256, 0, c->stream>>>((const R*)c->rho, (R*)c->f[c->cur], c->cls, c->d.N, 0, c->d.N);
     }
@@ -318,6 +324,10 @@ struct OpVel {
 template <class L, typename R, typename C>
 struct OpMeasure {
     static void go(lbm_ctx* c, const MeasureParams* mp) { Run<L, R, C>::measure_now(c, *mp); }
+};
+template <class L, typename R, typename C>
+struct OpYoung {
+    static void go(lbm_ctx* c, const YoungParams* yp) { Run<L, R, C>::young_count(c, *yp); }
 };
 template <class L, typename R, typename C>
 struct OpInit {
@@ -485,7 +495,8 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         (s = dalloc(c, &c->cls, (size_t)N)) || (s = dalloc(c, &c->nbmask, (size_t)N * 4)) ||
         (s = dalloc(c, &c->bidx, (size_t)N * 4)) ||
         (s = dalloc(c, &c->ctl, sizeof(DevCtl))) || (s = dalloc(c, &c->last, sizeof(AngleRec))) ||
-        (s = dalloc(c, &c->mass_part, kMassBlocks * sizeof(double))) || (s = dalloc(c, &c->mass_out, sizeof(double)))) {
+        (s = dalloc(c, &c->mass_part, kMassBlocks * sizeof(double))) || (s = dalloc(c, &c->mass_out, sizeof(double))) ||
+        (s = dalloc(c, &c->young_counts, 2 * LBM_MAX_SECTORS * sizeof(unsigned)))) {
         lbm_destroy(c);
         return s;
     }
@@ -510,7 +521,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
     drop_graphs(c);
     void* ps[] = {c->f[0], c->f[1], c->rho, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
                   c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
-                  c->mass_part, c->mass_out};
+                  c->mass_part, c->mass_out, c->young_counts};
     for (void* p : ps) dfree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -773,6 +784,62 @@ lbm_status lbm_measure_angle(lbm_ctx* c, const lbm_measure_opts* o, lbm_angle* o
     HIPCHK(c, hipStreamSynchronize(c->stream));
     out->step = c->t;
     if (out->status != 0) return fail(c, LBM_E_NO_CONTACT_LINE, "no sector holds both selected crossings");
+    return LBM_OK;
+}
+
+lbm_status lbm_young_force(lbm_ctx* c, const lbm_young_opts* yo, lbm_angle* angle, lbm_young* out) {
+    if (!c || !yo || !angle || !out) return LBM_E_ARG;
+    double lo = yo->band_lo, hi = yo->band_hi;
+    if (lo == 0.0 && hi == 0.0) {
+        lo = 0.1;
+        hi = 0.9;
+    }
+    if (!std::isfinite(yo->gamma) || !(yo->roughness > 0.0) || !(lo > 0.0 && lo < hi && hi < 1.0))
+        return fail(c, LBM_E_ARG, "young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
+    std::memset(out, 0, sizeof *out);
+    for (int k = 0; k < LBM_MAX_SECTORS; ++k) out->phi_d[k] = out->theta_eq_deg[k] = out->force[k] = NAN;
+    const lbm_status ms = lbm_measure_angle(c, &c->mopts, angle);
+    out->step = angle->step;
+    out->n_sectors = angle->n_sectors;
+    out->status = ms;
+    if (ms != LBM_OK) return ms;
+    // footprint counts on the density the measurement derived
+    const Solid& so = c->solids[c->mopts.solid_index];
+    YoungParams yp{};
+    for (int k = 0; k < 3; ++k) {
+        yp.c[k] = k < c->dim ? so.c[k] : 0.0;
+        yp.pole[k] = so.pole[k];
+        yp.axis[k] = angle->axis[k];
+    }
+    yp.R = so.r;
+    yp.width = so.width;
+    yp.wet_mode = so.wet_mode;
+    yp.n_sectors = angle->n_sectors;
+    yp.dim = c->dim;
+    const double rg = c->pr.rho_g, rl = c->pr.rho_l;
+    yp.lo = rg + lo * (rl - rg);
+    yp.hi = rg + hi * (rl - rg);
+    HIPCHK(c, hipMemsetAsync(c->young_counts, 0, 2 * LBM_MAX_SECTORS * sizeof(unsigned), c->stream));
+    dispatch<OpYoung>(c, &yp);
+    HIPCHK(c, hipGetLastError());
+    unsigned h[2 * LBM_MAX_SECTORS];
+    HIPCHK(c, hipMemcpyAsync(h, c->young_counts, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // Eq. 18 (phi_d the footprint share of the mu_w surface) and Eq. 17, in FP64
+    const double c1 = std::cos(yo->theta1_deg * M_PI / 180.0), c2 = std::cos(yo->theta2_deg * M_PI / 180.0);
+    for (int k = 0; k < angle->n_sectors; ++k) {
+        out->count[k][0] = (int32_t)h[2 * k];
+        out->count[k][1] = (int32_t)h[2 * k + 1];
+        const unsigned tot = h[2 * k] + h[2 * k + 1];
+        if (!tot) continue;
+        const double phi = (double)h[2 * k] / (double)tot;
+        double ce = yo->roughness * phi * c1 + (1.0 - phi) * c2;
+        ce = ce > 1.0 ? 1.0 : (ce < -1.0 ? -1.0 : ce);
+        out->phi_d[k] = phi;
+        out->theta_eq_deg[k] = std::acos(ce) * 180.0 / M_PI;
+        if (!std::isnan(angle->sector_deg[k]))
+            out->force[k] = yo->gamma * (std::cos(angle->sector_deg[k] * M_PI / 180.0) - ce);
+    }
     return LBM_OK;
 }
 

@@ -364,10 +364,32 @@ struct Frame {
     bool ok;
 };
 
-__device__ inline Frame make_frame(const MeasureSlots* ms, const MeasureParams& mp) {
+// frame about the unit drop axis a: b1 = the lattice axis least aligned with
+// a (compared on a 1/1024 grid), orthogonalised; b2 = a x b1
+__device__ inline Frame frame_from_axis(const double a[3], int dim) {
     Frame F;
+    F.ok = true;
+    int kb = 0;
+    long long best = 1ll << 40;
+    for (int k = 0; k < dim; ++k) {
+        long long qv = llround(fabs(a[k]) * 1024.0);
+        if (qv < best) { best = qv; kb = k; }
+    }
+    double b[3] = {0, 0, 0};
+    b[kb] = 1.0;
+    const double ab = a[kb];
+    for (int k = 0; k < 3; ++k) b[k] -= ab * a[k];
+    const double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    for (int k = 0; k < 3; ++k) { F.a[k] = a[k]; F.b1[k] = b[k] / bn; }
+    F.b2[0] = a[1] * F.b1[2] - a[2] * F.b1[1];
+    F.b2[1] = a[2] * F.b1[0] - a[0] * F.b1[2];
+    F.b2[2] = a[0] * F.b1[1] - a[1] * F.b1[0];
+    return F;
+}
+
+// frame of a measurement: the axis from the substrate centre to the liquid centroid
+__device__ inline Frame make_frame(const MeasureSlots* ms, const MeasureParams& mp) {
     const unsigned long long n = ms->cnt;
-    F.ok = n > 0;
     double G[3] = {0, 0, 0};
     if (n) {
         G[0] = (double)ms->sx / (double)n;
@@ -381,22 +403,8 @@ __device__ inline Frame make_frame(const MeasureSlots* ms, const MeasureParams& 
     } else {
         a[0] = 0; a[1] = mp.dim == 2 ? 1.0 : 0.0; a[2] = mp.dim == 2 ? 0.0 : 1.0;
     }
-    // reference axis: the lattice axis least aligned with a, compared on a 1/1024 grid
-    int kb = 0;
-    long long best = 1ll << 40;
-    for (int k = 0; k < mp.dim; ++k) {
-        long long qv = llround(fabs(a[k]) * 1024.0);
-        if (qv < best) { best = qv; kb = k; }
-    }
-    double b[3] = {0, 0, 0};
-    b[kb] = 1.0;
-    const double ab = a[kb];
-    for (int k = 0; k < 3; ++k) b[k] -= ab * a[k];
-    const double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-    for (int k = 0; k < 3; ++k) { F.a[k] = a[k]; F.b1[k] = b[k] / bn; }
-    F.b2[0] = a[1] * F.b1[2] - a[2] * F.b1[1];
-    F.b2[1] = a[2] * F.b1[0] - a[0] * F.b1[2];
-    F.b2[2] = a[0] * F.b1[1] - a[1] * F.b1[0];
+    Frame F = frame_from_axis(a, mp.dim);
+    F.ok = n > 0;
     return F;
 }
 
@@ -776,6 +784,56 @@ __device__ void finalize_slots(const R* __restrict__ rho, const Dims& d, const M
     ms->keys[s][0] = ~0ull;
     ms->keys[s][1] = ~0ull;
     if (s == 0) ms->cnt = ms->sx = ms->sy = ms->sz = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// footprint of the contact lines for the unbalanced Young force (Sec. IV E)
+// ---------------------------------------------------------------------------
+// Fluid nodes with a lattice neighbour inside the substrate primitive whose
+// density lies in [lo, hi] (the diffuse interface where its isodensity lines
+// end on the substrate), counted per (sector of the measurement frame,
+// surface kind): kind 0 on the primitive's mu_w surface (uniform, or an even
+// latitude stripe), kind 1 on mu_w2.  counts[s * 2 + kind], zeroed by the caller.
+struct YoungParams {
+    double c[3], R;          // substrate centre and radius
+    double pole[3], width;   // stripe pole (unit) and arc width
+    int wet_mode;            // 0 uniform, 1 stripes
+    int n_sectors, dim;
+    double lo, hi;           // density band
+    double axis[3];          // drop axis of the measurement
+};
+
+template <class L, typename R>
+__global__ void __launch_bounds__(256) k_young_count(const R* __restrict__ rho, const uint8_t* __restrict__ cls,
+                                                     Dims d, YoungParams yp, unsigned* __restrict__ counts) {
+    const Frame F = frame_from_axis(yp.axis, yp.dim);
+    const unsigned ntiles = (unsigned)d.tx * (unsigned)d.ty * (unsigned)d.nz;
+    for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int x, y, z;
+        tile_coords(d, t, x, y, z);
+        if (x >= d.nx || y >= d.ny) continue;
+        const long long idx = nid(d, x, y, z);
+        if ((cls[idx] & CLS_MASK) != CLS_FLUID) continue;
+        const double r0 = (double)rho[idx];
+        if (!(r0 >= yp.lo && r0 <= yp.hi)) continue;
+        bool touches = false;
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const double X = wrapc(x + L::E[i][0], d.nx) - yp.c[0], Y = wrapc(y + L::E[i][1], d.ny) - yp.c[1];
+            const double Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) - yp.c[2] : 0.0;
+            touches = touches || (X * X + Y * Y + Z * Z <= yp.R * yp.R);
+        }
+        if (!touches) continue;
+        const double r[3] = {x - yp.c[0], y - yp.c[1], L::D == 3 ? z - yp.c[2] : 0.0};
+        int kind = 0;
+        if (yp.wet_mode) {
+            const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+            double cp = rn > 0.0 ? (r[0] * yp.pole[0] + r[1] * yp.pole[1] + r[2] * yp.pole[2]) / rn : 1.0;
+            cp = cp > 1.0 ? 1.0 : (cp < -1.0 ? -1.0 : cp);
+            kind = (int)((long long)floor(yp.R * acos(cp) / yp.width) % 2);
+        }
+        atomicAdd(&counts[sector_of(r, F, yp.dim, yp.n_sectors) * 2 + kind], 1u);
+    }
 }
 
 template <class L, typename R>

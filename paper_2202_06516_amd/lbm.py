@@ -74,6 +74,17 @@ class lbm_angle(C.Structure):
         return np.array(self.sector_deg[: self.n_sectors])
 
 
+class lbm_young_opts(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("theta1_deg", C.c_double), ("theta2_deg", C.c_double),
+                ("roughness", C.c_double), ("band_lo", C.c_double), ("band_hi", C.c_double)]
+
+
+class lbm_young(C.Structure):
+    _fields_ = [("step", C.c_int64), ("status", C.c_int32), ("n_sectors", C.c_int32),
+                ("count", (C.c_int32 * 2) * MAX_SECTORS), ("phi_d", C.c_double * MAX_SECTORS),
+                ("theta_eq_deg", C.c_double * MAX_SECTORS), ("force", C.c_double * MAX_SECTORS)]
+
+
 class lbm_info(C.Structure):
     _fields_ = [
         ("Tc", C.c_double), ("T", C.c_double), ("alpha", C.c_double), ("rho_g", C.c_double),
@@ -112,7 +123,8 @@ _lib = None
 # exported symbols of include/lbm.h (the binding and the tests check them)
 EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops",
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
-           "lbm_get_info", "lbm_profile_step", "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy",
+           "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_last_error", "lbm_batch_create",
+           "lbm_batch_destroy",
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read",
            "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step", "lbm_batch_last_error",
            "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
@@ -147,6 +159,7 @@ def lib():
     L.lbm_step.argtypes = [vp, i64, i, P(lbm_angle), i, P(i)]
     L.lbm_set_measure.argtypes = [vp, P(lbm_measure_opts)]
     L.lbm_measure_angle.argtypes = [vp, P(lbm_measure_opts), P(lbm_angle)]
+    L.lbm_young_force.argtypes = [vp, P(lbm_young_opts), P(lbm_angle), P(lbm_young)]
     L.lbm_read.argtypes = [vp, i, vp, C.c_size_t, i]
     L.lbm_write.argtypes = [vp, i, vp, C.c_size_t, i]
     L.lbm_sync.argtypes = [vp]
@@ -194,7 +207,8 @@ def lib():
         getattr(L, name).restype = C.c_int
     for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
                  "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
-                 "lbm_get_info", "lbm_profile_step", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_step",
+                 "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_batch_create", "lbm_batch_destroy",
+                 "lbm_batch_step",
                  "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read", "lbm_batch_write",
                  "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step"):
         getattr(L, name).restype = C.c_int
@@ -316,6 +330,17 @@ class Lattice:
         if st not in (0, LBM_E_NO_CONTACT_LINE) or (st != 0 and not allow_missing):
             self._check(st)
         return a
+
+    def young_force(self, gamma, theta1_deg, theta2_deg=90.0, roughness=1.0, band=(0.1, 0.9)):
+        """Measure now (lbm_set_measure's options) and return (lbm_angle, lbm_young): Eq. 17 and Eq. 18
+        per sector; NaN values and status LBM_E_NO_CONTACT_LINE when there is no contact line."""
+        o = lbm_young_opts(float(gamma), float(theta1_deg), float(theta2_deg), float(roughness), float(band[0]),
+                           float(band[1]))
+        a, y = lbm_angle(), lbm_young()
+        st = lib().lbm_young_force(self._h, C.byref(o), C.byref(a), C.byref(y))
+        if st not in (0, LBM_E_NO_CONTACT_LINE):
+            self._check(st)
+        return a, y
 
     # -- fields ------------------------------------------------------------
     def read(self, field):

@@ -93,3 +93,67 @@ def test_gravity_advancing_receding():
     assert abs(a.adv_deg - b.adv_deg) < 1e-6 and abs(a.rec_deg - b.rec_deg) < 1e-6
     # g points to +x: the advancing side is the right-hand one (sector 0)
     assert a.adv_deg == a.sector_deg[0]
+
+
+# ------------------------------------------- unbalanced Young force (Eq. 17, 18)
+
+
+def _young_pair(gy, oy, ga, oa, tol):
+    assert gy.status == oy.status == 0
+    for s in range(ga.n_sectors):
+        assert list(gy.count[s]) == list(oy.count[s]), (s, list(gy.count[s]), list(oy.count[s]))
+        for name in ("phi_d", "theta_eq_deg", "force"):
+            g, o = getattr(gy, name)[s], getattr(oy, name)[s]
+            assert (math.isnan(g) and math.isnan(o)) or abs(g - o) <= tol, (name, s, g, o)
+
+
+@pytest.mark.parametrize("width", [20.0, 60 * math.pi / 6, 100.0])
+def test_young_force_on_wedge_matches_oracle(width):
+    # the exact wedge on a striped circle: the footprint entirely on the
+    # second stripe, split by a border, entirely on the first stripe
+    sol = dict(center=(100, 60), radius=60, stripes=(0.0, 0.05, width))
+    wl = dict(dim=2, n=(200, 180), wall=(0, 0), solids=[sol], drops=[])
+    gp = gpu_lattice(wl, G.LBM_F64)
+    gp.set_measure(0, 2)
+    inf = gp.info()
+    rho = W.wedge_density(gp.shape, (100, 60), 60, 90, inf["rho_m"], inf["rho_g"], inf["rho_l"], slope=1.0)
+    gp.write(G.FIELD_RHO, rho)
+    ga, gy = gp.young_force(0.05, 70.0, 130.0)
+    o = oracle_lattice(wl)
+    o.set_rho(rho)
+    oa, oy = o.young_force(0.05, 70.0, 130.0)
+    _young_pair(gy, oy, ga, oa, 1e-12)
+    assert sum(gy.count[0]) > 0
+
+
+def test_young_force_on_relaxing_striped_drops():
+    # a drop relaxing on a striped cylinder (2-D, two sides) and a striped
+    # sphere (3-D, 8 sectors): footprint counts bit-exact, phi_d / theta_eq /
+    # force to round-off (FP64)
+    wl2 = dict(dim=2, n=(96, 80), wall=(0, 0), Tr=0.8,
+               solids=[dict(center=(48.3, 24.6), radius=16.2, stripes=(-0.01, 0.08, 9.0))],
+               drops=[((48.0, 52.0), 12.0)])
+    wl3 = dict(dim=3, n=(48, 44, 46), wall=(1, 1, 1), Tr=0.8,
+               solids=[dict(center=(24.2, 22.1, 15.3), radius=9.1, stripes=(-0.01, 0.08, 5.0))],
+               drops=[((24.0, 22.0, 30.0), 8.0)])
+    for wl, ns, coll in ((wl2, 2, "mrt"), (wl3, 8, "bgk")):
+        gp = gpu_lattice(wl, G.LBM_F64, coll)
+        gp.set_measure(0, ns)
+        o = oracle_lattice(wl, coll)
+        gp.step(150)
+        o.step(150)
+        ga, gy = gp.young_force(0.06, 80.0, 120.0, roughness=1.0)
+        oa, oy = o.young_force(0.06, 80.0, 120.0, n_sectors=ns)
+        assert ga.n_valid == oa.n_valid and ga.n_valid >= 1
+        _young_pair(gy, oy, ga, oa, 1e-9)
+
+
+def test_young_force_without_contact_line_and_bad_options():
+    wl = dict(dim=2, n=(64, 64), wall=(0, 0), solids=[dict(center=(32, 16), radius=8, mu_w=0.0)], drops=[])
+    gp = gpu_lattice(wl, G.LBM_F64)
+    gp.write(G.FIELD_RHO, np.full(gp.shape, gp.info()["rho_g"]))
+    a, y = gp.young_force(0.05, 90.0)
+    assert y.status == G.LBM_E_NO_CONTACT_LINE and math.isnan(y.phi_d[0]) and math.isnan(y.force[1])
+    for kw in (dict(roughness=0.0), dict(band=(0.5, 0.4)), dict(band=(0.0, 1.0))):
+        with pytest.raises(G.LbmError):
+            gp.young_force(0.05, 90.0, **kw)
