@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--workload", default="sessile3d", choices=["sessile3d", "batch", "unet"],
                     help="sessile3d: the 256^3 D3Q19 benchmark; batch: 512 seeded D2Q9 cases in one batch; "
                          "unet: training steps of the warm-start U-Net at 256^2")
-    ap.add_argument("--batch", type=int, default=8, help="unet: samples per training step")
+    ap.add_argument("--batch", type=int, default=32, help="unet: samples per training step")
     ap.add_argument("--cases", type=int, default=512)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of GIB gibibytes (bandwidth / counter calibration)")

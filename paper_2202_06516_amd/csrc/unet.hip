@@ -1019,30 +1019,38 @@ __global__ void k_head_bwd_x(const float* __restrict__ dy, const float* __restri
     }
 }
 
-// head weight and bias gradients: per-block partials [blk][C + 1] (C divides 256)
+// head weight and bias gradients: per-block partials [blk][C + 1] (C a multiple
+// of 8 dividing 256).  A thread takes 8 channels (one 16-byte vector) of
+// every (256 / (C / 8))-th pixel of the block's range; the pixel lanes are
+// summed in LDS in lane order (deterministic).
 __global__ void __launch_bounds__(256) k_head_bwd_w(const float* __restrict__ dy, const bf16* __restrict__ X, i64 P,
                                                     int C, float* __restrict__ part) {
-    __shared__ float red[256];
+    __shared__ float red[256 * 8];
     __shared__ float redb[256];
-    const int c = threadIdx.x % C, grp = threadIdx.x / C, ngrp = 256 / C;
+    const int nv = C / 8, cv = (int)threadIdx.x % nv, lane = (int)threadIdx.x / nv, nl = 256 / nv;
     const i64 per = (P + gridDim.x - 1) / gridDim.x;
     const i64 beg = (i64)blockIdx.x * per, end = std::min<i64>(P, beg + per);
-    float s = 0.f, sb = 0.f;
-    for (i64 p = beg + grp; p < end; p += ngrp) {
-        s += dy[p] * (float)X[p * C + c];
-        if (c == 0) sb += dy[p];
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, sb = 0.f;
+#pragma unroll 4
+    for (i64 p = beg + lane; p < end; p += nl) {
+        const float d = dy[p];
+        const bf16x8 x = ld8(X + p * C + 8 * cv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += d * (float)x[j];
+        sb += d;
     }
-    red[threadIdx.x] = s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[lane * C + 8 * cv + j] = s[j];
     redb[threadIdx.x] = sb;
     __syncthreads();
     if ((int)threadIdx.x < C) {
         float t = 0.f;
-        for (int k = 0; k < ngrp; ++k) t += red[k * C + threadIdx.x];
+        for (int k = 0; k < nl; ++k) t += red[k * C + threadIdx.x];
         part[(i64)blockIdx.x * (C + 1) + threadIdx.x] = t;
     }
     if (threadIdx.x == 0) {
         float t = 0.f;
-        for (int k = 0; k < ngrp; ++k) t += redb[k * C];
+        for (int k = 0; k < nl; ++k) t += redb[k * nv];   // the cv = 0 thread of each lane
         part[(i64)blockIdx.x * (C + 1) + C] = t;
     }
 }
@@ -1301,7 +1309,7 @@ struct lbm_unet {
 
 namespace {
 
-constexpr int HEAD_BLOCKS = 512;
+constexpr int HEAD_BLOCKS = 2048;
 constexpr int MSE_BLOCKS = 1024;
 
 lbm_status ufail(lbm_unet* u, lbm_status s, const std::string& msg) {
