@@ -78,7 +78,7 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the step has no multi-GPU decomposition; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batch":
         batch_bench(args)
