@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per k_collide launch from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000) counters,
 # scaled by a plain-copy calibration; valid only for the kernel as it stands when they were taken
 # (profiles/k_collide_d3q19_f32_256cube.md).  Keyed by (lattice side, precision, collision).
-COUNTED_TRAFFIC = {}
+COUNTED_TRAFFIC = {(256, "f32", "bgk"): 3.301e9}
 
 
 def parse():
