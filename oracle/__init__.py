@@ -88,6 +88,7 @@ def lib():
         L.ora_create.restype = v; L.ora_create.argtypes = [p(Params)]
         L.ora_destroy.argtypes = [v]
         L.ora_add_sphere.argtypes = [v, p(d), d, i, d, d, d, p(d)]
+        L.ora_add_cavity.argtypes = [v, p(d), d, i, d, d, d, p(d)]
         L.ora_set_muw_map.argtypes = [v, p(d)]
         L.ora_build.argtypes = [v]
         L.ora_init_drops.argtypes = [v, p(d), p(d), i, d]
@@ -222,7 +223,9 @@ class Oracle:
     def __del__(self):
         self.close()
 
-    def add_sphere(self, centre, radius, mu_w=0.0, stripes=None, pole=None):
+    def add_sphere(self, centre, radius, mu_w=0.0, stripes=None, pole=None, cavity=False):
+        """Convex circle/ball (Fig. 2a), or with cavity=True the concave
+        substrate of Fig. 2b: solid outside the circle/ball."""
         c = np.zeros(3)
         c[: len(centre)] = centre
         if stripes is None:
@@ -230,8 +233,8 @@ class Oracle:
         else:
             mode, (mu_w, mu2, width) = 1, stripes
         pl = None if pole is None else _dp(np.asarray(pole, dtype=np.float64))
-        rc = lib().ora_add_sphere(self._h, _dp(c), float(radius), mode, float(mu_w), float(mu2),
-                                  float(width), pl)
+        add = lib().ora_add_cavity if cavity else lib().ora_add_sphere
+        rc = add(self._h, _dp(c), float(radius), mode, float(mu_w), float(mu2), float(width), pl)
         if rc != 0:
             raise ValueError("bad solid")
         lib().ora_build(self._h)

@@ -35,6 +35,7 @@ enum { C_FLUID = 0, C_L1 = 1, C_L2 = 2, C_DEEP = 3 };
 
 typedef struct {
     double c[3], r;
+    int concave; /* 0: solid ball |x - c| <= r; 1: solid outside, |x - c| >= r */
     int wet_mode;
     double mu1, mu2, width, pole[3];
 } ora_prim;
@@ -442,11 +443,12 @@ void ora_destroy(ora_ctx* c) {
     free(c);
 }
 
-int ora_add_sphere(ora_ctx* c, const double centre[3], double radius, int wet_mode,
-                   double mu_w, double mu_w2, double stripe_width, const double pole[3]) {
+static int add_prim(ora_ctx* c, int concave, const double centre[3], double radius, int wet_mode,
+                    double mu_w, double mu_w2, double stripe_width, const double pole[3]) {
     if (c->nprim >= MAXPRIM || radius <= 0) return -1;
     ora_prim* pr = &c->prim[c->nprim++];
     memset(pr, 0, sizeof *pr);
+    pr->concave = concave;
     for (int d = 0; d < 3; ++d) pr->c[d] = centre[d];
     if (c->dim == 2) pr->c[2] = 0;
     pr->r = radius;
@@ -461,6 +463,19 @@ int ora_add_sphere(ora_ctx* c, const double centre[3], double radius, int wet_mo
     return 0;
 }
 
+/* convex substrate of Fig. 2(a): a solid circle (2-D) or ball (3-D) */
+int ora_add_sphere(ora_ctx* c, const double centre[3], double radius, int wet_mode,
+                   double mu_w, double mu_w2, double stripe_width, const double pole[3]) {
+    return add_prim(c, 0, centre, radius, wet_mode, mu_w, mu_w2, stripe_width, pole);
+}
+
+/* concave substrate of Fig. 2(b): the fluid fills the inside of the circle or
+ * ball and everything outside it is solid */
+int ora_add_cavity(ora_ctx* c, const double centre[3], double radius, int wet_mode,
+                   double mu_w, double mu_w2, double stripe_width, const double pole[3]) {
+    return add_prim(c, 1, centre, radius, wet_mode, mu_w, mu_w2, stripe_width, pole);
+}
+
 int ora_set_muw_map(ora_ctx* c, const double* map) {
     free(c->muw_map);
     c->muw_map = NULL;
@@ -473,7 +488,8 @@ int ora_set_muw_map(ora_ctx* c, const double* map) {
 
 static int inside_prim(const ora_prim* pr, double x, double y, double z) {
     double dx = x - pr->c[0], dy = y - pr->c[1], dz = z - pr->c[2];
-    return dx * dx + dy * dy + dz * dz <= pr->r * pr->r;
+    double d2 = dx * dx + dy * dy + dz * dz, r2 = pr->r * pr->r;
+    return pr->concave ? d2 >= r2 : d2 <= r2;
 }
 
 static int is_wall_layer(const ora_ctx* c, int x, int y, int z) {
@@ -539,7 +555,9 @@ static double wall_mu_at(const ora_ctx* c, long long n, int x, int y, int z) {
 }
 
 /* wall distance fraction of the link from fluid x along e_dir (Sec. III A):
- * smallest root in (0,1] of |x + q e - C| = R for a sphere, 1/2 for a box wall */
+ * the root in (0,1] of |x + q e - C| = R -- the smaller one for a ball, whose
+ * outside x is in, the larger one for a cavity, whose inside x is in -- and
+ * 1/2 for a box wall */
 double ora_link_q(ora_ctx* c, int x, int y, int z, int dir) {
     long long n = lin(c, x, y, z);
     if (c->solid[n]) return -1;
@@ -558,7 +576,7 @@ double ora_link_q(ora_ctx* c, int x, int y, int z, int dir) {
         double Cc = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] - pr->r * pr->r;
         double disc = B * B - A * Cc;
         if (disc < 0) disc = 0;
-        double r = (-B - sqrt(disc)) / A;
+        double r = pr->concave ? (-B + sqrt(disc)) / A : (-B - sqrt(disc)) / A;
         if (r <= 0) r = 1e-12;
         if (r > 1) r = 1;
         if (r < q) q = r;
@@ -923,7 +941,7 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
             double t = (rho_m - c->rho[n]) / (c->rho[m] - c->rho[n]);
             double p[3] = {x + t * c->e[i][0], y + t * c->e[i][1], z + t * c->e[i][2]};
             double r[3] = {p[0] - pr->c[0], p[1] - pr->c[1], p[2] - pr->c[2]};
-            double dist = sqrt(dot3(r, r)) - pr->r;
+            double dist = pr->concave ? pr->r - sqrt(dot3(r, r)) : sqrt(dot3(r, r)) - pr->r;
             if (!(dist >= 0.5 && dist < 2.5)) continue;
             int band = dist < 1.5 ? 1 : 2;
             int sec = sector_of(c->dim, r, b1, b2, n_sectors);
@@ -970,8 +988,12 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
         }
         double w0 = w1 + lam * Dw, s0 = s1 + lam * Ds;
         double r0 = sqrt(w0 * w0 + s0 * s0);
-        double nw = w0 / r0, ns = s0 / r0;
-        double tw = -ns, ts = nw;
+        /* outward radial unit vector; the tangent toward the axis follows from
+         * it, and the substrate normal into the fluid is it (convex) or its
+         * opposite (concave) */
+        double ew = w0 / r0, es = s0 / r0;
+        double tw = -es, ts = ew;
+        double nw = pr->concave ? -ew : ew, ns = pr->concave ? -es : es;
         double vn = sqrt(A);
         double vw = Dw / vn, vs = Ds / vn;
         double th = atan2(vw * nw + vs * ns, vw * tw + vs * ts) * 180.0 / M_PI;

@@ -67,6 +67,9 @@ void     ora_destroy(ora_ctx* c);
 /* convex sphere (circle in 2-D); wet_mode 0 uniform mu_w, 1 latitude stripes */
 int  ora_add_sphere(ora_ctx* c, const double centre[3], double radius, int wet_mode,
                     double mu_w, double mu_w2, double stripe_width, const double pole[3]);
+/* concave cavity: solid wherever |x - centre| >= radius; same wetting modes */
+int  ora_add_cavity(ora_ctx* c, const double centre[3], double radius, int wet_mode,
+                    double mu_w, double mu_w2, double stripe_width, const double pole[3]);
 int  ora_set_muw_map(ora_ctx* c, const double* map /*[N] or NULL*/);
 int  ora_build(ora_ctx* c);                       /* classify nodes; call after adding solids */
 int  ora_init_drops(ora_ctx* c, const double* centres /*[n*3]*/, const double* radii, int n, double W);

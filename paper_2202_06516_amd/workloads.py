@@ -15,6 +15,9 @@ Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
   striped_3d   D3Q19 FP32 512^3 walled box, sphere r=120 with latitude stripes
                (width 16) of two wettabilities, sessile or pendent drop r0=80,
                gravity 1e-6 .. 1e-5 lu
+  cavity_2d    D2Q9 128x128 periodic, circular cavity r=56 at the centre, drop
+               r0=20 at its lowest point (concave substrate)
+  cavity_3d    D3Q19 64^3, spherical cavity r=28 at the centre, drop r0=16
   batch_cases  many D2Q9 drops on cylinders of random sizes (batched solver)
   warmstart_cases  256^2 D2Q9 drops on cylinders, cylinder radius 16..64, drop
                radius 18..48 (smaller drops dissolve into the gas at Tr=0.8
@@ -106,6 +109,67 @@ def wedge_density(shape, center, R, theta0_deg, rho_m, rho_lo, rho_hi, slope=0.0
         s = np.minimum(s, (xx - px) * mx + (yy - py) * my)
     rho = np.clip(rho_m + slope * s, rho_lo, rho_hi)
     return rho[None, :, :]
+
+
+def cavity_wedge_density(shape, center, R, theta0_deg, rho_m, rho_lo, rho_hi, slope=0.05, half_chord=30.0,
+                         top=40.0):
+    """Synthetic 2-D liquid pool at the bottom of a circular cavity, meeting the
+    cavity wall at a prescribed angle (the concave case of Fig. 2b).
+
+    The liquid is bounded by two straight lines through the wall points at
+    +-half_chord from the vertical axis, below the centre, each at angle theta0
+    to the wall's tangent measured through the liquid, and by a flat top top lu
+    above the cavity's lowest point.  The lines rise toward the axis only if
+    theta0 exceeds the half-angle of the chord, asin(half_chord / R).  The
+    density is rho_m + slope * s, s the minimum of the signed distances to
+    these lines (positive inside), clipped to [rho_lo, rho_hi].
+    Returns an array of shape (1, ny, nx).
+    """
+    _, ny, nx = shape
+    cx, cy = center
+    phi = np.arcsin(half_chord / R)
+    th = np.deg2rad(theta0_deg)
+    lines = []  # (point, inward unit normal)
+    for side_sign in (1.0, -1.0):
+        px, py = cx + side_sign * R * np.sin(phi), cy - R * np.cos(phi)
+        # tangent toward the axis (down the wall) and wall normal into the fluid
+        tx, ty = -side_sign * np.cos(phi), -np.sin(phi)
+        nx_, ny_ = -side_sign * np.sin(phi), np.cos(phi)
+        vx, vy = np.cos(th) * tx + np.sin(th) * nx_, np.cos(th) * ty + np.sin(th) * ny_
+        mx, my = -vy, vx
+        if mx * tx + my * ty < 0:
+            mx, my = -mx, -my
+        lines.append((px, py, mx, my))
+    lines.append((cx, cy - R + top, 0.0, -1.0))
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    s = np.full((ny, nx), np.inf)
+    for px, py, mx, my in lines:
+        s = np.minimum(s, (xx - px) * mx + (yy - py) * my)
+    rho = np.clip(rho_m + slope * s, rho_lo, rho_hi)
+    return rho[None, :, :]
+
+
+def cavity_2d(mu_w=0.04, n=128):
+    """Drop resting at the bottom of a circular cavity (concave substrate,
+    Fig. 2b) on a square lattice: cavity radius 7n/16 at the centre, drop
+    radius 5n/32 touching the wall from inside at the lowest point."""
+    s = n / 128.0
+    R, r0 = 56 * s, 20 * s
+    c = (64 * s, 64 * s)
+    return dict(dim=2, n=(n, n), wall=(0, 0), Tr=0.6,
+                solids=[dict(center=c, radius=R, mu_w=mu_w, cavity=True)],
+                drops=[((c[0], c[1] - R + r0), r0)], steps=5000, every=100)
+
+
+def cavity_3d(mu_w=0.04, n=64):
+    """Drop at the bottom of a spherical cavity in a cube (D3Q19, Tr = 0.8):
+    cavity radius 7n/16 at the centre, drop radius n/4 touching it from inside."""
+    s = n / 64.0
+    R, r0 = 28 * s, 16 * s
+    c = (32 * s, 32 * s, 32 * s)
+    return dict(dim=3, n=(n, n, n), wall=(0, 0, 0), Tr=0.8,
+                solids=[dict(center=c, radius=R, mu_w=mu_w, cavity=True)],
+                drops=[((c[0], c[1], c[2] - R + r0), r0)], steps=5000, every=100, n_sectors=16)
 
 
 def random_state_perturbation(shape, q, seed, amplitude=1e-3):

@@ -36,10 +36,11 @@ def oracle_lattice(wl, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start
     o = O.Oracle(wl["dim"], wl["n"], wall, bgk=int(collision == "bgk"), bc_mode=int(bc != "halfway"),
                  g=g, g_start=g_start, **params)
     for s in wl["solids"]:
+        cav = bool(s.get("cavity"))
         if "stripes" in s:
-            o.add_sphere(s["center"], s["radius"], stripes=s["stripes"], pole=s.get("pole"))
+            o.add_sphere(s["center"], s["radius"], stripes=s["stripes"], pole=s.get("pole"), cavity=cav)
         else:
-            o.add_sphere(s["center"], s["radius"], mu_w=s.get("mu_w", 0.0), pole=s.get("pole"))
+            o.add_sphere(s["center"], s["radius"], mu_w=s.get("mu_w", 0.0), pole=s.get("pole"), cavity=cav)
     if wl.get("drops"):
         o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=10.0)
     return o

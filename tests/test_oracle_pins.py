@@ -566,3 +566,88 @@ def test_young_force_at_a_stripe_border():
         assert abs(math.cos(math.radians(y.theta_eq_deg[0])) - c) < 1e-12
         phis.append(y.phi_d[0])
     assert phis[0] < phis[1] < phis[2]
+
+
+# ------------------------------------------------ concave substrate (Fig. 2b)
+
+
+def test_cavity_classes_and_link_fractions():
+    # a cavity is the complement of a ball: the fluid is the open disc, the
+    # first solid layer is every solid node with a fluid lattice neighbour and
+    # the second every other solid node next to the first
+    o = O.Oracle(2, (40, 40))
+    o.add_sphere((20.0, 20.0), 9.5, cavity=True)
+    cls = o.cls[0]
+    yy, xx = np.mgrid[0:40, 0:40]
+    fluid = (xx - 20.0) ** 2 + (yy - 20.0) ** 2 < 9.5**2
+    assert np.array_equal(cls == 0, fluid)
+    e, _ = O.lattice(2)
+    for yv, xv in zip(*np.nonzero(~fluid)):
+        nb = [cls[(yv + ey) % 40, (xv + ex) % 40] for ex, ey, _ in e[1:]]
+        assert cls[yv, xv] == (1 if 0 in nb else 2 if 1 in nb else 3)
+    # cut links end on the circle, seen from inside: along +x from (25, 20)
+    # the wall of radius 5.3 is 0.3 away; along (1, 1) from (23, 23) it is
+    # where (3 + q) sqrt(2) = 5.3
+    o = O.Oracle(2, (40, 40))
+    o.add_sphere((20.0, 20.0), 5.3, cavity=True)
+    assert abs(o.link_q(25, 20, 0, 1) - 0.3) < 1e-14
+    q = o.link_q(23, 23, 0, 5)
+    assert abs(q - (5.3 / math.sqrt(2.0) - 3.0)) < 1e-14 and 0 < q <= 1
+    assert o.link_q(20, 20, 0, 1) == -1
+
+
+@pytest.mark.parametrize("theta0", [30, 60, 90, 120, 150])
+def test_cavity_wedge_measured_exactly(theta0):
+    # a pool at the bottom of a cavity of radius 80 whose straight sides meet
+    # the wall at theta0: the substrate normal now points toward the centre,
+    # and the measured angle is theta0 to round-off on both sides
+    o = O.Oracle(2, (200, 180))
+    o.add_sphere((100, 90), 80, mu_w=0.0, cavity=True)
+    inf = o.info()
+    rm = 0.5 * (inf["rho_l"] + inf["rho_g"])
+    o.set_rho(W.cavity_wedge_density(o.shape, (100, 90), 80, theta0, rm, inf["rho_g"], inf["rho_l"]))
+    a = o.measure()
+    assert a.status == 0 and a.n_valid == 2
+    assert list(a.axis[:2]) == [0.0, -1.0]
+    for s, sign in ((0, 1), (1, -1)):
+        assert abs(a.sector_deg[s] - theta0) < 1e-9
+        # the contact points are the wall points 30 lu either side of the axis
+        assert abs(a.contact[s][0] - (100 + sign * 30)) < 1e-9
+        assert abs(a.contact[s][1] - (90 - 80 * math.cos(math.asin(30 / 80)))) < 1e-9
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_cavity_mass_and_mirror_symmetry(bc):
+    # a drop at the bottom of a cavity, symmetric about x = 64: mass is
+    # conserved to round-off and the two sides stay mirror images (Tr = 0.8:
+    # the interpolated wall scheme is unstable at Tr = 0.6 on either kind of
+    # substrate)
+    wl = W.cavity_2d(mu_w=0.04)
+    o = O.Oracle(2, wl["n"], bc_mode=bc, Tr=0.8)
+    s = wl["solids"][0]
+    o.add_sphere(s["center"], s["radius"], mu_w=s["mu_w"], cavity=True)
+    o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=10.0)
+    m0 = o.mass()
+    o.step(300)
+    assert abs(o.mass() / m0 - 1) < 1e-13
+    r = o.rho[0]
+    assert np.max(np.abs(r[:, 1:] - r[:, 1:][:, ::-1])) < 1e-11
+    a = o.measure()
+    assert a.status == 0 and abs(a.sector_deg[0] - a.sector_deg[1]) < 1e-7
+
+
+def test_cavity_angle_grows_with_wall_potential():
+    # Sec. IV A: the angle rises with the wall chemical potential, from below
+    # to above 90 deg across the paper's three values (-0.01, 0.04, 0.1)
+    th = []
+    for mu_w in W.MU_W_SWEEP:
+        wl = W.cavity_2d(mu_w=mu_w)
+        o = O.Oracle(2, wl["n"])
+        s = wl["solids"][0]
+        o.add_sphere(s["center"], s["radius"], mu_w=mu_w, cavity=True)
+        o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=10.0)
+        o.step(2000)
+        a = o.measure()
+        assert a.status == 0 and a.n_valid == 2
+        th.append(a.mean_deg)
+    assert th[0] < 90.0 < th[2] and th[0] < th[1] < th[2], th
