@@ -102,15 +102,21 @@ typedef struct {
 /* Fill *cfg with the library defaults for the given lattice. */
 void lbm_config_default(lbm_config* cfg, int lattice);
 
-enum { LBM_SOLID_SPHERE = 0 };                       /* circle in 2-D, sphere in 3-D */
+/* Substrate shapes of Fig. 2: a convex circle (2-D) or sphere (3-D), and the
+ * concave cavity, whose inside is fluid and outside solid. */
+enum { LBM_SOLID_SPHERE = 0, LBM_SOLID_CAVITY = 1 };
 enum { LBM_WET_UNIFORM = 0, LBM_WET_STRIPES = 1 };
 
-/* A convex solid primitive.  A node is solid iff |x - center| <= radius.
+/* A solid primitive.  LBM_SOLID_SPHERE: a node is solid iff
+ * |x - center| <= radius; LBM_SOLID_CAVITY: iff |x - center| >= radius.  The
+ * contact-angle measurement takes the substrate normal into the fluid (outward
+ * for a sphere, toward the centre for a cavity); everything else treats both
+ * kinds alike.  Any other kind is rejected with LBM_E_ARG.
  * Wettability (Sec. III A): mu_w on its solid nodes, or with LBM_WET_STRIPES
  * alternating mu_w / mu_w2 in latitude stripes of arc length stripe_width,
  * stripe = floor(radius * polar_angle / stripe_width), polar angle from pole. */
 typedef struct {
-    int kind;            /* LBM_SOLID_SPHERE */
+    int kind;            /* LBM_SOLID_SPHERE or LBM_SOLID_CAVITY */
     int wet_mode;        /* LBM_WET_UNIFORM or LBM_WET_STRIPES */
     double center[3];
     double radius;
@@ -259,7 +265,7 @@ typedef struct {
  * LBM_E_NO_CONTACT_LINE (out->status set, every value NaN), LBM_E_DEVICE. */
 lbm_status lbm_young_force(lbm_ctx* ctx, const lbm_young_opts* opts, lbm_angle* angle, lbm_young* out);
 
-/* Step the lattice nsteps times (no measurement) with a HIP event pair/* Step the lattice nsteps times (no measurement) with a HIP event pair
+/* Step the lattice nsteps times (no measurement) with a HIP event pair
  * around every kernel launch, and report the mean duration in milliseconds of
  * each kernel kind: names[i] (static strings) and ms[i] for i < *n_kinds
  * (cap entries at most).  Synchronises. */

@@ -105,6 +105,7 @@ MeasureParams measure_params(const lbm_ctx* c, const lbm_measure_opts& o) {
         mp.g[k] = k < c->dim ? c->cfg.g[k] : 0.0;
     }
     mp.R = s.r;
+    mp.concave = s.concave;
     mp.rho_m = o.rho_m > 0 ? o.rho_m : c->rho_m;
     mp.n_sectors = c->dim == 2 ? 2 : o.n_sectors;
     mp.dim = c->dim;
@@ -534,7 +535,8 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
     std::vector<Solid> ss;
     for (int i = 0; i < n; ++i) {
         const lbm_solid& p = prims[i];
-        if (p.kind != LBM_SOLID_SPHERE || !(p.radius > 0)) return fail(c, LBM_E_ARG, "set_solid: bad primitive");
+        if ((p.kind != LBM_SOLID_SPHERE && p.kind != LBM_SOLID_CAVITY) || !(p.radius > 0))
+            return fail(c, LBM_E_ARG, "set_solid: bad primitive");
         if (p.wet_mode != LBM_WET_UNIFORM && p.wet_mode != LBM_WET_STRIPES)
             return fail(c, LBM_E_ARG, "set_solid: bad wet_mode");
         if (p.wet_mode == LBM_WET_STRIPES && !(p.stripe_width > 0))
@@ -542,6 +544,7 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
         Solid s{};
         for (int k = 0; k < 3; ++k) s.c[k] = k < c->dim ? p.center[k] : 0.0;
         s.r = p.radius;
+        s.concave = p.kind == LBM_SOLID_CAVITY;
         s.wet_mode = p.wet_mode;
         s.mu1 = p.mu_w;
         s.mu2 = p.mu_w2;
@@ -812,6 +815,7 @@ lbm_status lbm_young_force(lbm_ctx* c, const lbm_young_opts* yo, lbm_angle* angl
         yp.axis[k] = angle->axis[k];
     }
     yp.R = so.r;
+    yp.concave = so.concave;
     yp.width = so.width;
     yp.wet_mode = so.wet_mode;
     yp.n_sectors = angle->n_sectors;

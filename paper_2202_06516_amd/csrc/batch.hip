@@ -656,9 +656,14 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
             lbm_batch_destroy(b);
             return LBM_E_ARG;
         }
+        if (cs.solid.kind != LBM_SOLID_SPHERE && cs.solid.kind != LBM_SOLID_CAVITY) {
+            lbm_batch_destroy(b);
+            return LBM_E_ARG;
+        }
         Solid s{};
         for (int k = 0; k < 3; ++k) s.c[k] = k < b->dim ? cs.solid.center[k] : 0.0;
         s.r = cs.solid.radius;
+        s.concave = cs.solid.kind == LBM_SOLID_CAVITY;
         s.wet_mode = cs.solid.wet_mode;
         s.mu1 = cs.solid.mu_w;
         s.mu2 = cs.solid.mu_w2;
@@ -688,6 +693,7 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
             mp.g[k] = k < b->dim ? base->g[k] : 0.0;
         }
         mp.R = s.r;
+        mp.concave = s.concave;
         mp.rho_m = b->rho_m;
         mp.n_sectors = b->dim == 2 ? 2 : 16;
         mp.dim = b->dim;

@@ -192,7 +192,8 @@ bool build_geometry(Geometry& g, int dim, const int n[3], const int wall[3], con
     };
     auto inside = [&](const Solid& s, double x, double y, double z) {
         const double dx = x - s.c[0], dy = y - s.c[1], dz = dim == 3 ? z - s.c[2] : 0.0;
-        return dx * dx + dy * dy + dz * dz <= s.r * s.r;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        return s.concave ? d2 >= s.r * s.r : d2 <= s.r * s.r;
     };
 
     std::vector<uint8_t> solid(N);
@@ -295,8 +296,9 @@ bool build_geometry(Geometry& g, int dim, const int n[3], const int wall[3], con
                 if (g.nbmask[i] & (1u << q)) {
                     const int X = x + L.e[q][0], Y = y + L.e[q][1], Z = z + L.e[q][2];
                     qq = 2.0;
-                    // box wall layers sit halfway; a sphere cuts the link at the
-                    // smaller root of |x + q e - c| = r
+                    // box wall layers sit halfway; a sphere cuts the link at a
+                    // root of |x + q e - c| = r: the smaller one for a ball (x is
+                    // outside it), the larger one for a cavity (x is inside)
                     int Xw = X, Yw = Y, Zw = Z;
                     if (Xw < 0 || Xw >= nn[0] || Yw < 0 || Yw >= nn[1] || Zw < 0 || Zw >= nn[2]) qq = 0.5;
                     else if (wall_layer(Xw, Yw, Zw)) qq = 0.5;
@@ -308,7 +310,7 @@ bool build_geometry(Geometry& g, int dim, const int n[3], const int wall[3], con
                         const double c0 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2] - s.r * s.r;
                         double disc = hb * hb - ee * c0;
                         if (disc < 0) disc = 0;
-                        double root = (-hb - std::sqrt(disc)) / ee;
+                        double root = s.concave ? (-hb + std::sqrt(disc)) / ee : (-hb - std::sqrt(disc)) / ee;
                         root = root <= 0 ? 1e-12 : (root > 1 ? 1.0 : root);
                         if (root < qq) qq = root;
                     }

@@ -26,6 +26,7 @@ bool pr_solve(PRState& s, std::string& err);
 
 struct Solid {
     double c[3], r;
+    bool concave;  // false: solid ball |x - c| <= r; true: solid outside, |x - c| >= r
     int wet_mode;  // 0 uniform, 1 stripes
     double mu1, mu2, width, pole[3];
 };

@@ -116,6 +116,7 @@ struct DevCtl {
 struct MeasureParams {
     double c[3];     // substrate centre
     double R;        // substrate radius
+    int concave;     // 0: convex ball, fluid outside; 1: cavity, fluid inside
     double rho_m;    // isodensity level
     double g[3];     // body acceleration (advancing side)
     int n_sectors;
@@ -468,7 +469,8 @@ __device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const 
     bool cand = false;
     const double rx = x - mp.c[0], ry = y - mp.c[1], rz = (L::D == 3) ? z - mp.c[2] : 0.0;
     if (fluid && (double)r0 < mp.rho_m) {
-        const double dn = sqrt(rx * rx + ry * ry + rz * rz) - mp.R;
+        const double rn = sqrt(rx * rx + ry * ry + rz * rz);
+        const double dn = mp.concave ? mp.R - rn : rn - mp.R;
         cand = dn < 4.0;  // crossings lie within sqrt(2) of the node; bands end at 2.5
     }
     if (__ballot(cand) == 0) return;
@@ -487,7 +489,8 @@ __device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const 
         double p[3];
         crossing_point((double)r0, rl, mp.rho_m, x, y, z, L::E[i][0], L::E[i][1], L::E[i][2], p);
         const double r[3] = {p[0] - mp.c[0], p[1] - mp.c[1], p[2] - mp.c[2]};
-        const double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) - mp.R;
+        const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        const double dist = mp.concave ? mp.R - rn : rn - mp.R;  // distance from the substrate
         if (!(dist >= 0.5 && dist < 2.5)) continue;
         const int band = dist < 1.5 ? 1 : 2;
         const int s = sector_of(r, F, mp.dim, mp.n_sectors);
@@ -736,8 +739,10 @@ __device__ void finalize_slots(const R* __restrict__ rho, const Dims& d, const M
                 }
                 const double w0 = w1 + lam * dw, s0 = s1 + lam * ds;
                 const double r0 = sqrt(w0 * w0 + s0 * s0);
-                const double nw = w0 / r0, ns = s0 / r0;      // outward normal
-                const double tw = -ns, ts = nw;               // tangent toward the drop axis
+                const double ew = w0 / r0, es = s0 / r0;      // outward radial direction
+                const double tw = -es, ts = ew;               // tangent toward the drop axis
+                // substrate normal into the fluid
+                const double nw = mp.concave ? -ew : ew, ns = mp.concave ? -es : es;
                 const double vl = sqrt(A);
                 const double vw = dw / vl, vs = ds / vl;
                 const double ang = atan2(vw * nw + vs * ns, vw * tw + vs * ts) * (180.0 / M_PI);
@@ -796,6 +801,7 @@ __device__ void finalize_slots(const R* __restrict__ rho, const Dims& d, const M
 // latitude stripe), kind 1 on mu_w2.  counts[s * 2 + kind], zeroed by the caller.
 struct YoungParams {
     double c[3], R;          // substrate centre and radius
+    int concave;             // 1: cavity (solid outside the sphere)
     double pole[3], width;   // stripe pole (unit) and arc width
     int wet_mode;            // 0 uniform, 1 stripes
     int n_sectors, dim;
@@ -821,7 +827,8 @@ __global__ void __launch_bounds__(256) k_young_count(const R* __restrict__ rho, 
         for (int i = 1; i < L::Q; ++i) {
             const double X = wrapc(x + L::E[i][0], d.nx) - yp.c[0], Y = wrapc(y + L::E[i][1], d.ny) - yp.c[1];
             const double Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) - yp.c[2] : 0.0;
-            touches = touches || (X * X + Y * Y + Z * Z <= yp.R * yp.R);
+            const double d2 = X * X + Y * Y + Z * Z;
+            touches = touches || (yp.concave ? d2 >= yp.R * yp.R : d2 <= yp.R * yp.R);
         }
         if (!touches) continue;
         const double r[3] = {x - yp.c[0], y - yp.c[1], L::D == 3 ? z - yp.c[2] : 0.0};

@@ -24,6 +24,7 @@ LBM_PERIODIC, LBM_WALL = 0, 1
 LBM_MRT, LBM_BGK = 0, 1
 LBM_BC_HALFWAY, LBM_BC_BOUZIDI_MC = 0, 1
 LBM_SOLID_SPHERE = 0
+LBM_SOLID_CAVITY = 1
 LBM_WET_UNIFORM, LBM_WET_STRIPES = 0, 1
 FIELD_RHO, FIELD_F, FIELD_VEL, FIELD_MU, FIELD_CLASS, FIELD_MASS = range(6)
 MAX_SECTORS = 64
@@ -275,22 +276,11 @@ class Lattice:
 
     # -- set-up ------------------------------------------------------------
     def set_solids(self, solids, mu_w_map=None):
+        """solids: dicts with center, radius, mu_w or stripes=(mu_w, mu_w2, width),
+        optional pole, and cavity=True for the concave substrate (solid outside)."""
         arr = (lbm_solid * max(len(solids), 1))()
         for i, s in enumerate(solids):
-            arr[i].kind = LBM_SOLID_SPHERE
-            c = list(s["center"]) + [0.0] * (3 - len(s["center"]))
-            for k in range(3):
-                arr[i].center[k] = c[k]
-            arr[i].radius = s["radius"]
-            if "stripes" in s:
-                arr[i].wet_mode = LBM_WET_STRIPES
-                arr[i].mu_w, arr[i].mu_w2, arr[i].stripe_width = s["stripes"]
-            else:
-                arr[i].wet_mode = LBM_WET_UNIFORM
-                arr[i].mu_w = s.get("mu_w", 0.0)
-            pole = s.get("pole", (0.0, 0.0, 0.0))
-            for k in range(3):
-                arr[i].pole[k] = pole[k] if k < len(pole) else 0.0
+            _fill_solid(arr[i], s)
         mp = None
         if mu_w_map is not None:
             self._muw = np.ascontiguousarray(mu_w_map, dtype=np.float64).reshape(-1)
@@ -393,7 +383,7 @@ class Lattice:
 
 
 def _fill_solid(dst, s):
-    dst.kind = LBM_SOLID_SPHERE
+    dst.kind = LBM_SOLID_CAVITY if s.get("cavity") else LBM_SOLID_SPHERE
     c = list(s["center"]) + [0.0] * (3 - len(s["center"]))
     for k in range(3):
         dst.center[k] = c[k]
@@ -404,6 +394,9 @@ def _fill_solid(dst, s):
     else:
         dst.wet_mode = LBM_WET_UNIFORM
         dst.mu_w = s.get("mu_w", 0.0)
+    pole = s.get("pole", (0.0, 0.0, 0.0))
+    for k in range(3):
+        dst.pole[k] = pole[k] if k < len(pole) else 0.0
 
 
 class Batch:
