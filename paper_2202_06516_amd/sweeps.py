@@ -1,0 +1,175 @@
+"""Parameter sweeps of Sec. IV A-B on the batched solver.
+
+Every sweep is a set of independent 2-D cases -- a drop on a circular bump of
+radius R rising H above a walled floor (Fig. 2a) -- advanced together by the
+batched solver until every measured angle has settled, then reduced to the
+statistics the paper reports:
+
+- ``wettability``: theta against mu_w (Fig. 3) and the relative L2 deviation
+  of theta(mu_w) from its least-squares line (the error E of Sec. IV A, its
+  integrals taken as sums over the sampled mu_w);
+- ``size``: theta for drop radii r0 = 30..100 on each of five wettabilities
+  (Fig. 4a) and its standard deviation over r0;
+- ``curvature``: theta for bump radii R = 150..400 (Fig. 4b) and its standard
+  deviation over R.
+
+Each case also gets the spherical-cap angle of Sec. IV A from its final
+density (base length L between the two measured contact points, cap height
+above that chord, theta = beta - alpha on the convex bump).  Python orders
+library calls and reduces angle series and one density read per case; every
+step of the method runs in the library's kernels.
+
+Command line: ``python -m paper_2202_06516_amd.sweeps --help``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import lbm as G
+from . import workloads as WL
+
+
+def make_batch(cases, Tr, precision=G.LBM_F32, stream=None):
+    # the floor and ceiling are two solid layers (walled along y), x periodic
+    return G.Batch(cases, precision=precision, axis_bc=(0, 1, 0), tile_w=256, blocks_per_cu=8, stream=stream,
+                   tau=1.0, Tr=Tr, k=0.28, kappa=0.01, collision=G.LBM_MRT)
+
+
+def settle(b, every=1000, tol=0.02, min_steps=10000, max_steps=200000, log=print):
+    """Step until every valid case's angle moved by less than tol degrees over
+    the last interval (after min_steps), or max_steps.  Returns the angle
+    history [intervals, cases] (NaN where a case had no contact line)."""
+    hist = []
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        b.step(every, measure_every=every)
+        steps += every
+        hist.append([a.mean_deg if a.status == 0 else math.nan for a in b.angles()])
+        if len(hist) >= 2 and steps >= min_steps:
+            d = np.abs(np.array(hist[-1]) - np.array(hist[-2]))
+            if np.all(d[np.isfinite(d)] < tol):
+                break
+        if steps % (10 * every) == 0:
+            log(f"sweep: step {steps}, {time.perf_counter() - t0:.1f} s")
+    try:
+        b.sync()
+    except G.LbmError as e:   # a case that lost finiteness keeps NaN below
+        if e.status != G.LBM_E_NONFINITE:
+            raise
+    return np.array(hist), steps, time.perf_counter() - t0
+
+
+def cap_angle(rho, cls, rho_m, centre, R, contact):
+    """Spherical-cap angle (Sec. IV A) of a drop on a convex circle: base L
+    between the two contact points, height Hc of the interface above that chord,
+    R0 = (4 Hc^2 + L^2) / 8 Hc, tan beta = L / 2 (R0 - Hc), theta = beta - alpha
+    with alpha = asin(L / 2R) the chord's half-angle seen from the centre."""
+    ny, nx = rho.shape
+    fl = cls == 0
+    pts = []
+    for dx, dy in ((1, 0), (0, 1)):
+        r0, r1 = rho[: ny - dy, : nx - dx], rho[dy:, dx:]
+        ok = fl[: ny - dy, : nx - dx] & fl[dy:, dx:] & ((r0 - rho_m) * (r1 - rho_m) < 0)
+        yy, xx = np.nonzero(ok)
+        t = (rho_m - r0[ok]) / (r1[ok] - r0[ok])
+        pts.append(np.c_[xx + t * dx, yy + t * dy])
+    pts = np.vstack(pts)
+    c1, c2 = np.asarray(contact[0][:2]), np.asarray(contact[1][:2])
+    L = float(np.linalg.norm(c2 - c1))
+    mid = 0.5 * (c1 + c2)
+    up = mid - np.asarray(centre[:2])
+    up /= np.linalg.norm(up)
+    Hc = float(np.max((pts - mid) @ up))
+    if not (L > 0 and Hc > 0 and L < 2 * R):
+        return math.nan
+    R0 = (4 * Hc * Hc + L * L) / (8 * Hc)
+    beta = math.degrees(math.atan2(L, 2 * (R0 - Hc)))
+    return beta - math.degrees(math.asin(0.5 * L / R))
+
+
+def linear_fit_error(x, y):
+    """Least-squares line F through (x, y) and E = ||y - F|| / ||F||."""
+    x, y = np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64)
+    A = np.c_[x, np.ones_like(x)]
+    (a, c), *_ = np.linalg.lstsq(A, y, rcond=None)
+    F = a * x + c
+    return float(np.linalg.norm(y - F) / np.linalg.norm(F)), float(a), float(c)
+
+
+def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, every=1000, tol=0.02,
+        min_steps=10000, max_steps=200000, stream=None, log=print):
+    cases, labels = WL.sweep_cases(kind, scale=scale, mu=mu, values=values)
+    nx, ny = cases[0]["n"]
+    H = 100.0 * scale
+    b = make_batch(cases, Tr, precision, stream)
+    inf = b.info()
+    rho_m = 0.5 * (inf["rho_g"] + inf["rho_l"])
+    log(f"sweep {kind}: {len(cases)} cases of {nx}x{ny}, Tr = {Tr}")
+    hist, steps, seconds = settle(b, every, tol, min_steps, max_steps, log)
+    final = b.angles()
+    res = []
+    for i, (cs, (v, m)) in enumerate(zip(cases, labels)):
+        th = hist[-1, i]
+        drift = float(abs(hist[-1, i] - hist[-2, i])) if len(hist) > 1 else math.nan
+        cap = math.nan
+        if math.isfinite(th):
+            rho = b.read(i, G.FIELD_RHO)[0].astype(np.float64)
+            cls = b.read(i, G.FIELD_CLASS)[0]
+            if np.isfinite(rho).all():
+                cap = cap_angle(rho, cls, rho_m, cs["solid"]["center"], cs["solid"]["radius"], final[i].contact)
+        res.append(dict(value=float(v), mu_w=float(m), theta=float(th), cap=float(cap), drift=drift,
+                        sectors=[float(final[i].sector_deg[k]) for k in range(2)],
+                        contact=[[round(float(final[i].contact[k][d]), 2) for d in range(2)] for k in range(2)]))
+    b.close()
+    out = dict(kind=kind, Tr=Tr, nx=nx, ny=ny, H=H, steps=steps, seconds=round(seconds, 2),
+               mlups=round(float(inf["fluid_nodes"]) * steps / seconds / 1e6, 1), cases=res)
+    ok = [r for r in res if math.isfinite(r["theta"])]
+    if kind == "wettability" and len(ok) >= 3:
+        E, a, c = linear_fit_error([r["mu_w"] for r in ok], [r["theta"] for r in ok])
+        out.update(E=round(E, 4), slope_deg_per_mu=round(a, 2), intercept_deg=round(c, 2))
+        okc = [r for r in ok if math.isfinite(r["cap"])]
+        if okc:
+            out["max_abs_theta_minus_cap"] = round(max(abs(r["theta"] - r["cap"]) for r in okc), 2)
+    if kind in ("size", "curvature"):
+        per = {}
+        for r in ok:
+            per.setdefault(r["mu_w"], []).append(r["theta"])
+        out["per_mu"] = {str(m): dict(mean=round(float(np.mean(t)), 2), std=round(float(np.std(t)), 3), n=len(t))
+                         for m, t in sorted(per.items())}
+    out["invalid"] = len(res) - len(ok)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="wettability / drop-size / curvature sweeps on the batched solver")
+    ap.add_argument("kind", choices=("wettability", "size", "curvature"))
+    ap.add_argument("--Tr", type=float, default=0.6)
+    ap.add_argument("--f64", action="store_true", help="FP64 storage and arithmetic (default FP32 storage)")
+    ap.add_argument("--scale", type=float, default=1.0, help="every length times this (1: the 700 x 400 lattice)")
+    ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--tol", type=float, default=0.02)
+    ap.add_argument("--min-steps", type=int, default=10000)
+    ap.add_argument("--max-steps", type=int, default=200000)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    rep = run(a.kind, Tr=a.Tr, precision=G.LBM_F64 if a.f64 else G.LBM_F32, scale=a.scale, every=a.every,
+              tol=a.tol, min_steps=a.min_steps, max_steps=a.max_steps, log=log)
+    print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
+    for r in rep["cases"]:
+        print(json.dumps(r), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(rep, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

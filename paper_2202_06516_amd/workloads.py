@@ -18,6 +18,9 @@ Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
   cavity_2d    D2Q9 128x128 periodic, circular cavity r=56 at the centre, drop
                r0=20 at its lowest point (concave substrate)
   cavity_3d    D3Q19 64^3, spherical cavity r=28 at the centre, drop r0=16
+  bump_case    a drop on a circular bump of radius R and height H above a
+               walled floor (Fig. 2a); sweep_cases builds the wettability,
+               drop-size and curvature sweeps of Sec. IV A-B from it
   batch_cases  many D2Q9 drops on cylinders of random sizes (batched solver)
   warmstart_cases  256^2 D2Q9 drops on cylinders, cylinder radius 16..64, drop
                radius 18..48 (smaller drops dissolve into the gas at Tr=0.8
@@ -170,6 +173,52 @@ def cavity_3d(mu_w=0.04, n=64):
     return dict(dim=3, n=(n, n, n), wall=(0, 0, 0), Tr=0.8,
                 solids=[dict(center=c, radius=R, mu_w=mu_w, cavity=True)],
                 drops=[((c[0], c[1], c[2] - R + r0), r0)], steps=5000, every=100, n_sectors=16)
+
+
+def bump_case(nx, ny, R, H, r0, mu_w):
+    """A drop on a circular bump (Fig. 2a): the arc of a circle of radius R rising
+    H above a flat floor, centred horizontally, with the drop of radius r0
+    tangent on its top.  For a lattice walled along y (two solid layers at each
+    end, the floor surface at y = 1.5 lu); the bump's width is
+    L = 2 sqrt(2 R H - H^2)."""
+    floor = 1.5
+    cy = floor + H - R
+    return dict(n=(int(nx), int(ny)), solid=dict(center=(nx / 2.0, cy), radius=float(R), mu_w=float(mu_w)),
+                drop=((nx / 2.0, floor + H + r0), float(r0)))
+
+
+# the sweeps of Sec. IV A-B on bumps (lattice 700 x 400 walled along y, as the
+# paper's gravity-free domain): wettability at r0 = 40 on R = 150, drop size
+# r0 = 30..100 on R = 400, curvature R = 150..400 at r0 = 40; all with H = 100.
+# Below mu_w = -0.02 a drop of r0 = 40 spreads to the foot of the bump at Tr = 0.6.
+SWEEP_MU = tuple(float(m) for m in np.round(np.linspace(-0.02, 0.16, 10), 4))
+SWEEP_MU5 = (-0.01, 0.02, 0.04, 0.07, 0.1)
+SWEEP_R0 = (30, 40, 50, 60, 70, 80, 90, 100)
+SWEEP_RS = (150, 200, 250, 300, 350, 400)
+
+
+def sweep_cases(kind, scale=1.0, mu=None, values=None):
+    """Case table of one sweep ("wettability", "size" or "curvature") with a
+    (value, mu_w) label per case; every length (lattice, H, R, r0) times scale."""
+    s = float(scale)
+    nx, ny, H = int(round(700 * s)), int(round(400 * s)), 100.0 * s
+    if kind == "wettability":
+        mu = SWEEP_MU if mu is None else mu
+        pairs = [(m, m) for m in mu]
+        cases = [bump_case(nx, ny, 150.0 * s, H, 40.0 * s, m) for m in mu]
+    elif kind == "size":
+        mu = SWEEP_MU5 if mu is None else mu
+        values = SWEEP_R0 if values is None else values
+        pairs = [(r, m) for m in mu for r in values]
+        cases = [bump_case(nx, ny, 400.0 * s, H, r * s, m) for r, m in pairs]
+    elif kind == "curvature":
+        mu = SWEEP_MU5 if mu is None else mu
+        values = SWEEP_RS if values is None else values
+        pairs = [(R, m) for m in mu for R in values]
+        cases = [bump_case(nx, ny, R * s, H, 40.0 * s, m) for R, m in pairs]
+    else:
+        raise ValueError(kind)
+    return cases, pairs
 
 
 def random_state_perturbation(shape, q, seed, amplitude=1e-3):

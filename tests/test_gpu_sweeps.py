@@ -1,0 +1,49 @@
+"""Sweeps of Sec. IV A-B on the batched solver (drops on bumps over a walled floor)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2202_06516_amd import lbm as G
+from paper_2202_06516_amd import sweeps as S
+from paper_2202_06516_amd import workloads as W
+
+from .pairs import BASE, gpu_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def test_walled_batch_equals_single_lattices():
+    # the sweeps run the batched solver with a floor and a ceiling (two solid
+    # layers each); every case must advance exactly as a lone walled lattice
+    cases = [W.bump_case(96, 70, 30.0, 16.0, 10.0, 0.04), W.bump_case(120, 64, 60.0, 12.0, 9.0, -0.01)]
+    b = G.Batch(cases, precision=G.LBM_F64, axis_bc=(0, 1, 0), **dict(BASE, Tr=0.8))
+    b.step(40, measure_every=20)
+    b.sync()
+    ang = b.angles()
+    for i, cs in enumerate(cases):
+        wl = dict(dim=2, n=cs["n"], wall=(0, 1), solids=[cs["solid"]], drops=[cs["drop"]])
+        s = gpu_lattice(wl, G.LBM_F64, Tr=0.8)
+        sa = s.step(40, measure_every=20, cap=4)
+        assert np.array_equal(b.read(i, G.FIELD_CLASS), s.read(G.FIELD_CLASS))
+        assert np.array_equal(b.read(i, G.FIELD_F), s.f), i
+        assert ang[i].step == sa[-1].step and ang[i].status == sa[-1].status == 0
+        for k in range(2):
+            assert abs(ang[i].sector_deg[k] - sa[-1].sector_deg[k]) <= 1e-12
+
+
+def test_small_wettability_sweep():
+    # 280 x 160 lattices (0.4 of the paper's 700 x 400), r0 = 16 on a bump of
+    # R = 60, H = 40: the angle rises with mu_w (Fig. 3), both sides agree
+    # (the layout is mirror-symmetric), and away from the hydrophilic end the
+    # spherical-cap angle of the same drop lies within 6 degrees
+    rep = S.run("wettability", scale=0.4, mu=(-0.02, 0.04, 0.1, 0.16), max_steps=30000, log=lambda s: None)
+    th = [r["theta"] for r in rep["cases"]]
+    print(rep)
+    assert rep["invalid"] == 0 and all(math.isfinite(t) for t in th)
+    assert th[0] < 90.0 < th[2] and th[0] < th[1] < th[2] < th[3], th
+    for r in rep["cases"]:
+        assert abs(r["sectors"][0] - r["sectors"][1]) < 0.5, r
+        if r["mu_w"] >= 0.04:
+            assert abs(r["theta"] - r["cap"]) < 6.0, r
+    assert rep["E"] < 0.1
