@@ -35,10 +35,10 @@ from . import lbm as G
 from . import workloads as WL
 
 
-def make_batch(cases, Tr, precision=G.LBM_F32, stream=None):
+def make_batch(cases, Tr, precision=G.LBM_F32, stream=None, k=0.28, kappa=0.01):
     # the floor and ceiling are two solid layers (walled along y), x periodic
     return G.Batch(cases, precision=precision, axis_bc=(0, 1, 0), tile_w=256, blocks_per_cu=8, stream=stream,
-                   tau=1.0, Tr=Tr, k=0.28, kappa=0.01, collision=G.LBM_MRT)
+                   tau=1.0, Tr=Tr, k=k, kappa=kappa, collision=G.LBM_MRT)
 
 
 def settle(b, every=1000, tol=0.02, min_steps=10000, max_steps=200000, log=print):
@@ -104,11 +104,11 @@ def linear_fit_error(x, y):
 
 
 def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, every=1000, tol=0.02,
-        min_steps=10000, max_steps=200000, stream=None, log=print):
+        min_steps=10000, max_steps=200000, k=0.28, kappa=0.01, stream=None, log=print):
     cases, labels = WL.sweep_cases(kind, scale=scale, mu=mu, values=values)
     nx, ny = cases[0]["n"]
     H = 100.0 * scale
-    b = make_batch(cases, Tr, precision, stream)
+    b = make_batch(cases, Tr, precision, stream, k=k, kappa=kappa)
     inf = b.info()
     rho_m = 0.5 * (inf["rho_g"] + inf["rho_l"])
     log(f"sweep {kind}: {len(cases)} cases of {nx}x{ny}, Tr = {Tr}")
@@ -128,7 +128,7 @@ def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, ever
                         sectors=[float(final[i].sector_deg[k]) for k in range(2)],
                         contact=[[round(float(final[i].contact[k][d]), 2) for d in range(2)] for k in range(2)]))
     b.close()
-    out = dict(kind=kind, Tr=Tr, nx=nx, ny=ny, H=H, steps=steps, seconds=round(seconds, 2),
+    out = dict(kind=kind, Tr=Tr, k=k, kappa=kappa, nx=nx, ny=ny, H=H, steps=steps, seconds=round(seconds, 2),
                mlups=round(float(inf["fluid_nodes"]) * steps / seconds / 1e6, 1), cases=res)
     ok = [r for r in res if math.isfinite(r["theta"])]
     if kind == "wettability" and len(ok) >= 3:
@@ -153,6 +153,9 @@ def main(argv=None):
     ap.add_argument("--Tr", type=float, default=0.6)
     ap.add_argument("--f64", action="store_true", help="FP64 storage and arithmetic (default FP32 storage)")
     ap.add_argument("--scale", type=float, default=1.0, help="every length times this (1: the 700 x 400 lattice)")
+    ap.add_argument("--k", type=float, default=0.28, help="EOS scaling k (a smaller k widens the interface)")
+    ap.add_argument("--kappa", type=float, default=0.01)
+    ap.add_argument("--mu", type=float, nargs="*", default=None, help="wall chemical potentials (default per sweep)")
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--min-steps", type=int, default=10000)
@@ -161,7 +164,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     rep = run(a.kind, Tr=a.Tr, precision=G.LBM_F64 if a.f64 else G.LBM_F32, scale=a.scale, every=a.every,
-              tol=a.tol, min_steps=a.min_steps, max_steps=a.max_steps, log=log)
+              tol=a.tol, min_steps=a.min_steps, max_steps=a.max_steps, k=a.k, kappa=a.kappa,
+              mu=tuple(a.mu) if a.mu else None, log=log)
     print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
     for r in rep["cases"]:
         print(json.dumps(r), flush=True)
