@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("omega", C.c_double), ("k", C.c_double), ("kappa", C.c_double),
         ("g", C.c_double * 3), ("g_start", C.c_longlong),
         ("rho_l", C.c_double), ("rho_g", C.c_double), ("wall_mu", C.c_double),
+        ("model", C.c_int), ("sc_G", C.c_double),
     ]
 
 
@@ -180,7 +181,7 @@ def feq(dim, rho, u):
 DEFAULTS = dict(tau=1.0, s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.54, s_m=1.9,
                 Tr=0.6, a=PR_A, b=PR_B, R=PR_R, omega=PR_OMEGA, k=0.28, kappa=0.01,
                 g=(0.0, 0.0, 0.0), g_start=0, rho_l=0.0, rho_g=0.0, wall_mu=math.nan,
-                bgk=0, bc_mode=0)
+                bgk=0, bc_mode=0, model=0, sc_G=0.0)
 
 
 def make_params(dim, n, wall=(0, 0, 0), **kw):
@@ -199,6 +200,8 @@ def make_params(dim, n, wall=(0, 0, 0), **kw):
                  "k", "kappa", "rho_l", "rho_g", "wall_mu"):
         setattr(p, name, float(cfg[name]))
     p.g_start = int(cfg["g_start"])
+    p.model = int(cfg["model"])
+    p.sc_G = float(cfg["sc_G"])
     return p
 
 

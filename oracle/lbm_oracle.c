@@ -423,6 +423,16 @@ ora_ctx* ora_create(const ora_params* p) {
     if (p->rho_l > 0) c->rho_l = p->rho_l;
     if (p->rho_g > 0) c->rho_g = p->rho_g;
     c->wall_mu = isnan(p->wall_mu) ? p->k * p->k * c->mu_sat : p->wall_mu;
+    if (p->model == 1) {
+        /* pseudopotential: the coexistence densities are inputs (they depend
+         * on the forcing scheme, not on a closed-form construction), and the
+         * wall value is a wall density, neutral default midway */
+        if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_l > p->rho_g)) { free(c); return NULL; }
+        if (isnan(p->wall_mu)) c->wall_mu = 0.5 * (p->rho_l + p->rho_g);
+    } else if (p->model != 0) {
+        free(c);
+        return NULL;
+    }
     size_t N = (size_t)c->N, Q = (size_t)c->Q;
     c->f = (double*)calloc(Q * N, sizeof(double));
     c->fpost = (double*)calloc(Q * N, sizeof(double));
@@ -683,13 +693,22 @@ static double d2(const ora_ctx* c, const double* phi, int x, int y, int z, int a
     return (-v[0] + 16.0 * v[1] - 30.0 * v[2] + 16.0 * v[3] - v[4]) / 12.0;
 }
 
-/* Eq. 11 / Eq. 12 on fluid nodes; the prescribed wall value on both solid layers */
+/* pseudopotential of the Shan-Chen model, psi(rho) = 1 - exp(-rho) (rho_0 = 1) */
+static double sc_psi(double rho) { return 1.0 - exp(-rho); }
+
+/* Eq. 11 / Eq. 12 on fluid nodes; the prescribed wall value on both solid
+ * layers.  Pseudopotential model: psi(rho) on fluid nodes and psi of the
+ * wall density on the layers (the virtual-density wetting condition). */
 void ora_phase_mu(ora_ctx* c) {
     const ora_params* p = &c->p;
 #pragma omp parallel for schedule(static)
     for (long long n = 0; n < c->N; ++n) {
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
-        if (c->cls[n] == C_FLUID) {
+        if (p->model == 1) {
+            if (c->cls[n] == C_FLUID) c->mu[n] = sc_psi(c->rho[n]);
+            else if (c->cls[n] == C_L1 || c->cls[n] == C_L2) c->mu[n] = sc_psi(wall_mu_at(c, n, x, y, z));
+            else c->mu[n] = 0.0;
+        } else if (c->cls[n] == C_FLUID) {
             double lap = 0;
             for (int ax = 0; ax < c->dim; ++ax) lap += d2(c, c->rho, x, y, z, ax);
             c->mu[n] = p->k * p->k * ora_pr_mu(c->rho[n], c->T, p->a, p->b, p->R, c->alpha) - p->kappa * lap;
@@ -701,7 +720,8 @@ void ora_phase_mu(ora_ctx* c) {
     }
 }
 
-/* Eq. 7, plus the body force rho g once the step counter reaches g_start */
+/* Eq. 7, plus the body force rho g once the step counter reaches g_start;
+ * the pseudopotential model takes the Shan-Chen interaction force instead */
 void ora_phase_force(ora_ctx* c) {
     const ora_params* p = &c->p;
     int grav = c->step >= p->g_start;
@@ -710,6 +730,22 @@ void ora_phase_force(ora_ctx* c) {
         for (int d = 0; d < 3; ++d) c->F[(size_t)d * c->N + n] = 0.0;
         if (c->cls[n] != C_FLUID) continue;
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
+        if (p->model == 1) {
+            /* Shan-Chen interaction with the lattice weights:
+             * F = -G psi(x) sum_i w_i psi(x + e_i) e_i */
+            double s[3] = {0, 0, 0};
+            for (int i = 1; i < c->Q; ++i) {
+                long long m = nbr(c, x, y, z, c->e[i][0], c->e[i][1], c->e[i][2]);
+                if (m < 0) continue;
+                for (int d = 0; d < 3; ++d) s[d] += c->w[i] * c->mu[m] * c->e[i][d];
+            }
+            for (int ax = 0; ax < c->dim; ++ax) {
+                double Fv = -p->sc_G * c->mu[n] * s[ax];
+                if (grav) Fv += c->rho[n] * p->g[ax];
+                c->F[(size_t)ax * c->N + n] = Fv;
+            }
+            continue;
+        }
         for (int ax = 0; ax < c->dim; ++ax) {
             double gm = d1(c, c->mu, x, y, z, ax);
             double gr = d1(c, c->rho, x, y, z, ax);

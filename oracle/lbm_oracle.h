@@ -31,6 +31,8 @@ typedef struct {
     long long g_start;                        /* first step at which g acts */
     double rho_l, rho_g;                      /* <= 0: Maxwell coexistence */
     double wall_mu;                           /* outer-wall chemical potential; NaN: k^2 mu_sat */
+    int model;          /* 0: chemical potential (Sec. II B); 1: pseudopotential (Shan-Chen) */
+    double sc_G;        /* pseudopotential interaction strength (model 1) */
 } ora_params;
 
 typedef struct {

@@ -21,6 +21,8 @@ Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
   bump_case    a drop on a circular bump of radius R and height H above a
                walled floor (Fig. 2a); sweep_cases builds the wettability,
                drop-size and curvature sweeps of Sec. IV A-B from it
+  sc_sessile_2d  the sessile layout for the pseudopotential model (wall density
+               rho_w in place of mu_w)
   batch_cases  many D2Q9 drops on cylinders of random sizes (batched solver)
   warmstart_cases  256^2 D2Q9 drops on cylinders, cylinder radius 16..64, drop
                radius 18..48 (smaller drops dissolve into the gas at Tr=0.8
@@ -219,6 +221,24 @@ def sweep_cases(kind, scale=1.0, mu=None, values=None):
     else:
         raise ValueError(kind)
     return cases, pairs
+
+
+# the pseudopotential (Shan-Chen) model: psi = 1 - exp(-rho), interaction
+# strength G, and the bulk densities of a flat interface it relaxes to (a
+# converged 128 x 4 slab of the oracle, MRT and BGK alike to 4e-5)
+SC_G = -6.0
+SC_RHO_L = 2.649
+SC_RHO_G = 0.0735
+
+
+def sc_sessile_2d(rho_w=0.8, n=128):
+    """The sessile layout of sessile_2d for the pseudopotential model: cylinder
+    r = 24 at (64, 40), drop r0 = 20 on top, interface width W = 5, wall
+    density rho_w on the cylinder (scaled with n/128)."""
+    s = n / 128.0
+    return dict(dim=2, n=(n, n), wall=(0, 0), model=1,
+                solids=[dict(center=(64 * s, 40 * s), radius=24 * s, mu_w=rho_w)],
+                drops=[((64 * s, 84 * s), 20 * s)], W=5.0, steps=5000, every=100)
 
 
 def random_state_perturbation(shape, q, seed, amplitude=1e-3):

@@ -651,3 +651,73 @@ def test_cavity_angle_grows_with_wall_potential():
         assert a.status == 0 and a.n_valid == 2
         th.append(a.mean_deg)
     assert th[0] < 90.0 < th[2] and th[0] < th[1] < th[2], th
+
+
+# ------------------------------- pseudopotential model (Sec. V: other models)
+
+SC = dict(model=1, sc_G=W.SC_G, rho_l=W.SC_RHO_L, rho_g=W.SC_RHO_G)
+
+
+def _sc_eos(rho, G):
+    # the bulk pressure of the Shan-Chen interaction written with the lattice
+    # weights: p = rho c_s^2 + G c_s^2 psi^2 / 2, c_s^2 = 1/3
+    psi = 1.0 - math.exp(-rho)
+    return rho / 3.0 + G * psi * psi / 6.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sc_force_exact_on_quadratic_psi(dim):
+    # the odd moments of the lattice weights vanish and the second ones are
+    # c_s^2 I, so sum_i w_i psi(x + e_i) e_i = c_s^2 grad psi exactly when psi
+    # is a quadratic: F = -G psi grad psi / 3 on every interior node
+    o = O.Oracle(dim, (12, 11, 10 if dim == 3 else 1), **SC)
+    zz, yy, xx = np.mgrid[0:o.shape[0], 0:o.shape[1], 0:o.shape[2]].astype(np.float64)
+    psi = 0.3 + 0.01 * xx + 0.015 * yy + 0.002 * xx * xx - 0.001 * xx * yy + 0.0015 * yy * yy
+    gx, gy, gz = 0.01 + 0.004 * xx - 0.001 * yy, 0.015 - 0.001 * xx + 0.003 * yy, 0.0 * xx
+    if dim == 3:
+        psi = psi + 0.01 * zz + 0.001 * zz * zz - 0.0007 * xx * zz
+        gx, gz = gx - 0.0007 * zz, 0.01 + 0.002 * zz - 0.0007 * xx
+    o.set_rho(-np.log(1.0 - psi))
+    for ph in ("density", "fill", "mu", "force"):
+        o.phase(ph)
+    inner = (slice(1, -1) if dim == 3 else slice(None), slice(1, -1), slice(1, -1))
+    F = o.force
+    for ax, g in enumerate((gx, gy, gz)[:dim]):
+        ref = -W.SC_G * psi * g / 3.0
+        assert np.max(np.abs(F[ax][inner] - ref[inner])) < 1e-14, ax
+
+
+def test_sc_flat_interface_has_equal_bulk_pressures():
+    # a liquid slab relaxes until the momentum flux through the flat interface
+    # balances: the bulk pressures of the two phases are equal (to 5e-13 after
+    # 40,000 steps; 1e-6 after 20,000)
+    o = O.Oracle(2, (128, 4), bgk=1, **SC)
+    x = np.arange(128)
+    r = 0.5 * (2.0 + 0.2) + 0.5 * (2.0 - 0.2) * np.tanh((32 - np.abs(x - 64.0)) / 2.0)
+    o.set_rho(np.broadcast_to(r, (1, 4, 128)).copy())
+    o.step(40000)
+    o.update_derived()
+    rl, rg = o.rho[0, 0, 64], o.rho[0, 0, 0]
+    assert rl > 2.5 and rg < 0.1
+    pl, pg = _sc_eos(rl, W.SC_G), _sc_eos(rg, W.SC_G)
+    assert abs(pl - pg) < 1e-10 * pl, (rl, rg, pl, pg)
+    assert abs(rl - W.SC_RHO_L) < 1e-3 and abs(rg - W.SC_RHO_G) < 1e-3
+
+
+def test_sc_mass_and_wetting_order():
+    # mass is conserved to round-off, and a denser wall wets more (Sec. V: the
+    # measurement is the same for any model that yields a density field)
+    th = []
+    for rho_w in (0.4, 0.8, 1.3):
+        wl = W.sc_sessile_2d(rho_w)
+        o = O.Oracle(2, wl["n"], **SC)
+        s = wl["solids"][0]
+        o.add_sphere(s["center"], s["radius"], mu_w=rho_w)
+        o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=wl["W"])
+        m0 = o.mass()
+        o.step(2500)
+        assert abs(o.mass() / m0 - 1) < 1e-12
+        a = o.measure()
+        assert a.status == 0 and a.n_valid == 2
+        th.append(a.mean_deg)
+    assert th[0] > 120.0 and th[0] > th[1] > th[2] and th[2] < 70.0, th
