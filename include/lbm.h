@@ -72,6 +72,16 @@ enum { LBM_F32 = 0, LBM_F64 = 1, LBM_F32_MIXED = 2 };
 enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
 enum { LBM_MRT = 0, LBM_BGK = 1 };
 enum { LBM_BC_HALFWAY = 0, LBM_BC_BOUZIDI_MC = 1 };
+/* Force model of the step.  The paper's own is the chemical-potential model
+ * (Sec. II B).  Sec. V states that the measurement serves other multiphase
+ * models as well, such as the pseudopotential ones.  LBM_MODEL_PSEUDOPOTENTIAL
+ * is the Shan-Chen model: psi(rho) = 1 - exp(-rho) and
+ * F = -G psi(x) sum_i w_i psi(x + e_i) e_i (+ rho g), with the same collision,
+ * streaming and measurement.  Wetting uses a wall density: every mu_w (of a
+ * primitive, a stripe, the map or the outer walls) is read as a density rho_w,
+ * and both solid layers carry psi(rho_w).  Its coexistence densities depend on
+ * the forcing scheme, so rho_l and rho_g must be given. */
+enum { LBM_MODEL_CHEMICAL_POTENTIAL = 0, LBM_MODEL_PSEUDOPOTENTIAL = 1 };
 
 #define LBM_MAX_SECTORS 64
 #define LBM_MAX_SOLIDS 16
@@ -95,8 +105,13 @@ typedef struct {
     double g[3];          /* body acceleration in lattice units; force rho g on fluid nodes */
     int64_t g_start_step; /* first step t at which g acts */
     double rho_l, rho_g;  /* coexistence densities; <= 0 selects the Maxwell construction */
-    double wall_mu;       /* chemical potential of outer walls; NaN selects k^2 mu_sat */
+    double wall_mu;       /* chemical potential of outer walls; NaN selects k^2 mu_sat
+                             (pseudopotential model: wall density, NaN selects (rho_l + rho_g) / 2) */
     void* stream;         /* hipStream_t to enqueue on, or NULL for a context-owned stream */
+    int model;            /* LBM_MODEL_CHEMICAL_POTENTIAL (default) or LBM_MODEL_PSEUDOPOTENTIAL; the
+                             pseudopotential model needs rho_l > rho_g > 0 and ignores Tr, pr_*, k, kappa;
+                             the batched solver accepts the default model only */
+    double sc_G;          /* pseudopotential interaction strength G (default -6) */
 } lbm_config;
 
 /* Fill *cfg with the library defaults for the given lattice. */
@@ -170,7 +185,8 @@ enum {
     LBM_FIELD_RHO = 0,   /* [N] density of S_t (fluid), Eq. 14 fill on the two solid layers */
     LBM_FIELD_F = 1,     /* [Q][N] populations S_t */
     LBM_FIELD_VEL = 2,   /* [3][N] v = u + F / (2 rho), Sec. II B */
-    LBM_FIELD_MU = 3,    /* [N] chemical potential of Eq. 12; wall value on the solid layers */
+    LBM_FIELD_MU = 3,    /* [N] chemical potential of Eq. 12; wall value on the solid layers
+                            (pseudopotential model: psi, and psi(rho_w) on the layers) */
     LBM_FIELD_CLASS = 4, /* [N] uint8: 0 fluid, 1 first solid layer, 2 second, 3 deeper solid */
     LBM_FIELD_MASS = 5   /* one double: sum of S_t over fluid nodes */
 };

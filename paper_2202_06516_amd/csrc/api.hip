@@ -161,6 +161,7 @@ struct Run {
         }
         for (int k = 0; k < 3; ++k) cp.g[k] = (C)(k < c->dim ? g.g[k] : 0.0);
         cp.g_start = g.g_start_step;
+        cp.sc_G = g.sc_G;
         return cp;
     }
     static dim3 grid(const lbm_ctx* c) { return dim3(c->d.nblocks, 1, 1); }
@@ -199,6 +200,24 @@ struct Run {
         }
     }
 
+    // chemical potential, or psi of the pseudopotential model, on fluid nodes
+    static void launch_mu(lbm_ctx* c, R* rho, R* mu) {
+        if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
+            k_mu<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+        else
+            k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+    }
+
+    template <bool PULL, bool MRT>
+    static void launch_collide(lbm_ctx* c, const R* fin, R* fout, R* rho, R* mu, const WallBC& bc,
+                               const Collision<C>& cp) {
+        const dim3 blk(256, 1, 1), grd = grid(c);
+        if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
+            k_collide<L, R, C, PULL, MRT, true><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+        else
+            k_collide<L, R, C, PULL, MRT><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+    }
+
     // the launches of one step, reading f[src] and writing f[1-src]; pull
     // selects the form of f[src] (post-collision populations, else S_t)
     static void step_launches(lbm_ctx* c, int src, bool pull, const MeasureParams& mp, hipEvent_t* ev, int* kinds) {
@@ -215,7 +234,7 @@ struct Run {
         mark(0);
         fills(c, ev, kinds, k);
         start();
-        k_mu<L, R, C><<<grd, blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+        launch_mu(c, rho, mu);
         mark(3);
         start();
         k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, c->ctl, mp);
@@ -225,11 +244,11 @@ struct Run {
         const Collision<C> cp = collision(c);
         const bool mrt = c->cfg.collision == LBM_MRT;
         if (pull) {
-            if (mrt) k_collide<L, R, C, true, true><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
-            else k_collide<L, R, C, true, false><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+            if (mrt) launch_collide<true, true>(c, fin, fout, rho, mu, bc, cp);
+            else launch_collide<true, false>(c, fin, fout, rho, mu, bc, cp);
         } else {
-            if (mrt) k_collide<L, R, C, false, true><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
-            else k_collide<L, R, C, false, false><<<grd, blk, 0, c->stream>>>(fin, fout, rho, mu, c->cls, c->d, bc, cp, c->ctl);
+            if (mrt) launch_collide<false, true>(c, fin, fout, rho, mu, bc, cp);
+            else launch_collide<false, false>(c, fin, fout, rho, mu, bc, cp);
         }
         mark(4);
         start();
@@ -257,21 +276,25 @@ struct Run {
         density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
         int k = 0;
         fills(c, nullptr, nullptr, k);
-        if (with_mu) k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c));
+        if (with_mu) launch_mu(c, (R*)c->rho, (R*)c->mu);
     }
 
     static void velocity(lbm_ctx* c, void* out) {
         derive(c, true);
         const R* S = materialize(c);
-        k_velocity<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d,
-                                                                        collision(c), c->t, (R*)out);
+        if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
+            k_velocity<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
+                S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
+        else
+            k_velocity<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
+                S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
     }
 
     static void measure_now(lbm_ctx* c, const MeasureParams& mp) {
         density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
         int k = 0;
         fills(c, nullptr, nullptr, k);
-        k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((R*)c->rho, (R*)c->mu, c->cls, c->d, thermo(c));
+        launch_mu(c, (R*)c->rho, (R*)c->mu);
         k_cross<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, c->ctl, mp);
         k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->rho, c->ctl, c->d, mp, nullptr, c->last, 0);
     }
@@ -412,6 +435,8 @@ void lbm_config_default(lbm_config* cfg, int lattice) {
     cfg->rho_l = cfg->rho_g = 0.0;
     cfg->wall_mu = NAN;
     cfg->stream = nullptr;
+    cfg->model = LBM_MODEL_CHEMICAL_POTENTIAL;
+    cfg->sc_G = -6.0;
 }
 
 const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -448,6 +473,10 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (cfg->bc_mode != LBM_BC_HALFWAY && cfg->bc_mode != LBM_BC_BOUZIDI_MC) return bad("bc_mode");
     if (!(cfg->k > 0) || !(cfg->kappa >= 0) || !(cfg->pr_a > 0) || !(cfg->pr_b > 0) || !(cfg->pr_R > 0))
         return bad("thermodynamic parameters");
+    if (cfg->model != LBM_MODEL_CHEMICAL_POTENTIAL && cfg->model != LBM_MODEL_PSEUDOPOTENTIAL) return bad("model");
+    if (cfg->model == LBM_MODEL_PSEUDOPOTENTIAL &&
+        (!(cfg->rho_g > 0) || !(cfg->rho_l > cfg->rho_g) || !std::isfinite(cfg->sc_G)))
+        return bad("the pseudopotential model needs rho_l > rho_g > 0 and a finite sc_G");
     c->d.nx = cfg->n[0];
     c->d.ny = cfg->n[1];
     c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
@@ -479,6 +508,11 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->rho_m = 0.5 * (c->pr.rho_l + c->pr.rho_g);
     c->wall_mu = std::isnan(cfg->wall_mu) ? cfg->k * cfg->k * c->pr.mu_sat : cfg->wall_mu;
     c->mu_ref = cfg->k * cfg->k * c->pr.mu_sat;
+    if (cfg->model == LBM_MODEL_PSEUDOPOTENTIAL) {
+        // wall values are densities; psi is stored unshifted
+        c->wall_mu = std::isnan(cfg->wall_mu) ? c->rho_m : cfg->wall_mu;
+        c->mu_ref = 0.0;
+    }
 
     lbm_status s = LBM_OK;
     if (cfg->stream) {
@@ -587,8 +621,12 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
     // static wall chemical potential on the two solid layers; zero elsewhere
     {
         std::vector<double> muh((size_t)g.N, 0.0);
-        for (size_t i = 0; i < g.l1_node.size(); ++i) muh[g.l1_node[i]] = g.l1_mu[i] - c->mu_ref;
-        for (size_t i = 0; i < g.l2_node.size(); ++i) muh[g.l2_node[i]] = g.l2_mu[i] - c->mu_ref;
+        // the layers' wall value: mu_w (stored shifted), or for the
+        // pseudopotential model psi of the wall density
+        const bool sc = c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL;
+        auto wall = [&](double v) { return sc ? 1.0 - std::exp(-v) : v - c->mu_ref; };
+        for (size_t i = 0; i < g.l1_node.size(); ++i) muh[g.l1_node[i]] = wall(g.l1_mu[i]);
+        for (size_t i = 0; i < g.l2_node.size(); ++i) muh[g.l2_node[i]] = wall(g.l2_mu[i]);
         if (c->f64) {
             HIPCHK(c, hipMemcpy(c->mu, muh.data(), g.N * 8, hipMemcpyHostToDevice));
         } else {

@@ -605,6 +605,7 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         return LBM_E_ARG;
     };
     if (base->lattice != LBM_D2Q9 && base->lattice != LBM_D3Q19) return bad();
+    if (base->model != LBM_MODEL_CHEMICAL_POTENTIAL) return bad();
     if (base->precision != LBM_F32 && base->precision != LBM_F64 && base->precision != LBM_F32_MIXED) return bad();
     if (!(base->tau > 0.5) || !(base->k > 0) || !(base->kappa >= 0)) return bad();
     b->dim = base->lattice == LBM_D2Q9 ? 2 : 3;

@@ -94,6 +94,7 @@ struct Collision {
     R rate[19];      // MRT: s_k / |row_k|^2 per moment
     R g[3];
     long long g_start;
+    double sc_G;     // pseudopotential interaction strength
 };
 
 // Reduction slots of one lattice's in-step measurement.
@@ -432,11 +433,19 @@ __device__ inline void crossing_point(double rho_g_node, double rho_l_node, doub
 // ---------------------------------------------------------------------------
 // chemical potential (+ fused crossing search on measure steps)
 // ---------------------------------------------------------------------------
-template <class L, typename R, typename C>
+template <class L, typename R, typename C, bool SC = false>
 __device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict__ mu, const uint8_t* __restrict__ cls,
                                         const Dims& d, const Thermo& th, int x, int y, int z, bool in, R& r0) {
     r0 = R(0);
     if (!in) return false;
+    if constexpr (SC) {
+        // pseudopotential model: psi(rho) = 1 - exp(-rho) on fluid nodes
+        const long long idx = nid(d, x, y, z);
+        if ((cls[idx] & CLS_MASK) != CLS_FLUID) return false;
+        r0 = rho[idx];
+        mu[idx] = (R)(C(1) - exp(-(C)r0));
+        return true;
+    }
     // the class and the density stencil are loaded together (every offset is
     // in bounds: periodic images), and the class decides only the store
     const long long idx = nid(d, x, y, z);
@@ -502,13 +511,13 @@ __device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const 
     }
 }
 
-template <class L, typename R, typename C>
+template <class L, typename R, typename C, bool SC = false>
 __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __restrict__ mu,
                                             const uint8_t* __restrict__ cls, Dims d, Thermo th) {
     int x, y, z;
     tile_node(d, x, y, z);
     R r0;
-    (void)mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
+    (void)mu_node<L, R, C, SC>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
 }
 
 // The crossing search of a measure step (Sec. III B), its own launch so that
@@ -540,7 +549,32 @@ template <class L, typename R, typename C, bool MRT, bool NT>
 __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
                                               R* __restrict__ o, long long N);
 
-template <class L, typename R, typename C, bool PULL, bool MRT, bool NT = false>
+// offset of the lattice neighbour x + e along one axis (e in {-1, 0, 1})
+__device__ __forceinline__ long long step_off(int e, const Nbr& o) { return e < 0 ? o.m1 : (e > 0 ? o.p1 : 0); }
+
+// Shan-Chen interaction of the pseudopotential model with the lattice
+// weights, F = -G psi(x) sum_i w_i psi(x + e_i) e_i, in double precision;
+// psi of fluid and solid-layer nodes is in the buffer passed as psi
+template <class L, typename R>
+__device__ __forceinline__ void sc_force(const R* __restrict__ psi, long long idx, const Nbr& ox, const Nbr& oy,
+                                         const Nbr& oz, double G, double& Fx, double& Fy, double& Fz) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        long long o = step_off(L::E[i][0], ox) + step_off(L::E[i][1], oy);
+        if (L::D == 3) o += step_off(L::E[i][2], oz);
+        const double v = L::w(i) * (double)psi[idx + o];
+        sx += v * L::E[i][0];
+        sy += v * L::E[i][1];
+        sz += v * L::E[i][2];
+    }
+    const double p0 = (double)psi[idx];
+    Fx = -G * p0 * sx;
+    Fy = -G * p0 * sy;
+    Fz = -G * p0 * sz;
+}
+
+template <class L, typename R, typename C, bool PULL, bool MRT, bool NT = false, bool SC = false>
 __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __restrict__ fout,
                                              const R* __restrict__ rho, const R* __restrict__ mu,
                                              const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
@@ -548,6 +582,24 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     if (x >= d.nx || y >= d.ny) return;
     const long long idx = nid(d, x, y, z);
     const uint8_t c = cls[idx];
+    if constexpr (SC) {
+        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
+        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.nx * d.ny) : Nbr{0, 0, 0, 0};
+        double Fx, Fy, Fz;
+        sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, Fx, Fy, Fz);
+        if (t >= cp.g_start) {
+            const double r0 = (double)rho[idx];
+            Fx += r0 * (double)cp.g[0];
+            Fy += r0 * (double)cp.g[1];
+            Fz += r0 * (double)cp.g[2];
+        }
+        asm volatile("" : : "v"(Fx), "v"(Fy), "v"(Fz));  // keeps the loads above the class test
+        if ((c & CLS_MASK) != CLS_FLUID) return;
+        R S[L::Q];
+        gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
+        collide_apply<L, R, C, MRT, NT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
+        return;
+    }
 
     // Eq. 7 with fourth-order central differences, formed before the class
     // test so that the stencil loads go out with the class load (every offset
@@ -668,14 +720,14 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
     }
 }
 
-template <class L, typename R, typename C, bool PULL, bool MRT>
+template <class L, typename R, typename C, bool PULL, bool MRT, bool SC = false>
 __global__ void __launch_bounds__(256) k_collide(const R* __restrict__ fin, R* __restrict__ fout,
                                                  const R* __restrict__ rho, const R* __restrict__ mu,
                                                  const uint8_t* __restrict__ cls, Dims d, WallBC bc,
                                                  Collision<C> cp, const DevCtl* __restrict__ ctl) {
     int x, y, z;
     tile_node(d, x, y, z);
-    collide_node<L, R, C, PULL, MRT, true>(fin, fout, rho, mu, cls, d, bc, cp, ctl->t, x, y, z);
+    collide_node<L, R, C, PULL, MRT, true, SC>(fin, fout, rho, mu, cls, d, bc, cp, ctl->t, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -903,7 +955,7 @@ __global__ void k_init_feq(const R* __restrict__ rho, R* __restrict__ f, const u
 
 // v = u + F / (2 rho) (Sec. II B), with F of Eq. 7 from the current rho and mu;
 // fin holds S_t
-template <class L, typename R, typename C = R>
+template <class L, typename R, typename C = R, bool SC = false>
 __global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, const R* __restrict__ rho,
                                                   const R* __restrict__ mu, const uint8_t* __restrict__ cls, Dims d,
                                                   Collision<C> cp, long long t, R* __restrict__ vel) {
@@ -918,7 +970,14 @@ __global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, con
     typedef double D;
     const D r0 = (D)rho[idx];
     D Fa[3] = {D(0), D(0), D(0)};
-    for (int a = 0; a < L::D; ++a) {
+    if constexpr (SC) {
+        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
+        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.nx * d.ny) : Nbr{0, 0, 0, 0};
+        sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, Fa[0], Fa[1], Fa[2]);
+        if (t >= cp.g_start)
+            for (int a = 0; a < 3; ++a) Fa[a] += r0 * (D)cp.g[a];
+    }
+    for (int a = 0; a < L::D && !SC; ++a) {
         int o[3] = {0, 0, 0};
         long long id[5];
         for (int k = -2; k <= 2; ++k) {

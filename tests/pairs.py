@@ -4,9 +4,14 @@ from __future__ import annotations
 import numpy as np
 
 from paper_2202_06516_amd import lbm as G
+from paper_2202_06516_amd import workloads as W
 
 # common physical parameters (both sides receive exactly these)
 BASE = dict(tau=1.0, s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.54, s_m=1.9, Tr=0.6, k=0.28, kappa=0.01)
+
+
+# the pseudopotential model's parameters (both sides receive exactly these)
+SC_PARAMS = dict(sc_G=W.SC_G, rho_l=W.SC_RHO_L, rho_g=W.SC_RHO_G)
 
 
 def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start=0, **extra):
@@ -15,6 +20,8 @@ def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0),
     params = dict(BASE)
     if "Tr" in wl:
         params["Tr"] = wl["Tr"]
+    if wl.get("model", 0) == 1:
+        params.update(SC_PARAMS, model=G.LBM_MODEL_PSEUDOPOTENTIAL)
     params.update(extra)
     gp = G.Lattice(lat, n=n, precision=precision, axis_bc=tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"])),
                    collision=G.LBM_MRT if collision == "mrt" else G.LBM_BGK,
@@ -22,7 +29,7 @@ def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0),
                    g=g, g_start_step=g_start, **params)
     gp.set_solids(wl["solids"])
     if wl.get("drops"):
-        gp.init_drops(wl["drops"], W=10.0)
+        gp.init_drops(wl["drops"], W=wl.get("W", 10.0))
     return gp
 
 
@@ -31,6 +38,8 @@ def oracle_lattice(wl, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start
     params = dict(BASE)
     if "Tr" in wl:
         params["Tr"] = wl["Tr"]
+    if wl.get("model", 0) == 1:
+        params.update(SC_PARAMS, model=1)
     params.update(extra)
     wall = tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"]))
     o = O.Oracle(wl["dim"], wl["n"], wall, bgk=int(collision == "bgk"), bc_mode=int(bc != "halfway"),
@@ -42,7 +51,7 @@ def oracle_lattice(wl, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start
         else:
             o.add_sphere(s["center"], s["radius"], mu_w=s.get("mu_w", 0.0), pole=s.get("pole"), cavity=cav)
     if wl.get("drops"):
-        o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=10.0)
+        o.init_drops([c for c, _ in wl["drops"]], [r for _, r in wl["drops"]], W=wl.get("W", 10.0))
     return o
 
 
