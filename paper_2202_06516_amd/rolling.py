@@ -14,7 +14,9 @@ Every ``every`` steps the in-step measurement gives the advancing angle (on
 the side the tangential part of g points to), the receding angle and both
 contact points.  The summary over the sliding phase: range (max - min) and
 standard deviation of theta_A and theta_R, and the hysteresis theta_A -
-theta_R (mean, max, share of samples within 5 degrees).
+theta_R (mean, max, share of samples within 5 degrees).  With ``young`` the
+unbalanced Young force (Sec. IV E, Eq. 17-18) of both contact lines is taken
+after every chunk of steps as well (Fig. 13-14).
 
 Command line: ``python -m paper_2202_06516_amd.rolling --help``.
 """
@@ -40,7 +42,10 @@ def start_drop(cx, cy, R, x0, r0):
 
 def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripes=None, g=5e-7, phi_deg=20.0,
         Tr=0.6, relax=20000, steps=600000, every=500, chunk=10000, stop_frac=0.6, precision=G.LBM_F32,
-        log=print):
+        young=None, log=print):
+    """young = (gamma, theta_1, theta_2): after every chunk of steps, also the
+    unbalanced Young force of Eq. 17 on both contact lines (lbm_young_force:
+    theta_eq of Eq. 18 from the footprint on the two kinds of band)."""
     phi = math.radians(phi_deg)
     # a closed box: with the tilted gravity an open (periodic) x axis would let
     # the whole gas column accelerate along x without bound
@@ -57,7 +62,7 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
     lat.set_measure(0, 2)
     half = math.sqrt(2 * R * H - H * H)       # half-width of the arc above the floor
     x_stop = cx + stop_frac * half
-    recs = []
+    recs, forces = [], []
     done = 0
     t0 = time.perf_counter()
     while done < steps:
@@ -73,8 +78,15 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
                              x_r=float(a.contact[1 - k][0]),
                              library_sides=bool(a.adv_deg == a.sector_deg[k] and a.rec_deg == a.sector_deg[1 - k])))
         done += n
+        if young is not None:
+            a, y = lat.young_force(*young)
+            if y.status == 0 and math.isfinite(y.force[0]) and math.isfinite(y.force[1]):
+                k = 0 if a.contact[0][0] > a.contact[1][0] else 1
+                forces.append(dict(step=int(a.step), force_a=float(y.force[k]), force_r=float(y.force[1 - k]),
+                                   theta_eq_a=float(y.theta_eq_deg[k]), theta_eq_r=float(y.theta_eq_deg[1 - k]),
+                                   phi_a=float(y.phi_d[k]), phi_r=float(y.phi_d[1 - k])))
         last = next((r for r in reversed(recs) if r["status"] == 0), None)
-        if (done // chunk) % 5 == 0:
+        if (done // chunk) % max(1, 50000 // chunk) == 0:
             log(f"rolling: step {done}, {time.perf_counter() - t0:.1f} s, "
                 f"advancing contact x = {last['x_a'] if last else float('nan'):.1f}")
         if last and done > relax and max(last["x_a"], last["x_r"]) > x_stop:
@@ -86,6 +98,14 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
     out = dict(nx=nx, ny=ny, R=R, H=H, r0=r0, mu_w=mu_w if stripes is None else None, stripes=stripes, g=g, phi_deg=phi_deg, Tr=Tr,
                steps=done, seconds=round(seconds, 2),
                mlups=round(float(inf["n_fluid"]) * done / seconds / 1e6, 1), records=recs)
+    fs = [f for f in forces if f["step"] > relax]
+    if young is not None and len(fs) >= 2:
+        fa = np.array([f["force_a"] for f in fs])
+        fr = np.array([f["force_r"] for f in fs])
+        out.update(young=list(young), forces=forces, force_a_mean=round(float(fa.mean()), 5),
+                   force_r_mean=round(float(fr.mean()), 5), force_a_range=[round(float(fa.min()), 5), round(float(fa.max()), 5)],
+                   force_r_range=[round(float(fr.min()), 5), round(float(fr.max()), 5)],
+                   force_r_largest_jump=round(float(np.max(np.abs(np.diff(fr)))), 5))
     if len(slide) >= 2:
         ta = np.array([r["theta_a"] for r in slide])
         tr = np.array([r["theta_r"] for r in slide])
@@ -116,12 +136,16 @@ def main(argv=None):
     ap.add_argument("--relax", type=int, default=20000)
     ap.add_argument("--steps", type=int, default=600000)
     ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--chunk", type=int, default=10000, help="steps between host checks (and Young-force samples)")
+    ap.add_argument("--young", type=float, nargs=3, default=None, metavar=("GAMMA", "THETA1", "THETA2"),
+                    help="also the unbalanced Young force (Eq. 17-18) after every chunk of steps")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     rep = run(nx=a.nx, ny=a.ny, R=a.R, H=a.H, r0=a.r0, x0=a.x0, mu_w=a.mu, stripes=a.stripes, g=a.g,
-              phi_deg=a.phi, Tr=a.Tr, relax=a.relax, steps=a.steps, every=a.every, log=log)
-    print(json.dumps({k: v for k, v in rep.items() if k != "records"}), flush=True)
+              phi_deg=a.phi, Tr=a.Tr, relax=a.relax, steps=a.steps, every=a.every, chunk=a.chunk,
+              young=tuple(a.young) if a.young else None, log=log)
+    print(json.dumps({k: v for k, v in rep.items() if k not in ("records", "forces")}), flush=True)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(rep, f, indent=1)
