@@ -27,6 +27,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # scaled by a plain-copy calibration; valid only for the kernel as it stands when they were taken
 # (profiles/k_collide_d3q19_f32_256cube.md).  Keyed by (lattice side, precision, collision).
 COUNTED_TRAFFIC = {(256, "f32", "bgk"): 3.301e9}
+# the same for kb_collide of the batched solver on the seeded table (profiles/kb_collide_batch_d2q9_512cases.md),
+# keyed by (number of cases, precision)
+BATCH_COUNTED_TRAFFIC = {(512, "f32"): 4.271e9}
 
 
 def parse():
@@ -198,7 +201,8 @@ def batch_bench(args):
                    "tuned_ms_per_step": inf["tune_ms_per_step"], "setup_s": round(t_setup, 2)},
         "cases_with_contact_angle": valid,
         "roofline": {"bound": "hbm", "kernel": "kb_collide", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": BATCH_COUNTED_TRAFFIC.get((args.cases, args.precision)),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
     }

@@ -318,7 +318,8 @@ typedef struct {
 } lbm_batch_opts;
 
 typedef struct {
-    int64_t total_nodes, fluid_nodes;
+    int64_t total_nodes, fluid_nodes;  /* lattice nodes of all cases (each row is padded to a multiple of
+                                          64 nodes in device memory), fluid nodes among them */
     int32_t ncases, tile_w, blocks_per_cu, n_items;
     double tune_ms_per_step;  /* time per step of the chosen launch shape (0 if not tuned) */
     int64_t step;

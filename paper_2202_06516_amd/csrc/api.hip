@@ -478,6 +478,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         (!(cfg->rho_g > 0) || !(cfg->rho_l > cfg->rho_g) || !std::isfinite(cfg->sc_G)))
         return bad("the pseudopotential model needs rho_l > rho_g > 0 and a finite sc_G");
     c->d.nx = cfg->n[0];
+    c->d.px = cfg->n[0];
     c->d.ny = cfg->n[1];
     c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
     c->d.N = N;

@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) kb_collide(const Item* __restrict__ items
         const Dims d = dims[it.c];
         int x, y, z;
         item_node(it, tile_w, x, y, z);
-        collide_node<L, R, C, PULL, MRT>(fin, fout, rho, mu, cls, d, bc, cp, t, x, y, z);
+        collide_node<L, R, C, PULL, MRT, true>(fin, fout, rho, mu, cls, d, bc, cp, t, x, y, z);
     }
 }
 
@@ -185,7 +185,8 @@ struct lbm_batch {
     size_t elem = 4;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    long long Ntot = 0, n_fluid = 0;
+    long long Ntot = 0, n_fluid = 0;   // packed nodes (rows padded), fluid nodes
+    long long n_nodes = 0;             // lattice nodes of all cases
     std::vector<Dims> dims_h;
     std::vector<MeasureParams> mp_h;
     Dims* dims = nullptr;
@@ -682,8 +683,17 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
             lbm_batch_destroy(b);
             return LBM_E_ARG;
         }
+        // rows padded to a multiple of 64 nodes, so that every row of every
+        // case starts on a 256-byte boundary (FP32) and the 64-wide tiles of
+        // the work list are aligned; pad nodes are deep solid and never read
+        const int px = (n[0] + 63) / 64 * 64;
+        const long long Np = (long long)px * n[1] * n[2];
+        auto at = [&](long long i) {  // unpadded node index of the case -> padded
+            return (i / n[0]) * px + i % n[0];
+        };
         Dims d{};
         d.nx = n[0];
+        d.px = px;
         d.ny = n[1];
         d.nz = n[2];
         d.off = off;
@@ -699,31 +709,34 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         mp.n_sectors = b->dim == 2 ? 2 : 16;
         mp.dim = b->dim;
         b->mp_h.push_back(mp);
-        cls.insert(cls.end(), g.cls.begin(), g.cls.end());
-        nbm.insert(nbm.end(), g.nbmask.begin(), g.nbmask.end());
-        std::vector<int> bi((size_t)g.N, -1);
-        for (size_t k = 0; k < g.b_node.size(); ++k) bi[g.b_node[k]] = nb_total + (int)k;
-        bidx.insert(bidx.end(), bi.begin(), bi.end());
+        const size_t base_at = cls.size();
+        cls.resize(base_at + (size_t)Np, (uint8_t)3);
+        nbm.resize(base_at + (size_t)Np, 0u);
+        bidx.resize(base_at + (size_t)Np, -1);
+        muh.resize(base_at + (size_t)Np, 0.0);
+        rhoh.resize(base_at + (size_t)Np, 0.0);
+        for (long long i = 0; i < g.N; ++i) {
+            cls[base_at + at(i)] = g.cls[i];
+            nbm[base_at + at(i)] = g.nbmask[i];
+        }
+        for (size_t k = 0; k < g.b_node.size(); ++k) bidx[base_at + at(g.b_node[k])] = nb_total + (int)k;
         bq.insert(bq.end(), g.b_q.begin(), g.b_q.end());
         nb_total += (int)g.b_node.size();
-        std::vector<double> m((size_t)g.N, 0.0);
         for (size_t k = 0; k < g.l1_node.size(); ++k) {
-            m[g.l1_node[k]] = g.l1_mu[k] - b->mu_ref;
-            fnode1.push_back(off + g.l1_node[k]);
+            muh[base_at + at(g.l1_node[k])] = g.l1_mu[k] - b->mu_ref;
+            fnode1.push_back(off + at(g.l1_node[k]));
             fmask1.push_back(g.l1_mask[k]);
             inv1.push_back(g.l1_inv[k]);
             fcase1.push_back(ci);
         }
         for (size_t k = 0; k < g.l2_node.size(); ++k) {
-            m[g.l2_node[k]] = g.l2_mu[k] - b->mu_ref;
-            fnode2.push_back(off + g.l2_node[k]);
+            muh[base_at + at(g.l2_node[k])] = g.l2_mu[k] - b->mu_ref;
+            fnode2.push_back(off + at(g.l2_node[k]));
             fmask2.push_back(g.l2_mask[k]);
             inv2.push_back(g.l2_inv[k]);
             fcase2.push_back(ci);
         }
-        muh.insert(muh.end(), m.begin(), m.end());
         // Eq. 16 around the case's drop
-        std::vector<double> r((size_t)g.N, 0.0);
         const double rg = b->pr.rho_g, rl = b->pr.rho_l;
         for (long long i = 0; i < g.N; ++i) {
             if ((g.cls[i] & 3) != 0) continue;
@@ -731,11 +744,11 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
             const double dx = x - cs.drop.center[0], dy = y - cs.drop.center[1];
             const double dz = b->dim == 3 ? z - cs.drop.center[2] : 0.0;
             const double rr = std::sqrt(dx * dx + dy * dy + dz * dz);
-            r[i] = 0.5 * (rg + rl) + 0.5 * (rg - rl) * std::tanh(2.0 * (rr - cs.drop.radius) / 10.0);
+            rhoh[base_at + at(i)] = 0.5 * (rg + rl) + 0.5 * (rg - rl) * std::tanh(2.0 * (rr - cs.drop.radius) / 10.0);
         }
-        rhoh.insert(rhoh.end(), r.begin(), r.end());
         b->n_fluid += g.n_fluid;
-        off += g.N;
+        b->n_nodes += g.N;
+        off += Np;
     }
     b->Ntot = off;
     if ((unsigned long long)b->Ntot * (unsigned long long)b->Q >= (1ull << 32)) {
@@ -912,24 +925,26 @@ lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t byt
     if (!b || !dst) return b ? bfail(b, LBM_E_ARG, "batch read: null destination") : LBM_E_ARG;
     if (ci < 0 || ci >= b->ncases) return bfail(b, LBM_E_ARG, "batch read: case index out of range");
     const Dims& d = b->dims_h[ci];
-    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    const size_t n = (size_t)d.nx * d.ny * d.nz, rows = (size_t)d.ny * d.nz;
+    const size_t e = b->elem, w = (size_t)d.nx * e, sp = (size_t)d.px * e;  // row bytes, padded row bytes
     const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (field == LBM_FIELD_RHO) {
-        if (bytes != n * b->elem) return bfail(b, LBM_E_ARG, "batch read RHO: bytes must be n * elem");
+        if (bytes != n * e) return bfail(b, LBM_E_ARG, "batch read RHO: bytes must be n * elem");
         bdispatch<BDerive>(b, grid_of(b));
-        BCHK(b, hipMemcpyAsync(dst, (char*)b->rho + (size_t)d.off * b->elem, bytes, kind, b->stream));
+        BCHK(b, hipMemcpy2DAsync(dst, w, (char*)b->rho + (size_t)d.off * e, sp, w, rows, kind, b->stream));
     } else if (field == LBM_FIELD_F) {
-        if (bytes != (size_t)b->Q * n * b->elem) return bfail(b, LBM_E_ARG, "batch read F: bytes must be Q * n * elem");
+        if (bytes != (size_t)b->Q * n * e) return bfail(b, LBM_E_ARG, "batch read F: bytes must be Q * n * elem");
         void* S = nullptr;
         bdispatch<BMaterialize>(b, grid_of(b), &S);
         for (int i = 0; i < b->Q; ++i)
-            BCHK(b, hipMemcpyAsync((char*)dst + (size_t)i * n * b->elem,
-                                   (char*)S + ((size_t)i * b->Ntot + (size_t)d.off) * b->elem, n * b->elem, kind, b->stream));
+            BCHK(b, hipMemcpy2DAsync((char*)dst + (size_t)i * n * e, w,
+                                     (char*)S + ((size_t)i * b->Ntot + (size_t)d.off) * e, sp, w, rows, kind,
+                                     b->stream));
     } else if (field == LBM_FIELD_CLASS) {
         if (bytes != n) return bfail(b, LBM_E_ARG, "batch read CLASS: bytes must be n");
         std::vector<uint8_t> h(n);
         BCHK(b, hipStreamSynchronize(b->stream));
-        BCHK(b, hipMemcpy(h.data(), b->cls + d.off, n, hipMemcpyDeviceToHost));
+        BCHK(b, hipMemcpy2D(h.data(), d.nx, b->cls + d.off, d.px, d.nx, rows, hipMemcpyDeviceToHost));
         for (auto& v : h) v &= 3;
         if (dst_on_device) BCHK(b, hipMemcpyAsync(dst, h.data(), n, hipMemcpyHostToDevice, b->stream));
         else std::memcpy(dst, h.data(), n);
@@ -945,7 +960,7 @@ lbm_status lbm_batch_write(lbm_batch* b, int ci, int field, const void* src, siz
     if (ci < 0 || ci >= b->ncases) return bfail(b, LBM_E_ARG, "batch write: case index out of range");
     if (field != LBM_FIELD_RHO) return bfail(b, LBM_E_ARG, "batch write: field must be RHO");
     const Dims& d = b->dims_h[ci];
-    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    const size_t n = (size_t)d.nx * d.ny * d.nz, rows = (size_t)d.ny * d.nz;
     if (bytes != n * b->elem) return bfail(b, LBM_E_ARG, "batch write RHO: bytes must be n * elem");
     // bring every case to form S (materialize), then replace this case's populations
     if (b->fstar) {
@@ -958,10 +973,11 @@ lbm_status lbm_batch_write(lbm_batch* b, int ci, int field, const void* src, siz
     BCHK(b, hipStreamSynchronize(b->stream));
     // stream-ordered: a device-to-device copy may otherwise still be in flight
     // when k_init_feq runs (or when the caller reuses src)
-    BCHK(b, hipMemcpyAsync((char*)b->rho + (size_t)d.off * b->elem, src, bytes,
-                           src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream));
-    // f_eq(rho, 0) on this case's range of the packed arrays
-    const long long beg = d.off, end = d.off + (long long)n;
+    BCHK(b, hipMemcpy2DAsync((char*)b->rho + (size_t)d.off * b->elem, (size_t)d.px * b->elem, src,
+                             (size_t)d.nx * b->elem, (size_t)d.nx * b->elem, rows,
+                             src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream));
+    // f_eq(rho, 0) on this case's range of the packed arrays (pad nodes are solid: zero)
+    const long long beg = d.off, end = d.off + (long long)d.px * d.ny * d.nz;
     if (b->dim == 2) {
         if (b->elem == 8) k_init_feq<D2Q9, double><<<1024, 256, 0, b->stream>>>((const double*)b->rho, (double*)b->f[b->cur], b->cls, b->Ntot, beg, end);
         else k_init_feq<D2Q9, float><<<1024, 256, 0, b->stream>>>((const float*)b->rho, (float*)b->f[b->cur], b->cls, b->Ntot, beg, end);
@@ -977,7 +993,7 @@ lbm_status lbm_batch_write(lbm_batch* b, int ci, int field, const void* src, siz
 lbm_status lbm_batch_get_info(lbm_batch* b, lbm_batch_info* info) {
     if (!b || !info) return LBM_E_ARG;
     std::memset(info, 0, sizeof *info);
-    info->total_nodes = b->Ntot;
+    info->total_nodes = b->n_nodes;
     info->fluid_nodes = b->n_fluid;
     info->ncases = b->ncases;
     info->tile_w = b->tile_w;

@@ -40,6 +40,7 @@ enum : uint8_t { CLS_FLUID = 0, CLS_L1 = 1, CLS_L2 = 2, CLS_DEEP = 3, CLS_MASK =
 
 struct Dims {
     int nx, ny, nz;
+    int px;              // row pitch in nodes (>= nx): consecutive rows start px nodes apart
     long long N;         // population stride (all packed nodes)
     long long off;       // first node of this lattice in the packed arrays
     int tx, ty;          // tiles per row / per plane
@@ -49,7 +50,7 @@ struct Dims {
 };
 
 __device__ __forceinline__ long long nid(const Dims& d, int x, int y, int z) {
-    return d.off + ((long long)z * d.ny + y) * d.nx + x;
+    return d.off + ((long long)z * d.ny + y) * d.px + x;
 }
 
 // Node of this thread in tile t (x fastest, then y, then z).
@@ -218,8 +219,8 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
     }
     // index offsets of x - 1, x, x + 1 along each axis (periodic wrap)
     const int ox[3] = {x >= 1 ? -1 : d.nx - 1, 0, x + 1 < d.nx ? 1 : 1 - d.nx};
-    const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.nx, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.nx};
-    const int sz = d.nx * d.ny;
+    const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.px, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.px};
+    const int sz = d.px * d.ny;
     const int oz[3] = {L::D == 3 ? (z >= 1 ? -1 : d.nz - 1) * sz : 0, 0, L::D == 3 ? (z + 1 < d.nz ? 1 : 1 - d.nz) * sz : 0};
     // source x - e_i
 #define LBM_SRC(i) (idx + (ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]))
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(256) k_materialize(const R* __restrict__ f, R*
 template <class L, typename R, typename C>
 __device__ __forceinline__ void fill_entry(long long idx, uint32_t m, R inv_den, R* __restrict__ rho, const Dims& d) {
     const long long loc = idx - d.off;
-    const int x = (int)(loc % d.nx), y = (int)((loc / d.nx) % d.ny), z = (int)(loc / ((long long)d.nx * d.ny));
+    const int x = (int)(loc % d.px), y = (int)((loc / d.px) % d.ny), z = (int)(loc / ((long long)d.px * d.ny));
     C num = C(0);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
@@ -452,12 +453,12 @@ __device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict
     const uint8_t c = cls[idx];
     const R* p = rho + idx;
     const R rc = p[0];
-    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
+    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
     const C c0 = (C)rc;
     C lap = d2c<C>(p[ox.m2], p[ox.m1], c0, p[ox.p1], p[ox.p2]);
     lap += d2c<C>(p[oy.m2], p[oy.m1], c0, p[oy.p1], p[oy.p2]);
     if (L::D == 3) {
-        const Nbr oz = nbr_offsets(z, d.nz, d.nx * d.ny);
+        const Nbr oz = nbr_offsets(z, d.nz, d.px * d.ny);
         lap += d2c<C>(p[oz.m2], p[oz.m1], c0, p[oz.p1], p[oz.p2]);
     }
     const C m = (psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap;
@@ -583,8 +584,8 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     const long long idx = nid(d, x, y, z);
     const uint8_t c = cls[idx];
     if constexpr (SC) {
-        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
-        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.nx * d.ny) : Nbr{0, 0, 0, 0};
+        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
+        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
         double Fx, Fy, Fz;
         sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, Fx, Fy, Fz);
         if (t >= cp.g_start) {
@@ -609,7 +610,7 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     typedef double D;
     const R* pr = rho + idx;
     const R* pm = mu + idx;
-    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
+    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
     const D r0 = (D)pr[0];
     const D gmx = d1c<D>(pm[ox.m2], pm[ox.m1], pm[ox.p1], pm[ox.p2]);
     const D grx = d1c<D>(pr[ox.m2], pr[ox.m1], pr[ox.p1], pr[ox.p2]);
@@ -617,7 +618,7 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     const D gry = d1c<D>(pr[oy.m2], pr[oy.m1], pr[oy.p1], pr[oy.p2]);
     D gmz = D(0), grz = D(0);
     if (L::D == 3) {
-        const Nbr oz = nbr_offsets(z, d.nz, d.nx * d.ny);
+        const Nbr oz = nbr_offsets(z, d.nz, d.px * d.ny);
         gmz = d1c<D>(pm[oz.m2], pm[oz.m1], pm[oz.p1], pm[oz.p2]);
         grz = d1c<D>(pr[oz.m2], pr[oz.m1], pr[oz.p1], pr[oz.p2]);
     }
@@ -643,8 +644,9 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
 // lattice is swept in whole aligned rows, so that the stream does not evict
 // the density and chemical-potential planes the stencils re-read (the
 // populations are next read one step later, after the whole lattice has
-// passed through the caches); plain for the batched solver, whose ragged rows
-// would turn into partial-line writes.
+// passed through the caches).  The batched solver pads every row to 64 nodes
+// for this: with ragged, unaligned rows NT stores turn into partial-line
+// writes and cost more than they save.
 template <bool NT, typename R>
 __device__ __forceinline__ void put(R* p, R v) {
     if constexpr (NT) __builtin_nontemporal_store(v, p);
@@ -758,8 +760,8 @@ __device__ void finalize_slots(const R* __restrict__ rho, const Dims& d, const M
 #pragma unroll
                 for (int q = 0; q < L::Q; ++q)
                     if (q == i) { ex = L::E[q][0]; ey = L::E[q][1]; ez = L::E[q][2]; }
-                const int x = (int)(loc % d.nx), y = (int)((loc / d.nx) % d.ny);
-                const int z = (int)(loc / ((long long)d.nx * d.ny));
+                const int x = (int)(loc % d.px), y = (int)((loc / d.px) % d.ny);
+                const int z = (int)(loc / ((long long)d.px * d.ny));
                 const int X = wrapc(x + ex, d.nx), Y = wrapc(y + ey, d.ny);
                 const int Z = L::D == 3 ? wrapc(z + ez, d.nz) : 0;
                 crossing_point((double)rho[d.off + loc], (double)rho[nid(d, X, Y, Z)], mp.rho_m, x, y, z, ex, ey, ez,
@@ -971,8 +973,8 @@ __global__ void __launch_bounds__(256) k_velocity(const R* __restrict__ fin, con
     const D r0 = (D)rho[idx];
     D Fa[3] = {D(0), D(0), D(0)};
     if constexpr (SC) {
-        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.nx);
-        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.nx * d.ny) : Nbr{0, 0, 0, 0};
+        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
+        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
         sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, Fa[0], Fa[1], Fa[2]);
         if (t >= cp.g_start)
             for (int a = 0; a < 3; ++a) Fa[a] += r0 * (D)cp.g[a];
