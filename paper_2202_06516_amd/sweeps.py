@@ -12,6 +12,10 @@ statistics the paper reports:
   (Fig. 4a) and its standard deviation over r0;
 - ``curvature``: theta for bump radii R = 150..400 (Fig. 4b) and its standard
   deviation over R;
+- ``gravity``: sessile drops of growing radius under gravity (Sec. IV C,
+  Fig. 5-6), or with the gravity reversed pendent ones (Fig. 7-8): the
+  measured angle against the spherical-cap angle as the drops deform, and
+  the radii at which a pendent drop detaches;
 - ``sc-wettability``: the same measurement on the pseudopotential model
   (Sec. V), theta against the wall density on single lattices.
 
@@ -37,10 +41,11 @@ from . import lbm as G
 from . import workloads as WL
 
 
-def make_batch(cases, Tr, precision=G.LBM_F32, stream=None, k=0.28, kappa=0.01):
-    # the floor and ceiling are two solid layers (walled along y), x periodic
+def make_batch(cases, Tr, precision=G.LBM_F32, stream=None, k=0.28, kappa=0.01, g=0.0, g_start=0):
+    # the floor and ceiling are two solid layers (walled along y), x periodic;
+    # g > 0 pulls toward the floor (sessile), g < 0 away from it (pendent)
     return G.Batch(cases, precision=precision, axis_bc=(0, 1, 0), tile_w=256, blocks_per_cu=8, stream=stream,
-                   tau=1.0, Tr=Tr, k=k, kappa=kappa, collision=G.LBM_MRT)
+                   tau=1.0, Tr=Tr, k=k, kappa=kappa, collision=G.LBM_MRT, g=(0.0, -g, 0.0), g_start_step=g_start)
 
 
 def settle(b, every=1000, tol=0.02, min_steps=10000, max_steps=200000, log=print):
@@ -106,11 +111,12 @@ def linear_fit_error(x, y):
 
 
 def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, every=1000, tol=0.02,
-        min_steps=10000, max_steps=200000, k=0.28, kappa=0.01, stream=None, log=print):
+        min_steps=10000, max_steps=200000, k=0.28, kappa=0.01, g=0.0, g_start=0, stream=None, log=print):
     cases, labels = WL.sweep_cases(kind, scale=scale, mu=mu, values=values)
     nx, ny = cases[0]["n"]
     H = 100.0 * scale
-    b = make_batch(cases, Tr, precision, stream, k=k, kappa=kappa)
+    b = make_batch(cases, Tr, precision, stream, k=k, kappa=kappa, g=g, g_start=g_start)
+    min_steps = max(min_steps, g_start + 2 * every)
     inf = b.info()
     rho_m = 0.5 * (inf["rho_g"] + inf["rho_l"])
     log(f"sweep {kind}: {len(cases)} cases of {nx}x{ny}, Tr = {Tr}")
@@ -130,7 +136,7 @@ def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, ever
                         sectors=[float(final[i].sector_deg[k]) for k in range(2)],
                         contact=[[round(float(final[i].contact[k][d]), 2) for d in range(2)] for k in range(2)]))
     b.close()
-    out = dict(kind=kind, Tr=Tr, k=k, kappa=kappa, nx=nx, ny=ny, H=H, steps=steps, seconds=round(seconds, 2),
+    out = dict(kind=kind, Tr=Tr, k=k, kappa=kappa, g=g, g_start=g_start, nx=nx, ny=ny, H=H, steps=steps, seconds=round(seconds, 2),
                mlups=round(float(inf["fluid_nodes"]) * steps / seconds / 1e6, 1), cases=res)
     ok = [r for r in res if math.isfinite(r["theta"])]
     if kind == "wettability" and len(ok) >= 3:
@@ -139,6 +145,22 @@ def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, ever
         okc = [r for r in ok if math.isfinite(r["cap"])]
         if okc:
             out["max_abs_theta_minus_cap"] = round(max(abs(r["theta"] - r["cap"]) for r in okc), 2)
+    if kind == "gravity":
+        # Sec. IV C: the drops flatten as r0 grows, so the spherical-cap angle
+        # drifts while the microscopic angle should not
+        per = {}
+        for r in res:
+            per.setdefault(r["mu_w"], []).append(r)
+        out["per_mu"] = {}
+        for m, rs in sorted(per.items()):
+            ok_ = [r for r in rs if math.isfinite(r["theta"])]
+            th = np.array([r["theta"] for r in ok_])
+            cp = np.array([r["cap"] for r in ok_])
+            out["per_mu"][str(m)] = dict(
+                r0=[r["value"] for r in ok_], theta=[round(float(v), 2) for v in th], cap=[round(float(v), 2) for v in cp],
+                theta_std=round(float(th.std()), 3) if len(th) else None,
+                cap_change=round(float(cp[-1] - cp[0]), 2) if len(cp) > 1 else None,
+                detached=[r["value"] for r in rs if not math.isfinite(r["theta"])])
     if kind in ("size", "curvature"):
         per = {}
         for r in ok:
@@ -188,13 +210,15 @@ def sc_wettability(rho_w=(0.3, 0.5, 0.7, 0.9, 1.1, 1.3, 1.5), n=256, R=48.0, r0=
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="wettability / drop-size / curvature sweeps on the batched solver")
-    ap.add_argument("kind", choices=("wettability", "size", "curvature", "sc-wettability"))
+    ap.add_argument("kind", choices=("wettability", "size", "curvature", "gravity", "sc-wettability"))
     ap.add_argument("--Tr", type=float, default=0.6)
     ap.add_argument("--f64", action="store_true", help="FP64 storage and arithmetic (default FP32 storage)")
     ap.add_argument("--scale", type=float, default=1.0, help="every length times this (1: the 700 x 400 lattice)")
     ap.add_argument("--k", type=float, default=0.28, help="EOS scaling k (a smaller k widens the interface)")
     ap.add_argument("--kappa", type=float, default=0.01)
     ap.add_argument("--mu", type=float, nargs="*", default=None, help="wall chemical potentials (default per sweep)")
+    ap.add_argument("--g", type=float, default=0.0, help="gravity toward the floor (negative: pendent drops)")
+    ap.add_argument("--g-start", type=int, default=20000, help="first step with gravity")
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--min-steps", type=int, default=10000)
@@ -209,7 +233,8 @@ def main(argv=None):
             print(json.dumps(r), flush=True)
         return 0
     rep = run(a.kind, Tr=a.Tr, precision=G.LBM_F64 if a.f64 else G.LBM_F32, scale=a.scale, every=a.every,
-              tol=a.tol, min_steps=a.min_steps, max_steps=a.max_steps, k=a.k, kappa=a.kappa,
+              tol=a.tol, min_steps=a.min_steps, max_steps=a.max_steps, k=a.k, kappa=a.kappa, g=a.g,
+              g_start=a.g_start if a.g else 0,
               mu=tuple(a.mu) if a.mu else None, log=log)
     print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
     for r in rep["cases"]:

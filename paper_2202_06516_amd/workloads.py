@@ -197,10 +197,12 @@ SWEEP_MU = tuple(float(m) for m in np.round(np.linspace(-0.02, 0.16, 10), 4))
 SWEEP_MU5 = (-0.01, 0.02, 0.04, 0.07, 0.1)
 SWEEP_R0 = (30, 40, 50, 60, 70, 80, 90, 100)
 SWEEP_RS = (150, 200, 250, 300, 350, 400)
+SWEEP_MU3 = (-0.01, 0.04, 0.1)            # the paper's 70 / 100 / 140 degree surfaces (Sec. IV C)
+SWEEP_R0_GRAVITY = (20, 35, 50, 65, 80, 95)
 
 
 def sweep_cases(kind, scale=1.0, mu=None, values=None):
-    """Case table of one sweep ("wettability", "size" or "curvature") with a
+    """Case table of one sweep ("wettability", "size", "curvature" or "gravity") with a
     (value, mu_w) label per case; every length (lattice, H, R, r0) times scale."""
     s = float(scale)
     nx, ny, H = int(round(700 * s)), int(round(400 * s)), 100.0 * s
@@ -211,6 +213,13 @@ def sweep_cases(kind, scale=1.0, mu=None, values=None):
     elif kind == "size":
         mu = SWEEP_MU5 if mu is None else mu
         values = SWEEP_R0 if values is None else values
+        pairs = [(r, m) for m in mu for r in values]
+        cases = [bump_case(nx, ny, 400.0 * s, H, r * s, m) for r, m in pairs]
+    elif kind == "gravity":
+        # sessile (or, with gravity reversed, pendent) drops of growing size on
+        # the wide bump: the Bond number grows as r0^2 (Sec. IV C)
+        mu = SWEEP_MU3 if mu is None else mu
+        values = SWEEP_R0_GRAVITY if values is None else values
         pairs = [(r, m) for m in mu for r in values]
         cases = [bump_case(nx, ny, 400.0 * s, H, r * s, m) for r, m in pairs]
     elif kind == "curvature":

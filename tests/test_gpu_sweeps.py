@@ -47,3 +47,16 @@ def test_small_wettability_sweep():
         if r["mu_w"] >= 0.04:
             assert abs(r["theta"] - r["cap"]) < 6.0, r
     assert rep["E"] < 0.1
+
+
+def test_gravity_deforms_the_cap_not_the_measured_angle():
+    # Sec. IV C at 0.4 scale: sessile drops of r0 = 12, 24, 38 on a wide bump
+    # (R = 160) with gravity; as the Bond number grows the spherical-cap angle
+    # of the flattened drop falls, while the measured (microscopic) angle stays
+    rep = S.run("gravity", scale=0.4, mu=(-0.01,), values=(30, 60, 95), g=2e-6, g_start=10000, max_steps=60000,
+                log=lambda s: None)
+    print(rep)
+    pm = rep["per_mu"]["-0.01"]
+    assert rep["invalid"] == 0 and len(pm["theta"]) == 3
+    assert pm["cap_change"] < -8.0, pm
+    assert max(pm["theta"]) - min(pm["theta"]) < 0.5 * abs(pm["cap_change"]), pm
