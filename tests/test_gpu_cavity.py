@@ -87,9 +87,8 @@ def test_cavity_d2q9_f32_small():
 
 @pytest.mark.parametrize("precision,tol,ang_tol", [(G.LBM_F64, 1e-12, 1e-6), (G.LBM_F32, 1e-6, 0.1)])
 def test_cavity_d3q19_small(precision, tol, ang_tol):
-    # spherical cavity r = 17.5 in a 40^3 periodic cube, 16 sectors; 25 steps
-    # (small three-dimensional drops at Tr = 0.8 do not survive a few hundred
-    # steps with this forcing, with or without a substrate)
+    # spherical cavity r = 17.5 in a 40^3 periodic cube, 16 sectors, BGK (the
+    # D3Q19 MRT rates make drops this small blow up at Tr = 0.8); 25 steps
     wl = W.cavity_3d(mu_w=0.04, n=40)
     gp = gpu_lattice(wl, precision, "bgk")
     o = oracle_lattice(wl, "bgk")
