@@ -340,6 +340,16 @@ lbm_status lbm_batch_sync(lbm_batch* b);
 lbm_status lbm_batch_angles(lbm_batch* b, lbm_angle* out, int n);
 /* Measure every case now and return cases 0..n-1 (synchronises). */
 lbm_status lbm_batch_measure(lbm_batch* b, lbm_angle* out, int n);
+/* Unbalanced Young force of every case (Sec. IV E, Eq. 17-18), as
+ * lbm_young_force computes it for one lattice: a measurement of every case now
+ * (written to angles[0..n), sectors as lbm_batch_measure), the footprint counts
+ * of each case on the density that measurement derived, then Eq. 18 and Eq. 17
+ * in FP64 into out[0..n).  A case without a contact line gets out[c].status =
+ * LBM_E_NO_CONTACT_LINE and NaN values; the call itself still succeeds.  n must
+ * equal the number of cases.  Synchronises.  Errors: LBM_E_ARG (null pointer,
+ * n, or options as for lbm_young_force), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_batch_young_force(lbm_batch* b, const lbm_young_opts* opts, lbm_angle* angles, lbm_young* out, int n);
+
 /* Fields of one case: RHO (n*elem bytes), F (Q*n*elem, [Q][n]), CLASS (n bytes).  Synchronises. */
 lbm_status lbm_batch_read(lbm_batch* b, int case_index, int field, void* dst, size_t bytes, int dst_on_device);
 /* Replace one case's state by f_eq(rho, 0) (LBM_FIELD_RHO only; a warm start). */

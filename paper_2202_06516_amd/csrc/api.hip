@@ -11,6 +11,7 @@
 #include "lbm.h"
 #include "host.hpp"
 #include "kernels.hpp"
+#include "young.hpp"
 
 using namespace lbm;
 
@@ -831,58 +832,22 @@ lbm_status lbm_measure_angle(lbm_ctx* c, const lbm_measure_opts* o, lbm_angle* o
 
 lbm_status lbm_young_force(lbm_ctx* c, const lbm_young_opts* yo, lbm_angle* angle, lbm_young* out) {
     if (!c || !yo || !angle || !out) return LBM_E_ARG;
-    double lo = yo->band_lo, hi = yo->band_hi;
-    if (lo == 0.0 && hi == 0.0) {
-        lo = 0.1;
-        hi = 0.9;
-    }
-    if (!std::isfinite(yo->gamma) || !(yo->roughness > 0.0) || !(lo > 0.0 && lo < hi && hi < 1.0))
-        return fail(c, LBM_E_ARG, "young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
-    std::memset(out, 0, sizeof *out);
-    for (int k = 0; k < LBM_MAX_SECTORS; ++k) out->phi_d[k] = out->theta_eq_deg[k] = out->force[k] = NAN;
+    if (!young_opts_ok(*yo)) return fail(c, LBM_E_ARG, "young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
+    double lo, hi;
+    young_band(*yo, lo, hi);
+    std::memset(angle, 0, sizeof *angle);
     const lbm_status ms = lbm_measure_angle(c, &c->mopts, angle);
-    out->step = angle->step;
-    out->n_sectors = angle->n_sectors;
-    out->status = ms;
+    young_clear(*angle, ms, out);
     if (ms != LBM_OK) return ms;
     // footprint counts on the density the measurement derived
-    const Solid& so = c->solids[c->mopts.solid_index];
-    YoungParams yp{};
-    for (int k = 0; k < 3; ++k) {
-        yp.c[k] = k < c->dim ? so.c[k] : 0.0;
-        yp.pole[k] = so.pole[k];
-        yp.axis[k] = angle->axis[k];
-    }
-    yp.R = so.r;
-    yp.concave = so.concave;
-    yp.width = so.width;
-    yp.wet_mode = so.wet_mode;
-    yp.n_sectors = angle->n_sectors;
-    yp.dim = c->dim;
-    const double rg = c->pr.rho_g, rl = c->pr.rho_l;
-    yp.lo = rg + lo * (rl - rg);
-    yp.hi = rg + hi * (rl - rg);
+    YoungParams yp = young_params(c->solids[c->mopts.solid_index], *angle, c->dim, c->pr.rho_g, c->pr.rho_l, lo, hi);
     HIPCHK(c, hipMemsetAsync(c->young_counts, 0, 2 * LBM_MAX_SECTORS * sizeof(unsigned), c->stream));
     dispatch<OpYoung>(c, &yp);
     HIPCHK(c, hipGetLastError());
     unsigned h[2 * LBM_MAX_SECTORS];
     HIPCHK(c, hipMemcpyAsync(h, c->young_counts, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    // Eq. 18 (phi_d the footprint share of the mu_w surface) and Eq. 17, in FP64
-    const double c1 = std::cos(yo->theta1_deg * M_PI / 180.0), c2 = std::cos(yo->theta2_deg * M_PI / 180.0);
-    for (int k = 0; k < angle->n_sectors; ++k) {
-        out->count[k][0] = (int32_t)h[2 * k];
-        out->count[k][1] = (int32_t)h[2 * k + 1];
-        const unsigned tot = h[2 * k] + h[2 * k + 1];
-        if (!tot) continue;
-        const double phi = (double)h[2 * k] / (double)tot;
-        double ce = yo->roughness * phi * c1 + (1.0 - phi) * c2;
-        ce = ce > 1.0 ? 1.0 : (ce < -1.0 ? -1.0 : ce);
-        out->phi_d[k] = phi;
-        out->theta_eq_deg[k] = std::acos(ce) * 180.0 / M_PI;
-        if (!std::isnan(angle->sector_deg[k]))
-            out->force[k] = yo->gamma * (std::cos(angle->sector_deg[k] * M_PI / 180.0) - ce);
-    }
+    young_from_counts(*yo, *angle, h, out);
     return LBM_OK;
 }
 

@@ -23,6 +23,7 @@
 #include "host.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
+#include "young.hpp"
 
 using namespace lbm;
 
@@ -129,6 +130,26 @@ __global__ void __launch_bounds__(256) kb_collide(const Item* __restrict__ items
     }
 }
 
+// footprint counts of the unbalanced Young force, every case at once; a case
+// whose measurement found no contact line has n_sectors = 0 and is skipped
+template <class L, typename R>
+__global__ void __launch_bounds__(256) kb_young_count(const Item* __restrict__ items, int nitems,
+                                                      const Dims* __restrict__ dims, int tile_w,
+                                                      const R* __restrict__ rho, const uint8_t* __restrict__ cls,
+                                                      const YoungParams* __restrict__ yps,
+                                                      unsigned* __restrict__ counts) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const YoungParams yp = yps[it.c];
+        if (yp.n_sectors == 0) continue;
+        const Dims d = dims[it.c];
+        const Frame F = frame_from_axis(yp.axis, yp.dim);
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        young_node<L, R>(rho, cls, d, yp, F, x, y, z, counts + (size_t)it.c * 2 * LBM_MAX_SECTORS);
+    }
+}
+
 // one workgroup of 64 per case
 template <class L, typename R>
 __global__ void __launch_bounds__(64) kb_finalize(const R* __restrict__ rho, const DevCtl* __restrict__ ctl,
@@ -189,6 +210,9 @@ struct lbm_batch {
     long long n_nodes = 0;             // lattice nodes of all cases
     std::vector<Dims> dims_h;
     std::vector<MeasureParams> mp_h;
+    std::vector<Solid> solids_h;       // the substrate of every case
+    YoungParams* yparams = nullptr;    // Young-force counting parameters per case (allocated on first use)
+    unsigned* ycounts = nullptr;       // footprint counts [case][sector][surface]
     Dims* dims = nullptr;
     MeasureParams* mp = nullptr;
     MeasureSlots* slots = nullptr;
@@ -435,6 +459,14 @@ struct BMeasure {
     }
 };
 
+template <class L, typename R, typename C>
+struct BYoung {
+    static void go(lbm_batch* b, int grid) {
+        kb_young_count<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho,
+                                                         b->cls, b->yparams, b->ycounts);
+    }
+};
+
 int grid_of(const lbm_batch* b) { return b->bpc * b->cus; }
 
 void drop_graph(lbm_batch* b) {
@@ -585,7 +617,8 @@ lbm_status lbm_batch_destroy(lbm_batch* b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     void* ps[] = {b->dims, b->mp,   b->slots, b->last, b->ctl,  b->f[0], b->f[1], b->rho,  b->mu,   b->inv,
-                  b->bq,   b->cls,  b->nbmask, b->fmask, b->bidx, b->fcase, b->fnode, b->items};
+                  b->bq,   b->cls,  b->nbmask, b->fmask, b->bidx, b->fcase, b->fnode, b->items,
+                  b->yparams, b->ycounts};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -698,6 +731,7 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         d.nz = n[2];
         d.off = off;
         b->dims_h.push_back(d);
+        b->solids_h.push_back(s);
         MeasureParams mp{};
         for (int k = 0; k < 3; ++k) {
             mp.c[k] = s.c[k];
@@ -919,6 +953,41 @@ lbm_status lbm_batch_measure(lbm_batch* b, lbm_angle* out, int n) {
     k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 0);
     BCHK(b, hipGetLastError());
     return lbm_batch_angles(b, out, n);
+}
+
+lbm_status lbm_batch_young_force(lbm_batch* b, const lbm_young_opts* yo, lbm_angle* angles, lbm_young* out, int n) {
+    if (!b) return LBM_E_ARG;
+    if (!yo || !angles || !out || n != b->ncases)
+        return bfail(b, LBM_E_ARG, "batch young: null pointer, or n is not the number of cases");
+    if (!young_opts_ok(*yo))
+        return bfail(b, LBM_E_ARG, "batch young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
+    double lo, hi;
+    young_band(*yo, lo, hi);
+    lbm_status st = lbm_batch_measure(b, angles, n);
+    if (st != LBM_OK) return st;
+    const size_t cbytes = (size_t)n * 2 * LBM_MAX_SECTORS * sizeof(unsigned);
+    if (!b->yparams) {
+        if (hipMalloc((void**)&b->yparams, (size_t)n * sizeof(YoungParams)) != hipSuccess ||
+            hipMalloc((void**)&b->ycounts, cbytes) != hipSuccess)
+            return bfail(b, LBM_E_NOMEM, "batch young: device allocation failed");
+    }
+    // counting parameters of every case with a contact line (the others are skipped)
+    std::vector<YoungParams> yp((size_t)n);
+    for (int c = 0; c < n; ++c)
+        if (angles[c].status == LBM_OK)
+            yp[c] = young_params(b->solids_h[c], angles[c], b->dim, b->pr.rho_g, b->pr.rho_l, lo, hi);
+    BCHK(b, hipMemcpyAsync(b->yparams, yp.data(), yp.size() * sizeof(YoungParams), hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipMemsetAsync(b->ycounts, 0, cbytes, b->stream));
+    bdispatch<BYoung>(b, grid_of(b));
+    BCHK(b, hipGetLastError());
+    std::vector<unsigned> h((size_t)n * 2 * LBM_MAX_SECTORS);
+    BCHK(b, hipMemcpyAsync(h.data(), b->ycounts, cbytes, hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    for (int c = 0; c < n; ++c) {
+        young_clear(angles[c], (lbm_status)angles[c].status, &out[c]);
+        if (angles[c].status == LBM_OK) young_from_counts(*yo, angles[c], &h[(size_t)c * 2 * LBM_MAX_SECTORS], &out[c]);
+    }
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t bytes, int dst_on_device) {

@@ -863,6 +863,38 @@ struct YoungParams {
     double axis[3];          // drop axis of the measurement
 };
 
+// one node's contribution to the footprint counts: a fluid node in the
+// density band with a lattice neighbour inside the substrate, counted in its
+// sector and on the kind of surface at its own polar angle
+template <class L, typename R>
+__device__ __forceinline__ void young_node(const R* __restrict__ rho, const uint8_t* __restrict__ cls, const Dims& d,
+                                           const YoungParams& yp, const Frame& F, int x, int y, int z,
+                                           unsigned* __restrict__ counts) {
+    if (x >= d.nx || y >= d.ny) return;
+    const long long idx = nid(d, x, y, z);
+    if ((cls[idx] & CLS_MASK) != CLS_FLUID) return;
+    const double r0 = (double)rho[idx];
+    if (!(r0 >= yp.lo && r0 <= yp.hi)) return;
+    bool touches = false;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const double X = wrapc(x + L::E[i][0], d.nx) - yp.c[0], Y = wrapc(y + L::E[i][1], d.ny) - yp.c[1];
+        const double Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) - yp.c[2] : 0.0;
+        const double d2 = X * X + Y * Y + Z * Z;
+        touches = touches || (yp.concave ? d2 >= yp.R * yp.R : d2 <= yp.R * yp.R);
+    }
+    if (!touches) return;
+    const double r[3] = {x - yp.c[0], y - yp.c[1], L::D == 3 ? z - yp.c[2] : 0.0};
+    int kind = 0;
+    if (yp.wet_mode) {
+        const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        double cp = rn > 0.0 ? (r[0] * yp.pole[0] + r[1] * yp.pole[1] + r[2] * yp.pole[2]) / rn : 1.0;
+        cp = cp > 1.0 ? 1.0 : (cp < -1.0 ? -1.0 : cp);
+        kind = (int)((long long)floor(yp.R * acos(cp) / yp.width) % 2);
+    }
+    atomicAdd(&counts[sector_of(r, F, yp.dim, yp.n_sectors) * 2 + kind], 1u);
+}
+
 template <class L, typename R>
 __global__ void __launch_bounds__(256) k_young_count(const R* __restrict__ rho, const uint8_t* __restrict__ cls,
                                                      Dims d, YoungParams yp, unsigned* __restrict__ counts) {
@@ -871,29 +903,7 @@ __global__ void __launch_bounds__(256) k_young_count(const R* __restrict__ rho, 
     for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int x, y, z;
         tile_coords(d, t, x, y, z);
-        if (x >= d.nx || y >= d.ny) continue;
-        const long long idx = nid(d, x, y, z);
-        if ((cls[idx] & CLS_MASK) != CLS_FLUID) continue;
-        const double r0 = (double)rho[idx];
-        if (!(r0 >= yp.lo && r0 <= yp.hi)) continue;
-        bool touches = false;
-#pragma unroll
-        for (int i = 1; i < L::Q; ++i) {
-            const double X = wrapc(x + L::E[i][0], d.nx) - yp.c[0], Y = wrapc(y + L::E[i][1], d.ny) - yp.c[1];
-            const double Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) - yp.c[2] : 0.0;
-            const double d2 = X * X + Y * Y + Z * Z;
-            touches = touches || (yp.concave ? d2 >= yp.R * yp.R : d2 <= yp.R * yp.R);
-        }
-        if (!touches) continue;
-        const double r[3] = {x - yp.c[0], y - yp.c[1], L::D == 3 ? z - yp.c[2] : 0.0};
-        int kind = 0;
-        if (yp.wet_mode) {
-            const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-            double cp = rn > 0.0 ? (r[0] * yp.pole[0] + r[1] * yp.pole[1] + r[2] * yp.pole[2]) / rn : 1.0;
-            cp = cp > 1.0 ? 1.0 : (cp < -1.0 ? -1.0 : cp);
-            kind = (int)((long long)floor(yp.R * acos(cp) / yp.width) % 2);
-        }
-        atomicAdd(&counts[sector_of(r, F, yp.dim, yp.n_sectors) * 2 + kind], 1u);
+        young_node<L, R>(rho, cls, d, yp, F, x, y, z, counts);
     }
 }
 

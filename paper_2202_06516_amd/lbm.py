@@ -128,8 +128,8 @@ EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
            "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_last_error", "lbm_batch_create",
            "lbm_batch_destroy",
-           "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read",
-           "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step", "lbm_batch_last_error",
+           "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
+           "lbm_batch_read", "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step", "lbm_batch_last_error",
            "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
            "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward",
            "lbm_unet_train_step", "lbm_unet_set_lr", "lbm_unet_save", "lbm_unet_load", "lbm_unet_encode",
@@ -176,6 +176,7 @@ def lib():
     L.lbm_batch_sync.argtypes = [vp]
     L.lbm_batch_angles.argtypes = [vp, P(lbm_angle), i]
     L.lbm_batch_measure.argtypes = [vp, P(lbm_angle), i]
+    L.lbm_batch_young_force.argtypes = [vp, P(lbm_young_opts), P(lbm_angle), P(lbm_young), i]
     L.lbm_batch_read.argtypes = [vp, i, i, vp, C.c_size_t, i]
     L.lbm_batch_write.argtypes = [vp, i, i, vp, C.c_size_t, i]
     L.lbm_batch_get_info.argtypes = [vp, P(lbm_batch_info)]
@@ -212,8 +213,8 @@ def lib():
                  "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
                  "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_batch_create", "lbm_batch_destroy",
                  "lbm_batch_step",
-                 "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_read", "lbm_batch_write",
-                 "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step"):
+                 "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
+                 "lbm_batch_read", "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -476,6 +477,15 @@ class Batch:
         arr = (lbm_angle * self.ncases)()
         self._check(lib().lbm_batch_measure(self._h, arr, self.ncases))
         return list(arr)
+
+    def young_force(self, gamma, theta1_deg, theta2_deg=90.0, roughness=1.0, band=(0.1, 0.9)):
+        """Measure every case now and return (angles, youngs): Eq. 17 and Eq. 18 per case and sector; a case
+        without a contact line has status LBM_E_NO_CONTACT_LINE and NaN values."""
+        o = lbm_young_opts(float(gamma), float(theta1_deg), float(theta2_deg), float(roughness), float(band[0]),
+                           float(band[1]))
+        a, y = (lbm_angle * self.ncases)(), (lbm_young * self.ncases)()
+        self._check(lib().lbm_batch_young_force(self._h, C.byref(o), a, y, self.ncases))
+        return list(a), list(y)
 
     def read(self, case, field):
         shp = self.shapes[case]

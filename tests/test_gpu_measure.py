@@ -7,7 +7,7 @@ import pytest
 from paper_2202_06516_amd import lbm as G
 from paper_2202_06516_amd import workloads as W
 
-from .pairs import gpu_lattice, oracle_lattice, rel_err
+from .pairs import BASE, gpu_lattice, oracle_lattice, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -157,3 +157,32 @@ def test_young_force_without_contact_line_and_bad_options():
     for kw in (dict(roughness=0.0), dict(band=(0.5, 0.4)), dict(band=(0.0, 1.0))):
         with pytest.raises(G.LbmError):
             gp.young_force(0.05, 90.0, **kw)
+
+
+def test_batch_young_force_equals_single_lattices():
+    # every case of a batch (uniform cylinder, striped cylinder, cavity) gives
+    # the footprint counts, phi_d, theta_eq and forces of the same case run alone
+    cases = [
+        dict(n=(96, 80), solid=dict(center=(48.3, 24.6), radius=16.2, mu_w=0.04), drop=((48.0, 52.0), 12.0)),
+        dict(n=(96, 80), solid=dict(center=(48.3, 24.6), radius=16.2, stripes=(-0.01, 0.08, 9.0)),
+             drop=((48.0, 52.0), 12.0)),
+        dict(n=(70, 52), solid=dict(center=(35.3, 26.1), radius=23.4, mu_w=0.04, cavity=True), drop=((35.0, 12.0), 9.0)),
+    ]
+    b = G.Batch(cases, precision=G.LBM_F64, **dict(BASE, Tr=0.8))
+    b.step(150)
+    ba, by = b.young_force(0.06, 80.0, 120.0)
+    for i, cs in enumerate(cases):
+        wl = dict(dim=2, n=cs["n"], wall=(0, 0), solids=[cs["solid"]], drops=[cs["drop"]])
+        s = gpu_lattice(wl, G.LBM_F64, Tr=0.8)
+        s.set_measure(0, 2)
+        s.step(150)
+        sa, sy = s.young_force(0.06, 80.0, 120.0)
+        assert by[i].status == sy.status == 0 and ba[i].step == sa.step
+        for k in range(2):
+            assert list(by[i].count[k]) == list(sy.count[k]), (i, k)
+            for name in ("phi_d", "theta_eq_deg", "force"):
+                g, r = getattr(by[i], name)[k], getattr(sy, name)[k]
+                assert (math.isnan(g) and math.isnan(r)) or abs(g - r) <= 1e-12, (i, k, name, g, r)
+    assert sum(by[1].count[0]) > 0 and by[0].phi_d[0] == 1.0
+    with pytest.raises(G.LbmError):
+        b.young_force(0.06, 80.0, 120.0, roughness=0.0)
