@@ -109,8 +109,8 @@ typedef struct {
                              (pseudopotential model: wall density, NaN selects (rho_l + rho_g) / 2) */
     void* stream;         /* hipStream_t to enqueue on, or NULL for a context-owned stream */
     int model;            /* LBM_MODEL_CHEMICAL_POTENTIAL (default) or LBM_MODEL_PSEUDOPOTENTIAL; the
-                             pseudopotential model needs rho_l > rho_g > 0 and ignores Tr, pr_*, k, kappa;
-                             the batched solver accepts the default model only */
+                             pseudopotential model needs rho_l > rho_g > 0 and ignores Tr, pr_*, k, kappa
+                             (the batched solver takes either model for all its cases) */
     double sc_G;          /* pseudopotential interaction strength G (default -6) */
 } lbm_config;
 

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) kb_fill(const long long* __restrict__ nod
         fill_entry<L, R, C>(node[k], mask[k], inv_den[k], rho, dims[ecase[k]]);
 }
 
-template <class L, typename R, typename C>
+template <class L, typename R, typename C, bool SC = false>
 __global__ void __launch_bounds__(256) kb_mu(const Item* __restrict__ items, int nitems, const Dims* __restrict__ dims,
                                              int tile_w, const R* __restrict__ rho, R* __restrict__ mu,
                                              const uint8_t* __restrict__ cls, Thermo th) {
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) kb_mu(const Item* __restrict__ items, int
         int x, y, z;
         item_node(it, tile_w, x, y, z);
         R r0;
-        (void)mu_node<L, R, C>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
+        (void)mu_node<L, R, C, SC>(rho, mu, cls, d, th, x, y, z, x < d.nx && y < d.ny, r0);
     }
 }
 
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) kb_cross(const Item* __restrict__ items, 
     }
 }
 
-template <class L, typename R, typename C, bool PULL, bool MRT>
+template <class L, typename R, typename C, bool PULL, bool MRT, bool SC = false>
 __global__ void __launch_bounds__(256) kb_collide(const Item* __restrict__ items, int nitems,
                                                   const Dims* __restrict__ dims, int tile_w, const R* __restrict__ fin,
                                                   R* __restrict__ fout, const R* __restrict__ rho,
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(256) kb_collide(const Item* __restrict__ items
         const Dims d = dims[it.c];
         int x, y, z;
         item_node(it, tile_w, x, y, z);
-        collide_node<L, R, C, PULL, MRT, true>(fin, fout, rho, mu, cls, d, bc, cp, t, x, y, z);
+        collide_node<L, R, C, PULL, MRT, true, SC>(fin, fout, rho, mu, cls, d, bc, cp, t, x, y, z);
     }
 }
 
@@ -334,6 +334,7 @@ struct BRun {
         }
         for (int k = 0; k < 3; ++k) cp.g[k] = (C)(k < b->dim ? g.g[k] : 0.0);
         cp.g_start = g.g_start_step;
+        cp.sc_G = b->cfg.sc_G;
         return cp;
     }
     static WallBC wall(const lbm_batch* b) {
@@ -365,6 +366,16 @@ struct BRun {
             kb_fill<L, R, C><<<ng2 < grid ? ng2 : grid, 256, 0, b->stream>>>(
                 b->fnode, b->fmask, (const R*)b->inv, b->fcase, b->n_l1, b->n_l1 + b->n_l2, (R*)b->rho, b->dims);
     }
+    // chemical potential, or psi of the pseudopotential model, on fluid nodes
+    static void launch_mu(lbm_batch* b, int grid) {
+        if (b->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
+            kb_mu<L, R, C, true><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w,
+                                                              (const R*)b->rho, (R*)b->mu, b->cls, thermo(b));
+        else
+            kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho,
+                                                        (R*)b->mu, b->cls, thermo(b));
+    }
+
     // one step from f[src] (pull form if pull) into f[1 - src]
     static void step(lbm_batch* b, int src, bool pull, int grid, hipEvent_t* ev = nullptr) {
         const int save = b->cur;
@@ -372,8 +383,7 @@ struct BRun {
         density(b, pull, grid, ev);
         b->cur = save;
         if (ev) (void)hipEventRecord(ev[2], b->stream);
-        kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
-                                                    b->cls, thermo(b));
+        launch_mu(b, grid);
         if (ev) (void)hipEventRecord(ev[3], b->stream);
         kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
                                                     b->ctl, b->slots, b->mp);
@@ -384,7 +394,15 @@ struct BRun {
         const bool mrt = b->cfg.collision == LBM_MRT;
 #define KB_ARGS b->items, b->nitems, b->dims, b->tile_w, fin, fout, (const R*)b->rho, (const R*)b->mu, b->cls, bc, cp, b->ctl
         if (ev) (void)hipEventRecord(ev[4], b->stream);
-        if (pull) {
+        if (b->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL) {
+            if (pull) {
+                if (mrt) kb_collide<L, R, C, true, true, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+                else kb_collide<L, R, C, true, false, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+            } else {
+                if (mrt) kb_collide<L, R, C, false, true, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+                else kb_collide<L, R, C, false, false, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
+            }
+        } else if (pull) {
             if (mrt) kb_collide<L, R, C, true, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
             else kb_collide<L, R, C, true, false><<<grid, 256, 0, b->stream>>>(KB_ARGS);
         } else {
@@ -451,8 +469,7 @@ template <class L, typename R, typename C>
 struct BMeasure {
     static void go(lbm_batch* b, int grid) {
         BRun<L, R, C>::density(b, b->fstar, grid);
-        kb_mu<L, R, C><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, (R*)b->mu,
-                                                    b->cls, BRun<L, R, C>::thermo(b));
+        BRun<L, R, C>::launch_mu(b, grid);
         kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
                                                     b->ctl, b->slots, b->mp);
         kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
@@ -639,7 +656,10 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         return LBM_E_ARG;
     };
     if (base->lattice != LBM_D2Q9 && base->lattice != LBM_D3Q19) return bad();
-    if (base->model != LBM_MODEL_CHEMICAL_POTENTIAL) return bad();
+    if (base->model != LBM_MODEL_CHEMICAL_POTENTIAL && base->model != LBM_MODEL_PSEUDOPOTENTIAL) return bad();
+    if (base->model == LBM_MODEL_PSEUDOPOTENTIAL &&
+        (!(base->rho_g > 0) || !(base->rho_l > base->rho_g) || !std::isfinite(base->sc_G)))
+        return bad();
     if (base->precision != LBM_F32 && base->precision != LBM_F64 && base->precision != LBM_F32_MIXED) return bad();
     if (!(base->tau > 0.5) || !(base->k > 0) || !(base->kappa >= 0)) return bad();
     b->dim = base->lattice == LBM_D2Q9 ? 2 : 3;
@@ -658,6 +678,13 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
     b->rho_m = 0.5 * (b->pr.rho_l + b->pr.rho_g);
     b->mu_ref = base->k * base->k * b->pr.mu_sat;
     b->wall_mu = std::isnan(base->wall_mu) ? b->mu_ref : base->wall_mu;
+    if (base->model == LBM_MODEL_PSEUDOPOTENTIAL) {
+        // wall values are densities; psi is stored unshifted
+        b->mu_ref = 0.0;
+        b->wall_mu = std::isnan(base->wall_mu) ? b->rho_m : base->wall_mu;
+    }
+    const bool sc = base->model == LBM_MODEL_PSEUDOPOTENTIAL;
+    auto wall_value = [&](double v) { return sc ? 1.0 - std::exp(-v) : v - b->mu_ref; };
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
@@ -757,14 +784,14 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         bq.insert(bq.end(), g.b_q.begin(), g.b_q.end());
         nb_total += (int)g.b_node.size();
         for (size_t k = 0; k < g.l1_node.size(); ++k) {
-            muh[base_at + at(g.l1_node[k])] = g.l1_mu[k] - b->mu_ref;
+            muh[base_at + at(g.l1_node[k])] = wall_value(g.l1_mu[k]);
             fnode1.push_back(off + at(g.l1_node[k]));
             fmask1.push_back(g.l1_mask[k]);
             inv1.push_back(g.l1_inv[k]);
             fcase1.push_back(ci);
         }
         for (size_t k = 0; k < g.l2_node.size(); ++k) {
-            muh[base_at + at(g.l2_node[k])] = g.l2_mu[k] - b->mu_ref;
+            muh[base_at + at(g.l2_node[k])] = wall_value(g.l2_mu[k]);
             fnode2.push_back(off + at(g.l2_node[k]));
             fmask2.push_back(g.l2_mask[k]);
             inv2.push_back(g.l2_inv[k]);

@@ -107,4 +107,26 @@ def test_sc_configuration_errors():
         G.Lattice(G.LBM_D2Q9, n=(64, 64, 1), precision=G.LBM_F64, **dict(cfg, rho_l=0.1, rho_g=2.0))
     cs = dict(n=(64, 64), solid=dict(center=(32.0, 20.0), radius=8.0), drop=((32.0, 38.0), 8.0))
     with pytest.raises(G.LbmError):
-        G.Batch([cs], precision=G.LBM_F64, **dict(BASE, model=G.LBM_MODEL_PSEUDOPOTENTIAL, **SC_PARAMS))
+        G.Batch([cs], precision=G.LBM_F64, **dict(BASE, model=G.LBM_MODEL_PSEUDOPOTENTIAL, sc_G=W.SC_G))
+
+
+def test_sc_batch_equals_single_lattices():
+    # the batched solver under the pseudopotential model: every case advances
+    # exactly as the same case alone (populations bit for bit, angles to 1e-12)
+    cases = [
+        dict(n=(70, 52), solid=dict(center=(35.3, 14.6), radius=11.2, mu_w=0.8), drop=((35.0, 35.0), 9.0)),
+        dict(n=(96, 80), solid=dict(center=(48.2, 45.0), radius=30.0, mu_w=1.3, cavity=True), drop=((48.0, 25.0), 10.0)),
+    ]
+    params = dict(BASE, model=G.LBM_MODEL_PSEUDOPOTENTIAL, **SC_PARAMS)
+    b = G.Batch(cases, precision=G.LBM_F64, **params)
+    b.step(60, measure_every=30)
+    b.sync()
+    ang = b.angles()
+    for i, cs in enumerate(cases):
+        wl = dict(dim=2, n=cs["n"], wall=(0, 0), model=1, solids=[cs["solid"]], drops=[cs["drop"]])
+        s = gpu_lattice(wl, G.LBM_F64)
+        sa = s.step(60, measure_every=30, cap=4)
+        assert np.array_equal(b.read(i, G.FIELD_F), s.f), i
+        assert ang[i].step == sa[-1].step and ang[i].status == sa[-1].status == 0
+        for k in range(2):
+            assert abs(ang[i].sector_deg[k] - sa[-1].sector_deg[k]) <= 1e-12
