@@ -146,3 +146,34 @@ def test_profiled_steps_are_ordinary_steps():
     assert a.info()["step"] == c.info()["step"] == 7
     for i in range(len(cases)):
         assert np.array_equal(a.read(i, G.FIELD_F), c.read(i, G.FIELD_F))
+
+
+@pytest.mark.parametrize("precision", [G.LBM_F64, G.LBM_F32])
+def test_batch_d3q19_equals_single(precision):
+    # three-dimensional cases (spheres, one cavity) in one batch: populations
+    # bit for bit and the 16-sector angles of the lone lattices
+    cases = [
+        dict(n=(40, 36, 40), solid=dict(center=(20.2, 18.1, 10.3), radius=7.4, mu_w=0.04),
+             drop=((20.0, 18.0, 25.0), 7.0)),
+        dict(n=(48, 40, 44), solid=dict(center=(24.0, 20.0, 22.0), radius=19.0, mu_w=0.02, cavity=True),
+             drop=((24.0, 20.0, 11.0), 8.0)),
+        dict(n=(36, 36, 36), solid=dict(center=(18.0, 18.0, 9.5), radius=6.0, mu_w=-0.01),
+             drop=((18.0, 18.0, 21.0), 7.5)),
+    ]
+    params = dict(PHYS, collision=G.LBM_BGK)
+    b = G.Batch(cases, lattice=G.LBM_D3Q19, precision=precision, **params)
+    b.step(30, measure_every=15)
+    b.sync()
+    ang = b.angles()
+    for i, cs in enumerate(cases):
+        wl = dict(dim=3, n=cs["n"], wall=(0, 0, 0), solids=[cs["solid"]], drops=[cs["drop"]])
+        s = gpu_lattice(wl, precision, "bgk", Tr=0.8)
+        s.set_measure(0, 16)
+        sa = s.step(30, measure_every=15, cap=4)
+        assert np.array_equal(b.read(i, G.FIELD_F), s.f), i
+        assert np.array_equal(b.read(i, G.FIELD_CLASS), s.read(G.FIELD_CLASS))
+        last = sa[-1]
+        assert ang[i].step == last.step and ang[i].status == last.status
+        for k in range(16):
+            x, y = ang[i].sector_deg[k], last.sector_deg[k]
+            assert (math.isnan(x) and math.isnan(y)) or abs(x - y) <= 1e-9, (i, k, x, y)
