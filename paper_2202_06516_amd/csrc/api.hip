@@ -166,6 +166,8 @@ struct Run {
         return cp;
     }
     static dim3 grid(const lbm_ctx* c) { return dim3(c->d.nblocks, 1, 1); }
+    // the z-chunked chemical-potential kernel
+    static dim3 zgrid(const lbm_ctx* c) { return dim3(c->d.zc > 1 ? c->d.nblocks_zc : c->d.nblocks, 1, 1); }
     // the crossing search walks the tiles in a grid-stride loop
     static dim3 cross_grid(const lbm_ctx* c) { return dim3(c->d.nblocks < 2048u ? c->d.nblocks : 2048u, 1, 1); }
 
@@ -203,10 +205,12 @@ struct Run {
 
     // chemical potential, or psi of the pseudopotential model, on fluid nodes
     static void launch_mu(lbm_ctx* c, R* rho, R* mu) {
-        if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
-            k_mu<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
-        else
-            k_mu<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+        const dim3 blk(256, 1, 1);
+        const bool sc = c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL, zch = c->d.zc > 1;
+        if (sc && zch) k_mu<L, R, C, true, true><<<zgrid(c), blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+        else if (sc) k_mu<L, R, C, true><<<grid(c), blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+        else if (zch) k_mu<L, R, C, false, true><<<zgrid(c), blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
+        else k_mu<L, R, C><<<grid(c), blk, 0, c->stream>>>(rho, mu, c->cls, c->d, thermo(c));
     }
 
     template <bool PULL, bool MRT>
@@ -494,6 +498,14 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->d.tx = (c->d.nx + (1 << c->d.tws) - 1) >> c->d.tws;
     c->d.ty = (c->d.ny + (256 >> c->d.tws) - 1) / (256 >> c->d.tws);
     c->d.nblocks = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)c->d.nz;
+    {
+        // planes per workgroup of the chemical-potential kernel (3-D): 8 took it from 0.080 to 0.067 ms
+        // at 256^3; LBM_ZCHUNK overrides
+        const char* e = std::getenv("LBM_ZCHUNK");
+        const int zc = c->dim == 3 ? (e ? std::atoi(e) : 8) : 1;
+        c->d.zc = zc < 1 ? 1 : zc;
+        c->d.nblocks_zc = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)((c->d.nz + c->d.zc - 1) / c->d.zc);
+    }
     {
         const char* e = std::getenv("LBM_XCD_REMAP");
         c->d.xcd_remap = e ? std::atoi(e) != 0 : 1;
