@@ -281,6 +281,19 @@ typedef struct {
  * LBM_E_NO_CONTACT_LINE (out->status set, every value NaN), LBM_E_DEVICE. */
 lbm_status lbm_young_force(lbm_ctx* ctx, const lbm_young_opts* opts, lbm_angle* angle, lbm_young* out);
 
+/* Take the unbalanced Young force (Eq. 17-18) at every in-step measurement of
+ * the following lbm_step calls, with these options (NULL turns it off).  Each
+ * measurement then counts the footprint in the same frame and sectors, and
+ * applies Eq. 18 and Eq. 17 on the device, in FP64, to the angles it has just
+ * measured.  lbm_young_series returns those records.  Synchronises.  Errors:
+ * LBM_E_ARG (options as for lbm_young_force), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_set_young(lbm_ctx* ctx, const lbm_young_opts* opts);
+
+/* The Young-force records of the last lbm_step call that wrote an angle
+ * series: out[i] belongs to series[i] of that call (min(cap, that count)
+ * records, *n_written).  Synchronises.  Errors: LBM_E_ARG, LBM_E_STATE (off). */
+lbm_status lbm_young_series(lbm_ctx* ctx, lbm_young* out, int cap, int* n_written);
+
 /* Step the lattice nsteps times (no measurement) with a HIP event pair
  * around every kernel launch, and report the mean duration in milliseconds of
  * each kernel kind: names[i] (static strings) and ms[i] for i < *n_kinds

@@ -53,6 +53,13 @@ struct lbm_ctx {
     double* mass_part = nullptr;
     double* mass_out = nullptr;
     unsigned* young_counts = nullptr;  // [LBM_MAX_SECTORS][2] footprint counts of lbm_young_force
+    bool young_on = false;             // the Young force at every in-step measurement (lbm_set_young)
+    lbm_young_opts yopts{};
+    YoungRec* ylast = nullptr;         // its latest record
+    unsigned* ystep_counts = nullptr;  // its footprint counts, zero between measurements
+    YoungRec* yseries = nullptr;       // its series, alongside the angle series
+    int yseries_capacity = 0;
+    int series_written = 0;            // records of the last lbm_step series
     bool have_geometry = false, have_state = false;
     std::vector<Solid> solids;
     lbm_measure_opts mopts{0, 32, 0.0};
@@ -203,6 +210,27 @@ struct Run {
         }
     }
 
+    // the in-step Young force: counting parameters (the drop axis comes from
+    // the measurement's own centroid on the device) and the Eq. 17-18 options
+    static YoungParams young_step_params(const lbm_ctx* c, const MeasureParams& mp) {
+        double lo, hi;
+        young_band(c->yopts, lo, hi);
+        lbm_angle a{};
+        a.n_sectors = mp.n_sectors;
+        return young_params(c->solids[c->mopts.solid_index], a, c->dim, c->pr.rho_g, c->pr.rho_l, lo, hi);
+    }
+    static YoungStep young_step(const lbm_ctx* c, const MeasureParams&) {
+        YoungStep ys{};
+        ys.on = 1;
+        ys.gamma = c->yopts.gamma;
+        ys.c1 = std::cos(c->yopts.theta1_deg * M_PI / 180.0);
+        ys.c2 = std::cos(c->yopts.theta2_deg * M_PI / 180.0);
+        ys.roughness = c->yopts.roughness;
+        ys.counts = c->ystep_counts;
+        ys.last = c->ylast;
+        return ys;
+    }
+
     // chemical potential, or psi of the pseudopotential model, on fluid nodes
     static void launch_mu(lbm_ctx* c, R* rho, R* mu) {
         const dim3 blk(256, 1, 1);
@@ -243,6 +271,12 @@ struct Run {
         mark(3);
         start();
         k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, c->ctl, mp);
+        YoungStep ys{};
+        if (c->young_on) {
+            ys = young_step(c, mp);
+            k_young_step<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, young_step_params(c, mp), mp,
+                                                                    c->ctl, c->ystep_counts);
+        }
         mark(5);
         start();
         const WallBC bc = wall(c);
@@ -257,7 +291,7 @@ struct Run {
         }
         mark(4);
         start();
-        k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1);
+        k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1, ys, c->yseries);
         mark(6);
         if (kinds) kinds[k] = -1;
     }
@@ -570,7 +604,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
     drop_graphs(c);
     void* ps[] = {c->f[0], c->f[1], c->rho, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
                   c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
-                  c->mass_part, c->mass_out, c->young_counts};
+                  c->mass_part, c->mass_out, c->young_counts, c->ylast, c->yseries, c->ystep_counts};
     for (void* p : ps) dfree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -747,11 +781,44 @@ static lbm_status ensure_series(lbm_ctx* c, int cap) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     lbm_status s = dalloc(c, &c->series, (size_t)cap * sizeof(AngleRec));
+    if (!s) s = dalloc(c, &c->yseries, (size_t)cap * sizeof(YoungRec));
     if (s) {
         c->series_capacity = 0;
         return s;
     }
     c->series_capacity = cap;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_young(lbm_ctx* c, const lbm_young_opts* yo) {
+    if (!c) return LBM_E_ARG;
+    if (yo && !young_opts_ok(*yo))
+        return fail(c, LBM_E_ARG, "set_young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->young_on = yo != nullptr;
+    if (!yo) return LBM_OK;
+    c->yopts = *yo;
+    if (!c->ylast) {
+        lbm_status s = dalloc(c, &c->ylast, sizeof(YoungRec));
+        if (!s) s = dalloc(c, &c->ystep_counts, 2 * LBM_MAX_SECTORS * sizeof(unsigned));
+        if (s) return s;
+    }
+    // the counts start at zero; every in-step measurement clears them after use
+    HIPCHK(c, hipMemset(c->ystep_counts, 0, 2 * LBM_MAX_SECTORS * sizeof(unsigned)));
+    return LBM_OK;
+}
+
+lbm_status lbm_young_series(lbm_ctx* c, lbm_young* out, int cap, int* n_written) {
+    if (!c || !out || cap < 0 || !n_written) return LBM_E_ARG;
+    *n_written = 0;
+    if (!c->young_on) return fail(c, LBM_E_STATE, "young_series: the in-step Young force is off (lbm_set_young)");
+    const int n = c->series_written < cap ? c->series_written : cap;
+    if (n > 0) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(out, c->yseries, (size_t)n * sizeof(YoungRec), hipMemcpyDeviceToHost));
+    }
+    *n_written = n;
     return LBM_OK;
 }
 
@@ -761,6 +828,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
     if (!c->have_state) return fail(c, LBM_E_STATE, "step: no initial state (call lbm_init_drops or lbm_write)");
     if (nsteps < 0 || measure_every < 0 || cap < 0) return fail(c, LBM_E_ARG, "step: negative argument");
     if (measure_every > 0 && c->solids.empty()) return fail(c, LBM_E_ARG, "step: measurement needs a solid");
+    if (c->young_on && c->solids.empty()) return fail(c, LBM_E_STATE, "step: the Young force needs a solid");
+    c->series_written = 0;
     if (series && cap > 0) {
         lbm_status s = ensure_series(c, cap);
         if (s) return s;
@@ -820,6 +889,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
         const int nw = h.series_count < cap ? h.series_count : cap;
         if (nw > 0) HIPCHK(c, hipMemcpy(series, c->series, (size_t)nw * sizeof(AngleRec), hipMemcpyDeviceToHost));
         if (n_written) *n_written = nw;
+        c->series_written = nw;
         if (h.status & 1) return fail(c, LBM_E_NONFINITE, "a density became non-finite, non-positive or >= 1/b");
     }
     return LBM_OK;

@@ -887,6 +887,22 @@ struct YoungParams {
     double axis[3];          // drop axis of the measurement
 };
 
+// One record of the unbalanced Young force; the layout of lbm_young.
+struct YoungRec {
+    long long step;
+    int status, n_sectors;
+    int count[64][2];
+    double phi_d[64], theta_eq_deg[64], force[64];
+};
+
+// The Young force taken at every in-step measurement (on = 0: not taken).
+struct YoungStep {
+    int on;
+    double gamma, c1, c2, roughness;   // gamma, cos theta_1, cos theta_2, r of Eq. 18
+    unsigned* counts;                  // [64][2] footprint counts, zero between measurements
+    YoungRec* last;                    // the latest record
+};
+
 // one node's contribution to the footprint counts: a fluid node in the
 // density band with a lattice neighbour inside the substrate, counted in its
 // sector and on the kind of surface at its own polar angle
@@ -919,6 +935,56 @@ __device__ __forceinline__ void young_node(const R* __restrict__ rho, const uint
     atomicAdd(&counts[sector_of(r, F, yp.dim, yp.n_sectors) * 2 + kind], 1u);
 }
 
+// the footprint counts of an in-step measurement (returns at once on the
+// other steps), in the frame the measurement's crossing search uses
+template <class L, typename R>
+__global__ void __launch_bounds__(256) k_young_step(const R* __restrict__ rho, const uint8_t* __restrict__ cls,
+                                                    Dims d, YoungParams yp, MeasureParams mp,
+                                                    const DevCtl* __restrict__ ctl, unsigned* __restrict__ counts) {
+    if (!measuring(ctl)) return;
+    const Frame F = make_frame(&ctl->m, mp);
+    if (!F.ok) return;
+    const unsigned ntiles = (unsigned)d.tx * (unsigned)d.ty * (unsigned)d.nz;
+    for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int x, y, z;
+        tile_coords(d, t, x, y, z);
+        young_node<L, R>(rho, cls, d, yp, F, x, y, z, counts);
+    }
+}
+
+// Eq. 18 and Eq. 17 for the record a measurement just wrote, one thread per
+// sector (64 threads); clears the counts for the next measurement
+__device__ inline void young_finish(const YoungStep& ys, const AngleRec* a, YoungRec* copy) {
+    const int s = threadIdx.x;
+    const bool ok = a->status == 0 && s < a->n_sectors;
+    const unsigned h0 = ok ? ys.counts[2 * s] : 0u, h1 = ok ? ys.counts[2 * s + 1] : 0u;
+    double phi = NAN, te = NAN, fo = NAN;
+    if (ok && h0 + h1 > 0u) {
+        phi = (double)h0 / (double)(h0 + h1);
+        double ce = ys.roughness * phi * ys.c1 + (1.0 - phi) * ys.c2;
+        ce = ce > 1.0 ? 1.0 : (ce < -1.0 ? -1.0 : ce);
+        te = acos(ce) * (180.0 / M_PI);
+        if (!isnan(a->sector_deg[s])) fo = ys.gamma * (cos(a->sector_deg[s] * (M_PI / 180.0)) - ce);
+    }
+    YoungRec* recs[2] = {ys.last, copy};
+    for (int k = 0; k < 2; ++k) {
+        YoungRec* r = recs[k];
+        if (!r) continue;
+        if (s == 0) {
+            r->step = a->step;
+            r->status = a->status;
+            r->n_sectors = a->n_sectors;
+        }
+        r->count[s][0] = (int)h0;
+        r->count[s][1] = (int)h1;
+        r->phi_d[s] = phi;
+        r->theta_eq_deg[s] = te;
+        r->force[s] = fo;
+    }
+    ys.counts[2 * s] = 0u;
+    ys.counts[2 * s + 1] = 0u;
+}
+
 template <class L, typename R>
 __global__ void __launch_bounds__(256) k_young_count(const R* __restrict__ rho, const uint8_t* __restrict__ cls,
                                                      Dims d, YoungParams yp, unsigned* __restrict__ counts) {
@@ -934,11 +1000,16 @@ __global__ void __launch_bounds__(256) k_young_count(const R* __restrict__ rho, 
 template <class L, typename R>
 __global__ void __launch_bounds__(64) k_finalize(const R* __restrict__ rho, DevCtl* __restrict__ ctl, Dims d,
                                                  MeasureParams mp, AngleRec* __restrict__ series,
-                                                 AngleRec* __restrict__ last, int tick) {
+                                                 AngleRec* __restrict__ last, int tick, YoungStep ys = YoungStep{},
+                                                 YoungRec* __restrict__ yseries = nullptr) {
     if (measuring(ctl)) {
         const bool keep = series && ctl->series_count < ctl->series_cap;
         finalize_slots<L, R>(rho, d, mp, &ctl->m, ctl->t, last, keep ? series + ctl->series_count : nullptr);
         __syncthreads();
+        if (ys.on) {
+            young_finish(ys, last, keep && yseries ? yseries + ctl->series_count : nullptr);
+            __syncthreads();
+        }
         if (threadIdx.x == 0 && keep) ctl->series_count += 1;
     }
     if (threadIdx.x == 0 && tick) ctl->t += 1;

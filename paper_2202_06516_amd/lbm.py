@@ -126,7 +126,8 @@ _lib = None
 # exported symbols of include/lbm.h (the binding and the tests check them)
 EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops",
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
-           "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_last_error", "lbm_batch_create",
+           "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_set_young", "lbm_young_series",
+           "lbm_last_error", "lbm_batch_create",
            "lbm_batch_destroy",
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
            "lbm_batch_read", "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step", "lbm_batch_last_error",
@@ -163,6 +164,8 @@ def lib():
     L.lbm_set_measure.argtypes = [vp, P(lbm_measure_opts)]
     L.lbm_measure_angle.argtypes = [vp, P(lbm_measure_opts), P(lbm_angle)]
     L.lbm_young_force.argtypes = [vp, P(lbm_young_opts), P(lbm_angle), P(lbm_young)]
+    L.lbm_set_young.argtypes = [vp, P(lbm_young_opts)]
+    L.lbm_young_series.argtypes = [vp, P(lbm_young), i, P(i)]
     L.lbm_read.argtypes = [vp, i, vp, C.c_size_t, i]
     L.lbm_write.argtypes = [vp, i, vp, C.c_size_t, i]
     L.lbm_sync.argtypes = [vp]
@@ -211,7 +214,8 @@ def lib():
         getattr(L, name).restype = C.c_int
     for name in ("lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops", "lbm_step",
                  "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
-                 "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_batch_create", "lbm_batch_destroy",
+                 "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_set_young", "lbm_young_series",
+                 "lbm_batch_create", "lbm_batch_destroy",
                  "lbm_batch_step",
                  "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
                  "lbm_batch_read", "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step"):
@@ -334,6 +338,22 @@ class Lattice:
         if st not in (0, LBM_E_NO_CONTACT_LINE):
             self._check(st)
         return a, y
+
+    def set_young(self, gamma=None, theta1_deg=90.0, theta2_deg=90.0, roughness=1.0, band=(0.1, 0.9)):
+        """Take the unbalanced Young force at every in-step measurement (gamma None: off)."""
+        if gamma is None:
+            self._check(lib().lbm_set_young(self._h, None))
+            return
+        o = lbm_young_opts(float(gamma), float(theta1_deg), float(theta2_deg), float(roughness), float(band[0]),
+                           float(band[1]))
+        self._check(lib().lbm_set_young(self._h, C.byref(o)))
+
+    def young_series(self, cap=4096):
+        """Young-force records of the last step call that wrote an angle series."""
+        arr = (lbm_young * max(cap, 1))()
+        n = C.c_int()
+        self._check(lib().lbm_young_series(self._h, arr, cap, C.byref(n)))
+        return [arr[k] for k in range(n.value)]
 
     # -- fields ------------------------------------------------------------
     def read(self, field):

@@ -186,3 +186,32 @@ def test_batch_young_force_equals_single_lattices():
     assert sum(by[1].count[0]) > 0 and by[0].phi_d[0] == 1.0
     with pytest.raises(G.LbmError):
         b.young_force(0.06, 80.0, 120.0, roughness=0.0)
+
+
+def test_young_force_in_step_matches_oracle():
+    # the Young force taken at every in-step measurement (every 100 steps of a
+    # drop relaxing on a striped cylinder) equals the oracle's Eq. 17-18 on the
+    # same states: counts bit-exact, phi_d / theta_eq / force to round-off
+    wl = dict(dim=2, n=(96, 80), wall=(0, 0), Tr=0.8,
+              solids=[dict(center=(48.3, 24.6), radius=16.2, stripes=(-0.01, 0.08, 9.0))],
+              drops=[((48.0, 52.0), 12.0)])
+    gp = gpu_lattice(wl, G.LBM_F64)
+    gp.set_measure(0, 2)
+    gp.set_young(0.06, 80.0, 120.0)
+    ga = gp.step(1000, measure_every=100, cap=16)
+    gy = gp.young_series()
+    assert len(ga) == len(gy) == 10
+    o = oracle_lattice(wl)
+    for k in range(10):
+        oa, oy = o.young_force(0.06, 80.0, 120.0)
+        assert gy[k].step == ga[k].step == oy.step == 100 * k and gy[k].status == oy.status
+        for s in range(2):
+            assert list(gy[k].count[s]) == list(oy.count[s]), (k, s)
+            for name in ("phi_d", "theta_eq_deg", "force"):
+                g, r = getattr(gy[k], name)[s], getattr(oy, name)[s]
+                assert (math.isnan(g) and math.isnan(r)) or abs(g - r) <= 1e-9, (k, s, name, g, r)
+        o.step(100)
+    assert any(sum(gy[k].count[0]) > 0 for k in range(10))
+    gp.set_young(None)
+    with pytest.raises(G.LbmError):
+        gp.young_series()
