@@ -1,8 +1,8 @@
 """GPU parity: the HIP library against the FP64 CPU oracle on the same seeded inputs.
 
 Every comparison is element by element.  FP64 runs are held to round-off
-(1e-12 relative to the largest density); FP32 runs to the 1e-6 relative
-density bound of the benchmark spec.
+(1e-12 relative to the largest density); FP32 runs to a relative density
+error of 1e-6.
 """
 import numpy as np
 import pytest
