@@ -363,6 +363,14 @@ lbm_status lbm_batch_measure(lbm_batch* b, lbm_angle* out, int n);
  * n, or options as for lbm_young_force), LBM_E_NOMEM, LBM_E_DEVICE. */
 lbm_status lbm_batch_young_force(lbm_batch* b, const lbm_young_opts* opts, lbm_angle* angles, lbm_young* out, int n);
 
+/* Take the unbalanced Young force at every in-step measurement of every case
+ * (as lbm_set_young does for one lattice; NULL turns it off), and read the
+ * latest record of cases 0..n-1 (status LBM_E_NO_CONTACT_LINE and NaN values
+ * before the first measurement or without a contact line).  Both synchronise.
+ * Errors: LBM_E_ARG, LBM_E_STATE (off, for the read), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_batch_set_young(lbm_batch* b, const lbm_young_opts* opts);
+lbm_status lbm_batch_young_last(lbm_batch* b, lbm_young* out, int n);
+
 /* Fields of one case: RHO (n*elem bytes), F (Q*n*elem, [Q][n]), CLASS (n bytes).  Synchronises. */
 lbm_status lbm_batch_read(lbm_batch* b, int case_index, int field, void* dst, size_t bytes, int dst_on_device);
 /* Replace one case's state by f_eq(rho, 0) (LBM_FIELD_RHO only; a warm start). */

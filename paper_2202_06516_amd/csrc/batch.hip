@@ -154,10 +154,41 @@ __global__ void __launch_bounds__(256) kb_young_count(const Item* __restrict__ i
 template <class L, typename R>
 __global__ void __launch_bounds__(64) kb_finalize(const R* __restrict__ rho, const DevCtl* __restrict__ ctl,
                                                   const Dims* __restrict__ dims, const MeasureParams* __restrict__ mp,
-                                                  MeasureSlots* __restrict__ slots, AngleRec* __restrict__ last) {
+                                                  MeasureSlots* __restrict__ slots, AngleRec* __restrict__ last,
+                                                  YoungStep ys = YoungStep{}) {
     if (!measuring(ctl)) return;
     const int c = blockIdx.x;
     finalize_slots<L, R>(rho, dims[c], mp[c], &slots[c], ctl->t, &last[c], nullptr);
+    if (ys.on) {
+        // this case's counts and record
+        __syncthreads();
+        YoungStep yc = ys;
+        yc.counts = ys.counts + (size_t)c * 2 * LBM_MAX_SECTORS;
+        yc.last = ys.last + c;
+        young_finish(yc, &last[c], nullptr);
+    }
+}
+
+// the footprint counts of an in-step measurement of every case (returns at
+// once on the other steps), each in its own measurement's frame
+template <class L, typename R>
+__global__ void __launch_bounds__(256) kb_young_step(const Item* __restrict__ items, int nitems,
+                                                     const Dims* __restrict__ dims, int tile_w,
+                                                     const R* __restrict__ rho, const uint8_t* __restrict__ cls,
+                                                     const YoungParams* __restrict__ yps,
+                                                     const MeasureParams* __restrict__ mp,
+                                                     const MeasureSlots* __restrict__ slots, const DevCtl* __restrict__ ctl,
+                                                     unsigned* __restrict__ counts) {
+    if (!measuring(ctl)) return;
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Frame F = make_frame(&slots[it.c], mp[it.c]);
+        if (!F.ok) continue;
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        young_node<L, R>(rho, cls, d, yps[it.c], F, x, y, z, counts + (size_t)it.c * 2 * LBM_MAX_SECTORS);
+    }
 }
 
 __global__ void kb_tick(DevCtl* ctl) {
@@ -213,6 +244,11 @@ struct lbm_batch {
     std::vector<Solid> solids_h;       // the substrate of every case
     YoungParams* yparams = nullptr;    // Young-force counting parameters per case (allocated on first use)
     unsigned* ycounts = nullptr;       // footprint counts [case][sector][surface]
+    bool young_on = false;             // the Young force at every in-step measurement
+    lbm_young_opts yopts{};
+    YoungParams* ystep_params = nullptr;  // its counting parameters per case
+    unsigned* ystep_counts = nullptr;     // its counts [case][sector][surface], zero between measurements
+    YoungRec* ylast = nullptr;            // its latest record per case
     Dims* dims = nullptr;
     MeasureParams* mp = nullptr;
     MeasureSlots* slots = nullptr;
@@ -387,6 +423,19 @@ struct BRun {
         if (ev) (void)hipEventRecord(ev[3], b->stream);
         kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
                                                     b->ctl, b->slots, b->mp);
+        YoungStep ys{};
+        if (b->young_on) {
+            kb_young_step<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho,
+                                                             b->cls, b->ystep_params, b->mp, b->slots, b->ctl,
+                                                             b->ystep_counts);
+            ys.on = 1;
+            ys.gamma = b->yopts.gamma;
+            ys.c1 = std::cos(b->yopts.theta1_deg * M_PI / 180.0);
+            ys.c2 = std::cos(b->yopts.theta2_deg * M_PI / 180.0);
+            ys.roughness = b->yopts.roughness;
+            ys.counts = b->ystep_counts;
+            ys.last = b->ylast;
+        }
         const R* fin = (const R*)b->f[src];
         R* fout = (R*)b->f[1 - src];
         const WallBC bc = wall(b);
@@ -411,7 +460,8 @@ struct BRun {
         }
 #undef KB_ARGS
         if (ev) (void)hipEventRecord(ev[5], b->stream);
-        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
+        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last,
+                                                          ys);
         kb_tick<<<1, 64, 0, b->stream>>>(b->ctl);
     }
     static R* materialize(lbm_batch* b, int grid) {
@@ -635,7 +685,7 @@ lbm_status lbm_batch_destroy(lbm_batch* b) {
     drop_graph(b);
     void* ps[] = {b->dims, b->mp,   b->slots, b->last, b->ctl,  b->f[0], b->f[1], b->rho,  b->mu,   b->inv,
                   b->bq,   b->cls,  b->nbmask, b->fmask, b->bidx, b->fcase, b->fnode, b->items,
-                  b->yparams, b->ycounts};
+                  b->yparams, b->ycounts, b->ystep_params, b->ystep_counts, b->ylast};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1014,6 +1064,54 @@ lbm_status lbm_batch_young_force(lbm_batch* b, const lbm_young_opts* yo, lbm_ang
         young_clear(angles[c], (lbm_status)angles[c].status, &out[c]);
         if (angles[c].status == LBM_OK) young_from_counts(*yo, angles[c], &h[(size_t)c * 2 * LBM_MAX_SECTORS], &out[c]);
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_young(lbm_batch* b, const lbm_young_opts* yo) {
+    if (!b) return LBM_E_ARG;
+    if (yo && !young_opts_ok(*yo))
+        return bfail(b, LBM_E_ARG, "batch set_young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
+    BCHK(b, hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    b->young_on = yo != nullptr;
+    if (!yo) return LBM_OK;
+    b->yopts = *yo;
+    const int n = b->ncases;
+    const size_t cbytes = (size_t)n * 2 * LBM_MAX_SECTORS * sizeof(unsigned);
+    if (!b->ylast) {
+        if (hipMalloc((void**)&b->ystep_params, (size_t)n * sizeof(YoungParams)) != hipSuccess ||
+            hipMalloc((void**)&b->ystep_counts, cbytes) != hipSuccess ||
+            hipMalloc((void**)&b->ylast, (size_t)n * sizeof(YoungRec)) != hipSuccess)
+            return bfail(b, LBM_E_NOMEM, "batch set_young: device allocation failed");
+    }
+    // static counting parameters per case; the drop axis comes from each measurement
+    double lo, hi;
+    young_band(*yo, lo, hi);
+    std::vector<YoungParams> yp((size_t)n);
+    for (int c = 0; c < n; ++c) {
+        lbm_angle a{};
+        a.n_sectors = b->mp_h[c].n_sectors;
+        yp[c] = young_params(b->solids_h[c], a, b->dim, b->pr.rho_g, b->pr.rho_l, lo, hi);
+    }
+    BCHK(b, hipMemcpy(b->ystep_params, yp.data(), yp.size() * sizeof(YoungParams), hipMemcpyHostToDevice));
+    BCHK(b, hipMemset(b->ystep_counts, 0, cbytes));
+    // records stay NaN until the first measurement
+    std::vector<YoungRec> empty((size_t)n);
+    for (auto& r : empty) {
+        std::memset(&r, 0, sizeof r);
+        r.status = LBM_E_NO_CONTACT_LINE;
+        for (int k = 0; k < LBM_MAX_SECTORS; ++k) r.phi_d[k] = r.theta_eq_deg[k] = r.force[k] = NAN;
+    }
+    BCHK(b, hipMemcpy(b->ylast, empty.data(), empty.size() * sizeof(YoungRec), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_young_last(lbm_batch* b, lbm_young* out, int n) {
+    if (!b) return LBM_E_ARG;
+    if (!out || n < 1 || n > b->ncases) return bfail(b, LBM_E_ARG, "batch young_last: bad count");
+    if (!b->young_on) return bfail(b, LBM_E_STATE, "batch young_last: the in-step Young force is off");
+    BCHK(b, hipStreamSynchronize(b->stream));
+    BCHK(b, hipMemcpy(out, b->ylast, (size_t)n * sizeof(YoungRec), hipMemcpyDeviceToHost));
     return LBM_OK;
 }
 

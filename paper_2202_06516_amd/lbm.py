@@ -130,6 +130,7 @@ EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "
            "lbm_last_error", "lbm_batch_create",
            "lbm_batch_destroy",
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
+           "lbm_batch_set_young", "lbm_batch_young_last",
            "lbm_batch_read", "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step", "lbm_batch_last_error",
            "lbm_unet_config_default", "lbm_unet_create", "lbm_unet_destroy", "lbm_unet_param_count",
            "lbm_unet_set_params", "lbm_unet_get_params", "lbm_unet_forward", "lbm_unet_loss", "lbm_unet_backward",
@@ -180,6 +181,8 @@ def lib():
     L.lbm_batch_angles.argtypes = [vp, P(lbm_angle), i]
     L.lbm_batch_measure.argtypes = [vp, P(lbm_angle), i]
     L.lbm_batch_young_force.argtypes = [vp, P(lbm_young_opts), P(lbm_angle), P(lbm_young), i]
+    L.lbm_batch_set_young.argtypes = [vp, P(lbm_young_opts)]
+    L.lbm_batch_young_last.argtypes = [vp, P(lbm_young), i]
     L.lbm_batch_read.argtypes = [vp, i, i, vp, C.c_size_t, i]
     L.lbm_batch_write.argtypes = [vp, i, i, vp, C.c_size_t, i]
     L.lbm_batch_get_info.argtypes = [vp, P(lbm_batch_info)]
@@ -218,6 +221,7 @@ def lib():
                  "lbm_batch_create", "lbm_batch_destroy",
                  "lbm_batch_step",
                  "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
+                 "lbm_batch_set_young", "lbm_batch_young_last",
                  "lbm_batch_read", "lbm_batch_write", "lbm_batch_get_info", "lbm_batch_tune", "lbm_batch_profile_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -496,6 +500,21 @@ class Batch:
     def measure(self):
         arr = (lbm_angle * self.ncases)()
         self._check(lib().lbm_batch_measure(self._h, arr, self.ncases))
+        return list(arr)
+
+    def set_young(self, gamma=None, theta1_deg=90.0, theta2_deg=90.0, roughness=1.0, band=(0.1, 0.9)):
+        """Take the unbalanced Young force at every in-step measurement of every case (gamma None: off)."""
+        if gamma is None:
+            self._check(lib().lbm_batch_set_young(self._h, None))
+            return
+        o = lbm_young_opts(float(gamma), float(theta1_deg), float(theta2_deg), float(roughness), float(band[0]),
+                           float(band[1]))
+        self._check(lib().lbm_batch_set_young(self._h, C.byref(o)))
+
+    def young_last(self):
+        """The latest in-step Young-force record of every case."""
+        arr = (lbm_young * self.ncases)()
+        self._check(lib().lbm_batch_young_last(self._h, arr, self.ncases))
         return list(arr)
 
     def young_force(self, gamma, theta1_deg, theta2_deg=90.0, roughness=1.0, band=(0.1, 0.9)):

@@ -215,3 +215,34 @@ def test_young_force_in_step_matches_oracle():
     gp.set_young(None)
     with pytest.raises(G.LbmError):
         gp.young_series()
+
+
+def test_batch_in_step_young_force_equals_single():
+    # the in-step Young force of every case of a batch equals that of the same
+    # case run alone (latest record after three measurements)
+    cases = [
+        dict(n=(96, 80), solid=dict(center=(48.3, 24.6), radius=16.2, stripes=(-0.01, 0.08, 9.0)),
+             drop=((48.0, 52.0), 12.0)),
+        dict(n=(70, 52), solid=dict(center=(35.3, 26.1), radius=23.4, mu_w=0.04, cavity=True), drop=((35.0, 12.0), 9.0)),
+    ]
+    b = G.Batch(cases, precision=G.LBM_F64, **dict(BASE, Tr=0.8))
+    b.set_young(0.06, 80.0, 120.0)
+    assert all(y.status == G.LBM_E_NO_CONTACT_LINE for y in b.young_last())
+    b.step(300, measure_every=100)
+    by = b.young_last()
+    for i, cs in enumerate(cases):
+        wl = dict(dim=2, n=cs["n"], wall=(0, 0), solids=[cs["solid"]], drops=[cs["drop"]])
+        s = gpu_lattice(wl, G.LBM_F64, Tr=0.8)
+        s.set_measure(0, 2)
+        s.set_young(0.06, 80.0, 120.0)
+        s.step(300, measure_every=100, cap=4)
+        sy = s.young_series()[-1]
+        assert by[i].step == sy.step == 200 and by[i].status == sy.status == 0
+        for k in range(2):
+            assert list(by[i].count[k]) == list(sy.count[k]), (i, k)
+            for name in ("phi_d", "theta_eq_deg", "force"):
+                g, r = getattr(by[i], name)[k], getattr(sy, name)[k]
+                assert (math.isnan(g) and math.isnan(r)) or abs(g - r) <= 1e-12, (i, k, name, g, r)
+    b.set_young(None)
+    with pytest.raises(G.LbmError):
+        b.young_last()
