@@ -43,9 +43,10 @@ def start_drop(cx, cy, R, x0, r0):
 def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripes=None, g=5e-7, phi_deg=20.0,
         Tr=0.6, relax=20000, steps=600000, every=500, chunk=10000, stop_frac=0.6, precision=G.LBM_F32,
         young=None, log=print):
-    """young = (gamma, theta_1, theta_2): after every chunk of steps, also the
-    unbalanced Young force of Eq. 17 on both contact lines (lbm_young_force:
-    theta_eq of Eq. 18 from the footprint on the two kinds of band)."""
+    """young = (gamma, theta_1, theta_2): also the unbalanced Young force of
+    Eq. 17 on both contact lines at every measurement, taken inside the step
+    loop (lbm_set_young: theta_eq of Eq. 18 from the footprint on the two kinds
+    of band)."""
     phi = math.radians(phi_deg)
     # a closed box: with the tilted gravity an open (periodic) x axis would let
     # the whole gas column accelerate along x without bound
@@ -60,6 +61,8 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
     lat.set_solids([sol])
     lat.init_drops([(start_drop(cx, cy, R, x0, r0), r0)], W=10.0)
     lat.set_measure(0, 2)
+    if young is not None:
+        lat.set_young(*young)
     half = math.sqrt(2 * R * H - H * H)       # half-width of the arc above the floor
     x_stop = cx + stop_frac * half
     recs, forces = [], []
@@ -67,7 +70,15 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
     t0 = time.perf_counter()
     while done < steps:
         n = min(chunk, steps - done)
-        for a in lat.step(n, measure_every=every, cap=n // every + 1):
+        series = lat.step(n, measure_every=every, cap=n // every + 1)
+        if young is not None:
+            for a, y in zip(series, lat.young_series()):
+                if a.status == 0 and y.status == 0 and math.isfinite(y.force[0]) and math.isfinite(y.force[1]):
+                    k = 0 if a.contact[0][0] > a.contact[1][0] else 1
+                    forces.append(dict(step=int(a.step), force_a=float(y.force[k]), force_r=float(y.force[1 - k]),
+                                       theta_eq_a=float(y.theta_eq_deg[k]), theta_eq_r=float(y.theta_eq_deg[1 - k]),
+                                       phi_a=float(y.phi_d[k]), phi_r=float(y.phi_d[1 - k])))
+        for a in series:
             if a.status != 0:
                 recs.append(dict(step=int(a.step), status=int(a.status)))
                 continue
@@ -78,13 +89,6 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
                              x_r=float(a.contact[1 - k][0]),
                              library_sides=bool(a.adv_deg == a.sector_deg[k] and a.rec_deg == a.sector_deg[1 - k])))
         done += n
-        if young is not None:
-            a, y = lat.young_force(*young)
-            if y.status == 0 and math.isfinite(y.force[0]) and math.isfinite(y.force[1]):
-                k = 0 if a.contact[0][0] > a.contact[1][0] else 1
-                forces.append(dict(step=int(a.step), force_a=float(y.force[k]), force_r=float(y.force[1 - k]),
-                                   theta_eq_a=float(y.theta_eq_deg[k]), theta_eq_r=float(y.theta_eq_deg[1 - k]),
-                                   phi_a=float(y.phi_d[k]), phi_r=float(y.phi_d[1 - k])))
         last = next((r for r in reversed(recs) if r["status"] == 0), None)
         if (done // chunk) % max(1, 50000 // chunk) == 0:
             log(f"rolling: step {done}, {time.perf_counter() - t0:.1f} s, "
@@ -138,7 +142,7 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--chunk", type=int, default=10000, help="steps between host checks (and Young-force samples)")
     ap.add_argument("--young", type=float, nargs=3, default=None, metavar=("GAMMA", "THETA1", "THETA2"),
-                    help="also the unbalanced Young force (Eq. 17-18) after every chunk of steps")
+                    help="also the unbalanced Young force (Eq. 17-18) at every measurement")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
