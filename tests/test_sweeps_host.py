@@ -38,3 +38,28 @@ def test_cap_angle_of_a_circular_drop():
         cls = np.where(np.hypot(xx - C[0], yy - C[1]) <= R, 1, 0).astype(np.uint8)
         cap = S.cap_angle(rho, cls, 0.5, C, R, contact)
         assert abs(cap - theta) < 0.5, (theta, cap)
+
+
+def test_sliding_drop_starts_tangent_to_the_plate():
+    # the drop of the sliding-drop run touches the arc from above at x0: its
+    # centre lies on the arc's normal, r0 beyond it
+    from paper_2202_06516_amd import rolling as RL
+    cx, cy, R, r0 = 1500.0, 1.5 + 100.0 - 6000.0, 6000.0, 100.0
+    for x0 in (600.0, 900.0, 1500.0, 2100.0):
+        px, py = RL.start_drop(cx, cy, R, x0, r0)
+        assert abs(math.hypot(px - cx, py - cy) - (R + r0)) < 1e-9
+        ys = cy + math.sqrt(R * R - (x0 - cx) ** 2)
+        assert abs(math.hypot(px - x0, py - ys) - r0) < 1e-9
+
+
+def test_bump_geometry():
+    # a bump of radius R rising H above the floor at y = 1.5 has the width
+    # L = 2 sqrt(2 R H - H^2) there, and the drop sits tangent on its top
+    from paper_2202_06516_amd import workloads as W
+    cs = W.bump_case(700, 400, 150.0, 100.0, 40.0, 0.04)
+    (cx, cy), R = cs["solid"]["center"], cs["solid"]["radius"]
+    assert abs(cy + R - (1.5 + 100.0)) < 1e-12
+    half = math.sqrt(R * R - (1.5 - cy) ** 2)
+    assert abs(2 * half - 2 * math.sqrt(2 * 150.0 * 100.0 - 100.0 ** 2)) < 1e-9
+    (dx, dy), r0 = cs["drop"]
+    assert dx == cx and abs(dy - r0 - (cy + R)) < 1e-12
