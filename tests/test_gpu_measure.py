@@ -215,6 +215,9 @@ def test_young_force_in_step_matches_oracle():
     gp.set_young(None)
     with pytest.raises(G.LbmError):
         gp.young_series()
+    for kw in (dict(roughness=0.0), dict(band=(0.5, 0.4)), dict(band=(0.0, 1.0))):
+        with pytest.raises(G.LbmError):
+            gp.set_young(0.06, 80.0, 120.0, **kw)
 
 
 def test_batch_in_step_young_force_equals_single():

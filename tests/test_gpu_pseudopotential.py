@@ -53,7 +53,7 @@ def test_sc_d2q9_f64_small(collision, bc):
     assert np.allclose(psi[o.cls == 1], 1.0 - math.exp(-0.8), rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("precision,tol", [(G.LBM_F64, 1e-12), (G.LBM_F32, 1e-6)])
+@pytest.mark.parametrize("precision,tol", [(G.LBM_F64, 1e-12), (G.LBM_F32_MIXED, 2e-7), (G.LBM_F32, 1e-6)])
 def test_sc_d3q19_small(precision, tol):
     wl = small_sc_3d()
     gp = gpu_lattice(wl, precision, "bgk")
