@@ -1129,6 +1129,28 @@ __global__ void k_cast_pad(const float* __restrict__ x, bf16* __restrict__ y, i6
     }
 }
 
+// one FP32 -> BF16 weight copy of the batched cast below: rows x Ci into rows x Cp,
+// elements [start, start + rows Cp) of the concatenated index space
+struct CastJob {
+    const float* x;
+    bf16* y;
+    i64 rows, start;
+    int Ci, Cp;
+};
+
+// every BF16 weight copy in one launch (after each Adam step): element i of the
+// concatenated index space belongs to the last job that starts at or before it
+__global__ void k_cast_pad_all(const CastJob* __restrict__ jobs, int njobs, i64 total) {
+    GRID_STRIDE(i, total) {
+        int j = 0;
+        while (j + 1 < njobs && jobs[j + 1].start <= i) ++j;
+        const CastJob J = jobs[j];
+        const i64 k = i - J.start, r = k / J.Cp;
+        const int c = (int)(k - r * J.Cp);
+        J.y[k] = (bf16)(c < J.Ci ? J.x[r * J.Ci + c] : 0.f);
+    }
+}
+
 __global__ void k_fill_f32(float* __restrict__ p, i64 n, float v) {
     GRID_STRIDE(i, n) { p[i] = v; }
 }
@@ -1304,6 +1326,9 @@ struct lbm_unet {
     float* upb = nullptr;   // transposed-convolution bias partials [4 Co]
     float* sphi = nullptr;  // smoothed phi of lbm_unet_warm_rho [H W]
     double *lpart = nullptr, *loss = nullptr, *winfo = nullptr;
+    CastJob* casts = nullptr;  // the BF16 weight copies, one launch (built on first use)
+    int ncasts = 0;
+    i64 cast_total = 0;
     i64 step = 0;
 };
 
@@ -1327,6 +1352,31 @@ Grid grid_of(const lbm_unet* u, int l) { return make_grid(u->nb, u->H >> l, u->W
 i64 pixels(const lbm_unet* u, int l) { return (i64)u->nb * (u->H >> l) * (u->W >> l); }
 
 void refresh_bf16(lbm_unet* u) {
+    if (!u->casts) {
+        std::vector<CastJob> jobs;
+        i64 start = 0;
+        auto add = [&](const float* x, bf16* y, i64 rows, int Ci, int Cp) {
+            jobs.push_back(CastJob{x, y, rows, start, Ci, Cp});
+            start += rows * Cp;
+        };
+        for (auto* layers : {&u->enc, &u->dec})
+            for (auto& c : *layers) add(u->w + c.w.off, c.wb, (i64)c.Co * 9, c.Ci1 + c.Ci2, c.Cp);
+        for (auto& p : u->up) add(u->w + p.w.off, p.wb, 4LL * p.Co, p.Ci, p.Ci);
+        if (hipMalloc((void**)&u->casts, jobs.size() * sizeof(CastJob)) == hipSuccess &&
+            hipMemcpy(u->casts, jobs.data(), jobs.size() * sizeof(CastJob), hipMemcpyHostToDevice) == hipSuccess) {
+            u->ncasts = (int)jobs.size();
+            u->cast_total = start;
+        } else {
+            if (u->casts) (void)hipFree(u->casts);
+            u->casts = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    if (u->casts) {
+        k_cast_pad_all<<<blocks_for(u->cast_total), 256, 0, u->stream>>>(u->casts, u->ncasts, u->cast_total);
+        return;
+    }
+    // one launch per layer if the job table could not be allocated
     for (auto* layers : {&u->enc, &u->dec})
         for (auto& c : *layers) {
             const i64 rows = (i64)c.Co * 9;
@@ -1538,7 +1588,8 @@ lbm_status lbm_unet_destroy(lbm_unet* u) {
         }
     for (auto p : u->arg) fr(p);
     for (void* p : {(void*)u->w, (void*)u->g, (void*)u->m, (void*)u->v, (void*)u->x0, (void*)u->y, (void*)u->dy,
-                    (void*)u->part, (void*)u->hpart, (void*)u->upb, (void*)u->lpart, (void*)u->loss, (void*)u->winfo, (void*)u->sphi})
+                    (void*)u->part, (void*)u->hpart, (void*)u->upb, (void*)u->lpart, (void*)u->loss, (void*)u->winfo, (void*)u->sphi,
+                    (void*)u->casts})
         fr(p);
     if (u->own_stream && u->stream) (void)hipStreamDestroy(u->stream);
     delete u;
