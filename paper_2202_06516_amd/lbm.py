@@ -352,7 +352,7 @@ class Lattice:
                            float(band[1]))
         self._check(lib().lbm_set_young(self._h, C.byref(o)))
 
-    def young_series(self, cap=4096):
+    def young_series(self, cap=256):
         """Young-force records of the last step call that wrote an angle series."""
         arr = (lbm_young * max(cap, 1))()
         n = C.c_int()

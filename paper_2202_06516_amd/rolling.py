@@ -72,7 +72,7 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
         n = min(chunk, steps - done)
         series = lat.step(n, measure_every=every, cap=n // every + 1)
         if young is not None:
-            for a, y in zip(series, lat.young_series()):
+            for a, y in zip(series, lat.young_series(cap=max(1, len(series)))):
                 if a.status == 0 and y.status == 0 and math.isfinite(y.force[0]) and math.isfinite(y.force[1]):
                     k = 0 if a.contact[0][0] > a.contact[1][0] else 1
                     forces.append(dict(step=int(a.step), force_a=float(y.force[k]), force_r=float(y.force[1 - k]),
