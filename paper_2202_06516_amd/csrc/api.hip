@@ -686,6 +686,7 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
     }
     c->have_geometry = true;
     c->have_state = false;
+    c->series_written = 0;
     if (!c->solids.empty() && c->mopts.solid_index >= (int)c->solids.size()) c->mopts.solid_index = 0;
     return LBM_OK;
 }
@@ -753,6 +754,7 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->fstar = false;
         c->have_state = true;
+        c->series_written = 0;
         return LBM_OK;
     }
     if (field == LBM_FIELD_F) {
@@ -762,6 +764,7 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->fstar = false;
         c->have_state = true;
+        c->series_written = 0;
         return LBM_OK;
     }
     return fail(c, LBM_E_ARG, "write: field must be RHO or F");
@@ -796,16 +799,19 @@ lbm_status lbm_set_young(lbm_ctx* c, const lbm_young_opts* yo) {
         return fail(c, LBM_E_ARG, "set_young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
-    c->young_on = yo != nullptr;
+    // off until both buffers are allocated and cleared: the step launches the
+    // in-step kernels only when it is on
+    c->young_on = false;
+    c->series_written = 0;  // records of earlier options are not returned
     if (!yo) return LBM_OK;
     c->yopts = *yo;
-    if (!c->ylast) {
-        lbm_status s = dalloc(c, &c->ylast, sizeof(YoungRec));
-        if (!s) s = dalloc(c, &c->ystep_counts, 2 * LBM_MAX_SECTORS * sizeof(unsigned));
-        if (s) return s;
-    }
+    lbm_status s = LBM_OK;
+    if (!c->ylast) s = dalloc(c, &c->ylast, sizeof(YoungRec));
+    if (!s && !c->ystep_counts) s = dalloc(c, &c->ystep_counts, 2 * LBM_MAX_SECTORS * sizeof(unsigned));
+    if (s) return s;
     // the counts start at zero; every in-step measurement clears them after use
     HIPCHK(c, hipMemset(c->ystep_counts, 0, 2 * LBM_MAX_SECTORS * sizeof(unsigned)));
+    c->young_on = true;
     return LBM_OK;
 }
 

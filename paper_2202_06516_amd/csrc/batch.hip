@@ -1073,17 +1073,23 @@ lbm_status lbm_batch_set_young(lbm_batch* b, const lbm_young_opts* yo) {
         return bfail(b, LBM_E_ARG, "batch set_young: gamma finite, roughness > 0, 0 < band_lo < band_hi < 1");
     BCHK(b, hipStreamSynchronize(b->stream));
     drop_graph(b);
-    b->young_on = yo != nullptr;
+    // off until every buffer below is allocated and initialised: the step
+    // graphs launch the in-step kernels only when it is on
+    b->young_on = false;
     if (!yo) return LBM_OK;
     b->yopts = *yo;
     const int n = b->ncases;
     const size_t cbytes = (size_t)n * 2 * LBM_MAX_SECTORS * sizeof(unsigned);
-    if (!b->ylast) {
-        if (hipMalloc((void**)&b->ystep_params, (size_t)n * sizeof(YoungParams)) != hipSuccess ||
-            hipMalloc((void**)&b->ystep_counts, cbytes) != hipSuccess ||
-            hipMalloc((void**)&b->ylast, (size_t)n * sizeof(YoungRec)) != hipSuccess)
-            return bfail(b, LBM_E_NOMEM, "batch set_young: device allocation failed");
-    }
+    auto get = [&](void** p, size_t bytes) {
+        if (*p) return true;
+        if (hipMalloc(p, bytes) == hipSuccess) return true;
+        *p = nullptr;
+        (void)hipGetLastError();
+        return false;
+    };
+    if (!get((void**)&b->ystep_params, (size_t)n * sizeof(YoungParams)) || !get((void**)&b->ystep_counts, cbytes) ||
+        !get((void**)&b->ylast, (size_t)n * sizeof(YoungRec)))
+        return bfail(b, LBM_E_NOMEM, "batch set_young: device allocation failed");
     // static counting parameters per case; the drop axis comes from each measurement
     double lo, hi;
     young_band(*yo, lo, hi);
@@ -1103,6 +1109,7 @@ lbm_status lbm_batch_set_young(lbm_batch* b, const lbm_young_opts* yo) {
         for (int k = 0; k < LBM_MAX_SECTORS; ++k) r.phi_d[k] = r.theta_eq_deg[k] = r.force[k] = NAN;
     }
     BCHK(b, hipMemcpy(b->ylast, empty.data(), empty.size() * sizeof(YoungRec), hipMemcpyHostToDevice));
+    b->young_on = true;
     return LBM_OK;
 }
 

@@ -698,19 +698,30 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
     const C uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + vy * vy + vz * vz;
 
     const long long sN = N;   // post-collision populations stay at the node (aligned stores)
+    // With FP32 arithmetic the lattice weights are rounded (1/3, 1/18 and 1/36
+    // in binary32 sum to 1 + 1.5e-8), so every collision would add that share
+    // of the density to the node: a systematic drift of 1.5e-8 per step.  The
+    // collision conserves mass exactly (Eq. 1: the density moment is not
+    // relaxed and the forcing term has no mass), so the rest population takes
+    // the remainder rho - sum_{i>0} f*_i of the stored values, in double.
+    constexpr bool kRestRemainder = sizeof(C) == 4;
+    double srest = 0.0;
     if (!MRT) {
         // BGK (Eq. 3) + exact-difference forcing (Eq. 13), one direction at a time
         const C om = cp.omega;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
+        for (int i = kRestRemainder ? 1 : 0; i < L::Q; ++i) {
             const C eu = C(L::E[i][0]) * ux + C(L::E[i][1]) * uy + C(L::E[i][2]) * uz;
             const C ev = C(L::E[i][0]) * vx + C(L::E[i][1]) * vy + C(L::E[i][2]) * vz;
             const C wr = rs * C(L::w(i));
             const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
             const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
             const C fi = (C)S[i];
-            put<NT>(&o[(size_t)i * sN], (R)(fi - om * (fi - feq) + (feq2 - feq)));
+            const R v = (R)(fi - om * (fi - feq) + (feq2 - feq));
+            if (kRestRemainder) srest += (double)v;
+            put<NT>(&o[(size_t)i * sN], v);
         }
+        if (kRestRemainder) put<NT>(&o[0], (R)(rd - srest));
     } else {
         // MRT (Eq. 1): non-conserved moments of f - f_eq relaxed by s_k and
         // mapped back with M^T D^-1, plus the forcing term
@@ -742,7 +753,12 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
             }
         }
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) put<NT>(&o[(size_t)i * sN], (R)out[i]);
+        for (int i = kRestRemainder ? 1 : 0; i < L::Q; ++i) {
+            const R v = (R)out[i];
+            if (kRestRemainder) srest += (double)v;
+            put<NT>(&o[(size_t)i * sN], v);
+        }
+        if (kRestRemainder) put<NT>(&o[0], (R)(rd - srest));
     }
 }
 

