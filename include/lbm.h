@@ -301,7 +301,38 @@ lbm_status lbm_young_series(lbm_ctx* ctx, lbm_young* out, int cap, int* n_writte
 lbm_status lbm_profile_step(lbm_ctx* ctx, int64_t nsteps, const char** names, double* ms,
                             int cap, int* n_kinds);
 
+/* The message of the last error on ctx; with ctx NULL, that of the last call
+ * without a context (lbm_measure_field) on this thread. */
 const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Contact angle of a density field the caller holds, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It is lbm_measure_angle without a context:
+ * the same kernels (liquid centroid, crossing search, finalising block) run on
+ * rho and cls as given, and the one record is written to out in device memory.
+ * The call allocates nothing and does not synchronise: it enqueues five small
+ * launches on stream (NULL: the null stream) and returns.
+ *   rho  device, [N] of the element type of precision (FP32 for LBM_F32 and
+ *        LBM_F32_MIXED, FP64 for LBM_F64), x fastest; only fluid nodes are read
+ *        as densities;
+ *   cls  device, [N] uint8 classes as lbm_read(LBM_FIELD_CLASS) writes them
+ *        (0 fluid; bits 0-1 are read);
+ *   solid  the substrate measured (host);  n_sectors  3-D: 1..64 (2-D: 2 sides);
+ *   rho_m  the isodensity level, > 0;  g  body acceleration for the advancing /
+ *        receding sectors (host, nullable = none);
+ *   out  device, one lbm_angle; out->step is 0.
+ * Scratch: the reduction slots live in a static device array of 2 KiB that
+ * each GPU holds for the life of the process; the call clears them before use.
+ * Calls on one GPU share it, so calls whose work overlaps in time on one GPU
+ * (different streams without ordering) race: order them.  Limits, rejected
+ * with LBM_E_ARG before anything is enqueued: n_sectors above 64 (the slots
+ * hold 64 sectors), N * Q >= 2^32 (32-bit link ids), n outside 5..2^20 per
+ * axis, n[2] != 1 for D2Q9, rho_m not positive, a bad primitive, a null
+ * pointer.  LBM_E_DEVICE if no device is current or a launch fails.  The
+ * message is lbm_last_error(NULL). */
+lbm_status lbm_measure_field(int lattice, int precision, const int n[3], const void* rho, const uint8_t* cls,
+                             const lbm_solid* solid, int n_sectors, double rho_m, const double g[3], lbm_angle* out,
+                             void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched solver: many independent lattices advanced together.

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,48 @@ namespace {
 
 constexpr int kGraphSteps = 32;  // steps per captured graph (even: buffer parity is preserved)
 constexpr int kMassBlocks = 1024;
+
+// Device memory of lbm_measure_field, the entry point that allocates nothing:
+// the control word and reduction slots (centroid sums, per-sector keys) of one
+// measurement.  Each GPU holds its own copy for the life of the process.  In
+// host code the name stands for no device address: kernels and copies get the
+// address hipGetSymbolAddress returns for the current device (scratch_ptr).
+constexpr size_t kScratchBytes = 2048;
+static_assert(sizeof(DevCtl) <= kScratchBytes, "the measurement's slots must fit the static scratch");
+static_assert(sizeof(AngleRec) == sizeof(lbm_angle), "AngleRec is written where lbm_angle is read");
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+thread_local std::string g_free_err;  // last error of a call without a context (lbm_last_error(NULL))
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// address of this device's scratch, looked up once per device
+lbm_status scratch_ptr(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        g_free_err = "measure_field: no current HIP device";
+        return LBM_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            g_free_err = std::string("measure_field: hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return LBM_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
 
 }  // namespace
 
@@ -126,6 +169,32 @@ lbm_status check_measure_opts(lbm_ctx* c, const lbm_measure_opts& o) {
     if (c->dim == 3 && (o.n_sectors < 1 || o.n_sectors > LBM_MAX_SECTORS))
         return fail(c, LBM_E_ARG, "measure: n_sectors must lie in 1..64");
     return LBM_OK;
+}
+
+// Tile shape and launch counts of a lattice whose nx, ny, nz are set.
+void tile_dims(Dims& d, int dim) {
+    {
+        // tile width: the widest of 256, 128, 64 nodes that the row fills (wide rows
+        // straddle fewer cache lines in the x-shifted gathers); LBM_TILE_W overrides
+        const char* e = std::getenv("LBM_TILE_W");
+        const int tw = e ? std::atoi(e) : (d.nx >= 256 ? 256 : d.nx >= 128 ? 128 : 64);
+        d.tws = tw == 256 ? 8 : tw == 128 ? 7 : 6;
+    }
+    d.tx = (d.nx + (1 << d.tws) - 1) >> d.tws;
+    d.ty = (d.ny + (256 >> d.tws) - 1) / (256 >> d.tws);
+    d.nblocks = (unsigned)d.tx * (unsigned)d.ty * (unsigned)d.nz;
+    {
+        // planes per workgroup of the chemical-potential kernel (3-D): 8 took it from 0.080 to 0.067 ms
+        // at 256^3; LBM_ZCHUNK overrides
+        const char* e = std::getenv("LBM_ZCHUNK");
+        const int zc = dim == 3 ? (e ? std::atoi(e) : 8) : 1;
+        d.zc = zc < 1 ? 1 : zc;
+        d.nblocks_zc = (unsigned)d.tx * (unsigned)d.ty * (unsigned)((d.nz + d.zc - 1) / d.zc);
+    }
+    {
+        const char* e = std::getenv("LBM_XCD_REMAP");
+        d.xcd_remap = e ? std::atoi(e) != 0 : 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -405,6 +474,21 @@ struct OpMass {
     static void go(lbm_ctx* c) { Run<L, R, C>::mass(c); }
 };
 
+// the measurement of lbm_measure_field on a caller's density field; the
+// slots live in the static scratch at ctl
+template <class L, typename R, typename C>
+struct OpMeasureField {
+    static void go(const Dims& d, const void* rho, const uint8_t* cls, DevCtl* ctl, const MeasureParams& mp,
+                   AngleRec* out, hipStream_t st) {
+        const R* r = (const R*)rho;
+        k_ctl_set<<<1, 64, 0, st>>>(ctl, 0, 0, 1, 0, 1);
+        k_ctl_reset<<<1, 64, 0, st>>>(ctl, 0, 1, 0);
+        k_centroid<L, R><<<d.nblocks, 256, 0, st>>>(r, cls, d, mp.rho_m, &ctl->m);
+        k_cross<L, R><<<d.nblocks < 2048u ? d.nblocks : 2048u, 256, 0, st>>>(r, cls, d, ctl, mp);
+        k_finalize<L, R><<<1, 64, 0, st>>>(r, ctl, d, mp, nullptr, out, 0);
+    }
+};
+
 // copy a host double array into a device array of the context precision
 lbm_status upload_real(lbm_ctx* c, void** dst, const std::vector<double>& v) {
     lbm_status s = dalloc(c, (char**)dst, v.size() * c->elem);
@@ -478,7 +562,10 @@ void lbm_config_default(lbm_config* cfg, int lattice) {
     cfg->sc_G = -6.0;
 }
 
-const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* lbm_last_error(const lbm_ctx* ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_free_err.empty() ? "null context" : g_free_err.c_str();
+}
 
 lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (!out) return LBM_E_ARG;
@@ -522,28 +609,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->d.nz = c->dim == 3 ? cfg->n[2] : 1;
     c->d.N = N;
     c->d.off = 0;
-    {
-        // tile width: the widest of 256, 128, 64 nodes that the row fills (wide rows
-        // straddle fewer cache lines in the x-shifted gathers); LBM_TILE_W overrides
-        const char* e = std::getenv("LBM_TILE_W");
-        const int tw = e ? std::atoi(e) : (c->d.nx >= 256 ? 256 : c->d.nx >= 128 ? 128 : 64);
-        c->d.tws = tw == 256 ? 8 : tw == 128 ? 7 : 6;
-    }
-    c->d.tx = (c->d.nx + (1 << c->d.tws) - 1) >> c->d.tws;
-    c->d.ty = (c->d.ny + (256 >> c->d.tws) - 1) / (256 >> c->d.tws);
-    c->d.nblocks = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)c->d.nz;
-    {
-        // planes per workgroup of the chemical-potential kernel (3-D): 8 took it from 0.080 to 0.067 ms
-        // at 256^3; LBM_ZCHUNK overrides
-        const char* e = std::getenv("LBM_ZCHUNK");
-        const int zc = c->dim == 3 ? (e ? std::atoi(e) : 8) : 1;
-        c->d.zc = zc < 1 ? 1 : zc;
-        c->d.nblocks_zc = (unsigned)c->d.tx * (unsigned)c->d.ty * (unsigned)((c->d.nz + c->d.zc - 1) / c->d.zc);
-    }
-    {
-        const char* e = std::getenv("LBM_XCD_REMAP");
-        c->d.xcd_remap = e ? std::atoi(e) != 0 : 1;
-    }
+    tile_dims(c->d, c->dim);
     c->pr.a = cfg->pr_a;
     c->pr.b = cfg->pr_b;
     c->pr.R = cfg->pr_R;
@@ -1080,6 +1146,68 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
     }
     *n_kinds = n;
     return check_status(c);
+}
+
+lbm_status lbm_measure_field(int lattice, int precision, const int n[3], const void* rho, const uint8_t* cls,
+                             const lbm_solid* solid, int n_sectors, double rho_m, const double g[3], lbm_angle* out,
+                             void* stream) {
+    auto bad = [](const char* m) {
+        g_free_err = std::string("measure_field: ") + m;
+        return LBM_E_ARG;
+    };
+    g_free_err.clear();
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return bad("lattice must be LBM_D2Q9 or LBM_D3Q19");
+    if (precision != LBM_F32 && precision != LBM_F64 && precision != LBM_F32_MIXED) return bad("precision");
+    if (!n || !rho || !cls || !solid || !out) return bad("null pointer");
+    const int dim = lattice == LBM_D2Q9 ? 2 : 3, Q = dim == 2 ? 9 : 19;
+    if (dim == 2 && n[2] != 1) return bad("n[2] must be 1 for D2Q9");
+    for (int k = 0; k < dim; ++k)
+        if (n[k] < 5 || n[k] > (1 << 20)) return bad("n out of range (5 .. 2^20 per axis)");
+    const long long N = (long long)n[0] * n[1] * (dim == 3 ? n[2] : 1);
+    if ((unsigned long long)N * (unsigned long long)Q >= (1ull << 32))
+        return bad("N * Q must stay below 2^32 (32-bit link ids of the selection keys)");
+    if (dim == 3 && (n_sectors < 1 || n_sectors > LBM_MAX_SECTORS))
+        return bad("n_sectors must lie in 1..64 (the static slots hold 64 sectors)");
+    if (!(rho_m > 0) || !std::isfinite(rho_m)) return bad("rho_m must be positive and finite");
+    if ((solid->kind != LBM_SOLID_SPHERE && solid->kind != LBM_SOLID_CAVITY) || !(solid->radius > 0))
+        return bad("bad solid primitive");
+    void* sp = nullptr;
+    lbm_status s = scratch_ptr(&sp);
+    if (s != LBM_OK) return s;
+    Dims d{};
+    d.nx = n[0];
+    d.px = n[0];
+    d.ny = n[1];
+    d.nz = dim == 3 ? n[2] : 1;
+    d.N = N;
+    d.off = 0;
+    tile_dims(d, dim);
+    MeasureParams mp{};
+    for (int k = 0; k < 3; ++k) {
+        mp.c[k] = k < dim ? solid->center[k] : 0.0;
+        mp.g[k] = g && k < dim ? g[k] : 0.0;
+    }
+    mp.R = solid->radius;
+    mp.concave = solid->kind == LBM_SOLID_CAVITY;
+    mp.rho_m = rho_m;
+    mp.n_sectors = dim == 2 ? 2 : n_sectors;
+    mp.dim = dim;
+    const hipStream_t st = (hipStream_t)stream;
+    DevCtl* ctl = (DevCtl*)sp;
+    AngleRec* rec = (AngleRec*)out;
+    if (dim == 2) {
+        if (precision == LBM_F64) OpMeasureField<D2Q9, double, double>::go(d, rho, cls, ctl, mp, rec, st);
+        else OpMeasureField<D2Q9, float, float>::go(d, rho, cls, ctl, mp, rec, st);
+    } else {
+        if (precision == LBM_F64) OpMeasureField<D3Q19, double, double>::go(d, rho, cls, ctl, mp, rec, st);
+        else OpMeasureField<D3Q19, float, float>::go(d, rho, cls, ctl, mp, rec, st);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_free_err = std::string("measure_field: launch: ") + hipGetErrorString(e);
+        return LBM_E_DEVICE;
+    }
+    return LBM_OK;
 }
 
 }  // extern "C"

@@ -297,9 +297,10 @@ __device__ __forceinline__ bool density_node(const R* __restrict__ f, R* __restr
     double s = 0.0;  // summed in double, as the collision's own moments are
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) s += (double)S[i];
-    rho[idx] = (R)s;
+    const R rs = (R)s;
+    rho[idx] = rs;
     if (!(s > 0.0 && s < (double)inv_b)) atomicOr(status, 1);  // also catches NaN
-    return s >= rho_m;
+    return (double)rs >= rho_m;  // the stored value, as the crossing search sees it
 }
 
 // block reduction (256 threads, 4 waves) of the liquid centroid sums
@@ -331,6 +332,21 @@ __global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __r
     const bool liquid = density_node<L, R, C, PULL>(f, rho, cls, d, bc, x, y, z, x < d.nx && y < d.ny, rho_m, inv_b,
                                                     &ctl->status);
     if (measuring(ctl)) centroid_reduce(liquid, x, y, z, &ctl->m);
+}
+
+// liquid centroid sums of a density field given as such (fluid nodes with
+// rho >= rho_m), the sums k_density forms on measure steps
+template <class L, typename R>
+__global__ void __launch_bounds__(256) k_centroid(const R* __restrict__ rho, const uint8_t* __restrict__ cls, Dims d,
+                                                  double rho_m, MeasureSlots* __restrict__ ms) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    bool liquid = false;
+    if (x < d.nx && y < d.ny) {
+        const long long idx = nid(d, x, y, z);
+        liquid = (cls[idx] & CLS_MASK) == CLS_FLUID && (double)rho[idx] >= rho_m;
+    }
+    centroid_reduce(liquid, x, y, z, ms);
 }
 
 // state S_t of every node (zero on solid nodes) into out

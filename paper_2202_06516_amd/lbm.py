@@ -127,7 +127,7 @@ _lib = None
 EXPORTS = ("lbm_config_default", "lbm_create", "lbm_destroy", "lbm_set_solid", "lbm_init_drops",
            "lbm_step", "lbm_set_measure", "lbm_measure_angle", "lbm_read", "lbm_write", "lbm_sync",
            "lbm_get_info", "lbm_profile_step", "lbm_young_force", "lbm_set_young", "lbm_young_series",
-           "lbm_last_error", "lbm_batch_create",
+           "lbm_last_error", "lbm_measure_field", "lbm_batch_create",
            "lbm_batch_destroy",
            "lbm_batch_step", "lbm_batch_sync", "lbm_batch_angles", "lbm_batch_measure", "lbm_batch_young_force",
            "lbm_batch_set_young", "lbm_batch_young_last",
@@ -174,6 +174,8 @@ def lib():
     L.lbm_profile_step.argtypes = [vp, i64, P(C.c_char_p), P(d), i, P(i)]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_last_error.argtypes = [vp]
+    L.lbm_measure_field.argtypes = [i, i, P(i), vp, vp, P(lbm_solid), i, d, P(d), vp, vp]
+    L.lbm_measure_field.restype = C.c_int
     L.lbm_batch_create.argtypes = [P(lbm_config), P(lbm_case), i, P(lbm_batch_opts), P(vp)]
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_step.argtypes = [vp, i64, i]
@@ -226,6 +228,22 @@ def lib():
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
+
+
+def measure_field(lattice, precision, n, rho_ptr, cls_ptr, solid, n_sectors, rho_m, out_ptr, g=None, stream=None):
+    """lbm_measure_field: the contact angle of a device density field into the device buffer at out_ptr
+    (one lbm_angle); enqueues on stream and returns without synchronising."""
+    nn = (C.c_int * 3)(*(list(n) + [1] * (3 - len(n))))
+    sd = lbm_solid()
+    _fill_solid(sd, solid)
+    gg = None
+    if g is not None:
+        gg = (C.c_double * 3)(*(list(g) + [0.0] * (3 - len(g))))
+    st = lib().lbm_measure_field(int(lattice), int(precision), nn, C.c_void_p(rho_ptr), C.c_void_p(cls_ptr),
+                                 C.byref(sd), int(n_sectors), float(rho_m), gg, C.c_void_p(out_ptr),
+                                 C.c_void_p(stream) if stream else None)
+    if st != 0:
+        raise LbmError(st, lib().lbm_last_error(None).decode())
 
 
 def config_default(lattice: int) -> lbm_config:
