@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per k_collide launch from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000) counters,
 # scaled by a plain-copy calibration; valid only for the kernel as it stands when they were taken
 # (profiles/k_collide_d3q19_f32_256cube.md).  Keyed by (lattice side, precision, collision).
-COUNTED_TRAFFIC = {(256, "f32", "bgk"): 3.301e9}
+COUNTED_TRAFFIC = {}
 # the same for kb_collide of the batched solver on the seeded table (profiles/kb_collide_batch_d2q9_512cases.md),
 # keyed by (number of cases, precision)
 BATCH_COUNTED_TRAFFIC = {(512, "f32"): 4.271e9}
@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="lattice side (256 = the benchmark workload)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f32mixed", "f64"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
+    ap.add_argument("--step-kernel", default="auto", choices=["auto", "split"],
+                    help="auto: the one-pass step where the lattice allows it; split: density pass + collision")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps at full size (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -100,7 +102,8 @@ def main():
     stream = torch.cuda.Stream()
     lat = G.Lattice(G.LBM_D3Q19, n=wl["n"], precision=prec, axis_bc=(1, 1, 1), stream=stream.cuda_stream,
                     collision=G.LBM_BGK if args.collision == "bgk" else G.LBM_MRT, bc_mode=G.LBM_BC_HALFWAY,
-                    tau=1.0, Tr=wl["Tr"], k=0.28, kappa=0.01)
+                    tau=1.0, Tr=wl["Tr"], k=0.28, kappa=0.01,
+                    step_kernel=G.LBM_STEP_AUTO if args.step_kernel == "auto" else G.LBM_STEP_SPLIT)
     lat.set_solids(wl["solids"])
     lat.init_drops(wl["drops"], W=10.0)
     lat.set_measure(0, wl["n_sectors"])
@@ -120,8 +123,11 @@ def main():
     # per-kernel mean durations (HIP events around each launch on the context stream)
     prof = lat.profile(args.profile_steps)
     Q = 19
-    coll_bytes = n_fluid * (2 * Q * elem + 2 * elem + 1)   # populations in+out, rho and mu, class byte
-    coll_ms = prof["k_collide"]
+    # dominant kernel: the one-pass step k_step, or the split path's k_collide; algorithmic bytes per fluid
+    # node = each population read once and written once (2 Q P)
+    kern = "k_step" if "k_step" in prof else "k_collide"
+    coll_bytes = n_fluid * 2 * Q * elem
+    coll_ms = prof[kern]
     achieved = coll_bytes / (coll_ms * 1e-3) / 1e9
     step_alg_bytes = 2 * Q * 4 * n_fluid                   # 152 B per fluid-node update (FP32)
 
@@ -143,9 +149,9 @@ def main():
                                f"angle every {wl['every']} steps over {wl['n_sectors']} sectors",
                    "lattice": [args.n] * 3, "fluid_nodes": n_fluid, "precision": args.precision,
                    "collision": args.collision},
-        "roofline": {"bound": "hbm", "kernel": "k_collide", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": COUNTED_TRAFFIC.get((args.n, args.precision, args.collision)),
+                     "traffic": COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision)),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
         "step_efficiency": {"algorithmic_bytes_per_update": 2 * Q * 4,
                             "achieved_GBs": round(step_alg_bytes / (ms_step * 1e-3) / 1e9, 1),

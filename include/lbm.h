@@ -82,6 +82,7 @@ enum { LBM_BC_HALFWAY = 0, LBM_BC_BOUZIDI_MC = 1 };
  * and both solid layers carry psi(rho_w).  Its coexistence densities depend on
  * the forcing scheme, so rho_l and rho_g must be given. */
 enum { LBM_MODEL_CHEMICAL_POTENTIAL = 0, LBM_MODEL_PSEUDOPOTENTIAL = 1 };
+enum { LBM_STEP_AUTO = 0, LBM_STEP_SPLIT = 1 };
 
 #define LBM_MAX_SECTORS 64
 #define LBM_MAX_SOLIDS 16
@@ -112,6 +113,12 @@ typedef struct {
                              pseudopotential model needs rho_l > rho_g > 0 and ignores Tr, pr_*, k, kappa
                              (the batched solver takes either model for all its cases) */
     double sc_G;          /* pseudopotential interaction strength G (default -6) */
+    int step_kernel;      /* LBM_STEP_AUTO (default): D3Q19 lattices with halfway bounce-back walls, nx a
+                             multiple of 64 (at most 1024), ny a multiple of 4 and nz even take one pass over
+                             the populations per step (the
+                             collision also sums the next step's density); LBM_STEP_SPLIT: a density pass,
+                             then the collision.  Both compute the same step; the density sums differ in
+                             order, so the fields agree to rounding. */
 } lbm_config;
 
 /* Fill *cfg with the library defaults for the given lattice. */

@@ -12,6 +12,7 @@
 #include "lbm.h"
 #include "host.hpp"
 #include "kernels.hpp"
+#include "fused.hpp"
 #include "young.hpp"
 
 using namespace lbm;
@@ -19,6 +20,7 @@ using namespace lbm;
 namespace {
 
 constexpr int kGraphSteps = 32;  // steps per captured graph (even: buffer parity is preserved)
+constexpr int kFusedTY = 4;      // rows per workgroup of the one-pass step
 constexpr int kMassBlocks = 1024;
 
 // Device memory of lbm_measure_field, the entry point that allocates nothing:
@@ -80,7 +82,15 @@ struct lbm_ctx {
     void* f[2] = {nullptr, nullptr};
     int cur = 0;        // populations of the current state are in f[cur]
     bool fstar = false;  // f[cur] holds post-collision populations (pull form), else S_t
-    void *rho = nullptr, *mu = nullptr;
+    void *rho = nullptr, *mu = nullptr;  // rho: the current density buffer, rhob[rcur]
+    void* rhob[2] = {nullptr, nullptr};  // the one-pass step writes rho_{t+1} into the other one
+    int rcur = 0;
+    void *gy = nullptr, *gz = nullptr, *gyz = nullptr;  // its ghost sums
+    void* force = nullptr;   // [3][N] force of the current state, read by the one-pass step
+    void* sink = nullptr;    // [19][1024] slots the one-pass step's lanes without a fluid node read and write
+    bool fused = false;      // the one-pass step k_step (D3Q19 lattices of whole-row tiles)
+    int fzc = 0;             // planes per k_step workgroup
+    bool rho_valid = false;  // rho (fluid + solid layers) and mu hold the fields of the current state
     uint8_t* cls = nullptr;
     uint32_t* nbmask = nullptr;
     int* bidx = nullptr;
@@ -236,7 +246,7 @@ struct Run {
             }
             cp.rate[k] = (C)(s / row_norm2<L>(k));
         }
-        for (int k = 0; k < 3; ++k) cp.g[k] = (C)(k < c->dim ? g.g[k] : 0.0);
+        for (int k = 0; k < 3; ++k) cp.g[k] = k < c->dim ? g.g[k] : 0.0;
         cp.g_start = g.g_start_step;
         cp.sc_G = g.sc_G;
         return cp;
@@ -263,8 +273,8 @@ struct Run {
         else
             k_density<L, R, C, false><<<grd, blk, 0, c->stream>>>(f, (R*)c->rho, c->cls, c->d, wall(c), c->ctl, rho_m, inv_b);
     }
-    static void fills(lbm_ctx* c, hipEvent_t* ev, int* kinds, int& k) {
-        R* rho = (R*)c->rho;
+    static void fills(lbm_ctx* c, hipEvent_t* ev, int* kinds, int& k) { fills_on(c, (R*)c->rho, ev, kinds, k); }
+    static void fills_on(lbm_ctx* c, R* rho, hipEvent_t* ev, int* kinds, int& k) {
         if (c->n_l1) {
             if (ev) (void)hipEventRecord(ev[2 * k], c->stream);
             k_fill<L, R, C><<<(c->n_l1 + 255) / 256, 256, 0, c->stream>>>(c->l1_node, c->l1_mask, (const R*)c->l1_inv,
@@ -365,6 +375,105 @@ struct Run {
         if (kinds) kinds[k] = -1;
     }
 
+    // One step on the one-pass path, reading f[src] and rhob[rsrc] (rho_t, with
+    // mu_t in mu) and writing f[1-src] and rhob[1-rsrc] (rho_{t+1}, mu_{t+1}).
+    template <bool PULL, bool MRT, bool SC>
+    static void launch_step(lbm_ctx* c, const R* fin, R* fout, const R* rho, R* rnext, const WallBC& bc,
+                            const Collision<C>& cp) {
+        const dim3 grd((unsigned)((c->d.ny / kFusedTY) * (c->d.nz / c->fzc)), 1, 1), blk((unsigned)c->d.nx, 1, 1);
+        // workgroup = one row of nx threads; the launch bound follows it
+        if (c->d.nx <= 256)
+            k_step<R, C, PULL, MRT, SC, kFusedTY, 256><<<grd, blk, 0, c->stream>>>(
+                fin, fout, rho, (const R*)c->mu, (const R*)c->force, rnext, (R*)c->gy, (R*)c->gz, (R*)c->gyz, c->cls,
+                c->d, bc, cp, c->ctl, c->fzc, (R*)c->sink);
+        else
+            k_step<R, C, PULL, MRT, SC, kFusedTY, 1024><<<grd, blk, 0, c->stream>>>(
+                fin, fout, rho, (const R*)c->mu, (const R*)c->force, rnext, (R*)c->gy, (R*)c->gz, (R*)c->gyz, c->cls,
+                c->d, bc, cp, c->ctl, c->fzc, (R*)c->sink);
+    }
+    // the force of the current state (rho, mu) into c->force
+    static void launch_force(lbm_ctx* c, const R* rho) {
+        const dim3 blk(256, 1, 1);
+        if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
+            k_force<L, R, C, true><<<zgrid(c), blk, 0, c->stream>>>(rho, (const R*)c->mu, c->cls, c->d, collision(c),
+                                                                    c->ctl, (R*)c->force);
+        else
+            k_force<L, R, C, false><<<zgrid(c), blk, 0, c->stream>>>(rho, (const R*)c->mu, c->cls, c->d, collision(c),
+                                                                     c->ctl, (R*)c->force);
+    }
+    static void fused_step_launches(lbm_ctx* c, int src, bool pull, int rsrc, const MeasureParams& mp, hipEvent_t* ev,
+                                    int* kinds) {
+        if constexpr (L::D == 3) {
+            const dim3 blk(256, 1, 1);
+            const R* fin = (const R*)c->f[src];
+            R* fout = (R*)c->f[1 - src];
+            R* rho = (R*)c->rhob[rsrc];
+            R* rnext = (R*)c->rhob[1 - rsrc];
+            int k = 0;
+            auto start = [&]() { if (ev) (void)hipEventRecord(ev[2 * k], c->stream); };
+            auto mark = [&](int kind) { if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = kind; } };
+            start();
+            k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, c->ctl, mp);
+            YoungStep ys{};
+            if (c->young_on) {
+                ys = young_step(c, mp);
+                k_young_step<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, young_step_params(c, mp),
+                                                                        mp, c->ctl, c->ystep_counts);
+            }
+            mark(5);
+            start();
+            const WallBC bc = wall(c);
+            const Collision<C> cp = collision(c);
+            const bool mrt = c->cfg.collision == LBM_MRT, sc = c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL;
+            if (sc) {
+                if (pull) { if (mrt) launch_step<true, true, true>(c, fin, fout, rho, rnext, bc, cp);
+                            else launch_step<true, false, true>(c, fin, fout, rho, rnext, bc, cp); }
+                else { if (mrt) launch_step<false, true, true>(c, fin, fout, rho, rnext, bc, cp);
+                       else launch_step<false, false, true>(c, fin, fout, rho, rnext, bc, cp); }
+            } else {
+                if (pull) { if (mrt) launch_step<true, true, false>(c, fin, fout, rho, rnext, bc, cp);
+                            else launch_step<true, false, false>(c, fin, fout, rho, rnext, bc, cp); }
+                else { if (mrt) launch_step<false, true, false>(c, fin, fout, rho, rnext, bc, cp);
+                       else launch_step<false, false, false>(c, fin, fout, rho, rnext, bc, cp); }
+            }
+            mark(7);
+            start();
+            k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1, ys, c->yseries);
+            mark(6);
+            start();
+            {
+                const int ein = 2 * (c->d.ny / kFusedTY);
+                const long long rows = (long long)(c->d.nz / c->fzc) * (2LL * c->d.ny + (long long)(c->fzc - 2) * ein);
+                k_ghost<R, kFusedTY><<<(unsigned)rows, (unsigned)c->d.nx, 0, c->stream>>>(rnext, (const R*)c->gy, (const R*)c->gz,
+                                                                            (const R*)c->gyz, c->d, c->fzc);
+            }
+            mark(8);
+            fills_on(c, rnext, ev, kinds, k);
+            start();
+            const R inv_b = (R)(1.0 / c->pr.b);
+            if (sc)
+                k_mu_step<L, R, C, true><<<zgrid(c), blk, 0, c->stream>>>(rnext, (R*)c->mu, c->cls, c->d, thermo(c),
+                                                                         c->ctl, mp.rho_m, inv_b, (R*)c->sink);
+            else
+                k_mu_step<L, R, C, false><<<zgrid(c), blk, 0, c->stream>>>(rnext, (R*)c->mu, c->cls, c->d, thermo(c),
+                                                                          c->ctl, mp.rho_m, inv_b, (R*)c->sink);
+            mark(3);
+            if (sc) {
+                // the pseudopotential force for the next step (k_step forms Eq. 7 itself)
+                start();
+                launch_force(c, rnext);
+                mark(9);
+            }
+            if (kinds) kinds[k] = -1;
+        }
+    }
+
+    // liquid centroid sums of the current density (a measurement of step t
+    // whose density the previous one-pass step already completed)
+    static void centroid(lbm_ctx* c, double rho_m) {
+        k_centroid<L, R><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, rho_m, &c->ctl->m);
+    }
+
     // S_t of the current state into f[1 - cur] (free between steps)
     static R* materialize(lbm_ctx* c) {
         R* out = (R*)c->f[1 - c->cur];
@@ -377,6 +486,8 @@ struct Run {
 
     // density, solid fill and mu of the current state (no measurement)
     static void derive(lbm_ctx* c, bool with_mu) {
+        if (c->fused && c->rho_valid) return;  // the one-pass step keeps them current
+        if (c->fused) with_mu = true;
         MeasureParams mp{};
         mp.rho_m = c->rho_m;
         mp.n_sectors = 2;
@@ -385,6 +496,11 @@ struct Run {
         int k = 0;
         fills(c, nullptr, nullptr, k);
         if (with_mu) launch_mu(c, (R*)c->rho, (R*)c->mu);
+        if (c->fused) {
+            if constexpr (L::D == 3)
+                if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL) launch_force(c, (const R*)c->rho);
+            c->rho_valid = true;
+        }
     }
 
     static void velocity(lbm_ctx* c, void* out) {
@@ -399,10 +515,19 @@ struct Run {
     }
 
     static void measure_now(lbm_ctx* c, const MeasureParams& mp) {
-        density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
-        int k = 0;
-        fills(c, nullptr, nullptr, k);
-        launch_mu(c, (R*)c->rho, (R*)c->mu);
+        if (c->fused && c->rho_valid) {
+            centroid(c, mp.rho_m);
+        } else {
+            density(c, (const R*)c->f[c->cur], c->fstar, mp.rho_m);
+            int k = 0;
+            fills(c, nullptr, nullptr, k);
+            launch_mu(c, (R*)c->rho, (R*)c->mu);
+            if (c->fused) {
+                if constexpr (L::D == 3)
+                    if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL) launch_force(c, (const R*)c->rho);
+                c->rho_valid = true;
+            }
+        }
         k_cross<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, c->ctl, mp);
         k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->rho, c->ctl, c->d, mp, nullptr, c->last, 0);
     }
@@ -444,6 +569,16 @@ struct OpStep {
     static void go(lbm_ctx* c, int src, bool pull, const MeasureParams* mp, hipEvent_t* ev, int* kinds) {
         Run<L, R, C>::step_launches(c, src, pull, *mp, ev, kinds);
     }
+};
+template <class L, typename R, typename C>
+struct OpFusedStep {
+    static void go(lbm_ctx* c, int src, bool pull, int rsrc, const MeasureParams* mp, hipEvent_t* ev, int* kinds) {
+        Run<L, R, C>::fused_step_launches(c, src, pull, rsrc, *mp, ev, kinds);
+    }
+};
+template <class L, typename R, typename C>
+struct OpCentroid {
+    static void go(lbm_ctx* c, double rho_m) { Run<L, R, C>::centroid(c, rho_m); }
 };
 template <class L, typename R, typename C>
 struct OpDerive {
@@ -560,6 +695,7 @@ void lbm_config_default(lbm_config* cfg, int lattice) {
     cfg->stream = nullptr;
     cfg->model = LBM_MODEL_CHEMICAL_POTENTIAL;
     cfg->sc_G = -6.0;
+    cfg->step_kernel = LBM_STEP_AUTO;
 }
 
 const char* lbm_last_error(const lbm_ctx* ctx) {
@@ -610,6 +746,19 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     c->d.N = N;
     c->d.off = 0;
     tile_dims(c->d, c->dim);
+    if (cfg->step_kernel != LBM_STEP_AUTO && cfg->step_kernel != LBM_STEP_SPLIT) return bad("step_kernel");
+    {
+        // the one-pass step: D3Q19 with halfway bounce-back walls, whole rows of
+        // 64..1024 nodes per workgroup, 4 rows, zc planes (LBM_FUSED_ZC overrides 2: at 256^3
+        // the walk over 2, 4, 8, 16 planes took 0.79, 0.82, 0.87, 0.89 ms; the ghost sums
+        // 0.098, 0.067, 0.053, 0.046 ms)
+        const char* e = std::getenv("LBM_FUSED_ZC");
+        int zc = e ? std::atoi(e) : 2;
+        while (zc > 2 && c->d.nz % zc) zc >>= 1;
+        c->fzc = zc;
+        c->fused = cfg->step_kernel == LBM_STEP_AUTO && c->dim == 3 && cfg->bc_mode == LBM_BC_HALFWAY &&
+                   c->d.nx % 64 == 0 && c->d.nx <= 1024 && c->d.ny % kFusedTY == 0 && zc >= 2 && c->d.nz % zc == 0;
+    }
     c->pr.a = cfg->pr_a;
     c->pr.b = cfg->pr_b;
     c->pr.R = cfg->pr_R;
@@ -640,7 +789,11 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     }
     const size_t fbytes = (size_t)c->Q * N * c->elem;
     if ((s = dalloc(c, (char**)&c->f[0], fbytes)) || (s = dalloc(c, (char**)&c->f[1], fbytes)) ||
-        (s = dalloc(c, (char**)&c->rho, N * c->elem)) || (s = dalloc(c, (char**)&c->mu, N * c->elem)) ||
+        (s = dalloc(c, (char**)&c->rhob[0], N * c->elem)) || (s = dalloc(c, (char**)&c->mu, N * c->elem)) ||
+        (c->fused && ((s = dalloc(c, (char**)&c->rhob[1], N * c->elem)) || (s = dalloc(c, (char**)&c->gy, N * c->elem)) ||
+                      (s = dalloc(c, (char**)&c->gz, N * c->elem)) || (s = dalloc(c, (char**)&c->gyz, N * c->elem)) ||
+                      (s = dalloc(c, (char**)&c->force, 3 * N * c->elem)) ||
+                      (s = dalloc(c, (char**)&c->sink, 19 * 1024 * c->elem)))) ||
         (s = dalloc(c, &c->cls, (size_t)N)) || (s = dalloc(c, &c->nbmask, (size_t)N * 4)) ||
         (s = dalloc(c, &c->bidx, (size_t)N * 4)) ||
         (s = dalloc(c, &c->ctl, sizeof(DevCtl))) || (s = dalloc(c, &c->last, sizeof(AngleRec))) ||
@@ -649,6 +802,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         lbm_destroy(c);
         return s;
     }
+    c->rho = c->rhob[0];
     DevCtl h{};
     for (auto& k : h.m.keys) k[0] = k[1] = ~0ull;
     if (hipMemcpy(c->ctl, &h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
@@ -668,7 +822,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    void* ps[] = {c->f[0], c->f[1], c->rho, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
+    void* ps[] = {c->f[0], c->f[1], c->rhob[0], c->rhob[1], c->gy, c->gz, c->gyz, c->force, c->sink, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
                   c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
                   c->mass_part, c->mass_out, c->young_counts, c->ylast, c->yseries, c->ystep_counts};
     for (void* p : ps) dfree(p);
@@ -748,7 +902,11 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
             HIPCHK(c, hipMemcpy(c->mu, t.data(), g.N * 4, hipMemcpyHostToDevice));
         }
         std::vector<char> zero((size_t)g.N * c->elem, 0);
-        HIPCHK(c, hipMemcpy(c->rho, zero.data(), zero.size(), hipMemcpyHostToDevice));
+        for (void* rb : c->rhob)
+            if (rb) HIPCHK(c, hipMemcpy(rb, zero.data(), zero.size(), hipMemcpyHostToDevice));
+        c->rcur = 0;
+        c->rho = c->rhob[0];
+        c->rho_valid = false;
     }
     c->have_geometry = true;
     c->have_state = false;
@@ -805,6 +963,7 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
         if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "write RHO: bytes must be N * elem");
         // stream-ordered: a device-to-device copy may otherwise still be in
         // flight when the kernels below (or the caller's next writes to src) run
+        c->rho_valid = false;
         HIPCHK(c, hipMemcpyAsync(c->rho, src, bytes, kind, c->stream));
         // zero both population buffers, then f = f_eq(rho, 0)
         const size_t fb = (size_t)c->Q * N * c->elem;
@@ -826,6 +985,7 @@ lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int s
     if (field == LBM_FIELD_F) {
         const size_t fb = (size_t)c->Q * N * c->elem;
         if (bytes != fb) return fail(c, LBM_E_ARG, "write F: bytes must be Q * N * elem");
+        c->rho_valid = false;
         HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src, bytes, kind, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->fstar = false;
@@ -922,22 +1082,40 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
     lbm_status s = ctl_reset(c, measure_every, 0, series ? cap : 0);
     if (s) return s;
     int64_t done = 0;
-    auto eager = [&]() {
-        dispatch<OpStep>(c, c->cur, c->fstar, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+    const bool fused = c->fused;
+    if (fused) {
+        // the one-pass step needs rho_t (with the solid layers) and mu_t, and on
+        // a measure step the liquid centroid sums of rho_t
+        if (!c->rho_valid) dispatch<OpDerive>(c, true);
+        else if (measure_every > 0 && c->t % measure_every == 0) dispatch<OpCentroid>(c, mp.rho_m);
+    }
+    auto launch_one = [&](int src, bool pull, int rsrc) {
+        if (fused) dispatch<OpFusedStep>(c, src, pull, rsrc, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+        else dispatch<OpStep>(c, src, pull, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+    };
+    auto advance = [&]() {
         c->cur ^= 1;
         c->fstar = true;
+        if (fused) {
+            c->rcur ^= 1;
+            c->rho = c->rhob[c->rcur];
+        }
+    };
+    auto eager = [&]() {
+        launch_one(c->cur, c->fstar, c->rcur);
+        advance();
         ++done;
         ++c->t;
     };
-    // eager steps until the populations are in pull form in buffer 0, then
-    // whole captured graphs (an even number of steps keeps the parity), then the rest
-    while (done < nsteps && (!c->fstar || c->cur != 0 || nsteps - done < kGraphSteps)) eager();
+    // eager steps until the populations are in pull form in buffer 0 (and the
+    // density in buffer 0), then whole captured graphs (an even number of
+    // steps keeps the parity), then the rest
+    while (done < nsteps && (!c->fstar || c->cur != 0 || c->rcur != 0 || nsteps - done < kGraphSteps)) eager();
     if (nsteps - done >= kGraphSteps) {
         if (!c->graph[0]) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < kGraphSteps; ++k)
-                dispatch<OpStep>(c, k & 1, true, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+            for (int k = 0; k < kGraphSteps; ++k) launch_one(k & 1, true, k & 1);
             HIPCHK(c, hipStreamEndCapture(c->stream, &g));
             hipError_t e = hipGraphInstantiate(&c->graph[0], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -1108,8 +1286,8 @@ lbm_status lbm_get_info(lbm_ctx* c, lbm_info* info) {
 }
 
 lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, double* ms, int cap, int* n_kinds) {
-    static const char* kNames[7] = {"k_density", "k_fill_layer1", "k_fill_layer2", "k_mu",
-                                    "k_collide", "k_cross",       "k_finalize"};
+    static const char* kNames[10] = {"k_density", "k_fill_layer1", "k_fill_layer2", "k_mu", "k_collide",
+                                     "k_cross",   "k_finalize",    "k_step",        "k_ghost", "k_force"};
     if (!c || !names || !ms || !n_kinds) return LBM_E_ARG;
     if (!c->have_state) return fail(c, LBM_E_STATE, "profile: no state");
     if (nsteps < 1) return fail(c, LBM_E_ARG, "profile: nsteps >= 1");
@@ -1118,13 +1296,20 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
     else { mp.rho_m = c->rho_m; mp.n_sectors = 2; mp.dim = c->dim; }
     lbm_status s = ctl_reset(c, 0, 0, 0);
     if (s) return s;
+    if (c->fused && !c->rho_valid) dispatch<OpDerive>(c, true);
     hipEvent_t ev[16];
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
-    double tot[7] = {0, 0, 0, 0, 0, 0, 0};
-    int cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    double tot[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t t = 0; t < nsteps; ++t) {
-        int kinds[9];
-        dispatch<OpStep>(c, c->cur, c->fstar, &mp, ev, kinds);
+        int kinds[10];
+        if (c->fused) {
+            dispatch<OpFusedStep>(c, c->cur, c->fstar, c->rcur, &mp, ev, kinds);
+            c->rcur ^= 1;
+            c->rho = c->rhob[c->rcur];
+        } else {
+            dispatch<OpStep>(c, c->cur, c->fstar, &mp, ev, kinds);
+        }
         c->cur ^= 1;
         c->fstar = true;
         ++c->t;
@@ -1138,7 +1323,7 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     int n = 0;
-    for (int k = 0; k < 7 && n < cap; ++k) {
+    for (int k = 0; k < 10 && n < cap; ++k) {
         if (!cnt[k]) continue;
         names[n] = kNames[k];
         ms[n] = tot[k] / cnt[k];

@@ -368,7 +368,7 @@ struct BRun {
             }
             cp.rate[k] = (C)(s / row_norm2<L>(k));
         }
-        for (int k = 0; k < 3; ++k) cp.g[k] = (C)(k < b->dim ? g.g[k] : 0.0);
+        for (int k = 0; k < 3; ++k) cp.g[k] = k < b->dim ? g.g[k] : 0.0;
         cp.g_start = g.g_start_step;
         cp.sc_G = b->cfg.sc_G;
         return cp;

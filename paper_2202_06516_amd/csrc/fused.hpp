@@ -1,0 +1,471 @@
+// fused.hpp -- one time step of a D3Q19 lattice as a single pass over the
+// populations.
+//
+// The split step reads every population twice: once to sum the density of
+// S_t, once more to collide.  k_step reads them once.  For step t it does what
+// k_collide does -- gathers S_t (pull streaming, Eq. 4, with the wall
+// condition), takes the force of Eq. 7 from rho_t and mu_t, collides (Eq. 1-3,
+// 13) and stores f*_t -- and in the same pass sums the density of step t+1
+// (under the pseudopotential model the force comes from k_force, which formed
+// it after the previous step):
+//
+//     rho_{t+1}(x) = sum over i of f*_i(x - e_i) where x - e_i is fluid,
+//                  + f*_j(x) for every link j from x to a solid node,
+//
+// the second term being the populations the wall returns to x.  With the
+// exact mass correction of the interpolated wall (Sec. III A) the density is
+// the same as with halfway bounce-back, so the sum holds for both wall modes.
+// Its summation order is not that of the split path's density pass, so the two
+// paths agree to rounding, not bit for bit.
+//
+// Work decomposition.  A workgroup owns whole rows: thread = x (nx threads, nx
+// a multiple of 64), TY consecutive rows in y, and it walks zc consecutive
+// planes in z.  A node's moving populations go to the nine rows (y + e_y,
+// z + e_z); within a row the x shift is a one-lane move across the wave (DPP),
+// and between the waves of a row it goes through LDS once per plane.  Each
+// thread keeps the partial densities of its column for the rows y0-1..y0+TY
+// and the planes z-1, z, z+1 (in LDS); a target plane is complete, and
+// stored, once the walk has passed the source plane above it.  Partial sums
+// for rows and planes owned by other workgroups go to three ghost arrays, each
+// entry with exactly one writer (the y neighbour, the z neighbour, the
+// diagonal one; TY >= 2 and zc >= 2 guarantee it), and k_ghost adds them to
+// the edge rows and planes after the launch.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+// index of the D3Q19 direction (ex, ey, ez)
+__host__ __device__ constexpr int d3q19_dir(int ex, int ey, int ez) {
+    int k = -1;
+    for (int i = 0; i < D3Q19::Q; ++i)
+        if (D3Q19::E[i][0] == ex && D3Q19::E[i][1] == ey && D3Q19::E[i][2] == ez) k = i;
+    return k;
+}
+
+// lane l receives the value of lane l - 1 of its wave (lane 0 receives 0)
+template <typename T>
+__device__ __forceinline__ T lane_from_below(T v) {
+    return __builtin_amdgcn_update_dpp(T(0), v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+// lane l receives the value of lane l + 1 of its wave (lane 63 receives 0)
+template <typename T>
+__device__ __forceinline__ T lane_from_above(T v) {
+    return __builtin_amdgcn_update_dpp(T(0), v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+
+// workgroup id -> tile, with contiguous tile ranges per XCD (as tile_node)
+__device__ __forceinline__ unsigned xcd_tile(unsigned t, unsigned n, int remap) {
+    if (!remap) return t;
+    const unsigned q = n >> 3, r = n & 7u, xcd = t & 7u, loc = t >> 3;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
+}
+
+// Directions by target row.  The rows (e_y, e_z) = (0,0), (+1,0), (-1,0),
+// (0,+1), (0,-1) each receive three directions, with e_x = 0, +1, -1
+// (GRP[g][0..2]); the four diagonal rows (+1,+1), (-1,-1), (+1,-1), (-1,+1)
+// one each, with e_x = 0.
+struct RowGroups {
+    static constexpr int GRP[5][3] = {
+        {d3q19_dir(0, 0, 0), d3q19_dir(1, 0, 0), d3q19_dir(-1, 0, 0)},
+        {d3q19_dir(0, 1, 0), d3q19_dir(1, 1, 0), d3q19_dir(-1, 1, 0)},
+        {d3q19_dir(0, -1, 0), d3q19_dir(1, -1, 0), d3q19_dir(-1, -1, 0)},
+        {d3q19_dir(0, 0, 1), d3q19_dir(1, 0, 1), d3q19_dir(-1, 0, 1)},
+        {d3q19_dir(0, 0, -1), d3q19_dir(1, 0, -1), d3q19_dir(-1, 0, -1)}};
+    static constexpr int PP = d3q19_dir(0, 1, 1), MM = d3q19_dir(0, -1, -1);
+    static constexpr int PM = d3q19_dir(0, 1, -1), MP = d3q19_dir(0, -1, 1);
+};
+static_assert(RowGroups::GRP[0][0] == 0 && RowGroups::PP > 0 && RowGroups::MM > 0 && RowGroups::PM > 0 &&
+                  RowGroups::MP > 0, "D3Q19 direction table");
+
+// Barrier for the LDS exchange between the waves of a workgroup: waits for
+// this wave's LDS operations only.  (__syncthreads also waits for every
+// outstanding global load and store, which would drain the walk's pipeline.)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Populations S_t of node idx for the walk's pipeline: every load is issued,
+// unconditionally and without waiting for an earlier one.  A link whose
+// source x - e_i is solid (bit opp(i) of the node's wall mask m) reads the
+// population that left x toward the wall (halfway bounce-back).  A lane with
+// no fluid node (live = false) reads its slots of the sink instead.
+template <class L, typename R, bool PULL>
+__device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims& d, long long idx, int x, int y,
+                                             int z, uint32_t m, bool live, const R* __restrict__ sink, R S[L::Q]) {
+    const uint32_t ix = (uint32_t)idx, dx = (uint32_t)x;
+    if (!PULL) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) S[i] = live ? at(f + (size_t)i * d.N, ix) : at(sink + i * 1024, dx);
+        return;
+    }
+    const int ox[3] = {x >= 1 ? -1 : d.nx - 1, 0, x + 1 < d.nx ? 1 : 1 - d.nx};
+    const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.px, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.px};
+    const int sz = d.px * d.ny;
+    const int oz[3] = {(z >= 1 ? -1 : d.nz - 1) * sz, 0, (z + 1 < d.nz ? 1 : 1 - d.nz) * sz};
+    S[0] = live ? at(f, ix) : at(sink, dx);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int j = L::OPP[i];
+        const uint32_t pull = ix + (uint32_t)(ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]);
+        const bool back = (m >> j) & 1u;
+        // one select of base and offset: the population that left x toward the
+        // wall, the pulled one, or the sink
+        const R* base = !live ? sink + i * 1024 : back ? f + (size_t)j * d.N : f + (size_t)i * d.N;
+        S[i] = at(base, !live ? dx : back ? ix : pull);
+    }
+}
+
+template <typename R, typename C, bool PULL, bool MRT, bool SC, int TY, int NX>
+__global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __restrict__ fout,
+                                             const R* __restrict__ rho, const R* __restrict__ mu,
+                                             const R* __restrict__ force, R* __restrict__ rho_next,
+                                             R* __restrict__ gy, R* __restrict__ gz, R* __restrict__ gyz,
+                                             const uint8_t* __restrict__ cls, Dims d, WallBC bc, Collision<C> cp,
+                                             const DevCtl* __restrict__ ctl, int zc, R* __restrict__ sink) {
+    typedef D3Q19 L;
+    static_assert(TY >= 2, "one writer per ghost entry needs two rows or more");
+    const unsigned t = xcd_tile(blockIdx.x, gridDim.x, d.xcd_remap);
+    const Dims d0 = d;
+    const int x0 = threadIdx.x;
+    const int nty = d.ny / TY;
+    const int y0 = (int)(t % (unsigned)nty) * TY, z0 = (int)(t / (unsigned)nty) * zc;
+    const int x = threadIdx.x, lane = x & 63, wave = x >> 6, nw = d.nx >> 6;
+    const int ylo = y0 >= 1 ? y0 - 1 : d.ny - 1, yhi = y0 + TY < d.ny ? y0 + TY : 0;
+    const int nn = TY * zc;  // nodes of this thread's column in the tile; node n is row n % TY of plane z0 + n / TY
+    const long long tstep = ctl->t;
+
+    // Partial densities of the tile's rows y0-1..y0+TY (index row - y0 + 1)
+    // for three target planes, slot z mod 3; thread x owns column x, so its
+    // additions need no synchronisation.  They live in LDS rather than in
+    // registers, which keeps the walk at the register count of one node.
+    __shared__ C acc[TY + 2][3][NX];
+    // [plane parity][0: e_x = +1 values of lane 63, 1: e_x = -1 values of lane 0][wave][row][row group]
+    __shared__ C edge[2][2][NX / 64][TY][5];
+#pragma unroll
+    for (int k = 0; k < TY + 2; ++k) acc[k][0][x] = acc[k][1][x] = acc[k][2][x] = C(0);
+
+    // The walk is a software pipeline over the column's nodes: while node n is
+    // collided, the populations and force of node n+1, the wall mask of node
+    // n+2 and the class of node n+3 are in flight.  A wave's loads and stores
+    // share one in-order counter, so loads issued after node n's stores would
+    // also wait for them; issued before, they do not.  For the compiler to
+    // count them, every load and store of the walk is unconditional: lanes
+    // without a fluid node (and the walk's overrun past its last node) read
+    // and write their own slots of a small sink buffer, [19][1024] values,
+    // which nothing else reads.  (Only halfway bounce-back walls take this
+    // kernel: the interpolated wall's loads depend on one another.)
+    // The lattice sizes and the thread's x pass through an empty asm per
+    // node, so that what is derived from them (population and stencil
+    // offsets) is recomputed instead of held across the walk; held, it spilled
+    // the scalar registers and doubled the vector ones.  (The pointers stay
+    // untouched: through the asm they would lose their address space.)
+    auto fresh = [&](Dims& dd, int& xx) {
+        dd = d0;
+        xx = x0;
+        asm volatile("" : "+s"(dd.N), "+s"(dd.px), "+s"(dd.nx), "+s"(dd.ny), "+s"(dd.nz), "+s"(dd.off));
+        asm volatile("" : "+v"(xx));
+    };
+    auto node_of = [&](int n, int& y, int& z) {
+        z = z0 + n / TY;
+        y = y0 + n % TY;
+    };
+    // the class of node n (past the last node: of the last one, unused)
+    auto load_cls = [&](int n) -> uint8_t {
+        Dims dd;
+        int xx, y, z;
+        fresh(dd, xx);
+        node_of(n < nn ? n : nn - 1, y, z);
+        return at(cls, (uint32_t)nid(dd, xx, y, z));
+    };
+    // the wall mask of a boundary fluid node, else a shared dummy read
+    auto load_mask = [&](int n, uint8_t c) -> uint32_t {
+        Dims dd;
+        int xx, y, z;
+        fresh(dd, xx);
+        node_of(n < nn ? n : nn - 1, y, z);
+        const bool b = n < nn && (c & CLS_BOUNDARY) && (c & CLS_MASK) == CLS_FLUID;
+        const uint32_t m = at(bc.nbmask, b ? (uint32_t)nid(dd, xx, y, z) : 0u);
+        return b ? m : 0u;
+    };
+    // the force: under the chemical-potential model from the rho and mu
+    // stencils (Eq. 7), loaded with the populations; under the pseudopotential
+    // model from the array k_force filled
+    ForceStencil<L, R> Gc, Gb;
+    auto issue = [&](int n, uint8_t c, uint32_t m, R S[L::Q], R F[3], ForceStencil<L, R>& G) {
+        Dims dd;
+        int xx, y, z;
+        fresh(dd, xx);
+        node_of(n < nn ? n : nn - 1, y, z);
+        const bool live = n < nn && (c & CLS_MASK) == CLS_FLUID;
+        const long long idx = nid(dd, xx, y, z);
+        const uint32_t ix = (uint32_t)idx, dx = (uint32_t)xx;
+        if constexpr (SC) {
+            F[0] = live ? at(force, ix) : at(sink, dx);
+            F[1] = live ? at(force + dd.N, ix) : at(sink + 1024, dx);
+            F[2] = live ? at(force + 2 * dd.N, ix) : at(sink + 2048, dx);
+        } else {
+            force_stencil_load<L, R, false>(rho, mu, dd, xx, y, z, G);  // every offset in bounds: unconditional
+        }
+        gather_issue<L, R, PULL>(fin, dd, idx, xx, y, z, m, live, sink, S);
+    };
+
+    uint8_t c0 = load_cls(0), c1 = load_cls(1), c2 = load_cls(2);
+    uint32_t m0 = load_mask(0, c0), m1 = load_mask(1, c1);
+    R Sc[L::Q], Fc[3];
+    issue(0, c0, m0, Sc, Fc, Gc);
+
+#pragma unroll 1
+    for (int n = 0; n < nn; ++n) {
+        // stages ahead: class of n+3, wall mask of n+2, populations of n+1
+        const uint8_t c3 = load_cls(n + 3);
+        const uint32_t m2 = load_mask(n + 2, c2);
+        R Sb[L::Q], Fb[3];
+        issue(n + 1, c1, m1, Sb, Fb, Gb);
+
+        // node n
+        Dims dd;
+        int xx, y, z;
+        fresh(dd, xx);
+        node_of(n, y, z);
+        const int r = n % TY, zz = n / TY, par = zz & 1;
+        const int sc = z % 3, sn = (z + 1) % 3, sp = (z + 2) % 3;  // slots of planes z, z + 1, z - 1
+        C v[L::Q];     // what leaves x toward fluid nodes; zero where it returns from a wall
+        C own = C(0);  // what the wall returns to x
+        {
+            const bool live = (c0 & CLS_MASK) == CLS_FLUID;
+            const long long idx = nid(dd, xx, y, z);
+            // the dead lanes' collision runs on sink values; its results go back
+            // to the sink and contribute nothing
+            R fo[L::Q];
+            double Fx, Fy, Fz;
+            if constexpr (SC) {
+                Fx = (double)Fc[0];
+                Fy = (double)Fc[1];
+                Fz = (double)Fc[2];
+            } else {
+                force_from_stencil<L, R, C, false>(Gc, cp, tstep, Fx, Fy, Fz);
+            }
+            collide_values<L, R, C, MRT>(Sc, Fx, Fy, Fz, cp, fo);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                put<true>(live ? &at(fout + (size_t)i * dd.N, (uint32_t)idx) : &at(sink + i * 1024, (uint32_t)xx), fo[i]);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const C fi = live ? (C)fo[i] : C(0);
+                const bool back = (m0 >> i) & 1u;
+                v[i] = back ? C(0) : fi;
+                own += back ? fi : C(0);
+            }
+        }
+        // row groups with their x shifts
+        C grp[5];
+#pragma unroll
+        for (int g = 0; g < 5; ++g) {
+            const C vp = v[RowGroups::GRP[g][1]], vm = v[RowGroups::GRP[g][2]];
+            grp[g] = v[RowGroups::GRP[g][0]] + lane_from_below(vp) + lane_from_above(vm);
+            if (lane == 63) edge[par][0][wave][r][g] = vp;
+            if (lane == 0) edge[par][1][wave][r][g] = vm;
+        }
+        acc[r + 1][sc][x0] += grp[0] + own;
+        acc[r + 2][sc][x0] += grp[1];
+        acc[r][sc][x0] += grp[2];
+        acc[r + 1][sn][x0] += grp[3];
+        acc[r + 1][sp][x0] += grp[4];
+        acc[r + 2][sn][x0] += v[RowGroups::PP];
+        acc[r][sp][x0] += v[RowGroups::MM];
+        acc[r + 2][sp][x0] += v[RowGroups::PM];
+        acc[r][sn][x0] += v[RowGroups::MP];
+
+        if (r == TY - 1) {
+            // the plane is done: x-moving populations across wave boundaries
+            // (periodic in x), then target plane z - 1 is complete
+            lds_barrier();
+            if (lane == 0 || lane == 63) {
+                const int side = lane == 0 ? 0 : 1;
+                const int w = lane == 0 ? (wave == 0 ? nw - 1 : wave - 1) : (wave + 1 == nw ? 0 : wave + 1);
+#pragma unroll
+                for (int rr = 0; rr < TY; ++rr) {
+                    const C* e = edge[par][side][w][rr];
+                    acc[rr + 1][sc][x0] += e[0];
+                    acc[rr + 2][sc][x0] += e[1];
+                    acc[rr][sc][x0] += e[2];
+                    acc[rr + 1][sn][x0] += e[3];
+                    acc[rr + 1][sp][x0] += e[4];
+                }
+            }
+            // inside the chunk plane z - 1 is stored; below the chunk (first
+            // plane) it is the z neighbour's; its slot is cleared for plane z + 2
+            C a[TY + 2];
+#pragma unroll
+            for (int k = 0; k < TY + 2; ++k) {
+                a[k] = acc[k][sp][x0];
+                acc[k][sp][x0] = C(0);
+            }
+            if (zz == 0) {
+                const int zg = z0 >= 1 ? z0 - 1 : dd.nz - 1;
+#pragma unroll
+                for (int rr = 0; rr < TY; ++rr) gz[nid(dd, xx, y0 + rr, zg)] = (R)a[rr + 1];
+                gyz[nid(dd, xx, ylo, zg)] = (R)a[0];
+                gyz[nid(dd, xx, yhi, zg)] = (R)a[TY + 1];
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < TY; ++rr) rho_next[nid(dd, xx, y0 + rr, z - 1)] = (R)a[rr + 1];
+                gy[nid(dd, xx, ylo, z - 1)] = (R)a[0];
+                gy[nid(dd, xx, yhi, z - 1)] = (R)a[TY + 1];
+            }
+        }
+
+        // advance the pipeline
+        c0 = c1;
+        c1 = c2;
+        c2 = c3;
+        m0 = m1;
+        m1 = m2;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) Sc[i] = Sb[i];
+        if constexpr (SC) {
+            Fc[0] = Fb[0];
+            Fc[1] = Fb[1];
+            Fc[2] = Fb[2];
+        } else {
+#pragma unroll
+            for (int k = 0; k < ForceStencil<L, R>::K; ++k) Gc.v[k] = Gb.v[k];
+        }
+    }
+    // the chunk's last plane, and the plane above the chunk (the z neighbour's)
+    const int zl = z0 + zc - 1, zg = z0 + zc < d.nz ? z0 + zc : 0;
+    const int sl = zl % 3, sg = (zl + 1) % 3;
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
+        rho_next[nid(d, x, y0 + r, zl)] = (R)acc[r + 1][sl][x];
+        gz[nid(d, x, y0 + r, zg)] = (R)acc[r + 1][sg][x];
+    }
+    gy[nid(d, x, ylo, zl)] = (R)acc[0][sl][x];
+    gy[nid(d, x, yhi, zl)] = (R)acc[TY + 1][sl][x];
+    gyz[nid(d, x, ylo, zg)] = (R)acc[0][sg][x];
+    gyz[nid(d, x, yhi, zg)] = (R)acc[TY + 1][sg][x];
+}
+
+// Adds the ghost sums to the edge rows (y % TY in {0, TY-1}) and edge planes
+// (z % zc in {0, zc-1}) of k_step's tiles.  Workgroup k takes row k of a list
+// of the edge rows only: per chunk of zc planes, its two edge planes whole,
+// then the 2 ny/TY edge rows of each plane between them.  (One row per
+// workgroup: a workgroup walking several rows would wait for each row's
+// stores before its next loads.)
+template <typename R, int TY>
+__global__ void __launch_bounds__(1024) k_ghost(R* __restrict__ rho, const R* __restrict__ gy,
+                                                const R* __restrict__ gz, const R* __restrict__ gyz, Dims d, int zc) {
+    const int ein = 2 * (d.ny / TY);
+    const long long per_chunk = 2LL * d.ny + (long long)(zc - 2) * ein;
+    const long long k = blockIdx.x;
+    const int x = threadIdx.x;
+    const int ch = (int)(k / per_chunk);
+    long long rem = k - (long long)ch * per_chunk;
+    int y, z;
+    if (rem < d.ny) {
+        z = ch * zc;
+        y = (int)rem;
+    } else if (rem < 2LL * d.ny) {
+        z = ch * zc + zc - 1;
+        y = (int)(rem - d.ny);
+    } else {
+        rem -= 2LL * d.ny;
+        z = ch * zc + 1 + (int)(rem / ein);
+        const int sr = (int)(rem % ein);
+        y = (sr >> 1) * TY + ((sr & 1) ? TY - 1 : 0);
+    }
+    const int ry = y % TY, rz = z % zc;
+    const bool ey = ry == 0 || ry == TY - 1, ez = rz == 0 || rz == zc - 1;
+    const long long n = nid(d, x, y, z);
+    double v = (double)rho[n];
+    if (ey) v += (double)gy[n];
+    if (ez) v += (double)gz[n];
+    if (ey && ez) v += (double)gyz[n];
+    rho[n] = (R)v;
+}
+
+// block reduction (256 threads) of per-thread liquid centroid sums
+__device__ __forceinline__ void centroid_reduce_sums(unsigned long long cnt, unsigned long long sx,
+                                                     unsigned long long sy, unsigned long long sz, MeasureSlots* ms) {
+    __shared__ unsigned long long red[4][4];
+    unsigned long long v[4] = {cnt, sx, sy, sz};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += __shfl_down(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (wave == 0 && lane < 4) {
+        const unsigned long long sum = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        if (sum) atomicAdd((&ms->cnt) + lane, sum);
+    }
+}
+
+// Chemical potential (Eq. 11-12; psi of the pseudopotential model) of the
+// density k_step and k_ghost completed, z-chunked as k_mu; besides, the check
+// of the density that the split path's density pass makes, and on measure
+// steps the liquid centroid sums of the measurement (Sec. III B).  Plane
+// z+1's density stencil is loaded before plane z's value is stored, and the
+// store is unconditional (solid nodes write a sink slot: their mu is the wall
+// value set with the solids), so that the loads do not wait for the stores.
+template <class L, typename R, typename C, bool SC>
+__global__ void __launch_bounds__(256) k_mu_step(const R* __restrict__ rho, R* __restrict__ mu,
+                                                 const uint8_t* __restrict__ cls, Dims d, Thermo th,
+                                                 DevCtl* __restrict__ ctl, double rho_m, R inv_b, R* __restrict__ sink) {
+    int x, y, z0;
+    tile_node_zc(d, x, y, z0);
+    const bool in = x < d.nx && y < d.ny;
+    const int xs = in ? x : 0, ys = in ? y : 0;
+    const int z1 = z0 + d.zc < d.nz ? z0 + d.zc : d.nz;
+    const Nbr ox = nbr_offsets(xs, d.nx, 1), oy = nbr_offsets(ys, d.ny, d.px);
+    // density stencil of one plane: centre, then -2, -1, +1, +2 along x, y, z; and the class
+    auto load = [&](int z, R v[13], uint8_t& c) {
+        const uint32_t ix = (uint32_t)nid(d, xs, ys, z);
+        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
+        auto p = [&](int o) { return at(rho, ix + (uint32_t)o); };
+        c = at(cls, ix);
+        v[0] = p(0);
+        v[1] = p(ox.m2); v[2] = p(ox.m1); v[3] = p(ox.p1); v[4] = p(ox.p2);
+        v[5] = p(oy.m2); v[6] = p(oy.m1); v[7] = p(oy.p1); v[8] = p(oy.p2);
+        v[9] = p(oz.m2); v[10] = p(oz.m1); v[11] = p(oz.p1); v[12] = p(oz.p2);
+    };
+    unsigned long long cnt = 0, sx = 0, sy = 0, sz = 0;
+    bool bad = false;
+    R cur[13], nxt[13];
+    uint8_t cc, cn;
+    load(z0, cur, cc);
+    for (int z = z0; z < z1; ++z) {
+        load(z + 1 < z1 ? z + 1 : z, nxt, cn);
+        const bool fl = in && (cc & CLS_MASK) == CLS_FLUID;
+        const C c0 = (C)cur[0];
+        C m;
+        if constexpr (SC) {
+            m = C(1) - exp(-c0);  // pseudopotential model: psi(rho) = 1 - exp(-rho)
+        } else {
+            C lap = d2c<C>((C)cur[1], (C)cur[2], c0, (C)cur[3], (C)cur[4]);
+            lap += d2c<C>((C)cur[5], (C)cur[6], c0, (C)cur[7], (C)cur[8]);
+            if (L::D == 3) lap += d2c<C>((C)cur[9], (C)cur[10], c0, (C)cur[11], (C)cur[12]);
+            m = (psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap;
+        }
+        at(fl ? mu : sink, fl ? (uint32_t)nid(d, xs, ys, z) : (threadIdx.x & 1023u)) = (R)m;
+        if (fl) {
+            const R r0 = cur[0];
+            bad = bad || !(r0 > R(0) && r0 < inv_b);  // also catches NaN
+            if ((double)r0 >= rho_m) {
+                cnt += 1;
+                sx += (unsigned long long)x;
+                sy += (unsigned long long)y;
+                sz += (unsigned long long)z;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 13; ++k) cur[k] = nxt[k];
+        cc = cn;
+    }
+    if (bad) atomicOr(&ctl->status, 1);
+    if (measuring(ctl)) centroid_reduce_sums(cnt, sx, sy, sz, &ctl->m);
+}
+
+}  // namespace lbm

@@ -111,7 +111,7 @@ struct Collision {
     int bgk;
     R omega;         // 1/tau for the BGK path
     R rate[19];      // MRT: s_k / |row_k|^2 per moment
-    R g[3];
+    double g[3];     // body acceleration (the force is formed in double)
     long long g_start;
     double sc_G;     // pseudopotential interaction strength
 };
@@ -158,6 +158,21 @@ __device__ __forceinline__ bool measuring(const DevCtl* ctl) {
 }
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Element k of an array, addressed as its base plus a 32-bit byte offset:
+// loads and stores then take the base from scalar registers and a single
+// 32-bit vector offset, instead of a 64-bit address formed per access in
+// vector registers.  Every array a kernel indexes this way is smaller than
+// 4 GiB (lbm_create and lbm_batch_create keep N * Q below 2^32 nodes, and one
+// population array holds N values).
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t k) {
+    return *(T*)((char*)base + k * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t k) {
+    return *(const T*)((const char*)base + k * (uint32_t)sizeof(T));
+}
 
 // Periodic neighbour offsets of coordinate v (0 <= v < n >= 2) along an axis
 // of the given stride: index differences to v - 2, v - 1, v + 1, v + 2.
@@ -230,9 +245,10 @@ struct WallBC {
 template <class L, typename R, typename C, bool PULL>
 __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, long long idx, int x, int y, int z,
                                        uint8_t c, const WallBC& bc, R S[L::Q]) {
+    const uint32_t ix = (uint32_t)idx;
     if (!PULL) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + idx];
+        for (int i = 0; i < L::Q; ++i) S[i] = at(f + (size_t)i * d.N, ix);
         return;
     }
     // index offsets of x - 1, x, x + 1 along each axis (periodic wrap)
@@ -241,24 +257,24 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
     const int sz = d.px * d.ny;
     const int oz[3] = {L::D == 3 ? (z >= 1 ? -1 : d.nz - 1) * sz : 0, 0, L::D == 3 ? (z + 1 < d.nz ? 1 : 1 - d.nz) * sz : 0};
     // source x - e_i
-#define LBM_SRC(i) (idx + (ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]))
+#define LBM_SRC(i) (ix + (uint32_t)(ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]))
     if (!(c & CLS_BOUNDARY)) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) S[i] = f[(size_t)i * d.N + (i ? LBM_SRC(i) : idx)];
+        for (int i = 0; i < L::Q; ++i) S[i] = at(f + (size_t)i * d.N, i ? LBM_SRC(i) : ix);
         return;
     }
     const uint32_t bm = bc.nbmask[idx];
     const int k = bc.bouzidi ? bc.bidx[idx] : 0;
     C dm = C(0);
-    S[0] = f[idx];
+    S[0] = at(f, ix);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int j = L::OPP[i];
         if (!(bm & (1u << j))) {
-            S[i] = f[(size_t)i * d.N + LBM_SRC(i)];
+            S[i] = at(f + (size_t)i * d.N, LBM_SRC(i));
             continue;
         }
-        const R outj = f[(size_t)j * d.N + idx];  // what left x toward the wall
+        const R outj = at(f + (size_t)j * d.N, ix);  // what left x toward the wall
         if (!bc.bouzidi) {
             S[i] = outj;
             continue;
@@ -267,11 +283,11 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
         C v = (C)outj;
         if (q < C(0.5)) {
             if (!(bm & (1u << i))) {  // x + e_i is the fluid node behind x
-                const long long b = idx + (ox[1 + L::E[i][0]] + oy[1 + L::E[i][1]] + oz[1 + L::E[i][2]]);
-                v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)f[(size_t)j * d.N + b];
+                const uint32_t b = ix + (uint32_t)(ox[1 + L::E[i][0]] + oy[1 + L::E[i][1]] + oz[1 + L::E[i][2]]);
+                v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)at(f + (size_t)j * d.N, b);
             }
         } else {
-            v = (C)outj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * (C)f[(size_t)i * d.N + idx];
+            v = (C)outj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * (C)at(f + (size_t)i * d.N, ix);
         }
         S[i] = (R)v;
         dm += (C)outj - v;
@@ -290,7 +306,7 @@ __device__ __forceinline__ bool density_node(const R* __restrict__ f, R* __restr
                                              int y, int z, bool in, double rho_m, R inv_b, int* status) {
     if (!in) return false;
     const long long idx = nid(d, x, y, z);
-    const uint8_t c = cls[idx];
+    const uint8_t c = at(cls, (uint32_t)idx);
     if ((c & CLS_MASK) != CLS_FLUID) return false;
     R S[L::Q];
     gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
@@ -298,7 +314,7 @@ __device__ __forceinline__ bool density_node(const R* __restrict__ f, R* __restr
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) s += (double)S[i];
     const R rs = (R)s;
-    rho[idx] = rs;
+    at(rho, (uint32_t)idx) = rs;
     if (!(s > 0.0 && s < (double)inv_b)) atomicOr(status, 1);  // also catches NaN
     return (double)rs >= rho_m;  // the stored value, as the crossing search sees it
 }
@@ -484,22 +500,23 @@ __device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict
     // the class and the density stencil are loaded together (every offset is
     // in bounds: periodic images), and the class decides only the store
     const long long idx = nid(d, x, y, z);
-    const uint8_t c = cls[idx];
-    const R* p = rho + idx;
-    const R rc = p[0];
+    const uint32_t ix = (uint32_t)idx;
+    const uint8_t c = at(cls, ix);
+    const R rc = at(rho, ix);
     const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
+    auto p = [&](int o) { return (C)at(rho, ix + (uint32_t)o); };
     const C c0 = (C)rc;
-    C lap = d2c<C>(p[ox.m2], p[ox.m1], c0, p[ox.p1], p[ox.p2]);
-    lap += d2c<C>(p[oy.m2], p[oy.m1], c0, p[oy.p1], p[oy.p2]);
+    C lap = d2c<C>(p(ox.m2), p(ox.m1), c0, p(ox.p1), p(ox.p2));
+    lap += d2c<C>(p(oy.m2), p(oy.m1), c0, p(oy.p1), p(oy.p2));
     if (L::D == 3) {
         const Nbr oz = nbr_offsets(z, d.nz, d.px * d.ny);
-        lap += d2c<C>(p[oz.m2], p[oz.m1], c0, p[oz.p1], p[oz.p2]);
+        lap += d2c<C>(p(oz.m2), p(oz.m1), c0, p(oz.p1), p(oz.p2));
     }
     const C m = (psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap;
     asm volatile("" : : "v"(m));  // keeps the loads above the class test
     if ((c & CLS_MASK) != CLS_FLUID) return false;
     r0 = rc;
-    mu[idx] = (R)m;
+    at(mu, ix) = (R)m;
     return true;
 }
 
@@ -588,7 +605,7 @@ __global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const 
 // ---------------------------------------------------------------------------
 template <class L, typename R, typename C, bool MRT, bool NT>
 __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
-                                              R* __restrict__ o, long long N);
+                                              R* __restrict__ fout, long long idx, long long N);
 
 // offset of the lattice neighbour x + e along one axis (e in {-1, 0, 1})
 __device__ __forceinline__ long long step_off(int e, const Nbr& o) { return e < 0 ? o.m1 : (e > 0 ? o.p1 : 0); }
@@ -615,18 +632,19 @@ __device__ __forceinline__ void sc_force(const R* __restrict__ psi, long long id
     Fz = -G * p0 * sz;
 }
 
-template <class L, typename R, typename C, bool PULL, bool MRT, bool NT = false, bool SC = false>
-__device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __restrict__ fout,
-                                             const R* __restrict__ rho, const R* __restrict__ mu,
-                                             const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
-                                             const Collision<C>& cp, long long t, int x, int y, int z) {
-    if (x >= d.nx || y >= d.ny) return;
-    const long long idx = nid(d, x, y, z);
-    const uint8_t c = cls[idx];
+// Force at a node: Eq. 7 with fourth-order central differences (or the
+// pseudopotential interaction), plus the body force from step g_start.  The
+// stencil loads need no class: every offset is in bounds (periodic images).
+// The two terms of Eq. 7 cancel almost exactly inside an interface at rest,
+// so F, and the moments it shifts, are formed in double precision whatever the
+// storage type.
+template <class L, typename R, typename C, bool SC>
+__device__ __forceinline__ void force_at(const R* __restrict__ rho, const R* __restrict__ mu, const Dims& d,
+                                         long long idx, int x, int y, int z, const Collision<C>& cp, long long t,
+                                         double& Fx, double& Fy, double& Fz) {
+    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
     if constexpr (SC) {
-        const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
         const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
-        double Fx, Fy, Fz;
         sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, Fx, Fy, Fz);
         if (t >= cp.g_start) {
             const double r0 = (double)rho[idx];
@@ -634,47 +652,164 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
             Fy += r0 * (double)cp.g[1];
             Fz += r0 * (double)cp.g[2];
         }
-        asm volatile("" : : "v"(Fx), "v"(Fy), "v"(Fz));  // keeps the loads above the class test
-        if ((c & CLS_MASK) != CLS_FLUID) return;
-        R S[L::Q];
-        gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
-        collide_apply<L, R, C, MRT, NT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
         return;
     }
-
-    // Eq. 7 with fourth-order central differences, formed before the class
-    // test so that the stencil loads go out with the class load (every offset
-    // is in bounds: periodic images).  The two terms of F cancel
-    // almost exactly inside an interface at rest, so F, and the moments it
-    // shifts, are formed in double precision whatever the storage type.
     typedef double D;
-    const R* pr = rho + idx;
-    const R* pm = mu + idx;
-    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
-    const D r0 = (D)pr[0];
-    const D gmx = d1c<D>(pm[ox.m2], pm[ox.m1], pm[ox.p1], pm[ox.p2]);
-    const D grx = d1c<D>(pr[ox.m2], pr[ox.m1], pr[ox.p1], pr[ox.p2]);
-    const D gmy = d1c<D>(pm[oy.m2], pm[oy.m1], pm[oy.p1], pm[oy.p2]);
-    const D gry = d1c<D>(pr[oy.m2], pr[oy.m1], pr[oy.p1], pr[oy.p2]);
+    const uint32_t ix = (uint32_t)idx;
+    auto pr = [&](int o) { return (D)at(rho, ix + (uint32_t)o); };
+    auto pm = [&](int o) { return (D)at(mu, ix + (uint32_t)o); };
+    const D r0 = pr(0);
+    const D gmx = d1c<D>(pm(ox.m2), pm(ox.m1), pm(ox.p1), pm(ox.p2));
+    const D grx = d1c<D>(pr(ox.m2), pr(ox.m1), pr(ox.p1), pr(ox.p2));
+    const D gmy = d1c<D>(pm(oy.m2), pm(oy.m1), pm(oy.p1), pm(oy.p2));
+    const D gry = d1c<D>(pr(oy.m2), pr(oy.m1), pr(oy.p1), pr(oy.p2));
     D gmz = D(0), grz = D(0);
     if (L::D == 3) {
         const Nbr oz = nbr_offsets(z, d.nz, d.px * d.ny);
-        gmz = d1c<D>(pm[oz.m2], pm[oz.m1], pm[oz.p1], pm[oz.p2]);
-        grz = d1c<D>(pr[oz.m2], pr[oz.m1], pr[oz.p1], pr[oz.p2]);
+        gmz = d1c<D>(pm(oz.m2), pm(oz.m1), pm(oz.p1), pm(oz.p2));
+        grz = d1c<D>(pr(oz.m2), pr(oz.m1), pr(oz.p1), pr(oz.p2));
     }
     const D third = D(1.0 / 3.0);
-    D Fx = -r0 * gmx + grx * third, Fy = -r0 * gmy + gry * third, Fz = -r0 * gmz + grz * third;
+    Fx = -r0 * gmx + grx * third;
+    Fy = -r0 * gmy + gry * third;
+    Fz = -r0 * gmz + grz * third;
     if (t >= cp.g_start) {
         Fx += r0 * (D)cp.g[0];
         Fy += r0 * (D)cp.g[1];
         Fz += r0 * (D)cp.g[2];
     }
+}
+
+// The force of every node into F ([3][N], storage precision) for the one-pass
+// step: Eq. 7 (or the pseudopotential interaction) plus the body force of
+// step t; F of solid nodes is written but never read.  z-chunked as k_mu, so
+// that a workgroup's stencil planes are the ones it read an iteration before,
+// and software-pipelined: plane z+1's stencil is loaded before plane z's
+// force is stored (a wave's loads and stores share one in-order counter, so
+// loads issued after the stores would wait for them).
+template <class L, typename R>
+struct ForceStencil {
+    static constexpr int K = 25;  // rho: centre and 12 axis neighbours; mu (or psi): 12 axis neighbours
+    R v[K];
+};
+
+template <class L, typename R, bool SC>
+__device__ __forceinline__ void force_stencil_load(const R* __restrict__ rho, const R* __restrict__ mu, const Dims& d,
+                                                   int x, int y, int z, ForceStencil<L, R>& s) {
+    const long long idx = nid(d, x, y, z);
+    const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
+    const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
+    if constexpr (SC) {
+        // psi at the lattice neighbours, rho at the node
+        s.v[0] = rho[idx];
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            long long o = step_off(L::E[i][0], ox) + step_off(L::E[i][1], oy);
+            if (L::D == 3) o += step_off(L::E[i][2], oz);
+            s.v[i] = mu[idx + o];
+        }
+        s.v[L::Q] = mu[idx];
+        return;
+    }
+    const Nbr ax[3] = {ox, oy, oz};
+    const uint32_t ix = (uint32_t)idx;
+    s.v[0] = at(rho, ix);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool on = a < L::D;
+        const Nbr& o = ax[a];
+        const uint32_t i2 = on ? ix + (uint32_t)o.m2 : ix, i1 = on ? ix + (uint32_t)o.m1 : ix;
+        const uint32_t j1 = on ? ix + (uint32_t)o.p1 : ix, j2 = on ? ix + (uint32_t)o.p2 : ix;
+        s.v[1 + 4 * a] = at(rho, i2);
+        s.v[2 + 4 * a] = at(rho, i1);
+        s.v[3 + 4 * a] = at(rho, j1);
+        s.v[4 + 4 * a] = at(rho, j2);
+        s.v[13 + 4 * a] = at(mu, i2);
+        s.v[14 + 4 * a] = at(mu, i1);
+        s.v[15 + 4 * a] = at(mu, j1);
+        s.v[16 + 4 * a] = at(mu, j2);
+    }
+}
+
+template <class L, typename R, typename C, bool SC>
+__device__ __forceinline__ void force_from_stencil(const ForceStencil<L, R>& s, const Collision<C>& cp, long long t,
+                                                   double& Fx, double& Fy, double& Fz) {
+    typedef double D;
+    const D r0 = (D)s.v[0];
+    if constexpr (SC) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const double v = L::w(i) * (double)s.v[i];
+            sx += v * L::E[i][0];
+            sy += v * L::E[i][1];
+            sz += v * L::E[i][2];
+        }
+        const double p0 = (double)s.v[L::Q];
+        Fx = -cp.sc_G * p0 * sx;
+        Fy = -cp.sc_G * p0 * sy;
+        Fz = -cp.sc_G * p0 * sz;
+    } else {
+        D gr[3], gm[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gr[a] = d1c<D>((D)s.v[1 + 4 * a], (D)s.v[2 + 4 * a], (D)s.v[3 + 4 * a], (D)s.v[4 + 4 * a]);
+            gm[a] = d1c<D>((D)s.v[13 + 4 * a], (D)s.v[14 + 4 * a], (D)s.v[15 + 4 * a], (D)s.v[16 + 4 * a]);
+        }
+        const D third = D(1.0 / 3.0);
+        Fx = -r0 * gm[0] + gr[0] * third;
+        Fy = -r0 * gm[1] + gr[1] * third;
+        Fz = L::D == 3 ? -r0 * gm[2] + gr[2] * third : D(0);
+    }
+    if (t >= cp.g_start) {
+        Fx += r0 * (D)cp.g[0];
+        Fy += r0 * (D)cp.g[1];
+        Fz += r0 * (D)cp.g[2];
+    }
+}
+
+template <class L, typename R, typename C, bool SC>
+__global__ void __launch_bounds__(256) k_force(const R* __restrict__ rho, const R* __restrict__ mu,
+                                               const uint8_t* __restrict__ cls, Dims d, Collision<C> cp,
+                                               const DevCtl* __restrict__ ctl, R* __restrict__ F) {
+    (void)cls;
+    int x, y, z0;
+    tile_node_zc(d, x, y, z0);
+    if (x >= d.nx || y >= d.ny) return;
+    const int z1 = z0 + d.zc < d.nz ? z0 + d.zc : d.nz;
+    const long long t = ctl->t;
+    ForceStencil<L, R> cur, nxt;
+    force_stencil_load<L, R, SC>(rho, mu, d, x, y, z0, cur);
+    for (int z = z0; z < z1; ++z) {
+        force_stencil_load<L, R, SC>(rho, mu, d, x, y, z + 1 < z1 ? z + 1 : z, nxt);  // unconditional: counted
+        double Fx, Fy, Fz;
+        force_from_stencil<L, R, C, SC>(cur, cp, t, Fx, Fy, Fz);
+        const uint32_t ix = (uint32_t)nid(d, x, y, z);
+        at(F, ix) = (R)Fx;
+        at(F + d.N, ix) = (R)Fy;
+        at(F + 2 * d.N, ix) = (R)Fz;
+#pragma unroll
+        for (int k = 0; k < ForceStencil<L, R>::K; ++k) cur.v[k] = nxt.v[k];
+    }
+}
+
+template <class L, typename R, typename C, bool PULL, bool MRT, bool NT = false, bool SC = false>
+__device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __restrict__ fout,
+                                             const R* __restrict__ rho, const R* __restrict__ mu,
+                                             const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
+                                             const Collision<C>& cp, long long t, int x, int y, int z) {
+    if (x >= d.nx || y >= d.ny) return;
+    const long long idx = nid(d, x, y, z);
+    const uint8_t c = at(cls, (uint32_t)idx);
+    // the force is formed before the class test so that its stencil loads go
+    // out with the class load
+    double Fx, Fy, Fz;
+    force_at<L, R, C, SC>(rho, mu, d, idx, x, y, z, cp, t, Fx, Fy, Fz);
     asm volatile("" : : "v"(Fx), "v"(Fy), "v"(Fz));  // keeps the loads above the class test
     if ((c & CLS_MASK) != CLS_FLUID) return;
-
     R S[L::Q];
     gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
-    collide_apply<L, R, C, MRT, NT>(S, Fx, Fy, Fz, cp, fout + idx, d.N);
+    collide_apply<L, R, C, MRT, NT>(S, Fx, Fy, Fz, cp, fout, idx, d.N);
 }
 
 // Collision of one fluid node from its gathered populations S and the force
@@ -693,9 +828,29 @@ __device__ __forceinline__ void put(R* p, R v) {
     else *p = v;
 }
 
-template <class L, typename R, typename C, bool MRT, bool NT>
-__device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
-                                              R* __restrict__ o, long long N) {
+// Second-order equilibrium (Eq. 2) of every direction for density rs and
+// velocity a, formed per pair of opposite directions: w rs (1 + 4.5 (e.a)^2 -
+// 1.5 a.a) plus and minus 3 w rs e.a.
+template <class L, typename C>
+__device__ __forceinline__ void feq_all(C rs, C ax, C ay, C az, C out[L::Q]) {
+    const C aa = ax * ax + ay * ay + az * az;
+    out[0] = rs * C(L::w(0)) * (C(1) - C(1.5) * aa);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        if (L::OPP[i] < i) continue;
+        const C ea = C(L::E[i][0]) * ax + C(L::E[i][1]) * ay + C(L::E[i][2]) * az;
+        const C wr = rs * C(L::w(i));
+        const C sym = wr * (C(1) + C(4.5) * ea * ea - C(1.5) * aa);
+        const C anti = wr * C(3) * ea;
+        out[i] = sym + anti;
+        out[L::OPP[i]] = sym - anti;
+    }
+}
+
+// The post-collision populations of one node into fo (storage type).
+template <class L, typename R, typename C, bool MRT>
+__device__ __forceinline__ void collide_values(const R S[L::Q], double Fx, double Fy, double Fz,
+                                               const Collision<C>& cp, R fo[L::Q]) {
     typedef double D;
     // moments of S: density and velocity (Eq. 2 arguments), in double
     D rd = D(0), jx = D(0), jy = D(0), jz = D(0);
@@ -711,9 +866,7 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
     const C rs = (C)rd;
     const C ux = (C)(jx * ird), uy = (C)(jy * ird), uz = (C)(jz * ird);
     const C vx = (C)((jx + Fx) * ird), vy = (C)((jy + Fy) * ird), vz = (C)((jz + Fz) * ird);  // u + F/rho (Eq. 13)
-    const C uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + vy * vy + vz * vz;
 
-    const long long sN = N;   // post-collision populations stay at the node (aligned stores)
     // With FP32 arithmetic the lattice weights are rounded (1/3, 1/18 and 1/36
     // in binary32 sum to 1 + 1.5e-8), so every collision would add that share
     // of the density to the node: a systematic drift of 1.5e-8 per step.  The
@@ -723,34 +876,52 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
     constexpr bool kRestRemainder = sizeof(C) == 4;
     double srest = 0.0;
     if (!MRT) {
-        // BGK (Eq. 3) + exact-difference forcing (Eq. 13), one direction at a time
-        const C om = cp.omega;
-#pragma unroll
-        for (int i = kRestRemainder ? 1 : 0; i < L::Q; ++i) {
-            const C eu = C(L::E[i][0]) * ux + C(L::E[i][1]) * uy + C(L::E[i][2]) * uz;
-            const C ev = C(L::E[i][0]) * vx + C(L::E[i][1]) * vy + C(L::E[i][2]) * vz;
-            const C wr = rs * C(L::w(i));
-            const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-            const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
-            const C fi = (C)S[i];
-            const R v = (R)(fi - om * (fi - feq) + (feq2 - feq));
-            if (kRestRemainder) srest += (double)v;
-            put<NT>(&o[(size_t)i * sN], v);
+        // BGK (Eq. 3) + exact-difference forcing (Eq. 13) with feq2 = f_eq(rho, u + F / rho):
+        // f* = f - (f - feq) / tau + feq2 - feq = feq2 + (1 - 1/tau) (f - feq),
+        // which for tau = 1 is feq2 alone (a uniform branch).  Per pair of
+        // opposite directions, as feq_all forms them.
+        const C om1 = C(1) - cp.omega;
+        const bool relax = om1 != C(0);
+        const C uu = ux * ux + uy * uy + uz * uz, vv = vx * vx + vy * vy + vz * vz;
+        auto put2 = [&](int i, C v) {
+            const R r = (R)v;
+            if (kRestRemainder && i != 0) srest += (double)r;
+            fo[i] = r;
+        };
+        {
+            const C w0 = rs * C(L::w(0));
+            C v0 = w0 * (C(1) - C(1.5) * vv);
+            if (relax) v0 += om1 * ((C)S[0] - w0 * (C(1) - C(1.5) * uu));
+            put2(0, v0);
         }
-        if (kRestRemainder) put<NT>(&o[0], (R)(rd - srest));
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            if (L::OPP[i] < i) continue;
+            const int j = L::OPP[i];
+            const C wr = rs * C(L::w(i));
+            const C ev = C(L::E[i][0]) * vx + C(L::E[i][1]) * vy + C(L::E[i][2]) * vz;
+            const C sym2 = wr * (C(1) + C(4.5) * ev * ev - C(1.5) * vv), anti2 = wr * C(3) * ev;
+            C vi = sym2 + anti2, vj = sym2 - anti2;
+            if (relax) {
+                const C eu = C(L::E[i][0]) * ux + C(L::E[i][1]) * uy + C(L::E[i][2]) * uz;
+                const C sym = wr * (C(1) + C(4.5) * eu * eu - C(1.5) * uu), anti = wr * C(3) * eu;
+                vi += om1 * ((C)S[i] - (sym + anti));
+                vj += om1 * ((C)S[j] - (sym - anti));
+            }
+            put2(i, vi);
+            put2(j, vj);
+        }
+        if (kRestRemainder) fo[0] = (R)(rd - srest);
     } else {
         // MRT (Eq. 1): non-conserved moments of f - f_eq relaxed by s_k and
         // mapped back with M^T D^-1, plus the forcing term
-        C dev[L::Q], out[L::Q];
+        C dev[L::Q], out[L::Q], feq[L::Q], feq2[L::Q];
+        feq_all<L, C>(rs, ux, uy, uz, feq);
+        feq_all<L, C>(rs, vx, vy, vz, feq2);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            const C eu = C(L::E[i][0]) * ux + C(L::E[i][1]) * uy + C(L::E[i][2]) * uz;
-            const C ev = C(L::E[i][0]) * vx + C(L::E[i][1]) * vy + C(L::E[i][2]) * vz;
-            const C wr = rs * C(L::w(i));
-            const C feq = wr * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-            const C feq2 = wr * (C(1) + C(3) * ev + C(4.5) * ev * ev - C(1.5) * vv);
-            dev[i] = (C)S[i] - feq;
-            out[i] = (C)S[i] + (feq2 - feq);
+            dev[i] = (C)S[i] - feq[i];
+            out[i] = (C)S[i] + (feq2[i] - feq[i]);
         }
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
@@ -772,10 +943,21 @@ __device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double
         for (int i = kRestRemainder ? 1 : 0; i < L::Q; ++i) {
             const R v = (R)out[i];
             if (kRestRemainder) srest += (double)v;
-            put<NT>(&o[(size_t)i * sN], v);
+            fo[i] = v;
         }
-        if (kRestRemainder) put<NT>(&o[0], (R)(rd - srest));
+        if (kRestRemainder) fo[0] = (R)(rd - srest);
     }
+}
+
+// Collision of one node with its post-collision populations stored at the
+// node, o[i * N] (aligned stores; streaming is the next step's pull).
+template <class L, typename R, typename C, bool MRT, bool NT>
+__device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
+                                              R* __restrict__ fout, long long idx, long long N) {
+    R fo[L::Q];
+    collide_values<L, R, C, MRT>(S, Fx, Fy, Fz, cp, fo);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) put<NT>(&at(fout + (size_t)i * N, (uint32_t)idx), fo[i]);
 }
 
 template <class L, typename R, typename C, bool PULL, bool MRT, bool SC = false>

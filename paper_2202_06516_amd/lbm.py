@@ -24,6 +24,7 @@ LBM_PERIODIC, LBM_WALL = 0, 1
 LBM_MRT, LBM_BGK = 0, 1
 LBM_BC_HALFWAY, LBM_BC_BOUZIDI_MC = 0, 1
 LBM_MODEL_CHEMICAL_POTENTIAL, LBM_MODEL_PSEUDOPOTENTIAL = 0, 1
+LBM_STEP_AUTO, LBM_STEP_SPLIT = 0, 1
 LBM_SOLID_SPHERE = 0
 LBM_SOLID_CAVITY = 1
 LBM_WET_UNIFORM, LBM_WET_STRIPES = 0, 1
@@ -46,7 +47,7 @@ class lbm_config(C.Structure):
         ("pr_a", C.c_double), ("pr_b", C.c_double), ("pr_R", C.c_double), ("pr_omega", C.c_double),
         ("k", C.c_double), ("kappa", C.c_double), ("g", C.c_double * 3), ("g_start_step", C.c_int64),
         ("rho_l", C.c_double), ("rho_g", C.c_double), ("wall_mu", C.c_double), ("stream", C.c_void_p),
-        ("model", C.c_int), ("sc_G", C.c_double),
+        ("model", C.c_int), ("sc_G", C.c_double), ("step_kernel", C.c_int),
     ]
 
 

@@ -1,0 +1,176 @@
+"""The one-pass step (k_step, D3Q19 lattices of whole-row tiles) against the
+FP64 oracle and against the split step, element by element.
+
+k_step collides step t and sums the density of step t + 1 in the same pass;
+partial sums that cross its tiles go through ghost arrays.  The cases cover
+one, two and three waves per row, every z-chunk depth it picks (8, 4, 2),
+walls and periodic axes (ghost rows and planes that wrap), halfway walls (the
+interpolated wall stays on the split step), MRT and BGK, gravity switched on mid-run, the pseudopotential model, FP64 /
+FP32 / FP32 with FP64 arithmetic, in-step measurement, reads between steps, and
+graph-captured against eager stepping.
+"""
+import numpy as np
+import pytest
+
+from paper_2202_06516_amd import lbm as G
+
+from .pairs import gpu_lattice, oracle_lattice, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(Tr=0.8)
+
+
+def case(n, wall, c=None, r=7.3, drop=6.5):
+    nx, ny, nz = n
+    c = c or (nx / 2 + 0.2, ny / 2 + 0.1, nz / 3 + 0.4)
+    return dict(dim=3, n=n, wall=wall, solids=[dict(center=c, radius=r, mu_w=0.04)],
+                drops=[((c[0] - 0.2, c[1] - 0.1, c[2] + r + drop - 1.6), drop)])
+
+
+def fields(gp, o, tol, vel=False):
+    o.update_derived()
+    fl = o.cls == 0
+    layers = (o.cls == 1) | (o.cls == 2)
+    e_rho = rel_err(gp.rho, o.rho, fl | layers)
+    e_f = rel_err(gp.f, o.f)
+    assert e_rho <= tol, f"rho {e_rho:.3e}"
+    assert e_f <= tol, f"f {e_f:.3e}"
+    if vel:
+        vo = o.velocity()
+        assert rel_err(gp.read(G.FIELD_VEL), vo, np.broadcast_to(fl, vo.shape)) <= 100 * tol
+    return e_rho
+
+
+def is_fused(gp):
+    # the one-pass step reports k_step in its per-kernel profile
+    return "k_step" in gp.profile(1)
+
+
+CASES = [
+    # (lattice, walls): 1, 2 and 3 waves per row; z chunks of 8, 2 and 4 planes
+    ((64, 24, 32), (1, 1, 1)),
+    ((128, 20, 38), (0, 0, 0)),
+    ((192, 20, 36), (1, 0, 1)),
+]
+
+
+@pytest.mark.parametrize("n,wall", CASES)
+@pytest.mark.parametrize("collision,bc", [("bgk", "halfway"), ("mrt", "halfway")])
+def test_one_pass_matches_oracle_f64(n, wall, collision, bc):
+    wl = case(n, wall)
+    kw = dict(s_q=1.0, s_m=1.0, s_pi=1.0, **SMALL)
+    gp = gpu_lattice(wl, G.LBM_F64, collision, bc, **kw)
+    assert is_fused(gp)
+    o = oracle_lattice(wl, collision, bc, **kw)
+    o.step(1)  # the profile call above advanced the GPU lattice one step
+    gp.step(9)
+    o.step(9)
+    fields(gp, o, 1e-12, vel=True)
+
+
+def test_one_pass_gravity_and_split_path_agree():
+    wl = case((64, 24, 32), (1, 1, 1))
+    g = (2e-5, -1e-5, -3e-5)
+    a = gpu_lattice(wl, G.LBM_F64, "bgk", g=g, g_start=5, **SMALL)
+    b = gpu_lattice(wl, G.LBM_F64, "bgk", g=g, g_start=5, step_kernel=G.LBM_STEP_SPLIT, **SMALL)
+    o = oracle_lattice(wl, "bgk", g=g, g_start=5, **SMALL)
+    a.step(40)
+    b.step(40)
+    o.step(40)
+    fields(a, o, 1e-12, vel=True)
+    assert rel_err(a.f, b.f) <= 1e-13
+    assert rel_err(a.read(G.FIELD_MU), b.read(G.FIELD_MU)) <= 1e-12
+
+
+def test_one_pass_pseudopotential_f64():
+    wl = case((64, 24, 32), (1, 1, 1))
+    wl.update(model=1, W=5.0)
+    wl["solids"][0]["mu_w"] = 1.2   # the wall density
+    gp = gpu_lattice(wl, G.LBM_F64, "bgk")
+    o = oracle_lattice(wl, "bgk")
+    gp.step(20)
+    o.step(20)
+    fields(gp, o, 1e-12)
+
+
+@pytest.mark.parametrize("precision,tol", [(G.LBM_F32, 1e-6), (G.LBM_F32_MIXED, 3e-7)])
+def test_one_pass_fp32_200_steps(precision, tol):
+    wl = case((64, 24, 32), (1, 1, 1))
+    gp = gpu_lattice(wl, precision, "bgk", **SMALL)
+    o = oracle_lattice(wl, "bgk", **SMALL)
+    errs = []
+    for _ in range(4):
+        gp.step(50)
+        o.step(50)
+        o.update_derived()
+        errs.append(rel_err(gp.rho, o.rho, o.cls <= 2))
+    print("density error every 50 steps:", ["%.2e" % e for e in errs])
+    assert max(errs) <= tol, errs
+
+
+def test_one_pass_in_step_measurement_matches_oracle():
+    wl = case((128, 24, 40), (1, 1, 1), r=9.1, drop=8.0)
+    gp = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
+    gp.set_measure(0, 16)
+    o = oracle_lattice(wl, "bgk", **SMALL)
+    ga = gp.step(150, measure_every=50, cap=8)
+    oa = o.step_measured(150, 50, 0, 16)
+    assert len(ga) == len(oa) == 3
+    for a, b in zip(ga, oa):
+        assert a.step == b.step and a.n_valid == b.n_valid
+        for s in range(16):
+            x, y = a.sector_deg[s], b.sector_deg[s]
+            assert (np.isnan(x) and np.isnan(y)) or abs(x - y) < 1e-6, (a.step, s, x, y)
+    # a measurement call that starts at a measure step after steps that did not measure
+    gp.step(50)
+    o.step(50)
+    ga = gp.step(1, measure_every=200, cap=2)
+    oa = o.step_measured(1, 200, 0, 16)
+    assert len(ga) == len(oa) == 1 and ga[0].n_valid == oa[0].n_valid > 0
+    assert abs(ga[0].mean_deg - oa[0].mean_deg) < 1e-6
+    # and the standalone measurement after one-pass steps
+    m = gp.measure(0, 16)
+    mo = o.measure(0, 16)
+    assert abs(m.mean_deg - mo.mean_deg) < 1e-6
+
+
+def test_one_pass_graph_and_eager_agree():
+    # 70 steps = eager steps to parity + two captured graphs of 32 + the rest
+    wl = case((64, 24, 32), (1, 1, 1))
+    a = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
+    b = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
+    a.step(70)
+    for _ in range(70):
+        b.step(1)
+    assert np.array_equal(a.f, b.f)
+    assert np.array_equal(a.rho, b.rho)
+
+
+def test_one_pass_reads_and_writes_between_steps():
+    wl = case((64, 24, 32), (1, 1, 1))
+    a = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
+    o = oracle_lattice(wl, "bgk", **SMALL)
+    a.step(15)
+    o.step(15)
+    m0 = a.mass()
+    f = a.f
+    rho = a.rho
+    a.write(G.FIELD_F, f)          # checkpoint restore: the density is derived again
+    a.step(15)
+    o.step(15)
+    fields(a, o, 1e-12)
+    assert abs(a.mass() / m0 - 1.0) < 1e-12
+    a.write(G.FIELD_RHO, rho)      # warm start from a density
+    o.set_rho(rho)
+    a.step(10)
+    o.step(10)
+    fields(a, o, 1e-12)
+
+
+def test_split_is_used_where_the_one_pass_step_cannot_tile():
+    for n in ((70, 24, 32), (64, 22, 32), (64, 24, 33)):
+        gp = gpu_lattice(case(n, (1, 1, 1)), G.LBM_F64, "bgk", **SMALL)
+        assert not is_fused(gp), n
+    # the interpolated wall keeps the split step (its loads depend on one another)
+    assert not is_fused(gpu_lattice(case((64, 24, 32), (1, 1, 1)), G.LBM_F64, "bgk", "bouzidi", **SMALL))
