@@ -154,6 +154,28 @@ def cavity_wedge_density(shape, center, R, theta0_deg, rho_m, rho_lo, rho_hi, sl
     return rho[None, :, :]
 
 
+def plane_film_density(shape, rho_m, rho_lo, rho_hi, heights, x_split, liquid_above=True, slope=0.5, far=14.0):
+    """Synthetic 3-D liquid bounded by a horizontal plane, for measurements on a
+    sphere: liquid above z = h (liquid_above) or below it, up to a far plane
+    far lu beyond.  heights = (h_left, h_right): the plane is at h_left for
+    x < x_split - 3, at h_right for x > x_split + 3, and between them linear in
+    x.  The density is rho_m + slope * s, s the signed distance-like quantity
+    min(+-(z - h(x)), far - +-(z - h(x))) (positive in the liquid), clipped to
+    [rho_lo, rho_hi]; away from the x band it is affine in z, so along every
+    lattice link isodensity crossings lie on the plane.  Returns an array of
+    shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    zz, _, xx = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                            np.arange(nx, dtype=np.float64), indexing="ij")
+    hl, hr = heights
+    t = np.clip((xx - (x_split - 3.0)) / 6.0, 0.0, 1.0)
+    h = hl + (hr - hl) * t
+    sgn = 1.0 if liquid_above else -1.0
+    s = sgn * (zz - h)
+    s = np.minimum(s, far - s)
+    return np.clip(rho_m + slope * s, rho_lo, rho_hi)
+
+
 def cavity_2d(mu_w=0.04, n=128):
     """Drop resting at the bottom of a circular cavity (concave substrate,
     Fig. 2b) on a square lattice: cavity radius 7n/16 at the centre, drop

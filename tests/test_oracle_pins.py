@@ -616,6 +616,123 @@ def test_cavity_wedge_measured_exactly(theta0):
         assert abs(a.contact[s][1] - (90 - 80 * math.cos(math.asin(30 / 80)))) < 1e-9
 
 
+# ------------------------------------------ 3-D measurement (Sec. III B, Eq. 15)
+
+SPHERE3 = ((31.5, 31.5, 26.0), 18.0)       # convex: liquid film above a plane cutting the sphere
+CAVITY3 = ((31.5, 31.5, 32.0), 26.0)       # concave: pool below a plane inside a spherical cavity
+
+
+def _film_on_sphere(phi_deg, cavity=False, g=(0.0, 0.0, 0.0), heights=None):
+    """A 64^3 periodic lattice holding a sphere (or a cavity) and liquid bounded
+    by a horizontal plane that meets it at polar angle phi from the +z pole
+    (from the -z pole in the cavity).  The density is affine in z near the
+    plane, so each isodensity crossing on a lattice link lies on the plane,
+    and every meridional secant of Eq. 15 is exactly the plane's trace."""
+    (c, r) = CAVITY3 if cavity else SPHERE3
+    o = O.Oracle(3, (64, 64, 64), g=g)
+    o.add_sphere(c, r, mu_w=0.0, cavity=cavity)
+    inf = o.info()
+    rm = 0.5 * (inf["rho_l"] + inf["rho_g"])
+    if heights is None:
+        h = c[2] - r * math.cos(math.radians(phi_deg)) if cavity else c[2] + r * math.cos(math.radians(phi_deg))
+        heights = (h, h)
+    # the far face of the liquid layer stays clear of the substrate
+    far = 100.0 if cavity else 60.0 - max(heights)
+    o.set_rho(W.plane_film_density(o.shape, rm, inf["rho_g"], inf["rho_l"], heights, c[0],
+                                   liquid_above=not cavity, far=far))
+    return o
+
+
+@pytest.mark.parametrize("ns", [8, 32, 64])
+@pytest.mark.parametrize("phi", [60, 90, 120])
+def test_3d_plane_on_sphere_measured_exactly(phi, ns):
+    # liquid above the plane z = z_c + R cos(phi): in every meridional plane
+    # the liquid side of the interface is the +z half-line, the outward normal
+    # at the contact point makes the angle phi with +z, so the angle through
+    # the liquid is 180 - phi in every sector
+    o = _film_on_sphere(phi)
+    a = o.measure(0, ns)
+    assert a.status == 0 and a.n_valid == ns
+    assert list(a.axis) == [0.0, 0.0, 1.0]
+    (c, r) = SPHERE3
+    h = c[2] + r * math.cos(math.radians(phi))
+    rho_c = r * math.sin(math.radians(phi))
+    for s in range(ns):
+        assert abs(a.sector_deg[s] - (180.0 - phi)) < 1e-9, (s, a.sector_deg[s])
+        # the contact point lies on the circle where the plane cuts the sphere
+        p = a.contact[s]
+        assert abs(p[2] - h) < 1e-9
+        assert abs(math.hypot(p[0] - c[0], p[1] - c[1]) - rho_c) < 1e-9
+    assert abs(a.mean_deg - (180.0 - phi)) < 1e-9
+
+
+@pytest.mark.parametrize("ns", [8, 32, 64])
+@pytest.mark.parametrize("psi", [60, 90, 120])
+def test_3d_pool_in_spherical_cavity_measured_exactly(psi, ns):
+    # a pool at the bottom of a spherical cavity, its free surface at polar
+    # angle psi from the -z pole: the substrate normal points to the centre
+    # and the angle through the liquid is psi itself
+    o = _film_on_sphere(psi, cavity=True)
+    a = o.measure(0, ns)
+    assert a.status == 0 and a.n_valid == ns
+    assert list(a.axis) == [0.0, 0.0, -1.0]
+    (c, r) = CAVITY3
+    for s in range(ns):
+        assert abs(a.sector_deg[s] - psi) < 1e-9, (s, a.sector_deg[s])
+        p = a.contact[s]
+        assert abs(p[2] - (c[2] - r * math.cos(math.radians(psi)))) < 1e-9
+        assert abs(math.hypot(p[0] - c[0], p[1] - c[1]) - r * math.sin(math.radians(psi))) < 1e-9
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("phi", [60, 90, 120])
+def test_3d_oblique_axis_measured_exactly(phi, sign):
+    # the same construction about the body diagonal a = +-(1,1,1)/sqrt(3) of a
+    # 72^3 lattice, with the liquid closed off by a ball of radius 33: the
+    # lattice maps onto itself under the 120-degree turns about a, so the
+    # centroid axis is a to round-off, and the sectors (which no longer line
+    # up with lattice planes) still measure 180 - phi exactly
+    n, c, r = 72, 35.5, 16.0
+    a = sign * np.ones(3) / math.sqrt(3.0)
+    o = O.Oracle(3, (n, n, n))
+    o.add_sphere((c, c, c), r, mu_w=0.0)
+    inf = o.info()
+    rm = 0.5 * (inf["rho_l"] + inf["rho_g"])
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    p = np.stack([xx - c, yy - c, zz - c], -1).astype(np.float64)
+    s = np.minimum(p @ a - r * math.cos(math.radians(phi)), 33.0 - np.linalg.norm(p, axis=-1))
+    o.set_rho(np.clip(rm + 0.5 * s, inf["rho_g"], inf["rho_l"]))
+    for ns in (8, 32):
+        m = o.measure(0, ns)
+        assert m.status == 0 and m.n_valid == ns
+        assert np.linalg.norm(np.array(m.axis) - a) < 1e-12
+        assert max(abs(t - (180.0 - phi)) for t in m.sector_deg[:ns]) < 1e-9
+
+
+@pytest.mark.parametrize("tilt", [1, -1])
+def test_3d_advancing_and_receding_follow_gravity(tilt):
+    # a film at two heights: on the +x side of the sphere it meets it at
+    # phi = 110 (angle 70), on the -x side at phi = 70 (angle 110), with a
+    # six-lattice-unit ramp between them over the sphere's top.  Gravity
+    # tilted 20 degrees from -z toward +x (tilt 1) makes +x the advancing
+    # side.  The liquid's centroid axis leans 0.55 degrees off z, which the
+    # sector angles carry as an error below 0.1 degrees at 32 and 64 sectors.
+    # Turning gravity toward -x swaps the two (the selection follows g, not
+    # the geometry).
+    (c, r) = SPHERE3
+    hl, hr = c[2] + r * math.cos(math.radians(70)), c[2] + r * math.cos(math.radians(110))
+    t = math.radians(20.0)
+    o = _film_on_sphere(None, g=(tilt * 1e-5 * math.sin(t), 0.0, -1e-5 * math.cos(t)), heights=(hl, hr))
+    for ns in (32, 64):
+        a = o.measure(0, ns)
+        assert a.status == 0 and a.n_valid == ns
+        adv, rec = (70.0, 110.0) if tilt > 0 else (110.0, 70.0)
+        assert abs(a.adv_deg - adv) < 0.1 and abs(a.rec_deg - rec) < 0.1, (ns, a.adv_deg, a.rec_deg)
+    # with gravity along the axis there is no advancing side
+    o = _film_on_sphere(90)
+    assert math.isnan(o.measure(0, 32).adv_deg)
+
+
 @pytest.mark.parametrize("bc", [0, 1])
 def test_cavity_mass_and_mirror_symmetry(bc):
     # a drop at the bottom of a cavity, symmetric about x = 64: mass is
