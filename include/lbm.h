@@ -160,7 +160,16 @@ typedef struct {
     double rho_m;        /* isodensity level; <= 0 selects (rho_l + rho_g) / 2 */
 } lbm_measure_opts;
 
-/* One contact-angle measurement.  Angles in degrees; NaN where invalid. */
+/* One contact-angle measurement.  Angles in degrees; NaN where invalid.
+ *
+ * 3-D sectors: a is the axis below; b1 is the lattice axis least aligned
+ * with a (|a_k| compared after rounding to multiples of 1/1024, ties to the
+ * lower axis) with its a-component removed and normalised, and b2 = a x b1.
+ * A point r (relative to the substrate centre) has azimuth
+ * psi = atan2(r.b2, r.b1) in [-pi, pi], and sector s holds
+ * -pi + 2 pi s / n_sectors <= psi < -pi + 2 pi (s + 1) / n_sectors.
+ * adv_deg is the sector holding the azimuth of g's part normal to a, rec_deg
+ * the sector n_sectors / 2 further on (2-D: side 0 holds r.b1 >= 0). */
 typedef struct {
     int64_t step;        /* t of the density field measured */
     int32_t status;      /* LBM_OK or LBM_E_NO_CONTACT_LINE */

@@ -64,6 +64,46 @@ def test_maxwell_coexistence(Tr):
     assert m["rho_g"] < m["rho_l"]
 
 
+def _relaxed_slab(Tr, steps):
+    # a flat liquid slab (y in 50..150) in gas on a periodic 6 x 200 lattice,
+    # relaxed until the velocity has died out; returns the bulk liquid and gas
+    # densities (slab middle, far gas) and the largest remaining speed
+    ny = 200
+    o = O.Oracle(2, (6, ny), Tr=Tr, k=0.28, kappa=0.01)
+    inf = o.info()
+    y = np.arange(ny)
+    prof = inf["rho_g"] + 0.5 * (inf["rho_l"] - inf["rho_g"]) * (np.tanh((y - 50) / 3.0) - np.tanh((y - 150) / 3.0))
+    o.set_rho(np.broadcast_to(prof[:, None], (ny, 6))[None].copy())
+    o.step(steps)
+    o.update_derived()
+    return o.rho[0, 100, 0], o.rho[0, 0, 0], float(np.abs(o.velocity()).max())
+
+
+@pytest.mark.parametrize("Tr,steps,tol_l,tol_g", [(0.95, 60000, 5e-4, 1e-3), (0.8, 80000, 1e-4, 1e-2)])
+def test_flat_interface_reaches_maxwell_coexistence(Tr, steps, tol_l, tol_g):
+    # Sec. II B: with the force of Eq. 7 a flat interface at rest sits at the
+    # Maxwell coexistence densities of the Peng-Robinson EOS, up to the
+    # discretisation of a few-lattice-unit interface (smallest near Tc)
+    rl, rg, umax = _relaxed_slab(Tr, steps)
+    m = O.maxwell(Tr)
+    assert umax < 1e-6
+    assert abs(rl / m["rho_l"] - 1) < tol_l, (rl, m["rho_l"])
+    assert abs(rg / m["rho_g"] - 1) < tol_g, (rg, m["rho_g"])
+
+
+def test_flat_interface_gas_density_gap_at_tr_06():
+    # at Tr = 0.6 (density ratio about 850) the liquid still sits within 1e-3
+    # of Maxwell's value, but the gas settles near 3.5 times its value: the
+    # interface is about three lattice units thick and the fourth-order
+    # stencils do not resolve its gas side.  The gap is a property of the
+    # discretised model, recorded here so that a change to it shows.
+    rl, rg, umax = _relaxed_slab(0.6, 40000)
+    m = O.maxwell(0.6)
+    assert umax < 1e-3
+    assert abs(rl / m["rho_l"] - 1) < 1e-3
+    assert 3.0 < rg / m["rho_g"] < 4.0, rg / m["rho_g"]
+
+
 # ---------------------------------------------------------------- lattice, MRT, forcing
 
 
@@ -507,6 +547,236 @@ def test_one_step_matches_brute_force_on_8x8():
     assert np.max(np.abs(o.f[:, 0] - new)) < 1e-13 * np.max(np.abs(new))
 
 
+# ------------------------------ brute force with walls and a curved solid
+
+
+def _brute_lattice(dim):
+    """D2Q9 / D3Q19 from their definition: every e in {-1, 0, 1}^dim with
+    |e|^2 <= 2, weights 4/9, 1/9, 1/36 (2-D) and 1/3, 1/18, 1/36 (3-D) by
+    |e|^2; returned in the oracle's direction order (checked against it)."""
+    import itertools
+    es = [e for e in itertools.product((-1, 0, 1), repeat=dim) if sum(c * c for c in e) <= 2]
+    wt = {2: (4 / 9, 1 / 9, 1 / 36), 3: (1 / 3, 1 / 18, 1 / 36)}[dim]
+    eo, wo = O.lattice(dim)
+    assert len(es) == len(eo)
+    order = [es.index(tuple(int(v) for v in eo[i][:dim])) for i in range(len(eo))]
+    e = np.array([list(es[k]) + [0] * (3 - dim) for k in order], dtype=np.int64)
+    w = np.array([wt[sum(c * c for c in es[k])] for k in order])
+    assert np.array_equal(e, np.asarray(eo, dtype=np.int64)) and np.allclose(w, wo, rtol=0, atol=1e-16)
+    return e, w
+
+
+def _brute_moments(dim, tau, s_e, s_eps, s_q, s_pi=None, s_m=None):
+    """Moment rows as velocity polynomials with their rates: Lallemand-Luo for
+    D2Q9, d'Humieres et al. for D3Q19 (conserved moments at rate 0, the shear
+    stresses at 1 / tau)."""
+    sv = 1.0 / tau
+    if dim == 2:
+        return [(lambda x, y, z, c2: 1.0, 0), (lambda x, y, z, c2: -4 + 3 * c2, s_e),
+                (lambda x, y, z, c2: 4 - 10.5 * c2 + 4.5 * c2 * c2, s_eps), (lambda x, y, z, c2: x, 0),
+                (lambda x, y, z, c2: (-5 + 3 * c2) * x, s_q), (lambda x, y, z, c2: y, 0),
+                (lambda x, y, z, c2: (-5 + 3 * c2) * y, s_q), (lambda x, y, z, c2: x * x - y * y, sv),
+                (lambda x, y, z, c2: x * y, sv)]
+    return [(lambda x, y, z, c2: 1.0, 0), (lambda x, y, z, c2: 19 * c2 - 30, s_e),
+            (lambda x, y, z, c2: (21 * c2 * c2 - 53 * c2 + 24) / 2, s_eps),
+            (lambda x, y, z, c2: x, 0), (lambda x, y, z, c2: (5 * c2 - 9) * x, s_q),
+            (lambda x, y, z, c2: y, 0), (lambda x, y, z, c2: (5 * c2 - 9) * y, s_q),
+            (lambda x, y, z, c2: z, 0), (lambda x, y, z, c2: (5 * c2 - 9) * z, s_q),
+            (lambda x, y, z, c2: 3 * x * x - c2, sv), (lambda x, y, z, c2: (3 * c2 - 5) * (3 * x * x - c2), s_pi),
+            (lambda x, y, z, c2: y * y - z * z, sv), (lambda x, y, z, c2: (3 * c2 - 5) * (y * y - z * z), s_pi),
+            (lambda x, y, z, c2: x * y, sv), (lambda x, y, z, c2: y * z, sv), (lambda x, y, z, c2: x * z, sv),
+            (lambda x, y, z, c2: (y * y - z * z) * x, s_m), (lambda x, y, z, c2: (z * z - x * x) * y, s_m),
+            (lambda x, y, z, c2: (x * x - y * y) * z, s_m)]
+
+
+def _brute_step(dim, n, wall, f, prm, discs, wall_mu, bc):
+    """One whole step by the definitions, node by node: classes of Sec. III A
+    (solid = a disc/ball or the two outer layers of a wall axis; first layer =
+    solid with a fluid neighbour, second = solid with a first-layer one), the
+    fill of Eq. 14 (w-weighted mean of the fluid neighbours, then of the
+    first-layer ones), the chemical potential of Eq. 11 on fluid nodes and the
+    prescribed one on both layers, the force of Eq. 7 with gravity, the MRT
+    collision of Eq. 1 with the forcing of Eq. 13, and the pull streaming of
+    Eq. 4 with the missing populations from halfway bounce-back (bc 0) or
+    Bouzidi's linear interpolation (bc 1; q the root of |x + q e - C| = R
+    found by bisection, 1/2 at a wall), the difference to the bounced-back
+    population going to the rest population.  f is [Q][z][y][x]."""
+    from scipy.optimize import brentq
+    e, w = _brute_lattice(dim)
+    Q = len(w)
+    opp = [int(np.nonzero((e == -e[i]).all(1))[0][0]) for i in range(Q)]
+    nx, ny, nz = (list(n) + [1])[:3]
+    size = (nx, ny, nz)
+
+    def wrap(p):
+        # periodic axes wrap; a wall axis never needs to (two solid layers)
+        q = list(p)
+        for d in range(dim):
+            if q[d] < 0 or q[d] >= size[d]:
+                if wall[d]:
+                    return None
+                q[d] %= size[d]
+        return tuple(q)
+
+    def in_disc(p):
+        for c, r, muw in discs:
+            if sum((p[d] - c[d]) ** 2 for d in range(dim)) <= r * r:
+                return (c, r, muw)
+        return None
+
+    def in_wall(p):
+        return any(wall[d] and (p[d] < 2 or p[d] >= size[d] - 2) for d in range(dim))
+
+    nodes = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
+    solid = {p: bool(in_disc(p) or in_wall(p)) for p in nodes}
+    nbrs = {p: [wrap((p[0] + e[i][0], p[1] + e[i][1], p[2] + e[i][2])) for i in range(Q)] for p in nodes}
+    cls = {}
+    for p in nodes:
+        cls[p] = 0 if not solid[p] else (1 if any(m and not solid[m] for m in nbrs[p][1:]) else 3)
+    for p in nodes:
+        if cls[p] == 3 and any(m and cls[m] == 1 for m in nbrs[p][1:]):
+            cls[p] = 2
+    fx = {p: f[:, p[2], p[1], p[0]] for p in nodes}
+    rho = {p: fx[p].sum() if cls[p] == 0 else 0.0 for p in nodes}
+    for layer, src in ((1, 0), (2, 1)):
+        for p in nodes:
+            if cls[p] == layer:
+                ws = [(w[i], rho[m]) for i, m in enumerate(nbrs[p]) if i and m and cls[m] == src]
+                rho[p] = sum(a * b for a, b in ws) / sum(a for a, _ in ws)
+
+    def shift(p, ax, k):
+        q = list(p)
+        q[ax] += k
+        return wrap(tuple(q))
+
+    def d1(fld, p, ax):
+        v = [fld[shift(p, ax, k)] for k in (-2, -1, 1, 2)]
+        return (v[0] - 8 * v[1] + 8 * v[2] - v[3]) / 12.0
+
+    def d2(fld, p, ax):
+        v = [fld[shift(p, ax, k)] for k in (-2, -1, 0, 1, 2)]
+        return (-v[0] + 16 * v[1] - 30 * v[2] + 16 * v[3] - v[4]) / 12.0
+
+    k, kappa, T, al = prm["k"], prm["kappa"], prm["T"], prm["alpha"]
+    mu = {}
+    for p in nodes:
+        if cls[p] == 0:
+            mu[p] = k * k * O.pr_mu(rho[p], T, al) - kappa * sum(d2(rho, p, ax) for ax in range(dim))
+        elif cls[p] in (1, 2):
+            dsc = in_disc(p)
+            mu[p] = dsc[2] if dsc else wall_mu
+        else:
+            mu[p] = 0.0
+    rows = _brute_moments(dim, prm["tau"], prm["s_e"], prm["s_eps"], prm["s_q"], prm.get("s_pi"), prm.get("s_m"))
+    c2 = (e * e).sum(1)
+    M = np.array([[fn(*e[i], c2[i]) for i in range(Q)] for fn, _ in rows], dtype=np.float64)
+    S = np.diag([r for _, r in rows])
+    A = np.linalg.solve(M, S @ M)                          # M^-1 S M
+    g = np.array(prm["g"], dtype=np.float64)
+
+    def feq(r, u):
+        eu = e @ u
+        return w * r * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (u @ u))
+
+    post = {}
+    for p in nodes:
+        if cls[p] != 0:
+            post[p] = np.zeros(Q)
+            continue
+        r = rho[p]
+        F = np.zeros(3)
+        for ax in range(dim):
+            F[ax] = -r * d1(mu, p, ax) + d1(rho, p, ax) / 3.0 + r * g[ax]
+        u = (e.T @ fx[p]) / r
+        f0, f1 = feq(r, u), feq(r, u + F / r)
+        post[p] = fx[p] - A @ (fx[p] - f0) + f1 - f0
+
+    def link_q(p, j):
+        t = nbrs[p][j]
+        if in_wall(t):
+            return 0.5
+        c, rr, _ = in_disc(t)
+        dist = lambda s: math.sqrt(sum((p[d] + s * e[j][d] - c[d]) ** 2 for d in range(dim))) - rr  # noqa: E731
+        return brentq(dist, 0.0, 1.0, xtol=1e-15, rtol=1e-15)
+
+    out = np.zeros_like(f)
+    used_q = []
+    for p in nodes:
+        if cls[p] != 0:
+            continue
+        new = np.zeros(Q)
+        dm = 0.0
+        for i in range(1, Q):
+            src = wrap((p[0] - e[i][0], p[1] - e[i][1], p[2] - e[i][2]))
+            if cls[src] == 0:
+                new[i] = post[src][i]
+                continue
+            j = opp[i]
+            back = post[p][j]
+            val = back
+            if bc == 1:
+                q = link_q(p, j)
+                xb = nbrs[p][i]
+                if q < 0.5 and cls[xb] == 0:
+                    val = 2 * q * back + (1 - 2 * q) * post[xb][j]
+                    used_q.append(q)
+                elif q >= 0.5:
+                    val = back / (2 * q) + (2 * q - 1) / (2 * q) * post[p][i]
+                    used_q.append(q)
+            new[i] = val
+            dm += back - val
+        new[0] = post[p][0] + dm
+        out[:, p[2], p[1], p[0]] = new
+    return out, cls, used_q
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_one_step_with_walls_and_a_disc_matches_brute_force(bc):
+    """16 x 16 D2Q9: walls on y (two solid layers each side, their own wall
+    chemical potential), periodic x, an off-node disc of radius 3.4 with its
+    own, tilted gravity, and a non-uniform state with non-equilibrium parts;
+    one oracle step equals the brute-force step above to 1e-12, with the
+    interpolated wall using links on both sides of q = 1/2."""
+    prm = dict(Tr=0.8, k=0.28, kappa=0.01, tau=0.8, s_e=1.64, s_eps=1.54, s_q=1.9, g=(3e-4, -2e-4, 0.0))
+    o = O.Oracle(2, (16, 16), (0, 1), bc_mode=bc, wall_mu=0.021, **prm)
+    disc = ((7.3, 8.6), 3.4, 0.057)
+    o.add_sphere(disc[0], disc[1], mu_w=disc[2])
+    rng = np.random.Generator(np.random.PCG64(16))
+    o.set_rho(rng.uniform(1.0, 5.0, o.shape))
+    o.step(1)                                        # a state with non-equilibrium parts
+    f = o.f.copy()
+    inf = o.info()
+    prm.update(T=inf["T"], alpha=inf["alpha"])
+    new, cls, used = _brute_step(2, (16, 16), (0, 1), f, prm, [disc], 0.021, bc)
+    assert all(o.cls[0, y, x] == cls[(x, y, 0)] for y in range(16) for x in range(16))
+    assert {1, 2} <= set(cls.values())
+    if bc == 1:
+        assert min(used) < 0.35 and max(used) > 0.65 and any(abs(q - 0.5) < 1e-15 for q in used), sorted(used)
+    o.step(1)
+    assert np.max(np.abs(o.f - new)) < 1e-12 * np.max(np.abs(new))
+    # the fluid mass is what it was (the mass correction of the interpolated wall)
+    assert abs(new.sum() / f.sum() - 1) < 1e-13
+
+
+def test_one_step_d3q19_matches_brute_force_on_8x8x8():
+    """8 x 8 x 8 D3Q19, periodic x and y, walls on z (four fluid planes), MRT
+    with five distinct rates in the d'Humieres basis, gravity in all three
+    directions: one oracle step equals the brute-force step to 1e-12."""
+    prm = dict(Tr=0.8, k=0.28, kappa=0.01, tau=0.8, s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.3, s_m=1.7,
+               g=(2e-4, -1e-4, -3e-4))
+    o = O.Oracle(3, (8, 8, 8), (0, 0, 1), wall_mu=0.03, **prm)
+    rng = np.random.Generator(np.random.PCG64(8))
+    o.set_rho(rng.uniform(1.0, 5.0, o.shape))
+    o.step(1)
+    f = o.f.copy()
+    inf = o.info()
+    prm.update(T=inf["T"], alpha=inf["alpha"])
+    new, cls, _ = _brute_step(3, (8, 8, 8), (0, 0, 1), f, prm, [], 0.03, 0)
+    assert all(o.cls[z, y, x] == cls[(x, y, z)] for z in range(8) for y in range(8) for x in range(8))
+    o.step(1)
+    assert np.max(np.abs(o.f - new)) < 1e-12 * np.max(np.abs(new))
+
+
 # --------------------------------------------- unbalanced Young force (Eq. 17, 18)
 
 
@@ -731,6 +1001,57 @@ def test_3d_advancing_and_receding_follow_gravity(tilt):
     # with gravity along the axis there is no advancing side
     o = _film_on_sphere(90)
     assert math.isnan(o.measure(0, 32).adv_deg)
+
+
+def _sector_frame(a):
+    # the documented sector frame: b1 = the lattice axis least aligned with a
+    # (on a 1/1024 grid, ties to the lower axis), orthogonalised; b2 = a x b1
+    k = min(range(3), key=lambda d: (round(abs(a[d]) * 1024), d))
+    b1 = np.eye(3)[k] - a[k] * a
+    b1 /= np.linalg.norm(b1)
+    return b1, np.cross(a, b1)
+
+
+@pytest.mark.parametrize("psi_g", [30.0, -100.0, 150.0])
+def test_3d_sector_numbering_and_advancing_index(psi_g):
+    # the two-height film, with gravity's tangential part at azimuth psi_g:
+    # every sector's selected crossing lies in its own azimuth range, and
+    # adv / rec are (bit for bit) the sectors holding psi_g and psi_g + 180
+    (c, r) = SPHERE3
+    hl, hr = c[2] + r * math.cos(math.radians(70)), c[2] + r * math.cos(math.radians(110))
+    t, pg = math.radians(20.0), math.radians(psi_g)
+    g = np.array([1e-5 * math.sin(t) * math.cos(pg), 1e-5 * math.sin(t) * math.sin(pg), -1e-5 * math.cos(t)])
+    o = _film_on_sphere(None, g=tuple(g), heights=(hl, hr))
+    for ns in (16, 32, 64):
+        m = o.measure(0, ns)
+        assert m.status == 0 and m.n_valid == ns
+        a = np.array(m.axis)
+        b1, b2 = _sector_frame(a)
+
+        def sector(v):
+            psi = math.atan2(v @ b2, v @ b1)
+            return min(int(math.floor((psi + math.pi) / (2 * math.pi) * ns)), ns - 1)
+
+        def in_sector(v, s):
+            # a point on a sector border (here crossings on the lattice line
+            # through the centre) may fall either side at round-off
+            psi = math.atan2(v @ b2, v @ b1)
+            lo = -math.pi + 2 * math.pi * s / ns
+            hi = lo + 2 * math.pi / ns
+            near = lambda x, y: abs(math.remainder(x - y, 2 * math.pi)) < 1e-12  # noqa: E731
+            return sector(v) == s or near(psi, lo) or near(psi, hi)
+
+        for s in range(ns):
+            assert in_sector(np.array(m.p1[s]) - np.array(c), s)
+            assert in_sector(np.array(m.p2[s]) - np.array(c), s)
+        gt = g - (g @ a) * a
+        sa = sector(gt)
+        sr = (sa + ns // 2) % ns
+        assert m.adv_deg == m.sector_deg[sa] and m.rec_deg == m.sector_deg[sr]
+        # the neighbouring sectors read other angles, so an index one off would show
+        for s0 in (sa, sr):
+            v = m.sector_deg[s0]
+            assert v != m.sector_deg[(s0 + 1) % ns] and v != m.sector_deg[(s0 - 1) % ns]
 
 
 @pytest.mark.parametrize("bc", [0, 1])
