@@ -87,31 +87,34 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // Populations S_t of node idx for the walk's pipeline: every load is issued,
 // unconditionally and without waiting for an earlier one.  A link whose
 // source x - e_i is solid (bit opp(i) of the node's wall mask m) reads the
-// population that left x toward the wall (halfway bounce-back).  A lane with
-// no fluid node (live = false) reads its slots of the sink instead.
+// population that left x toward the wall (halfway bounce-back).  Opposite
+// directions are stored next to each other (i and opp(i) differ by one), so
+// both candidates are addressed from the array of the lower of the two with
+// one select of a 32-bit offset.  A lane on a solid node (mask 0) pulls from
+// its periodic neighbours like a fluid one: every offset is in bounds and
+// its values are never used.
 template <class L, typename R, bool PULL>
 __device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims& d, long long idx, int x, int y,
-                                             int z, uint32_t m, bool live, const R* __restrict__ sink, R S[L::Q]) {
-    const uint32_t ix = (uint32_t)idx, dx = (uint32_t)x;
+                                             int z, uint32_t m, R S[L::Q]) {
+    const uint32_t ix = (uint32_t)idx, N = (uint32_t)d.N;
     if (!PULL) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) S[i] = live ? at(f + (size_t)i * d.N, ix) : at(sink + i * 1024, dx);
+        for (int i = 0; i < L::Q; ++i) S[i] = at(f + (size_t)i * d.N, ix);
         return;
     }
     const int ox[3] = {x >= 1 ? -1 : d.nx - 1, 0, x + 1 < d.nx ? 1 : 1 - d.nx};
     const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.px, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.px};
     const int sz = d.px * d.ny;
     const int oz[3] = {(z >= 1 ? -1 : d.nz - 1) * sz, 0, (z + 1 < d.nz ? 1 : 1 - d.nz) * sz};
-    S[0] = live ? at(f, ix) : at(sink, dx);
+    S[0] = at(f, ix);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
-        const int j = L::OPP[i];
+        const int j = L::OPP[i], lo = i < j ? i : j;
+        static_assert(L::OPP[1] == 2 && L::OPP[18] == 17, "opposite directions are adjacent");
         const uint32_t pull = ix + (uint32_t)(ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]);
         const bool back = (m >> j) & 1u;
-        // one select of base and offset: the population that left x toward the
-        // wall, the pulled one, or the sink
-        const R* base = !live ? sink + i * 1024 : back ? f + (size_t)j * d.N : f + (size_t)i * d.N;
-        S[i] = at(base, !live ? dx : back ? ix : pull);
+        const uint32_t a = (i > lo ? N : 0u) + pull, b = (j > lo ? N : 0u) + ix;
+        S[i] = at(f + (size_t)lo * d.N, back ? b : a);
     }
 }
 
@@ -149,11 +152,13 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
     // n+2 and the class of node n+3 are in flight.  A wave's loads and stores
     // share one in-order counter, so loads issued after node n's stores would
     // also wait for them; issued before, they do not.  For the compiler to
-    // count them, every load and store of the walk is unconditional: lanes
-    // without a fluid node (and the walk's overrun past its last node) read
-    // and write their own slots of a small sink buffer, [19][1024] values,
-    // which nothing else reads.  (Only halfway bounce-back walls take this
-    // kernel: the interpolated wall's loads depend on one another.)
+    // count them, every load and store of the walk is unconditional: a lane
+    // on a solid node reads and writes that node's own population slots,
+    // which nothing else reads (the wall condition takes the populations of
+    // the fluid node itself, and reads of the state give zero on solids), and
+    // the walk's overrun past its last node reloads the last one.  (Only
+    // halfway bounce-back walls take this kernel: the interpolated wall's
+    // loads depend on one another.)
     // The lattice sizes and the thread's x pass through an empty asm per
     // node, so that what is derived from them (population and stencil
     // offsets) is recomputed instead of held across the walk; held, it spilled
@@ -191,28 +196,27 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
     // stencils (Eq. 7), loaded with the populations; under the pseudopotential
     // model from the array k_force filled
     ForceStencil<L, R> Gc, Gb;
-    auto issue = [&](int n, uint8_t c, uint32_t m, R S[L::Q], R F[3], ForceStencil<L, R>& G) {
+    auto issue = [&](int n, uint32_t m, R S[L::Q], R F[3], ForceStencil<L, R>& G) {
         Dims dd;
         int xx, y, z;
         fresh(dd, xx);
         node_of(n < nn ? n : nn - 1, y, z);
-        const bool live = n < nn && (c & CLS_MASK) == CLS_FLUID;
         const long long idx = nid(dd, xx, y, z);
-        const uint32_t ix = (uint32_t)idx, dx = (uint32_t)xx;
+        const uint32_t ix = (uint32_t)idx;
         if constexpr (SC) {
-            F[0] = live ? at(force, ix) : at(sink, dx);
-            F[1] = live ? at(force + dd.N, ix) : at(sink + 1024, dx);
-            F[2] = live ? at(force + 2 * dd.N, ix) : at(sink + 2048, dx);
+            F[0] = at(force, ix);
+            F[1] = at(force + dd.N, ix);
+            F[2] = at(force + 2 * dd.N, ix);
         } else {
             force_stencil_load<L, R, false>(rho, mu, dd, xx, y, z, G);  // every offset in bounds: unconditional
         }
-        gather_issue<L, R, PULL>(fin, dd, idx, xx, y, z, m, live, sink, S);
+        gather_issue<L, R, PULL>(fin, dd, idx, xx, y, z, m, S);
     };
 
     uint8_t c0 = load_cls(0), c1 = load_cls(1), c2 = load_cls(2);
     uint32_t m0 = load_mask(0, c0), m1 = load_mask(1, c1);
     R Sc[L::Q], Fc[3];
-    issue(0, c0, m0, Sc, Fc, Gc);
+    issue(0, m0, Sc, Fc, Gc);
 
 #pragma unroll 1
     for (int n = 0; n < nn; ++n) {
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
         const uint8_t c3 = load_cls(n + 3);
         const uint32_t m2 = load_mask(n + 2, c2);
         R Sb[L::Q], Fb[3];
-        issue(n + 1, c1, m1, Sb, Fb, Gb);
+        issue(n + 1, m1, Sb, Fb, Gb);
 
         // node n
         Dims dd;
@@ -234,21 +238,21 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
         {
             const bool live = (c0 & CLS_MASK) == CLS_FLUID;
             const long long idx = nid(dd, xx, y, z);
-            // the dead lanes' collision runs on sink values; its results go back
-            // to the sink and contribute nothing
+            // a solid node's collision runs on values nothing uses; its results
+            // go to its own slots and add nothing to the densities
             R fo[L::Q];
-            double Fx, Fy, Fz;
+            C Fx, Fy, Fz;
             if constexpr (SC) {
-                Fx = (double)Fc[0];
-                Fy = (double)Fc[1];
-                Fz = (double)Fc[2];
+                Fx = (C)Fc[0];
+                Fy = (C)Fc[1];
+                Fz = (C)Fc[2];
             } else {
                 force_from_stencil<L, R, C, false>(Gc, cp, tstep, Fx, Fy, Fz);
             }
             collide_values<L, R, C, MRT>(Sc, Fx, Fy, Fz, cp, fo);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                put<true>(live ? &at(fout + (size_t)i * dd.N, (uint32_t)idx) : &at(sink + i * 1024, (uint32_t)xx), fo[i]);
+                put<true>(&at(fout + (size_t)i * dd.N, (uint32_t)idx), fo[i]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
                 const C fi = live ? (C)fo[i] : C(0);

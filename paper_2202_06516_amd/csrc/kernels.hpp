@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const 
 // collision + push streaming
 // ---------------------------------------------------------------------------
 template <class L, typename R, typename C, bool MRT, bool NT>
-__device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
+__device__ __forceinline__ void collide_apply(const R S[L::Q], C Fx, C Fy, C Fz, const Collision<C>& cp,
                                               R* __restrict__ fout, long long idx, long long N);
 
 // offset of the lattice neighbour x + e along one axis (e in {-1, 0, 1})
@@ -635,23 +635,30 @@ __device__ __forceinline__ void sc_force(const R* __restrict__ psi, long long id
 // Force at a node: Eq. 7 with fourth-order central differences (or the
 // pseudopotential interaction), plus the body force from step g_start.  The
 // stencil loads need no class: every offset is in bounds (periodic images).
-// The two terms of Eq. 7 cancel almost exactly inside an interface at rest,
-// so F, and the moments it shifts, are formed in double precision whatever the
-// storage type.
+// Formed in double whatever the storage and arithmetic types: the fourth-order
+// differences of the density span the jump across an interface (a factor of
+// up to 40 between neighbours), where single precision would leave an error of
+// order 1e-7 in F that is the same step after step, so the interface would
+// drift; and the two terms of Eq. 7 cancel almost exactly inside an interface
+// at rest.  F is then rounded to the arithmetic type C.
 template <class L, typename R, typename C, bool SC>
 __device__ __forceinline__ void force_at(const R* __restrict__ rho, const R* __restrict__ mu, const Dims& d,
                                          long long idx, int x, int y, int z, const Collision<C>& cp, long long t,
-                                         double& Fx, double& Fy, double& Fz) {
+                                         C& Fx, C& Fy, C& Fz) {
     const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
     if constexpr (SC) {
         const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
-        sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, Fx, Fy, Fz);
+        double fx, fy, fz;
+        sc_force<L, R>(mu, idx, ox, oy, oz, cp.sc_G, fx, fy, fz);
         if (t >= cp.g_start) {
             const double r0 = (double)rho[idx];
-            Fx += r0 * (double)cp.g[0];
-            Fy += r0 * (double)cp.g[1];
-            Fz += r0 * (double)cp.g[2];
+            fx += r0 * (double)cp.g[0];
+            fy += r0 * (double)cp.g[1];
+            fz += r0 * (double)cp.g[2];
         }
+        Fx = (C)fx;
+        Fy = (C)fy;
+        Fz = (C)fz;
         return;
     }
     typedef double D;
@@ -670,14 +677,17 @@ __device__ __forceinline__ void force_at(const R* __restrict__ rho, const R* __r
         grz = d1c<D>(pr(oz.m2), pr(oz.m1), pr(oz.p1), pr(oz.p2));
     }
     const D third = D(1.0 / 3.0);
-    Fx = -r0 * gmx + grx * third;
-    Fy = -r0 * gmy + gry * third;
-    Fz = -r0 * gmz + grz * third;
+    D fx = -r0 * gmx + grx * third;
+    D fy = -r0 * gmy + gry * third;
+    D fz = -r0 * gmz + grz * third;
     if (t >= cp.g_start) {
-        Fx += r0 * (D)cp.g[0];
-        Fy += r0 * (D)cp.g[1];
-        Fz += r0 * (D)cp.g[2];
+        fx += r0 * (D)cp.g[0];
+        fy += r0 * (D)cp.g[1];
+        fz += r0 * (D)cp.g[2];
     }
+    Fx = (C)fx;
+    Fy = (C)fy;
+    Fz = (C)fz;
 }
 
 // The force of every node into F ([3][N], storage precision) for the one-pass
@@ -733,9 +743,11 @@ __device__ __forceinline__ void force_stencil_load(const R* __restrict__ rho, co
 
 template <class L, typename R, typename C, bool SC>
 __device__ __forceinline__ void force_from_stencil(const ForceStencil<L, R>& s, const Collision<C>& cp, long long t,
-                                                   double& Fx, double& Fy, double& Fz) {
+                                                   C& Fx, C& Fy, C& Fz) {
+    // in double, as force_at
     typedef double D;
     const D r0 = (D)s.v[0];
+    D fx, fy, fz;
     if constexpr (SC) {
         double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
@@ -746,9 +758,9 @@ __device__ __forceinline__ void force_from_stencil(const ForceStencil<L, R>& s, 
             sz += v * L::E[i][2];
         }
         const double p0 = (double)s.v[L::Q];
-        Fx = -cp.sc_G * p0 * sx;
-        Fy = -cp.sc_G * p0 * sy;
-        Fz = -cp.sc_G * p0 * sz;
+        fx = -cp.sc_G * p0 * sx;
+        fy = -cp.sc_G * p0 * sy;
+        fz = -cp.sc_G * p0 * sz;
     } else {
         D gr[3], gm[3];
 #pragma unroll
@@ -757,15 +769,18 @@ __device__ __forceinline__ void force_from_stencil(const ForceStencil<L, R>& s, 
             gm[a] = d1c<D>((D)s.v[13 + 4 * a], (D)s.v[14 + 4 * a], (D)s.v[15 + 4 * a], (D)s.v[16 + 4 * a]);
         }
         const D third = D(1.0 / 3.0);
-        Fx = -r0 * gm[0] + gr[0] * third;
-        Fy = -r0 * gm[1] + gr[1] * third;
-        Fz = L::D == 3 ? -r0 * gm[2] + gr[2] * third : D(0);
+        fx = -r0 * gm[0] + gr[0] * third;
+        fy = -r0 * gm[1] + gr[1] * third;
+        fz = L::D == 3 ? -r0 * gm[2] + gr[2] * third : D(0);
     }
     if (t >= cp.g_start) {
-        Fx += r0 * (D)cp.g[0];
-        Fy += r0 * (D)cp.g[1];
-        Fz += r0 * (D)cp.g[2];
+        fx += r0 * (D)cp.g[0];
+        fy += r0 * (D)cp.g[1];
+        fz += r0 * (D)cp.g[2];
     }
+    Fx = (C)fx;
+    Fy = (C)fy;
+    Fz = (C)fz;
 }
 
 template <class L, typename R, typename C, bool SC>
@@ -782,7 +797,7 @@ __global__ void __launch_bounds__(256) k_force(const R* __restrict__ rho, const 
     force_stencil_load<L, R, SC>(rho, mu, d, x, y, z0, cur);
     for (int z = z0; z < z1; ++z) {
         force_stencil_load<L, R, SC>(rho, mu, d, x, y, z + 1 < z1 ? z + 1 : z, nxt);  // unconditional: counted
-        double Fx, Fy, Fz;
+        C Fx, Fy, Fz;
         force_from_stencil<L, R, C, SC>(cur, cp, t, Fx, Fy, Fz);
         const uint32_t ix = (uint32_t)nid(d, x, y, z);
         at(F, ix) = (R)Fx;
@@ -803,7 +818,7 @@ __device__ __forceinline__ void collide_node(const R* __restrict__ fin, R* __res
     const uint8_t c = at(cls, (uint32_t)idx);
     // the force is formed before the class test so that its stencil loads go
     // out with the class load
-    double Fx, Fy, Fz;
+    C Fx, Fy, Fz;
     force_at<L, R, C, SC>(rho, mu, d, idx, x, y, z, cp, t, Fx, Fy, Fz);
     asm volatile("" : : "v"(Fx), "v"(Fy), "v"(Fz));  // keeps the loads above the class test
     if ((c & CLS_MASK) != CLS_FLUID) return;
@@ -849,23 +864,47 @@ __device__ __forceinline__ void feq_all(C rs, C ax, C ay, C az, C out[L::Q]) {
 
 // The post-collision populations of one node into fo (storage type).
 template <class L, typename R, typename C, bool MRT>
-__device__ __forceinline__ void collide_values(const R S[L::Q], double Fx, double Fy, double Fz,
-                                               const Collision<C>& cp, R fo[L::Q]) {
-    typedef double D;
-    // moments of S: density and velocity (Eq. 2 arguments), in double
-    D rd = D(0), jx = D(0), jy = D(0), jz = D(0);
+__device__ __forceinline__ void collide_values(const R S[L::Q], C Fx, C Fy, C Fz, const Collision<C>& cp,
+                                               R fo[L::Q]) {
+    // the density moment of S (Eq. 2 argument) in double: the rest population
+    // below takes the remainder of it
+    double rd = 0.0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const D fi = (D)S[i];
-        rd += fi;
-        if (L::E[i][0]) jx += D(L::E[i][0]) * fi;
-        if (L::E[i][1]) jy += D(L::E[i][1]) * fi;
-        if (L::E[i][2]) jz += D(L::E[i][2]) * fi;
+    for (int i = 0; i < L::Q; ++i) rd += (double)S[i];
+    C rs, ux, uy, uz, vx, vy, vz;
+    if constexpr (sizeof(C) == 8) {
+        typedef double D;
+        D jx = D(0), jy = D(0), jz = D(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const D fi = (D)S[i];
+            if (L::E[i][0]) jx += D(L::E[i][0]) * fi;
+            if (L::E[i][1]) jy += D(L::E[i][1]) * fi;
+            if (L::E[i][2]) jz += D(L::E[i][2]) * fi;
+        }
+        const D ird = D(1) / rd;
+        rs = (C)rd;
+        ux = (C)(jx * ird), uy = (C)(jy * ird), uz = (C)(jz * ird);
+        vx = (C)((jx + Fx) * ird), vy = (C)((jy + Fy) * ird), vz = (C)((jz + Fz) * ird);  // u + F/rho (Eq. 13)
+    } else {
+        // FP32 arithmetic: the momentum from the differences of opposite
+        // populations, which are exact where the two differ by less than a
+        // factor of two (the populations near equilibrium), and 1 / rho from
+        // the hardware reciprocal (1 ulp)
+        C jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            if (L::OPP[i] < i) continue;
+            const C df = (C)S[i] - (C)S[L::OPP[i]];
+            if (L::E[i][0]) jx += C(L::E[i][0]) * df;
+            if (L::E[i][1]) jy += C(L::E[i][1]) * df;
+            if (L::E[i][2]) jz += C(L::E[i][2]) * df;
+        }
+        rs = (C)rd;
+        const C ir = __builtin_amdgcn_rcpf(rs);
+        ux = jx * ir, uy = jy * ir, uz = jz * ir;
+        vx = (jx + Fx) * ir, vy = (jy + Fy) * ir, vz = (jz + Fz) * ir;  // u + F/rho (Eq. 13)
     }
-    const D ird = D(1) / rd;
-    const C rs = (C)rd;
-    const C ux = (C)(jx * ird), uy = (C)(jy * ird), uz = (C)(jz * ird);
-    const C vx = (C)((jx + Fx) * ird), vy = (C)((jy + Fy) * ird), vz = (C)((jz + Fz) * ird);  // u + F/rho (Eq. 13)
 
     // With FP32 arithmetic the lattice weights are rounded (1/3, 1/18 and 1/36
     // in binary32 sum to 1 + 1.5e-8), so every collision would add that share
@@ -952,7 +991,7 @@ __device__ __forceinline__ void collide_values(const R S[L::Q], double Fx, doubl
 // Collision of one node with its post-collision populations stored at the
 // node, o[i * N] (aligned stores; streaming is the next step's pull).
 template <class L, typename R, typename C, bool MRT, bool NT>
-__device__ __forceinline__ void collide_apply(const R S[L::Q], double Fx, double Fy, double Fz, const Collision<C>& cp,
+__device__ __forceinline__ void collide_apply(const R S[L::Q], C Fx, C Fy, C Fz, const Collision<C>& cp,
                                               R* __restrict__ fout, long long idx, long long N) {
     R fo[L::Q];
     collide_values<L, R, C, MRT>(S, Fx, Fy, Fz, cp, fo);
