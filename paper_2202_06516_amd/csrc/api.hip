@@ -444,8 +444,9 @@ struct Run {
             {
                 const int ein = 2 * (c->d.ny / kFusedTY);
                 const long long rows = (long long)(c->d.nz / c->fzc) * (2LL * c->d.ny + (long long)(c->fzc - 2) * ein);
-                k_ghost<R, kFusedTY><<<(unsigned)rows, (unsigned)c->d.nx, 0, c->stream>>>(rnext, (const R*)c->gy, (const R*)c->gz,
-                                                                            (const R*)c->gyz, c->d, c->fzc);
+                const long long thr = rows * (c->d.nx / 4);
+                k_ghost<R, kFusedTY><<<(unsigned)((thr + 255) / 256), 256, 0, c->stream>>>(
+                    rnext, (const R*)c->gy, (const R*)c->gz, (const R*)c->gyz, c->d, c->fzc, rows);
             }
             mark(8);
             fills_on(c, rnext, ev, kinds, k);
@@ -749,11 +750,11 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (cfg->step_kernel != LBM_STEP_AUTO && cfg->step_kernel != LBM_STEP_SPLIT) return bad("step_kernel");
     {
         // the one-pass step: D3Q19 with halfway bounce-back walls, whole rows of
-        // 64..1024 nodes per workgroup, 4 rows, zc planes (LBM_FUSED_ZC overrides 2: at 256^3
-        // the walk over 2, 4, 8, 16 planes took 0.79, 0.82, 0.87, 0.89 ms; the ghost sums
-        // 0.098, 0.067, 0.053, 0.046 ms)
+        // 64..1024 nodes per workgroup, 4 rows, zc planes (LBM_FUSED_ZC overrides 8, halved
+        // until it divides nz: at 256^3 the walk over 2, 4, 8 planes took 0.622, 0.606,
+        // 0.607 ms and the ghost sums 0.043, 0.031, 0.025 ms)
         const char* e = std::getenv("LBM_FUSED_ZC");
-        int zc = e ? std::atoi(e) : 2;
+        int zc = e ? std::atoi(e) : 8;
         while (zc > 2 && c->d.nz % zc) zc >>= 1;
         c->fzc = zc;
         c->fused = cfg->step_kernel == LBM_STEP_AUTO && c->dim == 3 && cfg->bc_mode == LBM_BC_HALFWAY &&

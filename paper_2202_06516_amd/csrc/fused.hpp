@@ -107,13 +107,15 @@ __device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims
     const int sz = d.px * d.ny;
     const int oz[3] = {(z >= 1 ? -1 : d.nz - 1) * sz, 0, (z + 1 < d.nz ? 1 : 1 - d.nz) * sz};
     S[0] = at(f, ix);
+    auto pull = [&](int i) {
+        return ix + (uint32_t)(ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]);
+    };
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int j = L::OPP[i], lo = i < j ? i : j;
         static_assert(L::OPP[1] == 2 && L::OPP[18] == 17, "opposite directions are adjacent");
-        const uint32_t pull = ix + (uint32_t)(ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]);
         const bool back = (m >> j) & 1u;
-        const uint32_t a = (i > lo ? N : 0u) + pull, b = (j > lo ? N : 0u) + ix;
+        const uint32_t a = (i > lo ? N : 0u) + pull(i), b = (j > lo ? N : 0u) + ix;
         S[i] = at(f + (size_t)lo * d.N, back ? b : a);
     }
 }
@@ -351,18 +353,23 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
 }
 
 // Adds the ghost sums to the edge rows (y % TY in {0, TY-1}) and edge planes
-// (z % zc in {0, zc-1}) of k_step's tiles.  Workgroup k takes row k of a list
-// of the edge rows only: per chunk of zc planes, its two edge planes whole,
-// then the 2 ny/TY edge rows of each plane between them.  (One row per
-// workgroup: a workgroup walking several rows would wait for each row's
-// stores before its next loads.)
+// (z % zc in {0, zc-1}) of k_step's tiles.  The edge rows are listed per chunk
+// of zc planes: its two edge planes whole, then the 2 ny/TY edge rows of each
+// plane between them.  A thread takes four consecutive nodes of a listed row
+// (rows start on 64-node boundaries, so the four are one aligned vector);
+// nrows rows in all.
 template <typename R, int TY>
-__global__ void __launch_bounds__(1024) k_ghost(R* __restrict__ rho, const R* __restrict__ gy,
-                                                const R* __restrict__ gz, const R* __restrict__ gyz, Dims d, int zc) {
+__global__ void __launch_bounds__(256) k_ghost(R* __restrict__ rho, const R* __restrict__ gy,
+                                               const R* __restrict__ gz, const R* __restrict__ gyz, Dims d, int zc,
+                                               long long nrows) {
+    typedef R V __attribute__((ext_vector_type(4)));
+    const unsigned q = (unsigned)d.nx >> 2;
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (g >= nrows * (long long)q) return;
+    const long long k = g / q;
+    const int x = (int)(g - k * q) * 4;
     const int ein = 2 * (d.ny / TY);
     const long long per_chunk = 2LL * d.ny + (long long)(zc - 2) * ein;
-    const long long k = blockIdx.x;
-    const int x = threadIdx.x;
     const int ch = (int)(k / per_chunk);
     long long rem = k - (long long)ch * per_chunk;
     int y, z;
@@ -381,11 +388,20 @@ __global__ void __launch_bounds__(1024) k_ghost(R* __restrict__ rho, const R* __
     const int ry = y % TY, rz = z % zc;
     const bool ey = ry == 0 || ry == TY - 1, ez = rz == 0 || rz == zc - 1;
     const long long n = nid(d, x, y, z);
-    double v = (double)rho[n];
-    if (ey) v += (double)gy[n];
-    if (ez) v += (double)gz[n];
-    if (ey && ez) v += (double)gyz[n];
-    rho[n] = (R)v;
+    const V r = *(const V*)(rho + n);
+    const V a = ey ? *(const V*)(gy + n) : V(0);
+    const V b = ez ? *(const V*)(gz + n) : V(0);
+    const V c = (ey && ez) ? *(const V*)(gyz + n) : V(0);
+    V out;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        double v = (double)r[e];
+        if (ey) v += (double)a[e];
+        if (ez) v += (double)b[e];
+        if (ey && ez) v += (double)c[e];
+        out[e] = (R)v;
+    }
+    *(V*)(rho + n) = out;
 }
 
 // block reduction (256 threads) of per-thread liquid centroid sums
