@@ -757,8 +757,12 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         int zc = e ? std::atoi(e) : 8;
         while (zc > 2 && c->d.nz % zc) zc >>= 1;
         c->fzc = zc;
+        // (its node indices and the byte offsets of its population accesses, up to
+        // five arrays from one base, are 32-bit)
+        const size_t elem = cfg->precision == LBM_F64 ? 8 : 4;
         c->fused = cfg->step_kernel == LBM_STEP_AUTO && c->dim == 3 && cfg->bc_mode == LBM_BC_HALFWAY &&
-                   c->d.nx % 64 == 0 && c->d.nx <= 1024 && c->d.ny % kFusedTY == 0 && zc >= 2 && c->d.nz % zc == 0;
+                   c->d.nx % 64 == 0 && c->d.nx <= 1024 && c->d.ny % kFusedTY == 0 && zc >= 2 && c->d.nz % zc == 0 &&
+                   5ull * (unsigned long long)N * elem < (1ull << 32);
     }
     c->pr.a = cfg->pr_a;
     c->pr.b = cfg->pr_b;

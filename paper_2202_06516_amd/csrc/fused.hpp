@@ -94,9 +94,9 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // its periodic neighbours like a fluid one: every offset is in bounds and
 // its values are never used.
 template <class L, typename R, bool PULL>
-__device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims& d, long long idx, int x, int y,
+__device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims& d, uint32_t ix, int x, int y,
                                              int z, uint32_t m, R S[L::Q]) {
-    const uint32_t ix = (uint32_t)idx, N = (uint32_t)d.N;
+    const uint32_t N = (uint32_t)d.N;
     if (!PULL) {
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) S[i] = at(f + (size_t)i * d.N, ix);
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
         int xx, y, z;
         fresh(dd, xx);
         node_of(n < nn ? n : nn - 1, y, z);
-        return at(cls, (uint32_t)nid(dd, xx, y, z));
+        return at(cls, nid32(dd, xx, y, z));
     };
     // the wall mask of a boundary fluid node, else a shared dummy read
     auto load_mask = [&](int n, uint8_t c) -> uint32_t {
@@ -191,20 +191,19 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
         fresh(dd, xx);
         node_of(n < nn ? n : nn - 1, y, z);
         const bool b = n < nn && (c & CLS_BOUNDARY) && (c & CLS_MASK) == CLS_FLUID;
-        const uint32_t m = at(bc.nbmask, b ? (uint32_t)nid(dd, xx, y, z) : 0u);
+        const uint32_t m = at(bc.nbmask, b ? nid32(dd, xx, y, z) : 0u);
         return b ? m : 0u;
     };
     // the force: under the chemical-potential model from the rho and mu
     // stencils (Eq. 7), loaded with the populations; under the pseudopotential
     // model from the array k_force filled
-    ForceStencil<L, R> Gc, Gb;
+    ForceStencil<L, R> Ga, Gb;
     auto issue = [&](int n, uint32_t m, R S[L::Q], R F[3], ForceStencil<L, R>& G) {
         Dims dd;
         int xx, y, z;
         fresh(dd, xx);
         node_of(n < nn ? n : nn - 1, y, z);
-        const long long idx = nid(dd, xx, y, z);
-        const uint32_t ix = (uint32_t)idx;
+        const uint32_t ix = nid32(dd, xx, y, z);
         if constexpr (SC) {
             F[0] = at(force, ix);
             F[1] = at(force + dd.N, ix);
@@ -212,55 +211,59 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
         } else {
             force_stencil_load<L, R, false>(rho, mu, dd, xx, y, z, G);  // every offset in bounds: unconditional
         }
-        gather_issue<L, R, PULL>(fin, dd, idx, xx, y, z, m, S);
+        gather_issue<L, R, PULL>(fin, dd, ix, xx, y, z, m, S);
     };
 
     uint8_t c0 = load_cls(0), c1 = load_cls(1), c2 = load_cls(2);
     uint32_t m0 = load_mask(0, c0), m1 = load_mask(1, c1);
-    R Sc[L::Q], Fc[3];
-    issue(0, m0, Sc, Fc, Gc);
 
-#pragma unroll 1
-    for (int n = 0; n < nn; ++n) {
+    // One node of the walk: node n from the stage (Scur, Fcur, Gcur), while
+    // node n + 1 is issued into (Snext, Fnext, Gnext).
+    auto node = [&](int n, R(&Scur)[L::Q], R(&Fcur)[3], ForceStencil<L, R>& Gcur, R(&Snext)[L::Q],
+                    R(&Fnext)[3], ForceStencil<L, R>& Gnext) {
         // stages ahead: class of n+3, wall mask of n+2, populations of n+1
         const uint8_t c3 = load_cls(n + 3);
         const uint32_t m2 = load_mask(n + 2, c2);
-        R Sb[L::Q], Fb[3];
-        issue(n + 1, m1, Sb, Fb, Gb);
+        issue(n + 1, m1, Snext, Fnext, Gnext);
 
-        // node n
         Dims dd;
         int xx, y, z;
         fresh(dd, xx);
         node_of(n, y, z);
         const int r = n % TY, zz = n / TY, par = zz & 1;
         const int sc = z % 3, sn = (z + 1) % 3, sp = (z + 2) % 3;  // slots of planes z, z + 1, z - 1
-        C v[L::Q];     // what leaves x toward fluid nodes; zero where it returns from a wall
+        // What leaves x: f*_i, or nothing from a solid node.  A population that
+        // leaves toward a wall is also added to the solid node it points to;
+        // that node is on the first solid layer, whose density the fill of
+        // Eq. 14 sets afterwards, so the addition is harmless and saves a select.
+        C v[L::Q];
         C own = C(0);  // what the wall returns to x
         {
             const bool live = (c0 & CLS_MASK) == CLS_FLUID;
-            const long long idx = nid(dd, xx, y, z);
+            const uint32_t idx = nid32(dd, xx, y, z);
             // a solid node's collision runs on values nothing uses; its results
             // go to its own slots and add nothing to the densities
             R fo[L::Q];
             C Fx, Fy, Fz;
             if constexpr (SC) {
-                Fx = (C)Fc[0];
-                Fy = (C)Fc[1];
-                Fz = (C)Fc[2];
+                Fx = (C)Fcur[0];
+                Fy = (C)Fcur[1];
+                Fz = (C)Fcur[2];
             } else {
-                force_from_stencil<L, R, C, false>(Gc, cp, tstep, Fx, Fy, Fz);
+                force_from_stencil<L, R, C, false>(Gcur, cp, tstep, Fx, Fy, Fz);
             }
-            collide_values<L, R, C, MRT>(Sc, Fx, Fy, Fz, cp, fo);
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i)
-                put<true>(&at(fout + (size_t)i * dd.N, (uint32_t)idx), fo[i]);
+            collide_values<L, R, C, MRT>(Scur, Fx, Fy, Fz, cp, fo);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
-                const C fi = live ? (C)fo[i] : C(0);
-                const bool back = (m0 >> i) & 1u;
-                v[i] = back ? C(0) : fi;
-                own += back ? fi : C(0);
+                // five arrays per base address, 32-bit offsets from it
+                const int g = i / 5 * 5;
+                put<true>(&at(fout + (size_t)g * dd.N, (uint32_t)(i - g) * (uint32_t)dd.N + idx), fo[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) v[i] = live ? (C)fo[i] : C(0);
+            if (__builtin_amdgcn_ballot_w64(m0 != 0u) != 0) {  // a wave with wall links (uniform branch)
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) own += ((m0 >> i) & 1u) ? v[i] : C(0);
             }
         }
         // row groups with their x shifts
@@ -310,32 +313,40 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
             if (zz == 0) {
                 const int zg = z0 >= 1 ? z0 - 1 : dd.nz - 1;
 #pragma unroll
-                for (int rr = 0; rr < TY; ++rr) gz[nid(dd, xx, y0 + rr, zg)] = (R)a[rr + 1];
-                gyz[nid(dd, xx, ylo, zg)] = (R)a[0];
-                gyz[nid(dd, xx, yhi, zg)] = (R)a[TY + 1];
+                for (int rr = 0; rr < TY; ++rr) at(gz, nid32(dd, xx, y0 + rr, zg)) = (R)a[rr + 1];
+                at(gyz, nid32(dd, xx, ylo, zg)) = (R)a[0];
+                at(gyz, nid32(dd, xx, yhi, zg)) = (R)a[TY + 1];
             } else {
 #pragma unroll
-                for (int rr = 0; rr < TY; ++rr) rho_next[nid(dd, xx, y0 + rr, z - 1)] = (R)a[rr + 1];
-                gy[nid(dd, xx, ylo, z - 1)] = (R)a[0];
-                gy[nid(dd, xx, yhi, z - 1)] = (R)a[TY + 1];
+                for (int rr = 0; rr < TY; ++rr) at(rho_next, nid32(dd, xx, y0 + rr, z - 1)) = (R)a[rr + 1];
+                at(gy, nid32(dd, xx, ylo, z - 1)) = (R)a[0];
+                at(gy, nid32(dd, xx, yhi, z - 1)) = (R)a[TY + 1];
             }
         }
 
-        // advance the pipeline
+        // advance the class and mask stages
         c0 = c1;
         c1 = c2;
         c2 = c3;
         m0 = m1;
         m1 = m2;
+    };
+
+    R Sa[L::Q], Fa[3], Sb[L::Q], Fb[3];
+    issue(0, m0, Sa, Fa, Ga);
+#pragma unroll 1
+    for (int n = 0; n < nn; ++n) {
+        node(n, Sa, Fa, Ga, Sb, Fb, Gb);
+        // advance the population stage
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) Sc[i] = Sb[i];
+        for (int i = 0; i < L::Q; ++i) Sa[i] = Sb[i];
         if constexpr (SC) {
-            Fc[0] = Fb[0];
-            Fc[1] = Fb[1];
-            Fc[2] = Fb[2];
+            Fa[0] = Fb[0];
+            Fa[1] = Fb[1];
+            Fa[2] = Fb[2];
         } else {
 #pragma unroll
-            for (int k = 0; k < ForceStencil<L, R>::K; ++k) Gc.v[k] = Gb.v[k];
+            for (int k = 0; k < ForceStencil<L, R>::K; ++k) Ga.v[k] = Gb.v[k];
         }
     }
     // the chunk's last plane, and the plane above the chunk (the z neighbour's)
@@ -343,13 +354,13 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
     const int sl = zl % 3, sg = (zl + 1) % 3;
 #pragma unroll
     for (int r = 0; r < TY; ++r) {
-        rho_next[nid(d, x, y0 + r, zl)] = (R)acc[r + 1][sl][x];
-        gz[nid(d, x, y0 + r, zg)] = (R)acc[r + 1][sg][x];
+        at(rho_next, nid32(d, x, y0 + r, zl)) = (R)acc[r + 1][sl][x];
+        at(gz, nid32(d, x, y0 + r, zg)) = (R)acc[r + 1][sg][x];
     }
-    gy[nid(d, x, ylo, zl)] = (R)acc[0][sl][x];
-    gy[nid(d, x, yhi, zl)] = (R)acc[TY + 1][sl][x];
-    gyz[nid(d, x, ylo, zg)] = (R)acc[0][sg][x];
-    gyz[nid(d, x, yhi, zg)] = (R)acc[TY + 1][sg][x];
+    at(gy, nid32(d, x, ylo, zl)) = (R)acc[0][sl][x];
+    at(gy, nid32(d, x, yhi, zl)) = (R)acc[TY + 1][sl][x];
+    at(gyz, nid32(d, x, ylo, zg)) = (R)acc[0][sg][x];
+    at(gyz, nid32(d, x, yhi, zg)) = (R)acc[TY + 1][sg][x];
 }
 
 // Adds the ghost sums to the edge rows (y % TY in {0, TY-1}) and edge planes

@@ -54,6 +54,10 @@ struct Dims {
 __device__ __forceinline__ long long nid(const Dims& d, int x, int y, int z) {
     return d.off + ((long long)z * d.ny + y) * d.px + x;
 }
+// the same in 32 bits, for lattices of fewer than 2^32 packed nodes
+__device__ __forceinline__ uint32_t nid32(const Dims& d, int x, int y, int z) {
+    return (uint32_t)d.off + ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.px + (uint32_t)x;
+}
 
 // Node of this thread in tile t (x fastest, then y, then z).
 __device__ __forceinline__ void tile_coords(const Dims& d, unsigned t, int& x, int& y, int& z) {
@@ -706,10 +710,10 @@ struct ForceStencil {
 template <class L, typename R, bool SC>
 __device__ __forceinline__ void force_stencil_load(const R* __restrict__ rho, const R* __restrict__ mu, const Dims& d,
                                                    int x, int y, int z, ForceStencil<L, R>& s) {
-    const long long idx = nid(d, x, y, z);
     const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
     const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
     if constexpr (SC) {
+        const long long idx = nid(d, x, y, z);
         // psi at the lattice neighbours, rho at the node
         s.v[0] = rho[idx];
 #pragma unroll
@@ -722,7 +726,7 @@ __device__ __forceinline__ void force_stencil_load(const R* __restrict__ rho, co
         return;
     }
     const Nbr ax[3] = {ox, oy, oz};
-    const uint32_t ix = (uint32_t)idx;
+    const uint32_t ix = nid32(d, x, y, z);
     s.v[0] = at(rho, ix);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
