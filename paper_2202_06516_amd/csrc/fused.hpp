@@ -84,6 +84,12 @@ static_assert(RowGroups::GRP[0][0] == 0 && RowGroups::PP > 0 && RowGroups::MM > 
 // outstanding global load and store, which would drain the walk's pipeline.)
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// A streaming load: the populations are read once per step, and marked so
+// that they leave the caches first, before the density and chemical-potential
+// planes that the force stencils of the next nodes read again.
+template <typename R>
+__device__ __forceinline__ R ldnt(const R* p) { return __builtin_nontemporal_load(p); }
+
 // Populations S_t of node idx for the walk's pipeline: every load is issued,
 // unconditionally and without waiting for an earlier one.  A link whose
 // source x - e_i is solid (bit opp(i) of the node's wall mask m) reads the
@@ -99,14 +105,14 @@ __device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims
     const uint32_t N = (uint32_t)d.N;
     if (!PULL) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) S[i] = at(f + (size_t)i * d.N, ix);
+        for (int i = 0; i < L::Q; ++i) S[i] = ldnt(&at(f + (size_t)i * d.N, ix));
         return;
     }
     const int ox[3] = {x >= 1 ? -1 : d.nx - 1, 0, x + 1 < d.nx ? 1 : 1 - d.nx};
     const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.px, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.px};
     const int sz = d.px * d.ny;
     const int oz[3] = {(z >= 1 ? -1 : d.nz - 1) * sz, 0, (z + 1 < d.nz ? 1 : 1 - d.nz) * sz};
-    S[0] = at(f, ix);
+    S[0] = ldnt(&at(f, ix));
     auto pull = [&](int i) {
         return ix + (uint32_t)(ox[1 - L::E[i][0]] + oy[1 - L::E[i][1]] + oz[1 - L::E[i][2]]);
     };
@@ -116,7 +122,7 @@ __device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims
         static_assert(L::OPP[1] == 2 && L::OPP[18] == 17, "opposite directions are adjacent");
         const bool back = (m >> j) & 1u;
         const uint32_t a = (i > lo ? N : 0u) + pull(i), b = (j > lo ? N : 0u) + ix;
-        S[i] = at(f + (size_t)lo * d.N, back ? b : a);
+        S[i] = ldnt(&at(f + (size_t)lo * d.N, back ? b : a));
     }
 }
 
