@@ -23,10 +23,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# HBM bytes per k_collide launch from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE (x 1.000) counters,
-# scaled by a plain-copy calibration; valid only for the kernel as it stands when they were taken
-# (profiles/k_collide_d3q19_f32_256cube.md).  Keyed by (lattice side, precision, collision).
-COUNTED_TRAFFIC = {}
+# HBM bytes per launch of the dominant kernel from rocprofv3 counters: TCC_EA0_RDREQ_128B x 128 B +
+# TCC_EA0_RDREQ_64B x 64 B read, TCC_EA0_WRREQ_64B x 64 B written (a plain 1 GiB copy reads as 8388608
+# 128-byte and writes as 16777216 64-byte requests, exactly its bytes); valid only for the kernel as it
+# stands when they were taken (profiles/k_step_d3q19_f32_256cube.md).  Keyed by (kernel, lattice side,
+# precision, collision).
+COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk"): 16280000 * 128 + 1482 * 64 + 21890000 * 64}
 # the same for kb_collide of the batched solver on the seeded table (profiles/kb_collide_batch_d2q9_512cases.md),
 # keyed by (number of cases, precision)
 BATCH_COUNTED_TRAFFIC = {(512, "f32"): 4.271e9}
@@ -44,6 +46,7 @@ def parse():
                     help="auto: the one-pass step where the lattice allows it; split: density pass + collision")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps at full size (0 = skip)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps at full size on one thread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="sessile3d", choices=["sessile3d", "batch", "unet"],
                     help="sessile3d: the 256^3 D3Q19 benchmark; batch: 512 seeded D2Q9 cases in one batch; "
@@ -110,15 +113,34 @@ def main():
     info = lat.info()
     n_fluid = info["n_fluid"]
 
-    lat.step(args.warmup, measure_every=wl["every"])
+    every = wl["every"]
+    lat.step(args.warmup, measure_every=every)
+    # untimed steps up to the next multiple of the cadence, so that the timed window starts with a
+    # measured step whatever --steps and --warmup are
+    align = (-args.warmup) % every
+    if align:
+        lat.step(align, measure_every=every)
+    t_first = args.warmup + align
+    n_measured = len(range(t_first, t_first + args.steps, every))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    series = lat.step(args.steps, measure_every=wl["every"], cap=max(1, args.steps // wl["every"] + 1))
+    series = lat.step(args.steps, measure_every=every, cap=n_measured)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lat.sync()
     ms_step = dt * 1e3 / args.steps
     mlups = n_fluid * args.steps / dt / 1e6
+
+    # cost of the in-step measurement: steps that all measure against steps that do not (not part of value)
+    def per_step_ms(n, me):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(n, measure_every=me)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+    n_ov = max(10, min(args.steps, 100))
+    ms_meas, ms_plain = per_step_ms(n_ov, 1), per_step_ms(n_ov, 0)
 
     # per-kernel mean durations (HIP events around each launch on the context stream)
     prof = lat.profile(args.profile_steps)
@@ -157,11 +179,13 @@ def main():
                             "achieved_GBs": round(step_alg_bytes / (ms_step * 1e-3) / 1e9, 1),
                             "frac_of_peak": round(step_alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
-        "angle": {"mean_deg": series[-1].mean_deg if series else None,
-                  "n_valid": series[-1].n_valid if series else None},
+        "angle": {"timed_window_steps": [t_first, t_first + args.steps], "measured_steps": n_measured,
+                  "mean_deg": series[-1].mean_deg if series else None,
+                  "n_valid": series[-1].n_valid if series else None,
+                  "measured_step_overhead_ms": round(ms_meas - ms_plain, 5)},
     }
     if not args.no_cpu and args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps, args.collision)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps, args.collision, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)
 
 
@@ -293,19 +317,41 @@ def unet_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, steps, collision):
-    """The FP64 oracle on the same lattice, timed over a few full-size steps."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, steps, collision, steps_1t):
+    """The FP64 oracle on the same lattice, timed over a few full-size steps with every OpenMP thread
+    and over fewer steps on one thread."""
     import oracle as O
     O.build(force=False)
     from tests.pairs import oracle_lattice
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     o = oracle_lattice(wl, collision)
     n_fluid = int((o.cls == 0).sum())
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": round(n_fluid * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of the full {wl['n'][0]}^3 lattice (FP64, plain loops, OpenMP)"}
+    out = {"value": round(n_fluid * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} steps of the full {wl['n'][0]}^3 lattice (FP64, plain loops, OpenMP)",
+           "cpu_model": cpu_model()}
+    if steps_1t > 0:
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        o.step(steps_1t)
+        dt1 = time.perf_counter() - t0
+        O.set_threads(threads)
+        out["one_thread"] = {"value": round(n_fluid * steps_1t / dt1 / 1e6, 3), "unit": "MLUPS",
+                             "sample": f"{steps_1t} more steps of the same lattice on one thread"}
+    return out
 
 
 if __name__ == "__main__":

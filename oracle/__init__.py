@@ -70,6 +70,16 @@ class Young(C.Structure):
 _lib = None
 
 
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops from now on (same libgomp instance as
+    the oracle library); returns the number in effect."""
+    lib()
+    g = C.CDLL("libgomp.so.1")
+    g.omp_set_num_threads(C.c_int(int(n)))
+    g.omp_get_max_threads.restype = C.c_int
+    return int(g.omp_get_max_threads())
+
+
 def lib():
     global _lib
     if _lib is None:

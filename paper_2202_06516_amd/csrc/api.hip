@@ -472,7 +472,7 @@ struct Run {
     // liquid centroid sums of the current density (a measurement of step t
     // whose density the previous one-pass step already completed)
     static void centroid(lbm_ctx* c, double rho_m) {
-        k_centroid<L, R><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, rho_m, &c->ctl->m);
+        k_centroid<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, rho_m, &c->ctl->m);
     }
 
     // S_t of the current state into f[1 - cur] (free between steps)
@@ -619,7 +619,7 @@ struct OpMeasureField {
         const R* r = (const R*)rho;
         k_ctl_set<<<1, 64, 0, st>>>(ctl, 0, 0, 1, 0, 1);
         k_ctl_reset<<<1, 64, 0, st>>>(ctl, 0, 1, 0);
-        k_centroid<L, R><<<d.nblocks, 256, 0, st>>>(r, cls, d, mp.rho_m, &ctl->m);
+        k_centroid<L, R><<<d.nblocks < 2048u ? d.nblocks : 2048u, 256, 0, st>>>(r, cls, d, mp.rho_m, &ctl->m);
         k_cross<L, R><<<d.nblocks < 2048u ? d.nblocks : 2048u, 256, 0, st>>>(r, cls, d, ctl, mp);
         k_finalize<L, R><<<1, 64, 0, st>>>(r, ctl, d, mp, nullptr, out, 0);
     }

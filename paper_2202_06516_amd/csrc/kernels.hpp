@@ -355,18 +355,40 @@ __global__ void __launch_bounds__(256) k_density(const R* __restrict__ f, R* __r
 }
 
 // liquid centroid sums of a density field given as such (fluid nodes with
-// rho >= rho_m), the sums k_density forms on measure steps
+// rho >= rho_m), the sums k_density forms on measure steps: a grid-stride loop
+// over the tiles, so that few workgroups add to the four sums (atomics on one
+// address serialise)
 template <class L, typename R>
 __global__ void __launch_bounds__(256) k_centroid(const R* __restrict__ rho, const uint8_t* __restrict__ cls, Dims d,
                                                   double rho_m, MeasureSlots* __restrict__ ms) {
-    int x, y, z;
-    tile_node(d, x, y, z);
-    bool liquid = false;
-    if (x < d.nx && y < d.ny) {
-        const long long idx = nid(d, x, y, z);
-        liquid = (cls[idx] & CLS_MASK) == CLS_FLUID && (double)rho[idx] >= rho_m;
+    unsigned long long cnt = 0, sx = 0, sy = 0, sz = 0;
+    for (unsigned t = blockIdx.x; t < d.nblocks; t += gridDim.x) {
+        int x, y, z;
+        tile_coords(d, t, x, y, z);
+        if (x < d.nx && y < d.ny) {
+            const long long idx = nid(d, x, y, z);
+            if ((cls[idx] & CLS_MASK) == CLS_FLUID && (double)rho[idx] >= rho_m) {
+                cnt += 1;
+                sx += (unsigned long long)x;
+                sy += (unsigned long long)y;
+                sz += (unsigned long long)z;
+            }
+        }
     }
-    centroid_reduce(liquid, x, y, z, ms);
+    __shared__ unsigned long long red[4][4];
+    unsigned long long v[4] = {cnt, sx, sy, sz};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += __shfl_down(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (wave == 0 && lane < 4) {
+        const unsigned long long sum = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        if (sum) atomicAdd((&ms->cnt) + lane, sum);
+    }
 }
 
 // state S_t of every node (zero on solid nodes) into out
@@ -530,26 +552,40 @@ __device__ __forceinline__ bool mu_node(const R* __restrict__ rho, R* __restrict
 template <class L, typename R>
 __device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const uint8_t* __restrict__ cls,
                                                const Dims& d, int x, int y, int z, bool fluid, R r0,
-                                               const MeasureParams& mp, MeasureSlots* ms) {
+                                               const MeasureParams& mp, MeasureSlots* ms,
+                                               unsigned long long (*lkeys)[2] = nullptr) {
     bool cand = false;
-    const double rx = x - mp.c[0], ry = y - mp.c[1], rz = (L::D == 3) ? z - mp.c[2] : 0.0;
     if (fluid && (double)r0 < mp.rho_m) {
-        const double rn = sqrt(rx * rx + ry * ry + rz * rz);
-        const double dn = mp.concave ? mp.R - rn : rn - mp.R;
-        cand = dn < 4.0;  // crossings lie within sqrt(2) of the node; bands end at 2.5
+        // crossings lie within sqrt(2) of the node and the bands end 2.5 from
+        // the substrate, so only nodes within 4 of it can contribute; tested on
+        // the squared distance in single precision, with half a node to spare
+        const float rx = (float)(x - mp.c[0]), ry = (float)(y - mp.c[1]);
+        const float rz = (L::D == 3) ? (float)(z - mp.c[2]) : 0.f;
+        const float rr = rx * rx + ry * ry + rz * rz;
+        const float hi = (float)mp.R + 4.5f, lo = fmaxf((float)mp.R - 4.5f, 0.f);
+        cand = mp.concave ? rr > lo * lo : rr < hi * hi;
     }
     if (__ballot(cand) == 0) return;
     if (!cand) return;
     const Frame F = make_frame(ms, mp);
     if (!F.ok) return;
     const long long idx = nid(d, x, y, z), loc = idx - d.off;
+    // the class and density of every lattice neighbour, loaded together (the
+    // tests below would otherwise wait for them one link at a time)
+    uint8_t cj[L::Q];
+    R rj[L::Q];
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int X = wrapc(x + L::E[i][0], d.nx), Y = wrapc(y + L::E[i][1], d.ny);
         const int Z = L::D == 3 ? wrapc(z + L::E[i][2], d.nz) : 0;
         const long long j = nid(d, X, Y, Z);
-        if ((cls[j] & CLS_MASK) != CLS_FLUID) continue;
-        const double rl = (double)rho[j];
+        cj[i] = cls[j];
+        rj[i] = rho[j];
+    }
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        if ((cj[i] & CLS_MASK) != CLS_FLUID) continue;
+        const double rl = (double)rj[i];
         if (!(rl >= mp.rho_m)) continue;
         double p[3];
         crossing_point((double)r0, rl, mp.rho_m, x, y, z, L::E[i][0], L::E[i][1], L::E[i][2], p);
@@ -563,7 +599,8 @@ __device__ __forceinline__ void crossings_node(const R* __restrict__ rho, const 
         // link id within the lattice: ties go to the lower node, then the lower direction
         const unsigned long long key =
             ((unsigned long long)__float_as_uint(kv) << 32) | (unsigned long long)(loc * L::Q + i);
-        atomicMin(&ms->keys[s][band - 1], key);
+        if (lkeys) atomicMin(&lkeys[s][band - 1], key);  // the workgroup's table in LDS
+        else atomicMin(&ms->keys[s][band - 1], key);
     }
 }
 
@@ -582,17 +619,54 @@ __global__ void __launch_bounds__(256) k_mu(const R* __restrict__ rho, R* __rest
     }
 }
 
+// Tiles that can hold a node within 4 of the substrate: the box |x - c| <
+// R + 5 per axis (unwrapped coordinates, as the distance of Sec. III B),
+// clamped to the lattice, in whole tiles.
+struct TileBox {
+    unsigned tx0, ty0, z0, ntx, nty, n;
+};
+__device__ __forceinline__ TileBox cand_box(const Dims& d, const MeasureParams& mp) {
+    const double m = mp.R + 5.0;
+    const int nn[3] = {d.nx, d.ny, d.nz};
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double l = floor(mp.c[a] - m), h = ceil(mp.c[a] + m);
+        lo[a] = l < 0.0 ? 0 : (l > nn[a] - 1 ? nn[a] - 1 : (int)l);
+        hi[a] = h > nn[a] - 1 ? nn[a] - 1 : (h < 0.0 ? 0 : (int)h);
+    }
+    const int th = 256 >> d.tws;
+    TileBox b;
+    b.tx0 = (unsigned)(lo[0] >> d.tws);
+    b.ty0 = (unsigned)(lo[1] / th);
+    b.z0 = (unsigned)lo[2];
+    b.ntx = (unsigned)(hi[0] >> d.tws) - b.tx0 + 1u;
+    b.nty = (unsigned)(hi[1] / th) - b.ty0 + 1u;
+    b.n = b.ntx * b.nty * (unsigned)(hi[2] - lo[2] + 1);
+    return b;
+}
+
 // The crossing search of a measure step (Sec. III B), its own launch so that
 // the mu kernel carries none of its code: a grid-stride loop over the tiles
-// that returns at once on steps that do not measure.
+// of the box around the substrate that returns at once on steps that do not
+// measure.  (The keys are minima, so the order of the scan does not matter.)
+// The keys go to a table in LDS first and the workgroup's minima to the
+// context's slots once at the end: many links of one contact line compete for
+// the same few keys, and atomics on one address in device memory serialise.
 template <class L, typename R>
 __global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const uint8_t* __restrict__ cls, Dims d,
                                                DevCtl* __restrict__ ctl, MeasureParams mp) {
     if (!measuring(ctl)) return;
-    const unsigned ntiles = (unsigned)d.tx * (unsigned)d.ty * (unsigned)d.nz;
-    for (unsigned t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int x, y, z;
-        tile_coords(d, t, x, y, z);
+    __shared__ unsigned long long lkeys[64][2];
+    if (threadIdx.x < 128) lkeys[threadIdx.x >> 1][threadIdx.x & 1] = ~0ull;
+    __syncthreads();
+    const TileBox b = cand_box(d, mp);
+    for (unsigned t = blockIdx.x; t < b.n; t += gridDim.x) {
+        const unsigned txi = b.tx0 + t % b.ntx, rest = t / b.ntx;
+        const unsigned tyi = b.ty0 + rest % b.nty;
+        const int x = (int)(txi << d.tws) + (int)(threadIdx.x & ((1u << d.tws) - 1u));
+        const int y = (int)tyi * (256 >> d.tws) + (int)(threadIdx.x >> d.tws);
+        const int z = (int)(b.z0 + rest / b.nty);
         bool fluid = false;
         R r0 = R(0);
         if (x < d.nx && y < d.ny) {
@@ -600,7 +674,12 @@ __global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const 
             fluid = (cls[idx] & CLS_MASK) == CLS_FLUID;
             if (fluid) r0 = rho[idx];
         }
-        crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp, &ctl->m);
+        crossings_node<L, R>(rho, cls, d, x, y, z, fluid, r0, mp, &ctl->m, lkeys);
+    }
+    __syncthreads();
+    if (threadIdx.x < 128) {
+        const unsigned long long k = lkeys[threadIdx.x >> 1][threadIdx.x & 1];
+        if (k != ~0ull) atomicMin(&ctl->m.keys[threadIdx.x >> 1][threadIdx.x & 1], k);
     }
 }
 
