@@ -28,10 +28,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # 128-byte and writes as 16777216 64-byte requests, exactly its bytes); valid only for the kernel as it
 # stands when they were taken (profiles/k_step_d3q19_f32_256cube.md).  Keyed by (kernel, lattice side,
 # precision, collision).
-COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk"): 16280000 * 128 + 1482 * 64 + 21890000 * 64}
+COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk"): 16289872 * 128 + 1436 * 64 + 21889613 * 64,
+                   ("k_step", 256, "f32", "mrt"): 16626883 * 128 + 1838 * 64 + 21889397 * 64}
 # the same for kb_collide of the batched solver on the seeded table (profiles/kb_collide_batch_d2q9_512cases.md),
 # keyed by (number of cases, precision)
-BATCH_COUNTED_TRAFFIC = {(512, "f32"): 4.271e9}
+BATCH_COUNTED_TRAFFIC = {}
 
 
 def parse():
@@ -42,6 +43,10 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="lattice side (256 = the benchmark workload)")
     ap.add_argument("--precision", default="f32", choices=["f32", "f32mixed", "f64"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
+    ap.add_argument("--mrt-rates", default="dhumieres", choices=["dhumieres", "paper2d"],
+                    help="D3Q19 MRT rates: d'Humieres et al.'s set (s_e 1.19, s_eps 1.4, s_q 1.2, s_pi 1.4, "
+                         "s_m 1.98), or the paper's D2Q9 rates carried over (1.64, 1.54, 1.9, 1.54, 1.9), which "
+                         "blow this drop up")
     ap.add_argument("--step-kernel", default="auto", choices=["auto", "split"],
                     help="auto: the one-pass step where the lattice allows it; split: density pass + collision")
     ap.add_argument("--profile-steps", type=int, default=50)
@@ -103,10 +108,14 @@ def main():
     elem = 8 if prec == G.LBM_F64 else 4
     wl = W.sessile_3d(mu_w=0.04, n=args.n)
     stream = torch.cuda.Stream()
+    rates = {}
+    if args.collision == "mrt":
+        rates = (dict(s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.4, s_m=1.98) if args.mrt_rates == "dhumieres"
+                 else dict(s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.54, s_m=1.9))
     lat = G.Lattice(G.LBM_D3Q19, n=wl["n"], precision=prec, axis_bc=(1, 1, 1), stream=stream.cuda_stream,
                     collision=G.LBM_BGK if args.collision == "bgk" else G.LBM_MRT, bc_mode=G.LBM_BC_HALFWAY,
                     tau=1.0, Tr=wl["Tr"], k=0.28, kappa=0.01,
-                    step_kernel=G.LBM_STEP_AUTO if args.step_kernel == "auto" else G.LBM_STEP_SPLIT)
+                    step_kernel=G.LBM_STEP_AUTO if args.step_kernel == "auto" else G.LBM_STEP_SPLIT, **rates)
     lat.set_solids(wl["solids"])
     lat.init_drops(wl["drops"], W=10.0)
     lat.set_measure(0, wl["n_sectors"])
@@ -170,7 +179,7 @@ def main():
                                f"drop r0={40 * args.n // 256}, mu_w=0.04, Tr={wl['Tr']}, {args.collision.upper()} tau=1, "
                                f"angle every {wl['every']} steps over {wl['n_sectors']} sectors",
                    "lattice": [args.n] * 3, "fluid_nodes": n_fluid, "precision": args.precision,
-                   "collision": args.collision},
+                   "collision": args.collision, **({"mrt_rates": rates} if rates else {})},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision)),
