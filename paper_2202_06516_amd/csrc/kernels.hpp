@@ -1,14 +1,15 @@
 // kernels.hpp -- HIP kernels of one multiphase lattice Boltzmann step on gfx950.
 //
-// One step t -> t+1 (paper Sec. II and Sec. III A), as separate launches:
+// One step t -> t+1 (paper Sec. II and Sec. III A) on the split path, as
+// separate launches (fused.hpp holds the one-pass step of D3Q19 lattices):
 //   density     rho = sum_i S_i over fluid nodes; on measure steps also the
 //               integer centroid sums of the liquid (rho >= rho_m)
 //   fill        Eq. 14 over the compact list of first-layer solid nodes, then
 //               (second launch) over the second layer
-//   mu          mu = k^2 psi'(rho) - kappa lap4(rho) on fluid nodes (Eq. 11-12);
-//               on measure steps the same pass finds the isodensity crossings
-//               of Eq. 15 near the substrate and keeps, per sector and band,
-//               the crossing nearest 1 or 2 lu from the wall (64-bit atomicMin)
+//   mu          mu = k^2 psi'(rho) - kappa lap4(rho) on fluid nodes (Eq. 11-12)
+//   cross       on measure steps the isodensity crossings of Eq. 15 near the
+//               substrate; per sector and band the crossing nearest 1 or 2 lu
+//               from the wall (64-bit minimum of a packed key)
 //   collide     F = -rho grad4(mu) + cs^2 grad4(rho) + rho g (Eq. 7), MRT or BGK
 //               relaxation (Eq. 1-3) with exact-difference forcing (Eq. 13);
 //               streaming (Eq. 4) is the gather at the start of the next step
@@ -19,7 +20,8 @@
 // into mu once, when the solids are set.
 //
 // Every per-node computation is a device function ("body") shared by two kinds
-// of launch: one lattice tiled by 64 x 4 node workgroups, or many packed
+// of launch: one lattice tiled by 256-thread workgroups (one 256-node row
+// segment, or 128 x 2 / 64 x 4 nodes on narrower lattices), or many packed
 // lattices walked by a persistent work list (the batched solver).  A lattice
 // lives at offset off of the packed arrays; N is the population stride.
 //
@@ -684,7 +686,7 @@ __global__ void __launch_bounds__(256) k_cross(const R* __restrict__ rho, const 
 }
 
 // ---------------------------------------------------------------------------
-// collision + push streaming
+// collision (streaming is the pull at the start of the next step)
 // ---------------------------------------------------------------------------
 template <class L, typename R, typename C, bool MRT, bool NT>
 __device__ __forceinline__ void collide_apply(const R S[L::Q], C Fx, C Fy, C Fz, const Collision<C>& cp,
