@@ -43,6 +43,8 @@ class Params(C.Structure):
         ("g", C.c_double * 3), ("g_start", C.c_longlong),
         ("rho_l", C.c_double), ("rho_g", C.c_double), ("wall_mu", C.c_double),
         ("model", C.c_int), ("sc_G", C.c_double),
+        ("pf_A", C.c_double), ("pf_kappa", C.c_double), ("pf_gamma", C.c_double), ("pf_tau", C.c_double),
+        ("pf_rho0", C.c_double),
     ]
 
 
@@ -191,7 +193,8 @@ def feq(dim, rho, u):
 DEFAULTS = dict(tau=1.0, s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.54, s_m=1.9,
                 Tr=0.6, a=PR_A, b=PR_B, R=PR_R, omega=PR_OMEGA, k=0.28, kappa=0.01,
                 g=(0.0, 0.0, 0.0), g_start=0, rho_l=0.0, rho_g=0.0, wall_mu=math.nan,
-                bgk=0, bc_mode=0, model=0, sc_G=0.0)
+                bgk=0, bc_mode=0, model=0, sc_G=0.0,
+                pf_A=0.01, pf_kappa=0.02, pf_gamma=1.0, pf_tau=1.0, pf_rho0=1.0)
 
 
 def make_params(dim, n, wall=(0, 0, 0), **kw):
@@ -212,6 +215,8 @@ def make_params(dim, n, wall=(0, 0, 0), **kw):
     p.g_start = int(cfg["g_start"])
     p.model = int(cfg["model"])
     p.sc_G = float(cfg["sc_G"])
+    for name in ("pf_A", "pf_kappa", "pf_gamma", "pf_tau", "pf_rho0"):
+        setattr(p, name, float(cfg[name]))
     return p
 
 
@@ -307,6 +312,16 @@ class Oracle:
     @property
     def rho(self):
         return self._view(1, self.N).reshape(self.shape)
+
+    @property
+    def phi(self):
+        """Order parameter of the phase-field model."""
+        return self._view(6, self.N).reshape(self.shape)
+
+    @property
+    def g(self):
+        """Order-parameter populations of the phase-field model (state)."""
+        return self._view(7, self.Q * self.N).reshape((self.Q,) + self.shape)
 
     @property
     def mu(self):

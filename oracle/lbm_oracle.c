@@ -50,6 +50,7 @@ struct ora_ctx {
     double M[MAXQ][MAXQ], Minv[MAXQ][MAXQ], s[MAXQ];
     double Tc, T, alpha, rho_g, rho_l, mu_sat, p_sat, wall_mu;
     double *f, *fpost, *rho, *mu, *F, *muw_map;
+    double *g, *gpost, *phi;   /* phase-field model: order-parameter populations and phi */
     unsigned char* cls;
     unsigned char* solid;
     int nprim;
@@ -429,6 +430,17 @@ ora_ctx* ora_create(const ora_params* p) {
          * wall value is a wall density, neutral default midway */
         if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_l > p->rho_g)) { free(c); return NULL; }
         if (isnan(p->wall_mu)) c->wall_mu = 0.5 * (p->rho_l + p->rho_g);
+    } else if (p->model == 2) {
+        /* phase field: the two bulk phases are phi = 1 (liquid) and phi = -1;
+         * the measurement's isolevel is their mean, 0; the wall value is a wall
+         * order parameter, neutral default 0 */
+        if (!(p->pf_A > 0 && p->pf_kappa > 0 && p->pf_gamma > 0 && p->pf_tau > 0.5 && p->pf_rho0 > 0)) {
+            free(c);
+            return NULL;
+        }
+        c->rho_l = 1.0;
+        c->rho_g = -1.0;
+        if (isnan(p->wall_mu)) c->wall_mu = 0.0;
     } else if (p->model != 0) {
         free(c);
         return NULL;
@@ -442,6 +454,12 @@ ora_ctx* ora_create(const ora_params* p) {
     c->cls = (unsigned char*)calloc(N, 1);
     c->solid = (unsigned char*)calloc(N, 1);
     if (!c->f || !c->fpost || !c->rho || !c->mu || !c->F || !c->cls || !c->solid) { ora_destroy(c); return NULL; }
+    if (p->model == 2) {
+        c->g = (double*)calloc(Q * N, sizeof(double));
+        c->gpost = (double*)calloc(Q * N, sizeof(double));
+        c->phi = (double*)calloc(N, sizeof(double));
+        if (!c->g || !c->gpost || !c->phi) { ora_destroy(c); return NULL; }
+    }
     ora_build(c);
     return c;
 }
@@ -450,6 +468,7 @@ void ora_destroy(ora_ctx* c) {
     if (!c) return;
     free(c->f); free(c->fpost); free(c->rho); free(c->mu); free(c->F); free(c->cls);
     free(c->solid); free(c->muw_map);
+    free(c->g); free(c->gpost); free(c->phi);
     free(c);
 }
 
@@ -606,6 +625,11 @@ static void set_equilibrium_state(ora_ctx* c) {
         if (c->cls[n] == C_FLUID) ora_feq(c->dim, c->rho[n], u, feq);
         else for (int i = 0; i < c->Q; ++i) feq[i] = 0.0;
         for (int i = 0; i < c->Q; ++i) c->f[(size_t)i * c->N + n] = feq[i];
+        if (c->p.model == 2) {
+            /* the order parameter at rest in the rest population */
+            for (int i = 0; i < c->Q; ++i) c->g[(size_t)i * c->N + n] = 0.0;
+            c->g[n] = c->cls[n] == C_FLUID ? c->phi[n] : 0.0;
+        }
     }
     c->step = 0;
 }
@@ -622,14 +646,29 @@ int ora_init_drops(ora_ctx* c, const double* centres, const double* radii, int n
             double v = 0.5 * (c->rho_g + c->rho_l) + 0.5 * (c->rho_g - c->rho_l) * tanh(2.0 * (r - radii[d]) / W);
             if (v > best) best = v;
         }
-        c->rho[n] = c->cls[n] == C_FLUID ? best : 0.0;
+        /* phase field: Eq. 16 profiles the order parameter (rho_l = 1, rho_g = -1), the fluid density is rho0 */
+        if (c->p.model == 2) {
+            c->phi[n] = c->cls[n] == C_FLUID ? best : 0.0;
+            c->rho[n] = c->cls[n] == C_FLUID ? c->p.pf_rho0 : 0.0;
+        } else {
+            c->rho[n] = c->cls[n] == C_FLUID ? best : 0.0;
+        }
     }
     set_equilibrium_state(c);
     return 0;
 }
 
+/* the field the measurement reads (phase field: phi) set on fluid nodes; the
+ * populations set at rest around it */
 int ora_set_rho(ora_ctx* c, const double* rho) {
-    for (long long n = 0; n < c->N; ++n) c->rho[n] = c->cls[n] == C_FLUID ? rho[n] : 0.0;
+    for (long long n = 0; n < c->N; ++n) {
+        if (c->p.model == 2) {
+            c->phi[n] = c->cls[n] == C_FLUID ? rho[n] : 0.0;
+            c->rho[n] = c->cls[n] == C_FLUID ? c->p.pf_rho0 : 0.0;
+        } else {
+            c->rho[n] = c->cls[n] == C_FLUID ? rho[n] : 0.0;
+        }
+    }
     set_equilibrium_state(c);
     return 0;
 }
@@ -645,6 +684,12 @@ void ora_phase_density(ora_ctx* c) {
         double s = 0;
         for (int i = 0; i < c->Q; ++i) s += c->f[(size_t)i * c->N + n];
         c->rho[n] = s;
+        if (c->p.model == 2) {
+            /* phase field: the order parameter is the zeroth moment of g */
+            double q = 0;
+            for (int i = 0; i < c->Q; ++i) q += c->g[(size_t)i * c->N + n];
+            c->phi[n] = q;
+        }
     }
 }
 
@@ -666,6 +711,17 @@ static void fill_layer(ora_ctx* c, int layer, int from) {
 }
 
 void ora_phase_fill(ora_ctx* c) {
+    if (c->p.model == 2) {
+        /* phase field: both solid layers hold the wall order parameter (a
+         * virtual phi, the wetting condition of this model), which the
+         * Laplacian of mu and the gradient of the force reach */
+        for (long long n = 0; n < c->N; ++n) {
+            if (c->cls[n] != C_L1 && c->cls[n] != C_L2) continue;
+            int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
+            c->phi[n] = wall_mu_at(c, n, x, y, z);
+        }
+        return;
+    }
     fill_layer(c, C_L1, C_FLUID);
     fill_layer(c, C_L2, C_L1);
 }
@@ -704,7 +760,17 @@ void ora_phase_mu(ora_ctx* c) {
 #pragma omp parallel for schedule(static)
     for (long long n = 0; n < c->N; ++n) {
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
-        if (p->model == 1) {
+        if (p->model == 2) {
+            /* phase field: mu = dF/dphi = A (phi^3 - phi) - kappa lap(phi) */
+            if (c->cls[n] == C_FLUID) {
+                double lap = 0;
+                for (int ax = 0; ax < c->dim; ++ax) lap += d2(c, c->phi, x, y, z, ax);
+                double f = c->phi[n];
+                c->mu[n] = p->pf_A * (f * f * f - f) - p->pf_kappa * lap;
+            } else {
+                c->mu[n] = 0.0;
+            }
+        } else if (p->model == 1) {
             if (c->cls[n] == C_FLUID) c->mu[n] = sc_psi(c->rho[n]);
             else if (c->cls[n] == C_L1 || c->cls[n] == C_L2) c->mu[n] = sc_psi(wall_mu_at(c, n, x, y, z));
             else c->mu[n] = 0.0;
@@ -730,6 +796,16 @@ void ora_phase_force(ora_ctx* c) {
         for (int d = 0; d < 3; ++d) c->F[(size_t)d * c->N + n] = 0.0;
         if (c->cls[n] != C_FLUID) continue;
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
+        if (p->model == 2) {
+            /* phase field: the capillary force mu grad(phi) (the chemical-potential
+             * form, which differs from -phi grad(mu) by a pressure gradient) */
+            for (int ax = 0; ax < c->dim; ++ax) {
+                double Fv = c->mu[n] * d1(c, c->phi, x, y, z, ax);
+                if (grav) Fv += c->rho[n] * p->g[ax];
+                c->F[(size_t)ax * c->N + n] = Fv;
+            }
+            continue;
+        }
         if (p->model == 1) {
             /* Shan-Chen interaction with the lattice weights:
              * F = -G psi(x) sum_i w_i psi(x + e_i) e_i */
@@ -756,6 +832,38 @@ void ora_phase_force(ora_ctx* c) {
     }
 }
 
+/* Phase field: BGK relaxation of the order-parameter populations toward
+ *   g_i^eq = w_i [gamma mu / cs^2 + phi (e_i.v) / cs^2 + phi ((e_i.v)^2 / (2 cs^4) - v^2 / (2 cs^2))], i > 0,
+ *   g_0^eq = phi - sum_{i>0} g_i^eq,
+ * whose moments are phi, phi v and gamma mu I + phi v v: the Cahn-Hilliard
+ * equation d phi/dt + div(phi v) = M lap(mu) with M = gamma (tau_g - 1/2).
+ * v = (sum_i f_i e_i + F/2) / rho is the fluid velocity of the node. */
+static void pf_collide_g(ora_ctx* c, long long n, const double* f, const double F[3]) {
+    const ora_params* p = &c->p;
+    const double cs2 = 1.0 / 3.0;
+    double rho = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < c->Q; ++i) {
+        rho += f[i];
+        for (int d = 0; d < 3; ++d) j[d] += f[i] * c->e[i][d];
+    }
+    double v[3];
+    for (int d = 0; d < 3; ++d) v[d] = (j[d] + 0.5 * F[d]) / rho;
+    double phi = 0;
+    for (int i = 0; i < c->Q; ++i) phi += c->g[(size_t)i * c->N + n];
+    const double mu = c->mu[n], vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double geq[MAXQ], rest = phi;
+    for (int i = 1; i < c->Q; ++i) {
+        double ev = c->e[i][0] * v[0] + c->e[i][1] * v[1] + c->e[i][2] * v[2];
+        geq[i] = c->w[i] * (p->pf_gamma * mu / cs2 + phi * ev / cs2 + phi * (ev * ev / (2.0 * cs2 * cs2) - vv / (2.0 * cs2)));
+        rest -= geq[i];
+    }
+    geq[0] = rest;
+    for (int i = 0; i < c->Q; ++i) {
+        double gi = c->g[(size_t)i * c->N + n];
+        c->gpost[(size_t)i * c->N + n] = gi - (gi - geq[i]) / p->pf_tau;
+    }
+}
+
 void ora_phase_collide(ora_ctx* c) {
 #pragma omp parallel for schedule(static)
     for (long long n = 0; n < c->N; ++n) {
@@ -769,7 +877,12 @@ void ora_phase_collide(ora_ctx* c) {
         collide_one(c->dim, c->Q, (const int(*)[3])c->e, (const double(*)[MAXQ])c->M,
                     (const double(*)[MAXQ])c->Minv, c->s, f, F, out);
         for (int i = 0; i < c->Q; ++i) c->fpost[(size_t)i * c->N + n] = out[i];
+        if (c->p.model == 2) pf_collide_g(c, n, f, F);
     }
+    if (c->p.model == 2)
+        for (long long n = 0; n < c->N; ++n)
+            if (c->cls[n] != C_FLUID)
+                for (int i = 0; i < c->Q; ++i) c->gpost[(size_t)i * c->N + n] = 0.0;
 }
 
 /* Eq. 4 as a pull; a population whose source is solid is the missing one of
@@ -782,6 +895,8 @@ void ora_phase_stream(ora_ctx* c) {
     for (long long n = 0; n < c->N; ++n) {
         if (c->cls[n] != C_FLUID) {
             for (int i = 0; i < c->Q; ++i) c->f[i * N + n] = 0.0;
+            if (c->p.model == 2)
+                for (int i = 0; i < c->Q; ++i) c->g[i * N + n] = 0.0;
             continue;
         }
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
@@ -810,6 +925,16 @@ void ora_phase_stream(ora_ctx* c) {
             dm += out_j - val;
         }
         c->f[n] += dm;
+        if (c->p.model == 2) {
+            /* phase field: the order parameter streams with halfway bounce-back
+             * at every wall (no flux of phi through the solid) */
+            c->g[n] = c->gpost[n];
+            for (int i = 1; i < c->Q; ++i) {
+                long long src = nbr(c, x, y, z, -c->e[i][0], -c->e[i][1], -c->e[i][2]);
+                c->g[i * N + n] = (src >= 0 && c->cls[src] == C_FLUID) ? c->gpost[i * N + src]
+                                                                        : c->gpost[c->opp[i] * N + n];
+            }
+        }
     }
 }
 
@@ -856,6 +981,8 @@ void* ora_field(ora_ctx* c, int which) {
         case 3: return c->F;
         case 4: return c->cls;
         case 5: return c->fpost;
+        case 6: return c->phi;
+        case 7: return c->g;
         default: return NULL;
     }
 }
@@ -942,11 +1069,12 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
     out->n_sectors = n_sectors;
     ora_phase_density(c);
     const size_t N = (size_t)c->N;
+    const double* mf = c->p.model == 2 ? c->phi : c->rho;  /* the field whose isolevel is the interface */
 
     /* liquid centroid from integer coordinate sums */
     long long cnt = 0, sx = 0, sy = 0, sz = 0;
     for (long long n = 0; n < c->N; ++n) {
-        if (c->cls[n] != C_FLUID || !(c->rho[n] >= rho_m)) continue;
+        if (c->cls[n] != C_FLUID || !(mf[n] >= rho_m)) continue;
         cnt++;
         sx += n % c->nx;
         sy += (n / c->nx) % c->ny;
@@ -969,12 +1097,12 @@ int ora_measure(ora_ctx* c, int solid, int n_sectors, double rho_m, ora_angle* o
     cand_t best1[64], best2[64];
     for (int s = 0; s < 64; ++s) { best1[s].key = ~0ULL; best2[s].key = ~0ULL; }
     for (long long n = 0; n < c->N; ++n) {
-        if (c->cls[n] != C_FLUID || c->rho[n] >= rho_m) continue; /* gas end x_g */
+        if (c->cls[n] != C_FLUID || mf[n] >= rho_m) continue; /* gas end x_g */
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
         for (int i = 1; i < c->Q; ++i) {
             long long m = nbr(c, x, y, z, c->e[i][0], c->e[i][1], c->e[i][2]);
-            if (m < 0 || c->cls[m] != C_FLUID || !(c->rho[m] >= rho_m)) continue; /* liquid end x_l */
-            double t = (rho_m - c->rho[n]) / (c->rho[m] - c->rho[n]);
+            if (m < 0 || c->cls[m] != C_FLUID || !(mf[m] >= rho_m)) continue; /* liquid end x_l */
+            double t = (rho_m - mf[n]) / (mf[m] - mf[n]);
             double p[3] = {x + t * c->e[i][0], y + t * c->e[i][1], z + t * c->e[i][2]};
             double r[3] = {p[0] - pr->c[0], p[1] - pr->c[1], p[2] - pr->c[2]};
             double dist = pr->concave ? pr->r - sqrt(dot3(r, r)) : sqrt(dot3(r, r)) - pr->r;
@@ -1101,8 +1229,9 @@ int ora_young_force(ora_ctx* c, int solid, int n_sectors, double rho_m, double b
     double b1[3], b2[3];
     frame_of(c->dim, angle->axis, b1, b2);
     const double lo = c->rho_g + band_lo * (c->rho_l - c->rho_g), hi = c->rho_g + band_hi * (c->rho_l - c->rho_g);
+    const double* mf = c->p.model == 2 ? c->phi : c->rho;
     for (long long n = 0; n < c->N; ++n) {
-        if (c->cls[n] != C_FLUID || !(c->rho[n] >= lo && c->rho[n] <= hi)) continue;
+        if (c->cls[n] != C_FLUID || !(mf[n] >= lo && mf[n] <= hi)) continue;
         int x = (int)(n % c->nx), y = (int)((n / c->nx) % c->ny), z = (int)(n / ((long long)c->nx * c->ny));
         int touches = 0;
         for (int i = 1; i < c->Q && !touches; ++i) {

@@ -31,8 +31,12 @@ typedef struct {
     long long g_start;                        /* first step at which g acts */
     double rho_l, rho_g;                      /* <= 0: Maxwell coexistence */
     double wall_mu;                           /* outer-wall chemical potential; NaN: k^2 mu_sat */
-    int model;          /* 0: chemical potential (Sec. II B); 1: pseudopotential (Shan-Chen) */
+    int model;          /* 0: chemical potential (Sec. II B); 1: pseudopotential (Shan-Chen); 2: phase field */
     double sc_G;        /* pseudopotential interaction strength (model 1) */
+    /* phase-field model (model 2): order parameter phi in [-1, 1] carried by a
+     * second population set g, free energy A/4 (phi^2 - 1)^2 + kappa/2 |grad phi|^2,
+     * mobility M = gamma (tau_g - 1/2), fluid density rho0 in both phases */
+    double pf_A, pf_kappa, pf_gamma, pf_tau, pf_rho0;
 } ora_params;
 
 typedef struct {
@@ -99,7 +103,8 @@ int  ora_young_force(ora_ctx* c, int solid, int n_sectors, double rho_m, double 
                      double gamma, double theta1_deg, double theta2_deg, double roughness,
                      ora_angle* angle, ora_young* out);
 
-/* fields: 0 f (state, [Q][N]), 1 rho, 2 mu, 3 force ([3][N]), 4 class (uchar), 5 fpost */
+/* fields: 0 f (state, [Q][N]), 1 rho, 2 mu, 3 force ([3][N]), 4 class (uchar), 5 fpost;
+ * phase-field model: 6 phi, 7 g (state of the order parameter, [Q][N]) */
 void* ora_field(ora_ctx* c, int which);
 int   ora_update_derived(ora_ctx* c);   /* rho, fill, mu, force of the current state */
 void  ora_velocity(ora_ctx* c, double* v /*[3][N]*/);
