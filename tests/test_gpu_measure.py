@@ -249,3 +249,35 @@ def test_batch_in_step_young_force_equals_single():
     b.set_young(None)
     with pytest.raises(G.LbmError):
         b.young_last()
+
+
+@pytest.mark.parametrize("n", [(48, 44, 46), (64, 44, 46)])
+@pytest.mark.parametrize("precision", [G.LBM_F32, G.LBM_F32_MIXED])
+def test_young_force_in_step_3d_fp32_matches_oracle(n, precision):
+    # the in-step Young force on a striped sphere in 3-D (8 sectors; the
+    # split step at nx = 48, the one-pass step at nx = 64) with FP32 storage:
+    # each record equals the oracle's Eq. 17-18 on the density the GPU held at
+    # that step (counts bit-exact, phi_d / theta_eq / force to round-off)
+    c = (n[0] / 2 + 0.3, 22.2, 17.4)
+    wl = dict(dim=3, n=n, wall=(1, 1, 1), Tr=0.8, solids=[dict(center=c, radius=11.0, stripes=(-0.01, 0.08, 3.0))],
+              drops=[((c[0] - 0.2, c[1] - 0.1, c[2] + 11.0 + 8.0 - 1.6), 8.0)])
+    gp = gpu_lattice(wl, precision, "bgk")
+    gp.set_measure(0, 8)
+    gp.set_young(0.06, 80.0, 120.0)
+    o = oracle_lattice(wl, "bgk")
+    every, checked = 40, 0
+    for k in range(6):
+        rho = gp.rho  # the state the next call measures at its first step
+        ga = gp.step(every, measure_every=every, cap=2)
+        gy = gp.young_series()
+        assert len(ga) == len(gy) == 1 and gy[0].step == ga[0].step == every * k
+        o.set_rho(rho)
+        oa, oy = o.young_force(0.06, 80.0, 120.0, n_sectors=8)
+        assert gy[0].status == oy.status
+        for s in range(8):
+            assert list(gy[0].count[s]) == list(oy.count[s]), (k, s)
+            for name in ("phi_d", "theta_eq_deg", "force"):
+                g, r = getattr(gy[0], name)[s], getattr(oy, name)[s]
+                assert (math.isnan(g) and math.isnan(r)) or abs(g - r) <= 1e-9, (k, s, name, g, r)
+        checked += sum(1 for s in range(8) if not math.isnan(oy.force[s]))
+    assert checked > 0
