@@ -81,7 +81,19 @@ enum { LBM_BC_HALFWAY = 0, LBM_BC_BOUZIDI_MC = 1 };
  * primitive, a stripe, the map or the outer walls) is read as a density rho_w,
  * and both solid layers carry psi(rho_w).  Its coexistence densities depend on
  * the forcing scheme, so rho_l and rho_g must be given. */
-enum { LBM_MODEL_CHEMICAL_POTENTIAL = 0, LBM_MODEL_PSEUDOPOTENTIAL = 1 };
+/* LBM_MODEL_PHASE_FIELD is a phase-field model, the other family Sec. V names:
+ * an order parameter phi (liquid +1, gas -1) carried by a second population
+ * set g, free energy A/4 (phi^2 - 1)^2 + kappa/2 |grad phi|^2 (pf_A, pf_kappa),
+ * mu = A (phi^3 - phi) - kappa lap(phi), capillary force mu grad(phi) (+ rho g)
+ * on the fluid populations, g relaxed with 1/pf_tau toward the equilibrium of
+ * the Cahn-Hilliard equation with mobility pf_gamma (pf_tau - 1/2), g streamed
+ * with halfway bounce-back at every wall.  Wetting uses a wall order parameter:
+ * every mu_w is read as phi_w, held by both solid layers (NaN wall_mu: 0).  The
+ * measurement reads phi at the isolevel 0 (rho_l = 1 and rho_g = -1 stand for
+ * the two bulk values); lbm_init_drops profiles phi by Eq. 16 with the fluid
+ * density pf_rho0 everywhere.  The split step only (the one-pass step, the
+ * batched solver and the batched Young force are not built for it). */
+enum { LBM_MODEL_CHEMICAL_POTENTIAL = 0, LBM_MODEL_PSEUDOPOTENTIAL = 1, LBM_MODEL_PHASE_FIELD = 2 };
 enum { LBM_STEP_AUTO = 0, LBM_STEP_SPLIT = 1 };
 
 #define LBM_MAX_SECTORS 64
@@ -109,9 +121,10 @@ typedef struct {
     double wall_mu;       /* chemical potential of outer walls; NaN selects k^2 mu_sat
                              (pseudopotential model: wall density, NaN selects (rho_l + rho_g) / 2) */
     void* stream;         /* hipStream_t to enqueue on, or NULL for a context-owned stream */
-    int model;            /* LBM_MODEL_CHEMICAL_POTENTIAL (default) or LBM_MODEL_PSEUDOPOTENTIAL; the
-                             pseudopotential model needs rho_l > rho_g > 0 and ignores Tr, pr_*, k, kappa
-                             (the batched solver takes either model for all its cases) */
+    int model;            /* LBM_MODEL_CHEMICAL_POTENTIAL (default), LBM_MODEL_PSEUDOPOTENTIAL or
+                             LBM_MODEL_PHASE_FIELD; the pseudopotential model needs rho_l > rho_g > 0 and
+                             ignores Tr, pr_*, k, kappa (the batched solver takes either of the first two for
+                             all its cases); the phase-field model ignores Tr, pr_*, k, kappa, rho_l, rho_g */
     double sc_G;          /* pseudopotential interaction strength G (default -6) */
     int step_kernel;      /* LBM_STEP_AUTO (default): D3Q19 lattices with halfway bounce-back walls, nx a
                              multiple of 64 (at most 1024), ny a multiple of 4 and nz even take one pass over
@@ -119,6 +132,10 @@ typedef struct {
                              collision also sums the next step's density); LBM_STEP_SPLIT: a density pass,
                              then the collision.  Both compute the same step; the density sums differ in
                              order, so the fields agree to rounding. */
+    double pf_A, pf_kappa;  /* phase-field model: free-energy coefficients (default 0.01, 0.02) */
+    double pf_gamma;        /* mobility coefficient: M = pf_gamma (pf_tau - 1/2) (default 1) */
+    double pf_tau;          /* relaxation time of the order-parameter populations, > 1/2 (default 1) */
+    double pf_rho0;         /* fluid density of the initial state (default 1) */
 } lbm_config;
 
 /* Fill *cfg with the library defaults for the given lattice. */
@@ -204,7 +221,9 @@ enum {
     LBM_FIELD_MU = 3,    /* [N] chemical potential of Eq. 12; wall value on the solid layers
                             (pseudopotential model: psi, and psi(rho_w) on the layers) */
     LBM_FIELD_CLASS = 4, /* [N] uint8: 0 fluid, 1 first solid layer, 2 second, 3 deeper solid */
-    LBM_FIELD_MASS = 5   /* one double: sum of S_t over fluid nodes */
+    LBM_FIELD_MASS = 5,  /* one double: sum of S_t over fluid nodes */
+    LBM_FIELD_PHI = 6,   /* phase-field model: [N] order parameter sum_i g_i (fluid), phi_w on the solid layers */
+    LBM_FIELD_G = 7      /* phase-field model: [Q][N] order-parameter populations (state, as F) */
 };
 
 typedef struct lbm_ctx lbm_ctx;
@@ -248,14 +267,18 @@ lbm_status lbm_set_measure(lbm_ctx* ctx, const lbm_measure_opts* opts);
 lbm_status lbm_measure_angle(lbm_ctx* ctx, const lbm_measure_opts* opts, lbm_angle* out);
 
 /* Copy a field of the current state to dst (host memory unless
- * dst_on_device).  bytes must equal the field size: N * elem for RHO and MU,
- * Q * N * elem for F, 3 * N * elem for VEL (elem = 4 for LBM_F32 and
- * LBM_F32_MIXED, 8 for LBM_F64), N for CLASS, 8 for MASS (always double).  Synchronises. */
+ * dst_on_device).  bytes must equal the field size: N * elem for RHO, MU and PHI,
+ * Q * N * elem for F and G, 3 * N * elem for VEL (elem = 4 for LBM_F32 and
+ * LBM_F32_MIXED, 8 for LBM_F64), N for CLASS, 8 for MASS (always double).  PHI
+ * and G exist in the phase-field model only (LBM_E_ARG otherwise).  Synchronises. */
 lbm_status lbm_read(lbm_ctx* ctx, int field, void* dst, size_t bytes, int dst_on_device);
 
 /* Replace the state.  LBM_FIELD_F: populations S_t (checkpoint restore);
- * LBM_FIELD_RHO: density, state = f_eq(rho, 0) on fluid nodes.  Sizes as for
- * lbm_read.  Does not change t. */
+ * LBM_FIELD_RHO: density, state = f_eq(rho, 0) on fluid nodes.  Phase-field
+ * model: LBM_FIELD_PHI: order parameter on fluid nodes, state = f_eq(pf_rho0, 0)
+ * and g at rest (g_0 = phi); LBM_FIELD_F and LBM_FIELD_G replace one
+ * population set each (a checkpoint restore writes both); LBM_FIELD_RHO is
+ * refused.  Sizes as for lbm_read.  Does not change t. */
 lbm_status lbm_write(lbm_ctx* ctx, int field, const void* src, size_t bytes, int src_on_device);
 
 /* Wait for enqueued work; LBM_E_NONFINITE if a density went bad. */

@@ -13,6 +13,7 @@
 #include "host.hpp"
 #include "kernels.hpp"
 #include "fused.hpp"
+#include "phasefield.hpp"
 #include "young.hpp"
 
 using namespace lbm;
@@ -118,9 +119,17 @@ struct lbm_ctx {
     lbm_measure_opts mopts{0, 32, 0.0};
     long long t = 0;  // host mirror of the step counter
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // phase-field model: the order-parameter populations (same form and
+    // buffer parity as f) and the order parameter, whose solid layers hold phi_w
+    bool pf = false;
+    void* g[2] = {nullptr, nullptr};
+    void* phi = nullptr;
 };
 
 namespace {
+
+// the field whose isolevel is the interface: phi in the phase-field model, else rho
+inline void* mfield(const lbm_ctx* c) { return c->pf ? c->phi : c->rho; }
 
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -333,6 +342,10 @@ struct Run {
     // the launches of one step, reading f[src] and writing f[1-src]; pull
     // selects the form of f[src] (post-collision populations, else S_t)
     static void step_launches(lbm_ctx* c, int src, bool pull, const MeasureParams& mp, hipEvent_t* ev, int* kinds) {
+        if (c->pf) {
+            pf_step_launches(c, src, pull, mp, ev, kinds);
+            return;
+        }
         const dim3 blk(256, 1, 1), grd = grid(c);
         const R* fin = (const R*)c->f[src];
         R* fout = (R*)c->f[1 - src];
@@ -373,6 +386,101 @@ struct Run {
         k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1, ys, c->yseries);
         mark(6);
         if (kinds) kinds[k] = -1;
+    }
+
+    // phase-field model (the split step): parameters, density, mu, collision
+    static PhaseField phase_field(const lbm_ctx* c) {
+        PhaseField pf;
+        pf.A = c->cfg.pf_A;
+        pf.kappa = c->cfg.pf_kappa;
+        pf.gamma = c->cfg.pf_gamma;
+        pf.omega = 1.0 / c->cfg.pf_tau;
+        pf.rho0 = c->cfg.pf_rho0;
+        return pf;
+    }
+    static WallBC halfway(const lbm_ctx* c) {
+        WallBC bc = wall(c);
+        bc.bouzidi = 0;
+        return bc;
+    }
+    static void pf_density(lbm_ctx* c, int src, bool pull, double phi_m) {
+        const R* f = (const R*)c->f[src];
+        const R* g = (const R*)c->g[src];
+        if (pull)
+            k_pf_density<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
+                f, g, (R*)c->rho, (R*)c->phi, c->cls, c->d, wall(c), c->ctl, phi_m);
+        else
+            k_pf_density<L, R, C, false><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
+                f, g, (R*)c->rho, (R*)c->phi, c->cls, c->d, wall(c), c->ctl, phi_m);
+    }
+    static void pf_mu(lbm_ctx* c) {
+        if (c->d.zc > 1)
+            k_pf_mu<L, R, true><<<zgrid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->phi, (R*)c->mu, c->cls, c->d,
+                                                                             phase_field(c));
+        else
+            k_pf_mu<L, R, false><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->phi, (R*)c->mu, c->cls, c->d,
+                                                                             phase_field(c));
+    }
+    template <bool PULL, bool MRT>
+    static void pf_collide(lbm_ctx* c, int src, const WallBC& bc, const Collision<C>& cp) {
+        k_pf_collide<L, R, C, PULL, MRT><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
+            (const R*)c->f[src], (R*)c->f[1 - src], (const R*)c->g[src], (R*)c->g[1 - src], (const R*)c->rho,
+            (const R*)c->phi, (const R*)c->mu, c->cls, c->d, bc, cp, phase_field(c), c->ctl);
+    }
+    static void pf_step_launches(lbm_ctx* c, int src, bool pull, const MeasureParams& mp, hipEvent_t* ev,
+                                 int* kinds) {
+        const dim3 blk(256, 1, 1);
+        const R* phi = (const R*)c->phi;
+        int k = 0;
+        auto start = [&]() { if (ev) (void)hipEventRecord(ev[2 * k], c->stream); };
+        auto mark = [&](int kind) { if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = kind; } };
+        start();
+        pf_density(c, src, pull, mp.rho_m);
+        mark(0);
+        start();
+        pf_mu(c);
+        mark(3);
+        start();
+        k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(phi, c->cls, c->d, c->ctl, mp);
+        YoungStep ys{};
+        if (c->young_on) {
+            ys = young_step(c, mp);
+            k_young_step<L, R><<<cross_grid(c), blk, 0, c->stream>>>(phi, c->cls, c->d, young_step_params(c, mp), mp,
+                                                                    c->ctl, c->ystep_counts);
+        }
+        mark(5);
+        start();
+        const WallBC bc = wall(c);
+        const Collision<C> cp = collision(c);
+        const bool mrt = c->cfg.collision == LBM_MRT;
+        if (pull) {
+            if (mrt) pf_collide<true, true>(c, src, bc, cp);
+            else pf_collide<true, false>(c, src, bc, cp);
+        } else {
+            if (mrt) pf_collide<false, true>(c, src, bc, cp);
+            else pf_collide<false, false>(c, src, bc, cp);
+        }
+        mark(4);
+        start();
+        k_finalize<L, R><<<1, 64, 0, c->stream>>>(phi, c->ctl, c->d, mp, c->series, c->last, 1, ys, c->yseries);
+        mark(6);
+        if (kinds) kinds[k] = -1;
+    }
+    // S_t of the order-parameter populations into g[1 - cur]
+    static R* materialize_g(lbm_ctx* c) {
+        R* out = (R*)c->g[1 - c->cur];
+        if (c->fstar)
+            k_materialize<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->g[c->cur], out, c->cls,
+                                                                                    c->d, halfway(c));
+        else
+            k_materialize<L, R, C, false><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->g[c->cur], out,
+                                                                                     c->cls, c->d, halfway(c));
+        return out;
+    }
+    // the state of an order-parameter field (device array of N values)
+    static void pf_init(lbm_ctx* c, const void* src) {
+        k_pf_init<L, R><<<2048, 256, 0, c->stream>>>((const R*)src, (R*)c->phi, (R*)c->rho, (R*)c->f[c->cur],
+                                                     (R*)c->g[c->cur], c->cls, c->d.N, c->cfg.pf_rho0);
     }
 
     // One step on the one-pass path, reading f[src] and rhob[rsrc] (rho_t, with
@@ -487,6 +595,11 @@ struct Run {
 
     // density, solid fill and mu of the current state (no measurement)
     static void derive(lbm_ctx* c, bool with_mu) {
+        if (c->pf) {
+            pf_density(c, c->cur, c->fstar, c->rho_m);
+            if (with_mu) pf_mu(c);
+            return;
+        }
         if (c->fused && c->rho_valid) return;  // the one-pass step keeps them current
         if (c->fused) with_mu = true;
         MeasureParams mp{};
@@ -507,7 +620,10 @@ struct Run {
     static void velocity(lbm_ctx* c, void* out) {
         derive(c, true);
         const R* S = materialize(c);
-        if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
+        if (c->pf)
+            k_pf_velocity<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
+                S, (const R*)c->rho, (const R*)c->phi, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
+        else if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
             k_velocity<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
                 S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
         else
@@ -516,6 +632,12 @@ struct Run {
     }
 
     static void measure_now(lbm_ctx* c, const MeasureParams& mp) {
+        if (c->pf) {
+            pf_density(c, c->cur, c->fstar, mp.rho_m);
+            k_cross<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->phi, c->cls, c->d, c->ctl, mp);
+            k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->phi, c->ctl, c->d, mp, nullptr, c->last, 0);
+            return;
+        }
         if (c->fused && c->rho_valid) {
             centroid(c, mp.rho_m);
         } else {
@@ -534,7 +656,7 @@ struct Run {
     }
 
     static void young_count(lbm_ctx* c, const YoungParams& yp) {
-        k_young_count<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->rho, c->cls, c->d, yp,
+        k_young_count<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)mfield(c), c->cls, c->d, yp,
                                                                             c->young_counts);
     }
 
@@ -604,6 +726,14 @@ struct OpInit {
 template <class L, typename R, typename C>
 struct OpMaterialize {
     static void go(lbm_ctx* c, void** out) { *out = Run<L, R, C>::materialize(c); }
+};
+template <class L, typename R, typename C>
+struct OpMaterializeG {
+    static void go(lbm_ctx* c, void** out) { *out = Run<L, R, C>::materialize_g(c); }
+};
+template <class L, typename R, typename C>
+struct OpPfInit {
+    static void go(lbm_ctx* c, const void* src) { Run<L, R, C>::pf_init(c, src); }
 };
 template <class L, typename R, typename C>
 struct OpMass {
@@ -697,6 +827,11 @@ void lbm_config_default(lbm_config* cfg, int lattice) {
     cfg->model = LBM_MODEL_CHEMICAL_POTENTIAL;
     cfg->sc_G = -6.0;
     cfg->step_kernel = LBM_STEP_AUTO;
+    cfg->pf_A = 0.01;
+    cfg->pf_kappa = 0.02;
+    cfg->pf_gamma = 1.0;
+    cfg->pf_tau = 1.0;
+    cfg->pf_rho0 = 1.0;
 }
 
 const char* lbm_last_error(const lbm_ctx* ctx) {
@@ -736,7 +871,14 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (cfg->bc_mode != LBM_BC_HALFWAY && cfg->bc_mode != LBM_BC_BOUZIDI_MC) return bad("bc_mode");
     if (!(cfg->k > 0) || !(cfg->kappa >= 0) || !(cfg->pr_a > 0) || !(cfg->pr_b > 0) || !(cfg->pr_R > 0))
         return bad("thermodynamic parameters");
-    if (cfg->model != LBM_MODEL_CHEMICAL_POTENTIAL && cfg->model != LBM_MODEL_PSEUDOPOTENTIAL) return bad("model");
+    if (cfg->model != LBM_MODEL_CHEMICAL_POTENTIAL && cfg->model != LBM_MODEL_PSEUDOPOTENTIAL &&
+        cfg->model != LBM_MODEL_PHASE_FIELD)
+        return bad("model");
+    if (cfg->model == LBM_MODEL_PHASE_FIELD &&
+        (!(cfg->pf_A > 0) || !(cfg->pf_kappa > 0) || !(cfg->pf_gamma > 0) || !(cfg->pf_tau > 0.5) ||
+         !(cfg->pf_rho0 > 0) || !std::isfinite(cfg->pf_A + cfg->pf_kappa + cfg->pf_gamma + cfg->pf_tau + cfg->pf_rho0)))
+        return bad("the phase-field model needs pf_A, pf_kappa, pf_gamma, pf_rho0 > 0 and pf_tau > 1/2");
+    c->pf = cfg->model == LBM_MODEL_PHASE_FIELD;
     if (cfg->model == LBM_MODEL_PSEUDOPOTENTIAL &&
         (!(cfg->rho_g > 0) || !(cfg->rho_l > cfg->rho_g) || !std::isfinite(cfg->sc_G)))
         return bad("the pseudopotential model needs rho_l > rho_g > 0 and a finite sc_G");
@@ -760,7 +902,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         // (its node indices and the byte offsets of its population accesses, up to
         // five arrays from one base, are 32-bit)
         const size_t elem = cfg->precision == LBM_F64 ? 8 : 4;
-        c->fused = cfg->step_kernel == LBM_STEP_AUTO && c->dim == 3 && cfg->bc_mode == LBM_BC_HALFWAY &&
+        c->fused = cfg->step_kernel == LBM_STEP_AUTO && !c->pf && c->dim == 3 && cfg->bc_mode == LBM_BC_HALFWAY &&
                    c->d.nx % 64 == 0 && c->d.nx <= 1024 && c->d.ny % kFusedTY == 0 && zc >= 2 && c->d.nz % zc == 0 &&
                    5ull * (unsigned long long)N * elem < (1ull << 32);
     }
@@ -779,6 +921,14 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (cfg->model == LBM_MODEL_PSEUDOPOTENTIAL) {
         // wall values are densities; psi is stored unshifted
         c->wall_mu = std::isnan(cfg->wall_mu) ? c->rho_m : cfg->wall_mu;
+        c->mu_ref = 0.0;
+    }
+    if (c->pf) {
+        // bulk values of the order parameter; the wall values are order parameters
+        c->pr.rho_l = 1.0;
+        c->pr.rho_g = -1.0;
+        c->rho_m = 0.0;
+        c->wall_mu = std::isnan(cfg->wall_mu) ? 0.0 : cfg->wall_mu;
         c->mu_ref = 0.0;
     }
 
@@ -803,7 +953,9 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         (s = dalloc(c, &c->bidx, (size_t)N * 4)) ||
         (s = dalloc(c, &c->ctl, sizeof(DevCtl))) || (s = dalloc(c, &c->last, sizeof(AngleRec))) ||
         (s = dalloc(c, &c->mass_part, kMassBlocks * sizeof(double))) || (s = dalloc(c, &c->mass_out, sizeof(double))) ||
-        (s = dalloc(c, &c->young_counts, 2 * LBM_MAX_SECTORS * sizeof(unsigned)))) {
+        (s = dalloc(c, &c->young_counts, 2 * LBM_MAX_SECTORS * sizeof(unsigned))) ||
+        (c->pf && ((s = dalloc(c, (char**)&c->g[0], fbytes)) || (s = dalloc(c, (char**)&c->g[1], fbytes)) ||
+                   (s = dalloc(c, (char**)&c->phi, N * c->elem))))) {
         lbm_destroy(c);
         return s;
     }
@@ -829,7 +981,8 @@ lbm_status lbm_destroy(lbm_ctx* c) {
     drop_graphs(c);
     void* ps[] = {c->f[0], c->f[1], c->rhob[0], c->rhob[1], c->gy, c->gz, c->gyz, c->force, c->sink, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
                   c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
-                  c->mass_part, c->mass_out, c->young_counts, c->ylast, c->yseries, c->ystep_counts};
+                  c->mass_part, c->mass_out, c->young_counts, c->ylast, c->yseries, c->ystep_counts,
+                  c->g[0], c->g[1], c->phi};
     for (void* p : ps) dfree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -896,17 +1049,20 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
         std::vector<double> muh((size_t)g.N, 0.0);
         // the layers' wall value: mu_w (stored shifted), or for the
         // pseudopotential model psi of the wall density
+        // (phase-field model: the wall order parameter, into phi; mu stays zero there)
         const bool sc = c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL;
         auto wall = [&](double v) { return sc ? 1.0 - std::exp(-v) : v - c->mu_ref; };
         for (size_t i = 0; i < g.l1_node.size(); ++i) muh[g.l1_node[i]] = wall(g.l1_mu[i]);
         for (size_t i = 0; i < g.l2_node.size(); ++i) muh[g.l2_node[i]] = wall(g.l2_mu[i]);
+        std::vector<char> zero((size_t)g.N * c->elem, 0);
+        void* dst = c->pf ? c->phi : c->mu;
         if (c->f64) {
-            HIPCHK(c, hipMemcpy(c->mu, muh.data(), g.N * 8, hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(dst, muh.data(), g.N * 8, hipMemcpyHostToDevice));
         } else {
             std::vector<float> t(muh.begin(), muh.end());
-            HIPCHK(c, hipMemcpy(c->mu, t.data(), g.N * 4, hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(dst, t.data(), g.N * 4, hipMemcpyHostToDevice));
         }
-        std::vector<char> zero((size_t)g.N * c->elem, 0);
+        if (c->pf) HIPCHK(c, hipMemcpy(c->mu, zero.data(), zero.size(), hipMemcpyHostToDevice));
         for (void* rb : c->rhob)
             if (rb) HIPCHK(c, hipMemcpy(rb, zero.data(), zero.size(), hipMemcpyHostToDevice));
         c->rcur = 0;
@@ -944,11 +1100,13 @@ lbm_status lbm_init_drops(lbm_ctx* c, const lbm_drop* drops, int n, double W) {
         rho[i] = best;
     }
     lbm_status s;
+    // (phase-field model: the profile is the order parameter's, rho_l = 1, rho_g = -1)
+    const int field = c->pf ? LBM_FIELD_PHI : LBM_FIELD_RHO;
     if (c->f64) {
-        s = lbm_write(c, LBM_FIELD_RHO, rho.data(), rho.size() * 8, 0);
+        s = lbm_write(c, field, rho.data(), rho.size() * 8, 0);
     } else {
         std::vector<float> fr(rho.begin(), rho.end());
-        s = lbm_write(c, LBM_FIELD_RHO, fr.data(), fr.size() * 4, 0);
+        s = lbm_write(c, field, fr.data(), fr.size() * 4, 0);
     }
     if (s != LBM_OK) return s;
     c->t = 0;
@@ -958,12 +1116,55 @@ lbm_status lbm_init_drops(lbm_ctx* c, const lbm_drop* drops, int n, double W) {
     return LBM_OK;
 }
 
+// lbm_write of the phase-field model: PHI (state at rest around it), or one
+// population set of a checkpoint (F or G)
+static lbm_status pf_write(lbm_ctx* c, int field, const void* src, size_t bytes, hipMemcpyKind kind) {
+    const size_t N = (size_t)c->d.N, fb = (size_t)c->Q * N * c->elem;
+    auto zero = [&](void* p, size_t nbytes) {
+        if (c->f64) k_fill_value<double><<<2048, 256, 0, c->stream>>>((double*)p, nbytes / 8, 0.0);
+        else k_fill_value<float><<<2048, 256, 0, c->stream>>>((float*)p, nbytes / 4, 0.0f);
+    };
+    if (field == LBM_FIELD_PHI) {
+        if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "write PHI: bytes must be N * elem");
+        // the source is staged in g[1 - cur] (free between steps), stream-ordered,
+        // and both spare buffers are cleared afterwards
+        HIPCHK(c, hipMemcpyAsync(c->g[1 - c->cur], src, bytes, kind, c->stream));
+        dispatch<OpPfInit>(c, (const void*)c->g[1 - c->cur]);
+        zero(c->f[1 - c->cur], fb);
+        zero(c->g[1 - c->cur], fb);
+    } else if (field == LBM_FIELD_F || field == LBM_FIELD_G) {
+        if (bytes != fb) return fail(c, LBM_E_ARG, "write F/G: bytes must be Q * N * elem");
+        if (!c->have_state) {
+            // a fresh state: the set not written starts at zero
+            zero(c->f[c->cur], fb);
+            zero(c->g[c->cur], fb);
+        } else if (c->fstar) {
+            // both sets to S_t first, so that the two stay in one form
+            void* S = nullptr;
+            dispatch<OpMaterialize>(c, &S);
+            dispatch<OpMaterializeG>(c, &S);
+            c->cur ^= 1;
+        }
+        HIPCHK(c, hipMemcpyAsync(field == LBM_FIELD_F ? c->f[c->cur] : c->g[c->cur], src, bytes, kind, c->stream));
+    } else {
+        return fail(c, LBM_E_ARG, "write: the phase-field model takes PHI, F or G");
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->rho_valid = false;
+    c->fstar = false;
+    c->have_state = true;
+    c->series_written = 0;
+    return LBM_OK;
+}
+
 lbm_status lbm_write(lbm_ctx* c, int field, const void* src, size_t bytes, int src_on_device) {
     if (!c) return LBM_E_ARG;
     if (!src) return fail(c, LBM_E_ARG, "write: null source");
     if (!c->have_geometry) return fail(c, LBM_E_STATE, "write: no geometry");
     const size_t N = (size_t)c->d.N;
     const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (c->pf) return pf_write(c, field, src, bytes, kind);
     if (field == LBM_FIELD_RHO) {
         if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "write RHO: bytes must be N * elem");
         // stream-ordered: a device-to-device copy may otherwise still be in
@@ -1249,6 +1450,24 @@ lbm_status lbm_read(lbm_ctx* c, int field, void* dst, size_t bytes, int dst_on_d
             else std::memcpy(dst, h.data(), N);
             break;
         }
+        case LBM_FIELD_PHI:
+            if (!c->pf) return fail(c, LBM_E_ARG, "read PHI: a field of the phase-field model");
+            if (bytes != N * c->elem) return fail(c, LBM_E_ARG, "read PHI: bytes must be N * elem");
+            if ((s = ctl_reset(c, 0, 0, 0))) return s;
+            dispatch<OpDerive>(c, false);
+            HIPCHK(c, hipGetLastError());
+            HIPCHK(c, hipMemcpyAsync(dst, c->phi, bytes, kind, c->stream));
+            break;
+        case LBM_FIELD_G:
+            if (!c->pf) return fail(c, LBM_E_ARG, "read G: a field of the phase-field model");
+            if (bytes != (size_t)c->Q * N * c->elem) return fail(c, LBM_E_ARG, "read G: bytes must be Q * N * elem");
+            {
+                void* S = nullptr;
+                dispatch<OpMaterializeG>(c, &S);
+                HIPCHK(c, hipGetLastError());
+                HIPCHK(c, hipMemcpyAsync(dst, S, bytes, kind, c->stream));
+            }
+            break;
         case LBM_FIELD_MASS:
             if (bytes != 8) return fail(c, LBM_E_ARG, "read MASS: bytes must be 8");
             dispatch<OpMass>(c);

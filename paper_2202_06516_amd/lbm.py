@@ -23,12 +23,12 @@ LBM_F32, LBM_F64, LBM_F32_MIXED = 0, 1, 2
 LBM_PERIODIC, LBM_WALL = 0, 1
 LBM_MRT, LBM_BGK = 0, 1
 LBM_BC_HALFWAY, LBM_BC_BOUZIDI_MC = 0, 1
-LBM_MODEL_CHEMICAL_POTENTIAL, LBM_MODEL_PSEUDOPOTENTIAL = 0, 1
+LBM_MODEL_CHEMICAL_POTENTIAL, LBM_MODEL_PSEUDOPOTENTIAL, LBM_MODEL_PHASE_FIELD = 0, 1, 2
 LBM_STEP_AUTO, LBM_STEP_SPLIT = 0, 1
 LBM_SOLID_SPHERE = 0
 LBM_SOLID_CAVITY = 1
 LBM_WET_UNIFORM, LBM_WET_STRIPES = 0, 1
-FIELD_RHO, FIELD_F, FIELD_VEL, FIELD_MU, FIELD_CLASS, FIELD_MASS = range(6)
+FIELD_RHO, FIELD_F, FIELD_VEL, FIELD_MU, FIELD_CLASS, FIELD_MASS, FIELD_PHI, FIELD_G = range(8)
 MAX_SECTORS = 64
 
 
@@ -48,6 +48,8 @@ class lbm_config(C.Structure):
         ("k", C.c_double), ("kappa", C.c_double), ("g", C.c_double * 3), ("g_start_step", C.c_int64),
         ("rho_l", C.c_double), ("rho_g", C.c_double), ("wall_mu", C.c_double), ("stream", C.c_void_p),
         ("model", C.c_int), ("sc_G", C.c_double), ("step_kernel", C.c_int),
+        ("pf_A", C.c_double), ("pf_kappa", C.c_double), ("pf_gamma", C.c_double), ("pf_tau", C.c_double),
+        ("pf_rho0", C.c_double),
     ]
 
 
@@ -389,7 +391,7 @@ class Lattice:
             out = np.empty(self.shape, dtype=np.uint8)
         elif field == FIELD_MASS:
             out = np.empty(1, dtype=np.float64)
-        elif field == FIELD_F:
+        elif field in (FIELD_F, FIELD_G):
             out = np.empty((self.Q,) + self.shape, dtype=self.dtype)
         elif field == FIELD_VEL:
             out = np.empty((3,) + self.shape, dtype=self.dtype)
@@ -416,6 +418,16 @@ class Lattice:
     @property
     def f(self):
         return self.read(FIELD_F)
+
+    @property
+    def phi(self):
+        """Order parameter of the phase-field model."""
+        return self.read(FIELD_PHI)
+
+    @property
+    def g(self):
+        """Order-parameter populations S_t of the phase-field model."""
+        return self.read(FIELD_G)
 
     def mass(self):
         return float(self.read(FIELD_MASS))

@@ -23,6 +23,9 @@ Workloads (the paper's drops on curved solids, Sec. IV; no dataset exists):
                drop-size and curvature sweeps of Sec. IV A-B from it
   sc_sessile_2d  the sessile layout for the pseudopotential model (wall density
                rho_w in place of mu_w)
+  pf_sessile_2d / pf_sessile_3d  the sessile layout for the phase-field model
+               (order parameter +1 liquid, -1 gas; wall order parameter phi_w
+               in place of mu_w), a channel or box walled as stated
   batch_cases  many D2Q9 drops on cylinders of random sizes (batched solver)
   warmstart_cases  256^2 D2Q9 drops on cylinders, cylinder radius 16..64, drop
                radius 18..48 (smaller drops dissolve into the gas at Tr=0.8
@@ -270,6 +273,29 @@ def sc_sessile_2d(rho_w=0.8, n=128):
     return dict(dim=2, n=(n, n), wall=(0, 0), model=1,
                 solids=[dict(center=(64 * s, 40 * s), radius=24 * s, mu_w=rho_w)],
                 drops=[((64 * s, 84 * s), 20 * s)], W=5.0, steps=5000, every=100)
+
+
+# the phase-field model's parameters (both sides receive exactly these): interface
+# width xi = sqrt(2 kappa / A) = 2, so that the Eq. 16 profile of width W = 2 xi
+# is the flat-interface profile tanh(r / xi)
+PF_PARAMS = dict(pf_A=0.01, pf_kappa=0.02, pf_gamma=1.0, pf_tau=1.0, pf_rho0=1.0)
+PF_W = 4.0
+
+
+def pf_sessile_2d(phi_w=0.3, n=(96, 64)):
+    """Phase-field model: a disc in a channel walled along y, drop tangent on top."""
+    c, R, r0 = (47.7, 22.3), 12.4, 9.0
+    return dict(dim=2, n=n, wall=(0, 1), model=2, W=PF_W,
+                solids=[dict(center=c, radius=R, mu_w=phi_w)],
+                drops=[((47.5, c[1] + R + r0), r0)], every=100)
+
+
+def pf_sessile_3d(phi_w=0.3, n=(64, 48, 48)):
+    """Phase-field model: a sphere in a walled box, drop tangent on top."""
+    c, R, r0 = (31.6, 24.2, 16.3), 9.4, 8.0
+    return dict(dim=3, n=n, wall=(1, 1, 1), model=2, W=PF_W,
+                solids=[dict(center=c, radius=R, mu_w=phi_w)],
+                drops=[((31.6, 24.2, c[2] + R + r0), r0)], every=100, n_sectors=16)
 
 
 def random_state_perturbation(shape, q, seed, amplitude=1e-3):

@@ -22,6 +22,8 @@ def gpu_lattice(wl, precision, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0),
         params["Tr"] = wl["Tr"]
     if wl.get("model", 0) == 1:
         params.update(SC_PARAMS, model=G.LBM_MODEL_PSEUDOPOTENTIAL)
+    if wl.get("model", 0) == 2:
+        params.update(W.PF_PARAMS, model=G.LBM_MODEL_PHASE_FIELD)
     params.update(extra)
     gp = G.Lattice(lat, n=n, precision=precision, axis_bc=tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"])),
                    collision=G.LBM_MRT if collision == "mrt" else G.LBM_BGK,
@@ -40,6 +42,8 @@ def oracle_lattice(wl, collision="mrt", bc="halfway", g=(0.0, 0.0, 0.0), g_start
         params["Tr"] = wl["Tr"]
     if wl.get("model", 0) == 1:
         params.update(SC_PARAMS, model=1)
+    if wl.get("model", 0) == 2:
+        params.update(W.PF_PARAMS, model=2)
     params.update(extra)
     wall = tuple(wl["wall"]) + (0,) * (3 - len(wl["wall"]))
     o = O.Oracle(wl["dim"], wl["n"], wall, bgk=int(collision == "bgk"), bc_mode=int(bc != "halfway"),

@@ -1,0 +1,140 @@
+"""The phase-field model on the GPU against the oracle (Sec. V: the measurement
+serves phase-field models as well; the model is the oracle's, pinned by
+test_oracle_phasefield.py).
+
+Fields after every run: phi on fluid nodes and both solid layers (the wall
+order parameter), rho and mu on fluid nodes, both population sets S_t, and the
+in-step contact angles read on phi at the isolevel 0.  Tolerances: FP64 1e-12
+of the largest value (the operations differ from the oracle's only in their
+order); FP32 storage 1e-6 of |phi| <= 1 and 0.1 degree, as for the other
+models.
+"""
+import numpy as np
+import pytest
+
+from paper_2202_06516_amd import lbm as G
+from paper_2202_06516_amd import workloads as W
+
+from .pairs import gpu_lattice, oracle_lattice, rel_err
+from .test_gpu_fullsize import angles_close
+
+pytestmark = pytest.mark.gpu
+
+WALL_PHI = -0.13   # order parameter of the outer walls
+
+
+def run_pair(wl, precision, collision, bc, steps, every, nsec, g=(0.0, 0.0, 0.0), g_start=0):
+    gp = gpu_lattice(wl, precision, collision, bc, g=g, g_start=g_start, wall_mu=WALL_PHI)
+    o = oracle_lattice(wl, collision, bc, g=g, g_start=g_start, wall_mu=WALL_PHI)
+    gp.set_measure(0, nsec)
+    ga = gp.step(steps, measure_every=every, cap=steps // every + 1)
+    oa = o.step_measured(steps, every, 0, nsec)
+    o.update_derived()
+    return gp, o, ga, oa
+
+
+def check_fields(gp, o, tol, what):
+    fl = o.cls == 0
+    errs = dict(phi=rel_err(gp.phi, o.phi, o.cls <= 2), rho=rel_err(gp.rho, o.rho, fl),
+                mu=rel_err(gp.read(G.FIELD_MU), o.mu, fl), f=rel_err(gp.f, o.f), g=rel_err(gp.g, o.g))
+    print(what, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, (what, k, v)
+
+
+@pytest.mark.parametrize("collision,bc", [("mrt", "halfway"), ("bgk", "halfway"), ("mrt", "bouzidi")])
+def test_phase_field_2d_fp64(collision, bc):
+    wl = W.pf_sessile_2d()
+    gp, o, ga, oa = run_pair(wl, G.LBM_F64, collision, bc, 300, 100, 2)
+    check_fields(gp, o, 1e-12, f"2-D FP64 {collision} {bc}")
+    angles_close(ga, oa, 1e-6, "2-D FP64")
+    assert [a.step for a in ga] == [0, 100, 200] and all(a.n_valid == 2 for a in ga[1:])
+
+
+@pytest.mark.parametrize("precision", [G.LBM_F32, G.LBM_F32_MIXED])
+def test_phase_field_2d_fp32(precision):
+    wl = W.pf_sessile_2d()
+    gp, o, ga, oa = run_pair(wl, precision, "mrt", "halfway", 300, 100, 2)
+    fl = o.cls == 0
+    e = rel_err(gp.phi, o.phi, o.cls <= 2)
+    print("2-D FP32 phi error %.2e" % e)
+    assert e <= 1e-6
+    assert rel_err(gp.rho, o.rho, fl) <= 1e-6
+    angles_close(ga, oa, 0.1, "2-D FP32")
+
+
+@pytest.mark.parametrize("precision,tol,tol_deg", [(G.LBM_F64, 1e-12, 1e-6), (G.LBM_F32, 1e-6, 0.1)])
+def test_phase_field_3d_with_gravity(precision, tol, tol_deg):
+    # a lattice whose shape the one-pass step would take: the phase-field model
+    # stays on the split step
+    wl = W.pf_sessile_3d()
+    gp, o, ga, oa = run_pair(wl, precision, "bgk", "halfway", 200, 100, wl["n_sectors"],
+                             g=(2e-6, 0.0, -5e-6), g_start=50)
+    if precision == G.LBM_F64:
+        check_fields(gp, o, tol, "3-D FP64")
+    else:
+        e = rel_err(gp.phi, o.phi, o.cls <= 2)
+        print("3-D FP32 phi error %.2e" % e)
+        assert e <= tol
+    angles_close(ga, oa, tol_deg, "3-D")
+    assert ga[-1].n_valid > 0
+    assert "k_density" in gp.profile(1) and "k_step" not in gp.profile(1)
+
+
+def test_phase_field_velocity_and_young_force():
+    wl = W.pf_sessile_2d()
+    gp, o, _, _ = run_pair(wl, G.LBM_F64, "mrt", "halfway", 200, 100, 2)
+    v, ov = gp.read(G.FIELD_VEL), o.velocity()
+    # v = j / rho + F / (2 rho) with rho close to 1: its error is that of the
+    # populations (below 1e-12 of their largest value, 4/9), absolute
+    assert np.max(np.abs(v - ov)) <= 1e-12
+    a, y = gp.young_force(0.0133, 80.0, 90.0)
+    oa, oy = o.young_force(0.0133, 80.0, 90.0)
+    assert a.n_valid == oa.n_valid == 2
+    for s in range(2):
+        assert tuple(y.count[s]) == tuple(oy.count[s])
+        assert abs(y.force[s] - oy.force[s]) <= 1e-9
+
+
+def test_phase_field_conservation_fp32():
+    wl = W.pf_sessile_2d()
+    gp = gpu_lattice(wl, G.LBM_F32, "mrt", wall_mu=WALL_PHI)
+    fl = gp.read(G.FIELD_CLASS) == 0
+    p0 = float(np.sum(gp.phi[fl], dtype=np.float64))
+    m0 = gp.mass()
+    gp.step(1000)
+    p1 = float(np.sum(gp.phi[fl], dtype=np.float64))
+    assert abs(p1 - p0) <= 1e-6 * float(np.sum(np.abs(gp.phi[fl]), dtype=np.float64)), (p0, p1)
+    assert abs(gp.mass() / m0 - 1.0) <= 1e-6
+
+
+def test_phase_field_checkpoint_restore_is_exact():
+    wl = W.pf_sessile_2d()
+    a = gpu_lattice(wl, G.LBM_F32, "mrt", wall_mu=WALL_PHI)
+    a.step(50)
+    f, g = a.f, a.g
+    b = gpu_lattice(dict(wl, drops=[]), G.LBM_F32, "mrt", wall_mu=WALL_PHI)
+    b.write(G.FIELD_F, f)
+    b.write(G.FIELD_G, g)
+    assert np.array_equal(b.phi, a.phi)
+    a.step(70)
+    b.step(70)
+    assert np.array_equal(b.phi, a.phi) and np.array_equal(b.f, a.f) and np.array_equal(b.g, a.g)
+    # a write of one set into a state in the pull form keeps the other set
+    a.write(G.FIELD_F, a.f)
+    assert np.array_equal(a.g, b.g)
+
+
+def test_phase_field_errors():
+    wl = W.pf_sessile_2d()
+    gp = gpu_lattice(wl, G.LBM_F64, "mrt", wall_mu=WALL_PHI)
+    with pytest.raises(G.LbmError):
+        gp.write(G.FIELD_RHO, np.ones(gp.shape))
+    with pytest.raises(G.LbmError):
+        gpu_lattice(wl, G.LBM_F64, "mrt", pf_tau=0.5)
+    other = gpu_lattice(W.sessile_2d(n=64), G.LBM_F64, "mrt")
+    with pytest.raises(G.LbmError):
+        other.read(G.FIELD_PHI)
+    with pytest.raises(G.LbmError):
+        G.Batch([dict(n=(64, 64), solid=dict(center=(32, 20), radius=10, mu_w=0.1), drop=((32, 38), 8))],
+                model=G.LBM_MODEL_PHASE_FIELD)
