@@ -19,7 +19,10 @@
  *   - wetting: a prescribed chemical potential on two solid layers, whose
  *     densities follow Eq. 14 (Sec. III A);
  *   - streaming at the curved wall: halfway bounce-back, or linear
- *     interpolated bounce-back with an exact mass correction (Sec. III A);
+ *     interpolated bounce-back with an exact mass correction (Sec. III A),
+ *     whose q < 1/2 branch interpolates only with a partner population within
+ *     a factor of two of the node's own (else halfway: no interpolation across
+ *     the liquid-gas jump at a contact line);
  *   - contact angle: isodensity crossings on liquid-gas links (Eq. 15), the
  *     crossings nearest 1 and 2 lattice units from the substrate, their secant
  *     meets the substrate at the contact point, angle to the substrate tangent

@@ -914,9 +914,17 @@ void ora_phase_stream(ora_ctx* c) {
             if (c->p.bc_mode == 1) {
                 double q = ora_link_q(c, x, y, z, j);
                 if (q < 0.5) {
+                    /* the partner behind x must hold the same phase: its population
+                     * of direction j within a factor of two of x's own, else the
+                     * link keeps the halfway value (an interpolation across the
+                     * liquid-gas jump at a contact line would move up to the whole
+                     * density difference into the rest population) */
                     long long xb = nbr(c, x, y, z, c->e[i][0], c->e[i][1], c->e[i][2]);
-                    if (xb >= 0 && c->cls[xb] == C_FLUID)
-                        val = 2.0 * q * out_j + (1.0 - 2.0 * q) * c->fpost[j * N + xb];
+                    if (xb >= 0 && c->cls[xb] == C_FLUID) {
+                        double fb = c->fpost[j * N + xb];
+                        if (fb <= 2.0 * out_j && out_j <= 2.0 * fb)
+                            val = 2.0 * q * out_j + (1.0 - 2.0 * q) * fb;
+                    }
                 } else {
                     val = out_j / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * c->fpost[i * N + n];
                 }

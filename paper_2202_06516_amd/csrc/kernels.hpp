@@ -240,7 +240,9 @@ __device__ __forceinline__ R d2c(R m2, R m1, R c, R p1, R p2) {
 // the missing population of the curved wall: halfway bounce-back
 // S_i = f*_j(x) with j = opp(i), or the linear interpolation in the wall
 // fraction q of the link from x along e_j, and the difference to f*_j(x) is
-// added to S_0 so that the fluid mass is unchanged (Sec. III A).
+// added to S_0 so that the fluid mass is unchanged (Sec. III A).  For q < 1/2
+// the interpolation partner is the node behind x; it is used only when its
+// population lies within a factor of two of x's own (the same phase).
 struct WallBC {
     const uint32_t* nbmask;  // bit j: x + e_j solid (boundary fluid nodes)
     const int* bidx;         // boundary-list index of a boundary fluid node
@@ -290,7 +292,11 @@ __device__ __forceinline__ void gather(const R* __restrict__ f, const Dims& d, l
         if (q < C(0.5)) {
             if (!(bm & (1u << i))) {  // x + e_i is the fluid node behind x
                 const uint32_t b = ix + (uint32_t)(ox[1 + L::E[i][0]] + oy[1 + L::E[i][1]] + oz[1 + L::E[i][2]]);
-                v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)at(f + (size_t)j * d.N, b);
+                // only a partner of the same phase: its population within a
+                // factor of two of x's own (at a contact line the node behind
+                // can be across the liquid-gas jump), else the halfway value
+                const R fb = at(f + (size_t)j * d.N, b);
+                if (fb <= R(2) * outj && outj <= R(2) * fb) v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)fb;
             }
         } else {
             v = (C)outj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * (C)at(f + (size_t)i * d.N, ix);

@@ -41,11 +41,13 @@ from . import lbm as G
 from . import workloads as WL
 
 
-def make_batch(cases, Tr, precision=G.LBM_F32, stream=None, k=0.28, kappa=0.01, g=0.0, g_start=0):
+def make_batch(cases, Tr, precision=G.LBM_F32, stream=None, k=0.28, kappa=0.01, g=0.0, g_start=0,
+               bc_mode=G.LBM_BC_HALFWAY):
     # the floor and ceiling are two solid layers (walled along y), x periodic;
     # g > 0 pulls toward the floor (sessile), g < 0 away from it (pendent)
     return G.Batch(cases, precision=precision, axis_bc=(0, 1, 0), tile_w=256, blocks_per_cu=8, stream=stream,
-                   tau=1.0, Tr=Tr, k=k, kappa=kappa, collision=G.LBM_MRT, g=(0.0, -g, 0.0), g_start_step=g_start)
+                   tau=1.0, Tr=Tr, k=k, kappa=kappa, collision=G.LBM_MRT, g=(0.0, -g, 0.0), g_start_step=g_start,
+                   bc_mode=bc_mode)
 
 
 def settle(b, every=1000, tol=0.02, min_steps=10000, max_steps=200000, log=print):
@@ -111,11 +113,12 @@ def linear_fit_error(x, y):
 
 
 def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, every=1000, tol=0.02,
-        min_steps=10000, max_steps=200000, k=0.28, kappa=0.01, g=0.0, g_start=0, stream=None, log=print):
+        min_steps=10000, max_steps=200000, k=0.28, kappa=0.01, g=0.0, g_start=0, stream=None, log=print,
+        bc_mode=G.LBM_BC_HALFWAY):
     cases, labels = WL.sweep_cases(kind, scale=scale, mu=mu, values=values)
     nx, ny = cases[0]["n"]
     H = 100.0 * scale
-    b = make_batch(cases, Tr, precision, stream, k=k, kappa=kappa, g=g, g_start=g_start)
+    b = make_batch(cases, Tr, precision, stream, k=k, kappa=kappa, g=g, g_start=g_start, bc_mode=bc_mode)
     min_steps = max(min_steps, g_start + 2 * every)
     inf = b.info()
     rho_m = 0.5 * (inf["rho_g"] + inf["rho_l"])
@@ -136,7 +139,8 @@ def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, ever
                         sectors=[float(final[i].sector_deg[k]) for k in range(2)],
                         contact=[[round(float(final[i].contact[k][d]), 2) for d in range(2)] for k in range(2)]))
     b.close()
-    out = dict(kind=kind, Tr=Tr, k=k, kappa=kappa, g=g, g_start=g_start, nx=nx, ny=ny, H=H, steps=steps, seconds=round(seconds, 2),
+    out = dict(kind=kind, Tr=Tr, k=k, kappa=kappa, g=g, g_start=g_start, nx=nx, ny=ny, H=H,
+               wall="interpolated" if bc_mode == G.LBM_BC_BOUZIDI_MC else "halfway", steps=steps, seconds=round(seconds, 2),
                mlups=round(float(inf["fluid_nodes"]) * steps / seconds / 1e6, 1), cases=res)
     ok = [r for r in res if math.isfinite(r["theta"])]
     if kind == "wettability" and len(ok) >= 3:
@@ -219,6 +223,8 @@ def main(argv=None):
     ap.add_argument("--mu", type=float, nargs="*", default=None, help="wall chemical potentials (default per sweep)")
     ap.add_argument("--g", type=float, default=0.0, help="gravity toward the floor (negative: pendent drops)")
     ap.add_argument("--g-start", type=int, default=20000, help="first step with gravity")
+    ap.add_argument("--wall", choices=("halfway", "interpolated"), default="halfway",
+                    help="curved-wall scheme: halfway bounce-back, or the interpolated one with the mass correction")
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--min-steps", type=int, default=10000)
@@ -235,7 +241,8 @@ def main(argv=None):
     rep = run(a.kind, Tr=a.Tr, precision=G.LBM_F64 if a.f64 else G.LBM_F32, scale=a.scale, every=a.every,
               tol=a.tol, min_steps=a.min_steps, max_steps=a.max_steps, k=a.k, kappa=a.kappa, g=a.g,
               g_start=a.g_start if a.g else 0,
-              mu=tuple(a.mu) if a.mu else None, log=log)
+              mu=tuple(a.mu) if a.mu else None, log=log,
+              bc_mode=G.LBM_BC_BOUZIDI_MC if a.wall == "interpolated" else G.LBM_BC_HALFWAY)
     print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
     for r in rep["cases"]:
         print(json.dumps(r), flush=True)

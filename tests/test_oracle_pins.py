@@ -700,7 +700,7 @@ def _brute_step(dim, n, wall, f, prm, discs, wall_mu, bc):
         return brentq(dist, 0.0, 1.0, xtol=1e-15, rtol=1e-15)
 
     out = np.zeros_like(f)
-    used_q = []
+    used_q, kept_q = [], []    # links interpolated; links with q < 1/2 left halfway (partner of the other phase)
     for p in nodes:
         if cls[p] != 0:
             continue
@@ -718,8 +718,14 @@ def _brute_step(dim, n, wall, f, prm, discs, wall_mu, bc):
                 q = link_q(p, j)
                 xb = nbrs[p][i]
                 if q < 0.5 and cls[xb] == 0:
-                    val = 2 * q * back + (1 - 2 * q) * post[xb][j]
-                    used_q.append(q)
+                    # interpolation only between two populations of direction j
+                    # that lie within a factor of two of each other
+                    fb = post[xb][j]
+                    if fb <= 2 * back and back <= 2 * fb:
+                        val = 2 * q * back + (1 - 2 * q) * fb
+                        used_q.append(q)
+                    else:
+                        kept_q.append(q)
                 elif q >= 0.5:
                     val = back / (2 * q) + (2 * q - 1) / (2 * q) * post[p][i]
                     used_q.append(q)
@@ -727,7 +733,7 @@ def _brute_step(dim, n, wall, f, prm, discs, wall_mu, bc):
             dm += back - val
         new[0] = post[p][0] + dm
         out[:, p[2], p[1], p[0]] = new
-    return out, cls, used_q
+    return out, cls, (used_q, kept_q)
 
 
 @pytest.mark.parametrize("bc", [0, 1])
@@ -736,7 +742,9 @@ def test_one_step_with_walls_and_a_disc_matches_brute_force(bc):
     chemical potential), periodic x, an off-node disc of radius 3.4 with its
     own, tilted gravity, and a non-uniform state with non-equilibrium parts;
     one oracle step equals the brute-force step above to 1e-12, with the
-    interpolated wall using links on both sides of q = 1/2."""
+    interpolated wall using links on both sides of q = 1/2, and links with
+    q < 1/2 whose partner population differs by more than a factor of two
+    (the random density field spans a factor of five) left at the halfway value."""
     prm = dict(Tr=0.8, k=0.28, kappa=0.01, tau=0.8, s_e=1.64, s_eps=1.54, s_q=1.9, g=(3e-4, -2e-4, 0.0))
     o = O.Oracle(2, (16, 16), (0, 1), bc_mode=bc, wall_mu=0.021, **prm)
     disc = ((7.3, 8.6), 3.4, 0.057)
@@ -751,7 +759,9 @@ def test_one_step_with_walls_and_a_disc_matches_brute_force(bc):
     assert all(o.cls[0, y, x] == cls[(x, y, 0)] for y in range(16) for x in range(16))
     assert {1, 2} <= set(cls.values())
     if bc == 1:
+        used, kept = used
         assert min(used) < 0.35 and max(used) > 0.65 and any(abs(q - 0.5) < 1e-15 for q in used), sorted(used)
+        assert any(q < 0.5 for q in used) and kept, (sorted(used), sorted(kept))
     o.step(1)
     assert np.max(np.abs(o.f - new)) < 1e-12 * np.max(np.abs(new))
     # the fluid mass is what it was (the mass correction of the interpolated wall)
