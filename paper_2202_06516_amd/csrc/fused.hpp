@@ -443,10 +443,12 @@ __device__ __forceinline__ void centroid_reduce_sums(unsigned long long cnt, uns
 // Chemical potential (Eq. 11-12; psi of the pseudopotential model) of the
 // density k_step and k_ghost completed, z-chunked as k_mu; besides, the check
 // of the density that the split path's density pass makes, and on measure
-// steps the liquid centroid sums of the measurement (Sec. III B).  Plane
-// z+1's density stencil is loaded before plane z's value is stored, and the
-// store is unconditional (solid nodes write a sink slot: their mu is the wall
-// value set with the solids), so that the loads do not wait for the stores.
+// steps the liquid centroid sums of the measurement (Sec. III B).  The column
+// values z-2 .. z+2 stay in registers as the walk moves up (one new load per
+// plane), plane z+1's x and y neighbours are loaded before plane z's value is
+// stored, and the store is unconditional (solid nodes write a sink slot: their
+// mu is the wall value set with the solids), so that the loads do not wait for
+// the stores.
 template <class L, typename R, typename C, bool SC>
 __global__ void __launch_bounds__(256) k_mu_step(const R* __restrict__ rho, R* __restrict__ mu,
                                                  const uint8_t* __restrict__ cls, Dims d, Thermo th,
@@ -457,38 +459,40 @@ __global__ void __launch_bounds__(256) k_mu_step(const R* __restrict__ rho, R* _
     const int xs = in ? x : 0, ys = in ? y : 0;
     const int z1 = z0 + d.zc < d.nz ? z0 + d.zc : d.nz;
     const Nbr ox = nbr_offsets(xs, d.nx, 1), oy = nbr_offsets(ys, d.ny, d.px);
-    // density stencil of one plane: centre, then -2, -1, +1, +2 along x, y, z; and the class
-    auto load = [&](int z, R v[13], uint8_t& c) {
-        const uint32_t ix = (uint32_t)nid(d, xs, ys, z);
-        const Nbr oz = L::D == 3 ? nbr_offsets(z, d.nz, d.px * d.ny) : Nbr{0, 0, 0, 0};
+    // the x and y neighbours of one plane (-2, -1, +1, +2 along x, then y) and the class
+    auto load = [&](int z, R v[8], uint8_t& c) {
+        const uint32_t ix = nid32(d, xs, ys, z);
         auto p = [&](int o) { return at(rho, ix + (uint32_t)o); };
         c = at(cls, ix);
-        v[0] = p(0);
-        v[1] = p(ox.m2); v[2] = p(ox.m1); v[3] = p(ox.p1); v[4] = p(ox.p2);
-        v[5] = p(oy.m2); v[6] = p(oy.m1); v[7] = p(oy.p1); v[8] = p(oy.p2);
-        v[9] = p(oz.m2); v[10] = p(oz.m1); v[11] = p(oz.p1); v[12] = p(oz.p2);
+        v[0] = p(ox.m2); v[1] = p(ox.m1); v[2] = p(ox.p1); v[3] = p(ox.p2);
+        v[4] = p(oy.m2); v[5] = p(oy.m1); v[6] = p(oy.p1); v[7] = p(oy.p2);
     };
+    // the column x, y: planes z - 2 .. z + 2 held in a sliding window, so that
+    // each plane loads one new column value instead of five (periodic images)
+    auto col = [&](int z) { return at(rho, nid32(d, xs, ys, wrapc(z, d.nz))); };
     unsigned long long cnt = 0, sx = 0, sy = 0, sz = 0;
     bool bad = false;
-    R cur[13], nxt[13];
+    R cur[8], nxt[8];
+    R w0 = col(z0 - 2), w1 = col(z0 - 1), w2 = col(z0), w3 = col(z0 + 1), w4 = col(z0 + 2);
     uint8_t cc, cn;
     load(z0, cur, cc);
     for (int z = z0; z < z1; ++z) {
         load(z + 1 < z1 ? z + 1 : z, nxt, cn);
+        const R w5 = col(z + 3);  // unconditional: counted, in bounds
         const bool fl = in && (cc & CLS_MASK) == CLS_FLUID;
-        const C c0 = (C)cur[0];
+        const C c0 = (C)w2;
         C m;
         if constexpr (SC) {
             m = C(1) - exp(-c0);  // pseudopotential model: psi(rho) = 1 - exp(-rho)
         } else {
-            C lap = d2c<C>((C)cur[1], (C)cur[2], c0, (C)cur[3], (C)cur[4]);
-            lap += d2c<C>((C)cur[5], (C)cur[6], c0, (C)cur[7], (C)cur[8]);
-            if (L::D == 3) lap += d2c<C>((C)cur[9], (C)cur[10], c0, (C)cur[11], (C)cur[12]);
+            C lap = d2c<C>((C)cur[0], (C)cur[1], c0, (C)cur[2], (C)cur[3]);
+            lap += d2c<C>((C)cur[4], (C)cur[5], c0, (C)cur[6], (C)cur[7]);
+            lap += d2c<C>((C)w0, (C)w1, c0, (C)w3, (C)w4);
             m = (psi_prime<C>(c0, th) - (C)th.mu_ref) - (C)th.kappa * lap;
         }
         at(fl ? mu : sink, fl ? (uint32_t)nid(d, xs, ys, z) : (threadIdx.x & 1023u)) = (R)m;
         if (fl) {
-            const R r0 = cur[0];
+            const R r0 = w2;
             bad = bad || !(r0 > R(0) && r0 < inv_b);  // also catches NaN
             if ((double)r0 >= rho_m) {
                 cnt += 1;
@@ -498,8 +502,13 @@ __global__ void __launch_bounds__(256) k_mu_step(const R* __restrict__ rho, R* _
             }
         }
 #pragma unroll
-        for (int k = 0; k < 13; ++k) cur[k] = nxt[k];
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
         cc = cn;
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
+        w3 = w4;
+        w4 = w5;
     }
     if (bad) atomicOr(&ctl->status, 1);
     if (measuring(ctl)) centroid_reduce_sums(cnt, sx, sy, sz, &ctl->m);
