@@ -49,6 +49,9 @@ def parse():
                          "blow this drop up")
     ap.add_argument("--step-kernel", default="auto", choices=["auto", "split"],
                     help="auto: the one-pass step where the lattice allows it; split: density pass + collision")
+    ap.add_argument("--model", default="chemical-potential", choices=["chemical-potential", "phase-field"],
+                    help="force model of the sessile3d workload (the phase-field model runs the split step, both "
+                         "population sets: 304 algorithmic bytes per fluid-node update in FP32)")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps at full size (0 = skip)")
     ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps at full size on one thread")
@@ -107,6 +110,12 @@ def main():
     prec = {"f32": G.LBM_F32, "f32mixed": G.LBM_F32_MIXED, "f64": G.LBM_F64}[args.precision]
     elem = 8 if prec == G.LBM_F64 else 4
     wl = W.sessile_3d(mu_w=0.04, n=args.n)
+    pf = args.model == "phase-field"
+    extra = {}
+    if pf:
+        # the same geometry with the order parameter: phi_w = 0.04 on the sphere, Eq. 16 width 2 xi
+        wl = dict(wl, model=2, W=W.PF_W)
+        extra = dict(W.PF_PARAMS, model=G.LBM_MODEL_PHASE_FIELD)
     stream = torch.cuda.Stream()
     rates = {}
     if args.collision == "mrt":
@@ -115,9 +124,10 @@ def main():
     lat = G.Lattice(G.LBM_D3Q19, n=wl["n"], precision=prec, axis_bc=(1, 1, 1), stream=stream.cuda_stream,
                     collision=G.LBM_BGK if args.collision == "bgk" else G.LBM_MRT, bc_mode=G.LBM_BC_HALFWAY,
                     tau=1.0, Tr=wl["Tr"], k=0.28, kappa=0.01,
-                    step_kernel=G.LBM_STEP_AUTO if args.step_kernel == "auto" else G.LBM_STEP_SPLIT, **rates)
+                    step_kernel=G.LBM_STEP_AUTO if args.step_kernel == "auto" else G.LBM_STEP_SPLIT, **rates,
+                    **extra)
     lat.set_solids(wl["solids"])
-    lat.init_drops(wl["drops"], W=10.0)
+    lat.init_drops(wl["drops"], W=wl.get("W", 10.0))
     lat.set_measure(0, wl["n_sectors"])
     info = lat.info()
     n_fluid = info["n_fluid"]
@@ -155,12 +165,14 @@ def main():
     prof = lat.profile(args.profile_steps)
     Q = 19
     # dominant kernel: the one-pass step k_step, or the split path's k_collide; algorithmic bytes per fluid
-    # node = each population read once and written once (2 Q P)
+    # node = each population read once and written once (2 Q P; twice that with the phase-field model's
+    # second population set)
     kern = "k_step" if "k_step" in prof else "k_collide"
-    coll_bytes = n_fluid * 2 * Q * elem
+    sets = 2 if pf else 1
+    coll_bytes = n_fluid * 2 * Q * elem * sets
     coll_ms = prof[kern]
     achieved = coll_bytes / (coll_ms * 1e-3) / 1e9
-    step_alg_bytes = 2 * Q * 4 * n_fluid                   # 152 B per fluid-node update (FP32)
+    step_alg_bytes = 2 * Q * 4 * sets * n_fluid             # 152 B per fluid-node update (FP32), 304 phase field
 
     out = {
         "metric": "MLUPS (D3Q19 FP32 fluid-node updates/s) with %HBM roofline",
@@ -177,14 +189,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"sessile drop on a sphere, D3Q19 {args.n}^3 walled box, sphere r={60 * args.n // 256}, "
                                f"drop r0={40 * args.n // 256}, mu_w=0.04, Tr={wl['Tr']}, {args.collision.upper()} tau=1, "
-                               f"angle every {wl['every']} steps over {wl['n_sectors']} sectors",
+                               f"angle every {wl['every']} steps over {wl['n_sectors']} sectors"
+                               + (", phase-field model (order parameter, wall phi_w=0.04)" if pf else ""),
                    "lattice": [args.n] * 3, "fluid_nodes": n_fluid, "precision": args.precision,
                    "collision": args.collision, **({"mrt_rates": rates} if rates else {})},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision)),
+                     "traffic": None if pf else COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision)),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
-        "step_efficiency": {"algorithmic_bytes_per_update": 2 * Q * 4,
+        "step_efficiency": {"algorithmic_bytes_per_update": 2 * Q * 4 * sets,
                             "achieved_GBs": round(step_alg_bytes / (ms_step * 1e-3) / 1e9, 1),
                             "frac_of_peak": round(step_alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},

@@ -17,7 +17,9 @@ statistics the paper reports:
   measured angle against the spherical-cap angle as the drops deform, and
   the radii at which a pendent drop detaches;
 - ``sc-wettability``: the same measurement on the pseudopotential model
-  (Sec. V), theta against the wall density on single lattices.
+  (Sec. V), theta against the wall density on single lattices;
+- ``pf-wettability``: on the phase-field model (Sec. V), theta against the
+  wall order parameter on single lattices.
 
 Each case also gets the spherical-cap angle of Sec. IV A from its final
 density (base length L between the two measured contact points, cap height
@@ -175,21 +177,18 @@ def run(kind, Tr=0.6, precision=G.LBM_F32, scale=1.0, mu=None, values=None, ever
     return out
 
 
-def sc_wettability(rho_w=(0.3, 0.5, 0.7, 0.9, 1.1, 1.3, 1.5), n=256, R=48.0, r0=36.0, steps=40000, every=1000,
-                   precision=G.LBM_F64, log=print):
-    """The measurement on the pseudopotential model (Sec. V): drops on a
-    cylinder of radius R in a periodic n x n lattice, one lattice per wall
-    density rho_w, each run to steps; the measured angle and the spherical-cap
-    angle of the final drop.  The batched solver has no pseudopotential
-    variant, so the cases run one after the other."""
+def _lattice_wettability(kind, make, values, read_field, rho_m, n, R, r0, steps, every, W, log):
+    """Drops on a cylinder of radius R in a periodic n x n lattice, one lattice
+    per wall value (made by make(value)), each run to steps: the measured angle
+    and the spherical-cap angle of the final drop (isolevel rho_m of the field
+    read_field(lattice) returns)."""
     res = []
     t0 = time.perf_counter()
-    for rw in rho_w:
-        lat = G.Lattice(G.LBM_D2Q9, n=(n, n, 1), precision=precision, tau=1.0, collision=G.LBM_MRT,
-                        model=G.LBM_MODEL_PSEUDOPOTENTIAL, sc_G=WL.SC_G, rho_l=WL.SC_RHO_L, rho_g=WL.SC_RHO_G)
+    for v in values:
+        lat = make(v)
         c = (n / 2.0, 10.0 + R)
-        lat.set_solids([dict(center=c, radius=R, mu_w=rw)])
-        lat.init_drops([((c[0], c[1] + R + r0), r0)], W=5.0)
+        lat.set_solids([dict(center=c, radius=R, mu_w=v)])
+        lat.init_drops([((c[0], c[1] + R + r0), r0)], W=W)
         lat.set_measure(0, 2)
         ser = lat.step(steps, measure_every=every, cap=steps // every + 1)
         a = ser[-1]
@@ -197,24 +196,51 @@ def sc_wettability(rho_w=(0.3, 0.5, 0.7, 0.9, 1.1, 1.3, 1.5), n=256, R=48.0, r0=
         drift = abs(ser[-1].mean_deg - ser[-2].mean_deg) if len(ser) > 1 and a.status == 0 else math.nan
         cap = math.nan
         if math.isfinite(th):
-            rho = lat.rho[0].astype(np.float64)
+            fld = read_field(lat)[0].astype(np.float64)
             cls = lat.read(G.FIELD_CLASS)[0]
-            cap = cap_angle(rho, cls, 0.5 * (WL.SC_RHO_L + WL.SC_RHO_G), c, R, a.contact)
+            cap = cap_angle(fld, cls, rho_m, c, R, a.contact)
         lat.close()
-        res.append(dict(rho_w=rw, theta=float(th), cap=float(cap), drift=float(drift),
+        res.append(dict(wall=v, theta=float(th), cap=float(cap), drift=float(drift),
                         sectors=[float(a.sector_deg[0]), float(a.sector_deg[1])]))
-        log(f"sc-wettability: rho_w {rw}: theta {th:.2f}, cap {cap:.2f}, {time.perf_counter() - t0:.1f} s")
+        log(f"{kind}: wall value {v}: theta {th:.2f}, cap {cap:.2f}, {time.perf_counter() - t0:.1f} s")
     ok = [r for r in res if math.isfinite(r["theta"])]
-    out = dict(kind="sc-wettability", G=WL.SC_G, n=n, R=R, r0=r0, steps=steps, cases=res)
-    if ok:
-        d = [abs(r["theta"] - r["cap"]) for r in ok if math.isfinite(r["cap"])]
+    out = dict(kind=kind, n=n, R=R, r0=r0, steps=steps, cases=res)
+    d = [abs(r["theta"] - r["cap"]) for r in ok if math.isfinite(r["cap"])]
+    if d:
         out.update(max_abs_theta_minus_cap=round(max(d), 2), mean_abs_theta_minus_cap=round(float(np.mean(d)), 2))
+    return out
+
+
+def sc_wettability(rho_w=(0.3, 0.5, 0.7, 0.9, 1.1, 1.3, 1.5), n=256, R=48.0, r0=36.0, steps=40000, every=1000,
+                   precision=G.LBM_F64, log=print):
+    """The measurement on the pseudopotential model (Sec. V): theta and the
+    cap angle against the wall density rho_w.  The cases run one after the
+    other on single lattices."""
+    def make(v):
+        return G.Lattice(G.LBM_D2Q9, n=(n, n, 1), precision=precision, tau=1.0, collision=G.LBM_MRT,
+                         model=G.LBM_MODEL_PSEUDOPOTENTIAL, sc_G=WL.SC_G, rho_l=WL.SC_RHO_L, rho_g=WL.SC_RHO_G)
+    out = _lattice_wettability("sc-wettability", make, rho_w, lambda lat: lat.rho, 0.5 * (WL.SC_RHO_L + WL.SC_RHO_G),
+                               n, R, r0, steps, every, 5.0, log)
+    out["G"] = WL.SC_G
+    return out
+
+
+def pf_wettability(phi_w=(-0.6, -0.4, -0.2, 0.0, 0.2, 0.4, 0.6), n=256, R=48.0, r0=36.0, steps=40000, every=1000,
+                   precision=G.LBM_F64, log=print):
+    """The measurement on the phase-field model (Sec. V): theta and the cap
+    angle against the wall order parameter phi_w, read on phi at the isolevel 0."""
+    def make(v):
+        return G.Lattice(G.LBM_D2Q9, n=(n, n, 1), precision=precision, tau=1.0, collision=G.LBM_MRT,
+                         model=G.LBM_MODEL_PHASE_FIELD, **WL.PF_PARAMS)
+    out = _lattice_wettability("pf-wettability", make, phi_w, lambda lat: lat.phi, 0.0, n, R, r0, steps, every,
+                               WL.PF_W, log)
+    out.update(WL.PF_PARAMS)
     return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="wettability / drop-size / curvature sweeps on the batched solver")
-    ap.add_argument("kind", choices=("wettability", "size", "curvature", "gravity", "sc-wettability"))
+    ap.add_argument("kind", choices=("wettability", "size", "curvature", "gravity", "sc-wettability", "pf-wettability"))
     ap.add_argument("--Tr", type=float, default=0.6)
     ap.add_argument("--f64", action="store_true", help="FP64 storage and arithmetic (default FP32 storage)")
     ap.add_argument("--scale", type=float, default=1.0, help="every length times this (1: the 700 x 400 lattice)")
@@ -232,8 +258,8 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
-    if a.kind == "sc-wettability":
-        rep = sc_wettability(log=log)
+    if a.kind in ("sc-wettability", "pf-wettability"):
+        rep = (sc_wettability if a.kind == "sc-wettability" else pf_wettability)(log=log)
         print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
         for r in rep["cases"]:
             print(json.dumps(r), flush=True)
