@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -1330,6 +1331,13 @@ struct lbm_unet {
     int ncasts = 0;
     i64 cast_total = 0;
     i64 step = 0;
+    // lbm_unet_train_step's forward and backward passes, captured as two
+    // graphs for graph_nb samples (the input cast, the loss and the Adam step,
+    // which read the caller's pointers or the step count, stay eager);
+    // LBM_UNET_GRAPHS=0 keeps every launch eager
+    bool use_graphs = true;
+    int graph_nb = 0;
+    hipGraphExec_t gfwd = nullptr, gbwd = nullptr;
 };
 
 namespace {
@@ -1536,6 +1544,31 @@ lbm_status load_input(lbm_unet* u, const float* x, int n) {
     return LBM_OK;
 }
 
+void drop_graphs(lbm_unet* u) {
+    for (hipGraphExec_t* g : {&u->gfwd, &u->gbwd})
+        if (*g) {
+            (void)hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
+    u->graph_nb = 0;
+}
+
+// the launches of fn(u) on u's stream as an executable graph
+lbm_status capture(lbm_unet* u, void (*fn)(lbm_unet*), hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    UCHK(u, hipStreamBeginCapture(u->stream, hipStreamCaptureModeThreadLocal));
+    fn(u);
+    const hipError_t e = hipStreamEndCapture(u->stream, &g);
+    if (e != hipSuccess) return ufail(u, LBM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        *out = nullptr;
+        return ufail(u, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    return LBM_OK;
+}
+
 lbm_status fwd_bwd(lbm_unet* u, const float* x, const float* t, int n, double* loss) {
     lbm_status s = load_input(u, x, n);
     if (s) return s;
@@ -1575,6 +1608,7 @@ void lbm_unet_config_default(lbm_unet_config* c) {
 lbm_status lbm_unet_destroy(lbm_unet* u) {
     if (!u) return LBM_OK;
     if (u->stream) (void)hipStreamSynchronize(u->stream);
+    drop_graphs(u);
     auto fr = [](void* p) {
         if (p) (void)hipFree(p);
     };
@@ -1610,6 +1644,10 @@ lbm_status lbm_unet_create(const lbm_unet_config* cfg, lbm_unet** out) {
     lbm_unet* u = new (std::nothrow) lbm_unet();
     if (!u) return LBM_E_NOMEM;
     u->cfg = *cfg;
+    {
+        const char* e = std::getenv("LBM_UNET_GRAPHS");
+        u->use_graphs = !(e && std::atoi(e) == 0);
+    }
     u->H = cfg->H;
     u->W = cfg->W;
     u->B = cfg->batch;
@@ -1800,8 +1838,27 @@ lbm_status lbm_unet_backward(lbm_unet* u, const float* x, const float* target, i
 
 lbm_status lbm_unet_train_step(lbm_unet* u, const float* x, const float* target, int n, double* loss) {
     if (!u || !x || !target) return u ? ufail(u, LBM_E_ARG, "train_step: null pointer") : LBM_E_ARG;
-    lbm_status s = fwd_bwd(u, x, target, n, loss);
-    if (s) return s;
+    lbm_status s;
+    if (!u->use_graphs) {
+        if ((s = fwd_bwd(u, x, target, n, loss))) return s;
+    } else {
+        if ((s = load_input(u, x, n))) return s;
+        if (u->graph_nb != n) {
+            drop_graphs(u);
+            if ((s = capture(u, forward, &u->gfwd)) || (s = capture(u, backward, &u->gbwd))) {
+                drop_graphs(u);
+                return s;
+            }
+            u->graph_nb = n;
+        }
+        const i64 np = pixels(u, 0);
+        UCHK(u, hipGraphLaunch(u->gfwd, u->stream));
+        k_mse<<<MSE_BLOCKS, 256, 0, u->stream>>>(u->y, target, np, u->dy, u->lpart);
+        k_sum_parts<<<1, 256, 0, u->stream>>>(u->lpart, MSE_BLOCKS, 1.0 / (double)np, u->loss);
+        UCHK(u, hipGraphLaunch(u->gbwd, u->stream));
+        UCHK(u, hipGetLastError());
+        if (loss) UCHK(u, hipMemcpyAsync(loss, u->loss, 8, hipMemcpyDeviceToHost, u->stream));
+    }
     u->step += 1;
     const double b1 = u->cfg.beta1, b2 = u->cfg.beta2;
     const float c1 = (float)(1.0 - std::pow(b1, (double)u->step));

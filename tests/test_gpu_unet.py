@@ -251,3 +251,23 @@ def test_checkpoint_resumes_training_exactly(tmp_path):
         other.load(ck)
     with pytest.raises(G.LbmError):
         a.load(tmp_path / "missing.ckpt")
+
+
+def test_captured_training_steps_equal_eager_ones(monkeypatch):
+    # the training step replays its forward and backward passes as graphs:
+    # every replay (with eager launches and synchronisations in between, and a
+    # new capture when the sample count changes) equals the eager step bit for bit
+    th, x, t = case(3, 16, 64, 48, 3, 21)
+    xd, td = dev(x), dev(t)
+    g = make_net(3, 16, 64, 48, 3)
+    monkeypatch.setenv("LBM_UNET_GRAPHS", "0")
+    e = make_net(3, 16, 64, 48, 3)
+    monkeypatch.delenv("LBM_UNET_GRAPHS")
+    g.set_params(th)
+    e.set_params(th)
+    for n in (3, 3, 2, 3, 3):
+        lg = g.train_step(xd.data_ptr(), td.data_ptr(), n)
+        le = e.train_step(xd.data_ptr(), td.data_ptr(), n)
+        torch.cuda.synchronize()
+        assert lg == le, (n, lg, le)
+        assert np.array_equal(g.params(), e.params()) and np.array_equal(g.grads(), e.grads()), n
