@@ -26,13 +26,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per launch of the dominant kernel from rocprofv3 counters: TCC_EA0_RDREQ_128B x 128 B +
 # TCC_EA0_RDREQ_64B x 64 B read, TCC_EA0_WRREQ_64B x 64 B written (a plain 1 GiB copy reads as 8388608
 # 128-byte and writes as 16777216 64-byte requests, exactly its bytes); valid only for the kernel as it
-# stands when they were taken (profiles/k_step_d3q19_f32_256cube.md).  Keyed by (kernel, lattice side,
-# precision, collision).
-COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk"): 16289872 * 128 + 1436 * 64 + 21889613 * 64,
-                   ("k_step", 256, "f32", "mrt"): 16626883 * 128 + 1838 * 64 + 21889397 * 64}
-# the same for kb_collide of the batched solver on the seeded table (profiles/kb_collide_batch_d2q9_512cases.md),
-# keyed by (number of cases, precision)
-BATCH_COUNTED_TRAFFIC = {}
+# stands when they were taken (profiles/k_step_d3q19_f32_256cube.md; the phase-field model's k_pf_collide in
+# profiles/k_pf_collide_d3q19_f32_256cube.md, its writes that are not 64-byte requests counted as 32 bytes).
+# Keyed by (kernel, lattice side, precision, collision, force model).
+COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk", "chemical-potential"): 16286538 * 128 + 1472 * 64 + 21889565 * 64,
+                   ("k_step", 256, "f32", "mrt", "chemical-potential"): 16626883 * 128 + 1838 * 64 + 21889397 * 64,
+                   ("k_collide", 256, "f32", "bgk", "phase-field"):
+                       24626936 * 128 + 2257 * 64 + 36426673 * 64 + 439204 * 32}
+# the same for kb_collide of the batched solver on the seeded table, from FETCH_SIZE x 2 and WRITE_SIZE in KiB
+# (the scaling of a plain copy; profiles/kb_collide_batch_d2q9_512cases.md), keyed by (number of cases,
+# precision)
+BATCH_COUNTED_TRAFFIC = {(512, "f32"): (1392231 * 2 + 1386829) * 1024}
 
 
 def parse():
@@ -195,7 +199,7 @@ def main():
                    "collision": args.collision, **({"mrt_rates": rates} if rates else {})},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if pf else COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision)),
+                     "traffic": COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision, args.model)),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
         "step_efficiency": {"algorithmic_bytes_per_update": 2 * Q * 4 * sets,
                             "achieved_GBs": round(step_alg_bytes / (ms_step * 1e-3) / 1e9, 1),
@@ -238,7 +242,7 @@ def batch_bench(args):
     # dominant kernel: kb_collide, timed with HIP events on the batch's stream over eager steps
     prof = b.profile(args.profile_steps)
     Q, P = 9, (8 if args.precision == "f64" else 4)
-    coll_bytes = inf["fluid_nodes"] * (2 * Q * P + 2 * P + 1)   # populations in and out, rho, mu, class
+    coll_bytes = inf["fluid_nodes"] * 2 * Q * P   # algorithmic: each population read once and written once
     coll_ms = prof["kb_collide"]
     achieved = coll_bytes / (coll_ms * 1e-3) / 1e9
     out = {
