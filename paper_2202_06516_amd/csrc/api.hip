@@ -403,15 +403,23 @@ struct Run {
         bc.bouzidi = 0;
         return bc;
     }
-    static void pf_density(lbm_ctx* c, int src, bool pull, double phi_m) {
+    // phi of the state in f[src] / g[src]; with_rho: rho as well (the fields a
+    // read or a measurement returns; the step's collision forms rho itself)
+    static void pf_density(lbm_ctx* c, int src, bool pull, double phi_m, bool with_rho) {
         const R* f = (const R*)c->f[src];
         const R* g = (const R*)c->g[src];
-        if (pull)
-            k_pf_density<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
-                f, g, (R*)c->rho, (R*)c->phi, c->cls, c->d, wall(c), c->ctl, phi_m);
-        else
-            k_pf_density<L, R, C, false><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
-                f, g, (R*)c->rho, (R*)c->phi, c->cls, c->d, wall(c), c->ctl, phi_m);
+        const dim3 grd = grid(c), blk(256, 1, 1);
+#define LBM_PF_DENSITY(P, W) \
+    k_pf_density<L, R, C, P, W><<<grd, blk, 0, c->stream>>>(f, g, (R*)c->rho, (R*)c->phi, c->cls, c->d, wall(c), \
+                                                            c->ctl, phi_m)
+        if (pull) {
+            if (with_rho) LBM_PF_DENSITY(true, true);
+            else LBM_PF_DENSITY(true, false);
+        } else {
+            if (with_rho) LBM_PF_DENSITY(false, true);
+            else LBM_PF_DENSITY(false, false);
+        }
+#undef LBM_PF_DENSITY
     }
     static void pf_mu(lbm_ctx* c) {
         if (c->d.zc > 1)
@@ -424,8 +432,8 @@ struct Run {
     template <bool PULL, bool MRT>
     static void pf_collide(lbm_ctx* c, int src, const WallBC& bc, const Collision<C>& cp) {
         k_pf_collide<L, R, C, PULL, MRT><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
-            (const R*)c->f[src], (R*)c->f[1 - src], (const R*)c->g[src], (R*)c->g[1 - src], (const R*)c->rho,
-            (const R*)c->phi, (const R*)c->mu, c->cls, c->d, bc, cp, phase_field(c), c->ctl);
+            (const R*)c->f[src], (R*)c->f[1 - src], (const R*)c->g[src], (R*)c->g[1 - src], (const R*)c->phi,
+            (const R*)c->mu, c->cls, c->d, bc, cp, phase_field(c), c->ctl);
     }
     static void pf_step_launches(lbm_ctx* c, int src, bool pull, const MeasureParams& mp, hipEvent_t* ev,
                                  int* kinds) {
@@ -435,7 +443,7 @@ struct Run {
         auto start = [&]() { if (ev) (void)hipEventRecord(ev[2 * k], c->stream); };
         auto mark = [&](int kind) { if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = kind; } };
         start();
-        pf_density(c, src, pull, mp.rho_m);
+        pf_density(c, src, pull, mp.rho_m, false);
         mark(0);
         start();
         pf_mu(c);
@@ -596,7 +604,7 @@ struct Run {
     // density, solid fill and mu of the current state (no measurement)
     static void derive(lbm_ctx* c, bool with_mu) {
         if (c->pf) {
-            pf_density(c, c->cur, c->fstar, c->rho_m);
+            pf_density(c, c->cur, c->fstar, c->rho_m, true);
             if (with_mu) pf_mu(c);
             return;
         }
@@ -622,7 +630,7 @@ struct Run {
         const R* S = materialize(c);
         if (c->pf)
             k_pf_velocity<L, R, C><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
-                S, (const R*)c->rho, (const R*)c->phi, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
+                S, (const R*)c->phi, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
         else if (c->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
             k_velocity<L, R, C, true><<<grid(c), dim3(256, 1, 1), 0, c->stream>>>(
                 S, (const R*)c->rho, (const R*)c->mu, c->cls, c->d, collision(c), c->t, (R*)out);
@@ -633,7 +641,7 @@ struct Run {
 
     static void measure_now(lbm_ctx* c, const MeasureParams& mp) {
         if (c->pf) {
-            pf_density(c, c->cur, c->fstar, mp.rho_m);
+            pf_density(c, c->cur, c->fstar, mp.rho_m, true);
             k_cross<L, R><<<cross_grid(c), dim3(256, 1, 1), 0, c->stream>>>((const R*)c->phi, c->cls, c->d, c->ctl, mp);
             k_finalize<L, R><<<1, 64, 0, c->stream>>>((const R*)c->phi, c->ctl, c->d, mp, nullptr, c->last, 0);
             return;

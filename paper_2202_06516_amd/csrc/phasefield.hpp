@@ -20,10 +20,12 @@
 //                   once, when the solids are set), which the Laplacian and the
 //                   gradient reach
 // The measurement reads phi at the isolevel 0, the mean of the two bulk values.
-// A step: k_pf_density (rho and phi of S_t, the liquid centroid sums of phi on
-// measure steps), k_pf_mu, the crossing search on phi, k_pf_collide (f and g),
-// the finalize.  mu and F are formed in double in every precision: mu is the
-// difference of two terms that cancel inside an interface at rest.
+// A step: k_pf_density (phi of S_t, the liquid centroid sums of phi on measure
+// steps; rho = sum f only where the fields are read, since the collision forms
+// the density of its own gather), k_pf_mu, the crossing search on phi,
+// k_pf_collide (f and g), the finalize.  mu and F are formed in double in
+// every precision: mu is the difference of two terms that cancel inside an
+// interface at rest.
 #pragma once
 
 #include "kernels.hpp"
@@ -37,8 +39,9 @@ struct PhaseField {
     double rho0;      // fluid density of the initial state (both phases)
 };
 
-// rho = sum f and phi = sum g of the gathered populations of fluid nodes
-template <class L, typename R, typename C, bool PULL>
+// phi = sum g of the gathered populations of fluid nodes, and with RHO also
+// rho = sum f (the step itself needs no rho field)
+template <class L, typename R, typename C, bool PULL, bool RHO>
 __global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, const R* __restrict__ g,
                                                     R* __restrict__ rho, R* __restrict__ phi,
                                                     const uint8_t* __restrict__ cls, Dims d, WallBC bc,
@@ -52,10 +55,14 @@ __global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, con
         const uint8_t c = at(cls, ix);
         if ((c & CLS_MASK) == CLS_FLUID) {
             R S[L::Q];
-            gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
-            double s = 0.0;
+            if constexpr (RHO) {
+                gather<L, R, C, PULL>(f, d, idx, x, y, z, c, bc, S);
+                double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) s += (double)S[i];
+                for (int i = 0; i < L::Q; ++i) s += (double)S[i];
+                at(rho, ix) = (R)s;
+                if (!(s > 0.0 && s < 1e300)) atomicOr(&ctl->status, 1);  // also catches NaN
+            }
             WallBC hw = bc;
             hw.bouzidi = 0;
             gather<L, R, C, PULL>(g, d, idx, x, y, z, c, hw, S);
@@ -63,9 +70,8 @@ __global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, con
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) p += (double)S[i];
             const R ps = (R)p;
-            at(rho, ix) = (R)s;
             at(phi, ix) = ps;
-            if (!(s > 0.0 && s < 1e300) || !(fabs(p) < 1e300)) atomicOr(&ctl->status, 1);  // also catches NaN
+            if (!(fabs(p) < 1e300)) atomicOr(&ctl->status, 1);
             liquid = (double)ps >= phi_m;
         }
     }
@@ -110,11 +116,11 @@ __global__ void __launch_bounds__(256) k_pf_mu(const R* __restrict__ phi, R* __r
     }
 }
 
-// F = mu grad4(phi), plus rho g from step g_start, in double
+// F = mu grad4(phi), plus r0 g from step g_start (r0: the node's density), in double
 template <class L, typename R, typename C>
-__device__ __forceinline__ void pf_force(const R* __restrict__ rho, const R* __restrict__ phi,
-                                         const R* __restrict__ mu, const Dims& d, uint32_t ix, int x, int y, int z,
-                                         const Collision<C>& cp, long long t, double F[3]) {
+__device__ __forceinline__ void pf_force(double r0, const R* __restrict__ phi, const R* __restrict__ mu,
+                                         const Dims& d, uint32_t ix, int x, int y, int z, const Collision<C>& cp,
+                                         long long t, double F[3]) {
     const Nbr ox = nbr_offsets(x, d.nx, 1), oy = nbr_offsets(y, d.ny, d.px);
     auto p = [&](int o) { return (double)at(phi, ix + (uint32_t)o); };
     const double m0 = (double)at(mu, ix);
@@ -126,7 +132,6 @@ __device__ __forceinline__ void pf_force(const R* __restrict__ rho, const R* __r
         F[2] = m0 * d1c<double>(p(oz.m2), p(oz.m1), p(oz.p1), p(oz.p2));
     }
     if (t >= cp.g_start) {
-        const double r0 = (double)at(rho, ix);
 #pragma unroll
         for (int a = 0; a < 3; ++a) F[a] += r0 * cp.g[a];
     }
@@ -205,14 +210,14 @@ __device__ __forceinline__ void pf_collide_g(const R G[L::Q], const C v[3], C mu
 }
 
 // Collision of both population sets of one fluid node; post-collision values
-// stored at the node (streaming is the next step's pull)
+// stored at the node (streaming is the next step's pull).  The fluid density
+// of the node is the sum of its gathered populations, checked here.
 template <class L, typename R, typename C, bool PULL, bool MRT>
 __global__ void __launch_bounds__(256) k_pf_collide(const R* __restrict__ fin, R* __restrict__ fout,
                                                     const R* __restrict__ gin, R* __restrict__ gout,
-                                                    const R* __restrict__ rho, const R* __restrict__ phi,
-                                                    const R* __restrict__ mu, const uint8_t* __restrict__ cls, Dims d,
-                                                    WallBC bc, Collision<C> cp, PhaseField pf,
-                                                    const DevCtl* __restrict__ ctl) {
+                                                    const R* __restrict__ phi, const R* __restrict__ mu,
+                                                    const uint8_t* __restrict__ cls, Dims d, WallBC bc,
+                                                    Collision<C> cp, PhaseField pf, DevCtl* __restrict__ ctl) {
     int x, y, z;
     tile_node(d, x, y, z);
     if (x >= d.nx || y >= d.ny) return;
@@ -220,10 +225,14 @@ __global__ void __launch_bounds__(256) k_pf_collide(const R* __restrict__ fin, R
     const uint32_t ix = (uint32_t)idx;
     const uint8_t c = at(cls, ix);
     if ((c & CLS_MASK) != CLS_FLUID) return;
-    double F[3];
-    pf_force<L, R, C>(rho, phi, mu, d, ix, x, y, z, cp, ctl->t, F);
     R S[L::Q];
     gather<L, R, C, PULL>(fin, d, idx, x, y, z, c, bc, S);
+    double r0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) r0 += (double)S[i];
+    if (!(r0 > 0.0 && r0 < 1e300)) atomicOr(&ctl->status, 1);  // also catches NaN
+    double F[3];
+    pf_force<L, R, C>(r0, phi, mu, d, ix, x, y, z, cp, ctl->t, F);
     collide_apply<L, R, C, MRT, true>(S, (C)F[0], (C)F[1], (C)F[2], cp, fout, idx, d.N);
     C v[3];
     pf_velocity<L, R, C>(S, F, v);
@@ -257,8 +266,8 @@ __global__ void k_pf_init(const R* __restrict__ src, R* __restrict__ phi, R* __r
 
 // v = u + F / (2 rho) of S_t (fin) with the phase-field force
 template <class L, typename R, typename C>
-__global__ void __launch_bounds__(256) k_pf_velocity(const R* __restrict__ fin, const R* __restrict__ rho,
-                                                     const R* __restrict__ phi, const R* __restrict__ mu,
+__global__ void __launch_bounds__(256) k_pf_velocity(const R* __restrict__ fin, const R* __restrict__ phi,
+                                                     const R* __restrict__ mu,
                                                      const uint8_t* __restrict__ cls, Dims d, Collision<C> cp,
                                                      long long t, R* __restrict__ vel) {
     int x, y, z;
@@ -269,8 +278,6 @@ __global__ void __launch_bounds__(256) k_pf_velocity(const R* __restrict__ fin, 
         vel[idx] = vel[d.N + idx] = vel[2 * d.N + idx] = R(0);
         return;
     }
-    double F[3];
-    pf_force<L, R, C>(rho, phi, mu, d, (uint32_t)idx, x, y, z, cp, t, F);
     double rs = 0.0, j[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < L::Q; ++i) {
         const double fi = (double)fin[(size_t)i * d.N + idx];
@@ -279,6 +286,8 @@ __global__ void __launch_bounds__(256) k_pf_velocity(const R* __restrict__ fin, 
         j[1] += L::E[i][1] * fi;
         j[2] += L::E[i][2] * fi;
     }
+    double F[3];
+    pf_force<L, R, C>(rs, phi, mu, d, (uint32_t)idx, x, y, z, cp, t, F);
     for (int a = 0; a < 3; ++a) vel[(size_t)a * d.N + idx] = (R)(j[a] / rs + F[a] / (2.0 * rs));
 }
 

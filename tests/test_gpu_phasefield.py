@@ -138,3 +138,35 @@ def test_phase_field_errors():
     with pytest.raises(G.LbmError):
         G.Batch([dict(n=(64, 64), solid=dict(center=(32, 20), radius=10, mu_w=0.1), drop=((32, 38), 8))],
                 model=G.LBM_MODEL_PHASE_FIELD)
+
+
+def test_phase_field_3d_interpolated_wall():
+    # the fluid populations take the interpolated wall with its same-phase rule,
+    # the order parameter halfway bounce-back, in 3-D with a sphere and walls
+    wl = W.pf_sessile_3d()
+    gp, o, ga, oa = run_pair(wl, G.LBM_F64, "mrt", "bouzidi", 120, 60, 8)
+    check_fields(gp, o, 1e-12, "3-D FP64 MRT interpolated")
+    angles_close(ga, oa, 1e-6, "3-D interpolated")
+
+
+def test_phase_field_young_force_in_step():
+    # the Young force at every in-step measurement reads phi (footprint band
+    # between -0.8 and 0.8) on a striped disc, against the oracle on the same states
+    wl = dict(W.pf_sessile_2d(), solids=[dict(center=(47.7, 22.3), radius=12.4, stripes=(-0.2, 0.3, 6.0))])
+    gp = gpu_lattice(wl, G.LBM_F64, "mrt", wall_mu=WALL_PHI)
+    o = oracle_lattice(wl, "mrt", wall_mu=WALL_PHI)
+    gp.set_measure(0, 2)
+    gp.set_young(0.0133, 70.0, 110.0)
+    ga = gp.step(400, measure_every=100, cap=8)
+    gy = gp.young_series()
+    assert len(ga) == len(gy) == 4
+    for k in range(4):
+        oa, oy = o.young_force(0.0133, 70.0, 110.0)
+        assert gy[k].step == oy.step == 100 * k and gy[k].status == oy.status
+        for s in range(2):
+            assert list(gy[k].count[s]) == list(oy.count[s]), (k, s)
+            for name in ("phi_d", "theta_eq_deg", "force"):
+                g, r = getattr(gy[k], name)[s], getattr(oy, name)[s]
+                assert (np.isnan(g) and np.isnan(r)) or abs(g - r) <= 1e-9, (k, s, name, g, r)
+        o.step(100)
+    assert any(sum(gy[k].count[0]) + sum(gy[k].count[1]) > 0 for k in range(1, 4))
