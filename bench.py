@@ -53,6 +53,9 @@ def parse():
                          "blow this drop up")
     ap.add_argument("--step-kernel", default="auto", choices=["auto", "split"],
                     help="auto: the one-pass step where the lattice allows it; split: density pass + collision")
+    ap.add_argument("--wall", default="halfway", choices=["halfway", "interpolated"],
+                    help="curved-wall scheme of the sessile3d workload (interpolated: linear interpolated "
+                         "bounce-back with the mass correction)")
     ap.add_argument("--model", default="chemical-potential", choices=["chemical-potential", "phase-field"],
                     help="force model of the sessile3d workload (the phase-field model runs the split step, both "
                          "population sets: 304 algorithmic bytes per fluid-node update in FP32)")
@@ -126,7 +129,8 @@ def main():
         rates = (dict(s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.4, s_m=1.98) if args.mrt_rates == "dhumieres"
                  else dict(s_e=1.64, s_eps=1.54, s_q=1.9, s_pi=1.54, s_m=1.9))
     lat = G.Lattice(G.LBM_D3Q19, n=wl["n"], precision=prec, axis_bc=(1, 1, 1), stream=stream.cuda_stream,
-                    collision=G.LBM_BGK if args.collision == "bgk" else G.LBM_MRT, bc_mode=G.LBM_BC_HALFWAY,
+                    collision=G.LBM_BGK if args.collision == "bgk" else G.LBM_MRT,
+                    bc_mode=G.LBM_BC_HALFWAY if args.wall == "halfway" else G.LBM_BC_BOUZIDI_MC,
                     tau=1.0, Tr=wl["Tr"], k=0.28, kappa=0.01,
                     step_kernel=G.LBM_STEP_AUTO if args.step_kernel == "auto" else G.LBM_STEP_SPLIT, **rates,
                     **extra)
@@ -194,12 +198,14 @@ def main():
         "config": {"workload": f"sessile drop on a sphere, D3Q19 {args.n}^3 walled box, sphere r={60 * args.n // 256}, "
                                f"drop r0={40 * args.n // 256}, mu_w=0.04, Tr={wl['Tr']}, {args.collision.upper()} tau=1, "
                                f"angle every {wl['every']} steps over {wl['n_sectors']} sectors"
-                               + (", phase-field model (order parameter, wall phi_w=0.04)" if pf else ""),
+                               + (", phase-field model (order parameter, wall phi_w=0.04)" if pf else "")
+                               + (", interpolated wall" if args.wall == "interpolated" else ""),
                    "lattice": [args.n] * 3, "fluid_nodes": n_fluid, "precision": args.precision,
                    "collision": args.collision, **({"mrt_rates": rates} if rates else {})},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision, args.model)),
+                     "traffic": (COUNTED_TRAFFIC.get((kern, args.n, args.precision, args.collision, args.model))
+                                 if args.wall == "halfway" else None),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
         "step_efficiency": {"algorithmic_bytes_per_update": 2 * Q * 4 * sets,
                             "achieved_GBs": round(step_alg_bytes / (ms_step * 1e-3) / 1e9, 1),

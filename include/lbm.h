@@ -129,9 +129,9 @@ typedef struct {
                              ignores Tr, pr_*, k, kappa (the batched solver takes either of the first two for
                              all its cases); the phase-field model ignores Tr, pr_*, k, kappa, rho_l, rho_g */
     double sc_G;          /* pseudopotential interaction strength G (default -6) */
-    int step_kernel;      /* LBM_STEP_AUTO (default): D3Q19 lattices with halfway bounce-back walls, nx a
-                             multiple of 64 (at most 1024), ny a multiple of 4 and nz even take one pass over
-                             the populations per step (the
+    int step_kernel;      /* LBM_STEP_AUTO (default): D3Q19 lattices (either wall scheme; not the phase-field
+                             model) with nx a multiple of 64 (at most 1024), ny a multiple of 4 and nz even
+                             take one pass over the populations per step (the
                              collision also sums the next step's density); LBM_STEP_SPLIT: a density pass,
                              then the collision.  Both compute the same step; the density sums differ in
                              order, so the fields agree to rounding. */

@@ -97,6 +97,8 @@ struct lbm_ctx {
     int* bidx = nullptr;
     long long *l1_node = nullptr, *l2_node = nullptr, *b_node = nullptr;
     uint32_t *l1_mask = nullptr, *l2_mask = nullptr, *b_mask = nullptr;
+    int* curved = nullptr;  // boundary-list indices of nodes with a cut link of q other than 1/2
+    int n_curved = 0;       // their number when the one-pass step runs the interpolated wall, else 0
     void *l1_inv = nullptr, *l2_inv = nullptr, *b_q = nullptr;
     int n_l1 = 0, n_l2 = 0, n_b = 0;
     long long n_fluid = 0;
@@ -266,12 +268,15 @@ struct Run {
     // the crossing search walks the tiles in a grid-stride loop
     static dim3 cross_grid(const lbm_ctx* c) { return dim3(c->d.nblocks < 2048u ? c->d.nblocks : 2048u, 1, 1); }
 
+    // The wall condition of a gather of the stored state.  On the one-pass path
+    // the interpolated wall is already in the slots the pull reads
+    // (k_interp_wall after each step), so its gathers take halfway bounce-back.
     static WallBC wall(const lbm_ctx* c) {
         WallBC bc;
         bc.nbmask = c->nbmask;
         bc.bidx = c->bidx;
         bc.q = c->b_q;
-        bc.bouzidi = c->cfg.bc_mode == LBM_BC_BOUZIDI_MC;
+        bc.bouzidi = c->cfg.bc_mode == LBM_BC_BOUZIDI_MC && !c->fused;
         return bc;
     }
     static void density(lbm_ctx* c, const R* f, bool pull, double rho_m) {
@@ -553,6 +558,13 @@ struct Run {
                        else launch_step<false, false, false>(c, fin, fout, rho, rnext, bc, cp); }
             }
             mark(7);
+            if (c->n_curved) {
+                // the interpolated wall into the slots the next pull reads
+                start();
+                k_interp_wall<L, R, C><<<(c->n_curved + 255) / 256, blk, 0, c->stream>>>(
+                    c->curved, c->n_curved, c->b_node, c->b_mask, fout, c->d, bc);
+                mark(10);
+            }
             start();
             k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1, ys, c->yseries);
             mark(6);
@@ -899,7 +911,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     tile_dims(c->d, c->dim);
     if (cfg->step_kernel != LBM_STEP_AUTO && cfg->step_kernel != LBM_STEP_SPLIT) return bad("step_kernel");
     {
-        // the one-pass step: D3Q19 with halfway bounce-back walls, whole rows of
+        // the one-pass step: D3Q19 (either wall scheme), whole rows of
         // 64..1024 nodes per workgroup, 4 rows, zc planes (LBM_FUSED_ZC overrides 8, halved
         // until it divides nz: at 256^3 the walk over 2, 4, 8 planes took 0.622, 0.606,
         // 0.607 ms and the ghost sums 0.043, 0.031, 0.025 ms)
@@ -910,7 +922,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         // (its node indices and the byte offsets of its population accesses, up to
         // five arrays from one base, are 32-bit)
         const size_t elem = cfg->precision == LBM_F64 ? 8 : 4;
-        c->fused = cfg->step_kernel == LBM_STEP_AUTO && !c->pf && c->dim == 3 && cfg->bc_mode == LBM_BC_HALFWAY &&
+        c->fused = cfg->step_kernel == LBM_STEP_AUTO && !c->pf && c->dim == 3 &&
                    c->d.nx % 64 == 0 && c->d.nx <= 1024 && c->d.ny % kFusedTY == 0 && zc >= 2 && c->d.nz % zc == 0 &&
                    5ull * (unsigned long long)N * elem < (1ull << 32);
     }
@@ -990,7 +1002,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
     void* ps[] = {c->f[0], c->f[1], c->rhob[0], c->rhob[1], c->gy, c->gz, c->gyz, c->force, c->sink, c->mu, c->cls, c->nbmask, c->bidx, c->l1_node, c->l2_node, c->b_node,
                   c->l1_mask, c->l2_mask, c->b_mask, c->l1_inv, c->l2_inv, c->b_q, c->ctl, c->last, c->series,
                   c->mass_part, c->mass_out, c->young_counts, c->ylast, c->yseries, c->ystep_counts,
-                  c->g[0], c->g[1], c->phi};
+                  c->g[0], c->g[1], c->phi, c->curved};
     for (void* p : ps) dfree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1051,6 +1063,14 @@ lbm_status lbm_set_solid(lbm_ctx* c, const lbm_solid* prims, int n, const double
     c->n_l1 = (int)g.l1_node.size();
     c->n_l2 = (int)g.l2_node.size();
     c->n_b = (int)g.b_node.size();
+    {
+        std::vector<int> cv;
+        if (c->fused && c->cfg.bc_mode == LBM_BC_BOUZIDI_MC)
+            for (size_t k = 0; k < g.b_node.size(); ++k)
+                if (g.cls[g.b_node[k]] & CLS_CURVED_) cv.push_back((int)k);
+        if ((s = upload(c, &c->curved, cv))) return s;
+        c->n_curved = (int)cv.size();
+    }
     c->n_fluid = g.n_fluid;
     // static wall chemical potential on the two solid layers; zero elsewhere
     {
@@ -1518,8 +1538,9 @@ lbm_status lbm_get_info(lbm_ctx* c, lbm_info* info) {
 }
 
 lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, double* ms, int cap, int* n_kinds) {
-    static const char* kNames[10] = {"k_density", "k_fill_layer1", "k_fill_layer2", "k_mu", "k_collide",
-                                     "k_cross",   "k_finalize",    "k_step",        "k_ghost", "k_force"};
+    static const char* kNames[11] = {"k_density", "k_fill_layer1", "k_fill_layer2", "k_mu",    "k_collide",
+                                     "k_cross",   "k_finalize",    "k_step",        "k_ghost", "k_force",
+                                     "k_interp_wall"};
     if (!c || !names || !ms || !n_kinds) return LBM_E_ARG;
     if (!c->have_state) return fail(c, LBM_E_STATE, "profile: no state");
     if (nsteps < 1) return fail(c, LBM_E_ARG, "profile: nsteps >= 1");
@@ -1529,12 +1550,12 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
     lbm_status s = ctl_reset(c, 0, 0, 0);
     if (s) return s;
     if (c->fused && !c->rho_valid) dispatch<OpDerive>(c, true);
-    hipEvent_t ev[16];
+    hipEvent_t ev[24];
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
-    double tot[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double tot[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int cnt[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t t = 0; t < nsteps; ++t) {
-        int kinds[10];
+        int kinds[12];
         if (c->fused) {
             dispatch<OpFusedStep>(c, c->cur, c->fstar, c->rcur, &mp, ev, kinds);
             c->rcur ^= 1;
@@ -1546,7 +1567,7 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
         c->fstar = true;
         ++c->t;
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (int k = 0; k < 8 && kinds[k] >= 0; ++k) {
+        for (int k = 0; k < 11 && kinds[k] >= 0; ++k) {
             float e = 0;
             HIPCHK(c, hipEventElapsedTime(&e, ev[2 * k], ev[2 * k + 1]));
             tot[kinds[k]] += e;
@@ -1555,7 +1576,7 @@ lbm_status lbm_profile_step(lbm_ctx* c, int64_t nsteps, const char** names, doub
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     int n = 0;
-    for (int k = 0; k < 10 && n < cap; ++k) {
+    for (int k = 0; k < 11 && n < cap; ++k) {
         if (!cnt[k]) continue;
         names[n] = kNames[k];
         ms[n] = tot[k] / cnt[k];

@@ -126,6 +126,83 @@ __device__ __forceinline__ void gather_issue(const R* __restrict__ f, const Dims
     }
 }
 
+// The interpolated wall (Sec. III A) of one boundary fluid node from the
+// halfway values: for every cut link (bit j of bm: x + e_j is solid) S_i,
+// i = opp(j), holds f*_j(x); it becomes the linear interpolation in the link's
+// wall fraction q -- with the node behind x when q < 1/2, only if that
+// partner's population lies within a factor of two of x's own (the same
+// phase), else from f*_i(x) -- and the difference goes to S_0, as the split
+// path's gather forms them.  The mass correction leaves the node's density
+// that of halfway bounce-back.
+template <class L, typename R, typename C>
+__device__ __forceinline__ void interp_wall(const R* __restrict__ f, const Dims& d, uint32_t ix, int x, int y, int z,
+                                            uint32_t bm, const WallBC& bc, R S[L::Q]) {
+    const int ox[3] = {x >= 1 ? -1 : d.nx - 1, 0, x + 1 < d.nx ? 1 : 1 - d.nx};
+    const int oy[3] = {(y >= 1 ? -1 : d.ny - 1) * d.px, 0, (y + 1 < d.ny ? 1 : 1 - d.ny) * d.px};
+    const int sz = d.px * d.ny;
+    const int oz[3] = {(z >= 1 ? -1 : d.nz - 1) * sz, 0, (z + 1 < d.nz ? 1 : 1 - d.nz) * sz};
+    const int k = bc.bidx[ix];
+    const R* q_of = (const R*)bc.q + (size_t)k * L::Q;
+    C dm = C(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int j = L::OPP[i];
+        if (!(bm & (1u << j))) continue;
+        const R outj = S[i];
+        const C q = (C)q_of[j];
+        C v = (C)outj;
+        if (q < C(0.5)) {
+            if (!(bm & (1u << i))) {  // x + e_i is the fluid node behind x
+                const uint32_t b = ix + (uint32_t)(ox[1 + L::E[i][0]] + oy[1 + L::E[i][1]] + oz[1 + L::E[i][2]]);
+                const R fb = at(f + (size_t)j * d.N, b);
+                if (fb <= R(2) * outj && outj <= R(2) * fb) v = C(2) * q * (C)outj + (C(1) - C(2) * q) * (C)fb;
+            }
+        } else {
+            v = (C)outj / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * (C)at(f + (size_t)i * d.N, ix);
+        }
+        S[i] = (R)v;
+        dm += (C)outj - v;
+    }
+    S[0] = (R)((C)S[0] + dm);
+}
+
+// The one-pass step with the interpolated wall: after k_step has stored f*_t,
+// each node whose cut links include one of wall fraction other than 1/2 (the
+// box walls' links are halfway exactly) takes the values its next pull will
+// read through those links from interp_wall, written into the slots that pull
+// reads: f*_j(x) for a cut link j (which only x reads: x + e_j is solid) and
+// f*_0(x).  Every value a node reads here is its own or that of the fluid node
+// behind it along a cut link, whose slots in that direction are not cut links
+// (its neighbour there is x), so no node reads a slot another one writes.
+// The density of step t + 1 that k_step summed is unchanged by it (the mass
+// correction).  Every later gather of this state takes halfway bounce-back.
+template <class L, typename R, typename C>
+__global__ void __launch_bounds__(256) k_interp_wall(const int* __restrict__ list, int n,
+                                                     const long long* __restrict__ b_node,
+                                                     const uint32_t* __restrict__ b_mask, R* __restrict__ f, Dims d,
+                                                     WallBC bc) {
+    const int t = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (t >= n) return;
+    const int k = list[t];
+    const long long node = b_node[k];
+    const uint32_t ix = (uint32_t)node, bm = b_mask[k];
+    const int x = (int)(node % d.nx), y = (int)((node / d.nx) % d.ny), z = (int)(node / ((long long)d.nx * d.ny));
+    R S[L::Q];
+    S[0] = at(f, ix);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int j = L::OPP[i];
+        S[i] = (bm & (1u << j)) ? at(f + (size_t)j * d.N, ix) : R(0);
+    }
+    interp_wall<L, R, C>(f, d, ix, x, y, z, bm, bc, S);
+    at(f, ix) = S[0];
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int j = L::OPP[i];
+        if (bm & (1u << j)) at(f + (size_t)j * d.N, ix) = S[i];
+    }
+}
+
 template <typename R, typename C, bool PULL, bool MRT, bool SC, int TY, int NX>
 __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __restrict__ fout,
                                              const R* __restrict__ rho, const R* __restrict__ mu,
@@ -164,9 +241,9 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
     // on a solid node reads and writes that node's own population slots,
     // which nothing else reads (the wall condition takes the populations of
     // the fluid node itself, and reads of the state give zero on solids), and
-    // the walk's overrun past its last node reloads the last one.  (Only
-    // halfway bounce-back walls take this kernel: the interpolated wall's
-    // loads depend on one another.)
+    // the walk's overrun past its last node reloads the last one.  (The
+    // interpolated wall's loads depend on one another: k_interp_wall applies
+    // it after the launch to the slots the next pull reads.)
     // The lattice sizes and the thread's x pass through an empty asm per
     // node, so that what is derived from them (population and stencil
     // offsets) is recomputed instead of held across the walk; held, it spilled

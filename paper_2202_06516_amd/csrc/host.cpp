@@ -315,6 +315,7 @@ bool build_geometry(Geometry& g, int dim, const int n[3], const int wall[3], con
                         if (root < qq) qq = root;
                     }
                     if (qq > 1.0) qq = 0.5;
+                    if (qq != 0.5) g.cls[i] |= CLS_CURVED_;
                 }
                 g.b_q.push_back(qq);
             }

@@ -8,8 +8,10 @@
 
 namespace lbm {
 
-// node class codes (low two bits) and the boundary-fluid flag
-constexpr uint8_t CLS_FLUID_ = 0, CLS_BOUNDARY_ = 4;
+// node class codes (low two bits), the boundary-fluid flag, and the flag of a
+// boundary fluid node with a cut link whose wall fraction is not 1/2 (where
+// the interpolated wall differs from halfway bounce-back)
+constexpr uint8_t CLS_FLUID_ = 0, CLS_BOUNDARY_ = 4, CLS_CURVED_ = 8;
 
 // Peng-Robinson fluid (Eq. 10-11) at a reduced temperature.
 struct PRState {

@@ -38,7 +38,8 @@
 
 namespace lbm {
 
-enum : uint8_t { CLS_FLUID = 0, CLS_L1 = 1, CLS_L2 = 2, CLS_DEEP = 3, CLS_MASK = 3, CLS_BOUNDARY = 4 };
+// bit 3: a boundary fluid node with a cut link of wall fraction other than 1/2
+enum : uint8_t { CLS_FLUID = 0, CLS_L1 = 1, CLS_L2 = 2, CLS_DEEP = 3, CLS_MASK = 3, CLS_BOUNDARY = 4, CLS_CURVED = 8 };
 
 struct Dims {
     int nx, ny, nz;

@@ -4,8 +4,8 @@ FP64 oracle and against the split step, element by element.
 k_step collides step t and sums the density of step t + 1 in the same pass;
 partial sums that cross its tiles go through ghost arrays.  The cases cover
 one, two and three waves per row, every z-chunk depth it picks (8, 4, 2),
-walls and periodic axes (ghost rows and planes that wrap), halfway walls (the
-interpolated wall stays on the split step), MRT and BGK, gravity switched on mid-run, the pseudopotential model, FP64 /
+walls and periodic axes (ghost rows and planes that wrap), halfway and
+interpolated walls, MRT and BGK, gravity switched on mid-run, the pseudopotential model, FP64 /
 FP32 / FP32 with FP64 arithmetic, in-step measurement, reads between steps, and
 graph-captured against eager stepping.
 """
@@ -56,7 +56,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("n,wall", CASES)
-@pytest.mark.parametrize("collision,bc", [("bgk", "halfway"), ("mrt", "halfway")])
+@pytest.mark.parametrize("collision,bc", [("bgk", "halfway"), ("mrt", "halfway"), ("mrt", "bouzidi")])
 def test_one_pass_matches_oracle_f64(n, wall, collision, bc):
     wl = case(n, wall)
     kw = dict(s_q=1.0, s_m=1.0, s_pi=1.0, **SMALL)
@@ -172,5 +172,22 @@ def test_split_is_used_where_the_one_pass_step_cannot_tile():
     for n in ((70, 24, 32), (64, 22, 32), (64, 24, 33)):
         gp = gpu_lattice(case(n, (1, 1, 1)), G.LBM_F64, "bgk", **SMALL)
         assert not is_fused(gp), n
-    # the interpolated wall keeps the split step (its loads depend on one another)
-    assert not is_fused(gpu_lattice(case((64, 24, 32), (1, 1, 1)), G.LBM_F64, "bgk", "bouzidi", **SMALL))
+    # the interpolated wall takes the one-pass step too; the phase-field model does not
+    assert is_fused(gpu_lattice(case((64, 24, 32), (1, 1, 1)), G.LBM_F64, "bgk", "bouzidi", **SMALL))
+
+
+@pytest.mark.parametrize("precision,tol", [(G.LBM_F32, 1e-6), (G.LBM_F64, 1e-12)])
+def test_one_pass_interpolated_wall_matches_split_path(precision, tol):
+    # a sphere whose cut links span q in (0, 1) and a drop over it, 60 steps on
+    # both paths of the same build: the one-pass step's interpolated wall
+    # equals the split path's gather (the density sums differ in order only)
+    wl = case((128, 28, 40), (1, 1, 1), r=9.3, drop=7.0)
+    a = gpu_lattice(wl, precision, "bgk", "bouzidi", **SMALL)
+    b = gpu_lattice(wl, precision, "bgk", "bouzidi", step_kernel=G.LBM_STEP_SPLIT, **SMALL)
+    assert is_fused(a) and not is_fused(b)
+    a.step(59)
+    b.step(59)
+    fl = a.read(G.FIELD_CLASS) <= 2
+    assert rel_err(a.rho, b.rho, fl) <= tol
+    assert rel_err(a.f, b.f) <= tol
+    assert abs(a.mass() / b.mass() - 1.0) <= tol
