@@ -19,7 +19,11 @@ statistics the paper reports:
 - ``sc-wettability``: the same measurement on the pseudopotential model
   (Sec. V), theta against the wall density on single lattices;
 - ``pf-wettability``: on the phase-field model (Sec. V), theta against the
-  wall order parameter on single lattices.
+  wall order parameter on single lattices;
+- ``sessile3d``: the 256^3 sessile drop of the benchmark workload (D3Q19 FP32,
+  one-pass step) for several wall chemical potentials, its 32-sector measured
+  angle against the apparent angle of a sphere fitted to the drop (the 3-D
+  counterpart of the spherical-cap check of Sec. IV A), with either wall.
 
 Each case also gets the spherical-cap angle of Sec. IV A from its final
 density (base length L between the two measured contact points, cap height
@@ -238,9 +242,42 @@ def pf_wettability(phi_w=(-0.6, -0.4, -0.2, 0.0, 0.2, 0.4, 0.6), n=256, R=48.0, 
     return out
 
 
+def sessile3d(mu_w=(-0.01, 0.04, 0.1), n=256, steps=20000, every=1000, wall="halfway", log=print):
+    """The benchmark's sessile layout per wall chemical potential: the mean of
+    the 32 sector angles at the end, its spread over the sectors, the drift over
+    the last interval, and the apparent angle of the final drop."""
+    from .striped import apparent_angle
+    res = []
+    t0 = time.perf_counter()
+    for m in mu_w:
+        wl = WL.sessile_3d(mu_w=m, n=n)
+        lat = G.Lattice(G.LBM_D3Q19, n=wl["n"], precision=G.LBM_F32, axis_bc=(1, 1, 1), collision=G.LBM_BGK,
+                        bc_mode=G.LBM_BC_BOUZIDI_MC if wall == "interpolated" else G.LBM_BC_HALFWAY, tau=1.0,
+                        Tr=wl["Tr"], k=0.28, kappa=0.01)
+        lat.set_solids(wl["solids"])
+        lat.init_drops(wl["drops"], W=10.0)
+        lat.set_measure(0, wl["n_sectors"])
+        info = lat.info()
+        ser = lat.step(steps, measure_every=every, cap=steps // every + 1)
+        a = ser[-1]
+        sec = np.array([a.sector_deg[k] for k in range(a.n_sectors)], dtype=np.float64)
+        sol = wl["solids"][0]
+        app, D, Rd = apparent_angle(lat.rho, lat.read(G.FIELD_CLASS), info["rho_m"], sol["center"], sol["radius"])
+        lat.close()
+        r = dict(mu_w=m, theta=float(a.mean_deg) if a.status == 0 else math.nan, n_valid=int(a.n_valid),
+                 sector_spread=float(np.nanmax(sec) - np.nanmin(sec)) if a.n_valid else math.nan,
+                 drift=float(abs(ser[-1].mean_deg - ser[-2].mean_deg)) if len(ser) > 1 else math.nan,
+                 apparent=float(app), drop_radius=float(Rd) if Rd is not None else math.nan)
+        res.append(r)
+        log(f"sessile3d {wall}: mu_w {m}: theta {r['theta']:.2f} (spread {r['sector_spread']:.2f}), "
+            f"apparent {r['apparent']:.2f}, {time.perf_counter() - t0:.1f} s")
+    return dict(kind="sessile3d", wall=wall, n=n, steps=steps, cases=res)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="wettability / drop-size / curvature sweeps on the batched solver")
-    ap.add_argument("kind", choices=("wettability", "size", "curvature", "gravity", "sc-wettability", "pf-wettability"))
+    ap.add_argument("kind", choices=("wettability", "size", "curvature", "gravity", "sc-wettability", "pf-wettability",
+                                     "sessile3d"))
     ap.add_argument("--Tr", type=float, default=0.6)
     ap.add_argument("--f64", action="store_true", help="FP64 storage and arithmetic (default FP32 storage)")
     ap.add_argument("--scale", type=float, default=1.0, help="every length times this (1: the 700 x 400 lattice)")
@@ -258,6 +295,12 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
+    if a.kind == "sessile3d":
+        rep = sessile3d(wall=a.wall, log=log, **({"steps": a.max_steps} if a.max_steps != 200000 else {}))
+        print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
+        for r in rep["cases"]:
+            print(json.dumps(r), flush=True)
+        return 0
     if a.kind in ("sc-wettability", "pf-wettability"):
         rep = (sc_wettability if a.kind == "sc-wettability" else pf_wettability)(log=log)
         print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
