@@ -186,7 +186,8 @@ __global__ void __launch_bounds__(256) k_interp_wall(const int* __restrict__ lis
     const int k = list[t];
     const long long node = b_node[k];
     const uint32_t ix = (uint32_t)node, bm = b_mask[k];
-    const int x = (int)(node % d.nx), y = (int)((node / d.nx) % d.ny), z = (int)(node / ((long long)d.nx * d.ny));
+    const uint32_t row = ix / (uint32_t)d.px;
+    const int x = (int)(ix - row * (uint32_t)d.px), y = (int)(row % (uint32_t)d.ny), z = (int)(row / (uint32_t)d.ny);
     R S[L::Q];
     S[0] = at(f, ix);
 #pragma unroll

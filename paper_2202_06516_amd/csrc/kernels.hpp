@@ -422,8 +422,10 @@ __global__ void __launch_bounds__(256) k_materialize(const R* __restrict__ f, R*
 // ---------------------------------------------------------------------------
 template <class L, typename R, typename C>
 __device__ __forceinline__ void fill_entry(long long idx, uint32_t m, R inv_den, R* __restrict__ rho, const Dims& d) {
-    const long long loc = idx - d.off;
-    const int x = (int)(loc % d.px), y = (int)((loc / d.px) % d.ny), z = (int)(loc / ((long long)d.px * d.ny));
+    // coordinates by 32-bit divisions (a lattice holds fewer than 2^32 nodes;
+    // the 64-bit ones cost more than the rest of the entry)
+    const uint32_t loc = (uint32_t)(idx - d.off), row = loc / (uint32_t)d.px;
+    const int x = (int)(loc - row * (uint32_t)d.px), y = (int)(row % (uint32_t)d.ny), z = (int)(row / (uint32_t)d.ny);
     C num = C(0);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
