@@ -290,8 +290,10 @@ def evaluate(net, cases, horizon, every=100, tol=0.5, cut=0.05, smooth=2, stream
 
 
 def run(train_cases, val_cases, test_cases, gen_steps, horizon, epochs, levels=4, base=32, batch=8, lr=1e-3,
-        seed=0, log=print, ckpt=None, cut=0.05, smooth=2):
-    """The whole pipeline on one GPU; returns a JSON-able report."""
+        seed=0, log=print, ckpt=None, cut=0.05, smooth=2, resume=None):
+    """The whole pipeline on one GPU; returns a JSON-able report.  With resume,
+    training continues from that checkpoint (weights, Adam moments and step) on
+    the new cases, so that a larger training set can be seen chunk by chunk."""
     torch = _torch()
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
@@ -307,7 +309,10 @@ def run(train_cases, val_cases, test_cases, gen_steps, horizon, epochs, levels=4
         H, W = train_cases[0]["n"][1], train_cases[0]["n"][0]
         net = G.Unet(H=H, W=W, batch=batch, in_channels=IN_CHANNELS, base_channels=base, levels=levels, lr=lr,
                      stream=st.cuda_stream)
-        init_params(net, seed)
+        if resume:
+            net.load(resume)
+        else:
+            init_params(net, seed)
         t0 = time.perf_counter()
         hist = train(net, x, t, epochs, lr=lr, seed=seed + 1, xv=xv, tv=tv, log=log)
         rep["training"] = dict(epochs=epochs, seconds=round(time.perf_counter() - t0, 2), params=net.n_params,
@@ -337,6 +342,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--ckpt", default=None, help="write the trained network here (or read it with --eval-only)")
     ap.add_argument("--eval-only", action="store_true", help="load --ckpt and only run the cold/warm evaluation")
+    ap.add_argument("--resume", default=None, help="continue training from this checkpoint on the new cases")
+    ap.add_argument("--train-seed", type=int, default=WL.WARM_SEEDS["train"],
+                    help="seed of the training cases (a chunk of a larger set: a seed below the validation one)")
     ap.add_argument("--cut", type=float, default=0.05)
     ap.add_argument("--smooth", type=int, default=2, help="radius of the fluid-window mean applied to predictions")
     a = ap.parse_args(argv)
@@ -356,10 +364,12 @@ def main(argv=None):
             summary, res, _ = evaluate(net, te, a.horizon, cut=a.cut, smooth=a.smooth, stream=st.cuda_stream, log=log)
         rep = dict(warm_start=summary, cases=res)
     else:
-        tr = WL.warmstart_cases(a.train, WL.WARM_SEEDS["train"], **kw)
+        if not a.train_seed < WL.WARM_SEEDS["val"]:
+            ap.error("--train-seed must stay below the validation and test seeds")
+        tr = WL.warmstart_cases(a.train, a.train_seed, **kw)
         va = WL.warmstart_cases(a.val, WL.WARM_SEEDS["val"], **kw) if a.val else []
         rep = run(tr, va, te, a.gen_steps, a.horizon, a.epochs, levels=a.levels, base=a.base, lr=a.lr, log=log,
-                  ckpt=a.ckpt, cut=a.cut, smooth=a.smooth)
+                  ckpt=a.ckpt, cut=a.cut, smooth=a.smooth, resume=a.resume)
     line = json.dumps({k: v for k, v in rep.items() if k != "cases"})
     print(line, flush=True)
     if a.out:
