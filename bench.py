@@ -35,8 +35,8 @@ COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk", "chemical-potential"): 16286538
                        24626936 * 128 + 2257 * 64 + 36426673 * 64 + 439204 * 32}
 # the same for kb_collide of the batched solver on the seeded table, from FETCH_SIZE x 2 and WRITE_SIZE in KiB
 # (the scaling of a plain copy; profiles/kb_collide_batch_d2q9_512cases.md), keyed by (number of cases,
-# precision)
-BATCH_COUNTED_TRAFFIC = {(512, "f32"): (1392231 * 2 + 1386829) * 1024}
+# precision, force model)
+BATCH_COUNTED_TRAFFIC = {(512, "f32", "chemical-potential"): (1392231 * 2 + 1386829) * 1024}
 
 
 def parse():
@@ -57,8 +57,9 @@ def parse():
                     help="curved-wall scheme of the sessile3d workload (interpolated: linear interpolated "
                          "bounce-back with the mass correction)")
     ap.add_argument("--model", default="chemical-potential", choices=["chemical-potential", "phase-field"],
-                    help="force model of the sessile3d workload (the phase-field model runs the split step, both "
-                         "population sets: 304 algorithmic bytes per fluid-node update in FP32)")
+                    help="force model of the sessile3d and batch workloads (the phase-field model runs the split "
+                         "step, both population sets: 304 algorithmic bytes per fluid-node update in FP32 D3Q19, "
+                         "144 in D2Q9)")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps at full size (0 = skip)")
     ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps at full size on one thread")
@@ -229,11 +230,16 @@ def batch_bench(args):
     from paper_2202_06516_amd import workloads as W
 
     cases, acc = W.batch_cases(args.cases, seed=0)
+    pf = args.model == "phase-field"
+    extra = {}
+    if pf:
+        cases = W.pf_batch_cases(cases, seed=1)
+        extra = dict(W.PF_PARAMS, model=G.LBM_MODEL_PHASE_FIELD)
     prec = {"f32": G.LBM_F32, "f32mixed": G.LBM_F32_MIXED, "f64": G.LBM_F64}[args.precision]
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
     b = G.Batch(cases, precision=prec, autotune=True, stream=stream.cuda_stream, tau=1.0, Tr=0.8, k=0.28,
-                kappa=0.01, collision=G.LBM_MRT)
+                kappa=0.01, collision=G.LBM_MRT, **extra)
     t_setup = time.perf_counter() - t0
     inf = b.info()
     b.step(args.warmup, measure_every=100)
@@ -248,40 +254,48 @@ def batch_bench(args):
     # dominant kernel: kb_collide, timed with HIP events on the batch's stream over eager steps
     prof = b.profile(args.profile_steps)
     Q, P = 9, (8 if args.precision == "f64" else 4)
-    coll_bytes = inf["fluid_nodes"] * 2 * Q * P   # algorithmic: each population read once and written once
-    coll_ms = prof["kb_collide"]
+    # algorithmic: each population read once and written once (both sets of the phase-field model)
+    coll_bytes = inf["fluid_nodes"] * 2 * Q * P * (2 if pf else 1)
+    kern = "kb_pf_collide" if pf else "kb_collide"
+    coll_ms = prof[kern]
     achieved = coll_bytes / (coll_ms * 1e-3) / 1e9
+    what = ("R_s U[16,128], r0 U[12,96], mu_w U[-0.01,0.1], Tr=0.8, MRT tau=1, angle every 100" if not pf else
+            "R_s U[16,128], r0 U[12,96], phase-field model, wall order parameter U[-0.4,0.4], MRT tau=1, "
+            "angle every 100")
     out = {
         "metric": "aggregate MLUPS of the batched D2Q9 solver (fluid-node updates/s)",
         "value": round(inf["fluid_nodes"] * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4),
         "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"{args.cases} seeded D2Q9 drop-on-cylinder cases (PCG64 seed 0), sides U[64,512], "
-                               "R_s U[16,128], r0 U[12,96], mu_w U[-0.01,0.1], Tr=0.8, MRT tau=1, angle every 100",
+                               + what,
                    "total_nodes": inf["total_nodes"], "fluid_nodes": inf["fluid_nodes"], "accept_rate": acc,
                    "tile_w": inf["tile_w"], "blocks_per_cu": inf["blocks_per_cu"],
                    "tuned_ms_per_step": inf["tune_ms_per_step"], "setup_s": round(t_setup, 2)},
         "cases_with_contact_angle": valid,
-        "roofline": {"bound": "hbm", "kernel": "kb_collide", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": BATCH_COUNTED_TRAFFIC.get((args.cases, args.precision)),
+                     "traffic": BATCH_COUNTED_TRAFFIC.get((args.cases, args.precision, args.model)),
                      "bytes_per_launch": coll_bytes, "mean_ms": round(coll_ms, 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
     }
     if not args.no_cpu and args.cpu_steps > 0:
-        out["cpu_baseline"] = batch_cpu_baseline(cases[:16], 100)
+        out["cpu_baseline"] = batch_cpu_baseline(cases[:16], 100, pf)
     print(json.dumps(out), flush=True)
 
 
-def batch_cpu_baseline(cases, steps):
+def batch_cpu_baseline(cases, steps, pf=False):
     """The FP64 oracle on the first cases of the same seeded table, one lattice after another."""
     import oracle as O
     O.build(force=False)
+    from paper_2202_06516_amd import workloads as W
     from tests.pairs import oracle_lattice
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     fluid, dt = 0, 0.0
     for cs in cases:
         wl = dict(dim=2, n=cs["n"], wall=(0, 0), solids=[cs["solid"]], drops=[cs["drop"]])
+        if pf:
+            wl.update(model=2, W=W.PF_W)
         o = oracle_lattice(wl, Tr=0.8)
         t0 = time.perf_counter()
         o.step(steps)

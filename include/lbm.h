@@ -387,6 +387,12 @@ lbm_status lbm_measure_field(int lattice, int precision, const int n[3], const v
  * hipGraph.  A case advanced in a batch equals the same case advanced alone
  * with lbm_step, bit for bit.  The contact angle of every case is measured in
  * the step (2 sides in 2-D, 16 sectors in 3-D).
+ *
+ * Models: the chemical-potential model, the pseudopotential model and the
+ * phase-field model (LBM_MODEL_PHASE_FIELD, as for one lattice: mu_w of each
+ * solid and wall_mu are wall order parameters, the drop is the order
+ * parameter of Eq. 16 with W = 2 sqrt(2 pf_kappa / pf_A), the flat-interface
+ * width, and the measurement reads phi at the isolevel 0).
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch lbm_batch;
 
@@ -444,15 +450,21 @@ lbm_status lbm_batch_young_force(lbm_batch* b, const lbm_young_opts* opts, lbm_a
 lbm_status lbm_batch_set_young(lbm_batch* b, const lbm_young_opts* opts);
 lbm_status lbm_batch_young_last(lbm_batch* b, lbm_young* out, int n);
 
-/* Fields of one case: RHO (n*elem bytes), F (Q*n*elem, [Q][n]), CLASS (n bytes).  Synchronises. */
+/* Fields of one case: RHO (n*elem bytes), F (Q*n*elem, [Q][n]), CLASS (n bytes);
+ * the phase-field model also PHI (n*elem) and G (Q*n*elem).  Synchronises. */
 lbm_status lbm_batch_read(lbm_batch* b, int case_index, int field, void* dst, size_t bytes, int dst_on_device);
-/* Replace one case's state by f_eq(rho, 0) (LBM_FIELD_RHO only; a warm start). */
+/* Replace one case's state by f_eq(rho, 0) (LBM_FIELD_RHO; a warm start), or
+ * for the phase-field model by the state at rest of an order-parameter field
+ * (LBM_FIELD_PHI: phi on fluid nodes, rho = pf_rho0, g at rest).  Every other
+ * case keeps its state (both population sets are brought to the same form
+ * first).  Synchronises.  LBM_E_ARG for another field or a wrong size. */
 lbm_status lbm_batch_write(lbm_batch* b, int case_index, int field, const void* src, size_t bytes, int src_on_device);
 lbm_status lbm_batch_get_info(lbm_batch* b, lbm_batch_info* info);
 /* Re-run the autotuner (the state is unchanged). */
 lbm_status lbm_batch_tune(lbm_batch* b, const char* cache_path);
 /* Advance every case nsteps steps (no measurement) with a HIP event pair
- * around each launch of kb_density, kb_mu and kb_collide, and report their
+ * around each launch of kb_density, kb_mu and kb_collide (kb_pf_density,
+ * kb_pf_mu and kb_pf_collide for the phase-field model), and report their
  * mean duration in milliseconds: names[i] (static strings) and ms[i] for
  * i < *n_kinds (cap entries at most).  Synchronises.  Errors: LBM_E_ARG,
  * LBM_E_STATE before any initial state, LBM_E_DEVICE, LBM_E_NONFINITE. */

@@ -493,7 +493,7 @@ struct Run {
     // the state of an order-parameter field (device array of N values)
     static void pf_init(lbm_ctx* c, const void* src) {
         k_pf_init<L, R><<<2048, 256, 0, c->stream>>>((const R*)src, (R*)c->phi, (R*)c->rho, (R*)c->f[c->cur],
-                                                     (R*)c->g[c->cur], c->cls, c->d.N, c->cfg.pf_rho0);
+                                                     (R*)c->g[c->cur], c->cls, c->d.N, c->cfg.pf_rho0, 0, c->d.N);
     }
 
     // One step on the one-pass path, reading f[src] and rhob[rsrc] (rho_t, with

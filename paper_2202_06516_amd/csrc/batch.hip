@@ -5,7 +5,8 @@
 // launch: a fixed grid of workgroups walks a work list of (case, tile) items
 // and runs the same per-node device bodies as the single-lattice kernels, so a
 // case advanced in a batch is bitwise identical to the same case advanced
-// alone.  Step loops are captured in a hipGraph.  The tile width and the
+// alone.  The phase-field model runs on the same work list with its own
+// density, mu and collision bodies.  Step loops are captured in a hipGraph.  The tile width and the
 // number of workgroups per compute unit come from a small autotuner that times
 // candidate launches on the batch itself and caches its choice in a JSON file.
 #include <hip/hip_runtime.h>
@@ -23,6 +24,7 @@
 #include "host.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
+#include "phasefield.hpp"
 #include "young.hpp"
 
 using namespace lbm;
@@ -191,6 +193,60 @@ __global__ void __launch_bounds__(256) kb_young_step(const Item* __restrict__ it
     }
 }
 
+// --- the phase-field model: phi (and with RHO rho) of every case, mu of phi, and
+// the collision of both population sets; the crossing search and the finalize
+// read phi at the isolevel mp.rho_m (0)
+template <class L, typename R, typename C, bool PULL, bool RHO>
+__global__ void __launch_bounds__(256) kb_pf_density(const Item* __restrict__ items, int nitems,
+                                                     const Dims* __restrict__ dims, int tile_w, const R* __restrict__ f,
+                                                     const R* __restrict__ g, R* __restrict__ rho, R* __restrict__ phi,
+                                                     const uint8_t* __restrict__ cls, WallBC bc,
+                                                     DevCtl* __restrict__ ctl, MeasureSlots* __restrict__ slots,
+                                                     const MeasureParams* __restrict__ mp) {
+    const bool meas = measuring(ctl);
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        const bool liquid = pf_density_node<L, R, C, PULL, RHO>(f, g, rho, phi, cls, d, bc, &ctl->status,
+                                                                mp[it.c].rho_m, x, y, z);
+        if (meas) centroid_reduce(liquid, x, y, z, &slots[it.c]);
+    }
+}
+
+template <class L, typename R>
+__global__ void __launch_bounds__(256) kb_pf_mu(const Item* __restrict__ items, int nitems,
+                                                const Dims* __restrict__ dims, int tile_w, const R* __restrict__ phi,
+                                                R* __restrict__ mu, const uint8_t* __restrict__ cls, PhaseField pf) {
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        if (x < d.nx && y < d.ny) pf_mu_node<L, R>(phi, mu, cls, d, pf, x, y, z);
+    }
+}
+
+template <class L, typename R, typename C, bool PULL, bool MRT>
+__global__ void __launch_bounds__(256) kb_pf_collide(const Item* __restrict__ items, int nitems,
+                                                     const Dims* __restrict__ dims, int tile_w,
+                                                     const R* __restrict__ fin, R* __restrict__ fout,
+                                                     const R* __restrict__ gin, R* __restrict__ gout,
+                                                     const R* __restrict__ phi, const R* __restrict__ mu,
+                                                     const uint8_t* __restrict__ cls, WallBC bc, Collision<C> cp,
+                                                     PhaseField pf, DevCtl* __restrict__ ctl) {
+    const long long t = ctl->t;
+    for (int k = xcd_slot(); k < nitems; k += gridDim.x) {
+        const Item it = items[k];
+        const Dims d = dims[it.c];
+        int x, y, z;
+        item_node(it, tile_w, x, y, z);
+        pf_collide_node<L, R, C, PULL, MRT>(fin, fout, gin, gout, phi, mu, cls, d, bc, cp, pf, &ctl->status, t, x, y,
+                                            z);
+    }
+}
+
 __global__ void kb_tick(DevCtl* ctl) {
     if (threadIdx.x == 0) ctl->t += 1;
 }
@@ -255,6 +311,10 @@ struct lbm_batch {
     AngleRec* last = nullptr;
     DevCtl* ctl = nullptr;
     void* f[2] = {nullptr, nullptr};
+    bool pf = false;                   // the phase-field model
+    PhaseField pfp{};                  // its parameters
+    void* g[2] = {nullptr, nullptr};   // its order-parameter populations
+    void* phi = nullptr;               // its order parameter (wall values on the solid layers)
     int cur = 0;
     bool fstar = false, have_state = false;
     void *rho = nullptr, *mu = nullptr, *inv = nullptr, *bq = nullptr;
@@ -402,6 +462,31 @@ struct BRun {
             kb_fill<L, R, C><<<ng2 < grid ? ng2 : grid, 256, 0, b->stream>>>(
                 b->fnode, b->fmask, (const R*)b->inv, b->fcase, b->n_l1, b->n_l1 + b->n_l2, (R*)b->rho, b->dims);
     }
+    // phase-field model: phi of the state in f[src] / g[src] (with_rho: rho
+    // as well, for reads; the collision forms rho itself)
+    static void pf_density(lbm_batch* b, int src, bool pull, bool with_rho, int grid) {
+        const R* f = (const R*)b->f[src];
+        const R* g = (const R*)b->g[src];
+#define KB_PF_DENSITY(P, W)                                                                                        \
+    kb_pf_density<L, R, C, P, W><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, f, g,      \
+                                                              (R*)b->rho, (R*)b->phi, b->cls, wall(b), b->ctl,   \
+                                                              b->slots, b->mp)
+        if (pull) {
+            if (with_rho) KB_PF_DENSITY(true, true);
+            else KB_PF_DENSITY(true, false);
+        } else {
+            if (with_rho) KB_PF_DENSITY(false, true);
+            else KB_PF_DENSITY(false, false);
+        }
+#undef KB_PF_DENSITY
+    }
+    static void pf_mu(lbm_batch* b, int grid) {
+        kb_pf_mu<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->phi, (R*)b->mu,
+                                                    b->cls, b->pfp);
+    }
+    // the field the measurement reads: phi of the phase-field model, else rho
+    static const R* mfield(const lbm_batch* b) { return (const R*)(b->pf ? b->phi : b->rho); }
+
     // chemical potential, or psi of the pseudopotential model, on fluid nodes
     static void launch_mu(lbm_batch* b, int grid) {
         if (b->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL)
@@ -414,19 +499,27 @@ struct BRun {
 
     // one step from f[src] (pull form if pull) into f[1 - src]
     static void step(lbm_batch* b, int src, bool pull, int grid, hipEvent_t* ev = nullptr) {
-        const int save = b->cur;
-        b->cur = src;
-        density(b, pull, grid, ev);
-        b->cur = save;
+        if (b->pf) {
+            if (ev) (void)hipEventRecord(ev[0], b->stream);
+            pf_density(b, src, pull, false, grid);
+            if (ev) (void)hipEventRecord(ev[1], b->stream);
+        } else {
+            const int save = b->cur;
+            b->cur = src;
+            density(b, pull, grid, ev);
+            b->cur = save;
+        }
         if (ev) (void)hipEventRecord(ev[2], b->stream);
-        launch_mu(b, grid);
+        if (b->pf) pf_mu(b, grid);
+        else launch_mu(b, grid);
         if (ev) (void)hipEventRecord(ev[3], b->stream);
-        kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
-                                                    b->ctl, b->slots, b->mp);
+        const R* mf = mfield(b);
+        kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, mf, b->cls, b->ctl, b->slots,
+                                                    b->mp);
         YoungStep ys{};
         if (b->young_on) {
-            kb_young_step<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho,
-                                                             b->cls, b->ystep_params, b->mp, b->slots, b->ctl,
+            kb_young_step<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, mf, b->cls,
+                                                             b->ystep_params, b->mp, b->slots, b->ctl,
                                                              b->ystep_counts);
             ys.on = 1;
             ys.gamma = b->yopts.gamma;
@@ -443,7 +536,19 @@ struct BRun {
         const bool mrt = b->cfg.collision == LBM_MRT;
 #define KB_ARGS b->items, b->nitems, b->dims, b->tile_w, fin, fout, (const R*)b->rho, (const R*)b->mu, b->cls, bc, cp, b->ctl
         if (ev) (void)hipEventRecord(ev[4], b->stream);
-        if (b->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL) {
+        if (b->pf) {
+#define KB_PF_ARGS                                                                                              \
+    b->items, b->nitems, b->dims, b->tile_w, fin, fout, (const R*)b->g[src], (R*)b->g[1 - src], (const R*)b->phi, \
+        (const R*)b->mu, b->cls, bc, cp, b->pfp, b->ctl
+            if (pull) {
+                if (mrt) kb_pf_collide<L, R, C, true, true><<<grid, 256, 0, b->stream>>>(KB_PF_ARGS);
+                else kb_pf_collide<L, R, C, true, false><<<grid, 256, 0, b->stream>>>(KB_PF_ARGS);
+            } else {
+                if (mrt) kb_pf_collide<L, R, C, false, true><<<grid, 256, 0, b->stream>>>(KB_PF_ARGS);
+                else kb_pf_collide<L, R, C, false, false><<<grid, 256, 0, b->stream>>>(KB_PF_ARGS);
+            }
+#undef KB_PF_ARGS
+        } else if (b->cfg.model == LBM_MODEL_PSEUDOPOTENTIAL) {
             if (pull) {
                 if (mrt) kb_collide<L, R, C, true, true, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
                 else kb_collide<L, R, C, true, false, true><<<grid, 256, 0, b->stream>>>(KB_ARGS);
@@ -460,22 +565,32 @@ struct BRun {
         }
 #undef KB_ARGS
         if (ev) (void)hipEventRecord(ev[5], b->stream);
-        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last,
-                                                          ys);
+        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>(mf, b->ctl, b->dims, b->mp, b->slots, b->last, ys);
         kb_tick<<<1, 64, 0, b->stream>>>(b->ctl);
     }
-    static R* materialize(lbm_batch* b, int grid) {
-        R* out = (R*)b->f[1 - b->cur];
+    // S_t of the fluid populations (order: those of the phase-field model,
+    // which stream with halfway bounce-back) into the spare buffer
+    static R* materialize(lbm_batch* b, int grid, bool order = false) {
+        void* const* set = order ? b->g : b->f;
+        R* out = (R*)set[1 - b->cur];
+        WallBC bc = wall(b);
+        if (order) bc.bouzidi = 0;
         if (b->fstar)
             kb_materialize<L, R, C, true><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w,
-                                                                       (const R*)b->f[b->cur], out, b->cls, wall(b));
+                                                                       (const R*)set[b->cur], out, b->cls, bc);
         else
             kb_materialize<L, R, C, false><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w,
-                                                                        (const R*)b->f[b->cur], out, b->cls, wall(b));
+                                                                        (const R*)set[b->cur], out, b->cls, bc);
         return out;
     }
-    static void init_feq(lbm_batch* b) {
-        k_init_feq<L, R><<<4096, 256, 0, b->stream>>>((const R*)b->rho, (R*)b->f[b->cur], b->cls, b->Ntot, 0, b->Ntot);
+    // the state at rest of rho (f_eq(rho, 0)) or, for the phase-field model,
+    // of the order parameter staged in src, on packed nodes [beg, end)
+    static void init_state(lbm_batch* b, const void* src, long long beg, long long end) {
+        if (b->pf)
+            k_pf_init<L, R><<<2048, 256, 0, b->stream>>>((const R*)src, (R*)b->phi, (R*)b->rho, (R*)b->f[b->cur],
+                                                         (R*)b->g[b->cur], b->cls, b->Ntot, b->pfp.rho0, beg, end);
+        else
+            k_init_feq<L, R><<<4096, 256, 0, b->stream>>>((const R*)b->rho, (R*)b->f[b->cur], b->cls, b->Ntot, beg, end);
     }
 };
 
@@ -503,34 +618,48 @@ struct BStepTimed {
         BRun<L, R, C>::step(b, src, pull, grid, ev);
     }
 };
+// the fields of the current state: rho (with the solid fill), or for the
+// phase-field model phi and rho
 template <class L, typename R, typename C>
 struct BDerive {
-    static void go(lbm_batch* b, int grid) { BRun<L, R, C>::density(b, b->fstar, grid); }
+    static void go(lbm_batch* b, int grid) {
+        if (b->pf) BRun<L, R, C>::pf_density(b, b->cur, b->fstar, true, grid);
+        else BRun<L, R, C>::density(b, b->fstar, grid);
+    }
 };
 template <class L, typename R, typename C>
 struct BMaterialize {
-    static void go(lbm_batch* b, int grid, void** out) { *out = BRun<L, R, C>::materialize(b, grid); }
+    static void go(lbm_batch* b, int grid, void** out, bool order) {
+        *out = BRun<L, R, C>::materialize(b, grid, order);
+    }
 };
 template <class L, typename R, typename C>
 struct BInit {
-    static void go(lbm_batch* b) { BRun<L, R, C>::init_feq(b); }
+    static void go(lbm_batch* b, const void* src, long long beg, long long end) {
+        BRun<L, R, C>::init_state(b, src, beg, end);
+    }
 };
 template <class L, typename R, typename C>
 struct BMeasure {
     static void go(lbm_batch* b, int grid) {
-        BRun<L, R, C>::density(b, b->fstar, grid);
-        BRun<L, R, C>::launch_mu(b, grid);
-        kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho, b->cls,
-                                                    b->ctl, b->slots, b->mp);
-        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>((const R*)b->rho, b->ctl, b->dims, b->mp, b->slots, b->last);
+        if (b->pf) {
+            BRun<L, R, C>::pf_density(b, b->cur, b->fstar, true, grid);
+        } else {
+            BRun<L, R, C>::density(b, b->fstar, grid);
+            BRun<L, R, C>::launch_mu(b, grid);
+        }
+        const R* mf = BRun<L, R, C>::mfield(b);
+        kb_cross<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, mf, b->cls, b->ctl,
+                                                    b->slots, b->mp);
+        kb_finalize<L, R><<<b->ncases, 64, 0, b->stream>>>(mf, b->ctl, b->dims, b->mp, b->slots, b->last);
     }
 };
 
 template <class L, typename R, typename C>
 struct BYoung {
     static void go(lbm_batch* b, int grid) {
-        kb_young_count<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w, (const R*)b->rho,
-                                                         b->cls, b->yparams, b->ycounts);
+        kb_young_count<L, R><<<grid, 256, 0, b->stream>>>(b->items, b->nitems, b->dims, b->tile_w,
+                                                         BRun<L, R, C>::mfield(b), b->cls, b->yparams, b->ycounts);
     }
 };
 
@@ -549,6 +678,7 @@ std::string tune_key(const lbm_batch* b) {
     mix((unsigned long long)b->cfg.precision);
     mix((unsigned long long)b->cfg.collision);
     mix((unsigned long long)b->cfg.bc_mode);
+    mix((unsigned long long)b->cfg.model);
     for (const Dims& d : b->dims_h) {
         mix((unsigned long long)d.nx);
         mix((unsigned long long)d.ny);
@@ -621,8 +751,9 @@ lbm_status autotune(lbm_batch* b, const char* cache) {
     // time a few steps per candidate on a copy of the state; restore afterwards
     const size_t fb = (size_t)b->Q * b->Ntot * b->elem;
     void* snap = nullptr;
-    if (balloc(b, (char**)&snap, fb)) return LBM_E_NOMEM;
+    if (balloc(b, (char**)&snap, b->pf ? 2 * fb : fb)) return LBM_E_NOMEM;
     BCHK(b, hipMemcpyAsync(snap, b->f[b->cur], fb, hipMemcpyDeviceToDevice, b->stream));
+    if (b->pf) BCHK(b, hipMemcpyAsync((char*)snap + fb, b->g[b->cur], fb, hipMemcpyDeviceToDevice, b->stream));
     const int cur0 = b->cur;
     const bool fstar0 = b->fstar;
     k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 0);
@@ -662,6 +793,7 @@ lbm_status autotune(lbm_batch* b, const char* cache) {
     b->cur = cur0;
     b->fstar = fstar0;
     BCHK(b, hipMemcpyAsync(b->f[b->cur], snap, fb, hipMemcpyDeviceToDevice, b->stream));
+    if (b->pf) BCHK(b, hipMemcpyAsync(b->g[b->cur], (char*)snap + fb, fb, hipMemcpyDeviceToDevice, b->stream));
     k_ctl_set<<<1, 64, 0, b->stream>>>(b->ctl, b->t, 0, 0, 0, 1);
     BCHK(b, hipStreamSynchronize(b->stream));
     (void)hipFree(snap);
@@ -685,7 +817,7 @@ lbm_status lbm_batch_destroy(lbm_batch* b) {
     drop_graph(b);
     void* ps[] = {b->dims, b->mp,   b->slots, b->last, b->ctl,  b->f[0], b->f[1], b->rho,  b->mu,   b->inv,
                   b->bq,   b->cls,  b->nbmask, b->fmask, b->bidx, b->fcase, b->fnode, b->items,
-                  b->yparams, b->ycounts, b->ystep_params, b->ystep_counts, b->ylast};
+                  b->yparams, b->ycounts, b->ystep_params, b->ystep_counts, b->ylast, b->g[0], b->g[1], b->phi};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -706,7 +838,14 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         return LBM_E_ARG;
     };
     if (base->lattice != LBM_D2Q9 && base->lattice != LBM_D3Q19) return bad();
-    if (base->model != LBM_MODEL_CHEMICAL_POTENTIAL && base->model != LBM_MODEL_PSEUDOPOTENTIAL) return bad();
+    if (base->model != LBM_MODEL_CHEMICAL_POTENTIAL && base->model != LBM_MODEL_PSEUDOPOTENTIAL &&
+        base->model != LBM_MODEL_PHASE_FIELD)
+        return bad();
+    if (base->model == LBM_MODEL_PHASE_FIELD &&
+        (!(base->pf_A > 0) || !(base->pf_kappa > 0) || !(base->pf_gamma > 0) || !(base->pf_tau > 0.5) ||
+         !(base->pf_rho0 > 0) ||
+         !std::isfinite(base->pf_A + base->pf_kappa + base->pf_gamma + base->pf_tau + base->pf_rho0)))
+        return bad();
     if (base->model == LBM_MODEL_PSEUDOPOTENTIAL &&
         (!(base->rho_g > 0) || !(base->rho_l > base->rho_g) || !std::isfinite(base->sc_G)))
         return bad();
@@ -732,6 +871,25 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         // wall values are densities; psi is stored unshifted
         b->mu_ref = 0.0;
         b->wall_mu = std::isnan(base->wall_mu) ? b->rho_m : base->wall_mu;
+    }
+    b->pf = base->model == LBM_MODEL_PHASE_FIELD;
+    // initial interface width of Eq. 16
+    double W = 10.0;
+    if (b->pf) {
+        // bulk order parameters +1 / -1, isolevel 0; wall values are order
+        // parameters, written into phi; the drop takes the flat-interface
+        // profile tanh(r / xi), xi = sqrt(2 kappa / A), i.e. Eq. 16 with W = 2 xi
+        b->pr.rho_l = 1.0;
+        b->pr.rho_g = -1.0;
+        b->rho_m = 0.0;
+        b->mu_ref = 0.0;
+        b->wall_mu = std::isnan(base->wall_mu) ? 0.0 : base->wall_mu;
+        b->pfp.A = base->pf_A;
+        b->pfp.kappa = base->pf_kappa;
+        b->pfp.gamma = base->pf_gamma;
+        b->pfp.omega = 1.0 / base->pf_tau;
+        b->pfp.rho0 = base->pf_rho0;
+        W = 2.0 * std::sqrt(2.0 * base->pf_kappa / base->pf_A);
     }
     const bool sc = base->model == LBM_MODEL_PSEUDOPOTENTIAL;
     auto wall_value = [&](double v) { return sc ? 1.0 - std::exp(-v) : v - b->mu_ref; };
@@ -855,7 +1013,7 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
             const double dx = x - cs.drop.center[0], dy = y - cs.drop.center[1];
             const double dz = b->dim == 3 ? z - cs.drop.center[2] : 0.0;
             const double rr = std::sqrt(dx * dx + dy * dy + dz * dz);
-            rhoh[base_at + at(i)] = 0.5 * (rg + rl) + 0.5 * (rg - rl) * std::tanh(2.0 * (rr - cs.drop.radius) / 10.0);
+            rhoh[base_at + at(i)] = 0.5 * (rg + rl) + 0.5 * (rg - rl) * std::tanh(2.0 * (rr - cs.drop.radius) / W);
         }
         b->n_fluid += g.n_fluid;
         b->n_nodes += g.N;
@@ -885,7 +1043,11 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         (s = balloc(b, &b->slots, (size_t)ncases * sizeof(MeasureSlots))) ||
         (s = balloc(b, &b->last, (size_t)ncases * sizeof(AngleRec))) || (s = balloc(b, &b->ctl, sizeof(DevCtl))) ||
         (s = bupload(b, &b->cls, cls)) || (s = bupload(b, &b->nbmask, nbm)) || (s = bupload(b, &b->bidx, bidx)) ||
-        (s = bupload_real(b, &b->bq, bq)) || (s = bupload_real(b, &b->mu, muh)) || (s = bupload_real(b, &b->rho, rhoh)) ||
+        (s = bupload_real(b, &b->bq, bq)) ||
+        (s = bupload_real(b, b->pf ? &b->phi : &b->mu, muh)) ||
+        (b->pf && ((s = balloc(b, (char**)&b->g[0], fb)) || (s = balloc(b, (char**)&b->g[1], fb)) ||
+                   (s = bupload_real(b, &b->mu, std::vector<double>(muh.size(), 0.0))))) ||
+        (s = bupload_real(b, &b->rho, rhoh)) ||
         (s = bupload(b, &b->fnode, fnode)) || (s = bupload(b, &b->fmask, fmask)) || (s = bupload_real(b, &b->inv, inv)) ||
         (s = bupload(b, &b->fcase, fcase))) {
         std::string e = b->err;
@@ -899,10 +1061,23 @@ lbm_status lbm_batch_create(const lbm_config* base, const lbm_case* cases, int n
         return LBM_E_DEVICE;
     }
     kb_slots_reset<<<ncases, 64, 0, b->stream>>>(b->slots, ncases);
-    // state = f_eq(rho, 0) with rho of Eq. 16
-    if (b->elem == 8) k_fill_value<double><<<2048, 256, 0, b->stream>>>((double*)b->f[1], fb / 8, 0.0);
-    else k_fill_value<float><<<2048, 256, 0, b->stream>>>((float*)b->f[1], fb / 4, 0.0f);
-    bdispatch<BInit>(b);
+    // state = f_eq(rho, 0) with rho of Eq. 16; phase-field model: the order
+    // parameter of Eq. 16 (staged in rho) at rest, rho = rho0
+    auto zero = [&](void* p) {
+        if (b->elem == 8) k_fill_value<double><<<2048, 256, 0, b->stream>>>((double*)p, fb / 8, 0.0);
+        else k_fill_value<float><<<2048, 256, 0, b->stream>>>((float*)p, fb / 4, 0.0f);
+    };
+    zero(b->f[1]);
+    if (b->pf) {
+        zero(b->g[1]);
+        if (hipMemcpyAsync(b->g[1], b->rho, (size_t)b->Ntot * b->elem, hipMemcpyDeviceToDevice, b->stream) !=
+            hipSuccess) {
+            lbm_batch_destroy(b);
+            return LBM_E_DEVICE;
+        }
+    }
+    bdispatch<BInit>(b, b->pf ? (const void*)b->g[1] : nullptr, 0ll, b->Ntot);
+    if (b->pf) zero(b->g[1]);
     if (hipStreamSynchronize(b->stream) != hipSuccess) {
         lbm_batch_destroy(b);
         return LBM_E_DEVICE;
@@ -966,6 +1141,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int measure_every) {
 lbm_status lbm_batch_profile_step(lbm_batch* b, int64_t nsteps, const char** names, double* ms, int cap,
                                   int* n_kinds) {
     static const char* kNames[3] = {"kb_density", "kb_mu", "kb_collide"};
+    static const char* kPfNames[3] = {"kb_pf_density", "kb_pf_mu", "kb_pf_collide"};
     if (!b || !names || !ms || !n_kinds || cap < 0) return LBM_E_ARG;
     if (!b->have_state) return bfail(b, LBM_E_STATE, "batch profile: no state");
     if (nsteps < 1) return bfail(b, LBM_E_ARG, "batch profile: nsteps >= 1");
@@ -999,7 +1175,7 @@ lbm_status lbm_batch_profile_step(lbm_batch* b, int64_t nsteps, const char** nam
     if (err != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch profile: ") + hipGetErrorString(err));
     int n = 0;
     for (int k = 0; k < 3 && n < cap; ++k, ++n) {
-        names[n] = kNames[k];
+        names[n] = b->pf ? kPfNames[k] : kNames[k];
         ms[n] = tot[k] / (double)nsteps;
     }
     *n_kinds = n;
@@ -1129,14 +1305,15 @@ lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t byt
     const size_t n = (size_t)d.nx * d.ny * d.nz, rows = (size_t)d.ny * d.nz;
     const size_t e = b->elem, w = (size_t)d.nx * e, sp = (size_t)d.px * e;  // row bytes, padded row bytes
     const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (field == LBM_FIELD_RHO) {
-        if (bytes != n * e) return bfail(b, LBM_E_ARG, "batch read RHO: bytes must be n * elem");
+    if (field == LBM_FIELD_RHO || (field == LBM_FIELD_PHI && b->pf)) {
+        if (bytes != n * e) return bfail(b, LBM_E_ARG, "batch read RHO/PHI: bytes must be n * elem");
         bdispatch<BDerive>(b, grid_of(b));
-        BCHK(b, hipMemcpy2DAsync(dst, w, (char*)b->rho + (size_t)d.off * e, sp, w, rows, kind, b->stream));
-    } else if (field == LBM_FIELD_F) {
-        if (bytes != (size_t)b->Q * n * e) return bfail(b, LBM_E_ARG, "batch read F: bytes must be Q * n * elem");
+        const char* src = (const char*)(field == LBM_FIELD_RHO ? b->rho : b->phi);
+        BCHK(b, hipMemcpy2DAsync(dst, w, src + (size_t)d.off * e, sp, w, rows, kind, b->stream));
+    } else if (field == LBM_FIELD_F || (field == LBM_FIELD_G && b->pf)) {
+        if (bytes != (size_t)b->Q * n * e) return bfail(b, LBM_E_ARG, "batch read F/G: bytes must be Q * n * elem");
         void* S = nullptr;
-        bdispatch<BMaterialize>(b, grid_of(b), &S);
+        bdispatch<BMaterialize>(b, grid_of(b), &S, field == LBM_FIELD_G);
         for (int i = 0; i < b->Q; ++i)
             BCHK(b, hipMemcpy2DAsync((char*)dst + (size_t)i * n * e, w,
                                      (char*)S + ((size_t)i * b->Ntot + (size_t)d.off) * e, sp, w, rows, kind,
@@ -1150,7 +1327,7 @@ lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t byt
         if (dst_on_device) BCHK(b, hipMemcpyAsync(dst, h.data(), n, hipMemcpyHostToDevice, b->stream));
         else std::memcpy(dst, h.data(), n);
     } else {
-        return bfail(b, LBM_E_ARG, "batch read: field must be RHO, F or CLASS");
+        return bfail(b, LBM_E_ARG, "batch read: field must be RHO, F or CLASS (phase-field model: also PHI or G)");
     }
     BCHK(b, hipStreamSynchronize(b->stream));
     return LBM_OK;
@@ -1159,32 +1336,39 @@ lbm_status lbm_batch_read(lbm_batch* b, int ci, int field, void* dst, size_t byt
 lbm_status lbm_batch_write(lbm_batch* b, int ci, int field, const void* src, size_t bytes, int src_on_device) {
     if (!b || !src) return b ? bfail(b, LBM_E_ARG, "batch write: null source") : LBM_E_ARG;
     if (ci < 0 || ci >= b->ncases) return bfail(b, LBM_E_ARG, "batch write: case index out of range");
-    if (field != LBM_FIELD_RHO) return bfail(b, LBM_E_ARG, "batch write: field must be RHO");
+    const int want = b->pf ? LBM_FIELD_PHI : LBM_FIELD_RHO;
+    if (field != want)
+        return bfail(b, LBM_E_ARG, b->pf ? "batch write: field must be PHI (phase-field model)"
+                                         : "batch write: field must be RHO");
     const Dims& d = b->dims_h[ci];
     const size_t n = (size_t)d.nx * d.ny * d.nz, rows = (size_t)d.ny * d.nz;
-    if (bytes != n * b->elem) return bfail(b, LBM_E_ARG, "batch write RHO: bytes must be n * elem");
-    // bring every case to form S (materialize), then replace this case's populations
+    if (bytes != n * b->elem) return bfail(b, LBM_E_ARG, "batch write RHO/PHI: bytes must be n * elem");
+    // bring every case to form S (materialize; both population sets of the
+    // phase-field model), then replace this case's populations
     if (b->fstar) {
         void* S = nullptr;
-        bdispatch<BMaterialize>(b, grid_of(b), &S);
+        bdispatch<BMaterialize>(b, grid_of(b), &S, false);
+        if (b->pf) bdispatch<BMaterialize>(b, grid_of(b), &S, true);
         b->cur ^= 1;
         b->fstar = false;
         drop_graph(b);
     }
     BCHK(b, hipStreamSynchronize(b->stream));
     // stream-ordered: a device-to-device copy may otherwise still be in flight
-    // when k_init_feq runs (or when the caller reuses src)
-    BCHK(b, hipMemcpy2DAsync((char*)b->rho + (size_t)d.off * b->elem, (size_t)d.px * b->elem, src,
-                             (size_t)d.nx * b->elem, (size_t)d.nx * b->elem, rows,
+    // when the state is formed (or when the caller reuses src).  The order
+    // parameter is staged in the spare g buffer (free between steps) at the
+    // case's offset; rho is the field itself.
+    char* stage = (char*)(b->pf ? b->g[1 - b->cur] : b->rho);
+    BCHK(b, hipMemcpy2DAsync(stage + (size_t)d.off * b->elem, (size_t)d.px * b->elem, src, (size_t)d.nx * b->elem,
+                             (size_t)d.nx * b->elem, rows,
                              src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, b->stream));
-    // f_eq(rho, 0) on this case's range of the packed arrays (pad nodes are solid: zero)
+    // the state at rest on this case's range of the packed arrays (pad nodes are solid: zero)
     const long long beg = d.off, end = d.off + (long long)d.px * d.ny * d.nz;
-    if (b->dim == 2) {
-        if (b->elem == 8) k_init_feq<D2Q9, double><<<1024, 256, 0, b->stream>>>((const double*)b->rho, (double*)b->f[b->cur], b->cls, b->Ntot, beg, end);
-        else k_init_feq<D2Q9, float><<<1024, 256, 0, b->stream>>>((const float*)b->rho, (float*)b->f[b->cur], b->cls, b->Ntot, beg, end);
-    } else {
-        if (b->elem == 8) k_init_feq<D3Q19, double><<<1024, 256, 0, b->stream>>>((const double*)b->rho, (double*)b->f[b->cur], b->cls, b->Ntot, beg, end);
-        else k_init_feq<D3Q19, float><<<1024, 256, 0, b->stream>>>((const float*)b->rho, (float*)b->f[b->cur], b->cls, b->Ntot, beg, end);
+    bdispatch<BInit>(b, (const void*)stage, beg, end);
+    if (b->pf) {
+        const size_t fb = (size_t)b->Q * b->Ntot * b->elem;
+        if (b->elem == 8) k_fill_value<double><<<2048, 256, 0, b->stream>>>((double*)stage, fb / 8, 0.0);
+        else k_fill_value<float><<<2048, 256, 0, b->stream>>>((float*)stage, fb / 4, 0.0f);
     }
     BCHK(b, hipGetLastError());
     BCHK(b, hipStreamSynchronize(b->stream));

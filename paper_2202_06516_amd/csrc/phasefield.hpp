@@ -1,4 +1,5 @@
-// phasefield.hpp -- the phase-field model on the split step.
+// phasefield.hpp -- the phase-field model on the split step (a single lattice,
+// and every case of the batched solver through the same per-node bodies).
 //
 // Sec. V names phase-field models among the multiphase models whose diffuse
 // interface the measurement reads; the paper fixes none.  The model here is
@@ -39,15 +40,15 @@ struct PhaseField {
     double rho0;      // fluid density of the initial state (both phases)
 };
 
-// phi = sum g of the gathered populations of fluid nodes, and with RHO also
-// rho = sum f (the step itself needs no rho field)
+// phi = sum g of the gathered populations of a fluid node, and with RHO also
+// rho = sum f (the step itself needs no rho field); true if liquid.  Every
+// per-node body below serves a single lattice tiled by workgroups and the
+// packed lattices of the batched solver alike.
 template <class L, typename R, typename C, bool PULL, bool RHO>
-__global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, const R* __restrict__ g,
-                                                    R* __restrict__ rho, R* __restrict__ phi,
-                                                    const uint8_t* __restrict__ cls, Dims d, WallBC bc,
-                                                    DevCtl* __restrict__ ctl, double phi_m) {
-    int x, y, z;
-    tile_node(d, x, y, z);
+__device__ __forceinline__ bool pf_density_node(const R* __restrict__ f, const R* __restrict__ g,
+                                                R* __restrict__ rho, R* __restrict__ phi,
+                                                const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
+                                                int* status, double phi_m, int x, int y, int z) {
     bool liquid = false;
     if (x < d.nx && y < d.ny) {
         const long long idx = nid(d, x, y, z);
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, con
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i) s += (double)S[i];
                 at(rho, ix) = (R)s;
-                if (!(s > 0.0 && s < 1e300)) atomicOr(&ctl->status, 1);  // also catches NaN
+                if (!(s > 0.0 && s < 1e300)) atomicOr(status, 1);  // also catches NaN
             }
             WallBC hw = bc;
             hw.bouzidi = 0;
@@ -71,10 +72,21 @@ __global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, con
             for (int i = 0; i < L::Q; ++i) p += (double)S[i];
             const R ps = (R)p;
             at(phi, ix) = ps;
-            if (!(fabs(p) < 1e300)) atomicOr(&ctl->status, 1);
+            if (!(fabs(p) < 1e300)) atomicOr(status, 1);
             liquid = (double)ps >= phi_m;
         }
     }
+    return liquid;
+}
+
+template <class L, typename R, typename C, bool PULL, bool RHO>
+__global__ void __launch_bounds__(256) k_pf_density(const R* __restrict__ f, const R* __restrict__ g,
+                                                    R* __restrict__ rho, R* __restrict__ phi,
+                                                    const uint8_t* __restrict__ cls, Dims d, WallBC bc,
+                                                    DevCtl* __restrict__ ctl, double phi_m) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    const bool liquid = pf_density_node<L, R, C, PULL, RHO>(f, g, rho, phi, cls, d, bc, &ctl->status, phi_m, x, y, z);
     if (measuring(ctl)) centroid_reduce(liquid, x, y, z, &ctl->m);
 }
 
@@ -213,13 +225,12 @@ __device__ __forceinline__ void pf_collide_g(const R G[L::Q], const C v[3], C mu
 // stored at the node (streaming is the next step's pull).  The fluid density
 // of the node is the sum of its gathered populations, checked here.
 template <class L, typename R, typename C, bool PULL, bool MRT>
-__global__ void __launch_bounds__(256) k_pf_collide(const R* __restrict__ fin, R* __restrict__ fout,
-                                                    const R* __restrict__ gin, R* __restrict__ gout,
-                                                    const R* __restrict__ phi, const R* __restrict__ mu,
-                                                    const uint8_t* __restrict__ cls, Dims d, WallBC bc,
-                                                    Collision<C> cp, PhaseField pf, DevCtl* __restrict__ ctl) {
-    int x, y, z;
-    tile_node(d, x, y, z);
+__device__ __forceinline__ void pf_collide_node(const R* __restrict__ fin, R* __restrict__ fout,
+                                                const R* __restrict__ gin, R* __restrict__ gout,
+                                                const R* __restrict__ phi, const R* __restrict__ mu,
+                                                const uint8_t* __restrict__ cls, const Dims& d, const WallBC& bc,
+                                                const Collision<C>& cp, const PhaseField& pf, int* status,
+                                                long long t, int x, int y, int z) {
     if (x >= d.nx || y >= d.ny) return;
     const long long idx = nid(d, x, y, z);
     const uint32_t ix = (uint32_t)idx;
@@ -230,9 +241,9 @@ __global__ void __launch_bounds__(256) k_pf_collide(const R* __restrict__ fin, R
     double r0 = 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) r0 += (double)S[i];
-    if (!(r0 > 0.0 && r0 < 1e300)) atomicOr(&ctl->status, 1);  // also catches NaN
+    if (!(r0 > 0.0 && r0 < 1e300)) atomicOr(status, 1);  // also catches NaN
     double F[3];
-    pf_force<L, R, C>(r0, phi, mu, d, ix, x, y, z, cp, ctl->t, F);
+    pf_force<L, R, C>(r0, phi, mu, d, ix, x, y, z, cp, t, F);
     collide_apply<L, R, C, MRT, true>(S, (C)F[0], (C)F[1], (C)F[2], cp, fout, idx, d.N);
     C v[3];
     pf_velocity<L, R, C>(S, F, v);
@@ -245,13 +256,28 @@ __global__ void __launch_bounds__(256) k_pf_collide(const R* __restrict__ fin, R
     for (int i = 0; i < L::Q; ++i) put<true>(&at(gout + (size_t)i * d.N, ix), go[i]);
 }
 
-// The state of an order-parameter field src: on fluid nodes phi = src,
-// rho = rho0, f = f^eq(rho0, 0), g at rest (g_0 = phi); populations zero
-// elsewhere.  phi of the solid layers (the wall values) is left as it is.
+template <class L, typename R, typename C, bool PULL, bool MRT>
+__global__ void __launch_bounds__(256) k_pf_collide(const R* __restrict__ fin, R* __restrict__ fout,
+                                                    const R* __restrict__ gin, R* __restrict__ gout,
+                                                    const R* __restrict__ phi, const R* __restrict__ mu,
+                                                    const uint8_t* __restrict__ cls, Dims d, WallBC bc,
+                                                    Collision<C> cp, PhaseField pf, DevCtl* __restrict__ ctl) {
+    int x, y, z;
+    tile_node(d, x, y, z);
+    pf_collide_node<L, R, C, PULL, MRT>(fin, fout, gin, gout, phi, mu, cls, d, bc, cp, pf, &ctl->status, ctl->t, x,
+                                        y, z);
+}
+
+// The state of an order-parameter field src on nodes [beg, end) of arrays of
+// stride N: on fluid nodes phi = src, rho = rho0, f = f^eq(rho0, 0), g at
+// rest (g_0 = phi); populations zero elsewhere.  phi of the solid layers (the
+// wall values) is left as it is.
 template <class L, typename R>
 __global__ void k_pf_init(const R* __restrict__ src, R* __restrict__ phi, R* __restrict__ rho, R* __restrict__ f,
-                          R* __restrict__ g, const uint8_t* __restrict__ cls, long long N, double rho0) {
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+                          R* __restrict__ g, const uint8_t* __restrict__ cls, long long N, double rho0, long long beg,
+                          long long end) {
+    for (long long n = beg + (long long)blockIdx.x * blockDim.x + threadIdx.x; n < end;
+         n += (long long)gridDim.x * blockDim.x) {
         const bool fl = (cls[n] & CLS_MASK) == CLS_FLUID;
         const R p = fl ? src[n] : R(0);
         if (fl) phi[n] = p;

@@ -566,7 +566,7 @@ class Batch:
         shp = self.shapes[case]
         if field == FIELD_CLASS:
             out = np.empty(shp, dtype=np.uint8)
-        elif field == FIELD_F:
+        elif field in (FIELD_F, FIELD_G):
             out = np.empty((self.Q,) + shp, dtype=self.dtype)
         else:
             out = np.empty(shp, dtype=self.dtype)
@@ -576,6 +576,11 @@ class Batch:
     def write_rho(self, case, rho):
         a = np.ascontiguousarray(rho, dtype=self.dtype)
         self._check(lib().lbm_batch_write(self._h, case, FIELD_RHO, a.ctypes.data, a.nbytes, 0))
+
+    def write_phi(self, case, phi):
+        """Phase-field model: the state at rest of an order-parameter field for one case."""
+        a = np.ascontiguousarray(phi, dtype=self.dtype)
+        self._check(lib().lbm_batch_write(self._h, case, FIELD_PHI, a.ctypes.data, a.nbytes, 0))
 
     def read_device(self, case, field, ptr, nbytes):
         """Copy one case's field into device memory at ptr."""

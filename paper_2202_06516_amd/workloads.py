@@ -342,6 +342,13 @@ def batch_cases(n_cases=512, seed=0, nmin=64, nmax=512, rs=(16.0, 128.0), r0=(12
 WARM_SEEDS = dict(train=1000, val=2000, test=3000)
 
 
+def pf_batch_cases(cases, seed, phi_w=(-0.4, 0.4)):
+    """The case table for the phase-field model: the same layouts, the wall value
+    of each solid a wall order parameter uniform in phi_w (seeded PCG64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [dict(c, solid=dict(c["solid"], mu_w=float(rng.uniform(*phi_w)))) for c in cases]
+
+
 def warmstart_cases(n_cases, seed, side=256, rs=(16.0, 64.0), r0=(18.0, 48.0), mu=(-0.01, 0.1), W=10.0):
     """Drops on cylinders for the learned warm start (seeded PCG64).
 

@@ -135,9 +135,6 @@ def test_phase_field_errors():
     other = gpu_lattice(W.sessile_2d(n=64), G.LBM_F64, "mrt")
     with pytest.raises(G.LbmError):
         other.read(G.FIELD_PHI)
-    with pytest.raises(G.LbmError):
-        G.Batch([dict(n=(64, 64), solid=dict(center=(32, 20), radius=10, mu_w=0.1), drop=((32, 38), 8))],
-                model=G.LBM_MODEL_PHASE_FIELD)
 
 
 def test_phase_field_3d_interpolated_wall():
