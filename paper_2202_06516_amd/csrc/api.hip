@@ -912,12 +912,18 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (cfg->step_kernel != LBM_STEP_AUTO && cfg->step_kernel != LBM_STEP_SPLIT) return bad("step_kernel");
     {
         // the one-pass step: D3Q19 (either wall scheme), whole rows of
-        // 64..1024 nodes per workgroup, 4 rows, zc planes (LBM_FUSED_ZC overrides 8, halved
-        // until it divides nz: at 256^3 the walk over 2, 4, 8 planes took 0.622, 0.606,
-        // 0.607 ms and the ghost sums 0.043, 0.031, 0.025 ms)
+        // 64..1024 nodes per workgroup, 4 rows, zc planes: 32, halved until it
+        // divides nz, and by default halved down to 8 while the grid would hold
+        // fewer than 512 workgroups (two per compute unit of a 256-CU device);
+        // LBM_FUSED_ZC sets the starting value.  Interleaved on one device at
+        // 256^3, the walk over 8, 16, 32 planes took 0.607, 0.599, 0.592 ms and
+        // the ghost sums 0.025, 0.022, 0.020 ms; 64 planes (one workgroup per
+        // CU) took 0.729 ms; at 512^3, 16 and 32 planes 4.61 and 4.59 ms
         const char* e = std::getenv("LBM_FUSED_ZC");
-        int zc = e ? std::atoi(e) : 8;
+        int zc = e ? std::atoi(e) : 32;
         while (zc > 2 && c->d.nz % zc) zc >>= 1;
+        if (!e)
+            while (zc > 8 && (long long)(c->d.ny / kFusedTY) * (c->d.nz / zc) < 512) zc >>= 1;
         c->fzc = zc;
         // (its node indices and the byte offsets of its population accesses, up to
         // five arrays from one base, are 32-bit)

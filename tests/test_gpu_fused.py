@@ -3,7 +3,7 @@ FP64 oracle and against the split step, element by element.
 
 k_step collides step t and sums the density of step t + 1 in the same pass;
 partial sums that cross its tiles go through ghost arrays.  The cases cover
-one, two and three waves per row, every z-chunk depth it picks (8, 4, 2),
+one, two and three waves per row, every z-chunk depth it picks (32, 16, 8, 4, 2),
 walls and periodic axes (ghost rows and planes that wrap), halfway and
 interpolated walls, MRT and BGK, gravity switched on mid-run, the pseudopotential model, FP64 /
 FP32 / FP32 with FP64 arithmetic, in-step measurement, reads between steps, and
@@ -66,6 +66,21 @@ def test_one_pass_matches_oracle_f64(n, wall, collision, bc):
     o.step(1)  # the profile call above advanced the GPU lattice one step
     gp.step(9)
     o.step(9)
+    fields(gp, o, 1e-12, vel=True)
+
+
+@pytest.mark.parametrize("zc", ["16", "32"])
+def test_one_pass_deep_plane_chunks_match_oracle(zc, monkeypatch):
+    # 32 planes per workgroup (the default on large lattices) and 16, set
+    # through LBM_FUSED_ZC on a small lattice whose depth they divide
+    monkeypatch.setenv("LBM_FUSED_ZC", zc)
+    wl = case((64, 24, 64), (1, 0, 0), r=9.1, drop=7.5)
+    gp = gpu_lattice(wl, G.LBM_F64, "mrt", "bouzidi", **SMALL)
+    assert is_fused(gp)
+    o = oracle_lattice(wl, "mrt", "bouzidi", **SMALL)
+    o.step(1)
+    gp.step(11)
+    o.step(11)
     fields(gp, o, 1e-12, vel=True)
 
 
