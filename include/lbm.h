@@ -94,8 +94,9 @@ enum { LBM_BC_HALFWAY = 0, LBM_BC_BOUZIDI_MC = 1 };
  * every mu_w is read as phi_w, held by both solid layers (NaN wall_mu: 0).  The
  * measurement reads phi at the isolevel 0 (rho_l = 1 and rho_g = -1 stand for
  * the two bulk values); lbm_init_drops profiles phi by Eq. 16 with the fluid
- * density pf_rho0 everywhere.  The split step only (the one-pass step, the
- * batched solver and the batched Young force are not built for it). */
+ * density pf_rho0 everywhere.  On one lattice it runs the split step (the
+ * one-pass step is not built for it); the batched solver runs it on every
+ * case, the in-step and on-demand Young force included. */
 enum { LBM_MODEL_CHEMICAL_POTENTIAL = 0, LBM_MODEL_PSEUDOPOTENTIAL = 1, LBM_MODEL_PHASE_FIELD = 2 };
 enum { LBM_STEP_AUTO = 0, LBM_STEP_SPLIT = 1 };
 
@@ -126,8 +127,8 @@ typedef struct {
     void* stream;         /* hipStream_t to enqueue on, or NULL for a context-owned stream */
     int model;            /* LBM_MODEL_CHEMICAL_POTENTIAL (default), LBM_MODEL_PSEUDOPOTENTIAL or
                              LBM_MODEL_PHASE_FIELD; the pseudopotential model needs rho_l > rho_g > 0 and
-                             ignores Tr, pr_*, k, kappa (the batched solver takes either of the first two for
-                             all its cases); the phase-field model ignores Tr, pr_*, k, kappa, rho_l, rho_g */
+                             ignores Tr, pr_*, k, kappa (the batched solver takes any of the three for all its
+                             cases); the phase-field model ignores Tr, pr_*, k, kappa, rho_l, rho_g */
     double sc_G;          /* pseudopotential interaction strength G (default -6) */
     int step_kernel;      /* LBM_STEP_AUTO (default): D3Q19 lattices (either wall scheme; not the phase-field
                              model) with nx a multiple of 64 (at most 1024), ny a multiple of 4 and nz even

@@ -23,10 +23,10 @@ def pf_cases(n=4, seed=21):
     return W.pf_batch_cases(cases, seed + 1)
 
 
-def single(case, precision, dim=2, collision="mrt"):
+def single(case, precision, dim=2, collision="mrt", bc="halfway"):
     wl = dict(dim=dim, n=case["n"], wall=(0,) * dim, model=2, W=W.PF_W, solids=[case["solid"]],
               drops=[case["drop"]])
-    return gpu_lattice(wl, precision, collision)
+    return gpu_lattice(wl, precision, collision, bc)
 
 
 def same_angles(a, b):
@@ -108,3 +108,40 @@ def test_pf_batch_write_phi_and_profile():
         b.write_rho(0, phi)
     with pytest.raises(G.LbmError):
         G.Batch(cases, precision=G.LBM_F64, **dict(PF, pf_tau=0.5))
+
+
+def test_pf_batch_interpolated_wall_and_in_step_young():
+    # the fluid populations on the interpolated wall (the order parameter
+    # halfway), and the Young force at every in-step measurement read on phi
+    # (band -0.8..0.8): each case against its lone lattice, bit for bit
+    cases = pf_cases(3, seed=31)
+    cases[1]["solid"] = dict(cases[1]["solid"], stripes=(-0.3, 0.25, 7.0))
+    cases[1]["solid"].pop("mu_w")
+    b = G.Batch(cases, precision=G.LBM_F64, bc_mode=G.LBM_BC_BOUZIDI_MC, **PF)
+    b.set_young(0.0133, 70.0, 110.0)
+    b.step(90, measure_every=30)
+    by, ang = b.young_last(), b.angles()
+    da, dy = b.young_force(0.0133, 70.0, 110.0)   # on demand, at step 90
+    for i, cs in enumerate(cases):
+        s = single(cs, G.LBM_F64, bc="bouzidi")
+        s.set_measure(0, 2)
+        s.set_young(0.0133, 70.0, 110.0)
+        sa = s.step(90, measure_every=30, cap=4)
+        sy = s.young_series()[-1]
+        assert np.array_equal(b.read(i, G.FIELD_F), s.f), i
+        assert np.array_equal(b.read(i, G.FIELD_G), s.g), i
+        same_angles(ang[i], sa[-1])
+        assert by[i].step == sy.step == 60 and by[i].status == sy.status
+        for k in range(2):
+            assert list(by[i].count[k]) == list(sy.count[k]), (i, k)
+            for name in ("phi_d", "theta_eq_deg", "force"):
+                g, r = getattr(by[i], name)[k], getattr(sy, name)[k]
+                assert (math.isnan(g) and math.isnan(r)) or g == r, (i, k, name, g, r)
+        oa, oy = s.young_force(0.0133, 70.0, 110.0)
+        same_angles(da[i], oa)
+        assert dy[i].status == oy.status
+        for k in range(2):
+            assert list(dy[i].count[k]) == list(oy.count[k]), (i, k)
+            g, r = dy[i].force[k], oy.force[k]
+            assert (math.isnan(g) and math.isnan(r)) or g == r, (i, k, g, r)
+    assert any(sum(y.count[0]) + sum(y.count[1]) > 0 for y in by)
