@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # stands when they were taken (profiles/k_step_d3q19_f32_256cube.md; the phase-field model's k_pf_collide in
 # profiles/k_pf_collide_d3q19_f32_256cube.md, its writes that are not 64-byte requests counted as 32 bytes).
 # Keyed by (kernel, lattice side, precision, collision, force model).
-COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk", "chemical-potential"): 13457502 * 128 + 1467 * 64 + 21594567 * 64,
-                   ("k_step", 256, "f32", "mrt", "chemical-potential"): 13444247 * 128 + 1749 * 64 + 21594225 * 64,
+COUNTED_TRAFFIC = {("k_step", 256, "f32", "bgk", "chemical-potential"): 13015528 * 128 + 1550 * 64 + 21594750 * 64,
+                   ("k_step", 256, "f32", "mrt", "chemical-potential"): 12774044 * 128 + 1700 * 64 + 21594828 * 64,
                    ("k_collide", 256, "f32", "bgk", "phase-field"):
                        24626936 * 128 + 2257 * 64 + 36426673 * 64 + 439204 * 32}
 # the same for kb_collide of the batched solver on the seeded table, from FETCH_SIZE x 2 and WRITE_SIZE in KiB

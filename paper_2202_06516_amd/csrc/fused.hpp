@@ -230,6 +230,17 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
     __shared__ C acc[TY + 2][3][NX];
     // [plane parity][0: e_x = +1 values of lane 63, 1: e_x = -1 values of lane 0][wave][row][row group]
     __shared__ C edge[2][2][NX / 64][TY][5];
+    // The rho and mu values of the planes z - 2 .. z + 1 of each column, one
+    // slot per plane modulo 4 and per row of the tile: the force stencil
+    // takes its centre and z neighbours from the thread's own column and its
+    // x neighbours from the neighbouring columns' slots of plane z, and loads
+    // only plane z + 2 and the y neighbours; the node then stores plane z + 2
+    // into the slot of plane z - 2 (no longer needed by its row).  A slot is
+    // written two planes before another thread reads it and overwritten two
+    // planes after, with a barrier at the end of every plane in between.
+    // FP32 storage and rows of up to 256 nodes (32 KB).
+    constexpr bool RING = !SC && sizeof(R) == 4 && NX <= 256;
+    __shared__ R ring[RING ? 4 : 1][TY][2][RING ? NX : 1];
 #pragma unroll
     for (int k = 0; k < TY + 2; ++k) acc[k][0][x] = acc[k][1][x] = acc[k][2][x] = C(0);
 
@@ -292,11 +303,60 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
             F[0] = at(force, ix);
             F[1] = at(force + dd.N, ix);
             F[2] = at(force + 2 * dd.N, ix);
+        } else if constexpr (RING) {
+            // y neighbours and plane z + 2 from memory, the rest from the ring:
+            // the z neighbours from the thread's own slots, the x neighbours
+            // from the slots of plane z of the neighbouring columns, written
+            // two planes earlier with plane-end barriers in between
+            const int nc = n < nn ? n : nn - 1, r = nc % TY, zz = nc / TY;
+            const Nbr ox = nbr_offsets(xx, dd.nx, 1), oy = nbr_offsets(y, dd.ny, dd.px);
+            const Nbr oz = nbr_offsets(z, dd.nz, dd.px * dd.ny);
+            G.v[5] = at(rho, ix + (uint32_t)oy.m2);
+            G.v[6] = at(rho, ix + (uint32_t)oy.m1);
+            G.v[7] = at(rho, ix + (uint32_t)oy.p1);
+            G.v[8] = at(rho, ix + (uint32_t)oy.p2);
+            G.v[17] = at(mu, ix + (uint32_t)oy.m2);
+            G.v[18] = at(mu, ix + (uint32_t)oy.m1);
+            G.v[19] = at(mu, ix + (uint32_t)oy.p1);
+            G.v[20] = at(mu, ix + (uint32_t)oy.p2);
+            G.v[12] = at(rho, ix + (uint32_t)oz.p2);
+            G.v[24] = at(mu, ix + (uint32_t)oz.p2);
+            const int s0 = zz & 3, sm2 = (zz + 2) & 3, sm1 = (zz + 3) & 3, sp1 = (zz + 1) & 3;
+            G.v[1] = ring[s0][r][0][xx + ox.m2];
+            G.v[2] = ring[s0][r][0][xx + ox.m1];
+            G.v[3] = ring[s0][r][0][xx + ox.p1];
+            G.v[4] = ring[s0][r][0][xx + ox.p2];
+            G.v[13] = ring[s0][r][1][xx + ox.m2];
+            G.v[14] = ring[s0][r][1][xx + ox.m1];
+            G.v[15] = ring[s0][r][1][xx + ox.p1];
+            G.v[16] = ring[s0][r][1][xx + ox.p2];
+            G.v[0] = ring[s0][r][0][xx];
+            G.v[9] = ring[sm2][r][0][xx];
+            G.v[10] = ring[sm1][r][0][xx];
+            G.v[11] = ring[sp1][r][0][xx];
+            G.v[21] = ring[sm2][r][1][xx];
+            G.v[22] = ring[sm1][r][1][xx];
+            G.v[23] = ring[sp1][r][1][xx];
         } else {
             force_stencil_load<L, R, false>(rho, mu, dd, xx, y, z, G);  // every offset in bounds: unconditional
         }
         gather_issue<L, R, PULL>(fin, dd, ix, xx, y, z, m, S);
     };
+    if constexpr (RING) {
+        // planes z0 - 2 .. z0 + 1 of every row of the tile
+        const Nbr oz = nbr_offsets(z0, d.nz, d.px * d.ny);
+        const int off[4] = {0, oz.p1, oz.m2, oz.m1};  // slots of planes z0, z0 + 1, z0 - 2, z0 - 1
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            const uint32_t ix = nid32(d, x, y0 + r, z0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ring[k][r][0][x] = at(rho, ix + (uint32_t)off[k]);
+                ring[k][r][1][x] = at(mu, ix + (uint32_t)off[k]);
+            }
+        }
+        lds_barrier();  // the first plane's x neighbours are other threads' slots
+    }
 
     uint8_t c0 = load_cls(0), c1 = load_cls(1), c2 = load_cls(2);
     uint32_t m0 = load_mask(0, c0), m1 = load_mask(1, c1);
@@ -316,6 +376,11 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
         node_of(n, y, z);
         const int r = n % TY, zz = n / TY, par = zz & 1;
         const int sc = z % 3, sn = (z + 1) % 3, sp = (z + 2) % 3;  // slots of planes z, z + 1, z - 1
+        if constexpr (RING) {
+            // plane z + 2 of this row into the slot of plane z - 2
+            ring[(zz + 2) & 3][r][0][xx] = Gcur.v[12];
+            ring[(zz + 2) & 3][r][1][xx] = Gcur.v[24];
+        }
         // What leaves x: f*_i, or nothing from a solid node.  A population that
         // leaves toward a wall is also added to the solid node it points to;
         // that node is on the first solid layer, whose density the fill of
