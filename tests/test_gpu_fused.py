@@ -4,7 +4,8 @@ FP64 oracle and against the split step, element by element.
 k_step collides step t and sums the density of step t + 1 in the same pass;
 partial sums that cross its tiles go through ghost arrays.  The cases cover
 one, two and three waves per row, every z-chunk depth it picks (32, 16, 8, 4, 2),
-walls and periodic axes (ghost rows and planes that wrap), halfway and
+walls and periodic axes (ghost rows and planes that wrap), the FP32 force
+stencil's LDS ring on every shape, halfway and
 interpolated walls, MRT and BGK, gravity switched on mid-run, the pseudopotential model, FP64 /
 FP32 / FP32 with FP64 arithmetic, in-step measurement, reads between steps, and
 graph-captured against eager stepping.
@@ -122,6 +123,26 @@ def test_one_pass_fp32_200_steps(precision, tol):
         errs.append(rel_err(gp.rho, o.rho, o.cls <= 2))
     print("density error every 50 steps:", ["%.2e" % e for e in errs])
     assert max(errs) <= tol, errs
+
+
+@pytest.mark.parametrize("n,wall", CASES)
+@pytest.mark.parametrize("collision", ["bgk", "mrt"])
+def test_one_pass_fp32_stencil_ring_shapes(n, wall, collision):
+    # FP32 storage takes the force stencil's centre, z and x neighbours from the
+    # LDS ring: one, two and three waves per row (x neighbours across waves and
+    # across the periodic row end), every plane-chunk depth of CASES
+    wl = case(n, wall)
+    kw = dict(s_q=1.0, s_m=1.0, s_pi=1.0, **SMALL)
+    gp = gpu_lattice(wl, G.LBM_F32, collision, **kw)
+    assert is_fused(gp)
+    o = oracle_lattice(wl, collision, **kw)
+    o.step(1)
+    gp.step(59)
+    o.step(59)
+    o.update_derived()
+    e = rel_err(gp.rho, o.rho, o.cls <= 2)
+    print(f"{n} {collision}: density error {e:.2e}")
+    assert e <= 1e-6
 
 
 def test_one_pass_in_step_measurement_matches_oracle():
