@@ -238,7 +238,8 @@ __global__ void __launch_bounds__(NX) k_step(const R* __restrict__ fin, R* __res
     // into the slot of plane z - 2 (no longer needed by its row).  A slot is
     // written two planes before another thread reads it and overwritten two
     // planes after, with a barrier at the end of every plane in between.
-    // FP32 storage and rows of up to 256 nodes (32 KB).
+    // FP32 storage and rows of up to 256 nodes (32 KB).  (Rows of 512 in a
+    // 512-thread variant with the ring ran no faster at 512^3.)
     constexpr bool RING = !SC && sizeof(R) == 4 && NX <= 256;
     __shared__ R ring[RING ? 4 : 1][TY][2][RING ? NX : 1];
 #pragma unroll

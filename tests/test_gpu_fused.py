@@ -125,12 +125,13 @@ def test_one_pass_fp32_200_steps(precision, tol):
     assert max(errs) <= tol, errs
 
 
-@pytest.mark.parametrize("n,wall", CASES)
+@pytest.mark.parametrize("n,wall", CASES + [((512, 16, 32), (0, 1, 1))])
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
 def test_one_pass_fp32_stencil_ring_shapes(n, wall, collision):
     # FP32 storage takes the force stencil's centre, z and x neighbours from the
-    # LDS ring: one, two and three waves per row (x neighbours across waves and
-    # across the periodic row end), every plane-chunk depth of CASES
+    # LDS ring on rows of up to 256 nodes: one, two and three waves per row (x
+    # neighbours across waves and across the periodic row end), every
+    # plane-chunk depth of CASES; and a row of 512 (eight waves, no ring)
     wl = case(n, wall)
     kw = dict(s_q=1.0, s_m=1.0, s_pi=1.0, **SMALL)
     gp = gpu_lattice(wl, G.LBM_F32, collision, **kw)
