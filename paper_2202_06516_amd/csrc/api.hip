@@ -916,9 +916,10 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
         // divides nz, and by default halved down to 8 while the grid would hold
         // fewer than 512 workgroups (two per compute unit of a 256-CU device);
         // LBM_FUSED_ZC sets the starting value.  Interleaved on one device at
-        // 256^3, the walk over 8, 16, 32 planes took 0.607, 0.599, 0.592 ms and
-        // the ghost sums 0.025, 0.022, 0.020 ms; 64 planes (one workgroup per
-        // CU) took 0.729 ms; at 512^3, 16 and 32 planes 4.61 and 4.59 ms
+        // 256^3 (with the stencil ring), the walk over 8, 16, 32 planes took
+        // 0.574, 0.584, 0.570 ms and the ghost sums 0.025, 0.022, 0.020 ms;
+        // without the ring 64 planes (one workgroup per CU) took 0.729 ms, and
+        // at 512^3 16 and 32 planes 4.61 and 4.59 ms
         const char* e = std::getenv("LBM_FUSED_ZC");
         int zc = e ? std::atoi(e) : 32;
         while (zc > 2 && c->d.nz % zc) zc >>= 1;
