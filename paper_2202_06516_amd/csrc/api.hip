@@ -522,8 +522,11 @@ struct Run {
             k_force<L, R, C, false><<<zgrid(c), blk, 0, c->stream>>>(rho, (const R*)c->mu, c->cls, c->d, collision(c),
                                                                      c->ctl, (R*)c->force);
     }
+    // quiet: a step known on the host to measure nothing (t % every != 0); it
+    // leaves out k_cross, k_young_step and k_finalize, which return at once on
+    // such steps, and k_ghost counts the step instead of k_finalize
     static void fused_step_launches(lbm_ctx* c, int src, bool pull, int rsrc, const MeasureParams& mp, hipEvent_t* ev,
-                                    int* kinds) {
+                                    int* kinds, bool quiet = false) {
         if constexpr (L::D == 3) {
             const dim3 blk(256, 1, 1);
             const R* fin = (const R*)c->f[src];
@@ -533,15 +536,18 @@ struct Run {
             int k = 0;
             auto start = [&]() { if (ev) (void)hipEventRecord(ev[2 * k], c->stream); };
             auto mark = [&](int kind) { if (ev) { (void)hipEventRecord(ev[2 * k + 1], c->stream); kinds[k++] = kind; } };
-            start();
-            k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, c->ctl, mp);
             YoungStep ys{};
-            if (c->young_on) {
-                ys = young_step(c, mp);
-                k_young_step<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, young_step_params(c, mp),
-                                                                        mp, c->ctl, c->ystep_counts);
+            if (!quiet) {
+                start();
+                k_cross<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d, c->ctl, mp);
+                if (c->young_on) {
+                    ys = young_step(c, mp);
+                    k_young_step<L, R><<<cross_grid(c), blk, 0, c->stream>>>(rho, c->cls, c->d,
+                                                                            young_step_params(c, mp), mp, c->ctl,
+                                                                            c->ystep_counts);
+                }
+                mark(5);
             }
-            mark(5);
             start();
             const WallBC bc = wall(c);
             const Collision<C> cp = collision(c);
@@ -565,16 +571,20 @@ struct Run {
                     c->curved, c->n_curved, c->b_node, c->b_mask, fout, c->d, bc);
                 mark(10);
             }
-            start();
-            k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1, ys, c->yseries);
-            mark(6);
+            if (!quiet) {
+                start();
+                k_finalize<L, R><<<1, 64, 0, c->stream>>>(rho, c->ctl, c->d, mp, c->series, c->last, 1, ys,
+                                                          c->yseries);
+                mark(6);
+            }
             start();
             {
                 const int ein = 2 * (c->d.ny / kFusedTY);
                 const long long rows = (long long)(c->d.nz / c->fzc) * (2LL * c->d.ny + (long long)(c->fzc - 2) * ein);
                 const long long thr = rows * (c->d.nx / 4);
                 k_ghost<R, kFusedTY><<<(unsigned)((thr + 255) / 256), 256, 0, c->stream>>>(
-                    rnext, (const R*)c->gy, (const R*)c->gz, (const R*)c->gyz, c->d, c->fzc, rows);
+                    rnext, (const R*)c->gy, (const R*)c->gz, (const R*)c->gyz, c->d, c->fzc, rows,
+                    quiet ? c->ctl : nullptr);
             }
             mark(8);
             fills_on(c, rnext, ev, kinds, k);
@@ -715,8 +725,9 @@ struct OpStep {
 };
 template <class L, typename R, typename C>
 struct OpFusedStep {
-    static void go(lbm_ctx* c, int src, bool pull, int rsrc, const MeasureParams* mp, hipEvent_t* ev, int* kinds) {
-        Run<L, R, C>::fused_step_launches(c, src, pull, rsrc, *mp, ev, kinds);
+    static void go(lbm_ctx* c, int src, bool pull, int rsrc, const MeasureParams* mp, hipEvent_t* ev, int* kinds,
+                   bool quiet = false) {
+        Run<L, R, C>::fused_step_launches(c, src, pull, rsrc, *mp, ev, kinds, quiet);
     }
 };
 template <class L, typename R, typename C>
@@ -1330,8 +1341,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
         if (!c->rho_valid) dispatch<OpDerive>(c, true);
         else if (measure_every > 0 && c->t % measure_every == 0) dispatch<OpCentroid>(c, mp.rho_m);
     }
-    auto launch_one = [&](int src, bool pull, int rsrc) {
-        if (fused) dispatch<OpFusedStep>(c, src, pull, rsrc, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
+    auto launch_one = [&](int src, bool pull, int rsrc, bool quiet) {
+        if (fused) dispatch<OpFusedStep>(c, src, pull, rsrc, &mp, (hipEvent_t*)nullptr, (int*)nullptr, quiet);
         else dispatch<OpStep>(c, src, pull, &mp, (hipEvent_t*)nullptr, (int*)nullptr);
     };
     auto advance = [&]() {
@@ -1343,33 +1354,40 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps, int measure_every, lbm_angle* se
         }
     };
     auto eager = [&]() {
-        launch_one(c->cur, c->fstar, c->rcur);
+        launch_one(c->cur, c->fstar, c->rcur, false);
         advance();
         ++done;
         ++c->t;
     };
     // eager steps until the populations are in pull form in buffer 0 (and the
     // density in buffer 0), then whole captured graphs (an even number of
-    // steps keeps the parity), then the rest
+    // steps keeps the parity), then the rest.  The one-pass step has two
+    // graphs: graph[0] of full steps, and graph[1] of quiet steps for windows
+    // of kGraphSteps steps of which none is a measure step (t % every != 0).
+    auto quiet_window = [&](int64_t t0) {
+        if (!fused) return false;
+        if (measure_every <= 0) return true;
+        const int64_t r = t0 % measure_every;
+        return r != 0 && measure_every - r >= kGraphSteps;
+    };
     while (done < nsteps && (!c->fstar || c->cur != 0 || c->rcur != 0 || nsteps - done < kGraphSteps)) eager();
-    if (nsteps - done >= kGraphSteps) {
-        if (!c->graph[0]) {
+    while (nsteps - done >= kGraphSteps) {
+        const int gi = quiet_window(c->t) ? 1 : 0;
+        if (!c->graph[gi]) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < kGraphSteps; ++k) launch_one(k & 1, true, k & 1);
+            for (int k = 0; k < kGraphSteps; ++k) launch_one(k & 1, true, k & 1, gi == 1);
             HIPCHK(c, hipStreamEndCapture(c->stream, &g));
-            hipError_t e = hipGraphInstantiate(&c->graph[0], g, nullptr, nullptr, 0);
+            hipError_t e = hipGraphInstantiate(&c->graph[gi], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
-                c->graph[0] = nullptr;
+                c->graph[gi] = nullptr;
                 return fail(c, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
             }
         }
-        while (nsteps - done >= kGraphSteps) {
-            HIPCHK(c, hipGraphLaunch(c->graph[0], c->stream));
-            done += kGraphSteps;
-            c->t += kGraphSteps;
-        }
+        HIPCHK(c, hipGraphLaunch(c->graph[gi], c->stream));
+        done += kGraphSteps;
+        c->t += kGraphSteps;
     }
     while (done < nsteps) eager();
     HIPCHK(c, hipGetLastError());

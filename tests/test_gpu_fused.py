@@ -184,6 +184,38 @@ def test_one_pass_graph_and_eager_agree():
     assert np.array_equal(a.rho, b.rho)
 
 
+def test_one_pass_quiet_graphs_keep_the_measure_steps():
+    # cadence 40 over 200 steps: captured windows of 32 steps with a measure
+    # step (full steps) and without one (quiet steps, without k_cross and
+    # k_finalize); the angles, their steps and the fields equal those of
+    # single eager steps bit for bit, and so does a later measurement
+    wl = case((64, 24, 32), (1, 1, 1))
+    a = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
+    b = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
+    a.set_measure(0, 8)
+    b.set_measure(0, 8)
+    ga = a.step(200, measure_every=40, cap=8)
+    gb = []
+    for _ in range(200):
+        gb += b.step(1, measure_every=40, cap=1)
+    assert [r.step for r in ga] == [r.step for r in gb] == [0, 40, 80, 120, 160]
+    for x, y in zip(ga, gb):
+        assert x.n_valid == y.n_valid > 0
+        assert np.array_equal(np.asarray(x.sector_deg), np.asarray(y.sector_deg), equal_nan=True)
+    assert np.array_equal(a.f, b.f)
+    assert np.array_equal(a.rho, b.rho)
+    # a later call whose windows are all quiet, then one that measures at once
+    a.step(96, measure_every=1000)
+    for _ in range(96):
+        b.step(1, measure_every=1000)
+    ra, rb = a.step(40, measure_every=8, cap=8), b.step(40, measure_every=8, cap=8)
+    assert [r.step for r in ra] == [r.step for r in rb] == [296, 304, 312, 320, 328]
+    assert np.array_equal(np.asarray(ra[-1].sector_deg), np.asarray(rb[-1].sector_deg), equal_nan=True)
+    ma, mb = a.measure(0, 8), b.measure(0, 8)
+    assert ma.step == mb.step == 336 and ma.n_valid == mb.n_valid
+    assert np.array_equal(np.asarray(ma.sector_deg), np.asarray(mb.sector_deg), equal_nan=True)
+
+
 def test_one_pass_reads_and_writes_between_steps():
     wl = case((64, 24, 32), (1, 1, 1))
     a = gpu_lattice(wl, G.LBM_F64, "bgk", **SMALL)
